@@ -1,0 +1,556 @@
+"""Plain CPU reference ("oracle") for the Neural Dynamic GI decode and training path.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import or call anything in this package.
+The product path (the HIP library and its Python binding) never imports it and
+shares no code, tables or helpers with it.
+
+Everything here is float64 numpy (integer numpy for the block-compression codec),
+written to be checked by eye against the paper (arXiv 2604.12625):
+
+* Sec. 3.1, Eq. (3): the lighting at (u, v, t) is the output of a model H_Theta.
+* Sec. 3.3, Eq. (4)-(5): features are sampled from a spatial map and a
+  spatio-temporal map, concatenated and fed to a small MLP decoder G_Phi.
+* Sec. 3.4, Eq. (6)-(7) and supplementary Sec. B: a 4x4 block stores two
+  endpoints and per-texel weights; each texel is the linear interpolation of the
+  endpoints (block compression, BC).
+* Sec. 4 (Implementation): Adam, L2 loss.
+* Supplementary Sec. D.2: tiled PSNR with the dynamic range taken per tile.
+* Tables 2-3: bits per pixel accounting.
+
+The concrete feature layout (an 8-channel BC4 spatial map plus an 8-channel
+FP16/FP32 grid at quarter resolution, a 16-32-32-3 ReLU decoder with exponential
+output) is the workload this library is built for; each place where the paper
+does not fix a detail carries a "Reading" note.  Parity of the end-to-end decode
+is the composition of separately pinned parts (codec, interpolation, MLP); the
+trained quality of a model has no published value to pin against
+("parity unpinned" for trained PSNR).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+N_SPATIAL = 8      # channels of the block-compressed spatial map
+N_GRID = 8         # channels of the spatio-temporal grid
+N_IN = N_SPATIAL + N_GRID
+HIDDEN = 32
+N_OUT = 3
+
+# Offsets of the packed decoder parameters: [W1 32x16 | b1 | W2 32x32 | b2 | W3 3x32 | b3]
+# (row-major W[out][in], y = W x + b).
+MLP_W1 = 0
+MLP_B1 = MLP_W1 + HIDDEN * N_IN
+MLP_W2 = MLP_B1 + HIDDEN
+MLP_B2 = MLP_W2 + HIDDEN * HIDDEN
+MLP_W3 = MLP_B2 + HIDDEN
+MLP_B3 = MLP_W3 + N_OUT * HIDDEN
+MLP_SIZE = MLP_B3 + N_OUT  # 1699
+
+
+# --------------------------------------------------------------------------------------
+# Block compression (BC4: one channel, 4x4 texels, 8 bytes)
+# --------------------------------------------------------------------------------------
+
+def bc4_palette(e0: int, e1: int) -> list[int]:
+    """The eight 8-bit values a BC4 block with endpoints (e0, e1) can select.
+
+    Follows Eq. (7) / supplementary Eq. (5): value = (1 - w) e_a + w e_b with w on a
+    uniform grid.  Reading: two modes as in the public BC4 format; with e0 > e1 the
+    six interior codes use w = j/7 (j = 1..6), otherwise four interior codes use
+    w = j/5 (j = 1..4) and the last two codes are the constants 0 and 255.  The
+    rational value is rounded to the nearest integer (the denominators are odd, so no
+    ties occur): floor((N + (D-1)/2) / D) for numerator N and denominator D.
+    """
+    e0 = int(e0)
+    e1 = int(e1)
+    pal = [e0, e1]
+    if e0 > e1:
+        for j in range(1, 7):
+            pal.append(((7 - j) * e0 + j * e1 + 3) // 7)
+    else:
+        for j in range(1, 5):
+            pal.append(((5 - j) * e0 + j * e1 + 2) // 5)
+        pal += [0, 255]
+    return pal
+
+
+def bc4_codes(block: np.ndarray) -> np.ndarray:
+    """3-bit selector of each of the 16 texels of one 8-byte block, texel s = 4*row + col.
+
+    Bytes 2..7 form a little-endian 48-bit field; texel s uses bits 3s..3s+2.
+    """
+    field = 0
+    for b in range(6):
+        field |= int(block[2 + b]) << (8 * b)
+    return np.array([(field >> (3 * s)) & 7 for s in range(16)], dtype=np.int64)
+
+
+def bc4_decode_block(block: np.ndarray) -> np.ndarray:
+    """Decode one 8-byte BC4 block to a 4x4 uint8 array [row][col]."""
+    pal = bc4_palette(block[0], block[1])
+    codes = bc4_codes(block)
+    return np.array([pal[c] for c in codes], dtype=np.uint8).reshape(4, 4)
+
+
+def bc4_palette_value(e0: np.ndarray, e1: np.ndarray, code: np.ndarray) -> np.ndarray:
+    """Vectorised palette lookup (same definition as :func:`bc4_palette`)."""
+    e0 = e0.astype(np.int64)
+    e1 = e1.astype(np.int64)
+    code = code.astype(np.int64)
+    j = code - 1                                   # interior codes 2.. map to j = 1..
+    v8 = ((7 - j) * e0 + j * e1 + 3) // 7
+    v6 = ((5 - j) * e0 + j * e1 + 2) // 5
+    v6 = np.where(code == 6, 0, np.where(code == 7, 255, v6))
+    interior = np.where(e0 > e1, v8, v6)
+    out = np.where(code == 0, e0, np.where(code == 1, e1, interior))
+    return out.astype(np.uint8)
+
+
+def bc4_decode_blocks(blocks: np.ndarray) -> np.ndarray:
+    """Decode n blocks ([n][8] uint8) to [n][16] uint8 (texel s = 4*row + col)."""
+    blocks = np.asarray(blocks, dtype=np.uint8).reshape(-1, 8)
+    field = np.zeros(blocks.shape[0], dtype=np.int64)
+    for b in range(6):
+        field |= blocks[:, 2 + b].astype(np.int64) << (8 * b)
+    s = np.arange(16, dtype=np.int64)
+    codes = (field[:, None] >> (3 * s)[None, :]) & 7
+    e0 = np.repeat(blocks[:, 0:1], 16, axis=1)
+    e1 = np.repeat(blocks[:, 1:2], 16, axis=1)
+    return bc4_palette_value(e0, e1, codes)
+
+
+def spatial_texels(bc4: np.ndarray, xs: np.ndarray, ys: np.ndarray) -> np.ndarray:
+    """uint8 values of the 8 spatial channels at integer texels (xs, ys) -> [..., 8].
+
+    ``bc4`` is [H/4][W/4][8 channels][8 bytes]: the eight single-channel blocks of a
+    4x4 footprint are stored next to each other.
+    """
+    xs = np.asarray(xs, dtype=np.int64)
+    ys = np.asarray(ys, dtype=np.int64)
+    blocks = bc4[ys >> 2, xs >> 2]                       # [..., 8, 8]
+    field = np.zeros(blocks.shape[:-1], dtype=np.int64)   # [..., 8]
+    for b in range(6):
+        field |= blocks[..., 2 + b].astype(np.int64) << (8 * b)
+    slot = (4 * (ys & 3) + (xs & 3))[..., None]
+    codes = (field >> (3 * slot)) & 7
+    return bc4_palette_value(blocks[..., 0], blocks[..., 1], codes)
+
+
+# --------------------------------------------------------------------------------------
+# Feature sampling (Sec. 3.3) and the decoder MLP
+# --------------------------------------------------------------------------------------
+
+def _axis(coord: np.ndarray, size: int):
+    """Texel-centre linear interpolation along one axis with clamp-to-edge.
+
+    Reading: a coordinate c in [0, 1) maps to the continuous texel position
+    c*size - 0.5; the two neighbours are floor() and floor()+1, clamped to [0, size-1].
+    Returns (index0, index1, weight0, weight1).
+    """
+    p = coord * size - 0.5
+    p0 = np.floor(p)
+    f = p - p0
+    i0 = np.clip(p0.astype(np.int64), 0, size - 1)
+    i1 = np.clip(p0.astype(np.int64) + 1, 0, size - 1)
+    return i0, i1, 1.0 - f, f
+
+
+def _time_keys(t: np.ndarray, T: int):
+    """Keys and weights for linear interpolation in time.
+
+    Reading: T uniformly spaced keys at t_k = k/T on a periodic day cycle; t is
+    wrapped into [0, 1) and interpolation between the last key and key 0 wraps.
+    """
+    tw = t - np.floor(t)
+    tau = tw * T
+    k = np.floor(tau)
+    ft = tau - k
+    k0 = np.mod(k.astype(np.int64), T)
+    k1 = np.mod(k0 + 1, T)
+    return k0, k1, 1.0 - ft, ft
+
+
+def features(model: dict, u: np.ndarray, v: np.ndarray, t: np.ndarray) -> np.ndarray:
+    """The 16 decoder inputs at (u, v, t) in float64: [S_0..S_7, G_0..G_7].
+
+    S: bilinear sample of the decoded spatial map (value/255, Eq. (6) puts features
+    in [0, 1]).  G: bilinear in space and linear in time sample of the grid
+    [T][Gh][Gw][8] (the spatio-temporal feature map sampled at (u, v, t), Sec. 3.3).
+    """
+    W, H = model["W"], model["H"]
+    x0, x1, wx0, wx1 = _axis(u, W)
+    y0, y1, wy0, wy1 = _axis(v, H)
+    bc4 = model["bc4"]
+    S = np.zeros(u.shape + (N_SPATIAL,), dtype=np.float64)
+    for (yy, wy) in ((y0, wy0), (y1, wy1)):
+        for (xx, wx) in ((x0, wx0), (x1, wx1)):
+            tex = spatial_texels(bc4, xx, yy).astype(np.float64) / 255.0
+            S += (wx * wy)[..., None] * tex
+
+    Gw, Gh, T = model["Gw"], model["Gh"], model["T"]
+    grid = np.asarray(model["grid"]).astype(np.float64)     # [T][Gh][Gw][8]
+    gx0, gx1, gwx0, gwx1 = _axis(u, Gw)
+    gy0, gy1, gwy0, gwy1 = _axis(v, Gh)
+    k0, k1, wt0, wt1 = _time_keys(t, T)
+    G = np.zeros(u.shape + (N_GRID,), dtype=np.float64)
+    for (kk, wt) in ((k0, wt0), (k1, wt1)):
+        for (yy, wy) in ((gy0, gwy0), (gy1, gwy1)):
+            for (xx, wx) in ((gx0, gwx0), (gx1, gwx1)):
+                G += (wt * wy * wx)[..., None] * grid[kk, yy, xx]
+    return np.concatenate([S, G], axis=-1)
+
+
+def unpack_mlp(mlp) -> dict:
+    """Split the packed 1699-vector into float64 W1, b1, W2, b2, W3, b3."""
+    p = np.asarray(mlp).astype(np.float64).reshape(-1)
+    assert p.size == MLP_SIZE
+    return dict(
+        W1=p[MLP_W1:MLP_B1].reshape(HIDDEN, N_IN), b1=p[MLP_B1:MLP_W2],
+        W2=p[MLP_W2:MLP_B2].reshape(HIDDEN, HIDDEN), b2=p[MLP_B2:MLP_W3],
+        W3=p[MLP_W3:MLP_B3].reshape(N_OUT, HIDDEN), b3=p[MLP_B3:MLP_SIZE],
+    )
+
+
+def mlp_forward(mlp, x: np.ndarray) -> np.ndarray:
+    """Decoder G_Phi: two ReLU hidden layers of width 32, exponential output -> HDR RGB."""
+    P = unpack_mlp(mlp)
+    h1 = np.maximum(0.0, x @ P["W1"].T + P["b1"])
+    h2 = np.maximum(0.0, h1 @ P["W2"].T + P["b2"])
+    z = h2 @ P["W3"].T + P["b3"]
+    return np.exp(z)
+
+
+def decode_f64(model: dict, u: np.ndarray, v: np.ndarray, t: np.ndarray) -> np.ndarray:
+    """I(u, v, t) = H_Theta(u, v, t) (Eq. (3)) with float64 coordinates -> [n][3]."""
+    u = np.asarray(u, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    finite = np.isfinite(u) & np.isfinite(v) & np.isfinite(t)
+    uu = np.where(finite, u, 0.0)
+    vv = np.where(finite, v, 0.0)
+    tt = np.where(finite, t, 0.0)
+    rgb = mlp_forward(model["mlp"], features(model, uu, vv, tt))
+    # Reading: a query with a non-finite coordinate has no defined texel; it
+    # decodes to NaN in every channel.
+    return np.where(finite[..., None], rgb, np.nan)
+
+
+def decode(model: dict, uvt: np.ndarray) -> np.ndarray:
+    """Decode explicit queries; ``uvt`` is [n][3] float32 (converted exactly to float64)."""
+    q = np.asarray(uvt, dtype=np.float32).astype(np.float64).reshape(-1, 3)
+    return decode_f64(model, q[:, 0], q[:, 1], q[:, 2])
+
+
+def page_texels(model: dict, page_x: int, page_y: int, page: int):
+    """Texel coordinates (x, y) and exact float64 texel-centre (u, v) of one VT page."""
+    j, i = np.meshgrid(np.arange(page), np.arange(page), indexing="ij")
+    x = page * page_x + i
+    y = page * page_y + j
+    u = (x + 0.5) / model["W"]
+    v = (y + 0.5) / model["H"]
+    return x, y, u, v
+
+
+def decode_page(model: dict, page_x: int, page_y: int, t: float, page: int = 128) -> np.ndarray:
+    """Decode one virtual-texturing page (Sec. 3.5, supplementary Sec. C): [page][page][3]."""
+    _, _, u, v = page_texels(model, page_x, page_y, page)
+    tt = np.full(u.shape, np.float64(np.float32(t)))
+    return decode_f64(model, u, v, tt)
+
+
+def decode_pages(models: list, reqs: list, page: int, dst: np.ndarray, pitch: int) -> int:
+    """Write each valid request's page into ``dst`` ([rows*pitch][3]); returns #invalid.
+
+    A request is (model, page_x, page_y, t, dst_offset); texel (i, j) of the page goes to
+    dst[dst_offset + j*pitch + i].  A request whose model index or page lies outside its
+    map is skipped and counted.
+    """
+    bad = 0
+    for (m, px, py, t, off) in reqs:
+        if not (0 <= m < len(models)):
+            bad += 1
+            continue
+        md = models[m]
+        if px < 0 or py < 0 or page * (px + 1) > md["W"] or page * (py + 1) > md["H"]:
+            bad += 1
+            continue
+        rgb = decode_page(md, px, py, t, page)
+        for j in range(page):
+            dst[off + j * pitch: off + j * pitch + page] = rgb[j]
+    return bad
+
+
+# --------------------------------------------------------------------------------------
+# Training with BC simulation (Sec. 3.4, Eq. (6)-(7); Sec. 4)
+# --------------------------------------------------------------------------------------
+# Trainable state (float32 master copies):
+#   endpoints [H/4][W/4][8][2]  -- e1, e2 of each 4x4 block and channel, in [0, 1]
+#   weights   [H][W][8]         -- per-texel interpolation weight w_p, in [0, 1]
+#   grid      [T][Gh][Gw][8]
+#   mlp       [1699]
+
+def quantise_endpoint(e: np.ndarray) -> np.ndarray:
+    """8-bit endpoint E = round-half-even(fl32(255 * e)) (float32 product, as stored)."""
+    return np.rint(np.float32(255.0) * np.asarray(e, dtype=np.float32)).astype(np.int64)
+
+
+def quantise_weight(w: np.ndarray) -> np.ndarray:
+    """3-bit weight index J = round-half-even(fl32(7 * w))."""
+    return np.rint(np.float32(7.0) * np.asarray(w, dtype=np.float32)).astype(np.int64)
+
+
+def bcsim_value(E1: np.ndarray, E2: np.ndarray, J: np.ndarray) -> np.ndarray:
+    """Eq. (7) at the quantised point w = J/7, rounded to the nearest 8-bit value."""
+    return ((7 - J) * E1 + J * E2 + 3) // 7
+
+
+def bcsim_spatial(endpoints: np.ndarray, weights: np.ndarray, xs, ys):
+    """Spatial features of texels (xs, ys) under BC simulation.
+
+    Returns (value_u8 [..,8], E1, E2, J) so the caller can form the straight-through
+    derivatives.
+    """
+    xs = np.asarray(xs, dtype=np.int64)
+    ys = np.asarray(ys, dtype=np.int64)
+    ep = endpoints[ys >> 2, xs >> 2]          # [..., 8, 2]
+    E1 = quantise_endpoint(ep[..., 0])
+    E2 = quantise_endpoint(ep[..., 1])
+    J = quantise_weight(weights[ys, xs])      # [..., 8]
+    return bcsim_value(E1, E2, J), E1, E2, J
+
+
+def _sample_coords(dims: dict, xs, ys):
+    """Grid corners and weights of texel centres (xs, ys): same rule as :func:`_axis`."""
+    W, H, Gw, Gh = dims["W"], dims["H"], dims["Gw"], dims["Gh"]
+    u = (np.asarray(xs, dtype=np.float64) + 0.5) / W
+    v = (np.asarray(ys, dtype=np.float64) + 0.5) / H
+    gx0, gx1, wx0, wx1 = _axis(u, Gw)
+    gy0, gy1, wy0, wy1 = _axis(v, Gh)
+    return ((gy0, gx0, wy0 * wx0), (gy0, gx1, wy0 * wx1),
+            (gy1, gx0, wy1 * wx0), (gy1, gx1, wy1 * wx1))
+
+
+def train_forward(state: dict, xs, ys, ks, need_cache: bool = False):
+    """Predicted HDR RGB at training samples (texel (x, y) of key k, i.e. t = k/T).
+
+    Reading: samples sit exactly on a key, so the time weight of key k is 1 and the
+    next key contributes 0; the spatial feature is the BC-simulated texel itself.
+    """
+    dims = state["dims"]
+    val, E1, E2, J = bcsim_spatial(state["endpoints"], state["weights"], xs, ys)
+    S = val.astype(np.float64) / 255.0
+    grid = np.asarray(state["grid"]).astype(np.float64)
+    ks = np.asarray(ks, dtype=np.int64)
+    corners = _sample_coords(dims, xs, ys)
+    G = np.zeros(S.shape, dtype=np.float64)
+    for (gy, gx, w) in corners:
+        G += w[..., None] * grid[ks, gy, gx]
+    x = np.concatenate([S, G], axis=-1)
+    P = unpack_mlp(state["mlp"])
+    a1 = x @ P["W1"].T + P["b1"]
+    h1 = np.maximum(0.0, a1)
+    a2 = h1 @ P["W2"].T + P["b2"]
+    h2 = np.maximum(0.0, a2)
+    z = h2 @ P["W3"].T + P["b3"]
+    rgb = np.exp(z)
+    if not need_cache:
+        return rgb
+    cache = dict(x=x, a1=a1, h1=h1, a2=a2, h2=h2, rgb=rgb, E1=E1, E2=E2, J=J,
+                 corners=corners, P=P)
+    return rgb, cache
+
+
+def l2_loss(rgb: np.ndarray, target: np.ndarray) -> float:
+    """L2 loss (Sec. 4): mean over samples and the three channels of (pred - target)^2."""
+    d = rgb - np.asarray(target, dtype=np.float64)
+    return float(np.sum(d * d) / d.size)
+
+
+def train_grads(state: dict, xs, ys, ks, target: np.ndarray):
+    """Loss and analytic gradients of every trainable array (same shapes as the state).
+
+    Straight-through estimator (reading of "update the endpoints and weights",
+    Sec. 3.4): the derivative is that of the unrounded Eq. (7),
+    f = ((1 - w) e1 + w e2), evaluated at the quantised point e = E/255, w = J/7.
+    ReLU'(0) is taken as 0.
+    """
+    dims = state["dims"]
+    rgb, c = train_forward(state, xs, ys, ks, need_cache=True)
+    target = np.asarray(target, dtype=np.float64)
+    n = rgb.size
+    loss = float(np.sum((rgb - target) ** 2) / n)
+    P = c["P"]
+    dz = (2.0 / n) * (rgb - target) * rgb                  # d/dz of exp output
+    gW3 = dz.T @ c["h2"]
+    gb3 = dz.sum(axis=0)
+    dh2 = (dz @ P["W3"]) * (c["a2"] > 0)
+    gW2 = dh2.T @ c["h1"]
+    gb2 = dh2.sum(axis=0)
+    dh1 = (dh2 @ P["W2"]) * (c["a1"] > 0)
+    gW1 = dh1.T @ c["x"]
+    gb1 = dh1.sum(axis=0)
+    dx = dh1 @ P["W1"]
+    dS = dx[:, :N_SPATIAL]                   # d loss / d f with f = value/255 in [0, 1]
+    dG = dx[:, N_SPATIAL:]
+
+    g_mlp = np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3.ravel(), gb3])
+
+    xs = np.asarray(xs, dtype=np.int64)
+    ys = np.asarray(ys, dtype=np.int64)
+    ks = np.asarray(ks, dtype=np.int64)
+    J = c["J"].astype(np.float64)
+    E1 = c["E1"].astype(np.float64)
+    E2 = c["E2"].astype(np.float64)
+    g_end = np.zeros(state["endpoints"].shape, dtype=np.float64)
+    g_w = np.zeros(state["weights"].shape, dtype=np.float64)
+    ch = np.arange(N_SPATIAL)
+    bx = (xs >> 2)[:, None]
+    by = (ys >> 2)[:, None]
+    np.add.at(g_end, (by, bx, ch[None, :], 0), dS * (1.0 - J / 7.0))
+    np.add.at(g_end, (by, bx, ch[None, :], 1), dS * (J / 7.0))
+    np.add.at(g_w, (ys[:, None], xs[:, None], ch[None, :]), dS * (E2 - E1) / 255.0)
+
+    g_grid = np.zeros(np.asarray(state["grid"]).shape, dtype=np.float64)
+    for (gy, gx, w) in c["corners"]:
+        np.add.at(g_grid, (ks[:, None], gy[:, None], gx[:, None], ch[None, :]),
+                  w[:, None] * dG)
+    return loss, dict(endpoints=g_end, weights=g_w, grid=g_grid, mlp=g_mlp)
+
+
+def adam_update(param, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999,
+                eps=1e-8):
+    """One Adam step (Kingma & Ba; the bias-corrected form PyTorch uses), float64.
+
+    ``step`` is the 1-based step count after this update.  Returns (param, m, v).
+    """
+    g = np.asarray(grad, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    bc1 = 1.0 - beta1 ** step
+    bc2 = 1.0 - beta2 ** step
+    denom = np.sqrt(v) / np.sqrt(bc2) + eps
+    p = np.asarray(param, dtype=np.float64) - (lr / bc1) * m / denom
+    return p, m, v
+
+
+def train_step(state: dict, opt: dict, xs, ys, ks, target):
+    """One full step: forward, L2 loss, backward, Adam on every array, projection.
+
+    ``opt`` holds m/v arrays per key, 'step', 'lr_feat' (endpoints, weights, grid) and
+    'lr_mlp'.  Reading: endpoints and weights are projected back to [0, 1] after the
+    update (Eq. (6) constrains them to that interval).  Returns the loss.
+    """
+    loss, g = train_grads(state, xs, ys, ks, target)
+    opt["step"] += 1
+    for key in ("endpoints", "weights", "grid", "mlp"):
+        lr = opt["lr_mlp"] if key == "mlp" else opt["lr_feat"]
+        p, m, v = adam_update(state[key], g[key], opt["m"][key], opt["v"][key],
+                              opt["step"], lr, opt.get("beta1", 0.9),
+                              opt.get("beta2", 0.999), opt.get("eps", 1e-8))
+        if key in ("endpoints", "weights"):
+            p = np.clip(p, 0.0, 1.0)
+        state[key] = p
+        opt["m"][key] = m
+        opt["v"][key] = v
+    return loss
+
+
+# --------------------------------------------------------------------------------------
+# Export (Sec. 3.4 last paragraph): trained endpoints/weights -> real BC4 blocks
+# --------------------------------------------------------------------------------------
+
+def export_bc4(endpoints: np.ndarray, weights: np.ndarray) -> np.ndarray:
+    """Encode the BC-simulated spatial map as BC4 blocks [H/4][W/4][8][8] uint8.
+
+    Reading (one of several encodings that decode identically): with E1 > E2 the block
+    is (e0, e1) = (E1, E2) in 8-value mode and weight J maps to code 0 (J = 0), 1 (J = 7)
+    or J + 1; with E1 < E2 the endpoints swap and J becomes 7 - J; with E1 = E2 the block
+    is (E, E) in 6-value mode with every code 0.
+    """
+    Hb, Wb = endpoints.shape[0], endpoints.shape[1]
+    E1 = quantise_endpoint(endpoints[..., 0])        # [Hb][Wb][8]
+    E2 = quantise_endpoint(endpoints[..., 1])
+    J = quantise_weight(weights)                     # [H][W][8]
+    out = np.zeros((Hb, Wb, N_SPATIAL, 8), dtype=np.uint8)
+    for by in range(Hb):
+        for bx in range(Wb):
+            for c in range(N_SPATIAL):
+                a, b = int(E1[by, bx, c]), int(E2[by, bx, c])
+                field = 0
+                for s in range(16):
+                    j = int(J[4 * by + s // 4, 4 * bx + s % 4, c])
+                    if a == b:
+                        code = 0
+                    else:
+                        jj = j if a > b else 7 - j
+                        code = 0 if jj == 0 else (1 if jj == 7 else jj + 1)
+                    field |= code << (3 * s)
+                e0, e1 = (a, b) if a >= b else (b, a)
+                out[by, bx, c, 0] = e0
+                out[by, bx, c, 1] = e1
+                for k in range(6):
+                    out[by, bx, c, 2 + k] = (field >> (8 * k)) & 0xFF
+    return out
+
+
+# --------------------------------------------------------------------------------------
+# Evaluation: tiled PSNR (supplementary Sec. D.2) and bit-rate (Tables 2-3)
+# --------------------------------------------------------------------------------------
+
+def psnr_tiled(pred: np.ndarray, target: np.ndarray, tile: int = 128):
+    """Mean of per-tile PSNR over all tiles of all maps, and a global PSNR.
+
+    ``pred``/``target`` are [T][H][W][3].  Per tile the peak is (max - min) of the
+    target over the tile's texels and channels; PSNR = 10 log10(range^2 / MSE).
+    Reading: a tile of zero range is skipped, a tile with MSE = 0 scores 100 dB.  All
+    texels are valid (synthetic data has no mask).  Global PSNR uses the range and MSE
+    over everything.
+    """
+    p = np.asarray(pred, dtype=np.float64)
+    g = np.asarray(target, dtype=np.float64)
+    T, H, W, _ = g.shape
+    scores = []
+    for k in range(T):
+        for y0 in range(0, H, tile):
+            for x0 in range(0, W, tile):
+                gt = g[k, y0:y0 + tile, x0:x0 + tile]
+                pr = p[k, y0:y0 + tile, x0:x0 + tile]
+                rng = gt.max() - gt.min()
+                if rng <= 0:
+                    continue
+                mse = np.mean((pr - gt) ** 2)
+                scores.append(100.0 if mse == 0 else 10.0 * np.log10(rng * rng / mse))
+    mse_all = np.mean((p - g) ** 2)
+    rng_all = g.max() - g.min()
+    glob = 100.0 if mse_all == 0 else 10.0 * np.log10(rng_all * rng_all / mse_all)
+    return (float(np.mean(scores)) if scores else float("nan")), float(glob)
+
+
+def bits_per_texel_paper(W: int, H: int, n_maps: int, uvt_res: tuple, hidden: int,
+                         uv_ch=4, plane_len=64, plane_t=24, plane_ch=2) -> float:
+    """Bits per texel per map of the paper's hybrid layout (Table 1, Table 3).
+
+    F_uv (W x H, 4 channels) and each time slice of F_uvt are BC7 at 8 bits per texel;
+    F_ut and F_vt (plane_len x plane_t x 2 channels) are 8-bit; the MLP 16-h-h-3 is
+    FP16.  Divided by W * H * n_maps.
+    """
+    uw, uh, ut = uvt_res
+    bits = W * H * 8                       # F_uv, BC7
+    bits += uw * uh * ut * 8               # F_uvt slices, BC7
+    bits += 2 * plane_len * plane_t * plane_ch * 8
+    n_in = 16
+    params = hidden * n_in + hidden + hidden * hidden + hidden + 3 * hidden + 3
+    bits += params * 16
+    return bits / (W * H * n_maps)
+
+
+def bits_per_texel_bc4_grid(W: int, H: int, Gw: int, Gh: int, T: int,
+                            grid_bits=16, mlp_bits=16) -> float:
+    """Bits per texel per key of the 8-channel BC4 map + 8-channel grid + MLP layout.
+
+    BC4 stores 8 bytes per 4x4 block per channel (4 bits per texel per channel).
+    """
+    bits = W * H * N_SPATIAL * 4
+    bits += Gw * Gh * T * N_GRID * grid_bits
+    bits += MLP_SIZE * mlp_bits
+    return bits / (W * H * T)

@@ -1,0 +1,216 @@
+"""Seeded synthetic inputs for the NDGI decode and training path.
+
+This module only draws numbers and lays them out in the library's storage formats; it
+contains none of the method's arithmetic (no block decoding, interpolation or MLP).
+Both the HIP path (through tests and the benchmark) and the CPU reference use it.
+
+Every generator takes a ``numpy.random.Generator`` made by :func:`rng`, whose stream is
+``SeedSequence([seed, config, purpose, index])`` so that each workload, purpose (model,
+queries, requests, target, samples) and step has its own independent stream.
+
+The paper's lightmap dataset is not available; the synthetic workloads stand in for it:
+
+* random models: BC4 blocks with uniformly random bytes (so both BC4 modes and every
+  selector occur), a grid with values uniform in [-1, 1], He-normal decoder weights
+  with zero biases;
+* queries: texel centres of a map at given times, or (u, v, t) uniform in [0, 1);
+* virtual-texturing frames: maps with side 128 * round(2^U[1,5]) and page requests
+  drawn Zipf(1.1) over a seeded ranking of the maps;
+* a temporal lightmap target built from Gaussian lights with day-cycle intensity
+  curves, shadowed by rectangles that move with time.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+N_CH = 8
+HIDDEN = 32
+N_IN = 16
+N_OUT = 3
+MLP_SIZE = HIDDEN * N_IN + HIDDEN + HIDDEN * HIDDEN + HIDDEN + N_OUT * HIDDEN + N_OUT
+
+# purposes of the random streams
+P_MODEL, P_QUERY, P_REQ, P_TARGET, P_SAMPLES, P_INIT = range(6)
+
+
+def rng(config: int, purpose: int, index: int = 0, seed: int = 0) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, config, purpose, index])))
+
+
+# ------------------------------------------------------------------------------ models
+
+def random_bc4(W: int, H: int, g: np.random.Generator) -> np.ndarray:
+    """[H/4][W/4][8 channels][8 bytes] of uniformly random bytes."""
+    assert W % 4 == 0 and H % 4 == 0
+    return g.integers(0, 256, size=(H // 4, W // 4, N_CH, 8), dtype=np.uint8)
+
+
+def random_grid(Gw: int, Gh: int, T: int, dtype, g: np.random.Generator) -> np.ndarray:
+    """[T][Gh][Gw][8], values uniform in [-1, 1], stored in ``dtype`` (round to nearest)."""
+    return g.uniform(-1.0, 1.0, size=(T, Gh, Gw, N_CH)).astype(np.float32).astype(dtype)
+
+
+def he_normal_mlp(dtype, g: np.random.Generator) -> np.ndarray:
+    """Packed [W1 32x16 | b1 | W2 32x32 | b2 | W3 3x32 | b3]; W ~ N(0, 2/fan_in), b = 0."""
+    parts = []
+    for (fo, fi) in ((HIDDEN, N_IN), (HIDDEN, HIDDEN), (N_OUT, HIDDEN)):
+        parts.append(g.normal(0.0, math.sqrt(2.0 / fi), size=fo * fi))
+        parts.append(np.zeros(fo))
+    return np.concatenate(parts).astype(np.float32).astype(dtype)
+
+
+def random_model(W: int, H: int, Gw: int, Gh: int, T: int, grid_dtype=np.float32,
+                 mlp_dtype=np.float32, config: int = 0, index: int = 0) -> dict:
+    g = rng(config, P_MODEL, index)
+    return dict(W=W, H=H, Gw=Gw, Gh=Gh, T=T,
+                bc4=random_bc4(W, H, g),
+                grid=random_grid(Gw, Gh, T, grid_dtype, g),
+                mlp=he_normal_mlp(mlp_dtype, g))
+
+
+# ----------------------------------------------------------------------------- queries
+
+def texel_centre_queries(W: int, H: int, ts) -> np.ndarray:
+    """All texel centres ((x+0.5)/W, (y+0.5)/H) of a W x H map at each t: [len(ts)*H*W][3] f32."""
+    y, x = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    u = ((x + 0.5) / W).astype(np.float32).ravel()
+    v = ((y + 0.5) / H).astype(np.float32).ravel()
+    out = []
+    for t in ts:
+        out.append(np.stack([u, v, np.full_like(u, np.float32(t))], axis=1))
+    return np.concatenate(out, axis=0)
+
+
+def uniform_queries(n: int, g: np.random.Generator) -> np.ndarray:
+    """n queries with u, v, t uniform in [0, 1): [n][3] float32."""
+    q = g.random(size=(n, 3), dtype=np.float32)
+    return np.minimum(q, np.float32(np.nextafter(np.float32(1), np.float32(0))))
+
+
+# ------------------------------------------------------------------ virtual texturing
+
+def vt_map_sides(n_maps: int, g: np.random.Generator, page: int = 128) -> np.ndarray:
+    """Square map sides 128 * round(2^U[1, 5]) in [256, 4096]."""
+    return page * np.round(2.0 ** g.uniform(1.0, 5.0, size=n_maps)).astype(np.int64)
+
+
+def vt_requests(sides, n_req: int, g: np.random.Generator, page: int = 128,
+                zipf_s: float = 1.1):
+    """Page requests of one frame: arrays (model, page_x, page_y, t).
+
+    The map of each request is drawn Zipf(s) over a random ranking of the maps, the page
+    uniformly inside that map and t uniformly in [0, 1).
+    """
+    n_maps = len(sides)
+    rank = g.permutation(n_maps)
+    p = 1.0 / np.arange(1, n_maps + 1) ** zipf_s
+    p /= p.sum()
+    which = rank[g.choice(n_maps, size=n_req, p=p)]
+    npg = np.asarray(sides)[which] // page
+    px = (g.random(n_req) * npg).astype(np.int64)
+    py = (g.random(n_req) * npg).astype(np.int64)
+    t = g.random(n_req, dtype=np.float32)
+    return which.astype(np.int32), px.astype(np.int32), py.astype(np.int32), t
+
+
+# ------------------------------------------------------------- synthetic lightmap target
+
+def light_scene(W: int, H: int, g: np.random.Generator, n_lights: int = 64,
+                n_rects: int = 200) -> dict:
+    """Parameters of the synthetic temporal lightmap (lights and moving occluders)."""
+    s = W / 1024.0
+    return dict(
+        W=W, H=H,
+        mu=np.stack([g.uniform(0, W, n_lights), g.uniform(0, H, n_lights)], 1),
+        sigma=g.uniform(8.0, 64.0, n_lights) * s,
+        amp=10.0 ** g.uniform(-1.0, 1.0, n_lights),
+        colour=g.uniform(0.5, 1.0, (n_lights, 3)),
+        phase=g.uniform(0.0, 1.0, n_lights),
+        rc=np.stack([g.uniform(0, W, n_rects), g.uniform(0, H, n_rects)], 1),
+        rhalf=g.uniform(4.0, 32.0, (n_rects, 2)) * s,
+        rrad=g.uniform(0.0, 32.0, n_rects) * s,
+        rphase=g.uniform(0.0, 1.0, n_rects),
+        ambient=1e-3,
+    )
+
+
+def scene_frame_torch(scene: dict, t: float, device="cpu", rows=None):
+    """One frame of the target at time t, evaluated at texel centres: torch [H][W][3] f32.
+
+    I = ambient + M * sum_l colour_l * amp_l * (1 + sin 2pi(t + phase_l))/2 *
+    exp(-|p - mu_l|^2 / (2 sigma_l^2)), where M is 0 inside any occluder rectangle whose
+    centre moves on a circle of radius rrad with period 1.  ``rows`` selects a row range.
+    """
+    import torch
+    W, H = scene["W"], scene["H"]
+    y_lo, y_hi = (0, H) if rows is None else rows
+    f32 = dict(dtype=torch.float32, device=device)
+    ys = torch.arange(y_lo, y_hi, **f32) + 0.5
+    xs = torch.arange(W, **f32) + 0.5
+    out = torch.zeros((y_hi - y_lo, W, 3), **f32)
+    mu = torch.tensor(scene["mu"], **f32)
+    sig = torch.tensor(scene["sigma"], **f32)
+    a = torch.tensor(scene["amp"] * 0.5 * (1.0 + np.sin(2 * np.pi * (t + scene["phase"]))), **f32)
+    col = torch.tensor(scene["colour"], **f32)
+    for l in range(mu.shape[0]):
+        gx = torch.exp(-((xs - mu[l, 0]) ** 2) / (2 * sig[l] ** 2))
+        gy = torch.exp(-((ys - mu[l, 1]) ** 2) / (2 * sig[l] ** 2))
+        out += (a[l] * gy[:, None] * gx[None, :])[..., None] * col[l]
+    ang = 2 * np.pi * (t + scene["rphase"])
+    cx = scene["rc"][:, 0] + scene["rrad"] * np.cos(ang)
+    cy = scene["rc"][:, 1] + scene["rrad"] * np.sin(ang)
+    lit = torch.ones((y_hi - y_lo, W), dtype=torch.bool, device=device)
+    for r in range(cx.shape[0]):
+        inx = (xs - float(cx[r])).abs() <= float(scene["rhalf"][r, 0])
+        iny = (ys - float(cy[r])).abs() <= float(scene["rhalf"][r, 1])
+        lit &= ~(iny[:, None] & inx[None, :])
+    return scene["ambient"] + out * lit[..., None].to(torch.float32)
+
+
+def scene_target_torch(scene: dict, T: int, device="cpu"):
+    """Full target [T][H][W][3] float16 (round to nearest even), frames at t_k = k/T."""
+    import torch
+    W, H = scene["W"], scene["H"]
+    out = torch.empty((T, H, W, 3), dtype=torch.float16, device=device)
+    step = max(1, (1 << 22) // W)
+    for k in range(T):
+        for y0 in range(0, H, step):
+            y1 = min(H, y0 + step)
+            out[k, y0:y1] = scene_frame_torch(scene, k / T, device, (y0, y1)).to(torch.float16)
+    return out
+
+
+# ------------------------------------------------------------------------ training
+
+def train_samples(B: int, W: int, H: int, T: int, g: np.random.Generator):
+    """B training samples (x, y, k) drawn uniformly with replacement."""
+    x = g.integers(0, W, size=B)
+    y = g.integers(0, H, size=B)
+    k = g.integers(0, T, size=B)
+    return x.astype(np.int64), y.astype(np.int64), k.astype(np.int64)
+
+
+def pack_samples(x, y, k) -> np.ndarray:
+    """Packed uint32 sample words x | y << 12 | k << 24 (x, y < 4096, k < 256)."""
+    x = np.asarray(x, dtype=np.uint32)
+    y = np.asarray(y, dtype=np.uint32)
+    k = np.asarray(k, dtype=np.uint32)
+    assert x.max(initial=0) < 4096 and y.max(initial=0) < 4096 and k.max(initial=0) < 256
+    return x | (y << np.uint32(12)) | (k << np.uint32(24))
+
+
+def train_init(W: int, H: int, Gw: int, Gh: int, T: int, mean_rgb, g: np.random.Generator) -> dict:
+    """Initial trainable state (float32).
+
+    e1 ~ U[0, 0.5), e2 ~ U[0.5, 1], w ~ U[0, 1], grid ~ N(0, 0.1^2), decoder He-normal
+    with zero biases except b3 = log(mean target per channel).
+    """
+    ep = np.stack([g.uniform(0.0, 0.5, (H // 4, W // 4, N_CH)),
+                   g.uniform(0.5, 1.0, (H // 4, W // 4, N_CH))], axis=-1).astype(np.float32)
+    w = g.uniform(0.0, 1.0, (H, W, N_CH)).astype(np.float32)
+    grid = (0.1 * g.standard_normal((T, Gh, Gw, N_CH))).astype(np.float32)
+    mlp = he_normal_mlp(np.float32, g)
+    mlp[MLP_SIZE - 3:] = np.log(np.maximum(np.asarray(mean_rgb, dtype=np.float64), 1e-6)).astype(np.float32)
+    return dict(dims=dict(W=W, H=H, Gw=Gw, Gh=Gh, T=T), endpoints=ep, weights=w, grid=grid, mlp=mlp)
