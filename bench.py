@@ -1,0 +1,291 @@
+#!/usr/bin/env python3
+"""Benchmark of the NDGI decode hot path on one MI355X.
+
+One step = the 4096x4096 workload: decode every texel of the atlas at one time t through
+the persistent page decoder (1024 pages of 128^2), then 16,000,000 uniformly random
+(u, v, t) queries, both on the FP16 MFMA path.  Inputs are resident in device memory
+before the timed region.  The same JSON line also reports the FP32 path on the same
+step, a 32-map virtual-texturing frame (p50 / p99), the training step with BC simulation
+(1024^2 x 24, 2^18 samples), the roofline of the dominant kernel and the CPU oracle
+timed on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c2|c5]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "decoded texels/s (BC fetch+interp+MLP), FP16 MFMA vs FP32; train texels/s"
+HBM_PEAK_GBS = 8000.0
+W = H = 4096
+GW = GH = 1024
+T = 24
+N_RANDOM = 16_000_000
+PAGE = 128
+# algorithmic bytes per texel of the frame decode: 4 B of BC4 blocks (8 ch x 8 B per 16
+# texels), 2 B of FP16 grid (the two keys' 1024^2 x 8 x 2 B spread over 4096^2 texels),
+# 6 B of FP16 RGB out
+FRAME_BYTES_PER_TEXEL = 4.0 + 2.0 + 6.0
+# random queries: every BC4 block and every grid node of all 24 keys is read at least once
+# (compulsory), plus 12 B of query in and 6 B of RGB out per query
+RANDOM_COMPULSORY_BYTES = (W * H // 16 * 8 * 8) + (T * GH * GW * 8 * 2) + N_RANDOM * (12 + 6)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+class Timer:
+    """HIP events on torch's current stream (the stream every launch below uses)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.pairs = []
+
+    def start(self):
+        e = self.torch.cuda.Event(enable_timing=True)
+        e.record()
+        return e
+
+    def stop(self, e0):
+        e1 = self.torch.cuda.Event(enable_timing=True)
+        e1.record()
+        self.pairs.append((e0, e1))
+
+    def ms(self):
+        return [a.elapsed_time(b) for a, b in self.pairs]
+
+
+def c2_inputs(torch, N, I):
+    m = I.random_model_torch(W, H, GW, GH, T, seed=2, device="cuda")
+    dm = N.DeviceModel(W, H, GW, GH, T, m["bc4"], m["grid"], m["mlp"])
+    marr = N.models_array([dm])
+    t = 0.3711
+    py, px = torch.meshgrid(torch.arange(H // PAGE), torch.arange(W // PAGE), indexing="ij")
+    px = px.reshape(-1).numpy()
+    py = py.reshape(-1).numpy()
+    n_pages = px.size
+    rq = N.page_requests([0] * n_pages, px, py, [t] * n_pages, py * PAGE * W + px * PAGE)
+    nreq = torch.tensor([n_pages], dtype=torch.int32, device="cuda")
+    q = I.uniform_queries_torch(N_RANDOM, seed=3, device="cuda")
+    return dm, marr, rq, nreq, n_pages, q
+
+
+def run_c2(args, torch, N, I, ctx):
+    dm, marr, rq, nreq, n_pages, q = c2_inputs(torch, N, I)
+    out = {}
+    for prec, name in ((N.PREC_F16, "f16"), (N.PREC_F32, "f32")):
+        dt = torch.float16 if prec == N.PREC_F16 else torch.float32
+        frame = torch.empty((W * H, 3), dtype=dt, device="cuda")
+        rnd = torch.empty((N_RANDOM, 3), dtype=dt, device="cuda")
+
+        def step(tf=None, tr=None):
+            e = tf.start() if tf else None
+            ctx.decode_pages(marr, 1, rq, nreq, n_pages, PAGE, frame, W, prec)
+            if tf:
+                tf.stop(e)
+                e = tr.start()
+            ctx.decode(dm, q, prec, out=rnd)
+            if tr:
+                tr.stop(e)
+
+        steps = args.steps if prec == N.PREC_F16 else max(3, args.steps // 4)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        tf, tr = Timer(torch), Timer(torch)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step(tf, tr)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        fm, rm = tf.ms(), tr.ms()
+        out[name] = dict(steps=steps, wall_s=wall, frame_ms=sum(fm) / len(fm), random_ms=sum(rm) / len(rm))
+        log(f"C2 {name}: {1e3 * wall / steps:.3f} ms/step (frame {out[name]['frame_ms']:.3f} ms, "
+            f"random {out[name]['random_ms']:.3f} ms)")
+        del frame, rnd
+    return out, (dm, q)
+
+
+def run_c3(args, torch, N, I, ctx, frames=110, warm=10):
+    """32 maps, 2000 page requests per frame (Zipf 1.1), one graph replay per frame."""
+    import numpy as np
+    g = I.rng(3, I.P_MODEL)
+    sides = I.vt_map_sides(32, g)
+    models = []
+    for i, s in enumerate(sides):
+        m = I.random_model_torch(int(s), int(s), int(s) // 4, int(s) // 4, T, seed=1000 + i, device="cuda")
+        models.append(N.DeviceModel(int(s), int(s), int(s) // 4, int(s) // 4, T, m["bc4"], m["grid"], m["mlp"]))
+    marr = N.models_array(models)
+    n_req, per_row = 2000, 50
+    pitch = per_row * PAGE
+    dst = torch.empty((((n_req + per_row - 1) // per_row) * PAGE * pitch, 3), dtype=torch.float16, device="cuda")
+    offs = np.array([(i // per_row) * PAGE * pitch + (i % per_row) * PAGE for i in range(n_req)], dtype=np.int64)
+    all_rq = []
+    for f in range(frames):
+        mi, px, py, t = I.vt_requests(sides, n_req, I.rng(3, I.P_REQ, f))
+        all_rq.append(N.page_requests(mi, px, py, t, offs))
+    rq = torch.empty_like(all_rq[0])
+    nreq = torch.tensor([n_req], dtype=torch.int32, device="cuda")
+    tm = Timer(torch)
+    texels = n_req * PAGE * PAGE
+    for f in range(frames):
+        rq.copy_(all_rq[f])
+        e = tm.start()
+        ctx.decode_pages(marr, len(models), rq, nreq, n_req, PAGE, dst, pitch, N.PREC_F16, graph=True)
+        tm.stop(e)
+    torch.cuda.synchronize()
+    ms = sorted(tm.ms()[warm:])
+    p50 = ms[len(ms) // 2]
+    p99 = ms[min(len(ms) - 1, int(round(0.99 * (len(ms) - 1))))]
+    log(f"C3 VT frame: p50 {p50:.3f} ms, p99 {p99:.3f} ms ({texels / p50 / 1e6:.1f} G texels/s at p50)")
+    assert ctx.error_flags() == 0
+    return dict(p50_ms=p50, p99_ms=p99, texels_per_frame=texels, maps=[int(s) for s in sides])
+
+
+def run_c4(args, torch, N, I, ctx, steps=None, warm=3):
+    """Training step with BC simulation: 1024^2 x 24 target, 2^18 samples, Adam."""
+    import numpy as np
+    from paper_2604_12625_amd.train import Trainer
+    Wt = Ht = 1024
+    Gt = 256
+    scene = I.light_scene(Wt, Ht, I.rng(4, I.P_TARGET))
+    tgt = I.scene_target_torch(scene, T, device="cuda")
+    mean = tgt.float().mean(dim=(0, 1, 2)).cpu().numpy()
+    st = I.train_init(Wt, Ht, Gt, Gt, T, mean, I.rng(4, I.P_INIT))
+    tr = Trainer(ctx, st, lr_feat=1e-2, lr_mlp=1e-3)
+    tgt_bits = tgt.view(torch.int16)
+    B = 1 << 18
+    steps = steps or args.steps
+    smp = [I.train_samples_torch(B, Wt, Ht, T, seed=4000 + i) for i in range(warm + steps)]
+    for i in range(warm):
+        tr.step(smp[i], tgt_bits)
+    torch.cuda.synchronize()
+    tm = Timer(torch)
+    t0 = time.perf_counter()
+    for i in range(steps):
+        e = tm.start()
+        tr.step(smp[warm + i], tgt_bits)
+        tm.stop(e)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = sum(tm.ms()) / steps
+    loss = float(tr.loss.item())
+    log(f"C4 train: {ms:.3f} ms/step, {B / ms / 1e6:.3f} G samples/s, loss {loss:.4e}")
+    return dict(ms_per_step=ms, samples_per_s=B / (wall / steps), batch=B, params=int(tr.n_params), loss=loss)
+
+
+def cpu_baseline(args, dm, q, seconds):
+    """The CPU oracle decoding a bounded sample of the same workload on this host."""
+    import numpy as np
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:
+        threadpool_limits = None
+    from oracle import ndgi_oracle as O
+    model = dict(W=W, H=H, Gw=GW, Gh=GH, T=T, bc4=dm.bc4.cpu().numpy(), grid=dm.grid.cpu().numpy(),
+                 mlp=dm.mlp.cpu().numpy())
+    qs = q[: 1 << 20].cpu().numpy()
+    chunk = 1 << 15
+    done = 0
+    t0 = time.perf_counter()
+    ctxm = threadpool_limits(limits=1) if threadpool_limits else None
+    try:
+        while True:
+            a = (done // chunk) % ((1 << 20) // chunk)
+            O.decode(model, qs[a * chunk:(a + 1) * chunk])
+            done += chunk
+            if time.perf_counter() - t0 >= seconds:
+                break
+    finally:
+        if ctxm is not None:
+            ctxm.__exit__(None, None, None)
+    el = time.perf_counter() - t0
+    return dict(value=done / el, unit="texels/s", cores=1, kind="oracle",
+                sample=f"{done} of the workload's uniform random queries (chunks of {chunk}), FP64 numpy, "
+                       f"1 thread, {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c5"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--headline-only", action="store_true", help="skip the VT and training legs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
+              "see the sharding notes of the design document", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2604_12625_amd import inputs as I
+    from paper_2604_12625_amd import ndgi as N
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    ctx = N.Context(0)
+    if args.workload == "c5":
+        from paper_2604_12625_amd.large import run_c5
+        print(json.dumps(run_c5(args, torch, N, I, ctx)), flush=True)
+        return
+
+    c2, (dm, q) = run_c2(args, torch, N, I, ctx)
+    f16, f32 = c2["f16"], c2["f32"]
+    texels_per_step = W * H + N_RANDOM
+    ms_step = 1e3 * f16["wall_s"] / f16["steps"]
+    value = texels_per_step / (f16["wall_s"] / f16["steps"])
+    fp32_value = texels_per_step / (f32["wall_s"] / f32["steps"])
+
+    frame_bytes = FRAME_BYTES_PER_TEXEL * W * H
+    rl_frame = dict(bound="hbm", achieved=frame_bytes / (f16["frame_ms"] * 1e-3) / 1e9, peak=HBM_PEAK_GBS,
+                    unit="GB/s", traffic=None, kernel="k_decode_pages<FP16>", bytes_per_launch=frame_bytes)
+    rl_frame["frac"] = rl_frame["achieved"] / HBM_PEAK_GBS
+    rl_rand = dict(bound="hbm", achieved=RANDOM_COMPULSORY_BYTES / (f16["random_ms"] * 1e-3) / 1e9,
+                   peak=HBM_PEAK_GBS, unit="GB/s", traffic=None, kernel="k_decode_query<FP16>",
+                   bytes_per_launch=RANDOM_COMPULSORY_BYTES)
+    rl_rand["frac"] = rl_rand["achieved"] / HBM_PEAK_GBS
+    dominant = rl_rand if f16["random_ms"] >= f16["frame_ms"] else rl_frame
+    other = rl_frame if dominant is rl_rand else rl_rand
+
+    res = {
+        "metric": METRIC, "value": value, "unit": "texels/s", "n_gpus": 1, "steps": f16["steps"],
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f16", "data": "synthetic",
+        "config": {"workload": "4096x4096 atlas, T=24 keys; 8-channel BC4 spatial map + 1024^2 x 24 x 8 FP16 grid; "
+                               "16-32-32-3 FP16 decoder; step = full frame at one t (16,777,216 texels, 1024 "
+                               "pages of 128^2) + 16,000,000 uniform random (u,v,t) queries",
+                   "texels_per_step": texels_per_step, "precision": "FP16 MFMA, FP32 accumulate, FP16 out"},
+        "roofline": dominant,
+        "roofline_other": other,
+        "fp16_frame_texels_per_s": W * H / (f16["frame_ms"] * 1e-3),
+        "fp16_random_queries_per_s": N_RANDOM / (f16["random_ms"] * 1e-3),
+        "fp32_texels_per_s": fp32_value,
+        "fp32_frame_texels_per_s": W * H / (f32["frame_ms"] * 1e-3),
+        "fp32_random_queries_per_s": N_RANDOM / (f32["random_ms"] * 1e-3),
+        "fp16_over_fp32": value / fp32_value,
+    }
+    if not args.headline_only:
+        res["vt_frame"] = run_c3(args, torch, N, I, ctx)
+        c4 = run_c4(args, torch, N, I, ctx)
+        res["train_texels_per_s"] = c4["samples_per_s"]
+        res["train"] = c4
+    if not args.no_cpu_baseline:
+        log("CPU oracle baseline ...")
+        res["cpu_baseline"] = cpu_baseline(args, dm, q, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,251 @@
+/*
+ * ndgi.h -- C ABI of the MI355X (gfx950) Neural Dynamic GI decode and training library.
+ *
+ * The method (arXiv 2604.12625) represents a set of time-varying lightmaps by feature
+ * maps plus a small MLP: the lighting at (u, v, t) is I = H_Theta(u, v, t) (Sec. 3.1,
+ * Eq. 3).  This library implements the data-parallel hot path of that representation
+ * for one concrete layout:
+ *
+ *   spatial map  W x H texels, 8 channels, each channel BC4 block-compressed
+ *                (two 8-bit endpoints and sixteen 3-bit selectors per 4x4 block;
+ *                Sec. 3.4, Eq. 6-7 and supplementary Sec. B)
+ *   grid         Gw x Gh nodes x T time keys, 8 channels, FP32 or FP16, sampled
+ *                bilinearly in space and linearly in time (the spatio-temporal feature
+ *                map of Sec. 3.3)
+ *   decoder      16 -> 32 -> 32 -> 3 MLP, ReLU hidden layers, exponential output
+ *                (HDR RGB); inputs are [S_0..S_7, G_0..G_7]
+ *
+ * Conventions shared by every entry point
+ *   - Every pointer named *_dev or documented as "device" is device memory of the GPU
+ *     the context was created on; "host" pointers are ordinary host memory.
+ *   - The caller owns every buffer it passes.  The library never frees caller memory
+ *     and never allocates per call; a context owns only its own workspace.
+ *   - Calls are asynchronous on the given stream (0 = the null stream).  Arguments are
+ *     validated before anything is launched, so an argument error writes nothing.
+ *     Faults inside kernels surface at the caller's next synchronisation.
+ *   - Return value: NDGI_OK (0) or a negative NDGI_ERR_* code; ndgi_last_error()
+ *     returns a message for the calling thread's last failure.  No C++ exception
+ *     crosses this interface.
+ *   - A context may be used by one host thread at a time.
+ */
+#ifndef NDGI_H
+#define NDGI_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define NDGI_OK                0
+#define NDGI_ERR_INVALID_ARG  (-1)
+#define NDGI_ERR_UNSUPPORTED  (-2)
+#define NDGI_ERR_HIP          (-3)
+#define NDGI_ERR_OUT_OF_MEMORY (-4)
+
+/* storage dtypes */
+#define NDGI_DTYPE_F32 0
+#define NDGI_DTYPE_F16 1
+
+/* compute precision of the decode path
+ *   NDGI_PREC_F32: FP32 feature math, FP32 matrix cores (MFMA), FP32 output [n][3]
+ *   NDGI_PREC_F16: FP32 feature math rounded once to FP16, FP16 MFMA with FP32
+ *                  accumulation, FP32 exp, FP16 output [n][3] */
+#define NDGI_PREC_F32 0
+#define NDGI_PREC_F16 1
+
+/* device error flags (ndgi_get_error_flags) */
+#define NDGI_FLAG_BAD_PAGE_REQUEST 1u
+
+/* number of packed decoder parameters: [W1 32x16 | b1 32 | W2 32x32 | b2 32 | W3 3x32 | b3 3],
+ * row-major W[out][in], layer y = W x + b */
+#define NDGI_MLP_SIZE 1699
+
+/* A compressed model Theta (Eq. 5) in the layout above.  64 bytes, the same layout on
+ * host and device (ndgi_decode_pages reads an array of these from device memory). */
+typedef struct ndgi_model {
+    int32_t W, H;        /* spatial map size in texels; multiples of 4, 4..16384        */
+    int32_t Gw, Gh;      /* grid nodes per row / column, >= 1                          */
+    int32_t T;           /* time keys at t_k = k/T on a periodic day, 1..1024           */
+    int32_t grid_dtype;  /* NDGI_DTYPE_F32 or NDGI_DTYPE_F16                            */
+    int32_t mlp_dtype;   /* NDGI_DTYPE_F32 or NDGI_DTYPE_F16                            */
+    int32_t reserved0;   /* must be 0                                                   */
+    const uint8_t* bc4;  /* device [H/4][W/4][8 channels][8 bytes]; the 8 single-channel
+                            blocks of one 4x4 footprint are contiguous (64 bytes)          */
+    const void* grid;    /* device [T][Gh][Gw][8] in grid_dtype                          */
+    const void* mlp;     /* device [NDGI_MLP_SIZE] in mlp_dtype                          */
+    const void* reserved1;
+} ndgi_model;
+
+/* One virtual-texturing page request (supplementary Sec. C: a tile of a lightmap decoded
+ * into the physical texture).  24 bytes. */
+typedef struct ndgi_page_req {
+    int32_t model;       /* index into the models array                                 */
+    int32_t page_x;      /* page column: texels x = page*page_x .. page*page_x+page-1   */
+    int32_t page_y;      /* page row                                                    */
+    float t;             /* time of day; wrapped into [0, 1)                            */
+    int64_t dst_offset;  /* texel index in dst of the page's texel (0, 0)               */
+} ndgi_page_req;
+
+typedef struct ndgi_ctx ndgi_ctx;
+
+/* ---------------------------------------------------------------- context, errors */
+
+/* Create a context on HIP device `device` (it becomes current for the calling thread).
+ * Allocates the context workspace (error flags, per-wave gradient partials, loss and
+ * statistics scratch).  *out receives the context.  Errors: INVALID_ARG (bad device or
+ * out == NULL), HIP, OUT_OF_MEMORY. */
+int ndgi_create(ndgi_ctx** out, int32_t device);
+
+/* Release the context, its workspace and any captured graphs.  NULL is a no-op. */
+int ndgi_destroy(ndgi_ctx* ctx);
+
+/* Message describing the calling thread's most recent failed call ("" if none).
+ * The pointer stays valid until the thread's next library call. */
+const char* ndgi_last_error(void);
+
+/* Synchronise `stream`, then read and clear the context's device error flags
+ * (NDGI_FLAG_* bits) into *flags_out (host). */
+int ndgi_get_error_flags(ndgi_ctx* ctx, hipStream_t stream, uint32_t* flags_out);
+
+/* ---------------------------------------------------------------- block decoder */
+
+/* Decode n BC4 blocks (supplementary Sec. B: texel = interpolation of two endpoints;
+ * Eq. 7), bit-exactly.  blocks: device [n][8] bytes (e0, e1, 48-bit little-endian
+ * selector field; texel s = 4*row + col uses bits 3s..3s+2).  out16: device [n][16]
+ * bytes, texel s at out16[16*i + s].  e0 > e1 selects the 8-value palette
+ * round((7-j)/7 e0 + j/7 e1), j = 1..6; otherwise the 6-value palette
+ * round((5-j)/5 e0 + j/5 e1), j = 1..4, plus 0 and 255; selector 0 = e0, 1 = e1.
+ * n = 0 is a no-op.  Errors: INVALID_ARG (n < 0, NULL pointers when n > 0). */
+int ndgi_bc4_decode_blocks(const uint8_t* blocks, int64_t n, uint8_t* out16, hipStream_t stream);
+
+/* ---------------------------------------------------------------- decode */
+
+/* Random-access decode of n queries (Sec. 3.1 Eq. 3; Sec. 3.3 "random access"):
+ *   uvt: device float [n][3] = (u, v, t).  u, v in [0, 1) address texel centres
+ *        ((u*W - 0.5), (v*H - 0.5) in texel units); outside [0, 1) they clamp to the
+ *        edge.  t is wrapped into [0, 1); keys are periodic (key T-1 blends into key 0).
+ *        A query with a non-finite coordinate decodes to NaN.
+ *   out: device [n][3]; float if prec == NDGI_PREC_F32, _Float16 if NDGI_PREC_F16.
+ *   model: host pointer to a descriptor whose buffers are device memory.
+ * n = 0 is a no-op.  Errors: INVALID_ARG (bad descriptor, sizes, prec, NULL buffers). */
+int ndgi_decode(ndgi_ctx* ctx, const ndgi_model* model, const float* uvt, int64_t n,
+                void* out, int32_t prec, hipStream_t stream);
+
+/* Batched virtual-texturing page decode (Sec. 3.5; supplementary Sec. C): every valid
+ * request decodes the page x page texel centres of its page of models_dev[model] at its
+ * time t and writes texel (i, j) of the page to dst[dst_offset + j*dst_pitch + i]
+ * ([..][3] elements of float or _Float16 by prec).  One persistent launch covers all
+ * requests; each map may have its own size and decoder weights.
+ *   models_dev: device array of n_models descriptors.
+ *   reqs_dev:   device array of at least max_reqs requests.
+ *   n_reqs_dev: device int32 holding the number of requests to serve (read by the
+ *               kernel, clamped to [0, max_reqs]) so that a captured graph can be
+ *               replayed with new requests.
+ *   page:       page side in texels, a multiple of 16, 16..4096.
+ * A request whose model index is outside [0, n_models) or whose page does not lie
+ * inside its map is skipped and sets NDGI_FLAG_BAD_PAGE_REQUEST.  The caller guarantees
+ * that dst holds every texel addressed by a valid request.
+ * Errors: INVALID_ARG (sizes, prec, NULL pointers). */
+int ndgi_decode_pages(ndgi_ctx* ctx, const ndgi_model* models_dev, int32_t n_models,
+                      const ndgi_page_req* reqs_dev, const int32_t* n_reqs_dev,
+                      int32_t max_reqs, int32_t page, void* dst, int64_t dst_pitch,
+                      int32_t prec, hipStream_t stream);
+
+/* Same work as ndgi_decode_pages, launched as a HIP graph: the first call for a given
+ * argument set captures the persistent launch into a graph owned by the context, later
+ * calls with the same arguments replay it (new requests and counts are picked up from
+ * device memory).  Errors: as ndgi_decode_pages, plus HIP. */
+int ndgi_decode_pages_graph(ndgi_ctx* ctx, const ndgi_model* models_dev, int32_t n_models,
+                            const ndgi_page_req* reqs_dev, const int32_t* n_reqs_dev,
+                            int32_t max_reqs, int32_t page, void* dst, int64_t dst_pitch,
+                            int32_t prec, hipStream_t stream);
+
+/* Launch shape of the page decoder, chosen by an autotuner: each work item is a
+ * (16*tile_w) x (4*tile_h) texel sub-tile of one page; waves_per_cu persistent waves per
+ * compute unit.  tile_w, tile_h in 1..32 (page must be a multiple of both sub-tile sides,
+ * checked per call); waves_per_cu in 1..32.  Also sets the launch size of ndgi_decode.
+ * Drops captured graphs.  Errors: INVALID_ARG. */
+int ndgi_set_launch(ndgi_ctx* ctx, int32_t tile_w, int32_t tile_h, int32_t waves_per_cu);
+
+/* ---------------------------------------------------------------- training */
+
+/* Trainable state of one model under BC simulation (Sec. 3.4, Eq. 6-7).  All arrays are
+ * float32 device memory with one flat layout shared by params, grads, adam_m, adam_v:
+ *   [ endpoints [H/4][W/4][8][2]  (e1, e2 of each block and channel, in [0, 1])
+ *   | weights   [H][W][8]         (per-texel interpolation weight, in [0, 1])
+ *   | grid      [T][Gh][Gw][8]
+ *   | mlp       [NDGI_MLP_SIZE] ]
+ * ndgi_train_param_count() gives the total length. */
+typedef struct ndgi_train_state {
+    int32_t W, H, Gw, Gh, T;  /* W, H multiples of 4, <= 4096; T <= 256 */
+    int32_t reserved0;
+    float* params;
+    float* grads;
+    float* adam_m;
+    float* adam_v;
+    int64_t step;             /* Adam steps taken so far; ADAM and FUSED increment it */
+    float lr_feat;            /* Adam learning rate of endpoints, weights and grid      */
+    float lr_mlp;             /* Adam learning rate of the decoder                      */
+    float beta1, beta2, eps;
+    float reserved1;
+} ndgi_train_state;
+
+/* One batch of training samples.  A sample is texel (x, y) of key k, i.e. t = k/T. */
+typedef struct ndgi_batch {
+    const uint32_t* samples;  /* device [n]: x | y << 12 | k << 24                       */
+    int64_t n;                /* number of samples, >= 1                                 */
+    const uint16_t* target;   /* device FP16 bits [T][H][W][3] (LOSS_GRAD, FUSED)         */
+    float* pred;              /* device [n][3] (written by FORWARD; optional otherwise)   */
+    const float* grad_pred;   /* device [n][3] dLoss/dpred (BACKWARD)                     */
+} ndgi_batch;
+
+#define NDGI_TRAIN_FORWARD   0  /* pred = H_Theta(samples) under BC simulation               */
+#define NDGI_TRAIN_BACKWARD  1  /* grads += d(sum grad_pred . pred)/dparams (features recomputed) */
+#define NDGI_TRAIN_LOSS_GRAD 2  /* *loss_dev = L2 loss (FP64); grads += dL/dparams           */
+#define NDGI_TRAIN_FUSED     3  /* LOSS_GRAD, then ADAM                                      */
+#define NDGI_TRAIN_ADAM      4  /* Adam step on all params (PyTorch semantics, dense), clamp
+                                   endpoints and weights to [0, 1], zero grads, step += 1    */
+#define NDGI_TRAIN_ZERO_GRAD 5  /* grads = 0                                                 */
+
+/* Total number of float parameters of a state with the given sizes. */
+int64_t ndgi_train_param_count(int32_t W, int32_t H, int32_t Gw, int32_t Gh, int32_t T);
+
+/* Run one training operation (modes above) on `state` (host struct of device pointers;
+ * its `step` is updated on the host by ADAM and FUSED).  loss_dev: device double, written
+ * by LOSS_GRAD and FUSED (mean over samples and channels of (pred - target)^2; the sum is
+ * accumulated in FP64).  The quantisation is E = rint(fl32(255 e)), J = rint(fl32(7 w)),
+ * texel value floor(((7-J) E1 + J E2 + 3)/7) / 255; gradients reach e1, e2, w through the
+ * straight-through derivative of Eq. 7 at (E/255, J/7).
+ * Errors: INVALID_ARG (sizes, mode, NULL pointers needed by the mode). */
+int ndgi_train_step(ndgi_ctx* ctx, ndgi_train_state* state, const ndgi_batch* batch,
+                    int32_t mode, double* loss_dev, hipStream_t stream);
+
+/* Export the trained state as a decodable model (Sec. 3.4, last paragraph): BC4 blocks
+ * whose decode equals the BC-simulated texels bit for bit (E1 > E2: (e0, e1) = (E1, E2);
+ * E1 < E2: swapped with J -> 7 - J; E1 = E2: 6-value block of selector 0), the grid and
+ * the decoder converted to grid_dtype / mlp_dtype (round to nearest even).
+ *   bc4_out: device [H/4][W/4][8][8]; grid_out: device [T][Gh][Gw][8]; mlp_out: device
+ *   [NDGI_MLP_SIZE].  Errors: INVALID_ARG. */
+int ndgi_export(ndgi_ctx* ctx, const ndgi_train_state* state, uint8_t* bc4_out,
+                void* grid_out, int32_t grid_dtype, void* mlp_out, int32_t mlp_dtype,
+                hipStream_t stream);
+
+/* ---------------------------------------------------------------- evaluation */
+
+/* Per-tile statistics for the tiled PSNR of supplementary Sec. D.2, in FP64.
+ *   pred:   device [H][W][3] of pred_dtype (one decoded map)
+ *   target: device FP16 bits [H][W][3]
+ *   stats:  device double [ceil(H/tile)][ceil(W/tile)][3] = (max of target, min of
+ *           target, sum of squared error over the tile's texels and channels).
+ * tile in 1..4096.  Errors: INVALID_ARG. */
+int ndgi_tile_stats(ndgi_ctx* ctx, const void* pred, int32_t pred_dtype,
+                    const uint16_t* target, int32_t W, int32_t H, int32_t tile,
+                    double* stats, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NDGI_H */

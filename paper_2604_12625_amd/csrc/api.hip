@@ -1,0 +1,188 @@
+// C ABI entry points: argument validation, context lifecycle, graph capture.
+#include <cstdio>
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace ndgi {
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+int check_model(const ndgi_model* m, const char* who) {
+  if (!m) return fail(NDGI_ERR_INVALID_ARG, "%s: model is NULL", who);
+  if (m->W < 4 || m->H < 4 || m->W > 16384 || m->H > 16384 || (m->W & 3) || (m->H & 3))
+    return fail(NDGI_ERR_INVALID_ARG, "%s: W, H must be multiples of 4 in [4, 16384] (got %d x %d)", who, m->W, m->H);
+  if (m->Gw < 1 || m->Gh < 1 || m->Gw > 16384 || m->Gh > 16384)
+    return fail(NDGI_ERR_INVALID_ARG, "%s: grid size %d x %d out of range", who, m->Gw, m->Gh);
+  if (m->T < 1 || m->T > 1024) return fail(NDGI_ERR_INVALID_ARG, "%s: T=%d out of range", who, m->T);
+  if ((m->grid_dtype != NDGI_DTYPE_F32 && m->grid_dtype != NDGI_DTYPE_F16) ||
+      (m->mlp_dtype != NDGI_DTYPE_F32 && m->mlp_dtype != NDGI_DTYPE_F16))
+    return fail(NDGI_ERR_INVALID_ARG, "%s: unknown dtype", who);
+  if (m->reserved0 != 0) return fail(NDGI_ERR_INVALID_ARG, "%s: reserved0 must be 0", who);
+  if (!m->bc4 || !m->grid || !m->mlp) return fail(NDGI_ERR_INVALID_ARG, "%s: NULL model buffer", who);
+  return NDGI_OK;
+}
+
+static int check_pages(ndgi_ctx* ctx, const ndgi_model* models, int32_t n_models, const ndgi_page_req* reqs,
+                       const int32_t* n_reqs, int32_t max_reqs, int32_t page, void* dst, int64_t pitch, int32_t prec) {
+  if (!ctx) return fail(NDGI_ERR_INVALID_ARG, "decode_pages: ctx is NULL");
+  if (prec != NDGI_PREC_F32 && prec != NDGI_PREC_F16) return fail(NDGI_ERR_INVALID_ARG, "decode_pages: bad prec %d", prec);
+  if (n_models < 0 || max_reqs < 0) return fail(NDGI_ERR_INVALID_ARG, "decode_pages: negative count");
+  if (page < 16 || page > 4096 || (page & 15))
+    return fail(NDGI_ERR_INVALID_ARG, "decode_pages: page=%d must be a multiple of 16 in [16, 4096]", page);
+  if (page % (16 * ctx->tile_w) || page % (4 * ctx->tile_h))
+    return fail(NDGI_ERR_INVALID_ARG, "decode_pages: page=%d is not a multiple of the sub-tile %dx%d", page,
+                16 * ctx->tile_w, 4 * ctx->tile_h);
+  if (pitch < page) return fail(NDGI_ERR_INVALID_ARG, "decode_pages: dst_pitch=%lld < page", (long long)pitch);
+  if (!n_reqs || !dst || (n_models > 0 && !models) || (max_reqs > 0 && !reqs))
+    return fail(NDGI_ERR_INVALID_ARG, "decode_pages: NULL pointer");
+  return NDGI_OK;
+}
+
+}  // namespace ndgi
+
+using namespace ndgi;
+
+extern "C" {
+
+const char* ndgi_last_error(void) { return g_last_error.c_str(); }
+
+int ndgi_create(ndgi_ctx** out, int32_t device) {
+  clear_error();
+  if (!out) return fail(NDGI_ERR_INVALID_ARG, "create: out is NULL");
+  *out = nullptr;
+  int n = 0;
+  NDGI_HIP(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(NDGI_ERR_INVALID_ARG, "create: device %d of %d", device, n);
+  NDGI_HIP(hipSetDevice(device));
+  ndgi_ctx* c = new ndgi_ctx();
+  c->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    delete c;
+    return fail(NDGI_ERR_HIP, "create: hipGetDeviceProperties failed");
+  }
+  c->n_cu = prop.multiProcessorCount;
+  c->train_waves = c->n_cu * 8;
+  bool ok = hipMalloc(&c->flags_dev, 256) == hipSuccess &&
+            hipMalloc(&c->partials_dev, sizeof(float) * (size_t)c->train_waves * kPartialStride) == hipSuccess &&
+            hipMalloc(&c->loss_part_dev, sizeof(double) * (size_t)c->train_waves) == hipSuccess &&
+            hipMemset(c->flags_dev, 0, 256) == hipSuccess &&
+            hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) == hipSuccess;
+  if (!ok) {
+    ndgi_destroy(c);
+    return fail(NDGI_ERR_OUT_OF_MEMORY, "create: workspace allocation failed");
+  }
+  *out = c;
+  return NDGI_OK;
+}
+
+int ndgi_destroy(ndgi_ctx* c) {
+  clear_error();
+  if (!c) return NDGI_OK;
+  hipSetDevice(c->device);
+  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+  if (c->capture_stream) hipStreamDestroy(c->capture_stream);
+  hipFree(c->flags_dev);
+  hipFree(c->partials_dev);
+  hipFree(c->loss_part_dev);
+  delete c;
+  return NDGI_OK;
+}
+
+int ndgi_get_error_flags(ndgi_ctx* c, hipStream_t s, uint32_t* flags_out) {
+  clear_error();
+  if (!c || !flags_out) return fail(NDGI_ERR_INVALID_ARG, "get_error_flags: NULL argument");
+  NDGI_HIP(hipStreamSynchronize(s));
+  uint32_t f = 0;
+  NDGI_HIP(hipMemcpy(&f, c->flags_dev, sizeof(f), hipMemcpyDeviceToHost));
+  NDGI_HIP(hipMemset(c->flags_dev, 0, sizeof(uint32_t)));
+  *flags_out = f;
+  return NDGI_OK;
+}
+
+int ndgi_bc4_decode_blocks(const uint8_t* blocks, int64_t n, uint8_t* out16, hipStream_t s) {
+  clear_error();
+  if (n < 0) return fail(NDGI_ERR_INVALID_ARG, "bc4_decode_blocks: n < 0");
+  if (n == 0) return NDGI_OK;
+  if (!blocks || !out16) return fail(NDGI_ERR_INVALID_ARG, "bc4_decode_blocks: NULL pointer");
+  return launch_bc4_blocks(blocks, n, out16, s);
+}
+
+int ndgi_decode(ndgi_ctx* c, const ndgi_model* m, const float* uvt, int64_t n, void* out, int32_t prec,
+                hipStream_t s) {
+  clear_error();
+  if (!c) return fail(NDGI_ERR_INVALID_ARG, "decode: ctx is NULL");
+  if (n < 0) return fail(NDGI_ERR_INVALID_ARG, "decode: n < 0");
+  if (prec != NDGI_PREC_F32 && prec != NDGI_PREC_F16) return fail(NDGI_ERR_INVALID_ARG, "decode: bad prec %d", prec);
+  int rc = check_model(m, "decode");
+  if (rc) return rc;
+  if (n == 0) return NDGI_OK;
+  if (!uvt || !out) return fail(NDGI_ERR_INVALID_ARG, "decode: NULL query/output pointer");
+  return launch_decode(c, *m, uvt, n, out, prec, s);
+}
+
+int ndgi_decode_pages(ndgi_ctx* c, const ndgi_model* models, int32_t n_models, const ndgi_page_req* reqs,
+                      const int32_t* n_reqs, int32_t max_reqs, int32_t page, void* dst, int64_t pitch,
+                      int32_t prec, hipStream_t s) {
+  clear_error();
+  int rc = check_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec);
+  if (rc) return rc;
+  return launch_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, s);
+}
+
+int ndgi_decode_pages_graph(ndgi_ctx* c, const ndgi_model* models, int32_t n_models, const ndgi_page_req* reqs,
+                            const int32_t* n_reqs, int32_t max_reqs, int32_t page, void* dst, int64_t pitch,
+                            int32_t prec, hipStream_t s) {
+  clear_error();
+  int rc = check_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec);
+  if (rc) return rc;
+  const GraphKey key{models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, s};
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    hipGraph_t graph = nullptr;
+    NDGI_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+    rc = launch_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, c->capture_stream);
+    hipError_t e = hipStreamEndCapture(c->capture_stream, &graph);
+    if (rc) {
+      if (graph) hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(NDGI_ERR_HIP, "decode_pages_graph: capture failed: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(NDGI_ERR_HIP, "decode_pages_graph: instantiate failed: %s", hipGetErrorString(e));
+    it = c->graphs.emplace(key, exec).first;
+  }
+  NDGI_HIP(hipGraphLaunch(it->second, s));
+  return NDGI_OK;
+}
+
+int ndgi_set_launch(ndgi_ctx* c, int32_t tile_w, int32_t tile_h, int32_t waves_per_cu) {
+  clear_error();
+  if (!c) return fail(NDGI_ERR_INVALID_ARG, "set_launch: ctx is NULL");
+  if (tile_w < 1 || tile_w > 32 || tile_h < 1 || tile_h > 32 || waves_per_cu < 1 || waves_per_cu > 32)
+    return fail(NDGI_ERR_INVALID_ARG, "set_launch: tile_w, tile_h, waves_per_cu must be in [1, 32]");
+  hipSetDevice(c->device);
+  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  c->tile_w = tile_w;
+  c->tile_h = tile_h;
+  c->waves_per_cu = waves_per_cu;
+  return NDGI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,54 @@
+// Host-side internals shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdarg>
+#include <map>
+#include <string>
+#include <tuple>
+
+#include "ndgi.h"
+
+namespace ndgi {
+
+// thread-local message of the last failed call
+int fail(int code, const char* fmt, ...);
+void clear_error();
+
+#define NDGI_HIP(expr)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return ::ndgi::fail(NDGI_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+using GraphKey = std::tuple<const void*, int32_t, const void*, const void*, int32_t, int32_t,
+                            void*, int64_t, int32_t, hipStream_t>;
+
+// per-wave gradient partial slots reserved for the decoder weights
+constexpr int kPartialStride = 1712;   // >= NDGI_MLP_SIZE, multiple of 16
+
+}  // namespace ndgi
+
+struct ndgi_ctx {
+  int device = 0;
+  int n_cu = 0;
+  int tile_w = 1, tile_h = 4, waves_per_cu = 16;  // page decode launch shape
+  hipStream_t capture_stream = nullptr;
+  uint32_t* flags_dev = nullptr;
+  // training workspace
+  int train_waves = 0;          // persistent waves of the training kernel
+  float* partials_dev = nullptr;  // [train_waves][kPartialStride]
+  double* loss_part_dev = nullptr;  // [train_waves]
+  std::map<ndgi::GraphKey, hipGraphExec_t> graphs;
+};
+
+namespace ndgi {
+int check_model(const ndgi_model* m, const char* who);
+int launch_decode(ndgi_ctx* ctx, const ndgi_model& m, const float* uvt, int64_t n, void* out, int prec,
+                  hipStream_t s);
+int launch_pages(ndgi_ctx* ctx, const ndgi_model* models, int32_t n_models, const ndgi_page_req* reqs,
+                 const int32_t* n_reqs, int32_t max_reqs, int32_t page, void* dst, int64_t pitch, int prec,
+                 hipStream_t s);
+int launch_bc4_blocks(const uint8_t* blocks, int64_t n, uint8_t* out, hipStream_t s);
+}  // namespace ndgi

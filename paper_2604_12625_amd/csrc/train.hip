@@ -1,0 +1,619 @@
+// Training under BC simulation: fused forward / loss / backward, deterministic reduction
+// of the decoder gradients, dense Adam, export to BC4, and tiled-PSNR statistics.
+//
+// Forward per 16-sample group (lane (g, j) = sample j, inputs 2g, 2g+1 of each map), as in
+// the decoder but in FP32 MFMA (v_mfma_f32_16x16x4_f32) and with the BC-simulated spatial
+// texel.  Backward chains dz -> dh2 -> dh1 -> dx with the transposed weights as the A
+// operand, so each lane ends with d(loss)/d(its own four inputs) and scatters them to the
+// endpoint, weight and grid gradients with float atomics.  Decoder weight gradients
+// (sum over samples of outer products) run on MFMA with the samples as K: activations are
+// staged through LDS to put hidden units on lanes.  Bias gradients are per-lane sums reduced
+// across the wave with shuffles.  Each wave writes one partial row; a second kernel sums
+// the rows in a fixed order.
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace ndgi {
+
+constexpr int kPadU = 48;   // LDS row stride (floats) of 32-wide activations: rows g, g+1
+                            // of one half-wave land on disjoint banks
+constexpr int kPadX = 16;
+
+struct TrainLds {
+  float x[16 * kPadX];
+  float h1[16 * kPadU];
+  float h2[16 * kPadU];
+  float d1[16 * kPadU];
+  float d2[16 * kPadU];
+  float dz[16 * 4];
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ float half_bits(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
+
+struct TrainDims {
+  int W, H, Gw, Gh, T;
+  int64_t off_w, off_g, off_mlp;   // segment offsets in the flat arrays
+};
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_train(TrainDims d, const float* __restrict__ P, float* __restrict__ G,
+                                                const uint32_t* __restrict__ samples, int64_t n,
+                                                const uint16_t* __restrict__ target, float* __restrict__ pred,
+                                                const float* __restrict__ grad_pred, float inv3n,
+                                                float* __restrict__ partials, double* __restrict__ loss_part,
+                                                uint32_t* __restrict__ flags) {
+  __shared__ TrainLds lds_all[4];
+  const int wave = threadIdx.x >> 6;
+  TrainLds& L = lds_all[wave];
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4, j = lane & 15;
+  const float* ep = P;
+  const float* wts = P + d.off_w;
+  const float* grid = P + d.off_g;
+  const float* mlp = P + d.off_mlp;
+  float* g_ep = G;
+  float* g_w = G + d.off_w;
+  float* g_grid = G + d.off_g;
+
+  // forward weights (as in the FP32 decoder) and transposed weights for the backward pass
+  Dec32 fw;
+  load_dec32(fw, mlp, NDGI_DTYPE_F32, lane);
+  float w3t[2], w2t[2][8], w1t[8];
+#pragma unroll
+  for (int mc = 0; mc < 2; ++mc) {
+    w3t[mc] = g < 3 ? mlp[kOffW3 + g * 32 + 16 * mc + (lane & 15)] : 0.0f;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) w2t[mc][m] = mlp[kOffW2 + unit_of(g, m) * 32 + 16 * mc + (lane & 15)];
+  }
+#pragma unroll
+  for (int m = 0; m < 8; ++m) w1t[m] = mlp[kOffW1 + unit_of(g, m) * 16 + input_of((lane & 15) >> 2, lane & 3)];
+
+  f4v gW2[2][2], gW1[2], gW3[2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    gW1[a] = gW3[a] = f4v{0, 0, 0, 0};
+    gW2[a][0] = gW2[a][1] = f4v{0, 0, 0, 0};
+  }
+  float gb1[8], gb2[8], gb3 = 0.0f;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) gb1[e] = gb2[e] = 0.0f;
+  double loss = 0.0;
+
+  const int64_t groups = (n + 15) >> 4;
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  const int64_t wave_id = (int64_t)blockIdx.x * 4 + wave;
+  for (int64_t grp = wave_id; grp < groups; grp += nwaves) {
+    const int64_t s = (grp << 4) + j;
+    bool valid = s < n;
+    uint32_t word = valid ? samples[s] : 0u;
+    int x = word & 0xfff, y = (word >> 12) & 0xfff, k = word >> 24;
+    if (valid && (x >= d.W || y >= d.H || k >= d.T)) {
+      valid = false;
+      if (g == 0) atomicOr(flags, 2u);
+    }
+    if (!valid) x = y = k = 0;
+
+    // ---- inputs: BC-simulated spatial texel (channels 2g, 2g+1) and grid at key k
+    const size_t blk = ((size_t)(y >> 2) * (d.W >> 2) + (x >> 2)) * 8 + 2 * g;   // block-channel index
+    const float4 e4 = *(const float4*)(ep + blk * 2);            // (e1, e2) of channels 2g, 2g+1
+    const float2 w2 = *(const float2*)(wts + ((size_t)y * d.W + x) * 8 + 2 * g);
+    const int E1a = (int)rintf(__fmul_rn(255.0f, e4.x)), E2a = (int)rintf(__fmul_rn(255.0f, e4.y));
+    const int E1b = (int)rintf(__fmul_rn(255.0f, e4.z)), E2b = (int)rintf(__fmul_rn(255.0f, e4.w));
+    const int Ja = (int)rintf(__fmul_rn(7.0f, w2.x)), Jb = (int)rintf(__fmul_rn(7.0f, w2.y));
+    float f[4];
+    f[0] = (float)(((7 - Ja) * E1a + Ja * E2a + 3) / 7) * (1.0f / 255.0f);
+    f[1] = (float)(((7 - Jb) * E1b + Jb * E2b + 3) / 7) * (1.0f / 255.0f);
+    const Axis ax = texel_axis(x, d.Gw, d.W), ay = texel_axis(y, d.Gh, d.H);
+    {
+      float a = 0.0f, b = 0.0f;
+#pragma unroll
+      for (int yy = 0; yy < 2; ++yy)
+#pragma unroll
+        for (int xx = 0; xx < 2; ++xx) {
+          const float w = (yy ? ay.w1 : ay.w0) * (xx ? ax.w1 : ax.w0);
+          const size_t node = ((size_t)k * d.Gh + (yy ? ay.i1 : ay.i0)) * d.Gw + (xx ? ax.i1 : ax.i0);
+          const float2 v = *(const float2*)(grid + node * 8 + 2 * g);
+          a = fmaf(w, v.x, a);
+          b = fmaf(w, v.y, b);
+        }
+      f[2] = a;
+      f[3] = b;
+    }
+
+    // ---- forward MLP
+    f4v p0 = fw.c1[0], p1 = fw.c1[1];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      p0 = __builtin_amdgcn_mfma_f32_16x16x4f32(fw.a1[0][m], f[m], p0, 0, 0, 0);
+      p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(fw.a1[1][m], f[m], p1, 0, 0, 0);
+    }
+    float h1[8];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      h1[r] = fmaxf(p0[r], 0.0f);
+      h1[4 + r] = fmaxf(p1[r], 0.0f);
+    }
+    f4v r0 = fw.c2[0], r1 = fw.c2[1];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      r0 = __builtin_amdgcn_mfma_f32_16x16x4f32(fw.a2[0][m], h1[m], r0, 0, 0, 0);
+      r1 = __builtin_amdgcn_mfma_f32_16x16x4f32(fw.a2[1][m], h1[m], r1, 0, 0, 0);
+    }
+    float h2[8];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      h2[r] = fmaxf(r0[r], 0.0f);
+      h2[4 + r] = fmaxf(r1[r], 0.0f);
+    }
+    f4v z = fw.c3;   // output rows 0..2 of group 0's slot (lanes g = 0)
+#pragma unroll
+    for (int m = 0; m < 8; ++m) z = __builtin_amdgcn_mfma_f32_16x16x4f32(fw.a3[0][m], h2[m], z, 0, 0, 0);
+
+    // ---- output, loss, dL/dz (lanes g = 0 own sample j's three channels)
+    float dz0 = 0.0f, dz1 = 0.0f, dz2 = 0.0f;
+    if (g == 0 && valid) {
+      const float c0 = expf(z[0]), c1 = expf(z[1]), c2 = expf(z[2]);
+      if constexpr (MODE == NDGI_TRAIN_FORWARD) {
+        pred[s * 3 + 0] = c0;
+        pred[s * 3 + 1] = c1;
+        pred[s * 3 + 2] = c2;
+      } else if constexpr (MODE == NDGI_TRAIN_BACKWARD) {
+        dz0 = grad_pred[s * 3 + 0] * c0;
+        dz1 = grad_pred[s * 3 + 1] * c1;
+        dz2 = grad_pred[s * 3 + 2] * c2;
+      } else {
+        const uint16_t* tp = target + (((size_t)k * d.H + y) * d.W + x) * 3;
+        const float e0 = c0 - half_bits(tp[0]), e1 = c1 - half_bits(tp[1]), e2 = c2 - half_bits(tp[2]);
+        loss += (double)e0 * e0 + (double)e1 * e1 + (double)e2 * e2;
+        dz0 = 2.0f * inv3n * e0 * c0;
+        dz1 = 2.0f * inv3n * e1 * c1;
+        dz2 = 2.0f * inv3n * e2 * c2;
+        if (pred) {
+          pred[s * 3 + 0] = c0;
+          pred[s * 3 + 1] = c1;
+          pred[s * 3 + 2] = c2;
+        }
+      }
+    }
+    if constexpr (MODE == NDGI_TRAIN_FORWARD) continue;
+
+    // B operand of the output-layer backward: lane (g, j) takes channel g of sample j
+    const float v0 = __shfl(dz0, j), v1 = __shfl(dz1, j), v2 = __shfl(dz2, j);
+    const float dzb = g == 0 ? v0 : (g == 1 ? v1 : (g == 2 ? v2 : 0.0f));
+
+    // ---- backward through the decoder
+    f4v q0 = {0, 0, 0, 0}, q1 = {0, 0, 0, 0};
+    q0 = __builtin_amdgcn_mfma_f32_16x16x4f32(w3t[0], dzb, q0, 0, 0, 0);
+    q1 = __builtin_amdgcn_mfma_f32_16x16x4f32(w3t[1], dzb, q1, 0, 0, 0);
+    float d2[8];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      d2[r] = r0[r] > 0.0f ? q0[r] : 0.0f;
+      d2[4 + r] = r1[r] > 0.0f ? q1[r] : 0.0f;
+    }
+    f4v t0 = {0, 0, 0, 0}, t1 = {0, 0, 0, 0};
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      t0 = __builtin_amdgcn_mfma_f32_16x16x4f32(w2t[0][m], d2[m], t0, 0, 0, 0);
+      t1 = __builtin_amdgcn_mfma_f32_16x16x4f32(w2t[1][m], d2[m], t1, 0, 0, 0);
+    }
+    float d1[8];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      d1[r] = p0[r] > 0.0f ? t0[r] : 0.0f;
+      d1[4 + r] = p1[r] > 0.0f ? t1[r] : 0.0f;
+    }
+    f4v dx = {0, 0, 0, 0};
+#pragma unroll
+    for (int m = 0; m < 8; ++m) dx = __builtin_amdgcn_mfma_f32_16x16x4f32(w1t[m], d1[m], dx, 0, 0, 0);
+    // dx[r] = dLoss/d(input_of(g, r)) of sample j
+
+    // ---- scatter input gradients (straight-through BC simulation; grid corners)
+    if (valid) {
+      const float da = dx[0], db = dx[1];
+      float* ge = g_ep + blk * 2;
+      atomicAdd(ge + 0, da * (1.0f - (float)Ja * (1.0f / 7.0f)));
+      atomicAdd(ge + 1, da * ((float)Ja * (1.0f / 7.0f)));
+      atomicAdd(ge + 2, db * (1.0f - (float)Jb * (1.0f / 7.0f)));
+      atomicAdd(ge + 3, db * ((float)Jb * (1.0f / 7.0f)));
+      float* gw = g_w + ((size_t)y * d.W + x) * 8 + 2 * g;
+      atomicAdd(gw + 0, da * (float)(E2a - E1a) * (1.0f / 255.0f));
+      atomicAdd(gw + 1, db * (float)(E2b - E1b) * (1.0f / 255.0f));
+#pragma unroll
+      for (int yy = 0; yy < 2; ++yy)
+#pragma unroll
+        for (int xx = 0; xx < 2; ++xx) {
+          const float w = (yy ? ay.w1 : ay.w0) * (xx ? ax.w1 : ax.w0);
+          const size_t node = ((size_t)k * d.Gh + (yy ? ay.i1 : ay.i0)) * d.Gw + (xx ? ax.i1 : ax.i0);
+          float* gg = g_grid + node * 8 + 2 * g;
+          atomicAdd(gg + 0, w * dx[2]);
+          atomicAdd(gg + 1, w * dx[3]);
+        }
+    }
+
+    // ---- decoder weight gradients: stage activations with units on columns
+    *(float2*)&L.x[j * kPadX + 2 * g] = make_float2(f[0], f[1]);
+    *(float2*)&L.x[j * kPadX + 8 + 2 * g] = make_float2(f[2], f[3]);
+    *(float4*)&L.h1[j * kPadU + 4 * g] = make_float4(h1[0], h1[1], h1[2], h1[3]);
+    *(float4*)&L.h1[j * kPadU + 16 + 4 * g] = make_float4(h1[4], h1[5], h1[6], h1[7]);
+    *(float4*)&L.h2[j * kPadU + 4 * g] = make_float4(h2[0], h2[1], h2[2], h2[3]);
+    *(float4*)&L.h2[j * kPadU + 16 + 4 * g] = make_float4(h2[4], h2[5], h2[6], h2[7]);
+    *(float4*)&L.d2[j * kPadU + 4 * g] = make_float4(d2[0], d2[1], d2[2], d2[3]);
+    *(float4*)&L.d2[j * kPadU + 16 + 4 * g] = make_float4(d2[4], d2[5], d2[6], d2[7]);
+    *(float4*)&L.d1[j * kPadU + 4 * g] = make_float4(d1[0], d1[1], d1[2], d1[3]);
+    *(float4*)&L.d1[j * kPadU + 16 + 4 * g] = make_float4(d1[4], d1[5], d1[6], d1[7]);
+    L.dz[j * 4 + g] = dzb;
+    wave_sync();
+    const int i = lane & 15;
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int row = 4 * s4 + g;   // sample of this K step held by lane group g
+      const float a_d2_0 = L.d2[row * kPadU + i], a_d2_1 = L.d2[row * kPadU + 16 + i];
+      const float a_d1_0 = L.d1[row * kPadU + i], a_d1_1 = L.d1[row * kPadU + 16 + i];
+      const float a_dz = i < 3 ? L.dz[row * 4 + i] : 0.0f;
+      const float b_h1_0 = L.h1[row * kPadU + i], b_h1_1 = L.h1[row * kPadU + 16 + i];
+      const float b_h2_0 = L.h2[row * kPadU + i], b_h2_1 = L.h2[row * kPadU + 16 + i];
+      const float b_x = L.x[row * kPadX + i];
+      gW2[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_d2_0, b_h1_0, gW2[0][0], 0, 0, 0);
+      gW2[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_d2_0, b_h1_1, gW2[0][1], 0, 0, 0);
+      gW2[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_d2_1, b_h1_0, gW2[1][0], 0, 0, 0);
+      gW2[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_d2_1, b_h1_1, gW2[1][1], 0, 0, 0);
+      gW1[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_d1_0, b_x, gW1[0], 0, 0, 0);
+      gW1[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_d1_1, b_x, gW1[1], 0, 0, 0);
+      gW3[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_dz, b_h2_0, gW3[0], 0, 0, 0);
+      gW3[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_dz, b_h2_1, gW3[1], 0, 0, 0);
+    }
+    wave_sync();
+    // ---- bias gradients: per-lane sums, reduced across the wave after the loop
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      gb1[e] += d1[e];
+      gb2[e] += d2[e];
+    }
+    gb3 += dzb;
+  }
+
+  if constexpr (MODE == NDGI_TRAIN_FORWARD) return;
+  // reduce bias partials over the 16 samples-lanes of each row (xor within 16 lanes)
+#pragma unroll
+  for (int off = 1; off < 16; off <<= 1) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      gb1[e] += __shfl_xor(gb1[e], off);
+      gb2[e] += __shfl_xor(gb2[e], off);
+    }
+    gb3 += __shfl_xor(gb3, off);
+  }
+  float* out = partials + (size_t)wave_id * kPartialStride;
+  const int i = lane & 15;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+#pragma unroll
+    for (int mc = 0; mc < 2; ++mc) {
+      const int u = 16 * mc + 4 * g + r;
+      out[kOffW1 + u * 16 + i] = gW1[mc][r];
+      out[kOffW2 + u * 32 + i] = gW2[mc][0][r];
+      out[kOffW2 + u * 32 + 16 + i] = gW2[mc][1][r];
+    }
+    if (g == 0 && r < 3) {
+      out[kOffW3 + r * 32 + i] = gW3[0][r];
+      out[kOffW3 + r * 32 + 16 + i] = gW3[1][r];
+    }
+  }
+  if (i == 0) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      out[kOffB1 + unit_of(g, e)] = gb1[e];
+      out[kOffB2 + unit_of(g, e)] = gb2[e];
+    }
+    if (g < 3) out[kOffB3 + g] = gb3;
+  }
+  // FP64 loss: wave reduction, one value per wave
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) loss += __shfl_xor(loss, off);
+  if (lane == 0) loss_part[wave_id] = loss;
+}
+
+// Sum the per-wave partial rows into the decoder gradients (fixed order: deterministic),
+// and the loss parts into *loss_out.  One workgroup of 256 threads per 64 columns.
+__global__ __launch_bounds__(256) void k_reduce_partials(const float* __restrict__ partials, int rows,
+                                                          float* __restrict__ g_mlp, const double* __restrict__ loss_part,
+                                                          double scale, double* __restrict__ loss_out) {
+  __shared__ float red[4][64];
+  const int c = threadIdx.x & 63, ph = threadIdx.x >> 6;
+  const int col = blockIdx.x * 64 + c;
+  float acc = 0.0f;
+  if (col < NDGI_MLP_SIZE)
+    for (int r = ph; r < rows; r += 4) acc += partials[(size_t)r * kPartialStride + col];
+  red[ph][c] = acc;
+  __syncthreads();
+  if (ph == 0 && col < NDGI_MLP_SIZE) g_mlp[col] += ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+  if (blockIdx.x == 0 && loss_out) {
+    __shared__ double lred[256];
+    double l = 0.0;
+    for (int r = threadIdx.x; r < rows; r += 256) l += loss_part[r];
+    lred[threadIdx.x] = l;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) lred[threadIdx.x] += lred[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss_out = lred[0] * scale;
+  }
+}
+
+// Dense Adam (bias-corrected, as torch.optim.Adam), projection of the BC parameters to
+// [0, 1], gradient reset.  Four parameters per thread; segment boundaries are multiples of 4.
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __restrict__ gr, float* __restrict__ m,
+                                               float* __restrict__ v, int64_t n, int64_t off_g, int64_t off_mlp,
+                                               float lr_feat, float lr_mlp, float b1, float b2, float eps,
+                                               float step_feat, float step_mlp, float inv_sqrt_bc2) {
+  const int64_t n4 = n >> 2;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q <= n4; q += stride) {
+    const int64_t i0 = q << 2;
+    if (i0 >= n) break;
+    const bool clampseg = i0 < off_g;
+    const float ss = i0 < off_mlp ? step_feat : step_mlp;
+    if (i0 + 4 <= n) {
+      float4 P = *(float4*)(p + i0), Gv = *(float4*)(gr + i0), M = *(float4*)(m + i0), V = *(float4*)(v + i0);
+      float* pp = &P.x;
+      float* gg = &Gv.x;
+      float* mm = &M.x;
+      float* vv = &V.x;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        mm[e] = b1 * mm[e] + (1.0f - b1) * gg[e];
+        vv[e] = b2 * vv[e] + (1.0f - b2) * gg[e] * gg[e];
+        const float den = sqrtf(vv[e]) * inv_sqrt_bc2 + eps;
+        float np = pp[e] - ss * (mm[e] / den);
+        if (clampseg) np = fminf(fmaxf(np, 0.0f), 1.0f);
+        pp[e] = np;
+      }
+      *(float4*)(p + i0) = P;
+      *(float4*)(m + i0) = M;
+      *(float4*)(v + i0) = V;
+      *(float4*)(gr + i0) = make_float4(0, 0, 0, 0);
+    } else {
+      for (int64_t i = i0; i < n; ++i) {
+        const float gg = gr[i];
+        const float mm = b1 * m[i] + (1.0f - b1) * gg;
+        const float vv = b2 * v[i] + (1.0f - b2) * gg * gg;
+        const float den = sqrtf(vv) * inv_sqrt_bc2 + eps;
+        float np = p[i] - ss * (mm / den);
+        if (clampseg) np = fminf(fmaxf(np, 0.0f), 1.0f);
+        p[i] = np;
+        m[i] = mm;
+        v[i] = vv;
+        gr[i] = 0.0f;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fill_zero(float* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0f;
+}
+
+// Export: one thread per (block, channel) writes the 8-byte BC4 block.
+__global__ __launch_bounds__(256) void k_export_bc4(TrainDims d, const float* __restrict__ P, uint8_t* __restrict__ out) {
+  const int64_t nb = (int64_t)(d.H >> 2) * (d.W >> 2) * 8;
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(b & 7);
+    const int64_t blk = b >> 3;
+    const int bx = (int)(blk % (d.W >> 2)), by = (int)(blk / (d.W >> 2));
+    const float2 e = *(const float2*)(P + b * 2);
+    const int E1 = (int)rintf(__fmul_rn(255.0f, e.x)), E2 = (int)rintf(__fmul_rn(255.0f, e.y));
+    uint64_t sel = 0;
+    for (int s = 0; s < 16; ++s) {
+      const int x = 4 * bx + (s & 3), y = 4 * by + (s >> 2);
+      const int J = (int)rintf(__fmul_rn(7.0f, P[d.off_w + ((int64_t)y * d.W + x) * 8 + c]));
+      int code = 0;
+      if (E1 != E2) {
+        const int jj = E1 > E2 ? J : 7 - J;
+        code = jj == 0 ? 0 : (jj == 7 ? 1 : jj + 1);
+      }
+      sel |= (uint64_t)code << (3 * s);
+    }
+    const uint32_t e0 = (uint32_t)(E1 >= E2 ? E1 : E2), e1 = (uint32_t)(E1 >= E2 ? E2 : E1);
+    const uint32_t lo = e0 | (e1 << 8) | (uint32_t)((sel & 0xffffu) << 16);
+    const uint32_t hi = (uint32_t)(sel >> 16);
+    *(uint2*)(out + b * 8) = make_uint2(lo, hi);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_convert(const float* __restrict__ src, void* __restrict__ dst, int dt, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (dt == NDGI_DTYPE_F16) ((_Float16*)dst)[i] = (_Float16)src[i];
+    else ((float*)dst)[i] = src[i];
+  }
+}
+
+// Tile statistics for tiled PSNR: one workgroup per tile; FP64 max, min and squared error.
+__global__ __launch_bounds__(256) void k_tile_stats(const void* __restrict__ pred, int pdt,
+                                                     const uint16_t* __restrict__ target, int W, int H, int tile,
+                                                     double* __restrict__ stats) {
+  const int tx = blockIdx.x, ty = blockIdx.y;
+  const int x0 = tx * tile, y0 = ty * tile;
+  const int tw = min(tile, W - x0), th = min(tile, H - y0);
+  double mx = -INFINITY, mn = INFINITY, se = 0.0;
+  const int64_t cnt = (int64_t)tw * th * 3;
+  for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) {
+    const int c = (int)(e % 3);
+    const int64_t t = e / 3;
+    const int x = x0 + (int)(t % tw), y = y0 + (int)(t / tw);
+    const int64_t idx = ((int64_t)y * W + x) * 3 + c;
+    const double tv = (double)half_bits(target[idx]);
+    const double pv = pdt == NDGI_DTYPE_F16 ? (double)half_bits(((const uint16_t*)pred)[idx]) : (double)((const float*)pred)[idx];
+    mx = fmax(mx, tv);
+    mn = fmin(mn, tv);
+    se += (pv - tv) * (pv - tv);
+  }
+  __shared__ double smx[256], smn[256], sse[256];
+  smx[threadIdx.x] = mx;
+  smn[threadIdx.x] = mn;
+  sse[threadIdx.x] = se;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      smx[threadIdx.x] = fmax(smx[threadIdx.x], smx[threadIdx.x + s]);
+      smn[threadIdx.x] = fmin(smn[threadIdx.x], smn[threadIdx.x + s]);
+      sse[threadIdx.x] += sse[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double* o = stats + ((size_t)ty * gridDim.x + tx) * 3;
+    o[0] = smx[0];
+    o[1] = smn[0];
+    o[2] = sse[0];
+  }
+}
+
+}  // namespace ndgi
+
+using namespace ndgi;
+
+static int64_t param_count(int W, int H, int Gw, int Gh, int T) {
+  return (int64_t)(H / 4) * (W / 4) * 16 + (int64_t)H * W * 8 + (int64_t)T * Gh * Gw * 8 + NDGI_MLP_SIZE;
+}
+
+static int check_state(const ndgi_train_state* s, const char* who) {
+  if (!s) return fail(NDGI_ERR_INVALID_ARG, "%s: state is NULL", who);
+  if (s->W < 4 || s->H < 4 || s->W > 4096 || s->H > 4096 || (s->W & 3) || (s->H & 3))
+    return fail(NDGI_ERR_INVALID_ARG, "%s: W, H must be multiples of 4 in [4, 4096]", who);
+  if (s->Gw < 1 || s->Gh < 1 || s->Gw > 4096 || s->Gh > 4096 || s->T < 1 || s->T > 256)
+    return fail(NDGI_ERR_INVALID_ARG, "%s: grid %dx%d, T=%d out of range", who, s->Gw, s->Gh, s->T);
+  if (!s->params || !s->grads) return fail(NDGI_ERR_INVALID_ARG, "%s: NULL params/grads", who);
+  return NDGI_OK;
+}
+
+static TrainDims dims_of(const ndgi_train_state* s) {
+  TrainDims d;
+  d.W = s->W;
+  d.H = s->H;
+  d.Gw = s->Gw;
+  d.Gh = s->Gh;
+  d.T = s->T;
+  d.off_w = (int64_t)(s->H / 4) * (s->W / 4) * 16;
+  d.off_g = d.off_w + (int64_t)s->H * s->W * 8;
+  d.off_mlp = d.off_g + (int64_t)s->T * s->Gh * s->Gw * 8;
+  return d;
+}
+
+static int grid_for(int64_t n, int cap) {
+  const int64_t w = (n + 255) / 256;
+  return (int)(w < cap ? (w < 1 ? 1 : w) : cap);
+}
+
+extern "C" {
+
+int64_t ndgi_train_param_count(int32_t W, int32_t H, int32_t Gw, int32_t Gh, int32_t T) {
+  return param_count(W, H, Gw, Gh, T);
+}
+
+int ndgi_train_step(ndgi_ctx* c, ndgi_train_state* st, const ndgi_batch* b, int32_t mode, double* loss_dev,
+                    hipStream_t s) {
+  clear_error();
+  if (!c) return fail(NDGI_ERR_INVALID_ARG, "train_step: ctx is NULL");
+  int rc = check_state(st, "train_step");
+  if (rc) return rc;
+  if (mode < NDGI_TRAIN_FORWARD || mode > NDGI_TRAIN_ZERO_GRAD) return fail(NDGI_ERR_INVALID_ARG, "train_step: bad mode %d", mode);
+  const TrainDims d = dims_of(st);
+  const int64_t np = d.off_mlp + NDGI_MLP_SIZE;
+  if (mode == NDGI_TRAIN_ZERO_GRAD) {
+    hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(np, c->n_cu * 16)), dim3(256), 0, s, st->grads, np);
+    NDGI_HIP(hipGetLastError());
+    return NDGI_OK;
+  }
+  const bool needs_batch = mode != NDGI_TRAIN_ADAM;
+  if (needs_batch) {
+    if (!b || !b->samples || b->n < 1) return fail(NDGI_ERR_INVALID_ARG, "train_step: empty batch");
+    if (mode == NDGI_TRAIN_FORWARD && !b->pred) return fail(NDGI_ERR_INVALID_ARG, "train_step: FORWARD needs pred");
+    if (mode == NDGI_TRAIN_BACKWARD && !b->grad_pred)
+      return fail(NDGI_ERR_INVALID_ARG, "train_step: BACKWARD needs grad_pred");
+    if ((mode == NDGI_TRAIN_LOSS_GRAD || mode == NDGI_TRAIN_FUSED) && (!b->target || !loss_dev))
+      return fail(NDGI_ERR_INVALID_ARG, "train_step: LOSS_GRAD/FUSED need target and loss_dev");
+  }
+  if ((mode == NDGI_TRAIN_ADAM || mode == NDGI_TRAIN_FUSED) && (!st->adam_m || !st->adam_v))
+    return fail(NDGI_ERR_INVALID_ARG, "train_step: Adam needs adam_m, adam_v");
+
+  if (needs_batch) {
+    const int64_t groups = (b->n + 15) / 16;
+    int64_t wgs = (groups + 3) / 4;
+    const int64_t cap = c->train_waves / 4;
+    if (wgs > cap) wgs = cap;
+    const float inv3n = (float)(1.0 / (3.0 * (double)b->n));
+#define NDGI_TRAIN_LAUNCH(M)                                                                                        \
+  hipLaunchKernelGGL(k_train<M>, dim3((unsigned)wgs), dim3(256), 0, s, d, st->params, st->grads, b->samples, b->n, \
+                     b->target, b->pred, b->grad_pred, inv3n, c->partials_dev, c->loss_part_dev, c->flags_dev)
+    if (mode == NDGI_TRAIN_FORWARD) NDGI_TRAIN_LAUNCH(NDGI_TRAIN_FORWARD);
+    else if (mode == NDGI_TRAIN_BACKWARD) NDGI_TRAIN_LAUNCH(NDGI_TRAIN_BACKWARD);
+    else NDGI_TRAIN_LAUNCH(NDGI_TRAIN_LOSS_GRAD);
+#undef NDGI_TRAIN_LAUNCH
+    NDGI_HIP(hipGetLastError());
+    if (mode != NDGI_TRAIN_FORWARD) {
+      const bool want_loss = mode == NDGI_TRAIN_LOSS_GRAD || mode == NDGI_TRAIN_FUSED;
+      hipLaunchKernelGGL(k_reduce_partials, dim3((NDGI_MLP_SIZE + 63) / 64), dim3(256), 0, s, c->partials_dev,
+                         (int)(wgs * 4), st->grads + d.off_mlp, c->loss_part_dev, 1.0 / (3.0 * (double)b->n),
+                         want_loss ? loss_dev : nullptr);
+      NDGI_HIP(hipGetLastError());
+    }
+  }
+  if (mode == NDGI_TRAIN_ADAM || mode == NDGI_TRAIN_FUSED) {
+    const int64_t t = st->step + 1;
+    const double bc1 = 1.0 - pow((double)st->beta1, (double)t);
+    const double bc2 = 1.0 - pow((double)st->beta2, (double)t);
+    const float sf = (float)((double)st->lr_feat / bc1), sm = (float)((double)st->lr_mlp / bc1);
+    const float isb = (float)(1.0 / sqrt(bc2));
+    hipLaunchKernelGGL(k_adam, dim3(grid_for((np + 3) / 4, c->n_cu * 16)), dim3(256), 0, s, st->params, st->grads,
+                       st->adam_m, st->adam_v, np, d.off_g, d.off_mlp, 1.0f, 1.0f, st->beta1, st->beta2, st->eps, sf,
+                       sm, isb);
+    NDGI_HIP(hipGetLastError());
+    st->step = t;
+  }
+  return NDGI_OK;
+}
+
+int ndgi_export(ndgi_ctx* c, const ndgi_train_state* st, uint8_t* bc4_out, void* grid_out, int32_t grid_dtype,
+                void* mlp_out, int32_t mlp_dtype, hipStream_t s) {
+  clear_error();
+  if (!c) return fail(NDGI_ERR_INVALID_ARG, "export: ctx is NULL");
+  int rc = check_state(st, "export");
+  if (rc) return rc;
+  if (!bc4_out || !grid_out || !mlp_out) return fail(NDGI_ERR_INVALID_ARG, "export: NULL output");
+  if ((grid_dtype != NDGI_DTYPE_F32 && grid_dtype != NDGI_DTYPE_F16) ||
+      (mlp_dtype != NDGI_DTYPE_F32 && mlp_dtype != NDGI_DTYPE_F16))
+    return fail(NDGI_ERR_INVALID_ARG, "export: bad dtype");
+  const TrainDims d = dims_of(st);
+  const int64_t nb = (int64_t)(d.H / 4) * (d.W / 4) * 8;
+  hipLaunchKernelGGL(k_export_bc4, dim3(grid_for(nb, c->n_cu * 16)), dim3(256), 0, s, d, st->params, bc4_out);
+  const int64_t ng = d.off_mlp - d.off_g;
+  hipLaunchKernelGGL(k_convert, dim3(grid_for(ng, c->n_cu * 16)), dim3(256), 0, s, st->params + d.off_g, grid_out,
+                     grid_dtype, ng);
+  hipLaunchKernelGGL(k_convert, dim3(grid_for(NDGI_MLP_SIZE, 64)), dim3(256), 0, s, st->params + d.off_mlp, mlp_out,
+                     mlp_dtype, (int64_t)NDGI_MLP_SIZE);
+  NDGI_HIP(hipGetLastError());
+  return NDGI_OK;
+}
+
+int ndgi_tile_stats(ndgi_ctx* c, const void* pred, int32_t pred_dtype, const uint16_t* target, int32_t W, int32_t H,
+                    int32_t tile, double* stats, hipStream_t s) {
+  clear_error();
+  if (!c || !pred || !target || !stats) return fail(NDGI_ERR_INVALID_ARG, "tile_stats: NULL argument");
+  if (W < 1 || H < 1 || tile < 1 || tile > 4096) return fail(NDGI_ERR_INVALID_ARG, "tile_stats: bad sizes");
+  if (pred_dtype != NDGI_DTYPE_F32 && pred_dtype != NDGI_DTYPE_F16) return fail(NDGI_ERR_INVALID_ARG, "tile_stats: bad dtype");
+  const dim3 grid((W + tile - 1) / tile, (H + tile - 1) / tile);
+  hipLaunchKernelGGL(k_tile_stats, grid, dim3(256), 0, s, pred, pred_dtype, target, W, H, tile, stats);
+  NDGI_HIP(hipGetLastError());
+  return NDGI_OK;
+}
+
+}  // extern "C"

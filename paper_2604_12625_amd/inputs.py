@@ -214,3 +214,41 @@ def train_init(W: int, H: int, Gw: int, Gh: int, T: int, mean_rgb, g: np.random.
     mlp = he_normal_mlp(np.float32, g)
     mlp[MLP_SIZE - 3:] = np.log(np.maximum(np.asarray(mean_rgb, dtype=np.float64), 1e-6)).astype(np.float32)
     return dict(dims=dict(W=W, H=H, Gw=Gw, Gh=Gh, T=T), endpoints=ep, weights=w, grid=grid, mlp=mlp)
+
+
+# ---------------------------------------------------------- large inputs drawn on device
+
+def random_model_torch(W: int, H: int, Gw: int, Gh: int, T: int, seed: int, device="cuda",
+                       grid_dtype="float16", mlp_dtype="float16") -> dict:
+    """Same distributions as :func:`random_model`, drawn with torch on ``device`` (for sizes
+    where host generation and upload would dominate).  Returns torch tensors."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    bc4 = torch.randint(0, 256, (H // 4, W // 4, N_CH, 8), generator=gen, device=device, dtype=torch.uint8)
+    grid = (torch.rand((T, Gh, Gw, N_CH), generator=gen, device=device) * 2.0 - 1.0).to(getattr(torch, grid_dtype))
+    parts = []
+    for (fo, fi) in ((HIDDEN, N_IN), (HIDDEN, HIDDEN), (N_OUT, HIDDEN)):
+        parts.append(torch.randn(fo * fi, generator=gen, device=device) * math.sqrt(2.0 / fi))
+        parts.append(torch.zeros(fo, device=device))
+    mlp = torch.cat(parts).to(getattr(torch, mlp_dtype))
+    return dict(W=W, H=H, Gw=Gw, Gh=Gh, T=T, bc4=bc4, grid=grid, mlp=mlp)
+
+
+def uniform_queries_torch(n: int, seed: int, device="cuda"):
+    """n queries with u, v, t uniform in [0, 1): torch [n][3] float32 on ``device``."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    return torch.rand((n, 3), generator=gen, device=device, dtype=torch.float32)
+
+
+def train_samples_torch(B: int, W: int, H: int, T: int, seed: int, device="cuda"):
+    """Packed samples (x | y << 12 | k << 24) drawn uniformly with replacement, on device."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    x = torch.randint(0, W, (B,), generator=gen, device=device, dtype=torch.int32)
+    y = torch.randint(0, H, (B,), generator=gen, device=device, dtype=torch.int32)
+    k = torch.randint(0, T, (B,), generator=gen, device=device, dtype=torch.int32)
+    return x | (y << 12) | (k << 24)

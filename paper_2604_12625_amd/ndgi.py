@@ -1,0 +1,247 @@
+"""Thin Python binding of libndgi.so (ctypes).
+
+Argument marshalling only: every step of the decode and training path runs in the HIP
+kernels behind the C ABI (include/ndgi.h).  PyTorch provides device memory and the
+current stream.  Loading fails loudly when the library has not been built; there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libndgi.so")
+
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_OOM = 0, -1, -2, -3, -4
+DTYPE_F32, DTYPE_F16 = 0, 1
+PREC_F32, PREC_F16 = 0, 1
+FLAG_BAD_PAGE_REQUEST = 1
+MLP_SIZE = 1699
+TRAIN_FORWARD, TRAIN_BACKWARD, TRAIN_LOSS_GRAD, TRAIN_FUSED, TRAIN_ADAM, TRAIN_ZERO_GRAD = range(6)
+
+EXPORTED = (
+    "ndgi_create", "ndgi_destroy", "ndgi_last_error", "ndgi_get_error_flags",
+    "ndgi_bc4_decode_blocks", "ndgi_decode", "ndgi_decode_pages", "ndgi_decode_pages_graph",
+    "ndgi_set_launch", "ndgi_train_param_count", "ndgi_train_step", "ndgi_export",
+    "ndgi_tile_stats",
+)
+
+
+class NdgiModel(C.Structure):
+    _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("Gw", C.c_int32), ("Gh", C.c_int32),
+                ("T", C.c_int32), ("grid_dtype", C.c_int32), ("mlp_dtype", C.c_int32),
+                ("reserved0", C.c_int32), ("bc4", C.c_void_p), ("grid", C.c_void_p),
+                ("mlp", C.c_void_p), ("reserved1", C.c_void_p)]
+
+
+class NdgiPageReq(C.Structure):
+    _fields_ = [("model", C.c_int32), ("page_x", C.c_int32), ("page_y", C.c_int32),
+                ("t", C.c_float), ("dst_offset", C.c_int64)]
+
+
+class NdgiTrainState(C.Structure):
+    _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("Gw", C.c_int32), ("Gh", C.c_int32),
+                ("T", C.c_int32), ("reserved0", C.c_int32), ("params", C.c_void_p),
+                ("grads", C.c_void_p), ("adam_m", C.c_void_p), ("adam_v", C.c_void_p),
+                ("step", C.c_int64), ("lr_feat", C.c_float), ("lr_mlp", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("reserved1", C.c_float)]
+
+
+class NdgiBatch(C.Structure):
+    _fields_ = [("samples", C.c_void_p), ("n", C.c_int64), ("target", C.c_void_p),
+                ("pred", C.c_void_p), ("grad_pred", C.c_void_p)]
+
+
+assert C.sizeof(NdgiModel) == 64 and C.sizeof(NdgiPageReq) == 24
+
+
+class NdgiError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise NdgiError(f"{LIB_PATH} not found: build it with "
+                            "`python -m paper_2604_12625_amd.build` (no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.ndgi_create.argtypes = [C.POINTER(vp), i32]
+        L.ndgi_destroy.argtypes = [vp]
+        L.ndgi_last_error.restype = C.c_char_p
+        L.ndgi_get_error_flags.argtypes = [vp, vp, C.POINTER(C.c_uint32)]
+        L.ndgi_bc4_decode_blocks.argtypes = [vp, i64, vp, vp]
+        L.ndgi_decode.argtypes = [vp, C.POINTER(NdgiModel), vp, i64, vp, i32, vp]
+        pages = [vp, vp, i32, vp, vp, i32, i32, vp, i64, i32, vp]
+        L.ndgi_decode_pages.argtypes = pages
+        L.ndgi_decode_pages_graph.argtypes = pages
+        L.ndgi_set_launch.argtypes = [vp, i32, i32, i32]
+        if hasattr(L, "ndgi_train_step"):
+            L.ndgi_train_param_count.argtypes = [i32, i32, i32, i32, i32]
+            L.ndgi_train_param_count.restype = i64
+            L.ndgi_train_step.argtypes = [vp, C.POINTER(NdgiTrainState), C.POINTER(NdgiBatch), i32, vp, vp]
+            L.ndgi_export.argtypes = [vp, C.POINTER(NdgiTrainState), vp, vp, i32, vp, i32, vp]
+            L.ndgi_tile_stats.argtypes = [vp, vp, i32, vp, i32, i32, i32, vp, vp]
+        _lib = L
+    return _lib
+
+
+def check(rc: int, what: str = ""):
+    if rc != OK:
+        msg = lib().ndgi_last_error().decode(errors="replace")
+        raise NdgiError(f"{what} failed ({rc}): {msg}")
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else t.data_ptr()
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class DeviceModel:
+    """A compressed model whose arrays live in device memory (torch tensors)."""
+
+    def __init__(self, W, H, Gw, Gh, T, bc4, grid, mlp):
+        import torch
+        self.W, self.H, self.Gw, self.Gh, self.T = int(W), int(H), int(Gw), int(Gh), int(T)
+        self.bc4 = bc4.contiguous()
+        self.grid = grid.contiguous()
+        self.mlp = mlp.contiguous()
+        dt = {torch.float32: DTYPE_F32, torch.float16: DTYPE_F16}
+        self.desc = NdgiModel(self.W, self.H, self.Gw, self.Gh, self.T, dt[self.grid.dtype],
+                              dt[self.mlp.dtype], 0, self.bc4.data_ptr(), self.grid.data_ptr(),
+                              self.mlp.data_ptr(), None)
+
+    @classmethod
+    def from_numpy(cls, m: dict, device="cuda"):
+        import torch
+        return cls(m["W"], m["H"], m["Gw"], m["Gh"], m["T"],
+                   torch.from_numpy(m["bc4"]).to(device),
+                   torch.from_numpy(m["grid"]).to(device),
+                   torch.from_numpy(m["mlp"]).to(device))
+
+    def desc_bytes(self) -> bytes:
+        return bytes(self.desc)
+
+
+class Context:
+    """Owns an ndgi_ctx on one device."""
+
+    def __init__(self, device: int = 0):
+        self.h = C.c_void_p()
+        check(lib().ndgi_create(C.byref(self.h), device), "ndgi_create")
+
+    def close(self):
+        if self.h:
+            lib().ndgi_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ decode
+    def decode(self, model: DeviceModel, uvt, prec=PREC_F16, out=None, stream=None):
+        import torch
+        n = uvt.shape[0]
+        if out is None:
+            out = torch.empty((n, 3), dtype=torch.float16 if prec == PREC_F16 else torch.float32,
+                              device=uvt.device)
+        check(lib().ndgi_decode(self.h, C.byref(model.desc), _ptr(uvt), n, _ptr(out), prec,
+                                _stream(stream)), "ndgi_decode")
+        return out
+
+    def decode_pages(self, models_dev, n_models, reqs_dev, n_reqs_dev, max_reqs, page, dst,
+                     pitch, prec=PREC_F16, graph=False, stream=None):
+        f = lib().ndgi_decode_pages_graph if graph else lib().ndgi_decode_pages
+        check(f(self.h, _ptr(models_dev), n_models, _ptr(reqs_dev), _ptr(n_reqs_dev), max_reqs,
+                page, _ptr(dst), pitch, prec, _stream(stream)), "ndgi_decode_pages")
+        return dst
+
+    def set_launch(self, tile_w, tile_h, waves_per_cu):
+        check(lib().ndgi_set_launch(self.h, tile_w, tile_h, waves_per_cu), "ndgi_set_launch")
+
+    def tile_stats(self, pred, target_bits, W, H, tile=128, out=None, stream=None):
+        """Per-tile (max target, min target, squared error) in FP64 for one [H][W][3] map."""
+        import torch
+        ny, nx = (H + tile - 1) // tile, (W + tile - 1) // tile
+        if out is None:
+            out = torch.empty((ny, nx, 3), dtype=torch.float64, device=pred.device)
+        pdt = DTYPE_F16 if pred.dtype == torch.float16 else DTYPE_F32
+        check(lib().ndgi_tile_stats(self.h, _ptr(pred), pdt, _ptr(target_bits), W, H, tile, _ptr(out),
+                                    _stream(stream)), "ndgi_tile_stats")
+        return out
+
+    def error_flags(self, stream=None) -> int:
+        f = C.c_uint32(0)
+        check(lib().ndgi_get_error_flags(self.h, _stream(stream), C.byref(f)), "ndgi_get_error_flags")
+        return f.value
+
+
+def bc4_decode_blocks(blocks, out=None, stream=None):
+    """Decode [n][8] uint8 device blocks to [n][16] uint8."""
+    import torch
+    n = blocks.shape[0]
+    if out is None:
+        out = torch.empty((n, 16), dtype=torch.uint8, device=blocks.device)
+    check(lib().ndgi_bc4_decode_blocks(_ptr(blocks), n, _ptr(out), _stream(stream)),
+          "ndgi_bc4_decode_blocks")
+    return out
+
+
+def models_array(models, device="cuda"):
+    """Device array of ndgi_model descriptors (keeps no reference to the models)."""
+    import torch
+    raw = b"".join(m.desc_bytes() for m in models)
+    return torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
+
+
+def page_requests(model, px, py, t, dst_offset, device="cuda"):
+    """Device array of ndgi_page_req from equal-length sequences."""
+    import numpy as np
+    import torch
+    n = len(model)
+    rec = np.zeros(n, dtype=np.dtype([("model", "<i4"), ("px", "<i4"), ("py", "<i4"),
+                                       ("t", "<f4"), ("off", "<i8")]))
+    rec["model"], rec["px"], rec["py"], rec["t"], rec["off"] = model, px, py, t, dst_offset
+    return torch.from_numpy(rec.view(np.uint8).copy()).to(device)
+
+
+def psnr_from_stats(stats, W, H, tile=128):
+    """Mean tiled PSNR and global PSNR from per-map tile statistics (host arithmetic on the
+    FP64 sums): PSNR = 10 log10(range^2 / MSE) per tile, tiles of zero range skipped,
+    MSE = 0 scored 100 dB."""
+    import math
+    scores = []
+    sse = 0.0
+    cnt_all = 0
+    gmax, gmin = -math.inf, math.inf
+    for s in stats:
+        ny, nx = s.shape[0], s.shape[1]
+        for ty in range(ny):
+            for tx in range(nx):
+                mx, mn, e = (float(v) for v in s[ty, tx])
+                c = min(tile, H - tile * ty) * min(tile, W - tile * tx) * 3
+                sse += e
+                cnt_all += c
+                gmax, gmin = max(gmax, mx), min(gmin, mn)
+                rng = mx - mn
+                if rng <= 0:
+                    continue
+                scores.append(100.0 if e == 0 else 10.0 * math.log10(rng * rng / (e / c)))
+    tiled = sum(scores) / len(scores) if scores else float("nan")
+    glob = 100.0 if sse == 0 else 10.0 * math.log10((gmax - gmin) ** 2 / (sse / cnt_all))
+    return tiled, glob

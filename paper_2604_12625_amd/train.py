@@ -1,0 +1,153 @@
+"""Training under BC simulation through the C ABI (ndgi_train_step), plus the
+torch.autograd.Function wrapper whose backward recomputes the decoded features."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import ndgi as N
+
+
+class Trainer:
+    """Trainable state in device memory: flat float32 params / grads / Adam m, v with the
+    layout [endpoints [H/4][W/4][8][2] | weights [H][W][8] | grid [T][Gh][Gw][8] | mlp]."""
+
+    def __init__(self, ctx: N.Context, init: dict, lr_feat=1e-2, lr_mlp=1e-3, betas=(0.9, 0.999),
+                 eps=1e-8, device="cuda"):
+        import torch
+        d = init["dims"]
+        self.ctx = ctx
+        self.W, self.H, self.Gw, self.Gh, self.T = d["W"], d["H"], d["Gw"], d["Gh"], d["T"]
+        n = N.lib().ndgi_train_param_count(self.W, self.H, self.Gw, self.Gh, self.T)
+        self.n_params = n
+        flat = np.concatenate([np.asarray(init[k], dtype=np.float32).ravel()
+                               for k in ("endpoints", "weights", "grid", "mlp")])
+        assert flat.size == n, (flat.size, n)
+        self.params = torch.from_numpy(flat).to(device)
+        self.grads = torch.zeros(n, dtype=torch.float32, device=device)
+        self.m = torch.zeros(n, dtype=torch.float32, device=device)
+        self.v = torch.zeros(n, dtype=torch.float32, device=device)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=device)
+        self.state = N.NdgiTrainState(self.W, self.H, self.Gw, self.Gh, self.T, 0,
+                                      self.params.data_ptr(), self.grads.data_ptr(),
+                                      self.m.data_ptr(), self.v.data_ptr(), 0,
+                                      float(lr_feat), float(lr_mlp), float(betas[0]),
+                                      float(betas[1]), float(eps), 0.0)
+
+    # segment views ------------------------------------------------------------------
+    def split(self, flat):
+        W, H, Gw, Gh, T = self.W, self.H, self.Gw, self.Gh, self.T
+        n_e = (H // 4) * (W // 4) * 16
+        n_w = H * W * 8
+        n_g = T * Gh * Gw * 8
+        return dict(endpoints=flat[:n_e].view(H // 4, W // 4, 8, 2),
+                    weights=flat[n_e:n_e + n_w].view(H, W, 8),
+                    grid=flat[n_e + n_w:n_e + n_w + n_g].view(T, Gh, Gw, 8),
+                    mlp=flat[n_e + n_w + n_g:])
+
+    @property
+    def step_count(self) -> int:
+        return int(self.state.step)
+
+    def _run(self, mode, samples=None, target=None, pred=None, grad_pred=None, stream=None):
+        b = N.NdgiBatch(N._ptr(samples), 0 if samples is None else samples.shape[0],
+                        N._ptr(target), N._ptr(pred), N._ptr(grad_pred))
+        N.check(N.lib().ndgi_train_step(self.ctx.h, C.byref(self.state), C.byref(b), mode,
+                                        self.loss.data_ptr(), N._stream(stream)), "ndgi_train_step")
+
+    def forward(self, samples, pred=None):
+        import torch
+        if pred is None:
+            pred = torch.empty((samples.shape[0], 3), dtype=torch.float32, device=samples.device)
+        self._run(N.TRAIN_FORWARD, samples, pred=pred)
+        return pred
+
+    def backward(self, samples, grad_pred):
+        self._run(N.TRAIN_BACKWARD, samples, grad_pred=grad_pred)
+
+    def loss_grad(self, samples, target, pred=None):
+        self._run(N.TRAIN_LOSS_GRAD, samples, target=target, pred=pred)
+        return self.loss
+
+    def step(self, samples, target):
+        """Forward, FP64 L2 loss, backward and Adam in one stream order; returns the loss tensor."""
+        self._run(N.TRAIN_FUSED, samples, target=target)
+        return self.loss
+
+    def adam(self):
+        self._run(N.TRAIN_ADAM)
+
+    def zero_grad(self):
+        self._run(N.TRAIN_ZERO_GRAD)
+
+    def export(self, grid_dtype=N.DTYPE_F16, mlp_dtype=N.DTYPE_F16) -> N.DeviceModel:
+        import torch
+        dev = self.params.device
+        bc4 = torch.empty((self.H // 4, self.W // 4, 8, 8), dtype=torch.uint8, device=dev)
+        tdt = {N.DTYPE_F16: torch.float16, N.DTYPE_F32: torch.float32}
+        grid = torch.empty((self.T, self.Gh, self.Gw, 8), dtype=tdt[grid_dtype], device=dev)
+        mlp = torch.empty(N.MLP_SIZE, dtype=tdt[mlp_dtype], device=dev)
+        N.check(N.lib().ndgi_export(self.ctx.h, C.byref(self.state), bc4.data_ptr(), grid.data_ptr(),
+                                    grid_dtype, mlp.data_ptr(), mlp_dtype, N._stream(None)), "ndgi_export")
+        return N.DeviceModel(self.W, self.H, self.Gw, self.Gh, self.T, bc4, grid, mlp)
+
+
+def _autograd_function():
+    import torch
+
+    class NdgiFunction(torch.autograd.Function):
+        """pred = H_Theta(samples) under BC simulation.  Forward saves only the samples; the
+        backward recomputes the decoded features inside the kernel and returns the gradient
+        of the flat parameter tensor."""
+
+        @staticmethod
+        def forward(ctx, params, samples, trainer):
+            assert params.data_ptr() == trainer.params.data_ptr()
+            ctx.save_for_backward(samples)
+            ctx.trainer = trainer
+            return trainer.forward(samples)
+
+        @staticmethod
+        def backward(ctx, grad_pred):
+            (samples,) = ctx.saved_tensors
+            tr = ctx.trainer
+            tr.zero_grad()
+            tr.backward(samples, grad_pred.contiguous().float())
+            return tr.grads.clone(), None, None
+
+    return NdgiFunction
+
+
+_FN = None
+
+
+def ndgi_apply(trainer: Trainer, samples):
+    """Differentiable prediction at packed samples (see NdgiFunction)."""
+    global _FN
+    if _FN is None:
+        _FN = _autograd_function()
+    return _FN.apply(trainer.params, samples, trainer)
+
+
+def smoke_train_step(ctx: N.Context):
+    """One LOSS_GRAD step on a tiny problem checked against the oracle (used by smoke())."""
+    import torch
+
+    from oracle import ndgi_oracle as O
+
+    from . import inputs as I
+    g = I.rng(4, I.P_INIT, 99)
+    st = I.train_init(16, 16, 4, 4, 4, [0.5, 0.5, 0.5], g)
+    x, y, k = I.train_samples(512, 16, 16, 4, g)
+    tgt = g.uniform(0.1, 2.0, (4, 16, 16, 3)).astype(np.float16)
+    tr = Trainer(ctx, st)
+    smp = torch.from_numpy(I.pack_samples(x, y, k).view(np.int32)).cuda()
+    tgt_d = torch.from_numpy(tgt.view(np.uint16).view(np.int16)).cuda()
+    loss = float(tr.loss_grad(smp, tgt_d).item())
+    ref_loss, ref = O.train_grads(st, x, y, k, tgt[k, y, x].astype(np.float64))
+    assert abs(loss - ref_loss) <= 1e-5 * abs(ref_loss), (loss, ref_loss)
+    gm = tr.split(tr.grads)["mlp"].cpu().numpy()
+    err = np.max(np.abs(gm - ref["mlp"])) / np.max(np.abs(ref["mlp"]))
+    assert err <= 1e-4, err
+    print(f"smoke train: loss {loss:.6e} (oracle {ref_loss:.6e}), decoder grad err {err:.2e}")

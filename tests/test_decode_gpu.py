@@ -1,0 +1,239 @@
+"""GPU parity of the decode path against the CPU oracle, through the C ABI.
+
+Tolerances: BC4 decode bit-exact; decoded RGB within 1e-5 (FP32 path) and 2e-3 (FP16
+MFMA path) relative per channel, max over the compared set."""
+import numpy as np
+import pytest
+
+from oracle import ndgi_oracle as O
+from paper_2604_12625_amd import inputs as I
+from tests.gpu_util import assert_rel, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+TOL16 = 2e-3
+
+
+@pytest.fixture(scope="module")
+def N():
+    torch_cuda()
+    from paper_2604_12625_amd import ndgi
+    return ndgi
+
+
+@pytest.fixture(scope="module")
+def ctx(N):
+    c = N.Context(0)
+    yield c
+    c.close()
+
+
+def _dec(N, ctx, model, q, prec):
+    import torch
+    dm = N.DeviceModel.from_numpy(model)
+    out = ctx.decode(dm, torch.from_numpy(q).cuda(), prec)
+    torch.cuda.synchronize()
+    return out.float().cpu().numpy()
+
+
+# ------------------------------------------------------------------------------ BC4
+def test_bc4_blocks_bit_exact(N):
+    import torch
+    from tests.test_oracle import _golden_blocks
+    gold = _golden_blocks()
+    blocks = np.stack([b for b, _ in gold])
+    out = N.bc4_decode_blocks(torch.from_numpy(blocks).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(out, np.stack([w for _, w in gold]))
+    g = np.random.default_rng(20)
+    rnd = g.integers(0, 256, size=(1_000_003, 8), dtype=np.uint8)
+    out = N.bc4_decode_blocks(torch.from_numpy(rnd).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(out, O.bc4_decode_blocks(rnd))
+    empty = torch.empty((0, 8), dtype=torch.uint8, device="cuda")
+    assert N.bc4_decode_blocks(empty).shape == (0, 16)
+
+
+# --------------------------------------------------------------------------- decode
+def c1_model():
+    """64x64 map, grid 16x16x8(t)x8 FP32 U[-1,1], He-normal FP32 decoder (seed 0)."""
+    return I.random_model(64, 64, 16, 16, 8, np.float32, np.float32, config=1)
+
+
+def test_decode_c1_fp32_all_texel_centres(N, ctx):
+    m = c1_model()
+    ts = I.rng(1, I.P_QUERY).random(8, dtype=np.float32)
+    q = I.texel_centre_queries(64, 64, ts)
+    assert q.shape == (32768, 3)
+    assert_rel(_dec(N, ctx, m, q, N.PREC_F32), O.decode(m, q), TOL32, "C1 FP32")
+
+
+@pytest.mark.parametrize("prec,tol", [(1, TOL16), (0, TOL32)])
+def test_decode_fp16_model_centres_and_random(N, ctx, prec, tol):
+    m = I.random_model(256, 192, 64, 48, 24, np.float16, np.float16, config=50)
+    q1 = I.texel_centre_queries(256, 192, [0.0, 0.61])
+    q2 = I.uniform_queries(70001, I.rng(50, I.P_QUERY))
+    q = np.concatenate([q1, q2])
+    assert_rel(_dec(N, ctx, m, q, prec), O.decode(m, q), tol, f"prec {prec}")
+
+
+@pytest.mark.parametrize("n", [1, 15, 63, 64, 65, 1000])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_decode_ragged_counts(N, ctx, n, prec):
+    m = I.random_model(64, 64, 16, 16, 8, np.float16, np.float16, config=51)
+    q = I.uniform_queries(n, I.rng(51, I.P_QUERY, n))
+    assert_rel(_dec(N, ctx, m, q, prec), O.decode(m, q), TOL16 if prec else TOL32, f"n={n}")
+
+
+def test_decode_edges_clamp_wrap_nan(N, ctx):
+    m = I.random_model(128, 64, 32, 16, 12, np.float16, np.float16, config=52)
+    q = np.array([[-0.5, 0.5, 0.2], [1.7, 0.5, 0.2], [0.5, -3.0, 0.2], [0.5, 9.0, 0.2],
+                  [0.0, 0.0, 0.0], [0.999999, 0.999999, 0.999999], [0.3, 0.4, -0.25],
+                  [0.3, 0.4, 7.75], [0.3, 0.4, 11.0 / 12.0 + 1e-4], [0.25, 0.75, 0.999]],
+                 dtype=np.float32)
+    bad = np.array([[np.nan, 0.5, 0.2], [0.5, np.inf, 0.2], [0.5, 0.5, -np.inf]], dtype=np.float32)
+    for prec, tol in ((0, TOL32), (1, TOL16)):
+        assert_rel(_dec(N, ctx, m, q, prec), O.decode(m, q), tol, "edges")
+        assert np.isnan(_dec(N, ctx, m, bad, prec)).all()
+
+
+def test_decode_argument_errors(N, ctx):
+    import ctypes
+    import torch
+    m = I.random_model(64, 64, 16, 16, 8, np.float16, np.float16, config=53)
+    dm = N.DeviceModel.from_numpy(m)
+    q = torch.zeros((4, 3), device="cuda")
+    with pytest.raises(N.NdgiError):
+        ctx.decode(dm, q, prec=7)
+    dm.desc.W = 62
+    with pytest.raises(N.NdgiError, match="multiples of 4"):
+        ctx.decode(dm, q, N.PREC_F32)
+    dm.desc.W = 64
+    rc = N.lib().ndgi_decode(ctx.h, ctypes.byref(dm.desc), None, 4, None, 0, None)
+    assert rc == N.ERR_INVALID_ARG
+
+
+# ---------------------------------------------------------------------------- pages
+def _vt_setup(prec, seed=60):
+    sides = [(256, 256, 24), (384, 384, 24), (512, 256, 12)]
+    models = [I.random_model(W, H, W // 4, H // 4, T, np.float16, np.float16, config=seed, index=i)
+              for i, (W, H, T) in enumerate(sides)]
+    g = I.rng(seed, I.P_REQ)
+    reqs = []
+    for r in range(24):
+        mi = int(g.integers(0, 3))
+        W, H, _ = sides[mi]
+        reqs.append((mi, int(g.integers(0, W // 128)), int(g.integers(0, H // 128)),
+                     float(g.random(dtype=np.float32)), 0))
+    reqs += [(3, 0, 0, 0.5, 0), (-1, 0, 0, 0.5, 0), (0, 2, 0, 0.5, 0), (2, 3, 2, 0.5, 0), (1, -1, 0, 0.1, 0)]
+    # physical texture: 8 pages per row
+    reqs = [(m, px, py, t, (i // 8) * 128 * 1024 + (i % 8) * 128) for i, (m, px, py, t, _) in enumerate(reqs)]
+    return models, reqs
+
+
+def _run_pages(N, ctx, models, reqs, prec, graph=False, n_serve=None, dst=None):
+    import torch
+    dms = [N.DeviceModel.from_numpy(m) for m in models]
+    marr = N.models_array(dms)
+    r = np.array(reqs, dtype=object)
+    rq = N.page_requests(r[:, 0].astype(np.int32), r[:, 1].astype(np.int32), r[:, 2].astype(np.int32),
+                         r[:, 3].astype(np.float32), r[:, 4].astype(np.int64))
+    nreq = torch.tensor([len(reqs) if n_serve is None else n_serve], dtype=torch.int32, device="cuda")
+    rows = ((len(reqs) + 7) // 8) * 128
+    dt = torch.float16 if prec == 1 else torch.float32
+    if dst is None:
+        dst = torch.full((rows * 1024, 3), -7.0, dtype=dt, device="cuda")
+    ctx.decode_pages(marr, len(models), rq, nreq, len(reqs), 128, dst, 1024, prec, graph=graph)
+    torch.cuda.synchronize()
+    return dst.float().cpu().numpy(), (dms, marr, rq, nreq)
+
+
+@pytest.mark.parametrize("prec,tol", [(1, TOL16), (0, TOL32)])
+def test_pages_many_models_and_bad_requests(N, ctx, prec, tol):
+    models, reqs = _vt_setup(prec)
+    out, _ = _run_pages(N, ctx, models, reqs, prec)
+    assert ctx.error_flags() & N.FLAG_BAD_PAGE_REQUEST
+    assert ctx.error_flags() == 0                      # reading clears the flags
+    rows = out.shape[0] // 1024
+    ref = np.full((rows * 1024, 3), -7.0)
+    bad = O.decode_pages(models, reqs, 128, ref, 1024)
+    assert bad == 5
+    valid = ref[:, 0] != -7.0
+    assert_rel(out[valid], ref[valid], tol, "pages")
+    np.testing.assert_array_equal(out[~valid], -7.0)
+
+
+def test_pages_graph_replay_with_new_requests(N, ctx):
+    import torch
+    models, reqs = _vt_setup(1, seed=61)
+    reqs = reqs[:24]
+    out1, keep = _run_pages(N, ctx, models, reqs, 1, graph=True)
+    dms, marr, rq, nreq = keep
+    ref = np.full(out1.shape, -7.0)
+    O.decode_pages(models, reqs, 128, ref, 1024)
+    assert_rel(out1[ref[:, 0] != -7.0], ref[ref[:, 0] != -7.0], TOL16, "graph #1")
+    # new times and a smaller count in the same device buffers, replay
+    reqs2 = [(m, px, py, (t + 0.37) % 1.0, off) for (m, px, py, t, off) in reqs]
+    r = np.array(reqs2, dtype=object)
+    rq.copy_(N.page_requests(r[:, 0].astype(np.int32), r[:, 1].astype(np.int32), r[:, 2].astype(np.int32),
+                             r[:, 3].astype(np.float32), r[:, 4].astype(np.int64)))
+    nreq.fill_(16)
+    dst = torch.full((out1.shape[0], 3), -7.0, dtype=torch.float16, device="cuda")
+    for _ in range(3):
+        ctx.decode_pages(marr, len(models), rq, nreq, len(reqs), 128, dst, 1024, 1, graph=True)
+        torch.cuda.synchronize()
+        out2 = dst.float().cpu().numpy()
+        ref2 = np.full(out1.shape, -7.0)
+        O.decode_pages(models, reqs2[:16], 128, ref2, 1024)
+        v = ref2[:, 0] != -7.0
+        assert_rel(out2[v], ref2[v], TOL16, "graph replay")
+        np.testing.assert_array_equal(out2[~v], -7.0)
+
+
+def test_page_launch_shapes_agree_bitwise(N):
+    models, reqs = _vt_setup(1, seed=62)
+    reqs = reqs[:24]
+    outs = []
+    for shape in ((1, 4, 16), (2, 8, 8), (8, 32, 4), (1, 1, 32)):
+        c = N.Context(0)
+        c.set_launch(*shape)
+        outs.append(_run_pages(N, c, models, reqs, 1)[0])
+        c.close()
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+
+
+# ---------------------------------------------------- full-size frame + random queries
+@pytest.fixture(scope="module")
+def c2_model():
+    return I.random_model(4096, 4096, 1024, 1024, 24, np.float16, np.float16, config=2)
+
+
+def test_c2_frame_and_random_sampled(N, ctx, c2_model):
+    """4096^2 atlas, T = 24, FP16 storage: the full frame through the page decoder and
+    16M random queries, both at their real size, checked on sampled outputs."""
+    import torch
+    m = c2_model
+    dm = N.DeviceModel.from_numpy(m)
+    marr = N.models_array([dm])
+    t = float(I.rng(2, I.P_QUERY).random(dtype=np.float32))
+    py, px = np.meshgrid(np.arange(32), np.arange(32), indexing="ij")
+    rq = N.page_requests(np.zeros(1024, np.int32), px.ravel().astype(np.int32), py.ravel().astype(np.int32),
+                         np.full(1024, t, np.float32), (py * 128 * 4096 + px * 128).ravel().astype(np.int64))
+    nreq = torch.tensor([1024], dtype=torch.int32, device="cuda")
+    g = np.random.default_rng(21)
+    sel = g.integers(0, 4096 * 4096, 1 << 16)
+    xs, ys = sel % 4096, sel // 4096
+    ref = O.decode_f64(m, (xs + 0.5) / 4096, (ys + 0.5) / 4096, np.full(sel.size, np.float64(np.float32(t))))
+    for prec, tol in ((1, TOL16), (0, TOL32)):
+        dst = torch.empty((4096 * 4096, 3), dtype=torch.float16 if prec else torch.float32, device="cuda")
+        ctx.decode_pages(marr, 1, rq, nreq, 1024, 128, dst, 4096, prec)
+        got = dst[torch.from_numpy(sel).cuda()].float().cpu().numpy()
+        assert_rel(got, ref, tol, f"frame prec {prec}")
+    q = I.uniform_queries(16_000_000, I.rng(2, I.P_QUERY, 1))
+    qd = torch.from_numpy(q).cuda()
+    sel = g.integers(0, q.shape[0], 1 << 16)
+    ref = O.decode(m, q[sel])
+    for prec, tol in ((1, TOL16), (0, TOL32)):
+        out = ctx.decode(dm, qd, prec)
+        got = out[torch.from_numpy(sel).cuda()].float().cpu().numpy()
+        assert_rel(got, ref, tol, f"random prec {prec}")

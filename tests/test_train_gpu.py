@@ -1,0 +1,194 @@
+"""GPU parity of the training path (BC-simulated forward, FP64 loss, hand-written backward,
+Adam, export, tile statistics) against the CPU oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from oracle import ndgi_oracle as O
+from paper_2604_12625_amd import inputs as I
+from tests.gpu_util import assert_rel, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = torch_cuda()
+    from paper_2604_12625_amd import ndgi as N
+    from paper_2604_12625_amd import train as TR
+    ctx = N.Context(0)
+    yield torch, N, TR, ctx
+    ctx.close()
+
+
+def problem(W, H, Gw, Gh, T, B, seed, tgt_scale=2.0):
+    g = I.rng(40 + seed, I.P_INIT)
+    st = I.train_init(W, H, Gw, Gh, T, [0.5, 0.4, 0.3], g)
+    st["grid"] = (st["grid"] * 5.0).astype(np.float32)
+    x, y, k = I.train_samples(B, W, H, T, I.rng(40 + seed, I.P_SAMPLES))
+    tgt = g.uniform(0.05, tgt_scale, (T, H, W, 3)).astype(np.float16)
+    return st, x, y, k, tgt
+
+
+def device_batch(torch, x, y, k, tgt):
+    smp = torch.from_numpy(I.pack_samples(x, y, k).view(np.int32)).cuda()
+    tg = torch.from_numpy(tgt.view(np.int16)).cuda()
+    return smp, tg
+
+
+def assert_grad(got, ref, what, rel=1e-4):
+    """Per element |got - ref| <= rel * |ref| + rel * 1e-2 * max|ref| (FP32 atomics reorder sums)."""
+    got = np.asarray(got, dtype=np.float64).ravel()
+    ref = np.asarray(ref, dtype=np.float64).ravel()
+    scale = np.max(np.abs(ref)) if ref.size else 0.0
+    bad = np.abs(got - ref) > rel * np.abs(ref) + rel * 1e-2 * scale
+    assert not bad.any(), f"{what}: {int(bad.sum())} of {bad.size} elements off " \
+                          f"(worst {np.max(np.abs(got - ref)):.3e}, scale {scale:.3e})"
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 4, 4, 4, 1000), (64, 32, 16, 8, 6, 4097), (12, 8, 5, 3, 3, 37)])
+def test_forward_loss_and_gradients(env, shape):
+    torch, N, TR, ctx = env
+    W, H, Gw, Gh, T, B = shape
+    st, x, y, k, tgt = problem(W, H, Gw, Gh, T, B, seed=W + B)
+    tr = TR.Trainer(ctx, st)
+    smp, tg = device_batch(torch, x, y, k, tgt)
+    pred = tr.forward(smp)
+    ref_pred = O.train_forward(st, x, y, k)
+    assert_rel(pred.cpu().numpy(), ref_pred, 1e-5, "train forward")
+    loss = float(tr.loss_grad(smp, tg).item())
+    ref_loss, ref = O.train_grads(st, x, y, k, tgt[k, y, x].astype(np.float64))
+    assert abs(loss - ref_loss) <= 2e-6 * ref_loss
+    gr = tr.split(tr.grads)
+    for key in ("mlp", "grid", "endpoints", "weights"):
+        assert_grad(gr[key].cpu().numpy(), ref[key], key)
+
+
+def test_backward_mode_equals_loss_gradient(env):
+    torch, N, TR, ctx = env
+    st, x, y, k, tgt = problem(32, 32, 8, 8, 4, 3000, seed=7)
+    smp, tg = device_batch(torch, x, y, k, tgt)
+    a = TR.Trainer(ctx, st)
+    a.loss_grad(smp, tg)
+    b = TR.Trainer(ctx, st)
+    pred = b.forward(smp)
+    tv = torch.from_numpy(tgt[k, y, x].astype(np.float32)).cuda()
+    gp = (2.0 / (3 * len(x))) * (pred - tv)
+    b.backward(smp, gp.contiguous())
+    assert_grad(b.grads.cpu().numpy(), a.grads.cpu().numpy(), "backward vs loss_grad", rel=1e-5)
+
+
+def test_autograd_function_matches_finite_differences(env):
+    torch, N, TR, ctx = env
+    st, x, y, k, tgt = problem(16, 16, 4, 4, 4, 600, seed=8)
+    smp, tg = device_batch(torch, x, y, k, tgt)
+    tr = TR.Trainer(ctx, st)
+    tr.params.requires_grad_(True)
+    tv = torch.from_numpy(tgt[k, y, x].astype(np.float32)).cuda()
+    pred = TR.ndgi_apply(tr, smp)
+    loss = ((pred - tv) ** 2).mean()
+    loss.backward()
+    grad = tr.params.grad.detach().cpu().numpy()
+    # central differences of the oracle loss (FP64) on decoder and grid parameters
+    n_e = np.asarray(st["endpoints"]).size
+    n_w = np.asarray(st["weights"]).size
+    n_g = np.asarray(st["grid"]).size
+    idx = np.concatenate([np.arange(n_e + n_w + n_g, tr.n_params)[::37],
+                          np.arange(n_e + n_w, n_e + n_w + n_g)[::11]])
+    flat = np.concatenate([np.asarray(st[kk], np.float64).ravel() for kk in ("endpoints", "weights", "grid", "mlp")])
+    h = 1e-5
+    for i in idx:
+        for sgn, store in ((1, "p"), (-1, "m")):
+            f2 = flat.copy()
+            f2[i] += sgn * h
+            s2 = dict(st)
+            off = 0
+            for kk in ("endpoints", "weights", "grid", "mlp"):
+                n = np.asarray(st[kk]).size
+                s2[kk] = f2[off:off + n].reshape(np.asarray(st[kk]).shape)
+                off += n
+            val = O.l2_loss(O.train_forward(s2, x, y, k), tgt[k, y, x].astype(np.float64))
+            if store == "p":
+                lp = val
+            else:
+                lm = val
+        fd = (lp - lm) / (2 * h)
+        assert abs(grad[i] - fd) <= 1e-3 * abs(fd) + 1e-7, (int(i), grad[i], fd)
+
+
+def test_fused_steps_match_oracle_on_c4_sized_problem(env):
+    """1024^2 x 24 state (22M parameters), 2^12 samples, 3 fused steps (Adam lr 1e-2/1e-3)."""
+    torch, N, TR, ctx = env
+    W = H = 1024
+    Gw = Gh = 256
+    T = 24
+    g = I.rng(4, I.P_INIT)
+    st = I.train_init(W, H, Gw, Gh, T, [0.5, 0.4, 0.3], g)
+    tr = TR.Trainer(ctx, st, lr_feat=1e-2, lr_mlp=1e-3)
+    opt = dict(step=0, lr_feat=1e-2, lr_mlp=1e-3,
+               m={kk: np.zeros(np.asarray(st[kk]).shape) for kk in ("endpoints", "weights", "grid", "mlp")},
+               v={kk: np.zeros(np.asarray(st[kk]).shape) for kk in ("endpoints", "weights", "grid", "mlp")})
+    ref = {kk: np.asarray(st[kk], np.float64).copy() for kk in ("endpoints", "weights", "grid", "mlp")}
+    ref["dims"] = st["dims"]
+    for step in range(3):
+        x, y, k = I.train_samples(4096, W, H, T, I.rng(4, I.P_SAMPLES, step))
+        tv = g.uniform(0.05, 3.0, (4096, 3)).astype(np.float16)
+        tgt = np.zeros((T, H, W, 3), dtype=np.float16)
+        tgt[k, y, x] = tv
+        smp, tg = device_batch(torch, x, y, k, tgt)
+        loss = float(tr.step(smp, tg).item())
+        ref_loss = O.train_step(ref, opt, x, y, k, tgt[k, y, x].astype(np.float64))
+        assert abs(loss - ref_loss) <= 1e-5 * ref_loss, (step, loss, ref_loss)
+    assert tr.step_count == 3
+    got = tr.split(tr.params)
+    # Adam moves a parameter by about lr per step whatever the gradient's size, so FP32
+    # gradient noise on a cancelling sum shows up as a fraction of lr: the absolute floor
+    # is 1e-3 * lr per step.  Separately, an FP32 and an FP64 master value can round to
+    # different 8-bit endpoints / 3-bit weights at a quantisation boundary, which changes
+    # that texel's feature by a code step; all but 1e-3 of the parameters must match to
+    # 1e-4 relative + 1e-6.
+    for kk in ("mlp", "grid", "endpoints", "weights"):
+        lr = 1e-3 if kk == "mlp" else 1e-2
+        a = got[kk].cpu().numpy().astype(np.float64)
+        b = ref[kk]
+        err = np.abs(a - b)
+        bad = err > 1e-4 * np.abs(b) + 3e-3 * lr
+        assert bad.sum() == 0, f"{kk}: {int(bad.sum())} params off, worst {err.max():.3e}"
+        loose = err > 1e-4 * np.abs(b) + 1e-6
+        assert loose.sum() <= max(1, int(1e-3 * b.size)), f"{kk}: {int(loose.sum())} params above 1e-4"
+    assert float(tr.grads.abs().max()) == 0.0       # Adam zeroes the gradients
+
+
+def test_export_decodes_to_bc_simulation_bit_exact(env):
+    torch, N, TR, ctx = env
+    st, x, y, k, tgt = problem(64, 48, 16, 12, 5, 10, seed=9)
+    ep = st["endpoints"]
+    ep[0, 0, 0] = [0.5, 0.5]
+    ep[0, 1, 1] = [0.2, 0.9]
+    st["weights"][0, :4, :] = 0.0
+    st["weights"][1, :4, :] = 1.0
+    tr = TR.Trainer(ctx, st)
+    dm = tr.export(N.DTYPE_F16, N.DTYPE_F16)
+    blocks = dm.bc4.cpu().numpy()
+    np.testing.assert_array_equal(blocks, O.export_bc4(st["endpoints"], st["weights"]))
+    dec = N.bc4_decode_blocks(dm.bc4.view(-1, 8)).cpu().numpy().reshape(12, 16, 8, 4, 4)
+    yy, xx = np.meshgrid(np.arange(48), np.arange(64), indexing="ij")
+    val, *_ = O.bcsim_spatial(st["endpoints"], st["weights"], xx.ravel(), yy.ravel())
+    np.testing.assert_array_equal(dec[yy >> 2, xx >> 2, :, yy & 3, xx & 3].reshape(-1, 8), val)
+    np.testing.assert_array_equal(dm.grid.cpu().numpy(), st["grid"].astype(np.float16))
+    np.testing.assert_array_equal(dm.mlp.cpu().numpy(), st["mlp"].astype(np.float16))
+
+
+def test_tile_stats_match_oracle_psnr(env):
+    torch, N, TR, ctx = env
+    g = np.random.default_rng(30)
+    T, H, W = 2, 300, 260                       # ragged tiles on both axes
+    tgt = g.uniform(0.0, 4.0, (T, H, W, 3)).astype(np.float16)
+    tgt[1, :128, :128] = 1.5                    # a zero-range tile (skipped)
+    pred = (tgt.astype(np.float32) + g.normal(0, 0.01, tgt.shape)).astype(np.float32)
+    stats = [ctx.tile_stats(torch.from_numpy(pred[kk]).cuda(),
+                            torch.from_numpy(tgt[kk].view(np.int16)).cuda(), W, H, 128).cpu().numpy()
+             for kk in range(T)]
+    tiled, glob = N.psnr_from_stats(stats, W, H, 128)
+    want_tiled, want_glob = O.psnr_tiled(pred, tgt, 128)
+    assert abs(tiled - want_tiled) < 1e-9
+    assert abs(glob - want_glob) < 1e-9
