@@ -188,7 +188,7 @@ def features(model: dict, u: np.ndarray, v: np.ndarray, t: np.ndarray) -> np.nda
             S += (wx * wy)[..., None] * tex
 
     Gw, Gh, T = model["Gw"], model["Gh"], model["T"]
-    grid = np.asarray(model["grid"]).astype(np.float64)     # [T][Gh][Gw][8]
+    grid = np.asarray(model["grid"])                         # [T][Gh][Gw][8], as stored
     gx0, gx1, gwx0, gwx1 = _axis(u, Gw)
     gy0, gy1, gwy0, gwy1 = _axis(v, Gh)
     k0, k1, wt0, wt1 = _time_keys(t, T)
@@ -196,7 +196,7 @@ def features(model: dict, u: np.ndarray, v: np.ndarray, t: np.ndarray) -> np.nda
     for (kk, wt) in ((k0, wt0), (k1, wt1)):
         for (yy, wy) in ((gy0, gwy0), (gy1, gwy1)):
             for (xx, wx) in ((gx0, gwx0), (gx1, gwx1)):
-                G += (wt * wy * wx)[..., None] * grid[kk, yy, xx]
+                G += (wt * wy * wx)[..., None] * grid[kk, yy, xx].astype(np.float64)
     return np.concatenate([S, G], axis=-1)
 
 
@@ -339,12 +339,12 @@ def train_forward(state: dict, xs, ys, ks, need_cache: bool = False):
     dims = state["dims"]
     val, E1, E2, J = bcsim_spatial(state["endpoints"], state["weights"], xs, ys)
     S = val.astype(np.float64) / 255.0
-    grid = np.asarray(state["grid"]).astype(np.float64)
+    grid = np.asarray(state["grid"])
     ks = np.asarray(ks, dtype=np.int64)
     corners = _sample_coords(dims, xs, ys)
     G = np.zeros(S.shape, dtype=np.float64)
     for (gy, gx, w) in corners:
-        G += w[..., None] * grid[ks, gy, gx]
+        G += w[..., None] * grid[ks, gy, gx].astype(np.float64)
     x = np.concatenate([S, G], axis=-1)
     P = unpack_mlp(state["mlp"])
     a1 = x @ P["W1"].T + P["b1"]
