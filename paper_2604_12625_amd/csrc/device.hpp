@@ -25,8 +25,10 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 // packed decoder parameters [W1 32x16 | b1 | W2 32x32 | b2 | W3 3x32 | b3]
 constexpr int kOffW1 = 0, kOffB1 = 512, kOffW2 = 544, kOffB2 = 1568, kOffW3 = 1600, kOffB3 = 1696;
 
-__device__ __forceinline__ float mlp_at(const void* p, int dt, int i) {
-  return dt == NDGI_DTYPE_F16 ? (float)((const _Float16*)p)[i] : ((const float*)p)[i];
+template <int DT>
+__device__ __forceinline__ float ld(const void* p, size_t i) {
+  if constexpr (DT == NDGI_DTYPE_F16) return (float)((const _Float16*)p)[i];
+  else return ((const float*)p)[i];
 }
 
 // Decoder input fed by element e (0..3) of lane group g in the first layer:
@@ -35,6 +37,13 @@ __device__ __forceinline__ int input_of(int g, int e) { return e < 2 ? 2 * g + e
 // Hidden unit fed by element e (0..7) of lane group g in a 32-deep K operand: the
 // lane's rows 4g..4g+3 of the first and of the second 16-row output tile.
 __device__ __forceinline__ int unit_of(int g, int e) { return e < 4 ? 4 * g + e : 16 + 4 * g + (e - 4); }
+
+// Order LDS traffic of one wave: writes before the barrier are visible to reads after it.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // ------------------------------------------------------------------------ BC4 texel
 // 8-byte block: e0, e1, then a 48-bit little-endian selector field; texel s uses bits
@@ -64,10 +73,12 @@ __device__ __forceinline__ uint32_t bc4_texel(uint32_t lo, uint32_t hi, uint32_t
 struct Axis { int i0, i1; float w0, w1; };
 
 // Axis of normalised coordinate c with the texel-centre convention: continuous position
-// c*size - 0.5, neighbours floor() and floor()+1 clamped to [0, size-1].  The fraction is
-// one fused multiply-add of the exact product, c*size - 0.5 - floor(...), so it carries a
-// single rounding (a separately rounded product would add up to half an ulp of c*size,
-// about 1e-5 texel at size 192).  A position clamped to [-1, size] (including NaN) gets
+// c*size - 0.5, neighbours floor() and floor()+1 clamped to [0, size-1].  The cell and the
+// fraction come from the exact product: the fraction is one fused multiply-add,
+// c*size - 0.5 - floor(...), so it carries a single rounding, and a rounded position that
+// lands on an integer above the exact one is moved back to the cell below.  (With a
+// rounded product the fraction is off by up to half an ulp of c*size, about 1e-5 texel at
+// size 192, and the wrong cell extrapolates across a texel discontinuity.)  A position clamped to [-1, size] (including NaN) gets
 // fraction 0: both neighbours are then the same edge texel.
 __device__ __forceinline__ Axis coord_axis(float c, int size) {
   const float s = (float)size;
@@ -75,8 +86,14 @@ __device__ __forceinline__ Axis coord_axis(float c, int size) {
   const float qc = fminf(fmaxf(q0, -1.0f), s);
   const float qf = floorf(qc);
   float f = fmaf(c, s, -0.5f - qf);
+  int i = (int)qf;
+  // the rounded position can land on the integer just above the exact one (never below):
+  // then the exact fraction is negative and the cell is the one below
+  if (f < 0.0f) {
+    f += 1.0f;
+    i -= 1;
+  }
   f = (q0 == qc) ? f : 0.0f;
-  const int i = (int)qf;
   Axis a;
   a.i0 = min(max(i, 0), size - 1);
   a.i1 = min(max(i + 1, 0), size - 1);
@@ -88,9 +105,10 @@ __device__ __forceinline__ Axis coord_axis(float c, int size) {
 // Axis on a grid of G nodes for the centre of texel x of a map S texels wide: position
 // (x + 0.5) * G / S - 0.5 = ((2x + 1) G - S) / (2S), split into floor and fraction with
 // integer arithmetic (exact); the common S = 4G case needs only shifts.
+template <bool R4>
 __device__ __forceinline__ Axis texel_axis(int x, int G, int S) {
   int q, r, den;
-  if (S == 4 * G) {
+  if constexpr (R4) {
     const int num = 2 * x - 3;              // position * 8
     q = num >> 3;                           // floor division (arithmetic shift)
     r = num & 7;
@@ -120,17 +138,22 @@ __device__ __forceinline__ Keys make_keys(float t, int T) {
   const float kf = floorf(fmaf(tw, s, 0.0f));
   Keys k;
   k.w1 = fmaf(tw, s, -kf);
-  k.w0 = 1.0f - k.w1;
   int k0 = (int)kf;
-  k0 = k0 >= T ? k0 - T : k0;
+  if (k.w1 < 0.0f) {            // rounded t*T landed on the key above the exact value
+    k.w1 += 1.0f;
+    k0 -= 1;
+  }
+  k.w0 = 1.0f - k.w1;
+  k0 = k0 < 0 ? k0 + T : (k0 >= T ? k0 - T : k0);
   k.k0 = k0;
   k.k1 = k0 + 1 >= T ? 0 : k0 + 1;
   return k;
 }
 
 // Grid channels (2p, 2p+1) of node `node` ([T][Gh][Gw] flattened), 8 channels per node.
-__device__ __forceinline__ float2 grid_pair(const void* grid, int dt, size_t node, int p) {
-  if (dt == NDGI_DTYPE_F16) {
+template <int GDT>
+__device__ __forceinline__ float2 grid_pair(const void* grid, size_t node, int p) {
+  if constexpr (GDT == NDGI_DTYPE_F16) {
     const uint32_t w = ((const uint32_t*)grid)[node * 4 + p];
     const _Float16 lo = __builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
     const _Float16 hi = __builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
@@ -140,6 +163,7 @@ __device__ __forceinline__ float2 grid_pair(const void* grid, int dt, size_t nod
 }
 
 // Grid sample of channels 2g, 2g+1: bilinear in space on the node axes, linear in time.
+template <int GDT>
 __device__ __forceinline__ float2 grid_sample(const ndgi_model& m, const Axis& ax, const Axis& ay, const Keys& k,
                                               int g) {
   float a = 0.0f, b = 0.0f;
@@ -156,7 +180,7 @@ __device__ __forceinline__ float2 grid_sample(const ndgi_model& m, const Axis& a
       for (int xx = 0; xx < 2; ++xx) {
         const int gx = xx ? ax.i1 : ax.i0;
         const float w = wy * (xx ? ax.w1 : ax.w0);
-        const float2 v = grid_pair(m.grid, m.grid_dtype, row + gx, g);
+        const float2 v = grid_pair<GDT>(m.grid, row + gx, g);
         a = fmaf(w, v.x, a);
         b = fmaf(w, v.y, b);
       }
@@ -173,6 +197,7 @@ __device__ __forceinline__ uint2 spatial_pair(const ndgi_model& m, int x, int y,
 }
 
 // Lane inputs for an explicit query (u, v, t).
+template <int GDT>
 __device__ __forceinline__ void query_inputs(const ndgi_model& m, float u, float v, float t, int g, float f[4]) {
   const Axis ax = coord_axis(u, m.W);
   const Axis ay = coord_axis(v, m.H);
@@ -191,7 +216,7 @@ __device__ __forceinline__ void query_inputs(const ndgi_model& m, float u, float
     }
   }
   const Keys k = make_keys(t, m.T);
-  const float2 gv = grid_sample(m, coord_axis(u, m.Gw), coord_axis(v, m.Gh), k, g);
+  const float2 gv = grid_sample<GDT>(m, coord_axis(u, m.Gw), coord_axis(v, m.Gh), k, g);
   f[0] = s0 * (1.0f / 255.0f);
   f[1] = s1 * (1.0f / 255.0f);
   f[2] = gv.x;
@@ -200,9 +225,10 @@ __device__ __forceinline__ void query_inputs(const ndgi_model& m, float u, float
 
 // Lane inputs at the centre of texel (x, y) (page / frame decode): the spatial sample is
 // the texel itself; the grid axes come from texel_axis.
+template <int GDT, bool R4>
 __device__ __forceinline__ void texel_inputs(const ndgi_model& m, int x, int y, const Keys& k, int g, float f[4]) {
   const uint2 s = spatial_pair(m, x, y, g);
-  const float2 gv = grid_sample(m, texel_axis(x, m.Gw, m.W), texel_axis(y, m.Gh, m.H), k, g);
+  const float2 gv = grid_sample<GDT>(m, texel_axis<R4>(x, m.Gw, m.W), texel_axis<R4>(y, m.Gh, m.H), k, g);
   f[0] = (float)s.x * (1.0f / 255.0f);
   f[1] = (float)s.y * (1.0f / 255.0f);
   f[2] = gv.x;
@@ -211,32 +237,123 @@ __device__ __forceinline__ void texel_inputs(const ndgi_model& m, int x, int y, 
 
 // ------------------------------------------------------------------ FP16 MFMA decoder
 // Every FP16 operand that is not stored data (decoder inputs, hidden activations) is fed
-// as a compensated pair v = hi + lo, hi = fp16(v), lo = fp16(v - hi), so the products see
-// about 22 bits of v; the weights are exact in FP16.  The lo halves double the K depth of
-// each layer: layer 1 (K = 16 -> 32) still takes one v_mfma_f32_16x16x32_f16 per 16 rows,
+// as a compensated pair v = hi + lo with lo = fp16(v - hi), so the products see about 22
+// bits of v; the weights are exact in FP16.  The lo halves double the K depth of each
+// layer: layer 1 (K = 16 -> 32) still takes one v_mfma_f32_16x16x32_f16 per 16 rows,
 // layers 2 and 3 take two.  Without the lo terms the FP16 rounding of inputs and
 // activations alone reaches 2.5e-3 relative output error on He-normal decoders.
+//
+// Two layer-1 input forms share the rest of the decoder:
+//  * general (explicit queries): K slots [S_2g, S_2g+1, G_2g, G_2g+1] as hi, then as lo;
+//  * texel centres: the spatial texel is an exact integer, fed as the FP16 value
+//    1024 + u8 (bit pattern 0x6400 | u8) in both halves of K, against the hi and the lo
+//    part of W1/255; the 1024 offset is removed through the bias.  Only the grid inputs
+//    need a hi/lo split.
+
+// d.lo16 = fp16(v0 - hi.lo16), d.hi16 = fp16(v1 - hi.hi16): the residuals of a packed
+// pair of FP16 values against the FP32 values they came from (one v_fma_mix each).
+__device__ __forceinline__ uint32_t resid_pair(uint32_t hi, float v0, float v1) {
+  uint32_t d = 0;
+  asm("v_fma_mixlo_f16 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "+v"(d) : "v"(hi), "v"(v0));
+  asm("v_fma_mixhi_f16 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "+v"(d) : "v"(hi), "v"(v1));
+  return d;
+}
+// Same with the result clamped to [0, 1] (the hardware clamp bit).
+__device__ __forceinline__ uint32_t resid_pair_clamp(uint32_t hi, float v0, float v1) {
+  uint32_t d = 0;
+  asm("v_fma_mixlo_f16 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0] clamp" : "+v"(d) : "v"(hi), "v"(v0));
+  asm("v_fma_mixhi_f16 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0] clamp" : "+v"(d) : "v"(hi), "v"(v1));
+  return d;
+}
+
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+
+// ReLU and hi/lo split of two 4-row output tiles into two 8-element K shares.  hi is
+// rounded toward zero, so for a positive value the residual lies in [0, 1) and for a
+// non-positive value it is <= 0: clamping the residual to [0, 1] is then exactly the ReLU
+// of the lo part, and max(hi, 0) the ReLU of the hi part.
+__device__ __forceinline__ void relu_split(const f4v& p0, const f4v& p1, h8v& hi, h8v& lo) {
+  u4v H, Lo;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const f4v& p = t ? p1 : p0;
+#pragma unroll
+    for (int r = 0; r < 4; r += 2) {
+      h2v v = __builtin_bit_cast(h2v, __builtin_amdgcn_cvt_pkrtz(p[r], p[r + 1]));
+      v = __builtin_elementwise_max(v, (h2v){0, 0});
+      const uint32_t hb = __builtin_bit_cast(uint32_t, v);
+      H[2 * t + r / 2] = hb;
+      Lo[2 * t + r / 2] = resid_pair_clamp(hb, p[r], p[r + 1]);
+    }
+  }
+  hi = __builtin_bit_cast(h8v, H);
+  lo = __builtin_bit_cast(h8v, Lo);
+}
+
+// hi/lo split of four general inputs into the layer-1 K share [hi(4), lo(4)].
+__device__ __forceinline__ h8v split_inputs(const float f[4]) {
+  const uint32_t h01 = __builtin_bit_cast(uint32_t, (h2v){(_Float16)f[0], (_Float16)f[1]});
+  const uint32_t h23 = __builtin_bit_cast(uint32_t, (h2v){(_Float16)f[2], (_Float16)f[3]});
+  const u4v x = {h01, h23, resid_pair(h01, f[0], f[1]), resid_pair(h23, f[2], f[3])};
+  return __builtin_bit_cast(h8v, x);
+}
+
+// Layer-1 K share at a texel centre: spatial pair given as 0x6400|u8 halves, grid pair split.
+__device__ __forceinline__ h8v texel_x(uint32_t sp, float ga, float gb) {
+  const uint32_t gh = __builtin_bit_cast(uint32_t, (h2v){(_Float16)ga, (_Float16)gb});
+  const u4v x = {sp, gh, sp, resid_pair(gh, ga, gb)};
+  return __builtin_bit_cast(h8v, x);
+}
+
 struct Dec16 {
-  h8v a1[2];   // W1 rows 16mc + i: inputs input_of(g, 0..3), then the same four again (lo)
+  h8v a1[2];   // layer 1, rows 16mc + i (see load_dec16 for the K slots)
   h8v a2[2];   // W2 rows 16mo + i, units unit_of(g, 0..7)
   h8v a3[4];   // W3 placed at rows 4q..4q+2 for group q, zero elsewhere
   f4v c1[2], c2[2], c3;   // biases in C layout (rows 4g..4g+3)
 };
 
-__device__ __forceinline__ void load_dec16(Dec16& d, const void* mlp, int dt, int lane) {
+// TEXEL = false: layer-1 slots e = 0..3 take W1 at input_of(g, e), slots 4..7 the same
+// weights (they multiply the lo halves).  TEXEL = true: slots 0, 1 take hi(W1/255) of
+// spatial 2g, 2g+1, slots 4, 5 lo(W1/255), slots 2, 3 and 6, 7 the grid weights; c1 has
+// 1024 * sum_s (hi + lo) removed.
+template <int MDT, bool TEXEL>
+__device__ __forceinline__ void load_dec16(Dec16& d, const void* mlp, int lane) {
   const int g = lane >> 4, i = lane & 15;
 #pragma unroll
   for (int mc = 0; mc < 2; ++mc) {
+    const int u = 16 * mc + i;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int in = input_of(g, e & 3);
+      const float w = ld<MDT>(mlp, kOffW1 + u * 16 + in);
+      if (TEXEL && (e & 3) < 2) {
+        const float ws = w * (1.0f / 255.0f);
+        const _Float16 hi = (_Float16)ws;
+        d.a1[mc][e] = e < 4 ? hi : (_Float16)(ws - (float)hi);
+      } else {
+        d.a1[mc][e] = (_Float16)w;
+      }
+    }
 #pragma unroll
     for (int e = 0; e < 8; ++e)
-      d.a1[mc][e] = (_Float16)mlp_at(mlp, dt, kOffW1 + (16 * mc + i) * 16 + input_of(g, e & 3));
-#pragma unroll
-    for (int e = 0; e < 8; ++e)
-      d.a2[mc][e] = (_Float16)mlp_at(mlp, dt, kOffW2 + (16 * mc + i) * 32 + unit_of(g, e));
+      d.a2[mc][e] = (_Float16)ld<MDT>(mlp, kOffW2 + u * 32 + unit_of(g, e));
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      d.c1[mc][r] = mlp_at(mlp, dt, kOffB1 + 16 * mc + 4 * g + r);
-      d.c2[mc][r] = mlp_at(mlp, dt, kOffB2 + 16 * mc + 4 * g + r);
+      const int ur = 16 * mc + 4 * g + r;
+      float b = ld<MDT>(mlp, kOffB1 + ur);
+      if (TEXEL) {
+        float off = 0.0f;
+#pragma unroll
+        for (int sc = 0; sc < 8; ++sc) {
+          const float ws = ld<MDT>(mlp, kOffW1 + ur * 16 + sc) * (1.0f / 255.0f);
+          const _Float16 hi = (_Float16)ws;
+          off += (float)hi + (float)(_Float16)(ws - (float)hi);
+        }
+        b -= 1024.0f * off;
+      }
+      d.c1[mc][r] = b;
+      d.c2[mc][r] = ld<MDT>(mlp, kOffB2 + ur);
     }
   }
 #pragma unroll
@@ -244,32 +361,15 @@ __device__ __forceinline__ void load_dec16(Dec16& d, const void* mlp, int dt, in
 #pragma unroll
     for (int e = 0; e < 8; ++e)
       d.a3[q][e] = ((i >> 2) == q && (i & 3) < 3)
-                       ? (_Float16)mlp_at(mlp, dt, kOffW3 + (i & 3) * 32 + unit_of(g, e))
+                       ? (_Float16)ld<MDT>(mlp, kOffW3 + (i & 3) * 32 + unit_of(g, e))
                        : (_Float16)0.0f;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) d.c3[r] = r < 3 ? mlp_at(mlp, dt, kOffB3 + r) : 0.0f;
+  for (int r = 0; r < 4; ++r) d.c3[r] = r < 3 ? ld<MDT>(mlp, kOffB3 + r) : 0.0f;
 }
 
-// hi/lo split of ReLU'd pre-activations (two 4-row tiles) into two 8-element K shares
-__device__ __forceinline__ void relu_split(const f4v& p0, const f4v& p1, h8v& hi, h8v& lo) {
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const float a = __builtin_fmaxf(p0[r], 0.0f), b = __builtin_fmaxf(p1[r], 0.0f);
-    hi[r] = (_Float16)a;
-    hi[4 + r] = (_Float16)b;
-    lo[r] = (_Float16)(a - (float)hi[r]);
-    lo[4 + r] = (_Float16)(b - (float)hi[4 + r]);
-  }
-}
-
-// One 16-texel group through the decoder; the output layer accumulates into acc.
-__device__ __forceinline__ void dec16_group(const Dec16& d, const float f[4], int q, f4v& acc) {
-  h8v x;
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    x[e] = (_Float16)f[e];
-    x[4 + e] = (_Float16)(f[e] - (float)x[e]);
-  }
+// One 16-texel group through the decoder from its layer-1 K share; the output layer
+// accumulates into acc.
+__device__ __forceinline__ void dec16_group(const Dec16& d, const h8v& x, int q, f4v& acc) {
   const f4v p0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(d.a1[0], x, d.c1[0], 0, 0, 0);
   const f4v p1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(d.a1[1], x, d.c1[1], 0, 0, 0);
   h8v h, hl;
@@ -295,27 +395,28 @@ struct Dec32 {
   f4v c1[2], c2[2], c3;
 };
 
-__device__ __forceinline__ void load_dec32(Dec32& d, const void* mlp, int dt, int lane) {
+template <int MDT>
+__device__ __forceinline__ void load_dec32(Dec32& d, const void* mlp, int lane) {
   const int g = lane >> 4, i = lane & 15;
 #pragma unroll
   for (int mc = 0; mc < 2; ++mc) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) d.a1[mc][e] = mlp_at(mlp, dt, kOffW1 + (16 * mc + i) * 16 + input_of(g, e));
+    for (int e = 0; e < 4; ++e) d.a1[mc][e] = ld<MDT>(mlp, kOffW1 + (16 * mc + i) * 16 + input_of(g, e));
 #pragma unroll
-    for (int e = 0; e < 8; ++e) d.a2[mc][e] = mlp_at(mlp, dt, kOffW2 + (16 * mc + i) * 32 + unit_of(g, e));
+    for (int e = 0; e < 8; ++e) d.a2[mc][e] = ld<MDT>(mlp, kOffW2 + (16 * mc + i) * 32 + unit_of(g, e));
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      d.c1[mc][r] = mlp_at(mlp, dt, kOffB1 + 16 * mc + 4 * g + r);
-      d.c2[mc][r] = mlp_at(mlp, dt, kOffB2 + 16 * mc + 4 * g + r);
+      d.c1[mc][r] = ld<MDT>(mlp, kOffB1 + 16 * mc + 4 * g + r);
+      d.c2[mc][r] = ld<MDT>(mlp, kOffB2 + 16 * mc + 4 * g + r);
     }
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int e = 0; e < 8; ++e)
-      d.a3[q][e] = ((i >> 2) == q && (i & 3) < 3) ? mlp_at(mlp, dt, kOffW3 + (i & 3) * 32 + unit_of(g, e)) : 0.0f;
+      d.a3[q][e] = ((i >> 2) == q && (i & 3) < 3) ? ld<MDT>(mlp, kOffW3 + (i & 3) * 32 + unit_of(g, e)) : 0.0f;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) d.c3[r] = r < 3 ? mlp_at(mlp, dt, kOffB3 + r) : 0.0f;
+  for (int r = 0; r < 4; ++r) d.c3[r] = r < 3 ? ld<MDT>(mlp, kOffB3 + r) : 0.0f;
 }
 
 __device__ __forceinline__ void dec32_group(const Dec32& d, const float f[4], int q, f4v& acc) {
@@ -351,13 +452,21 @@ __device__ __forceinline__ void dec32_group(const Dec32& d, const float f[4], in
 template <int PREC> struct Dec;
 template <> struct Dec<NDGI_PREC_F16> {
   Dec16 d;
-  __device__ __forceinline__ void load(const void* mlp, int dt, int lane) { load_dec16(d, mlp, dt, lane); }
-  __device__ __forceinline__ void group(const float f[4], int q, f4v& acc) const { dec16_group(d, f, q, acc); }
+  __device__ __forceinline__ void load(const void* mlp, int dt, int lane) {
+    if (dt == NDGI_DTYPE_F16) load_dec16<NDGI_DTYPE_F16, false>(d, mlp, lane);
+    else load_dec16<NDGI_DTYPE_F32, false>(d, mlp, lane);
+  }
+  __device__ __forceinline__ void group(const float f[4], int q, f4v& acc) const {
+    dec16_group(d, split_inputs(f), q, acc);
+  }
   __device__ __forceinline__ f4v bias3() const { return d.c3; }
 };
 template <> struct Dec<NDGI_PREC_F32> {
   Dec32 d;
-  __device__ __forceinline__ void load(const void* mlp, int dt, int lane) { load_dec32(d, mlp, dt, lane); }
+  __device__ __forceinline__ void load(const void* mlp, int dt, int lane) {
+    if (dt == NDGI_DTYPE_F16) load_dec32<NDGI_DTYPE_F16>(d, mlp, lane);
+    else load_dec32<NDGI_DTYPE_F32>(d, mlp, lane);
+  }
   __device__ __forceinline__ void group(const float f[4], int q, f4v& acc) const { dec32_group(d, f, q, acc); }
   __device__ __forceinline__ f4v bias3() const { return d.c3; }
 };

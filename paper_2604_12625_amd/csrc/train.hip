@@ -28,12 +28,6 @@ struct TrainLds {
   float dz[16 * 4];
 };
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 __device__ __forceinline__ float half_bits(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
 
 struct TrainDims {
@@ -41,7 +35,7 @@ struct TrainDims {
   int64_t off_w, off_g, off_mlp;   // segment offsets in the flat arrays
 };
 
-template <int MODE>
+template <int MODE, bool R4>
 __global__ __launch_bounds__(256) void k_train(TrainDims d, const float* __restrict__ P, float* __restrict__ G,
                                                 const uint32_t* __restrict__ samples, int64_t n,
                                                 const uint16_t* __restrict__ target, float* __restrict__ pred,
@@ -63,7 +57,7 @@ __global__ __launch_bounds__(256) void k_train(TrainDims d, const float* __restr
 
   // forward weights (as in the FP32 decoder) and transposed weights for the backward pass
   Dec32 fw;
-  load_dec32(fw, mlp, NDGI_DTYPE_F32, lane);
+  load_dec32<NDGI_DTYPE_F32>(fw, mlp, lane);
   float w3t[2], w2t[2][8], w1t[8];
 #pragma unroll
   for (int mc = 0; mc < 2; ++mc) {
@@ -109,7 +103,7 @@ __global__ __launch_bounds__(256) void k_train(TrainDims d, const float* __restr
     float f[4];
     f[0] = (float)(((7 - Ja) * E1a + Ja * E2a + 3) / 7) * (1.0f / 255.0f);
     f[1] = (float)(((7 - Jb) * E1b + Jb * E2b + 3) / 7) * (1.0f / 255.0f);
-    const Axis ax = texel_axis(x, d.Gw, d.W), ay = texel_axis(y, d.Gh, d.H);
+    const Axis ax = texel_axis<R4>(x, d.Gw, d.W), ay = texel_axis<R4>(y, d.Gh, d.H);
     {
       float a = 0.0f, b = 0.0f;
 #pragma unroll
@@ -551,9 +545,18 @@ int ndgi_train_step(ndgi_ctx* c, ndgi_train_state* st, const ndgi_batch* b, int3
     const int64_t cap = c->train_waves / 4;
     if (wgs > cap) wgs = cap;
     const float inv3n = (float)(1.0 / (3.0 * (double)b->n));
-#define NDGI_TRAIN_LAUNCH(M)                                                                                        \
-  hipLaunchKernelGGL(k_train<M>, dim3((unsigned)wgs), dim3(256), 0, s, d, st->params, st->grads, b->samples, b->n, \
-                     b->target, b->pred, b->grad_pred, inv3n, c->partials_dev, c->loss_part_dev, c->flags_dev)
+    const bool r4 = d.W == 4 * d.Gw && d.H == 4 * d.Gh;
+#define NDGI_TRAIN_LAUNCH(M)                                                                                     \
+  do {                                                                                                           \
+    if (r4)                                                                                                      \
+      hipLaunchKernelGGL((k_train<M, true>), dim3((unsigned)wgs), dim3(256), 0, s, d, st->params, st->grads,     \
+                         b->samples, b->n, b->target, b->pred, b->grad_pred, inv3n, c->partials_dev,             \
+                         c->loss_part_dev, c->flags_dev);                                                        \
+    else                                                                                                         \
+      hipLaunchKernelGGL((k_train<M, false>), dim3((unsigned)wgs), dim3(256), 0, s, d, st->params, st->grads,    \
+                         b->samples, b->n, b->target, b->pred, b->grad_pred, inv3n, c->partials_dev,             \
+                         c->loss_part_dev, c->flags_dev);                                                        \
+  } while (0)
     if (mode == NDGI_TRAIN_FORWARD) NDGI_TRAIN_LAUNCH(NDGI_TRAIN_FORWARD);
     else if (mode == NDGI_TRAIN_BACKWARD) NDGI_TRAIN_LAUNCH(NDGI_TRAIN_BACKWARD);
     else NDGI_TRAIN_LAUNCH(NDGI_TRAIN_LOSS_GRAD);
