@@ -79,8 +79,15 @@ def c2_inputs(torch, N, I):
 
 
 def run_c2(args, torch, N, I, ctx):
+    from paper_2604_12625_amd.autotune import tune_pages
     dm, marr, rq, nreq, n_pages, q = c2_inputs(torch, N, I)
     out = {}
+    tune_dst = torch.empty((W * H, 3), dtype=torch.float16, device="cuda")
+    shape, timings = tune_pages(ctx, lambda: ctx.decode_pages(marr, 1, rq, nreq, n_pages, PAGE, tune_dst, W,
+                                                              N.PREC_F16), "frame4096", use_cache=False)
+    del tune_dst
+    log(f"autotuned page launch (tile_w, tile_h, waves/CU) = {shape}")
+    out["launch_shape"] = list(shape)
     for prec, name in ((N.PREC_F16, "f16"), (N.PREC_F32, "f32")):
         dt = torch.float16 if prec == N.PREC_F16 else torch.float32
         frame = torch.empty((W * H, 3), dtype=dt, device="cuda")
@@ -117,6 +124,7 @@ def run_c2(args, torch, N, I, ctx):
 def run_c3(args, torch, N, I, ctx, frames=110, warm=10):
     """32 maps, 2000 page requests per frame (Zipf 1.1), one graph replay per frame."""
     import numpy as np
+    from paper_2604_12625_amd.autotune import tune_pages
     g = I.rng(3, I.P_MODEL)
     sides = I.vt_map_sides(32, g)
     models = []
@@ -134,6 +142,10 @@ def run_c3(args, torch, N, I, ctx, frames=110, warm=10):
         all_rq.append(N.page_requests(mi, px, py, t, offs))
     rq = torch.empty_like(all_rq[0])
     nreq = torch.tensor([n_req], dtype=torch.int32, device="cuda")
+    rq.copy_(all_rq[0])
+    shape, _ = tune_pages(ctx, lambda: ctx.decode_pages(marr, len(models), rq, nreq, n_req, PAGE, dst, pitch,
+                                                        N.PREC_F16), "vt32", use_cache=False)
+    log(f"autotuned VT launch (tile_w, tile_h, waves/CU) = {shape}")
     tm = Timer(torch)
     texels = n_req * PAGE * PAGE
     for f in range(frames):
@@ -147,7 +159,8 @@ def run_c3(args, torch, N, I, ctx, frames=110, warm=10):
     p99 = ms[min(len(ms) - 1, int(round(0.99 * (len(ms) - 1))))]
     log(f"C3 VT frame: p50 {p50:.3f} ms, p99 {p99:.3f} ms ({texels / p50 / 1e6:.1f} G texels/s at p50)")
     assert ctx.error_flags() == 0
-    return dict(p50_ms=p50, p99_ms=p99, texels_per_frame=texels, maps=[int(s) for s in sides])
+    return dict(p50_ms=p50, p99_ms=p99, texels_per_frame=texels, launch_shape=list(shape),
+                maps=[int(s) for s in sides])
 
 
 def run_c4(args, torch, N, I, ctx, steps=None, warm=3):
@@ -285,8 +298,11 @@ def main():
         "fp32_random_queries_per_s": N_RANDOM / (f32["random_ms"] * 1e-3),
         "fp16_over_fp32": value / fp32_value,
     }
+    res["config"]["launch_shape"] = c2["launch_shape"]
     if not args.headline_only:
-        res["vt_frame"] = run_c3(args, torch, N, I, ctx)
+        ctx3 = N.Context(0)
+        res["vt_frame"] = run_c3(args, torch, N, I, ctx3)
+        ctx3.close()
         c4 = run_c4(args, torch, N, I, ctx)
         res["train_texels_per_s"] = c4["samples_per_s"]
         res["train"] = c4

@@ -20,6 +20,22 @@ int fail(int code, const char* fmt, ...) {
 
 void clear_error() { g_last_error.clear(); }
 
+int resident_wgs(const ndgi_ctx* ctx, const void* kernel) {
+  auto& occ = const_cast<ndgi_ctx*>(ctx)->occupancy;
+  auto it = occ.find(kernel);
+  int per_cu;
+  if (it == occ.end()) {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, 256, 0) != hipSuccess || b < 1) b = 1;
+    occ[kernel] = b;
+    per_cu = b;
+  } else {
+    per_cu = it->second;
+  }
+  const int cap = ctx->waves_per_cu / 4 > 0 ? ctx->waves_per_cu / 4 : 1;
+  return ctx->n_cu * (per_cu < cap ? per_cu : cap);
+}
+
 int check_model(const ndgi_model* m, const char* who) {
   if (!m) return fail(NDGI_ERR_INVALID_ARG, "%s: model is NULL", who);
   if (m->W < 4 || m->H < 4 || m->W > 16384 || m->H > 16384 || (m->W & 3) || (m->H & 3))

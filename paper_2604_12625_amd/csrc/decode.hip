@@ -70,9 +70,14 @@ int launch_decode(ndgi_ctx* ctx, const ndgi_model& m, const float* uvt, int64_t 
   if (n == 0) return NDGI_OK;
   const int64_t passes = (n + 63) / 64;
   int64_t wgs = (passes + 3) / 4;
-  const int64_t cap = (int64_t)ctx->n_cu * (ctx->waves_per_cu > 4 ? ctx->waves_per_cu / 4 : 1);
-  if (wgs > cap) wgs = cap;
   const bool g16 = m.grid_dtype == NDGI_DTYPE_F16;
+  const void* kern = (prec == NDGI_PREC_F16)
+                         ? (g16 ? (const void*)k_decode_query<NDGI_PREC_F16, NDGI_DTYPE_F16>
+                                : (const void*)k_decode_query<NDGI_PREC_F16, NDGI_DTYPE_F32>)
+                         : (g16 ? (const void*)k_decode_query<NDGI_PREC_F32, NDGI_DTYPE_F16>
+                                : (const void*)k_decode_query<NDGI_PREC_F32, NDGI_DTYPE_F32>);
+  const int64_t cap = resident_wgs(ctx, kern);
+  if (wgs > cap) wgs = cap;
   if (prec == NDGI_PREC_F16 && g16)
     hipLaunchKernelGGL((k_decode_query<NDGI_PREC_F16, NDGI_DTYPE_F16>), dim3((unsigned)wgs), dim3(256), 0, s, m, uvt, n, out);
   else if (prec == NDGI_PREC_F16)
@@ -133,7 +138,38 @@ __device__ __forceinline__ void bc4_rows(uint32_t lo, uint32_t hi, int rp, uint3
   }
 }
 
-template <int GDT>
+// Global loads of one pass: this lane's BC4 block (footprint db, channel dc) and its grid
+// window items (keys k0 and k1).  Issued one pass ahead of use.
+struct TileLoads {
+  uint2 blk;
+  uint32_t g0[2], g1[2];
+};
+
+__device__ __forceinline__ void tile_issue(const ndgi_model& m, const Keys& k, int x0, int y0, int lane, int db,
+                                           int dc, TileLoads& t) {
+  t.blk = *(const uint2*)(m.bc4 + ((size_t)(y0 >> 2) * (m.W >> 2) + (x0 >> 2) + db) * 64 + 8 * dc);
+  const int gx0 = (x0 >> 2) - 1, gy0 = (y0 >> 2) - 1;
+  const size_t plane = (size_t)m.Gh * m.Gw;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const int item = it ? (lane < 8 ? lane + 64 : lane) : lane;   // items 64..71 on lanes 0..7
+    const int n = item >> 2, pr = item & 3;
+    const int ny = n / 6, nx = n - 6 * ny;
+    const int gx = min(max(gx0 + nx, 0), m.Gw - 1), gy = min(max(gy0 + ny, 0), m.Gh - 1);
+    const size_t node = (size_t)gy * m.Gw + gx;
+    const uint32_t* gp = (const uint32_t*)m.grid;
+    t.g0[it] = gp[((size_t)k.k0 * plane + node) * 4 + pr];
+    t.g1[it] = gp[((size_t)k.k1 * plane + node) * 4 + pr];
+  }
+}
+
+__device__ __forceinline__ float2 half2_bits(uint32_t w) {
+  return make_float2((float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu)),
+                     (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16)));
+}
+
+// FP16-grid tile path over one sub-tile.  Passes run row-slab by column-slab; the loads of
+// pass p+1 are in flight while pass p computes.
 __device__ __forceinline__ void tile_subtile(const Dec16& dec, const ndgi_model& m, const ndgi_page_req& rq,
                                              const Keys& k, int page, int ox, int oy, int tw, int th, void* dst,
                                              int64_t pitch, int lane, TileLds& L) {
@@ -144,50 +180,46 @@ __device__ __forceinline__ void tile_subtile(const Dec16& dec, const ndgi_model&
   // decode role: footprint db, channel dc, row pair drp
   const int db = lane >> 4, dc = (lane >> 1) & 7, drp = lane & 1;
   const uint8_t* sp8 = (const uint8_t*)L.sp;
-  const int bx = page * rq.page_x, by = page * rq.page_y;
-  for (int b = 0; b < th; ++b) {
-    for (int a = 0; a < tw; ++a) {
-      const int x0 = bx + ox + 16 * a, y0 = by + oy + 4 * b;
-      const uint2 blk = *(const uint2*)(m.bc4 + ((size_t)(y0 >> 2) * (m.W >> 2) + (x0 >> 2) + db) * 64 + 8 * dc);
-      // grid window: 18 nodes x 4 channel pairs, clamped to the grid, blended in time
-      const int gx0 = (x0 >> 2) - 1, gy0 = (y0 >> 2) - 1;
+  const int bx = page * rq.page_x + ox, by = page * rq.page_y + oy;
+  const int np = tw * th;
+  TileLoads cur;
+  tile_issue(m, k, bx, by, lane, db, dc, cur);
+  for (int p = 0; p < np; ++p) {
+    const int a = p % tw, b = p / tw;
+    // stage this pass: time-blend the grid window, decode the BC4 rows
 #pragma unroll
-      for (int it = 0; it < 2; ++it) {
-        const int item = lane + 64 * it;
-        if (item < 72) {
-          const int n = item >> 2, pr = item & 3;
-          const int ny = n / 6, nx = n - 6 * ny;
-          const int gx = min(max(gx0 + nx, 0), m.Gw - 1), gy = min(max(gy0 + ny, 0), m.Gh - 1);
-          const size_t node = (size_t)gy * m.Gw + gx;
-          const size_t plane = (size_t)m.Gh * m.Gw;
-          const float2 v0 = grid_pair<GDT>(m.grid, (size_t)k.k0 * plane + node, pr);
-          const float2 v1 = grid_pair<GDT>(m.grid, (size_t)k.k1 * plane + node, pr);
-          L.gt[item] = make_float2(fmaf(k.w1, v1.x, k.w0 * v0.x), fmaf(k.w1, v1.y, k.w0 * v0.y));
-        }
+    for (int it = 0; it < 2; ++it) {
+      if (it == 0 || lane < 8) {
+        const float2 v0 = half2_bits(cur.g0[it]), v1 = half2_bits(cur.g1[it]);
+        L.gt[it ? lane + 64 : lane] = make_float2(fmaf(k.w1, v1.x, k.w0 * v0.x), fmaf(k.w1, v1.y, k.w0 * v0.y));
       }
-      uint32_t row0, row1;
-      bc4_rows(blk.x, blk.y, drp, row0, row1);
-      L.sp[dc * 20 + (2 * drp) * 4 + db] = row0;
-      L.sp[dc * 20 + (2 * drp + 1) * 4 + db] = row1;
-      wave_sync();
-      f4v acc = dec.c3;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t sa = sp8[(2 * g) * 80 + q * 16 + j];
-        const uint32_t sb = sp8[(2 * g + 1) * 80 + q * 16 + j];
-        const uint32_t spair = sa | (sb << 16) | 0x64006400u;
-        const int cy = ((2 * q - 3) >> 3) + 1;
-        const float wy1 = (float)((2 * q - 3) & 7) * 0.125f, wy0 = 1.0f - wy1;
-        const float2 c00 = L.gt[(cy * 6 + cx) * 4 + g], c01 = L.gt[(cy * 6 + cx + 1) * 4 + g];
-        const float2 c10 = L.gt[((cy + 1) * 6 + cx) * 4 + g], c11 = L.gt[((cy + 1) * 6 + cx + 1) * 4 + g];
-        const float ga = wy0 * fmaf(wx1, c01.x, wx0 * c00.x) + wy1 * fmaf(wx1, c11.x, wx0 * c10.x);
-        const float gb = wy0 * fmaf(wx1, c01.y, wx0 * c00.y) + wy1 * fmaf(wx1, c11.y, wx0 * c10.y);
-        dec16_group(dec, texel_x(spair, ga, gb), q, acc);
-      }
-      wave_sync();
-      const int64_t di = rq.dst_offset + (int64_t)(oy + 4 * b + g) * pitch + (ox + 16 * a + j);
-      store_rgb<NDGI_PREC_F16>(dst, (size_t)di, acc, false);
     }
+    uint32_t row0, row1;
+    bc4_rows(cur.blk.x, cur.blk.y, drp, row0, row1);
+    L.sp[dc * 20 + (2 * drp) * 4 + db] = row0;
+    L.sp[dc * 20 + (2 * drp + 1) * 4 + db] = row1;
+    if (p + 1 < np) {
+      const int a1 = (p + 1) % tw, b1 = (p + 1) / tw;
+      tile_issue(m, k, bx + 16 * a1, by + 4 * b1, lane, db, dc, cur);
+    }
+    wave_sync();
+    f4v acc = dec.c3;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t sa = sp8[(2 * g) * 80 + q * 16 + j];
+      const uint32_t sb = sp8[(2 * g + 1) * 80 + q * 16 + j];
+      const uint32_t spair = sa | (sb << 16) | 0x64006400u;
+      const int cy = ((2 * q - 3) >> 3) + 1;
+      const float wy1 = (float)((2 * q - 3) & 7) * 0.125f, wy0 = 1.0f - wy1;
+      const float2 c00 = L.gt[(cy * 6 + cx) * 4 + g], c01 = L.gt[(cy * 6 + cx + 1) * 4 + g];
+      const float2 c10 = L.gt[((cy + 1) * 6 + cx) * 4 + g], c11 = L.gt[((cy + 1) * 6 + cx + 1) * 4 + g];
+      const float ga = wy0 * fmaf(wx1, c01.x, wx0 * c00.x) + wy1 * fmaf(wx1, c11.x, wx0 * c10.x);
+      const float gb = wy0 * fmaf(wx1, c01.y, wx0 * c00.y) + wy1 * fmaf(wx1, c11.y, wx0 * c10.y);
+      dec16_group(dec, texel_x(spair, ga, gb), q, acc);
+    }
+    wave_sync();
+    const int64_t di = rq.dst_offset + (int64_t)(oy + 4 * b + g) * pitch + (ox + 16 * a + j);
+    store_rgb<NDGI_PREC_F16>(dst, (size_t)di, acc, false);
   }
 }
 
@@ -215,12 +247,43 @@ __device__ __forceinline__ void page_subtile(const Dec<PREC>& dec, const ndgi_mo
   }
 }
 
-template <int PREC>
-__global__ __launch_bounds__(256, 2) void k_decode_pages(const ndgi_model* __restrict__ models, int32_t n_models,
-                                                          const ndgi_page_req* __restrict__ reqs,
-                                                          const int32_t* __restrict__ n_reqs_dev, int32_t max_reqs,
-                                                          int32_t page, void* __restrict__ dst, int64_t pitch, int tw,
-                                                          int th, uint32_t* __restrict__ flags) {
+// Maps the FP16 tile kernel serves: grid at a quarter of the texel resolution, FP16 grid
+// and decoder.
+__device__ __forceinline__ bool tile_eligible(const ndgi_model& m) {
+  return m.W == 4 * m.Gw && m.H == 4 * m.Gh && m.grid_dtype == NDGI_DTYPE_F16 && m.mlp_dtype == NDGI_DTYPE_F16;
+}
+
+// Request scan shared by the two page kernels: item `it` -> request, sub-tile, model.
+// Returns false (and flags the request once) when the request is invalid.
+struct PageItem {
+  ndgi_page_req rq;
+  int s;
+};
+
+__device__ __forceinline__ bool page_item(const ndgi_model* __restrict__ models, int32_t n_models,
+                                          const ndgi_page_req* __restrict__ reqs, int64_t it, int64_t per_req,
+                                          int page, int lane, int& cur, ndgi_model& m, PageItem& pi,
+                                          uint32_t* __restrict__ flags, bool report) {
+  const int r = (int)(it / per_req);
+  pi.s = (int)(it - (int64_t)r * per_req);
+  pi.rq = reqs[r];
+  const ndgi_page_req& rq = pi.rq;
+  bool ok = rq.model >= 0 && rq.model < n_models && rq.page_x >= 0 && rq.page_y >= 0;
+  if (ok && rq.model != cur) {
+    m = models[rq.model];
+    cur = rq.model;
+  }
+  ok = ok && (int64_t)page * (rq.page_x + 1) <= m.W && (int64_t)page * (rq.page_y + 1) <= m.H;
+  if (!ok && report && lane == 0 && pi.s == 0) atomicOr(flags, NDGI_FLAG_BAD_PAGE_REQUEST);
+  return ok;
+}
+
+// FP16 requests on tile-eligible maps (tile path).
+__global__ __launch_bounds__(256) void k_decode_tiles(const ndgi_model* __restrict__ models, int32_t n_models,
+                                                      const ndgi_page_req* __restrict__ reqs,
+                                                      const int32_t* __restrict__ n_reqs_dev, int32_t max_reqs,
+                                                      int32_t page, void* __restrict__ dst, int64_t pitch, int tw,
+                                                      int th, uint32_t* __restrict__ flags) {
   const int lane = threadIdx.x & 63;
   int n_req = *n_reqs_dev;
   n_req = n_req < 0 ? 0 : (n_req > max_reqs ? max_reqs : n_req);
@@ -231,59 +294,61 @@ __global__ __launch_bounds__(256, 2) void k_decode_pages(const ndgi_model* __res
   const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
   const int64_t wave0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
   __shared__ TileLds tlds[4];
-
-  // one decoder in registers, reloaded when the model or its form changes
-  Dec<PREC> dec;
-  int dmodel = -1, dform = -1;   // form 0: general inputs, 1: texel-centre (tile) inputs
-  int cur = -1;
+  Dec16 dec;
+  int dmodel = -1, cur = -1;
   ndgi_model m = {};
+  PageItem pi;
   for (int64_t it = wave0; it < total; it += nwaves) {
-    const int r = (int)(it / per_req);
-    const int s = (int)(it - (int64_t)r * per_req);
-    const ndgi_page_req rq = reqs[r];
-    bool ok = rq.model >= 0 && rq.model < n_models && rq.page_x >= 0 && rq.page_y >= 0;
-    if (ok && rq.model != cur) {
-      m = models[rq.model];
-      cur = rq.model;
+    if (!page_item(models, n_models, reqs, it, per_req, page, lane, cur, m, pi, flags, true)) continue;
+    if (!tile_eligible(m)) continue;                            // served by the general kernel
+    if (dmodel != pi.rq.model) {
+      load_dec16<NDGI_DTYPE_F16, true>(dec, m.mlp, lane);
+      dmodel = pi.rq.model;
     }
-    ok = ok && (int64_t)page * (rq.page_x + 1) <= m.W && (int64_t)page * (rq.page_y + 1) <= m.H;
-    if (!ok) {
-      if (lane == 0 && s == 0) atomicOr(flags, NDGI_FLAG_BAD_PAGE_REQUEST);
-      continue;
-    }
-    const Keys k = make_keys(rq.t, m.T);
-    const int ox = (s % nsx) * sub_w, oy = (s / nsx) * sub_h;   // sub-tile origin in the page
+    const Keys k = make_keys(pi.rq.t, m.T);
+    const int ox = (pi.s % nsx) * sub_w, oy = (pi.s / nsx) * sub_h;
+    tile_subtile(dec, m, pi.rq, k, page, ox, oy, tw, th, dst, pitch, lane, tlds[threadIdx.x >> 6]);
+  }
+}
+
+// General page decode (any grid ratio, either precision).  With SKIP_TILES the requests the
+// tile kernel serves are skipped.
+template <int PREC, bool SKIP_TILES>
+__global__ __launch_bounds__(256) void k_decode_pages(const ndgi_model* __restrict__ models, int32_t n_models,
+                                                      const ndgi_page_req* __restrict__ reqs,
+                                                      const int32_t* __restrict__ n_reqs_dev, int32_t max_reqs,
+                                                      int32_t page, void* __restrict__ dst, int64_t pitch, int tw,
+                                                      int th, uint32_t* __restrict__ flags) {
+  const int lane = threadIdx.x & 63;
+  int n_req = *n_reqs_dev;
+  n_req = n_req < 0 ? 0 : (n_req > max_reqs ? max_reqs : n_req);
+  const int sub_w = 16 * tw, sub_h = 4 * th;
+  const int nsx = page / sub_w, nsy = page / sub_h;
+  const int64_t per_req = (int64_t)nsx * nsy;
+  const int64_t total = (int64_t)n_req * per_req;
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const int64_t wave0 = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+  Dec<PREC> dec;
+  int dmodel = -1, cur = -1;
+  ndgi_model m = {};
+  PageItem pi;
+  for (int64_t it = wave0; it < total; it += nwaves) {
+    // the tile kernel already reported invalid requests when it runs
+    if (!page_item(models, n_models, reqs, it, per_req, page, lane, cur, m, pi, flags, !SKIP_TILES)) continue;
     const bool r4 = m.W == 4 * m.Gw && m.H == 4 * m.Gh;
-    const int form = (PREC == NDGI_PREC_F16 && r4) ? 1 : 0;
-    if (dmodel != rq.model || dform != form) {
-      if constexpr (PREC == NDGI_PREC_F16) {
-        if (form) {
-          if (m.mlp_dtype == NDGI_DTYPE_F16) load_dec16<NDGI_DTYPE_F16, true>(dec.d, m.mlp, lane);
-          else load_dec16<NDGI_DTYPE_F32, true>(dec.d, m.mlp, lane);
-        } else {
-          dec.load(m.mlp, m.mlp_dtype, lane);
-        }
-      } else {
-        dec.load(m.mlp, m.mlp_dtype, lane);
-      }
-      dmodel = rq.model;
-      dform = form;
+    if (SKIP_TILES && tile_eligible(m)) continue;
+    if (dmodel != pi.rq.model) {
+      dec.load(m.mlp, m.mlp_dtype, lane);
+      dmodel = pi.rq.model;
     }
-    if constexpr (PREC == NDGI_PREC_F16) {
-      if (form) {
-        if (m.grid_dtype == NDGI_DTYPE_F16)
-          tile_subtile<NDGI_DTYPE_F16>(dec.d, m, rq, k, page, ox, oy, tw, th, dst, pitch, lane, tlds[threadIdx.x >> 6]);
-        else
-          tile_subtile<NDGI_DTYPE_F32>(dec.d, m, rq, k, page, ox, oy, tw, th, dst, pitch, lane, tlds[threadIdx.x >> 6]);
-        continue;
-      }
-    }
+    const Keys k = make_keys(pi.rq.t, m.T);
+    const int ox = (pi.s % nsx) * sub_w, oy = (pi.s / nsx) * sub_h;
     if (m.grid_dtype == NDGI_DTYPE_F16) {
-      if (r4) page_subtile<PREC, NDGI_DTYPE_F16, true>(dec, m, rq, k, page, ox, oy, tw, th, dst, pitch, lane);
-      else page_subtile<PREC, NDGI_DTYPE_F16, false>(dec, m, rq, k, page, ox, oy, tw, th, dst, pitch, lane);
+      if (r4) page_subtile<PREC, NDGI_DTYPE_F16, true>(dec, m, pi.rq, k, page, ox, oy, tw, th, dst, pitch, lane);
+      else page_subtile<PREC, NDGI_DTYPE_F16, false>(dec, m, pi.rq, k, page, ox, oy, tw, th, dst, pitch, lane);
     } else {
-      if (r4) page_subtile<PREC, NDGI_DTYPE_F32, true>(dec, m, rq, k, page, ox, oy, tw, th, dst, pitch, lane);
-      else page_subtile<PREC, NDGI_DTYPE_F32, false>(dec, m, rq, k, page, ox, oy, tw, th, dst, pitch, lane);
+      if (r4) page_subtile<PREC, NDGI_DTYPE_F32, true>(dec, m, pi.rq, k, page, ox, oy, tw, th, dst, pitch, lane);
+      else page_subtile<PREC, NDGI_DTYPE_F32, false>(dec, m, pi.rq, k, page, ox, oy, tw, th, dst, pitch, lane);
     }
   }
 }
@@ -291,13 +356,19 @@ __global__ __launch_bounds__(256, 2) void k_decode_pages(const ndgi_model* __res
 int launch_pages(ndgi_ctx* ctx, const ndgi_model* models, int32_t n_models, const ndgi_page_req* reqs,
                  const int32_t* n_reqs, int32_t max_reqs, int32_t page, void* dst, int64_t pitch, int prec,
                  hipStream_t s) {
-  const int wgs = ctx->n_cu * ctx->waves_per_cu / 4 > 0 ? ctx->n_cu * ctx->waves_per_cu / 4 : 1;
-  if (prec == NDGI_PREC_F16)
-    hipLaunchKernelGGL(k_decode_pages<NDGI_PREC_F16>, dim3(wgs), dim3(256), 0, s, models, n_models, reqs, n_reqs,
-                       max_reqs, page, dst, pitch, ctx->tile_w, ctx->tile_h, ctx->flags_dev);
-  else
-    hipLaunchKernelGGL(k_decode_pages<NDGI_PREC_F32>, dim3(wgs), dim3(256), 0, s, models, n_models, reqs, n_reqs,
-                       max_reqs, page, dst, pitch, ctx->tile_w, ctx->tile_h, ctx->flags_dev);
+  if (prec == NDGI_PREC_F16) {
+    hipLaunchKernelGGL(k_decode_tiles, dim3(resident_wgs(ctx, (const void*)k_decode_tiles)), dim3(256), 0, s, models,
+                       n_models, reqs, n_reqs, max_reqs, page, dst, pitch, ctx->tile_w, ctx->tile_h, ctx->flags_dev);
+    hipLaunchKernelGGL((k_decode_pages<NDGI_PREC_F16, true>),
+                       dim3(resident_wgs(ctx, (const void*)k_decode_pages<NDGI_PREC_F16, true>)), dim3(256), 0, s,
+                       models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, ctx->tile_w, ctx->tile_h,
+                       ctx->flags_dev);
+  } else {
+    hipLaunchKernelGGL((k_decode_pages<NDGI_PREC_F32, false>),
+                       dim3(resident_wgs(ctx, (const void*)k_decode_pages<NDGI_PREC_F32, false>)), dim3(256), 0, s,
+                       models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, ctx->tile_w, ctx->tile_h,
+                       ctx->flags_dev);
+  }
   NDGI_HIP(hipGetLastError());
   return NDGI_OK;
 }

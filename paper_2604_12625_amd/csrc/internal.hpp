@@ -25,6 +25,11 @@ void clear_error();
 using GraphKey = std::tuple<const void*, int32_t, const void*, const void*, int32_t, int32_t,
                             void*, int64_t, int32_t, hipStream_t>;
 
+// Workgroups of 256 threads that one launch may keep resident: CUs x the kernel's
+// occupancy (so a persistent or grid-stride grid runs in one round), capped by the
+// launch shape's waves per CU.
+int resident_wgs(const ndgi_ctx* ctx, const void* kernel);
+
 // per-wave gradient partial slots reserved for the decoder weights
 constexpr int kPartialStride = 1712;   // >= NDGI_MLP_SIZE, multiple of 16
 
@@ -33,7 +38,7 @@ constexpr int kPartialStride = 1712;   // >= NDGI_MLP_SIZE, multiple of 16
 struct ndgi_ctx {
   int device = 0;
   int n_cu = 0;
-  int tile_w = 1, tile_h = 4, waves_per_cu = 16;  // page decode launch shape
+  int tile_w = 1, tile_h = 4, waves_per_cu = 32;  // page decode launch shape
   hipStream_t capture_stream = nullptr;
   uint32_t* flags_dev = nullptr;
   // training workspace
@@ -41,6 +46,7 @@ struct ndgi_ctx {
   float* partials_dev = nullptr;  // [train_waves][kPartialStride]
   double* loss_part_dev = nullptr;  // [train_waves]
   std::map<ndgi::GraphKey, hipGraphExec_t> graphs;
+  std::map<const void*, int> occupancy;   // kernel -> resident 256-thread workgroups per CU
 };
 
 namespace ndgi {

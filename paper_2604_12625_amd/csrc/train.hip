@@ -542,7 +542,9 @@ int ndgi_train_step(ndgi_ctx* c, ndgi_train_state* st, const ndgi_batch* b, int3
   if (needs_batch) {
     const int64_t groups = (b->n + 15) / 16;
     int64_t wgs = (groups + 3) / 4;
-    const int64_t cap = c->train_waves / 4;
+    // one round of resident workgroups, and no more waves than partial rows
+    int64_t cap = resident_wgs(c, (const void*)k_train<NDGI_TRAIN_LOSS_GRAD, true>);
+    if (cap > c->train_waves / 4) cap = c->train_waves / 4;
     if (wgs > cap) wgs = cap;
     const float inv3n = (float)(1.0 / (3.0 * (double)b->n));
     const bool r4 = d.W == 4 * d.Gw && d.H == 4 * d.Gh;
