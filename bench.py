@@ -92,6 +92,14 @@ def run_c2(args, torch, N, I, ctx):
         dt = torch.float16 if prec == N.PREC_F16 else torch.float32
         frame = torch.empty((W * H, 3), dtype=dt, device="cuda")
         rnd = torch.empty((N_RANDOM, 3), dtype=dt, device="cuda")
+        # the binned decode's workspace is allocated once, outside the timed region
+        ws = torch.empty(ctx.binned_workspace_bytes(dm, N_RANDOM), dtype=torch.uint8, device="cuda")
+
+        def random_leg():
+            if args.random_path == "binned":
+                ctx.decode_binned(dm, q, prec, out=rnd, workspace=ws)
+            else:
+                ctx.decode(dm, q, prec, out=rnd)
 
         def step(tf=None, tr=None):
             e = tf.start() if tf else None
@@ -99,7 +107,7 @@ def run_c2(args, torch, N, I, ctx):
             if tf:
                 tf.stop(e)
                 e = tr.start()
-            ctx.decode(dm, q, prec, out=rnd)
+            random_leg()
             if tr:
                 tr.stop(e)
 
@@ -115,9 +123,21 @@ def run_c2(args, torch, N, I, ctx):
         wall = time.perf_counter() - t0
         fm, rm = tf.ms(), tr.ms()
         out[name] = dict(steps=steps, wall_s=wall, frame_ms=sum(fm) / len(fm), random_ms=sum(rm) / len(rm))
+        # the other random-access path on the same queries, for comparison (not in the step)
+        other = "direct" if args.random_path == "binned" else "binned"
+        to = Timer(torch)
+        for _ in range(3):
+            e = to.start()
+            if other == "binned":
+                ctx.decode_binned(dm, q, prec, out=rnd, workspace=ws)
+            else:
+                ctx.decode(dm, q, prec, out=rnd)
+            to.stop(e)
+        torch.cuda.synchronize()
+        out[name][f"random_{other}_ms"] = sorted(to.ms())[1]
         log(f"C2 {name}: {1e3 * wall / steps:.3f} ms/step (frame {out[name]['frame_ms']:.3f} ms, "
             f"random {out[name]['random_ms']:.3f} ms)")
-        del frame, rnd
+        del frame, rnd, ws
     return out, (dm, q)
 
 
@@ -233,6 +253,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2", choices=["c2", "c5"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--random-path", default="binned", choices=["binned", "direct"],
+                    help="decode of the random queries: tile-binned (default) or in arrival order")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--headline-only", action="store_true", help="skip the VT and training legs")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -275,7 +297,9 @@ def main():
                     unit="GB/s", traffic=None, kernel="k_decode_pages<FP16>", bytes_per_launch=frame_bytes)
     rl_frame["frac"] = rl_frame["achieved"] / HBM_PEAK_GBS
     rl_rand = dict(bound="hbm", achieved=RANDOM_COMPULSORY_BYTES / (f16["random_ms"] * 1e-3) / 1e9,
-                   peak=HBM_PEAK_GBS, unit="GB/s", traffic=None, kernel="k_decode_query<FP16>",
+                   peak=HBM_PEAK_GBS, unit="GB/s", traffic=None,
+                   kernel=("ndgi_decode_binned (k_bin_count, k_bin_colscan, k_bin_starts, k_bin_scatter, "
+                           "k_decode_binned<FP16>)" if args.random_path == "binned" else "k_decode_query<FP16>"),
                    bytes_per_launch=RANDOM_COMPULSORY_BYTES)
     rl_rand["frac"] = rl_rand["achieved"] / HBM_PEAK_GBS
     dominant = rl_rand if f16["random_ms"] >= f16["frame_ms"] else rl_frame

@@ -134,6 +134,25 @@ int ndgi_bc4_decode_blocks(const uint8_t* blocks, int64_t n, uint8_t* out16, hip
 int ndgi_decode(ndgi_ctx* ctx, const ndgi_model* model, const float* uvt, int64_t n,
                 void* out, int32_t prec, hipStream_t stream);
 
+/* Binned random-access decode: the same result as ndgi_decode, bit for bit, for the same
+ * queries (Sec. 3.1 Eq. 3; Sec. 3.3 "random access"), reached by first counting-sorting the
+ * queries by the 32x32 (64x64 on maps above 4096x4096 texels) tile of their bilinear
+ * footprint so that each tile's BC4 blocks are decoded once into LDS and its grid window
+ * is reused from cache.  Pays off when there are on the order of a hundred queries or
+ * more per tile; for sparse queries use ndgi_decode.
+ *   uvt, out, prec, model: as for ndgi_decode; n < 2^31.
+ *   workspace: caller-owned device memory, 256-byte aligned, of at least the size that
+ *              ndgi_decode_binned_workspace reports for (model, n); its contents on entry
+ *              are ignored and on return are unspecified.  Calls that share a workspace
+ *              must be ordered on one stream.
+ * Nothing is allocated; the call is safe to capture in a HIP graph.
+ * Errors: INVALID_ARG (as ndgi_decode; workspace NULL, misaligned or too small);
+ * UNSUPPORTED (maps of more than 16384 tiles of 64x64 texels, i.e. above 8192x8192). */
+int ndgi_decode_binned_workspace(const ndgi_model* model, int64_t n, int64_t* bytes_out);
+int ndgi_decode_binned(ndgi_ctx* ctx, const ndgi_model* model, const float* uvt, int64_t n,
+                       void* out, int32_t prec, void* workspace, int64_t workspace_bytes,
+                       hipStream_t stream);
+
 /* Batched virtual-texturing page decode (Sec. 3.5; supplementary Sec. C): every valid
  * request decodes the page x page texel centres of its page of models_dev[model] at its
  * time t and writes texel (i, j) of the page to dst[dst_offset + j*dst_pitch + i]

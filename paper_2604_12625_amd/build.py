@@ -23,11 +23,18 @@ FLAGS = [
     "-fno-gpu-rdc", "-Wno-unused-command-line-argument",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]
+# Decode kernels keep MFMA accumulators in ordinary VGPRs: the activations between layers
+# are VALU work on the MFMA results, and results held in AGPRs would first need a copy
+# each.  (The training kernel keeps the default: it uses the AGPRs as extra registers.)
+PER_FILE = {
+    "decode.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+    "binned.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+}
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *PER_FILE.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

@@ -1,4 +1,5 @@
 // C ABI entry points: argument validation, context lifecycle, graph capture.
+#include <climits>
 #include <cstdio>
 #include <cstring>
 
@@ -48,6 +49,9 @@ int check_model(const ndgi_model* m, const char* who) {
     return fail(NDGI_ERR_INVALID_ARG, "%s: unknown dtype", who);
   if (m->reserved0 != 0) return fail(NDGI_ERR_INVALID_ARG, "%s: reserved0 must be 0", who);
   if (!m->bc4 || !m->grid || !m->mlp) return fail(NDGI_ERR_INVALID_ARG, "%s: NULL model buffer", who);
+  const uint64_t grid_bytes = (uint64_t)m->T * m->Gh * m->Gw * 8 * (m->grid_dtype == NDGI_DTYPE_F16 ? 2 : 4);
+  if (grid_bytes >= (1ull << 32) || (uint64_t)m->W * m->H * 4 >= (1ull << 32))
+    return fail(NDGI_ERR_UNSUPPORTED, "%s: map or grid of 4 GiB or more", who);
   return NDGI_OK;
 }
 
@@ -148,6 +152,30 @@ int ndgi_decode(ndgi_ctx* c, const ndgi_model* m, const float* uvt, int64_t n, v
   if (n == 0) return NDGI_OK;
   if (!uvt || !out) return fail(NDGI_ERR_INVALID_ARG, "decode: NULL query/output pointer");
   return launch_decode(c, *m, uvt, n, out, prec, s);
+}
+
+int ndgi_decode_binned_workspace(const ndgi_model* m, int64_t n, int64_t* bytes_out) {
+  clear_error();
+  if (!bytes_out) return fail(NDGI_ERR_INVALID_ARG, "decode_binned_workspace: bytes_out is NULL");
+  *bytes_out = 0;
+  if (n < 0 || n > INT32_MAX) return fail(NDGI_ERR_INVALID_ARG, "decode_binned_workspace: n out of [0, 2^31)");
+  int rc = check_model(m, "decode_binned_workspace");
+  if (rc) return rc;
+  return binned_workspace(*m, n, bytes_out);
+}
+
+int ndgi_decode_binned(ndgi_ctx* c, const ndgi_model* m, const float* uvt, int64_t n, void* out, int32_t prec,
+                       void* workspace, int64_t workspace_bytes, hipStream_t s) {
+  clear_error();
+  if (!c) return fail(NDGI_ERR_INVALID_ARG, "decode_binned: ctx is NULL");
+  if (n < 0 || n > INT32_MAX) return fail(NDGI_ERR_INVALID_ARG, "decode_binned: n out of [0, 2^31)");
+  if (prec != NDGI_PREC_F32 && prec != NDGI_PREC_F16)
+    return fail(NDGI_ERR_INVALID_ARG, "decode_binned: bad prec %d", prec);
+  int rc = check_model(m, "decode_binned");
+  if (rc) return rc;
+  if (n == 0) return NDGI_OK;
+  if (!uvt || !out || !workspace) return fail(NDGI_ERR_INVALID_ARG, "decode_binned: NULL query/output/workspace");
+  return launch_decode_binned(c, *m, uvt, n, out, prec, workspace, workspace_bytes, s);
 }
 
 int ndgi_decode_pages(ndgi_ctx* c, const ndgi_model* models, int32_t n_models, const ndgi_page_req* reqs,

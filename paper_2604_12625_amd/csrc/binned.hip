@@ -1,0 +1,348 @@
+// Spatially binned random-access decode.
+//
+// Random (u, v, t) queries taken in arrival order each touch their own 128-byte lines for
+// the four BC4 footprints and the eight grid nodes they read, so a direct decode moves
+// many times the bytes it uses.  Here the queries are first counting-sorted by the tile
+// of TS x TS texels that holds the upper-left texel of their bilinear footprint.  The
+// sorted queries of each tile are split into work items of at most kPiece queries; for
+// each item the workgroup decodes the tile's BC4 footprints (plus a one-footprint halo on
+// the right and bottom) into LDS once and orders the item's queries by time key, so each
+// query reads its four texels from LDS and its grid nodes from a one- or two-key window
+// that stays in cache, and writes its RGB at its original index.  The per-query
+// arithmetic is the direct decode's, so both give the same bits.
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace ndgi {
+
+constexpr int kSortWgs = 256;       // workgroups of the counting sort (1024 threads each)
+constexpr int kSortThreads = 1024;
+constexpr int kMaxBins = 16384;     // LDS histogram capacity (64 KiB)
+constexpr int kPiece = 2048;        // at most this many queries per decode work item
+constexpr int kMaxKeys = 1024;      // largest T the host accepts
+
+struct BinGeom {
+  int ts_log2;      // tile side = 1 << ts_log2 texels (5 or 6)
+  int ntx, nty;     // tiles per row / column
+};
+
+static bool bin_geom(int W, int H, BinGeom& g) {
+  for (g.ts_log2 = 5; g.ts_log2 <= 6; ++g.ts_log2) {
+    g.ntx = (W + (1 << g.ts_log2) - 1) >> g.ts_log2;
+    g.nty = (H + (1 << g.ts_log2) - 1) >> g.ts_log2;
+    if ((int64_t)g.ntx * g.nty <= kMaxBins) return true;
+  }
+  return false;
+}
+
+// Tile of a query: the one holding the clamped upper-left texel of its bilinear footprint
+// (coordinates outside the map, and NaN, clamp to an edge texel as the decode does), so
+// the footprint lies inside the tile plus one texel to the right and below.
+__device__ __forceinline__ int query_bin(float u, float v, const ndgi_model& m, const BinGeom& bg) {
+  const Axis ax = coord_axis(u, m.W), ay = coord_axis(v, m.H);
+  return (ay.i0 >> bg.ts_log2) * bg.ntx + (ax.i0 >> bg.ts_log2);
+}
+
+// counts[wg][bin] = queries of sort workgroup wg (a contiguous slice of `slice` queries)
+// that fall in bin.
+__global__ __launch_bounds__(kSortThreads) void k_bin_count(ndgi_model m, BinGeom bg, const float* __restrict__ uvt,
+                                                            int64_t n, int64_t slice, int32_t* __restrict__ counts) {
+  __shared__ int32_t hist[kMaxBins];
+  const int nbins = bg.ntx * bg.nty;
+  for (int i = threadIdx.x; i < nbins; i += kSortThreads) hist[i] = 0;
+  __syncthreads();
+  const int64_t lo = (int64_t)blockIdx.x * slice, hi = min(n, lo + slice);
+#pragma unroll 4
+  for (int64_t q = lo + threadIdx.x; q < hi; q += kSortThreads)
+    atomicAdd(&hist[query_bin(uvt[q * 3], uvt[q * 3 + 1], m, bg)], 1);
+  __syncthreads();
+  int32_t* row = counts + (int64_t)blockIdx.x * nbins;
+  for (int i = threadIdx.x; i < nbins; i += kSortThreads) row[i] = hist[i];
+}
+
+// Per bin (one thread each): exclusive prefix of counts over the sort workgroups, in
+// place, and the bin's total into start[bin].
+__global__ __launch_bounds__(256) void k_bin_colscan(int32_t* __restrict__ counts, int nbins,
+                                                     int32_t* __restrict__ start) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= nbins) return;
+  int32_t run = 0;
+  for (int w = 0; w < kSortWgs; ++w) {
+    const int32_t c = counts[(int64_t)w * nbins + b];
+    counts[(int64_t)w * nbins + b] = run;
+    run += c;
+  }
+  start[b] = run;
+}
+
+// start[0..nbins) := exclusive prefix of the bin totals, start[nbins] := n;
+// items[b] := exclusive prefix of the work items per bin (ceil(count / kPiece)),
+// items[nbins] := total.  One workgroup of 1024 threads, each over a run of bins.
+__global__ __launch_bounds__(1024) void k_bin_starts(int32_t* __restrict__ start, int32_t* __restrict__ items,
+                                                     int nbins, int32_t n) {
+  __shared__ int32_t sh[1024], shi[1024];
+  const int per = (nbins + 1023) / 1024;
+  const int lo = threadIdx.x * per, hi = min(nbins, lo + per);
+  int32_t s = 0, si = 0;
+  for (int i = lo; i < hi; ++i) {
+    s += start[i];
+    si += (start[i] + kPiece - 1) / kPiece;
+  }
+  sh[threadIdx.x] = s;
+  shi[threadIdx.x] = si;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int32_t a = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+    const int32_t b = (int)threadIdx.x >= off ? shi[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += a;
+    shi[threadIdx.x] += b;
+    __syncthreads();
+  }
+  int32_t run = sh[threadIdx.x] - s, runi = shi[threadIdx.x] - si;
+  for (int i = lo; i < hi; ++i) {
+    const int32_t c = start[i];
+    start[i] = run;
+    items[i] = runi;
+    run += c;
+    runi += (c + kPiece - 1) / kPiece;
+  }
+  if (threadIdx.x == 1023) {
+    start[nbins] = n;
+    items[nbins] = runi;
+  }
+}
+
+// Scatter: every query of sort workgroup wg goes to the next free slot of its bin; a
+// slot holds (u, v, t, original index).  The order inside a bin is unspecified; each
+// query's result does not depend on it.
+__global__ __launch_bounds__(kSortThreads) void k_bin_scatter(ndgi_model m, BinGeom bg, const float* __restrict__ uvt,
+                                                              int64_t n, int64_t slice,
+                                                              const int32_t* __restrict__ counts,
+                                                              const int32_t* __restrict__ start,
+                                                              float4* __restrict__ sorted) {
+  __shared__ int32_t pos[kMaxBins];
+  const int nbins = bg.ntx * bg.nty;
+  const int32_t* row = counts + (int64_t)blockIdx.x * nbins;
+  for (int i = threadIdx.x; i < nbins; i += kSortThreads) pos[i] = start[i] + row[i];
+  __syncthreads();
+  const int64_t lo = (int64_t)blockIdx.x * slice, hi = min(n, lo + slice);
+#pragma unroll 4
+  for (int64_t q = lo + threadIdx.x; q < hi; q += kSortThreads) {
+    const float u = uvt[q * 3], v = uvt[q * 3 + 1], t = uvt[q * 3 + 2];
+    const int p = atomicAdd(&pos[query_bin(u, v, m, bg)], 1);
+    sorted[p] = make_float4(u, v, t, __builtin_bit_cast(float, (uint32_t)q));
+  }
+}
+
+// Bytes i of a, b, c, d packed into one word, for each i: a 4 x 4 byte transpose.
+__device__ __forceinline__ void transpose4(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t o[4]) {
+  const uint32_t ab_lo = __builtin_amdgcn_perm(b, a, 0x05010400u);   // a0 b0 a1 b1
+  const uint32_t ab_hi = __builtin_amdgcn_perm(b, a, 0x07030602u);   // a2 b2 a3 b3
+  const uint32_t cd_lo = __builtin_amdgcn_perm(d, c, 0x05010400u);
+  const uint32_t cd_hi = __builtin_amdgcn_perm(d, c, 0x07030602u);
+  o[0] = __builtin_amdgcn_perm(cd_lo, ab_lo, 0x05040100u);           // a0 b0 c0 d0
+  o[1] = __builtin_amdgcn_perm(cd_lo, ab_lo, 0x07060302u);
+  o[2] = __builtin_amdgcn_perm(cd_hi, ab_hi, 0x05040100u);
+  o[3] = __builtin_amdgcn_perm(cd_hi, ab_hi, 0x07060302u);
+}
+
+// Exclusive prefix sum of a[0..len) in place by one wave (len <= 64 * 16).
+__device__ __forceinline__ void wave_exclusive_scan(int32_t* a, int len, int lane) {
+  const int per = (len + 63) >> 6;
+  const int lo = lane * per, hi = min(len, lo + per);
+  int32_t s = 0;
+  for (int i = lo; i < hi; ++i) s += a[i];
+  int32_t incl = s;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t o = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += o;
+  }
+  int32_t run = incl - s;
+  for (int i = lo; i < hi; ++i) {
+    const int32_t c = a[i];
+    a[i] = run;
+    run += c;
+  }
+}
+
+// Decode of the sorted queries.  Per work item the workgroup
+//  * decodes the tile region into LDS: R = TS + 4 texels a side (the tile plus one
+//    footprint of halo), 8 bytes per texel (channel c in byte c);
+//  * orders the item's queries by their first time key with a counting sort in LDS (perm),
+//    so that the queries of a wave read one or two keys' grid window, which stays in L1/L2;
+//  * runs the two-phase query decode over the queries in that order.
+// The FP16 decoder fits 4 waves per SIMD (the LDS of 32-texel tiles allows 4 workgroups
+// per CU); the FP32 decoder needs more registers than that leaves.
+template <int PREC, int TSL>
+constexpr int binned_waves() { return (PREC == NDGI_PREC_F16 && TSL == 5) ? 4 : 1; }
+
+template <int PREC, int GDT, int TSL>
+__global__ __launch_bounds__(256, (binned_waves<PREC, TSL>())) void k_decode_binned(ndgi_model m, BinGeom bg, const float4* __restrict__ sorted,
+                                                       const int32_t* __restrict__ start,
+                                                       const int32_t* __restrict__ items, void* __restrict__ out) {
+  constexpr int TS = 1 << TSL;
+  constexpr int R = TS + 4;
+  constexpr int FP = R / 4;                      // footprints per region side
+  constexpr int kTasks = FP * FP * 2;            // (footprint, row pair)
+  __shared__ uint2 reg[R * R];
+  __shared__ float feat_all[4 * 64 * kFeatStride];
+  __shared__ uint16_t perm[kPiece];
+  // the key histogram lives only in the item prologue, when no wave uses its feature block
+  int32_t* khist = (int32_t*)feat_all;
+  static_assert(kMaxKeys * 4 <= 4 * 64 * kFeatStride * 4, "key histogram must fit the feature blocks");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, j = lane & 15;
+  float* feat = feat_all + wave * 64 * kFeatStride;
+  Dec<PREC> dec;
+  dec.load(m.mlp, m.mlp_dtype, lane);
+  const int nbins = bg.ntx * bg.nty;
+  const int n_items = items[nbins];
+  const uint32_t bw = (uint32_t)m.W >> 2, bh = (uint32_t)m.H >> 2;
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    // bin of this item: the last b with items[b] <= it (items is non-decreasing)
+    int lo = 0, hi = nbins;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (items[mid] <= it) lo = mid;
+      else hi = mid;
+    }
+    const int b = lo;
+    const int64_t s_lo = (int64_t)start[b] + (int64_t)(it - items[b]) * kPiece;
+    const int cnt = (int)(min((int64_t)start[b + 1], s_lo + kPiece) - s_lo);
+    const int tx0 = (b % bg.ntx) << TSL, ty0 = (b / bg.ntx) << TSL;
+    __syncthreads();     // the previous item's readers of reg, perm and khist are done
+    for (int i = threadIdx.x; i < m.T; i += 256) khist[i] = 0;
+#pragma unroll 1
+    for (int task = threadIdx.x; task < kTasks; task += 256) {
+      const int rp = task & 1, f = task >> 1;
+      const int fy = f / FP, fx = f - FP * fy;
+      const uint32_t gfx = (uint32_t)(tx0 >> 2) + fx, gfy = (uint32_t)(ty0 >> 2) + fy;
+      if (gfx < bw && gfy < bh) {
+        const uint4* fp = (const uint4*)(m.bc4 + (gfy * bw + gfx) * 64u);
+        uint32_t r0[8], r1[8];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const uint4 blk = fp[h];
+          bc4_rows(blk.x, blk.y, rp, r0[2 * h], r1[2 * h]);
+          bc4_rows(blk.z, blk.w, rp, r0[2 * h + 1], r1[2 * h + 1]);
+        }
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+          const uint32_t* r = rr ? r1 : r0;
+          uint32_t lo4[4], hi4[4];
+          transpose4(r[0], r[1], r[2], r[3], lo4);
+          transpose4(r[4], r[5], r[6], r[7], hi4);
+          uint4* d = (uint4*)(reg + (4 * fy + 2 * rp + rr) * R + 4 * fx);
+          d[0] = make_uint4(lo4[0], hi4[0], lo4[1], hi4[1]);
+          d[1] = make_uint4(lo4[2], hi4[2], lo4[3], hi4[3]);
+        }
+      }
+    }
+    __syncthreads();     // khist zeroed
+    // keys are recomputed in the scatter pass rather than kept: registers hold the decoder
+#pragma unroll 1
+    for (int i = threadIdx.x; i < cnt; i += 256) atomicAdd(&khist[make_keys(sorted[s_lo + i].z, m.T).k0], 1);
+    __syncthreads();
+    if (wave == 0) wave_exclusive_scan(khist, m.T, lane);
+    __syncthreads();
+#pragma unroll 1
+    for (int i = threadIdx.x; i < cnt; i += 256)
+      perm[atomicAdd(&khist[make_keys(sorted[s_lo + i].z, m.T).k0], 1)] = (uint16_t)i;
+    __syncthreads();     // reg and perm complete
+    for (int p0 = 64 * wave; p0 < cnt; p0 += 256) {
+      const int mine = p0 + lane;
+      const float4 rec = sorted[s_lo + perm[min(mine, cnt - 1)]];
+      float sp[8], gr[8];
+      spatial8_lds(reg, R, tx0, ty0, coord_axis(rec.x, m.W), coord_axis(rec.y, m.H), sp);
+      query_grid8<GDT>(m, rec.x, rec.y, rec.z, gr);
+      wave_sync();
+      store_feats(feat, lane, sp, gr);
+      wave_sync();
+      const f4v acc = decode_feats<PREC>(dec, feat, g, j);
+      if (mine < cnt)
+        store_rgb<PREC>(out, (size_t)__builtin_bit_cast(uint32_t, rec.w), acc,
+                        !(isfinite(rec.x) && isfinite(rec.y) && isfinite(rec.z)));
+    }
+  }
+}
+
+struct BinnedLayout {
+  BinGeom bg;
+  int nbins;
+  int64_t counts_off, start_off, items_off, sorted_off, bytes;
+};
+
+static int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
+
+static bool binned_layout(const ndgi_model& m, int64_t n, BinnedLayout& L) {
+  if (!bin_geom(m.W, m.H, L.bg)) return false;
+  L.nbins = L.bg.ntx * L.bg.nty;
+  L.counts_off = 0;
+  L.start_off = align256((int64_t)kSortWgs * L.nbins * 4);
+  L.items_off = L.start_off + align256((int64_t)(L.nbins + 1) * 4);
+  L.sorted_off = L.items_off + align256((int64_t)(L.nbins + 1) * 4);
+  L.bytes = L.sorted_off + n * 16;
+  return true;
+}
+
+int binned_workspace(const ndgi_model& m, int64_t n, int64_t* bytes) {
+  BinnedLayout L;
+  if (!binned_layout(m, n, L))
+    return fail(NDGI_ERR_UNSUPPORTED, "decode_binned: maps above %d tiles of 64x64 texels are not binned",
+                kMaxBins);
+  *bytes = L.bytes;
+  return NDGI_OK;
+}
+
+int launch_decode_binned(ndgi_ctx* ctx, const ndgi_model& m, const float* uvt, int64_t n, void* out, int prec,
+                         void* ws, int64_t ws_bytes, hipStream_t s) {
+  BinnedLayout L;
+  if (!binned_layout(m, n, L))
+    return fail(NDGI_ERR_UNSUPPORTED, "decode_binned: maps above %d tiles of 64x64 texels are not binned",
+                kMaxBins);
+  if (ws_bytes < L.bytes)
+    return fail(NDGI_ERR_INVALID_ARG, "decode_binned: workspace of %lld bytes, %lld needed", (long long)ws_bytes,
+                (long long)L.bytes);
+  if ((uintptr_t)ws % 256) return fail(NDGI_ERR_INVALID_ARG, "decode_binned: workspace not 256-byte aligned");
+  int32_t* counts = (int32_t*)((char*)ws + L.counts_off);
+  int32_t* start = (int32_t*)((char*)ws + L.start_off);
+  int32_t* items = (int32_t*)((char*)ws + L.items_off);
+  float4* sorted = (float4*)((char*)ws + L.sorted_off);
+  const int64_t slice = (n + kSortWgs - 1) / kSortWgs;
+  hipLaunchKernelGGL(k_bin_count, dim3(kSortWgs), dim3(kSortThreads), 0, s, m, L.bg, uvt, n, slice, counts);
+  hipLaunchKernelGGL(k_bin_colscan, dim3((L.nbins + 255) / 256), dim3(256), 0, s, counts, L.nbins, start);
+  hipLaunchKernelGGL(k_bin_starts, dim3(1), dim3(1024), 0, s, start, items, L.nbins, (int32_t)n);
+  hipLaunchKernelGGL(k_bin_scatter, dim3(kSortWgs), dim3(kSortThreads), 0, s, m, L.bg, uvt, n, slice, counts, start,
+                     sorted);
+  NDGI_HIP(hipGetLastError());
+  const bool g16 = m.grid_dtype == NDGI_DTYPE_F16;
+  // at most one item per kPiece queries plus one per bin
+  const int64_t max_items = n / kPiece + L.nbins;
+#define NDGI_BINNED(P, G, TSL)                                                                                     \
+  do {                                                                                                             \
+    int64_t wgs = resident_wgs(ctx, (const void*)k_decode_binned<P, G, TSL>);                                      \
+    if (wgs > max_items) wgs = max_items;                                                                          \
+    hipLaunchKernelGGL((k_decode_binned<P, G, TSL>), dim3((unsigned)wgs), dim3(256), 0, s, m, L.bg, sorted, start, \
+                       items, out);                                                                                \
+  } while (0)
+#define NDGI_BINNED_TS(P, G)                     \
+  do {                                           \
+    if (L.bg.ts_log2 == 5) NDGI_BINNED(P, G, 5); \
+    else NDGI_BINNED(P, G, 6);                   \
+  } while (0)
+  if (prec == NDGI_PREC_F16) {
+    if (g16) NDGI_BINNED_TS(NDGI_PREC_F16, NDGI_DTYPE_F16);
+    else NDGI_BINNED_TS(NDGI_PREC_F16, NDGI_DTYPE_F32);
+  } else {
+    if (g16) NDGI_BINNED_TS(NDGI_PREC_F32, NDGI_DTYPE_F16);
+    else NDGI_BINNED_TS(NDGI_PREC_F32, NDGI_DTYPE_F32);
+  }
+#undef NDGI_BINNED_TS
+#undef NDGI_BINNED
+  NDGI_HIP(hipGetLastError());
+  return NDGI_OK;
+}
+
+}  // namespace ndgi

@@ -30,38 +30,36 @@ int launch_bc4_blocks(const uint8_t* blocks, int64_t n, uint8_t* out, hipStream_
 }
 
 // ------------------------------------------------------------------- query decode
-// Each wave takes passes of 64 consecutive queries; 4 waves per workgroup; grid-stride.
+// Each wave takes passes of 64 consecutive queries (phase A: one query per lane into the
+// wave's LDS block; phase B: the decoder); 4 waves per workgroup; grid-stride.
 template <int PREC, int GDT>
 __global__ __launch_bounds__(256) void k_decode_query(ndgi_model m, const float* __restrict__ uvt, int64_t n,
                                                        void* __restrict__ out) {
+  __shared__ float feat_all[4 * 64 * kFeatStride];
   const int lane = threadIdx.x & 63;
   const int g = lane >> 4, j = lane & 15;
+  float* feat = feat_all + (threadIdx.x >> 6) * 64 * kFeatStride;
   Dec<PREC> dec;
   dec.load(m.mlp, m.mlp_dtype, lane);
   const int64_t passes = (n + 63) >> 6;
   const int64_t wave0 = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * 4;
   for (int64_t p = wave0; p < passes; p += nwaves) {
-    f4v acc = dec.bias3();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t idx = (p << 6) + 16 * q + j;
-      float u = 0.5f, v = 0.5f, t = 0.0f;
-      if (idx < n) {
-        u = uvt[idx * 3 + 0];
-        v = uvt[idx * 3 + 1];
-        t = uvt[idx * 3 + 2];
-      }
-      float f[4];
-      query_inputs<GDT>(m, u, v, t, g, f);
-      dec.group(f, q, acc);
-    }
     const int64_t mine = (p << 6) + lane;
+    float u = 0.5f, v = 0.5f, t = 0.0f;
     if (mine < n) {
-      const float u = uvt[mine * 3 + 0], v = uvt[mine * 3 + 1], t = uvt[mine * 3 + 2];
-      const bool bad = !(isfinite(u) && isfinite(v) && isfinite(t));
-      store_rgb<PREC>(out, (size_t)mine, acc, bad);
+      u = uvt[mine * 3 + 0];
+      v = uvt[mine * 3 + 1];
+      t = uvt[mine * 3 + 2];
     }
+    float sp[8], gr[8];
+    spatial8_global(m, coord_axis(u, m.W), coord_axis(v, m.H), sp);
+    query_grid8<GDT>(m, u, v, t, gr);
+    wave_sync();                      // the previous pass's phase B reads are done
+    store_feats(feat, lane, sp, gr);
+    wave_sync();
+    const f4v acc = decode_feats<PREC>(dec, feat, g, j);
+    if (mine < n) store_rgb<PREC>(out, (size_t)mine, acc, !(isfinite(u) && isfinite(v) && isfinite(t)));
   }
 }
 
@@ -106,37 +104,6 @@ struct TileLds {
                          // keeps the four lane groups of a read on distinct banks
   float2 gt[18 * 4];     // [node row 0..2][node column 0..5][channel pair], time-blended
 };
-
-// Rows 2rp and 2rp+1 of a BC4 block (lo = bytes 0..3, hi = bytes 4..7) as 4 bytes each.
-// The 8-entry palette is built once: the interior entries are 1024 + e0 + 0.5 + j*(e1-e0)/D
-// rounded toward zero to FP16 (integers are exact in [1024, 2048)), which equals the
-// palette's round-to-nearest value since the exact quotient is never within 0.5/D of an
-// integer.  The row's four 3-bit selectors are spread into a byte selector and one
-// v_perm_b32 picks four texels from the palette.
-__device__ __forceinline__ void bc4_rows(uint32_t lo, uint32_t hi, int rp, uint32_t& r0, uint32_t& r1) {
-  const uint32_t ie0 = lo & 0xffu, ie1 = (lo >> 8) & 0xffu;
-  const bool eight = ie0 > ie1;
-  const float e0 = (float)ie0, e1 = (float)ie1;
-  const float B = (e1 - e0) * (eight ? (1.0f / 7.0f) : 0.2f);
-  const float A = e0 + 1024.5f;
-  const uint32_t p12 = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(fmaf(1.0f, B, A), fmaf(2.0f, B, A)));
-  const uint32_t p34 = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(fmaf(3.0f, B, A), fmaf(4.0f, B, A)));
-  const uint32_t p56 = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(fmaf(5.0f, B, A), fmaf(6.0f, B, A)));
-  // palette bytes: [e0, e1, p1, p2 | p3, p4, p5, p6] or, in 6-value mode, [.. | p3, p4, 0, 255]
-  const uint32_t pal_lo = __builtin_amdgcn_perm(p12, lo, 0x06040100u);
-  const uint32_t pal_hi = __builtin_amdgcn_perm(p56, p34, eight ? 0x06040200u : 0x0D0C0200u);
-  const uint64_t bits = (((uint64_t)hi << 32) | lo) >> (16 + 24 * rp);
-  const uint32_t c24 = (uint32_t)bits;
-#pragma unroll
-  for (int rr = 0; rr < 2; ++rr) {
-    const uint32_t c = (c24 >> (12 * rr)) & 0xfffu;    // four 3-bit selectors
-    uint32_t t = (c | (c << 10)) & 0x003f003fu;
-    t = (t | (t << 5)) & 0x07070707u;                  // one selector per byte
-    const uint32_t v = __builtin_amdgcn_perm(pal_hi, pal_lo, t);
-    if (rr == 0) r0 = v;
-    else r1 = v;
-  }
-}
 
 // Global loads of one pass: this lane's BC4 block (footprint db, channel dc) and its grid
 // window items (keys k0 and k1).  Issued one pass ahead of use.

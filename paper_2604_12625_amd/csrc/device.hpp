@@ -69,6 +69,53 @@ __device__ __forceinline__ uint32_t bc4_texel(uint32_t lo, uint32_t hi, uint32_t
   return v;
 }
 
+// Same value as bc4_texel, as a float, with no integer division: for selector c the
+// palette entry is floor(e0 + 0.5 + j (e1 - e0) / D) with D = 7 (e0 > e1) or 5, and
+// j = 0 for c = 0, D for c = 1, c - 1 otherwise (the exact quotient is never within 0.5/D
+// of an integer, so the rounded FMA floors correctly); in 6-value mode c = 6, 7 give 0, 255.
+__device__ __forceinline__ float bc4_texel_f(uint32_t lo, uint32_t hi, uint32_t slot) {
+  const float e0 = (float)(lo & 0xffu), e1 = (float)((lo >> 8) & 0xffu);
+  const bool eight = e0 > e1;
+  const float B = (e1 - e0) * (eight ? (1.0f / 7.0f) : 0.2f);
+  const uint32_t code = (uint32_t)((((uint64_t)hi << 32) | lo) >> (16u + 3u * slot)) & 7u;
+  const uint32_t lut = eight ? 0x65432170u : 0x00432150u;
+  const float jf = (float)((lut >> (4u * code)) & 15u);
+  float v = floorf(fmaf(jf, B, e0 + 0.5f));
+  if (!eight && code >= 6u) v = (code == 7u) ? 255.0f : 0.0f;
+  return v;
+}
+
+// Rows 2rp and 2rp+1 of a BC4 block (lo = bytes 0..3, hi = bytes 4..7) as 4 bytes each.
+// The 8-entry palette is built once: the interior entries are 1024 + e0 + 0.5 + j*(e1-e0)/D
+// rounded toward zero to FP16 (integers are exact in [1024, 2048)), which equals the
+// palette's round-to-nearest value since the exact quotient is never within 0.5/D of an
+// integer.  The row's four 3-bit selectors are spread into a byte selector and one
+// v_perm_b32 picks four texels from the palette.
+__device__ __forceinline__ void bc4_rows(uint32_t lo, uint32_t hi, int rp, uint32_t& r0, uint32_t& r1) {
+  const uint32_t ie0 = lo & 0xffu, ie1 = (lo >> 8) & 0xffu;
+  const bool eight = ie0 > ie1;
+  const float e0 = (float)ie0, e1 = (float)ie1;
+  const float B = (e1 - e0) * (eight ? (1.0f / 7.0f) : 0.2f);
+  const float A = e0 + 1024.5f;
+  const uint32_t p12 = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(fmaf(1.0f, B, A), fmaf(2.0f, B, A)));
+  const uint32_t p34 = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(fmaf(3.0f, B, A), fmaf(4.0f, B, A)));
+  const uint32_t p56 = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(fmaf(5.0f, B, A), fmaf(6.0f, B, A)));
+  // palette bytes: [e0, e1, p1, p2 | p3, p4, p5, p6] or, in 6-value mode, [.. | p3, p4, 0, 255]
+  const uint32_t pal_lo = __builtin_amdgcn_perm(p12, lo, 0x06040100u);
+  const uint32_t pal_hi = __builtin_amdgcn_perm(p56, p34, eight ? 0x06040200u : 0x0D0C0200u);
+  const uint64_t bits = (((uint64_t)hi << 32) | lo) >> (16 + 24 * rp);
+  const uint32_t c24 = (uint32_t)bits;
+#pragma unroll
+  for (int rr = 0; rr < 2; ++rr) {
+    const uint32_t c = (c24 >> (12 * rr)) & 0xfffu;    // four 3-bit selectors
+    uint32_t t = (c | (c << 10)) & 0x003f003fu;
+    t = (t | (t << 5)) & 0x07070707u;                  // one selector per byte
+    const uint32_t v = __builtin_amdgcn_perm(pal_hi, pal_lo, t);
+    if (rr == 0) r0 = v;
+    else r1 = v;
+  }
+}
+
 // ------------------------------------------------------------------ sampling helpers
 struct Axis { int i0, i1; float w0, w1; };
 
@@ -196,31 +243,122 @@ __device__ __forceinline__ uint2 spatial_pair(const ndgi_model& m, int x, int y,
   return make_uint2(bc4_texel(b.x, b.y, slot), bc4_texel(b.z, b.w, slot));
 }
 
-// Lane inputs for an explicit query (u, v, t).
+// ------------------------------------------------------- explicit-query features
+// The decode of explicit (u, v, t) queries runs in two phases per wave pass of 64
+// queries.  Phase A: lane l computes all 16 decoder inputs of query l in FP32 (x[0..7]
+// spatial, x[8..15] grid) and writes them to a wave-private LDS block.  Phase B: the MFMA
+// decoder reads them back in its operand layout (lane (g, j) of group q takes inputs
+// 2g, 2g+1 and 8+2g, 8+2g+1 of query 16q + j).  Address and weight arithmetic is thus done
+// once per query instead of once per lane group.  Every explicit-query decode uses these
+// helpers, with the bilinear taps summed in the order (y0,x0), (y0,x1), (y1,x0), (y1,x1)
+// and the keys k0 then k1, so that they agree bit for bit.
+
+constexpr int kFeatStride = 20;   // floats per query row of the LDS block (80 B: 16-B aligned)
+
+// Bilinear weights of the four taps, in summation order.
+__device__ __forceinline__ void tap_weights(const Axis& ax, const Axis& ay, float w[4]) {
+  w[0] = ay.w0 * ax.w0;
+  w[1] = ay.w0 * ax.w1;
+  w[2] = ay.w1 * ax.w0;
+  w[3] = ay.w1 * ax.w1;
+}
+
+// Eight grid channels of query (u, v, t): bilinear on the node axes, linear in time.
+// Offsets are 32-bit (the host limits grids to 4 GiB).
 template <int GDT>
-__device__ __forceinline__ void query_inputs(const ndgi_model& m, float u, float v, float t, int g, float f[4]) {
-  const Axis ax = coord_axis(u, m.W);
-  const Axis ay = coord_axis(v, m.H);
-  float s0 = 0.0f, s1 = 0.0f;
+__device__ __forceinline__ void query_grid8(const ndgi_model& m, float u, float v, float t, float x[8]) {
+  const Keys k = make_keys(t, m.T);
+  const Axis gx = coord_axis(u, m.Gw), gy = coord_axis(v, m.Gh);
+  float w[4];
+  tap_weights(gx, gy, w);
+  const uint32_t plane = (uint32_t)m.Gh * (uint32_t)m.Gw;
+  const uint32_t n00 = (uint32_t)gy.i0 * (uint32_t)m.Gw + (uint32_t)gx.i0;
+  const uint32_t dx = (uint32_t)(gx.i1 - gx.i0), dy = (uint32_t)(gy.i1 - gy.i0) * (uint32_t)m.Gw;
+  const uint32_t tap[4] = {n00, n00 + dx, n00 + dy, n00 + dy + dx};
 #pragma unroll
-  for (int yy = 0; yy < 2; ++yy) {
-    const int y = yy ? ay.i1 : ay.i0;
-    const float wy = yy ? ay.w1 : ay.w0;
+  for (int c = 0; c < 8; ++c) x[c] = 0.0f;
 #pragma unroll
-    for (int xx = 0; xx < 2; ++xx) {
-      const int x = xx ? ax.i1 : ax.i0;
-      const float w = wy * (xx ? ax.w1 : ax.w0);
-      const uint2 s = spatial_pair(m, x, y, g);
-      s0 = fmaf(w, (float)s.x, s0);
-      s1 = fmaf(w, (float)s.y, s1);
+  for (int tk = 0; tk < 2; ++tk) {
+    const uint32_t kb = (uint32_t)(tk ? k.k1 : k.k0) * plane;
+    const float wt = tk ? k.w1 : k.w0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float wi = wt * w[i];
+      const uint32_t node = kb + tap[i];
+      if constexpr (GDT == NDGI_DTYPE_F16) {
+        const uint4 r = *(const uint4*)((const uint8_t*)m.grid + node * 16u);
+        const uint32_t wd[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          x[2 * c] = fmaf(wi, (float)__builtin_bit_cast(_Float16, (uint16_t)(wd[c] & 0xffffu)), x[2 * c]);
+          x[2 * c + 1] = fmaf(wi, (float)__builtin_bit_cast(_Float16, (uint16_t)(wd[c] >> 16)), x[2 * c + 1]);
+        }
+      } else {
+        const float4 a = *(const float4*)((const uint8_t*)m.grid + node * 32u);
+        const float4 b = *(const float4*)((const uint8_t*)m.grid + node * 32u + 16u);
+        const float vv[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int c = 0; c < 8; ++c) x[c] = fmaf(wi, vv[c], x[c]);
+      }
     }
   }
-  const Keys k = make_keys(t, m.T);
-  const float2 gv = grid_sample<GDT>(m, coord_axis(u, m.Gw), coord_axis(v, m.Gh), k, g);
-  f[0] = s0 * (1.0f / 255.0f);
-  f[1] = s1 * (1.0f / 255.0f);
-  f[2] = gv.x;
-  f[3] = gv.y;
+}
+
+// Eight spatial channels of a query, the four texels decoded straight from their BC4
+// blocks (64 B per footprint: channel c in bytes 8c..8c+7).
+__device__ __forceinline__ void spatial8_global(const ndgi_model& m, const Axis& ax, const Axis& ay, float x[8]) {
+  float w[4];
+  tap_weights(ax, ay, w);
+  const uint32_t bw = (uint32_t)m.W >> 2;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) x[c] = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t y = (uint32_t)((i & 2) ? ay.i1 : ay.i0), xx = (uint32_t)((i & 1) ? ax.i1 : ax.i0);
+    const uint8_t* fp = m.bc4 + ((y >> 2) * bw + (xx >> 2)) * 64u;
+    const uint32_t slot = 4u * (y & 3u) + (xx & 3u);
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const uint4 b = *(const uint4*)(fp + 16 * h);
+      x[2 * h] = fmaf(w[i], bc4_texel_f(b.x, b.y, slot), x[2 * h]);
+      x[2 * h + 1] = fmaf(w[i], bc4_texel_f(b.z, b.w, slot), x[2 * h + 1]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) x[c] *= (1.0f / 255.0f);
+}
+
+// Eight spatial channels of a query from a decoded region in LDS: R x R texels from
+// (tx0, ty0), 8 bytes per texel (channel c in byte c), row-major.
+__device__ __forceinline__ void spatial8_lds(const uint2* reg, int R, int tx0, int ty0, const Axis& ax,
+                                             const Axis& ay, float x[8]) {
+  float w[4];
+  tap_weights(ax, ay, w);
+  const int o00 = (ay.i0 - ty0) * R + (ax.i0 - tx0);
+  const int dx = ax.i1 - ax.i0, dy = (ay.i1 - ay.i0) * R;
+  const int tap[4] = {o00, o00 + dx, o00 + dy, o00 + dy + dx};
+#pragma unroll
+  for (int c = 0; c < 8; ++c) x[c] = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint2 p = reg[tap[i]];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      x[c] = fmaf(w[i], (float)((p.x >> (8 * c)) & 0xffu), x[c]);
+      x[4 + c] = fmaf(w[i], (float)((p.y >> (8 * c)) & 0xffu), x[4 + c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) x[c] *= (1.0f / 255.0f);
+}
+
+// Phase A store: this lane's 16 inputs into its row of the wave's block.
+__device__ __forceinline__ void store_feats(float* feat, int lane, const float s[8], const float gr[8]) {
+  float4* r = (float4*)(feat + lane * kFeatStride);
+  r[0] = make_float4(s[0], s[1], s[2], s[3]);
+  r[1] = make_float4(s[4], s[5], s[6], s[7]);
+  r[2] = make_float4(gr[0], gr[1], gr[2], gr[3]);
+  r[3] = make_float4(gr[4], gr[5], gr[6], gr[7]);
 }
 
 // Lane inputs at the centre of texel (x, y) (page / frame decode): the spatial sample is
@@ -470,6 +608,22 @@ template <> struct Dec<NDGI_PREC_F32> {
   __device__ __forceinline__ void group(const float f[4], int q, f4v& acc) const { dec32_group(d, f, q, acc); }
   __device__ __forceinline__ f4v bias3() const { return d.c3; }
 };
+
+// Phase B: the decoder over the 64 queries of a wave's feature block; lane l ends with
+// the output-layer values of query l.
+template <int PREC>
+__device__ __forceinline__ f4v decode_feats(const Dec<PREC>& dec, const float* feat, int g, int j) {
+  f4v acc = dec.bias3();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float* r = feat + (16 * q + j) * kFeatStride;
+    const float2 sp = *(const float2*)(r + 2 * g);
+    const float2 gr = *(const float2*)(r + 8 + 2 * g);
+    const float f[4] = {sp.x, sp.y, gr.x, gr.y};
+    dec.group(f, q, acc);
+  }
+  return acc;
+}
 
 // Store the RGB of one texel: exp of the output layer, FP16 (rounded once) or FP32.
 template <int PREC>

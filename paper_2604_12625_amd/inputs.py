@@ -243,6 +243,27 @@ def uniform_queries_torch(n: int, seed: int, device="cuda"):
     return torch.rand((n, 3), generator=gen, device=device, dtype=torch.float32)
 
 
+def train_init_torch(W: int, H: int, Gw: int, Gh: int, T: int, mean_rgb, seed: int,
+                     device="cuda") -> dict:
+    """Same distributions as :func:`train_init`, drawn with torch on ``device`` as one flat
+    float32 tensor in the trainer's layout (for sizes where host generation and upload would
+    dominate).  The decoder is drawn on the host by :func:`he_normal_mlp`."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    f32 = dict(dtype=torch.float32, device=device)
+    nb = (H // 4) * (W // 4) * N_CH
+    ep = torch.empty((nb, 2), **f32)
+    ep[:, 0].uniform_(0.0, 0.5, generator=gen)
+    ep[:, 1].uniform_(0.5, 1.0, generator=gen)
+    w = torch.empty(H * W * N_CH, **f32).uniform_(0.0, 1.0, generator=gen)
+    grid = torch.empty(T * Gh * Gw * N_CH, **f32).normal_(0.0, 0.1, generator=gen)
+    mlp = he_normal_mlp(np.float32, rng(seed, P_INIT))
+    mlp[MLP_SIZE - 3:] = np.log(np.maximum(np.asarray(mean_rgb, dtype=np.float64), 1e-6)).astype(np.float32)
+    flat = torch.cat([ep.reshape(-1), w, grid, torch.from_numpy(mlp).to(device)])
+    return dict(dims=dict(W=W, H=H, Gw=Gw, Gh=Gh, T=T), flat=flat)
+
+
 def train_samples_torch(B: int, W: int, H: int, T: int, seed: int, device="cuda"):
     """Packed samples (x | y << 12 | k << 24) drawn uniformly with replacement, on device."""
     import torch

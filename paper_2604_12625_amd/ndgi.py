@@ -24,7 +24,7 @@ EXPORTED = (
     "ndgi_create", "ndgi_destroy", "ndgi_last_error", "ndgi_get_error_flags",
     "ndgi_bc4_decode_blocks", "ndgi_decode", "ndgi_decode_pages", "ndgi_decode_pages_graph",
     "ndgi_set_launch", "ndgi_train_param_count", "ndgi_train_step", "ndgi_export",
-    "ndgi_tile_stats",
+    "ndgi_tile_stats", "ndgi_decode_binned_workspace", "ndgi_decode_binned",
 )
 
 
@@ -83,12 +83,13 @@ def lib():
         L.ndgi_decode_pages.argtypes = pages
         L.ndgi_decode_pages_graph.argtypes = pages
         L.ndgi_set_launch.argtypes = [vp, i32, i32, i32]
-        if hasattr(L, "ndgi_train_step"):
-            L.ndgi_train_param_count.argtypes = [i32, i32, i32, i32, i32]
-            L.ndgi_train_param_count.restype = i64
-            L.ndgi_train_step.argtypes = [vp, C.POINTER(NdgiTrainState), C.POINTER(NdgiBatch), i32, vp, vp]
-            L.ndgi_export.argtypes = [vp, C.POINTER(NdgiTrainState), vp, vp, i32, vp, i32, vp]
-            L.ndgi_tile_stats.argtypes = [vp, vp, i32, vp, i32, i32, i32, vp, vp]
+        L.ndgi_train_param_count.argtypes = [i32, i32, i32, i32, i32]
+        L.ndgi_train_param_count.restype = i64
+        L.ndgi_train_step.argtypes = [vp, C.POINTER(NdgiTrainState), C.POINTER(NdgiBatch), i32, vp, vp]
+        L.ndgi_export.argtypes = [vp, C.POINTER(NdgiTrainState), vp, vp, i32, vp, i32, vp]
+        L.ndgi_tile_stats.argtypes = [vp, vp, i32, vp, i32, i32, i32, vp, vp]
+        L.ndgi_decode_binned_workspace.argtypes = [C.POINTER(NdgiModel), i64, C.POINTER(i64)]
+        L.ndgi_decode_binned.argtypes = [vp, C.POINTER(NdgiModel), vp, i64, vp, i32, vp, i64, vp]
         _lib = L
     return _lib
 
@@ -163,6 +164,29 @@ class Context:
         check(lib().ndgi_decode(self.h, C.byref(model.desc), _ptr(uvt), n, _ptr(out), prec,
                                 _stream(stream)), "ndgi_decode")
         return out
+
+    def binned_workspace_bytes(self, model: DeviceModel, n: int) -> int:
+        b = C.c_int64(0)
+        check(lib().ndgi_decode_binned_workspace(C.byref(model.desc), n, C.byref(b)),
+              "ndgi_decode_binned_workspace")
+        return b.value
+
+    def decode_binned(self, model: DeviceModel, uvt, prec=PREC_F16, out=None, workspace=None,
+                      stream=None):
+        """Binned decode; `workspace` is a uint8 device tensor reused across calls
+        (allocated here when None or too small, returned with the output)."""
+        import torch
+        n = uvt.shape[0]
+        if out is None:
+            out = torch.empty((n, 3), dtype=torch.float16 if prec == PREC_F16 else torch.float32,
+                              device=uvt.device)
+        need = self.binned_workspace_bytes(model, n)
+        if workspace is None or workspace.numel() < need:
+            workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=uvt.device)
+        check(lib().ndgi_decode_binned(self.h, C.byref(model.desc), _ptr(uvt), n, _ptr(out), prec,
+                                       _ptr(workspace), workspace.numel(), _stream(stream)),
+              "ndgi_decode_binned")
+        return out, workspace
 
     def decode_pages(self, models_dev, n_models, reqs_dev, n_reqs_dev, max_reqs, page, dst,
                      pitch, prec=PREC_F16, graph=False, stream=None):

@@ -21,10 +21,14 @@ class Trainer:
         self.W, self.H, self.Gw, self.Gh, self.T = d["W"], d["H"], d["Gw"], d["Gh"], d["T"]
         n = N.lib().ndgi_train_param_count(self.W, self.H, self.Gw, self.Gh, self.T)
         self.n_params = n
-        flat = np.concatenate([np.asarray(init[k], dtype=np.float32).ravel()
-                               for k in ("endpoints", "weights", "grid", "mlp")])
-        assert flat.size == n, (flat.size, n)
-        self.params = torch.from_numpy(flat).to(device)
+        if "flat" in init:     # device tensor already in the flat layout
+            assert init["flat"].numel() == n and init["flat"].dtype == torch.float32
+            self.params = init["flat"].to(device).contiguous()
+        else:
+            flat = np.concatenate([np.asarray(init[k], dtype=np.float32).ravel()
+                                   for k in ("endpoints", "weights", "grid", "mlp")])
+            assert flat.size == n, (flat.size, n)
+            self.params = torch.from_numpy(flat).to(device)
         self.grads = torch.zeros(n, dtype=torch.float32, device=device)
         self.m = torch.zeros(n, dtype=torch.float32, device=device)
         self.v = torch.zeros(n, dtype=torch.float32, device=device)

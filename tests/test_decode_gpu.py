@@ -112,6 +112,89 @@ def test_decode_argument_errors(N, ctx):
     assert rc == N.ERR_INVALID_ARG
 
 
+# --------------------------------------------------------------------------- binned
+def _dec_binned(N, ctx, model, q, prec, ws=None):
+    import torch
+    dm = N.DeviceModel.from_numpy(model)
+    out, ws = ctx.decode_binned(dm, torch.from_numpy(q).cuda(), prec, workspace=ws)
+    torch.cuda.synchronize()
+    return out.float().cpu().numpy(), ws
+
+
+EDGE_Q = np.array([[-0.5, 0.5, 0.2], [1.7, 0.5, 0.2], [0.5, -3.0, 0.2], [0.5, 9.0, 0.2],
+                   [0.0, 0.0, 0.0], [0.999999, 0.999999, 0.999999], [0.3, 0.4, -0.25],
+                   [1.0, 1.0, 0.5], [0.3, 0.4, 7.75], [0.25, 0.75, 0.999]], dtype=np.float32)
+BAD_Q = np.array([[np.nan, 0.5, 0.2], [0.5, np.inf, 0.2], [0.5, 0.5, -np.inf],
+                  [-np.inf, np.nan, 0.1], [np.inf, np.inf, 0.3]], dtype=np.float32)
+
+
+@pytest.mark.parametrize("prec,tol", [(1, TOL16), (0, TOL32)])
+@pytest.mark.parametrize("grid_dt", [np.float16, np.float32])
+def test_binned_equals_direct_and_oracle(N, ctx, prec, tol, grid_dt):
+    """Several 32x32 tiles with a ragged edge (200 x 148 texels), all texel centres at one
+    time, random queries, out-of-range and non-finite queries: the binned decode gives
+    the direct decode's bits and the oracle's values."""
+    m = I.random_model(200, 148, 50, 37, 12, grid_dt, np.float16, config=54)
+    q = np.concatenate([I.texel_centre_queries(200, 148, [0.37]),
+                        I.uniform_queries(50001, I.rng(54, I.P_QUERY)), EDGE_Q, BAD_Q])
+    direct = _dec(N, ctx, m, q, prec)
+    binned, _ = _dec_binned(N, ctx, m, q, prec)
+    np.testing.assert_array_equal(binned, direct)
+    ok = np.isfinite(q).all(axis=1)
+    assert np.isnan(binned[~ok]).all()
+    assert_rel(binned[ok], O.decode(m, q[ok]), tol, f"binned prec {prec}")
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 65, 1023, 1025, 4097])
+def test_binned_ragged_counts_reuse_workspace(N, ctx, n):
+    """Counts around the wave (64) and chunk (1024) sizes; one workspace serves calls of
+    decreasing size in a row, and its stale contents do not leak into later results."""
+    m = I.random_model(96, 64, 24, 16, 8, np.float16, np.float16, config=55)
+    q_big = I.uniform_queries(9000, I.rng(55, I.P_QUERY, 0))
+    _, ws = _dec_binned(N, ctx, m, q_big, 1)
+    q = I.uniform_queries(n, I.rng(55, I.P_QUERY, n))
+    got, ws2 = _dec_binned(N, ctx, m, q, 1, ws)
+    assert ws2 is ws
+    np.testing.assert_array_equal(got, _dec(N, ctx, m, q, 1))
+    assert_rel(got, O.decode(m, q), TOL16, f"n={n}")
+
+
+def test_binned_64_texel_tiles(N, ctx):
+    """A map of more than 16384 tiles of 32^2 texels (8192 x 2112) bins by 64^2 tiles."""
+    import torch
+    m = I.random_model(8192, 2112, 2048, 528, 4, np.float16, np.float16, config=56)
+    assert ctx.binned_workspace_bytes(N.DeviceModel.from_numpy(m), 0) == 256 * 128 * 33 * 4 + \
+        2 * (((128 * 33 + 1) * 4 + 255) // 256 * 256)
+    q = I.uniform_queries(300_000, I.rng(56, I.P_QUERY))
+    got, _ = _dec_binned(N, ctx, m, q, 1)
+    np.testing.assert_array_equal(got, _dec(N, ctx, m, q, 1))
+    sel = np.random.default_rng(56).integers(0, q.shape[0], 4096)
+    assert_rel(got[sel], O.decode(m, q[sel]), TOL16, "64^2 tiles")
+    del torch
+
+
+def test_binned_argument_errors(N, ctx):
+    import ctypes
+    import torch
+    m = I.random_model(64, 64, 16, 16, 8, np.float16, np.float16, config=53)
+    dm = N.DeviceModel.from_numpy(m)
+    q = torch.rand((100, 3), device="cuda")
+    out = torch.empty((100, 3), dtype=torch.float16, device="cuda")
+    need = ctx.binned_workspace_bytes(dm, 100)
+    ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    L = N.lib()
+    args = (ctx.h, ctypes.byref(dm.desc), q.data_ptr(), 100, out.data_ptr(), 1)
+    assert L.ndgi_decode_binned(*args, ws.data_ptr(), need - 1, None) == N.ERR_INVALID_ARG
+    assert b"needed" in L.ndgi_last_error()
+    assert L.ndgi_decode_binned(*args, ws.data_ptr() + 16, need, None) == N.ERR_INVALID_ARG
+    assert L.ndgi_decode_binned(*args, None, need, None) == N.ERR_INVALID_ARG
+    assert L.ndgi_decode_binned(ctx.h, ctypes.byref(dm.desc), q.data_ptr(), 100, out.data_ptr(), 5,
+                                ws.data_ptr(), need, None) == N.ERR_INVALID_ARG
+    assert L.ndgi_decode_binned(ctx.h, ctypes.byref(dm.desc), None, 0, None, 1, None, 0, None) == N.OK
+    assert L.ndgi_decode_binned(*args, ws.data_ptr(), need, None) == N.OK
+    torch.cuda.synchronize()
+
+
 # ---------------------------------------------------------------------------- pages
 def _vt_setup(prec, seed=60):
     sides = [(256, 256, 24), (384, 384, 24), (512, 256, 12)]
@@ -233,7 +316,11 @@ def test_c2_frame_and_random_sampled(N, ctx, c2_model):
     qd = torch.from_numpy(q).cuda()
     sel = g.integers(0, q.shape[0], 1 << 16)
     ref = O.decode(m, q[sel])
+    ws = None
     for prec, tol in ((1, TOL16), (0, TOL32)):
         out = ctx.decode(dm, qd, prec)
         got = out[torch.from_numpy(sel).cuda()].float().cpu().numpy()
         assert_rel(got, ref, tol, f"random prec {prec}")
+        binned, ws = ctx.decode_binned(dm, qd, prec, workspace=ws)
+        assert torch.equal(binned.view(torch.int16 if prec else torch.int32),
+                           out.view(torch.int16 if prec else torch.int32)), f"binned != direct, prec {prec}"
