@@ -42,6 +42,35 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def source_digest() -> str:
+    """sha256 over the kernel sources, the ABI header and the build flags: the identity of
+    the code whose HBM byte counters profiles/traffic.json records."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2604_12625_amd", "csrc", "*")))
+    files += [os.path.join(ROOT, "include", "ndgi.h"), os.path.join(ROOT, "paper_2604_12625_amd", "build.py")]
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel_key: str):
+    """HBM bytes per launch of `kernel_key` from the committed byte-counter summary, or None
+    when there is none or the sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("sources_sha256") != source_digest():
+        return None
+    k = rec.get("per_launch", {}).get(kernel_key)
+    return None if k is None else k["traffic_bytes"]
+
+
 class Timer:
     """HIP events on torch's current stream (the stream every launch below uses)."""
 
@@ -294,10 +323,13 @@ def main():
 
     frame_bytes = FRAME_BYTES_PER_TEXEL * W * H
     rl_frame = dict(bound="hbm", achieved=frame_bytes / (f16["frame_ms"] * 1e-3) / 1e9, peak=HBM_PEAK_GBS,
-                    unit="GB/s", traffic=None, kernel="k_decode_pages<FP16>", bytes_per_launch=frame_bytes)
+                    unit="GB/s", traffic=measured_traffic("frame_f16"),
+                    kernel="k_decode_tiles (+ k_decode_pages<FP16> for items off the tile path)",
+                    bytes_per_launch=frame_bytes)
     rl_frame["frac"] = rl_frame["achieved"] / HBM_PEAK_GBS
     rl_rand = dict(bound="hbm", achieved=RANDOM_COMPULSORY_BYTES / (f16["random_ms"] * 1e-3) / 1e9,
-                   peak=HBM_PEAK_GBS, unit="GB/s", traffic=None,
+                   peak=HBM_PEAK_GBS, unit="GB/s",
+                   traffic=measured_traffic("random_f16_" + args.random_path),
                    kernel=("ndgi_decode_binned (k_bin_count, k_bin_colscan, k_bin_starts, k_bin_scatter, "
                            "k_decode_binned<FP16>)" if args.random_path == "binned" else "k_decode_query<FP16>"),
                    bytes_per_launch=RANDOM_COMPULSORY_BYTES)

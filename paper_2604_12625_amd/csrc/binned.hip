@@ -61,32 +61,44 @@ __global__ __launch_bounds__(kSortThreads) void k_bin_count(ndgi_model m, BinGeo
 }
 
 // Per bin (one thread each): exclusive prefix of counts over the sort workgroups, in
-// place, and the bin's total into start[bin].
+// place, and the bin's total into start[bin].  Loads go 16 rows at a time so that many
+// are in flight.
 __global__ __launch_bounds__(256) void k_bin_colscan(int32_t* __restrict__ counts, int nbins,
                                                      int32_t* __restrict__ start) {
   const int b = blockIdx.x * 256 + threadIdx.x;
   if (b >= nbins) return;
   int32_t run = 0;
-  for (int w = 0; w < kSortWgs; ++w) {
-    const int32_t c = counts[(int64_t)w * nbins + b];
-    counts[(int64_t)w * nbins + b] = run;
-    run += c;
+  static_assert(kSortWgs % 16 == 0, "column scan works in groups of 16 rows");
+  for (int w0 = 0; w0 < kSortWgs; w0 += 16) {
+    int32_t c[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) c[r] = counts[(int64_t)(w0 + r) * nbins + b];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      counts[(int64_t)(w0 + r) * nbins + b] = run;
+      run += c[r];
+    }
   }
   start[b] = run;
 }
 
 // start[0..nbins) := exclusive prefix of the bin totals, start[nbins] := n;
 // items[b] := exclusive prefix of the work items per bin (ceil(count / kPiece)),
-// items[nbins] := total.  One workgroup of 1024 threads, each over a run of bins.
+// items[nbins] := total.  One workgroup of 1024 threads: the totals are staged in LDS
+// with coalesced loads, each thread scans a run of bins, the run sums are scanned across
+// the workgroup.
 __global__ __launch_bounds__(1024) void k_bin_starts(int32_t* __restrict__ start, int32_t* __restrict__ items,
                                                      int nbins, int32_t n) {
+  __shared__ int32_t tot[kMaxBins];
   __shared__ int32_t sh[1024], shi[1024];
+  for (int i = threadIdx.x; i < nbins; i += 1024) tot[i] = start[i];
+  __syncthreads();
   const int per = (nbins + 1023) / 1024;
   const int lo = threadIdx.x * per, hi = min(nbins, lo + per);
   int32_t s = 0, si = 0;
   for (int i = lo; i < hi; ++i) {
-    s += start[i];
-    si += (start[i] + kPiece - 1) / kPiece;
+    s += tot[i];
+    si += (tot[i] + kPiece - 1) / kPiece;
   }
   sh[threadIdx.x] = s;
   shi[threadIdx.x] = si;
@@ -100,9 +112,10 @@ __global__ __launch_bounds__(1024) void k_bin_starts(int32_t* __restrict__ start
     __syncthreads();
   }
   int32_t run = sh[threadIdx.x] - s, runi = shi[threadIdx.x] - si;
+  // each thread rewrites only its own run of tot: totals become exclusive prefixes
   for (int i = lo; i < hi; ++i) {
-    const int32_t c = start[i];
-    start[i] = run;
+    const int32_t c = tot[i];
+    tot[i] = run;
     items[i] = runi;
     run += c;
     runi += (c + kPiece - 1) / kPiece;
@@ -111,6 +124,8 @@ __global__ __launch_bounds__(1024) void k_bin_starts(int32_t* __restrict__ start
     start[nbins] = n;
     items[nbins] = runi;
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nbins; i += 1024) start[i] = tot[i];
 }
 
 // Scatter: every query of sort workgroup wg goes to the next free slot of its bin; a

@@ -391,16 +391,21 @@ __device__ __forceinline__ void texel_inputs(const ndgi_model& m, int x, int y, 
 // d.lo16 = fp16(v0 - hi.lo16), d.hi16 = fp16(v1 - hi.hi16): the residuals of a packed
 // pair of FP16 values against the FP32 values they came from (one v_fma_mix each).
 __device__ __forceinline__ uint32_t resid_pair(uint32_t hi, float v0, float v1) {
-  uint32_t d = 0;
-  asm("v_fma_mixlo_f16 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "+v"(d) : "v"(hi), "v"(v0));
-  asm("v_fma_mixhi_f16 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "+v"(d) : "v"(hi), "v"(v1));
+  uint32_t d;
+  // one statement writes both halves, so the result needs no initial value
+  asm("v_fma_mixlo_f16 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]\n\t"
+      "v_fma_mixhi_f16 %0, -%1, 1.0, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+      : "=&v"(d)
+      : "v"(hi), "v"(v0), "v"(v1));
   return d;
 }
 // Same with the result clamped to [0, 1] (the hardware clamp bit).
 __device__ __forceinline__ uint32_t resid_pair_clamp(uint32_t hi, float v0, float v1) {
-  uint32_t d = 0;
-  asm("v_fma_mixlo_f16 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0] clamp" : "+v"(d) : "v"(hi), "v"(v0));
-  asm("v_fma_mixhi_f16 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0] clamp" : "+v"(d) : "v"(hi), "v"(v1));
+  uint32_t d;
+  asm("v_fma_mixlo_f16 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0] clamp\n\t"
+      "v_fma_mixhi_f16 %0, -%1, 1.0, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0] clamp"
+      : "=&v"(d)
+      : "v"(hi), "v"(v0), "v"(v1));
   return d;
 }
 

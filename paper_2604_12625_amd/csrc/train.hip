@@ -28,6 +28,10 @@ struct TrainLds {
   float dz[16 * 4];
 };
 
+// Slots of the per-lane weight table (see k_train).
+constexpr int kSA1 = 0, kSA2 = 8, kSA3 = 24, kSW3T = 32, kSW2T = 34, kSW1T = 50, kSC1 = 58, kSC2 = 66,
+              kSC3 = 74, kWSlots = 78;
+
 __device__ __forceinline__ float half_bits(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
 
 struct TrainDims {
@@ -43,6 +47,7 @@ __global__ __launch_bounds__(256) void k_train(TrainDims d, const float* __restr
                                                 float* __restrict__ partials, double* __restrict__ loss_part,
                                                 uint32_t* __restrict__ flags) {
   __shared__ TrainLds lds_all[4];
+  __shared__ float wsl[kWSlots][64];
   const int wave = threadIdx.x >> 6;
   TrainLds& L = lds_all[wave];
   const int lane = threadIdx.x & 63;
@@ -55,18 +60,46 @@ __global__ __launch_bounds__(256) void k_train(TrainDims d, const float* __restr
   float* g_w = G + d.off_w;
   float* g_grid = G + d.off_g;
 
-  // forward weights (as in the FP32 decoder) and transposed weights for the backward pass
-  Dec32 fw;
-  load_dec32<NDGI_DTYPE_F32>(fw, mlp, lane);
-  float w3t[2], w2t[2][8], w1t[8];
-#pragma unroll
-  for (int mc = 0; mc < 2; ++mc) {
-    w3t[mc] = g < 3 ? mlp[kOffW3 + g * 32 + 16 * mc + (lane & 15)] : 0.0f;
-#pragma unroll
-    for (int m = 0; m < 8; ++m) w2t[mc][m] = mlp[kOffW2 + unit_of(g, m) * 32 + 16 * mc + (lane & 15)];
+  // Forward weights (the FP32 decoder's A operands), transposed weights for the backward
+  // pass and the biases in C layout, one float per lane per slot, staged in LDS once per
+  // workgroup: held in registers they would leave room for one wave per SIMD only.
+  for (int idx = threadIdx.x; idx < kWSlots * 64; idx += 256) {
+    const int slot = idx >> 6, ln = idx & 63;
+    const int gg = ln >> 4, ii = ln & 15;
+    float v = 0.0f;
+    if (slot < kSA2) {                       // a1[mc][e]
+      const int mc = (slot - kSA1) >> 2, e = (slot - kSA1) & 3;
+      v = mlp[kOffW1 + (16 * mc + ii) * 16 + input_of(gg, e)];
+    } else if (slot < kSA3) {                // a2[mc][e]
+      const int mc = (slot - kSA2) >> 3, e = (slot - kSA2) & 7;
+      v = mlp[kOffW2 + (16 * mc + ii) * 32 + unit_of(gg, e)];
+    } else if (slot < kSW3T) {               // a3 of output group 0: rows 0..2 at lanes i < 3
+      const int e = slot - kSA3;
+      v = ii < 3 ? mlp[kOffW3 + ii * 32 + unit_of(gg, e)] : 0.0f;
+    } else if (slot < kSW2T) {               // w3t[mc]
+      const int mc = slot - kSW3T;
+      v = gg < 3 ? mlp[kOffW3 + gg * 32 + 16 * mc + ii] : 0.0f;
+    } else if (slot < kSW1T) {               // w2t[mc][m]
+      const int mc = (slot - kSW2T) >> 3, m = (slot - kSW2T) & 7;
+      v = mlp[kOffW2 + unit_of(gg, m) * 32 + 16 * mc + ii];
+    } else if (slot < kSC1) {                // w1t[m]
+      const int m = slot - kSW1T;
+      v = mlp[kOffW1 + unit_of(gg, m) * 16 + input_of(ii >> 2, ii & 3)];
+    } else if (slot < kSC2) {                // c1[mc][r]
+      const int mc = (slot - kSC1) >> 2, r = (slot - kSC1) & 3;
+      v = mlp[kOffB1 + 16 * mc + 4 * gg + r];
+    } else if (slot < kSC3) {                // c2[mc][r]
+      const int mc = (slot - kSC2) >> 2, r = (slot - kSC2) & 3;
+      v = mlp[kOffB2 + 16 * mc + 4 * gg + r];
+    } else {                                 // c3[r]
+      const int r = slot - kSC3;
+      v = r < 3 ? mlp[kOffB3 + r] : 0.0f;
+    }
+    wsl[slot][ln] = v;
   }
-#pragma unroll
-  for (int m = 0; m < 8; ++m) w1t[m] = mlp[kOffW1 + unit_of(g, m) * 16 + input_of((lane & 15) >> 2, lane & 3)];
+  __syncthreads();
+  auto W = [&](int slot) { return wsl[slot][lane]; };
+  auto C4 = [&](int slot) { return f4v{W(slot), W(slot + 1), W(slot + 2), W(slot + 3)}; };
 
   f4v gW2[2][2], gW1[2], gW3[2];
 #pragma unroll
@@ -121,11 +154,11 @@ __global__ __launch_bounds__(256) void k_train(TrainDims d, const float* __restr
     }
 
     // ---- forward MLP
-    f4v p0 = fw.c1[0], p1 = fw.c1[1];
+    f4v p0 = C4(kSC1), p1 = C4(kSC1 + 4);
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      p0 = __builtin_amdgcn_mfma_f32_16x16x4f32(fw.a1[0][m], f[m], p0, 0, 0, 0);
-      p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(fw.a1[1][m], f[m], p1, 0, 0, 0);
+      p0 = __builtin_amdgcn_mfma_f32_16x16x4f32(W(kSA1 + m), f[m], p0, 0, 0, 0);
+      p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(W(kSA1 + 4 + m), f[m], p1, 0, 0, 0);
     }
     float h1[8];
 #pragma unroll
@@ -133,11 +166,11 @@ __global__ __launch_bounds__(256) void k_train(TrainDims d, const float* __restr
       h1[r] = fmaxf(p0[r], 0.0f);
       h1[4 + r] = fmaxf(p1[r], 0.0f);
     }
-    f4v r0 = fw.c2[0], r1 = fw.c2[1];
+    f4v r0 = C4(kSC2), r1 = C4(kSC2 + 4);
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      r0 = __builtin_amdgcn_mfma_f32_16x16x4f32(fw.a2[0][m], h1[m], r0, 0, 0, 0);
-      r1 = __builtin_amdgcn_mfma_f32_16x16x4f32(fw.a2[1][m], h1[m], r1, 0, 0, 0);
+      r0 = __builtin_amdgcn_mfma_f32_16x16x4f32(W(kSA2 + m), h1[m], r0, 0, 0, 0);
+      r1 = __builtin_amdgcn_mfma_f32_16x16x4f32(W(kSA2 + 8 + m), h1[m], r1, 0, 0, 0);
     }
     float h2[8];
 #pragma unroll
@@ -145,9 +178,9 @@ __global__ __launch_bounds__(256) void k_train(TrainDims d, const float* __restr
       h2[r] = fmaxf(r0[r], 0.0f);
       h2[4 + r] = fmaxf(r1[r], 0.0f);
     }
-    f4v z = fw.c3;   // output rows 0..2 of group 0's slot (lanes g = 0)
+    f4v z = C4(kSC3);   // output rows 0..2 of group 0's slot (lanes g = 0)
 #pragma unroll
-    for (int m = 0; m < 8; ++m) z = __builtin_amdgcn_mfma_f32_16x16x4f32(fw.a3[0][m], h2[m], z, 0, 0, 0);
+    for (int m = 0; m < 8; ++m) z = __builtin_amdgcn_mfma_f32_16x16x4f32(W(kSA3 + m), h2[m], z, 0, 0, 0);
 
     // ---- output, loss, dL/dz (lanes g = 0 own sample j's three channels)
     float dz0 = 0.0f, dz1 = 0.0f, dz2 = 0.0f;
@@ -183,8 +216,8 @@ __global__ __launch_bounds__(256) void k_train(TrainDims d, const float* __restr
 
     // ---- backward through the decoder
     f4v q0 = {0, 0, 0, 0}, q1 = {0, 0, 0, 0};
-    q0 = __builtin_amdgcn_mfma_f32_16x16x4f32(w3t[0], dzb, q0, 0, 0, 0);
-    q1 = __builtin_amdgcn_mfma_f32_16x16x4f32(w3t[1], dzb, q1, 0, 0, 0);
+    q0 = __builtin_amdgcn_mfma_f32_16x16x4f32(W(kSW3T), dzb, q0, 0, 0, 0);
+    q1 = __builtin_amdgcn_mfma_f32_16x16x4f32(W(kSW3T + 1), dzb, q1, 0, 0, 0);
     float d2[8];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -194,8 +227,8 @@ __global__ __launch_bounds__(256) void k_train(TrainDims d, const float* __restr
     f4v t0 = {0, 0, 0, 0}, t1 = {0, 0, 0, 0};
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      t0 = __builtin_amdgcn_mfma_f32_16x16x4f32(w2t[0][m], d2[m], t0, 0, 0, 0);
-      t1 = __builtin_amdgcn_mfma_f32_16x16x4f32(w2t[1][m], d2[m], t1, 0, 0, 0);
+      t0 = __builtin_amdgcn_mfma_f32_16x16x4f32(W(kSW2T + m), d2[m], t0, 0, 0, 0);
+      t1 = __builtin_amdgcn_mfma_f32_16x16x4f32(W(kSW2T + 8 + m), d2[m], t1, 0, 0, 0);
     }
     float d1[8];
 #pragma unroll
@@ -205,7 +238,7 @@ __global__ __launch_bounds__(256) void k_train(TrainDims d, const float* __restr
     }
     f4v dx = {0, 0, 0, 0};
 #pragma unroll
-    for (int m = 0; m < 8; ++m) dx = __builtin_amdgcn_mfma_f32_16x16x4f32(w1t[m], d1[m], dx, 0, 0, 0);
+    for (int m = 0; m < 8; ++m) dx = __builtin_amdgcn_mfma_f32_16x16x4f32(W(kSW1T + m), d1[m], dx, 0, 0, 0);
     // dx[r] = dLoss/d(input_of(g, r)) of sample j
 
     // ---- scatter input gradients (straight-through BC simulation; grid corners)
