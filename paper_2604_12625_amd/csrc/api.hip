@@ -99,6 +99,8 @@ int ndgi_create(ndgi_ctx** out, int32_t device) {
   bool ok = hipMalloc(&c->flags_dev, 256) == hipSuccess &&
             hipMalloc(&c->partials_dev, sizeof(float) * (size_t)c->train_waves * kPartialStride) == hipSuccess &&
             hipMalloc(&c->loss_part_dev, sizeof(double) * (size_t)c->train_waves) == hipSuccess &&
+            hipMalloc(&c->stage_dev, sizeof(float) * (size_t)(c->train_waves / 64 + 1) * kPartialStride) ==
+                hipSuccess &&
             hipMemset(c->flags_dev, 0, 256) == hipSuccess &&
             hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) == hipSuccess;
   if (!ok) {
@@ -118,6 +120,7 @@ int ndgi_destroy(ndgi_ctx* c) {
   hipFree(c->flags_dev);
   hipFree(c->partials_dev);
   hipFree(c->loss_part_dev);
+  hipFree(c->stage_dev);
   delete c;
   return NDGI_OK;
 }

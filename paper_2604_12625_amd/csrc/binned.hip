@@ -10,12 +10,15 @@
 // query reads its four texels from LDS and its grid nodes from a one- or two-key window
 // that stays in cache, and writes its RGB at its original index.  The per-query
 // arithmetic is the direct decode's, so both give the same bits.
+#include <algorithm>
+
 #include "device.hpp"
 #include "internal.hpp"
 
 namespace ndgi {
 
 constexpr int kSortWgs = 256;       // workgroups of the counting sort (1024 threads each)
+constexpr int kBatch = 8;           // queries per thread whose loads are in flight together
 constexpr int kSortThreads = 1024;
 constexpr int kMaxBins = 16384;     // LDS histogram capacity (64 KiB)
 constexpr int kPiece = 2048;        // at most this many queries per decode work item
@@ -52,9 +55,19 @@ __global__ __launch_bounds__(kSortThreads) void k_bin_count(ndgi_model m, BinGeo
   for (int i = threadIdx.x; i < nbins; i += kSortThreads) hist[i] = 0;
   __syncthreads();
   const int64_t lo = (int64_t)blockIdx.x * slice, hi = min(n, lo + slice);
-#pragma unroll 4
-  for (int64_t q = lo + threadIdx.x; q < hi; q += kSortThreads)
-    atomicAdd(&hist[query_bin(uvt[q * 3], uvt[q * 3 + 1], m, bg)], 1);
+  // loads of kBatch queries are issued before any is used, so they are in flight together
+  for (int64_t base = lo + threadIdx.x; base < hi; base += kSortThreads * kBatch) {
+    float u[kBatch], v[kBatch];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const int64_t q = min(base + (int64_t)kSortThreads * k, hi - 1);
+      u[k] = uvt[q * 3];
+      v[k] = uvt[q * 3 + 1];
+    }
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k)
+      if (base + (int64_t)kSortThreads * k < hi) atomicAdd(&hist[query_bin(u[k], v[k], m, bg)], 1);
+  }
   __syncthreads();
   int32_t* row = counts + (int64_t)blockIdx.x * nbins;
   for (int i = threadIdx.x; i < nbins; i += kSortThreads) row[i] = hist[i];
@@ -142,11 +155,23 @@ __global__ __launch_bounds__(kSortThreads) void k_bin_scatter(ndgi_model m, BinG
   for (int i = threadIdx.x; i < nbins; i += kSortThreads) pos[i] = start[i] + row[i];
   __syncthreads();
   const int64_t lo = (int64_t)blockIdx.x * slice, hi = min(n, lo + slice);
-#pragma unroll 4
-  for (int64_t q = lo + threadIdx.x; q < hi; q += kSortThreads) {
-    const float u = uvt[q * 3], v = uvt[q * 3 + 1], t = uvt[q * 3 + 2];
-    const int p = atomicAdd(&pos[query_bin(u, v, m, bg)], 1);
-    sorted[p] = make_float4(u, v, t, __builtin_bit_cast(float, (uint32_t)q));
+  for (int64_t base = lo + threadIdx.x; base < hi; base += kSortThreads * kBatch) {
+    float u[kBatch], v[kBatch], t[kBatch];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const int64_t q = min(base + (int64_t)kSortThreads * k, hi - 1);
+      u[k] = uvt[q * 3];
+      v[k] = uvt[q * 3 + 1];
+      t[k] = uvt[q * 3 + 2];
+    }
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const int64_t q = base + (int64_t)kSortThreads * k;
+      if (q < hi) {
+        const int p = atomicAdd(&pos[query_bin(u[k], v[k], m, bg)], 1);
+        sorted[p] = make_float4(u[k], v[k], t[k], __builtin_bit_cast(float, (uint32_t)q));
+      }
+    }
   }
 }
 
@@ -188,22 +213,50 @@ __device__ __forceinline__ void wave_exclusive_scan(int32_t* a, int len, int lan
 //  * orders the item's queries by their first time key with a counting sort in LDS (perm),
 //    so that the queries of a wave read one or two keys' grid window, which stays in L1/L2;
 //  * runs the two-phase query decode over the queries in that order.
-// The FP16 decoder fits 4 waves per SIMD (the LDS of 32-texel tiles allows 4 workgroups
-// per CU); the FP32 decoder needs more registers than that leaves.
-template <int PREC, int TSL>
-constexpr int binned_waves() { return (PREC == NDGI_PREC_F16 && TSL == 5) ? 4 : 1; }
+// Grid-node window of a tile along one axis: every node that a query binned to texels
+// [t0, t0 + TS) can read, i.e. [floor(qlo), floor(qhi) + 1] for the grid positions
+// q = (p + 0.5) G / S - 0.5 of the texel positions p in [t0, t0 + TS), widened by 0.01 node
+// against rounding and clamped to the grid.  Queries clamped to the map's edge read edge
+// nodes, which the clamp keeps inside.  The same arithmetic runs on the host for the
+// largest window (kept unfused there and here).
+__host__ __device__ __forceinline__ void node_window(int t0, int TS, int S, int G, int& lo, int& hi) {
+#pragma clang fp contract(off)
+  const float r = (float)G / (float)S;
+  const float qlo = ((float)t0 + 0.5f) * r - 0.5f;
+  const float qhi = ((float)(t0 + TS) + 0.5f) * r - 0.5f;
+  lo = max((int)floorf(qlo - 0.01f), 0);
+  hi = min((int)floorf(qhi + 0.01f) + 1, G - 1);
+}
 
-template <int PREC, int GDT, int TSL>
-__global__ __launch_bounds__(256, (binned_waves<PREC, TSL>())) void k_decode_binned(ndgi_model m, BinGeom bg, const float4* __restrict__ sorted,
-                                                       const int32_t* __restrict__ start,
-                                                       const int32_t* __restrict__ items, void* __restrict__ out) {
+constexpr int kGridLdsBytes = 48 * 1024;   // LDS for a tile's grid window over all keys
+
+// Workgroups per CU that fit: the FP16 decoder at 4 waves per SIMD with the LDS of
+// 32-texel tiles and global grid reads; otherwise the compiler's choice.
+template <int PREC, int TSL, bool GLDS>
+constexpr int binned_waves() { return (PREC == NDGI_PREC_F16 && TSL == 5 && !GLDS) ? 4 : 1; }
+
+// Decode of the sorted queries.  Per work item the workgroup
+//  * decodes the tile region into LDS: R = TS + 4 texels a side (the tile plus one
+//    footprint of halo), 8 bytes per texel (channel c in byte c);
+//  * GLDS: stages the tile's grid window (all keys) in LDS, so the query loop reads no
+//    grid node from HBM;
+//    otherwise: orders the item's queries by their first time key with a counting sort in
+//    LDS (perm), so that the queries of a wave read one or two keys' window from cache;
+//  * runs the two-phase query decode over the item's queries.
+template <int PREC, int GDT, int TSL, bool GLDS>
+__global__ __launch_bounds__(256, (binned_waves<PREC, TSL, GLDS>())) void k_decode_binned(
+    ndgi_model m, BinGeom bg, const float4* __restrict__ sorted, const int32_t* __restrict__ start,
+    const int32_t* __restrict__ items, void* __restrict__ out) {
   constexpr int TS = 1 << TSL;
   constexpr int R = TS + 4;
   constexpr int FP = R / 4;                      // footprints per region side
   constexpr int kTasks = FP * FP * 2;            // (footprint, row pair)
+  constexpr int kNodeU4 = GDT == NDGI_DTYPE_F16 ? 1 : 2;   // uint4 per grid node
+  constexpr int kWinU4 = GLDS ? kGridLdsBytes / 16 : 1;
   __shared__ uint2 reg[R * R];
   __shared__ float feat_all[4 * 64 * kFeatStride];
-  __shared__ uint16_t perm[kPiece];
+  __shared__ uint16_t perm[GLDS ? 1 : kPiece];
+  __shared__ uint4 gwin[kWinU4];
   // the key histogram lives only in the item prologue, when no wave uses its feature block
   int32_t* khist = (int32_t*)feat_all;
   static_assert(kMaxKeys * 4 <= 4 * 64 * kFeatStride * 4, "key histogram must fit the feature blocks");
@@ -215,7 +268,17 @@ __global__ __launch_bounds__(256, (binned_waves<PREC, TSL>())) void k_decode_bin
   const int nbins = bg.ntx * bg.nty;
   const int n_items = items[nbins];
   const uint32_t bw = (uint32_t)m.W >> 2, bh = (uint32_t)m.H >> 2;
-  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+  // Item order: workgroups are dispatched to the 8 XCDs round-robin, so workgroup ids
+  // x, x+8, ... share one L2.  Each XCD takes one contiguous eighth of the items (tiles in
+  // row-major order), so tiles processed side by side on an XCD share their halo lines in
+  // its L2.  Small grids take items round-robin.
+  const bool by_xcd = (gridDim.x & 7) == 0 && n_items >= (int)gridDim.x;
+  const int xcd = blockIdx.x & 7, per_xcd = gridDim.x >> 3;
+  const int chunk = (n_items + 7) >> 3;
+  const int it0 = by_xcd ? xcd * chunk + ((int)blockIdx.x >> 3) : (int)blockIdx.x;
+  const int it_end = by_xcd ? min(n_items, (xcd + 1) * chunk) : n_items;
+  const int it_step = by_xcd ? per_xcd : (int)gridDim.x;
+  for (int it = it0; it < it_end; it += it_step) {
     // bin of this item: the last b with items[b] <= it (items is non-decreasing)
     int lo = 0, hi = nbins;
     while (hi - lo > 1) {
@@ -227,8 +290,36 @@ __global__ __launch_bounds__(256, (binned_waves<PREC, TSL>())) void k_decode_bin
     const int64_t s_lo = (int64_t)start[b] + (int64_t)(it - items[b]) * kPiece;
     const int cnt = (int)(min((int64_t)start[b + 1], s_lo + kPiece) - s_lo);
     const int tx0 = (b % bg.ntx) << TSL, ty0 = (b / bg.ntx) << TSL;
-    __syncthreads();     // the previous item's readers of reg, perm and khist are done
-    for (int i = threadIdx.x; i < m.T; i += 256) khist[i] = 0;
+    int wx0 = 0, wy0 = 0, nwx = 1, nwy = 1;
+    __syncthreads();     // the previous item's readers of reg, gwin, perm and khist are done
+    if constexpr (GLDS) {
+      int wx1, wy1;
+      node_window(tx0, TS, m.W, m.Gw, wx0, wx1);
+      node_window(ty0, TS, m.H, m.Gh, wy0, wy1);
+      nwx = wx1 - wx0 + 1;
+      nwy = wy1 - wy0 + 1;
+      const int total = m.T * nwy * nwx * kNodeU4;   // the host checked total <= kWinU4
+      const uint4* gsrc = (const uint4*)m.grid;
+      // 4 loads per thread in flight before their LDS stores
+#pragma unroll 1
+      for (int base = threadIdx.x; base < total; base += 256 * 4) {
+        uint4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int idx = min(base + 256 * k, total - 1);
+          const int nd = idx / kNodeU4, part = idx - nd * kNodeU4;
+          const int key = nd / (nwy * nwx), rem = nd - key * (nwy * nwx);
+          const int gy = rem / nwx, gx = rem - gy * nwx;
+          v[k] = gsrc[(((uint32_t)key * (uint32_t)m.Gh + (uint32_t)(wy0 + gy)) * (uint32_t)m.Gw +
+                       (uint32_t)(wx0 + gx)) * kNodeU4 + part];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (base + 256 * k < total) gwin[base + 256 * k] = v[k];
+      }
+    } else {
+      for (int i = threadIdx.x; i < m.T; i += 256) khist[i] = 0;
+    }
 #pragma unroll 1
     for (int task = threadIdx.x; task < kTasks; task += 256) {
       const int rp = task & 1, f = task >> 1;
@@ -255,23 +346,40 @@ __global__ __launch_bounds__(256, (binned_waves<PREC, TSL>())) void k_decode_bin
         }
       }
     }
-    __syncthreads();     // khist zeroed
-    // keys are recomputed in the scatter pass rather than kept: registers hold the decoder
+    if constexpr (!GLDS) {
+      __syncthreads();     // khist zeroed
+      // keys are recomputed in the scatter pass rather than kept: registers hold the decoder
 #pragma unroll 1
-    for (int i = threadIdx.x; i < cnt; i += 256) atomicAdd(&khist[make_keys(sorted[s_lo + i].z, m.T).k0], 1);
-    __syncthreads();
-    if (wave == 0) wave_exclusive_scan(khist, m.T, lane);
-    __syncthreads();
+      for (int i = threadIdx.x; i < cnt; i += 256) atomicAdd(&khist[make_keys(sorted[s_lo + i].z, m.T).k0], 1);
+      __syncthreads();
+      if (wave == 0) wave_exclusive_scan(khist, m.T, lane);
+      __syncthreads();
 #pragma unroll 1
-    for (int i = threadIdx.x; i < cnt; i += 256)
-      perm[atomicAdd(&khist[make_keys(sorted[s_lo + i].z, m.T).k0], 1)] = (uint16_t)i;
-    __syncthreads();     // reg and perm complete
+      for (int i = threadIdx.x; i < cnt; i += 256)
+        perm[atomicAdd(&khist[make_keys(sorted[s_lo + i].z, m.T).k0], 1)] = (uint16_t)i;
+    }
+    __syncthreads();     // reg, gwin and perm complete
+    // the record of the wave's next pass is loaded while this pass computes
+    auto record = [&](int i) {
+      const int c = min(i, cnt - 1);
+      return sorted[s_lo + (GLDS ? c : (int)perm[c])];
+    };
+    float4 next = record(64 * wave + lane);
     for (int p0 = 64 * wave; p0 < cnt; p0 += 256) {
       const int mine = p0 + lane;
-      const float4 rec = sorted[s_lo + perm[min(mine, cnt - 1)]];
+      const float4 rec = next;
+      if (p0 + 256 < cnt) next = record(mine + 256);
       float sp[8], gr[8];
       spatial8_lds(reg, R, tx0, ty0, coord_axis(rec.x, m.W), coord_axis(rec.y, m.H), sp);
-      query_grid8<GDT>(m, rec.x, rec.y, rec.z, gr);
+      if constexpr (GLDS) {
+        // window-local node; the clamp only guards the LDS bounds
+        query_grid8_at<GDT>(m, rec.x, rec.y, rec.z, [&](int key, int gy, int gx) {
+          const int ly = min(max(gy - wy0, 0), nwy - 1), lx = min(max(gx - wx0, 0), nwx - 1);
+          return (const uint4*)&gwin[((key * nwy + ly) * nwx + lx) * kNodeU4];
+        }, gr);
+      } else {
+        query_grid8<GDT>(m, rec.x, rec.y, rec.z, gr);
+      }
       wave_sync();
       store_feats(feat, lane, sp, gr);
       wave_sync();
@@ -281,6 +389,21 @@ __global__ __launch_bounds__(256, (binned_waves<PREC, TSL>())) void k_decode_bin
                         !(isfinite(rec.x) && isfinite(rec.y) && isfinite(rec.z)));
     }
   }
+}
+
+// Largest grid window (in uint4) of any tile of the map, by the kernel's own arithmetic.
+static int64_t max_window_u4(const ndgi_model& m, const BinGeom& bg) {
+  const int TS = 1 << bg.ts_log2;
+  int mx = 0, my = 0, lo, hi;
+  for (int t = 0; t < bg.ntx; ++t) {
+    node_window(t * TS, TS, m.W, m.Gw, lo, hi);
+    mx = std::max(mx, hi - lo + 1);
+  }
+  for (int t = 0; t < bg.nty; ++t) {
+    node_window(t * TS, TS, m.H, m.Gh, lo, hi);
+    my = std::max(my, hi - lo + 1);
+  }
+  return (int64_t)mx * my * m.T * (m.grid_dtype == NDGI_DTYPE_F16 ? 1 : 2);
 }
 
 struct BinnedLayout {
@@ -335,17 +458,20 @@ int launch_decode_binned(ndgi_ctx* ctx, const ndgi_model& m, const float* uvt, i
   const bool g16 = m.grid_dtype == NDGI_DTYPE_F16;
   // at most one item per kPiece queries plus one per bin
   const int64_t max_items = n / kPiece + L.nbins;
-#define NDGI_BINNED(P, G, TSL)                                                                                     \
+  // grid window in LDS when it fits (32-texel tiles only)
+  const bool glds = L.bg.ts_log2 == 5 && max_window_u4(m, L.bg) * 16 <= kGridLdsBytes;
+#define NDGI_BINNED(P, G, TSL, GL)                                                                               \
   do {                                                                                                             \
-    int64_t wgs = resident_wgs(ctx, (const void*)k_decode_binned<P, G, TSL>);                                      \
+    int64_t wgs = resident_wgs(ctx, (const void*)k_decode_binned<P, G, TSL, GL>);                                  \
     if (wgs > max_items) wgs = max_items;                                                                          \
-    hipLaunchKernelGGL((k_decode_binned<P, G, TSL>), dim3((unsigned)wgs), dim3(256), 0, s, m, L.bg, sorted, start, \
-                       items, out);                                                                                \
+    hipLaunchKernelGGL((k_decode_binned<P, G, TSL, GL>), dim3((unsigned)wgs), dim3(256), 0, s, m, L.bg, sorted,     \
+                       start, items, out);                                                                         \
   } while (0)
-#define NDGI_BINNED_TS(P, G)                     \
-  do {                                           \
-    if (L.bg.ts_log2 == 5) NDGI_BINNED(P, G, 5); \
-    else NDGI_BINNED(P, G, 6);                   \
+#define NDGI_BINNED_TS(P, G)                                 \
+  do {                                                       \
+    if (L.bg.ts_log2 == 5 && glds) NDGI_BINNED(P, G, 5, true); \
+    else if (L.bg.ts_log2 == 5) NDGI_BINNED(P, G, 5, false);   \
+    else NDGI_BINNED(P, G, 6, false);                          \
   } while (0)
   if (prec == NDGI_PREC_F16) {
     if (g16) NDGI_BINNED_TS(NDGI_PREC_F16, NDGI_DTYPE_F16);

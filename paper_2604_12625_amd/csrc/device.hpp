@@ -263,45 +263,59 @@ __device__ __forceinline__ void tap_weights(const Axis& ax, const Axis& ay, floa
   w[3] = ay.w1 * ax.w1;
 }
 
-// Eight grid channels of query (u, v, t): bilinear on the node axes, linear in time.
-// Offsets are 32-bit (the host limits grids to 4 GiB).
+// Accumulate one grid node (8 channels) with weight w: FP16 nodes are 16 bytes (one uint4),
+// FP32 nodes 32 bytes (two uint4).
 template <int GDT>
-__device__ __forceinline__ void query_grid8(const ndgi_model& m, float u, float v, float t, float x[8]) {
+__device__ __forceinline__ void grid_node_fma(const uint4* node, float w, float x[8]) {
+  if constexpr (GDT == NDGI_DTYPE_F16) {
+    const uint4 r = node[0];
+    const uint32_t wd[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      x[2 * c] = fmaf(w, (float)__builtin_bit_cast(_Float16, (uint16_t)(wd[c] & 0xffffu)), x[2 * c]);
+      x[2 * c + 1] = fmaf(w, (float)__builtin_bit_cast(_Float16, (uint16_t)(wd[c] >> 16)), x[2 * c + 1]);
+    }
+  } else {
+    const uint4 a = node[0], b = node[1];
+    const float vv[8] = {__uint_as_float(a.x), __uint_as_float(a.y), __uint_as_float(a.z), __uint_as_float(a.w),
+                         __uint_as_float(b.x), __uint_as_float(b.y), __uint_as_float(b.z), __uint_as_float(b.w)};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) x[c] = fmaf(w, vv[c], x[c]);
+  }
+}
+
+// Eight grid channels of query (u, v, t): bilinear on the node axes, linear in time.
+// `node(key, gy, gx)` returns the address of a node (in HBM, or in a window staged in
+// LDS); the weights and the summation order do not depend on where the nodes live.
+template <int GDT, typename NodeAt>
+__device__ __forceinline__ void query_grid8_at(const ndgi_model& m, float u, float v, float t, NodeAt node,
+                                               float x[8]) {
   const Keys k = make_keys(t, m.T);
   const Axis gx = coord_axis(u, m.Gw), gy = coord_axis(v, m.Gh);
   float w[4];
   tap_weights(gx, gy, w);
-  const uint32_t plane = (uint32_t)m.Gh * (uint32_t)m.Gw;
-  const uint32_t n00 = (uint32_t)gy.i0 * (uint32_t)m.Gw + (uint32_t)gx.i0;
-  const uint32_t dx = (uint32_t)(gx.i1 - gx.i0), dy = (uint32_t)(gy.i1 - gy.i0) * (uint32_t)m.Gw;
-  const uint32_t tap[4] = {n00, n00 + dx, n00 + dy, n00 + dy + dx};
 #pragma unroll
   for (int c = 0; c < 8; ++c) x[c] = 0.0f;
 #pragma unroll
   for (int tk = 0; tk < 2; ++tk) {
-    const uint32_t kb = (uint32_t)(tk ? k.k1 : k.k0) * plane;
+    const int key = tk ? k.k1 : k.k0;
     const float wt = tk ? k.w1 : k.w0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const float wi = wt * w[i];
-      const uint32_t node = kb + tap[i];
-      if constexpr (GDT == NDGI_DTYPE_F16) {
-        const uint4 r = *(const uint4*)((const uint8_t*)m.grid + node * 16u);
-        const uint32_t wd[4] = {r.x, r.y, r.z, r.w};
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          x[2 * c] = fmaf(wi, (float)__builtin_bit_cast(_Float16, (uint16_t)(wd[c] & 0xffffu)), x[2 * c]);
-          x[2 * c + 1] = fmaf(wi, (float)__builtin_bit_cast(_Float16, (uint16_t)(wd[c] >> 16)), x[2 * c + 1]);
-        }
-      } else {
-        const float4 a = *(const float4*)((const uint8_t*)m.grid + node * 32u);
-        const float4 b = *(const float4*)((const uint8_t*)m.grid + node * 32u + 16u);
-        const float vv[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-#pragma unroll
-        for (int c = 0; c < 8; ++c) x[c] = fmaf(wi, vv[c], x[c]);
-      }
-    }
+    for (int i = 0; i < 4; ++i)
+      grid_node_fma<GDT>(node(key, (i & 2) ? gy.i1 : gy.i0, (i & 1) ? gx.i1 : gx.i0), wt * w[i], x);
   }
+}
+
+// The same with the nodes read from HBM.  Offsets are 32-bit (the host limits grids to
+// 4 GiB).
+template <int GDT>
+__device__ __forceinline__ void query_grid8(const ndgi_model& m, float u, float v, float t, float x[8]) {
+  const uint32_t plane = (uint32_t)m.Gh * (uint32_t)m.Gw;
+  constexpr uint32_t kNodeBytes = GDT == NDGI_DTYPE_F16 ? 16u : 32u;
+  const uint8_t* grid = (const uint8_t*)m.grid;
+  query_grid8_at<GDT>(m, u, v, t, [&](int key, int gy, int gx) {
+    return (const uint4*)(grid + ((uint32_t)key * plane + (uint32_t)gy * (uint32_t)m.Gw + (uint32_t)gx) * kNodeBytes);
+  }, x);
 }
 
 // Eight spatial channels of a query, the four texels decoded straight from their BC4
@@ -499,13 +513,15 @@ __device__ __forceinline__ void load_dec16(Dec16& d, const void* mlp, int lane) 
       d.c2[mc][r] = ld<MDT>(mlp, kOffB2 + ur);
     }
   }
+  // every load is unconditional (clamped index, then a select): a conditional load would
+  // be branched around and serialise the whole set
+  float w3[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) w3[e] = ld<MDT>(mlp, kOffW3 + min(i & 3, 2) * 32 + unit_of(g, e));
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
-    for (int e = 0; e < 8; ++e)
-      d.a3[q][e] = ((i >> 2) == q && (i & 3) < 3)
-                       ? (_Float16)ld<MDT>(mlp, kOffW3 + (i & 3) * 32 + unit_of(g, e))
-                       : (_Float16)0.0f;
+    for (int e = 0; e < 8; ++e) d.a3[q][e] = ((i >> 2) == q && (i & 3) < 3) ? (_Float16)w3[e] : (_Float16)0.0f;
 #pragma unroll
   for (int r = 0; r < 4; ++r) d.c3[r] = r < 3 ? ld<MDT>(mlp, kOffB3 + r) : 0.0f;
 }
@@ -553,11 +569,13 @@ __device__ __forceinline__ void load_dec32(Dec32& d, const void* mlp, int lane) 
       d.c2[mc][r] = ld<MDT>(mlp, kOffB2 + 16 * mc + 4 * g + r);
     }
   }
+  float w3[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) w3[e] = ld<MDT>(mlp, kOffW3 + min(i & 3, 2) * 32 + unit_of(g, e));
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
-    for (int e = 0; e < 8; ++e)
-      d.a3[q][e] = ((i >> 2) == q && (i & 3) < 3) ? ld<MDT>(mlp, kOffW3 + (i & 3) * 32 + unit_of(g, e)) : 0.0f;
+    for (int e = 0; e < 8; ++e) d.a3[q][e] = ((i >> 2) == q && (i & 3) < 3) ? w3[e] : 0.0f;
 #pragma unroll
   for (int r = 0; r < 4; ++r) d.c3[r] = r < 3 ? ld<MDT>(mlp, kOffB3 + r) : 0.0f;
 }

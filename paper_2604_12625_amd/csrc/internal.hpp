@@ -45,6 +45,7 @@ struct ndgi_ctx {
   int train_waves = 0;          // persistent waves of the training kernel
   float* partials_dev = nullptr;  // [train_waves][kPartialStride]
   double* loss_part_dev = nullptr;  // [train_waves]
+  float* stage_dev = nullptr;     // [train_waves / 64 + 1][kPartialStride]: first reduction stage
   std::map<ndgi::GraphKey, hipGraphExec_t> graphs;
   std::map<const void*, int> occupancy;   // kernel -> resident 256-thread workgroups per CU
 };

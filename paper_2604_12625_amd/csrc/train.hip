@@ -347,11 +347,33 @@ __global__ __launch_bounds__(256) void k_train(TrainDims d, const float* __restr
   if (lane == 0) loss_part[wave_id] = loss;
 }
 
-// Sum the per-wave partial rows into the decoder gradients (fixed order: deterministic),
-// and the loss parts into *loss_out.  One workgroup of 256 threads per 64 columns.
+// First stage of the decoder-gradient reduction: workgroup (cb, rb) sums rows
+// [rb * kRowBlock, (rb + 1) * kRowBlock) of the per-wave partial rows for 256 columns, in
+// row order, into stage row rb.  Fixed order throughout, so the result is deterministic.
+constexpr int kRowBlock = 64;
+__global__ __launch_bounds__(256) void k_reduce_rows(const float* __restrict__ partials, int rows,
+                                                      float* __restrict__ stage) {
+  const int col = blockIdx.x * 256 + threadIdx.x;
+  if (col >= NDGI_MLP_SIZE) return;
+  const int r0 = blockIdx.y * kRowBlock, r1 = min(rows, r0 + kRowBlock);
+  float acc = 0.0f;
+  int r = r0;
+  for (; r + 8 <= r1; r += 8) {
+    float v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = partials[(size_t)(r + k) * kPartialStride + col];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc += v[k];
+  }
+  for (; r < r1; ++r) acc += partials[(size_t)r * kPartialStride + col];
+  stage[(size_t)blockIdx.y * kPartialStride + col] = acc;
+}
+
+// Second stage: sum the stage rows into the decoder gradients (fixed order), and the loss
+// parts into *loss_out.  One workgroup of 256 threads per 64 columns.
 __global__ __launch_bounds__(256) void k_reduce_partials(const float* __restrict__ partials, int rows,
                                                           float* __restrict__ g_mlp, const double* __restrict__ loss_part,
-                                                          double scale, double* __restrict__ loss_out) {
+                                                          int loss_rows, double scale, double* __restrict__ loss_out) {
   __shared__ float red[4][64];
   const int c = threadIdx.x & 63, ph = threadIdx.x >> 6;
   const int col = blockIdx.x * 64 + c;
@@ -364,7 +386,7 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const float* __restrict
   if (blockIdx.x == 0 && loss_out) {
     __shared__ double lred[256];
     double l = 0.0;
-    for (int r = threadIdx.x; r < rows; r += 256) l += loss_part[r];
+    for (int r = threadIdx.x; r < loss_rows; r += 256) l += loss_part[r];
     lred[threadIdx.x] = l;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
@@ -599,8 +621,11 @@ int ndgi_train_step(ndgi_ctx* c, ndgi_train_state* st, const ndgi_batch* b, int3
     NDGI_HIP(hipGetLastError());
     if (mode != NDGI_TRAIN_FORWARD) {
       const bool want_loss = mode == NDGI_TRAIN_LOSS_GRAD || mode == NDGI_TRAIN_FUSED;
-      hipLaunchKernelGGL(k_reduce_partials, dim3((NDGI_MLP_SIZE + 63) / 64), dim3(256), 0, s, c->partials_dev,
-                         (int)(wgs * 4), st->grads + d.off_mlp, c->loss_part_dev, 1.0 / (3.0 * (double)b->n),
+      const int rows = (int)(wgs * 4), blocks = (rows + kRowBlock - 1) / kRowBlock;
+      hipLaunchKernelGGL(k_reduce_rows, dim3((NDGI_MLP_SIZE + 255) / 256, blocks), dim3(256), 0, s, c->partials_dev,
+                         rows, c->stage_dev);
+      hipLaunchKernelGGL(k_reduce_partials, dim3((NDGI_MLP_SIZE + 63) / 64), dim3(256), 0, s, c->stage_dev, blocks,
+                         st->grads + d.off_mlp, c->loss_part_dev, rows, 1.0 / (3.0 * (double)b->n),
                          want_loss ? loss_dev : nullptr);
       NDGI_HIP(hipGetLastError());
     }

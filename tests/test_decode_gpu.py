@@ -145,6 +145,20 @@ def test_binned_equals_direct_and_oracle(N, ctx, prec, tol, grid_dt):
     assert_rel(binned[ok], O.decode(m, q[ok]), tol, f"binned prec {prec}")
 
 
+@pytest.mark.parametrize("grid_dt", [np.float16, np.float32])
+def test_binned_long_time_axis(N, ctx, grid_dt):
+    """T = 64 keys: the tile's grid window over all keys exceeds the LDS budget, so the
+    decode reads nodes from HBM in time-key order; still the direct decode's bits."""
+    m = I.random_model(128, 96, 32, 24, 64, grid_dt, np.float16, config=57)
+    q = np.concatenate([I.uniform_queries(40000, I.rng(57, I.P_QUERY)), EDGE_Q])
+    for prec, tol in ((1, TOL16), (0, TOL32)):
+        direct = _dec(N, ctx, m, q, prec)
+        binned, _ = _dec_binned(N, ctx, m, q, prec)
+        np.testing.assert_array_equal(binned, direct)
+        sel = np.random.default_rng(57).integers(0, q.shape[0], 4096)
+        assert_rel(binned[sel], O.decode(m, q[sel]), tol, f"T=64 prec {prec}")
+
+
 @pytest.mark.parametrize("n", [1, 2, 63, 65, 1023, 1025, 4097])
 def test_binned_ragged_counts_reuse_workspace(N, ctx, n):
     """Counts around the wave (64) and chunk (1024) sizes; one workspace serves calls of
