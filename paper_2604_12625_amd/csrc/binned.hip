@@ -97,11 +97,11 @@ __global__ __launch_bounds__(256) void k_bin_colscan(int32_t* __restrict__ count
 
 // start[0..nbins) := exclusive prefix of the bin totals, start[nbins] := n;
 // items[b] := exclusive prefix of the work items per bin (ceil(count / kPiece)),
-// items[nbins] := total.  One workgroup of 1024 threads: the totals are staged in LDS
+// items[nbins] := total; item_bin[i] := the bin of work item i.  One workgroup of 1024 threads: the totals are staged in LDS
 // with coalesced loads, each thread scans a run of bins, the run sums are scanned across
 // the workgroup.
 __global__ __launch_bounds__(1024) void k_bin_starts(int32_t* __restrict__ start, int32_t* __restrict__ items,
-                                                     int nbins, int32_t n) {
+                                                     int32_t* __restrict__ item_bin, int nbins, int32_t n) {
   __shared__ int32_t tot[kMaxBins];
   __shared__ int32_t sh[1024], shi[1024];
   for (int i = threadIdx.x; i < nbins; i += 1024) tot[i] = start[i];
@@ -130,8 +130,10 @@ __global__ __launch_bounds__(1024) void k_bin_starts(int32_t* __restrict__ start
     const int32_t c = tot[i];
     tot[i] = run;
     items[i] = runi;
+    const int32_t pieces = (c + kPiece - 1) / kPiece;
+    for (int k = 0; k < pieces; ++k) item_bin[runi + k] = i;
     run += c;
-    runi += (c + kPiece - 1) / kPiece;
+    runi += pieces;
   }
   if (threadIdx.x == 1023) {
     start[nbins] = n;
@@ -230,163 +232,279 @@ __host__ __device__ __forceinline__ void node_window(int t0, int TS, int S, int 
 
 constexpr int kGridLdsBytes = 48 * 1024;   // LDS for a tile's grid window over all keys
 
-// Workgroups per CU that fit: the FP16 decoder at 4 waves per SIMD with the LDS of
-// 32-texel tiles and global grid reads; otherwise the compiler's choice.
-template <int PREC, int TSL, bool GLDS>
-constexpr int binned_waves() { return (PREC == NDGI_PREC_F16 && TSL == 5 && !GLDS) ? 4 : 1; }
+// Item order: workgroups are dispatched to the 8 XCDs round-robin, so workgroup ids
+// x, x+8, ... share one L2.  Each XCD takes one contiguous eighth of the items (tiles in
+// row-major order), so tiles processed side by side on an XCD share their halo lines in
+// its L2.  Small grids take items round-robin.
+struct ItemWalk {
+  int first, end, step;
+};
+__device__ __forceinline__ ItemWalk item_walk(int n_items) {
+  ItemWalk w;
+  if ((gridDim.x & 7) == 0 && n_items >= (int)gridDim.x) {
+    const int chunk = (n_items + 7) >> 3, xcd = blockIdx.x & 7;
+    w.first = xcd * chunk + ((int)blockIdx.x >> 3);
+    w.end = min(n_items, (xcd + 1) * chunk);
+    w.step = gridDim.x >> 3;
+  } else {
+    w.first = blockIdx.x;
+    w.end = n_items;
+    w.step = gridDim.x;
+  }
+  return w;
+}
 
-// Decode of the sorted queries.  Per work item the workgroup
-//  * decodes the tile region into LDS: R = TS + 4 texels a side (the tile plus one
-//    footprint of halo), 8 bytes per texel (channel c in byte c);
-//  * GLDS: stages the tile's grid window (all keys) in LDS, so the query loop reads no
-//    grid node from HBM;
-//    otherwise: orders the item's queries by their first time key with a counting sort in
-//    LDS (perm), so that the queries of a wave read one or two keys' window from cache;
-//  * runs the two-phase query decode over the item's queries.
-template <int PREC, int GDT, int TSL, bool GLDS>
-__global__ __launch_bounds__(256, (binned_waves<PREC, TSL, GLDS>())) void k_decode_binned(
+// Tile and query range of one work item.
+struct Item {
+  int64_t s_lo;     // first sorted query
+  int cnt;          // queries (1..kPiece)
+  int tx0, ty0;     // tile origin in texels
+};
+template <int TSL>
+__device__ __forceinline__ Item item_at(int it, const BinGeom& bg, const int32_t* __restrict__ start,
+                                        const int32_t* __restrict__ items, const int32_t* __restrict__ item_bin) {
+  const int b = item_bin[it];
+  Item I;
+  I.s_lo = (int64_t)start[b] + (int64_t)(it - items[b]) * kPiece;
+  I.cnt = (int)(min((int64_t)start[b + 1], I.s_lo + kPiece) - I.s_lo);
+  I.tx0 = (b % bg.ntx) << TSL;
+  I.ty0 = (b / bg.ntx) << TSL;
+  return I;
+}
+
+// Decoded spatial texels of the footprint (fx, fy) of a region, row pair rp, from its 64
+// block bytes: both rows, 8 bytes per texel (channel c in byte c), written to the region.
+template <int R>
+__device__ __forceinline__ void region_rows(uint2* reg, const uint4 blk[4], int fx, int fy, int rp) {
+  uint32_t r0[8], r1[8];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    bc4_rows(blk[h].x, blk[h].y, rp, r0[2 * h], r1[2 * h]);
+    bc4_rows(blk[h].z, blk[h].w, rp, r0[2 * h + 1], r1[2 * h + 1]);
+  }
+#pragma unroll
+  for (int rr = 0; rr < 2; ++rr) {
+    const uint32_t* r = rr ? r1 : r0;
+    uint32_t lo4[4], hi4[4];
+    transpose4(r[0], r[1], r[2], r[3], lo4);
+    transpose4(r[4], r[5], r[6], r[7], hi4);
+    uint4* d = (uint4*)(reg + (4 * fy + 2 * rp + rr) * R + 4 * fx);
+    d[0] = make_uint4(lo4[0], hi4[0], lo4[1], hi4[1]);
+    d[1] = make_uint4(lo4[2], hi4[2], lo4[3], hi4[3]);
+  }
+}
+
+// One pass of 64 sorted queries of a wave: two-phase decode, RGB to the original index.
+template <int PREC, int GDT, int R, typename GridFn>
+__device__ __forceinline__ void binned_pass(const Dec<PREC>& dec, const ndgi_model& m, const uint2* reg, int tx0,
+                                            int ty0, const float4& rec, bool live, float* feat, int lane,
+                                            GridFn grid, void* out) {
+  float sp[8], gr[8];
+  spatial8_lds(reg, R, tx0, ty0, coord_axis(rec.x, m.W), coord_axis(rec.y, m.H), sp);
+  grid(rec, gr);
+  wave_sync();
+  store_feats(feat, lane, sp, gr);
+  wave_sync();
+  const f4v acc = decode_feats<PREC>(dec, feat, lane >> 4, lane & 15);
+  if (live)
+    store_rgb<PREC>(out, (size_t)__builtin_bit_cast(uint32_t, rec.w), acc,
+                    !(isfinite(rec.x) && isfinite(rec.y) && isfinite(rec.z)));
+}
+
+// Decode of the sorted queries with the grid read from HBM (windows too large for LDS, or
+// 64-texel tiles).  Per work item the workgroup decodes the tile region into LDS (R = TS + 4
+// texels a side: the tile plus one footprint of halo, 8 bytes per texel), orders the
+// item's queries by their first time key with a counting sort in LDS (perm), so that a
+// wave's queries read one or two keys' grid window from cache, and runs the passes.
+template <int PREC, int TSL>
+constexpr int binned_waves() { return (PREC == NDGI_PREC_F16 && TSL == 5) ? 4 : 1; }
+
+template <int PREC, int GDT, int TSL>
+__global__ __launch_bounds__(256, (binned_waves<PREC, TSL>())) void k_decode_binned(
     ndgi_model m, BinGeom bg, const float4* __restrict__ sorted, const int32_t* __restrict__ start,
-    const int32_t* __restrict__ items, void* __restrict__ out) {
+    const int32_t* __restrict__ items, const int32_t* __restrict__ item_bin, void* __restrict__ out) {
   constexpr int TS = 1 << TSL;
   constexpr int R = TS + 4;
   constexpr int FP = R / 4;                      // footprints per region side
   constexpr int kTasks = FP * FP * 2;            // (footprint, row pair)
-  constexpr int kNodeU4 = GDT == NDGI_DTYPE_F16 ? 1 : 2;   // uint4 per grid node
-  constexpr int kWinU4 = GLDS ? kGridLdsBytes / 16 : 1;
   __shared__ uint2 reg[R * R];
   __shared__ float feat_all[4 * 64 * kFeatStride];
-  __shared__ uint16_t perm[GLDS ? 1 : kPiece];
-  __shared__ uint4 gwin[kWinU4];
+  __shared__ uint16_t perm[kPiece];
   // the key histogram lives only in the item prologue, when no wave uses its feature block
   int32_t* khist = (int32_t*)feat_all;
   static_assert(kMaxKeys * 4 <= 4 * 64 * kFeatStride * 4, "key histogram must fit the feature blocks");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int g = lane >> 4, j = lane & 15;
   float* feat = feat_all + wave * 64 * kFeatStride;
   Dec<PREC> dec;
   dec.load(m.mlp, m.mlp_dtype, lane);
-  const int nbins = bg.ntx * bg.nty;
-  const int n_items = items[nbins];
   const uint32_t bw = (uint32_t)m.W >> 2, bh = (uint32_t)m.H >> 2;
-  // Item order: workgroups are dispatched to the 8 XCDs round-robin, so workgroup ids
-  // x, x+8, ... share one L2.  Each XCD takes one contiguous eighth of the items (tiles in
-  // row-major order), so tiles processed side by side on an XCD share their halo lines in
-  // its L2.  Small grids take items round-robin.
-  const bool by_xcd = (gridDim.x & 7) == 0 && n_items >= (int)gridDim.x;
-  const int xcd = blockIdx.x & 7, per_xcd = gridDim.x >> 3;
-  const int chunk = (n_items + 7) >> 3;
-  const int it0 = by_xcd ? xcd * chunk + ((int)blockIdx.x >> 3) : (int)blockIdx.x;
-  const int it_end = by_xcd ? min(n_items, (xcd + 1) * chunk) : n_items;
-  const int it_step = by_xcd ? per_xcd : (int)gridDim.x;
-  for (int it = it0; it < it_end; it += it_step) {
-    // bin of this item: the last b with items[b] <= it (items is non-decreasing)
-    int lo = 0, hi = nbins;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (items[mid] <= it) lo = mid;
-      else hi = mid;
-    }
-    const int b = lo;
-    const int64_t s_lo = (int64_t)start[b] + (int64_t)(it - items[b]) * kPiece;
-    const int cnt = (int)(min((int64_t)start[b + 1], s_lo + kPiece) - s_lo);
-    const int tx0 = (b % bg.ntx) << TSL, ty0 = (b / bg.ntx) << TSL;
-    int wx0 = 0, wy0 = 0, nwx = 1, nwy = 1;
-    __syncthreads();     // the previous item's readers of reg, gwin, perm and khist are done
-    if constexpr (GLDS) {
-      int wx1, wy1;
-      node_window(tx0, TS, m.W, m.Gw, wx0, wx1);
-      node_window(ty0, TS, m.H, m.Gh, wy0, wy1);
-      nwx = wx1 - wx0 + 1;
-      nwy = wy1 - wy0 + 1;
-      const int total = m.T * nwy * nwx * kNodeU4;   // the host checked total <= kWinU4
-      const uint4* gsrc = (const uint4*)m.grid;
-      // 4 loads per thread in flight before their LDS stores
-#pragma unroll 1
-      for (int base = threadIdx.x; base < total; base += 256 * 4) {
-        uint4 v[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int idx = min(base + 256 * k, total - 1);
-          const int nd = idx / kNodeU4, part = idx - nd * kNodeU4;
-          const int key = nd / (nwy * nwx), rem = nd - key * (nwy * nwx);
-          const int gy = rem / nwx, gx = rem - gy * nwx;
-          v[k] = gsrc[(((uint32_t)key * (uint32_t)m.Gh + (uint32_t)(wy0 + gy)) * (uint32_t)m.Gw +
-                       (uint32_t)(wx0 + gx)) * kNodeU4 + part];
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          if (base + 256 * k < total) gwin[base + 256 * k] = v[k];
-      }
-    } else {
-      for (int i = threadIdx.x; i < m.T; i += 256) khist[i] = 0;
-    }
+  const ItemWalk walk = item_walk(items[bg.ntx * bg.nty]);
+  for (int it = walk.first; it < walk.end; it += walk.step) {
+    const Item I = item_at<TSL>(it, bg, start, items, item_bin);
+    __syncthreads();     // the previous item's readers of reg, perm and khist are done
+    for (int i = threadIdx.x; i < m.T; i += 256) khist[i] = 0;
 #pragma unroll 1
     for (int task = threadIdx.x; task < kTasks; task += 256) {
       const int rp = task & 1, f = task >> 1;
       const int fy = f / FP, fx = f - FP * fy;
-      const uint32_t gfx = (uint32_t)(tx0 >> 2) + fx, gfy = (uint32_t)(ty0 >> 2) + fy;
+      const uint32_t gfx = (uint32_t)(I.tx0 >> 2) + fx, gfy = (uint32_t)(I.ty0 >> 2) + fy;
       if (gfx < bw && gfy < bh) {
         const uint4* fp = (const uint4*)(m.bc4 + (gfy * bw + gfx) * 64u);
-        uint32_t r0[8], r1[8];
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-          const uint4 blk = fp[h];
-          bc4_rows(blk.x, blk.y, rp, r0[2 * h], r1[2 * h]);
-          bc4_rows(blk.z, blk.w, rp, r0[2 * h + 1], r1[2 * h + 1]);
-        }
-#pragma unroll
-        for (int rr = 0; rr < 2; ++rr) {
-          const uint32_t* r = rr ? r1 : r0;
-          uint32_t lo4[4], hi4[4];
-          transpose4(r[0], r[1], r[2], r[3], lo4);
-          transpose4(r[4], r[5], r[6], r[7], hi4);
-          uint4* d = (uint4*)(reg + (4 * fy + 2 * rp + rr) * R + 4 * fx);
-          d[0] = make_uint4(lo4[0], hi4[0], lo4[1], hi4[1]);
-          d[1] = make_uint4(lo4[2], hi4[2], lo4[3], hi4[3]);
-        }
+        const uint4 blk[4] = {fp[0], fp[1], fp[2], fp[3]};
+        region_rows<R>(reg, blk, fx, fy, rp);
       }
     }
-    if constexpr (!GLDS) {
-      __syncthreads();     // khist zeroed
-      // keys are recomputed in the scatter pass rather than kept: registers hold the decoder
+    __syncthreads();     // khist zeroed
+    // keys are recomputed in the scatter pass rather than kept: registers hold the decoder
 #pragma unroll 1
-      for (int i = threadIdx.x; i < cnt; i += 256) atomicAdd(&khist[make_keys(sorted[s_lo + i].z, m.T).k0], 1);
-      __syncthreads();
-      if (wave == 0) wave_exclusive_scan(khist, m.T, lane);
-      __syncthreads();
+    for (int i = threadIdx.x; i < I.cnt; i += 256) atomicAdd(&khist[make_keys(sorted[I.s_lo + i].z, m.T).k0], 1);
+    __syncthreads();
+    if (wave == 0) wave_exclusive_scan(khist, m.T, lane);
+    __syncthreads();
 #pragma unroll 1
-      for (int i = threadIdx.x; i < cnt; i += 256)
-        perm[atomicAdd(&khist[make_keys(sorted[s_lo + i].z, m.T).k0], 1)] = (uint16_t)i;
-    }
-    __syncthreads();     // reg, gwin and perm complete
-    // the record of the wave's next pass is loaded while this pass computes
-    auto record = [&](int i) {
-      const int c = min(i, cnt - 1);
-      return sorted[s_lo + (GLDS ? c : (int)perm[c])];
-    };
+    for (int i = threadIdx.x; i < I.cnt; i += 256)
+      perm[atomicAdd(&khist[make_keys(sorted[I.s_lo + i].z, m.T).k0], 1)] = (uint16_t)i;
+    __syncthreads();     // reg and perm complete
+    auto record = [&](int i) { return sorted[I.s_lo + perm[min(i, I.cnt - 1)]]; };
     float4 next = record(64 * wave + lane);
-    for (int p0 = 64 * wave; p0 < cnt; p0 += 256) {
-      const int mine = p0 + lane;
+    for (int p0 = 64 * wave; p0 < I.cnt; p0 += 256) {
       const float4 rec = next;
-      if (p0 + 256 < cnt) next = record(mine + 256);
-      float sp[8], gr[8];
-      spatial8_lds(reg, R, tx0, ty0, coord_axis(rec.x, m.W), coord_axis(rec.y, m.H), sp);
-      if constexpr (GLDS) {
-        // window-local node; the clamp only guards the LDS bounds
-        query_grid8_at<GDT>(m, rec.x, rec.y, rec.z, [&](int key, int gy, int gx) {
-          const int ly = min(max(gy - wy0, 0), nwy - 1), lx = min(max(gx - wx0, 0), nwx - 1);
-          return (const uint4*)&gwin[((key * nwy + ly) * nwx + lx) * kNodeU4];
-        }, gr);
-      } else {
-        query_grid8<GDT>(m, rec.x, rec.y, rec.z, gr);
-      }
-      wave_sync();
-      store_feats(feat, lane, sp, gr);
-      wave_sync();
-      const f4v acc = decode_feats<PREC>(dec, feat, g, j);
-      if (mine < cnt)
-        store_rgb<PREC>(out, (size_t)__builtin_bit_cast(uint32_t, rec.w), acc,
-                        !(isfinite(rec.x) && isfinite(rec.y) && isfinite(rec.z)));
+      if (p0 + 256 < I.cnt) next = record(p0 + 256 + lane);
+      binned_pass<PREC, GDT, R>(dec, m, reg, I.tx0, I.ty0, rec, p0 + lane < I.cnt, feat, lane,
+                                [&](const float4& q, float* gr) { query_grid8<GDT>(m, q.x, q.y, q.z, gr); }, out);
+    }
+  }
+}
+
+// Grid-node window of a tile (both axes).
+struct Win {
+  int x0, y0, nx, ny;
+};
+template <int TS>
+__device__ __forceinline__ Win tile_window(const ndgi_model& m, const Item& I) {
+  Win w;
+  int x1, y1;
+  node_window(I.tx0, TS, m.W, m.Gw, w.x0, x1);
+  node_window(I.ty0, TS, m.H, m.Gh, w.y0, y1);
+  w.nx = x1 - w.x0 + 1;
+  w.ny = y1 - w.y0 + 1;
+  return w;
+}
+
+constexpr int kWinU4 = kGridLdsBytes / 16;
+constexpr int kWinPer = kWinU4 / 256;          // window uint4 per thread
+// staging registers use native vectors (arrays of HIP's uint4 wrapper stay in scratch)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Issue this thread's loads for an item: its share of the grid window (node-major over
+// keys, rows, columns), the 64 bytes of its region footprint, and its wave's first record.
+template <int GDT, int FP, int kTasks>
+__device__ __forceinline__ void stage_fetch(const ndgi_model& m, const Item& I, const Win& w,
+                                            const float4* __restrict__ sorted, u32x4 (&wv)[kWinPer],
+                                            u32x4 (&blk)[4], float4& rec0, int fx, int fy, int wave, int lane) {
+  constexpr int kNodeU4 = GDT == NDGI_DTYPE_F16 ? 1 : 2;
+  const u32x4* gsrc = (const u32x4*)m.grid;
+  const int total = m.T * w.ny * w.nx * kNodeU4;   // the host checked total <= kWinU4
+#pragma unroll
+  for (int k = 0; k < kWinPer; ++k) {
+    const int idx = min((int)threadIdx.x + 256 * k, total - 1);
+    const int nd = idx / kNodeU4, part = idx - nd * kNodeU4;
+    const int key = nd / (w.ny * w.nx), rem = nd - key * (w.ny * w.nx);
+    const int gy = rem / w.nx, gx = rem - gy * w.nx;
+    wv[k] = gsrc[(((uint32_t)key * (uint32_t)m.Gh + (uint32_t)(w.y0 + gy)) * (uint32_t)m.Gw +
+                  (uint32_t)(w.x0 + gx)) * kNodeU4 + part];
+  }
+  const uint32_t bw = (uint32_t)m.W >> 2, bh = (uint32_t)m.H >> 2;
+  const uint32_t gfx = min((uint32_t)(I.tx0 >> 2) + fx, bw - 1), gfy = min((uint32_t)(I.ty0 >> 2) + fy, bh - 1);
+  const u32x4* fp = (const u32x4*)(m.bc4 + (gfy * bw + gfx) * 64u);
+#pragma unroll
+  for (int h = 0; h < 4; ++h) blk[h] = fp[h];
+  rec0 = sorted[I.s_lo + min(64 * wave + lane, I.cnt - 1)];
+}
+
+// Write the staged item to LDS: the grid window, and the decoded region rows of this
+// thread's task (tasks whose footprint lies outside the map write nothing).
+template <int GDT, int R, int kTasks>
+__device__ __forceinline__ void stage_commit(const ndgi_model& m, const Item& I, const Win& w,
+                                             const u32x4 (&wv)[kWinPer], const u32x4 (&blk)[4], u32x4* gwin,
+                                             uint2* reg, int fx, int fy, int rp) {
+  constexpr int kNodeU4 = GDT == NDGI_DTYPE_F16 ? 1 : 2;
+  const int total = m.T * w.ny * w.nx * kNodeU4;
+#pragma unroll
+  for (int k = 0; k < kWinPer; ++k) {
+    const int idx = (int)threadIdx.x + 256 * k;
+    if (idx < total) gwin[idx] = wv[k];
+  }
+  const uint32_t gfx = (uint32_t)(I.tx0 >> 2) + fx, gfy = (uint32_t)(I.ty0 >> 2) + fy;
+  if ((int)threadIdx.x < kTasks && gfx < ((uint32_t)m.W >> 2) && gfy < ((uint32_t)m.H >> 2)) {
+    const uint4 b4[4] = {make_uint4(blk[0].x, blk[0].y, blk[0].z, blk[0].w),
+                         make_uint4(blk[1].x, blk[1].y, blk[1].z, blk[1].w),
+                         make_uint4(blk[2].x, blk[2].y, blk[2].z, blk[2].w),
+                         make_uint4(blk[3].x, blk[3].y, blk[3].z, blk[3].w)};
+    region_rows<R>(reg, b4, fx, fy, rp);
+  }
+}
+
+// Decode of the sorted queries with the tile's grid window (all keys) staged in LDS, for
+// 32-texel tiles whose window fits kGridLdsBytes.  The staging is double-buffered through
+// registers: while the queries of item i decode, each thread already holds its share of
+// item i+1's window, BC4 blocks and first query record in flight, and writes them to LDS
+// after the barrier that ends item i.
+template <int PREC, int GDT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_decode_binned_lds(
+    ndgi_model m, BinGeom bg, const float4* __restrict__ sorted, const int32_t* __restrict__ start,
+    const int32_t* __restrict__ items, const int32_t* __restrict__ item_bin, void* __restrict__ out) {
+  constexpr int TSL = 5, TS = 32, R = TS + 4, FP = R / 4;
+  constexpr int kTasks = FP * FP * 2;            // (footprint, row pair): 162 <= 256 threads
+  static_assert(kTasks <= 256, "one region task per thread");
+  constexpr int kNodeU4 = GDT == NDGI_DTYPE_F16 ? 1 : 2;   // uint4 per grid node
+  __shared__ uint2 reg[R * R];
+  __shared__ float feat_all[4 * 64 * kFeatStride];
+  __shared__ u32x4 gwin[kWinU4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float* feat = feat_all + wave * 64 * kFeatStride;
+  Dec<PREC> dec;
+  dec.load(m.mlp, m.mlp_dtype, lane);
+  const ItemWalk walk = item_walk(items[bg.ntx * bg.nty]);
+  // this thread's region task
+  const int rp = threadIdx.x & 1, f = threadIdx.x >> 1;
+  const int fy = f / FP, fx = f - FP * fy;
+
+  // staging registers for the next item
+  u32x4 wv[kWinPer], blk[4];
+  float4 rec0;
+  int it = walk.first;
+  Item cur{};
+  Win cw{};
+  if (it < walk.end) {
+    cur = item_at<TSL>(it, bg, start, items, item_bin);
+    cw = tile_window<TS>(m, cur);
+    stage_fetch<GDT, FP, kTasks>(m, cur, cw, sorted, wv, blk, rec0, fx, fy, wave, lane);
+  }
+  for (; it < walk.end; it += walk.step) {
+    __syncthreads();     // the previous item's readers of reg and gwin are done
+    stage_commit<GDT, R, kTasks>(m, cur, cw, wv, blk, gwin, reg, fx, fy, rp);
+    float4 next = rec0;
+    const Item I = cur;
+    const Win w = cw;
+    __syncthreads();     // reg and gwin complete
+    if (it + walk.step < walk.end) {     // start the next item's loads
+      cur = item_at<TSL>(it + walk.step, bg, start, items, item_bin);
+      cw = tile_window<TS>(m, cur);
+      stage_fetch<GDT, FP, kTasks>(m, cur, cw, sorted, wv, blk, rec0, fx, fy, wave, lane);
+    }
+    for (int p0 = 64 * wave; p0 < I.cnt; p0 += 256) {
+      const float4 rec = next;
+      if (p0 + 256 < I.cnt) next = sorted[I.s_lo + min(p0 + 256 + lane, I.cnt - 1)];
+      // window-local node; the clamp only guards the LDS bounds
+      binned_pass<PREC, GDT, R>(dec, m, reg, I.tx0, I.ty0, rec, p0 + lane < I.cnt, feat, lane,
+                                [&](const float4& q, float* gr) {
+                                  query_grid8_at<GDT>(m, q.x, q.y, q.z, [&](int key, int gy, int gx) {
+                                    const int ly = min(max(gy - w.y0, 0), w.ny - 1);
+                                    const int lx = min(max(gx - w.x0, 0), w.nx - 1);
+                                    return (const uint4*)&gwin[((key * w.ny + ly) * w.nx + lx) * kNodeU4];
+                                  }, gr);
+                                }, out);
     }
   }
 }
@@ -409,7 +527,8 @@ static int64_t max_window_u4(const ndgi_model& m, const BinGeom& bg) {
 struct BinnedLayout {
   BinGeom bg;
   int nbins;
-  int64_t counts_off, start_off, items_off, sorted_off, bytes;
+  int64_t max_items;
+  int64_t counts_off, start_off, items_off, item_bin_off, sorted_off, bytes;
 };
 
 static int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
@@ -420,7 +539,10 @@ static bool binned_layout(const ndgi_model& m, int64_t n, BinnedLayout& L) {
   L.counts_off = 0;
   L.start_off = align256((int64_t)kSortWgs * L.nbins * 4);
   L.items_off = L.start_off + align256((int64_t)(L.nbins + 1) * 4);
-  L.sorted_off = L.items_off + align256((int64_t)(L.nbins + 1) * 4);
+  // at most one item per kPiece queries plus one per bin
+  L.max_items = n / kPiece + L.nbins;
+  L.item_bin_off = L.items_off + align256((int64_t)(L.nbins + 1) * 4);
+  L.sorted_off = L.item_bin_off + align256(L.max_items * 4);
   L.bytes = L.sorted_off + n * 16;
   return true;
 }
@@ -447,31 +569,29 @@ int launch_decode_binned(ndgi_ctx* ctx, const ndgi_model& m, const float* uvt, i
   int32_t* counts = (int32_t*)((char*)ws + L.counts_off);
   int32_t* start = (int32_t*)((char*)ws + L.start_off);
   int32_t* items = (int32_t*)((char*)ws + L.items_off);
+  int32_t* item_bin = (int32_t*)((char*)ws + L.item_bin_off);
   float4* sorted = (float4*)((char*)ws + L.sorted_off);
   const int64_t slice = (n + kSortWgs - 1) / kSortWgs;
   hipLaunchKernelGGL(k_bin_count, dim3(kSortWgs), dim3(kSortThreads), 0, s, m, L.bg, uvt, n, slice, counts);
   hipLaunchKernelGGL(k_bin_colscan, dim3((L.nbins + 255) / 256), dim3(256), 0, s, counts, L.nbins, start);
-  hipLaunchKernelGGL(k_bin_starts, dim3(1), dim3(1024), 0, s, start, items, L.nbins, (int32_t)n);
+  hipLaunchKernelGGL(k_bin_starts, dim3(1), dim3(1024), 0, s, start, items, item_bin, L.nbins, (int32_t)n);
   hipLaunchKernelGGL(k_bin_scatter, dim3(kSortWgs), dim3(kSortThreads), 0, s, m, L.bg, uvt, n, slice, counts, start,
                      sorted);
   NDGI_HIP(hipGetLastError());
   const bool g16 = m.grid_dtype == NDGI_DTYPE_F16;
-  // at most one item per kPiece queries plus one per bin
-  const int64_t max_items = n / kPiece + L.nbins;
   // grid window in LDS when it fits (32-texel tiles only)
   const bool glds = L.bg.ts_log2 == 5 && max_window_u4(m, L.bg) * 16 <= kGridLdsBytes;
-#define NDGI_BINNED(P, G, TSL, GL)                                                                               \
-  do {                                                                                                             \
-    int64_t wgs = resident_wgs(ctx, (const void*)k_decode_binned<P, G, TSL, GL>);                                  \
-    if (wgs > max_items) wgs = max_items;                                                                          \
-    hipLaunchKernelGGL((k_decode_binned<P, G, TSL, GL>), dim3((unsigned)wgs), dim3(256), 0, s, m, L.bg, sorted,     \
-                       start, items, out);                                                                         \
+#define NDGI_BINNED_KERNEL(K)                                                                             \
+  do {                                                                                                    \
+    int64_t wgs = resident_wgs(ctx, (const void*)K);                                                      \
+    if (wgs > L.max_items) wgs = L.max_items;                                                             \
+    hipLaunchKernelGGL(K, dim3((unsigned)wgs), dim3(256), 0, s, m, L.bg, sorted, start, items, item_bin, out); \
   } while (0)
-#define NDGI_BINNED_TS(P, G)                                 \
-  do {                                                       \
-    if (L.bg.ts_log2 == 5 && glds) NDGI_BINNED(P, G, 5, true); \
-    else if (L.bg.ts_log2 == 5) NDGI_BINNED(P, G, 5, false);   \
-    else NDGI_BINNED(P, G, 6, false);                          \
+#define NDGI_BINNED_TS(P, G)                                              \
+  do {                                                                    \
+    if (glds) NDGI_BINNED_KERNEL((k_decode_binned_lds<P, G>));            \
+    else if (L.bg.ts_log2 == 5) NDGI_BINNED_KERNEL((k_decode_binned<P, G, 5>)); \
+    else NDGI_BINNED_KERNEL((k_decode_binned<P, G, 6>));                  \
   } while (0)
   if (prec == NDGI_PREC_F16) {
     if (g16) NDGI_BINNED_TS(NDGI_PREC_F16, NDGI_DTYPE_F16);
@@ -481,7 +601,7 @@ int launch_decode_binned(ndgi_ctx* ctx, const ndgi_model& m, const float* uvt, i
     else NDGI_BINNED_TS(NDGI_PREC_F32, NDGI_DTYPE_F32);
   }
 #undef NDGI_BINNED_TS
-#undef NDGI_BINNED
+#undef NDGI_BINNED_KERNEL
   NDGI_HIP(hipGetLastError());
   return NDGI_OK;
 }
