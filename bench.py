@@ -331,7 +331,7 @@ def main():
                    peak=HBM_PEAK_GBS, unit="GB/s",
                    traffic=measured_traffic("random_f16_" + args.random_path),
                    kernel=("ndgi_decode_binned (k_bin_count, k_bin_colscan, k_bin_starts, k_bin_scatter, "
-                           "k_decode_binned<FP16>)" if args.random_path == "binned" else "k_decode_query<FP16>"),
+                           "k_decode_binned_lds<FP16>)" if args.random_path == "binned" else "k_decode_query<FP16>"),
                    bytes_per_launch=RANDOM_COMPULSORY_BYTES)
     rl_rand["frac"] = rl_rand["achieved"] / HBM_PEAK_GBS
     dominant = rl_rand if f16["random_ms"] >= f16["frame_ms"] else rl_frame
