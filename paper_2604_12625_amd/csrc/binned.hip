@@ -18,6 +18,7 @@
 namespace ndgi {
 
 constexpr int kSortWgs = 256;       // workgroups of the counting sort (1024 threads each)
+static_assert(kSortWgs % 8 == 0, "sort slices are spread evenly over the 8 XCDs");
 constexpr int kBatch = 8;           // queries per thread whose loads are in flight together
 constexpr int kSortThreads = 1024;
 constexpr int kMaxBins = 16384;     // LDS histogram capacity (64 KiB)
@@ -46,7 +47,16 @@ __device__ __forceinline__ int query_bin(float u, float v, const ndgi_model& m, 
   return (ay.i0 >> bg.ts_log2) * bg.ntx + (ax.i0 >> bg.ts_log2);
 }
 
-// counts[wg][bin] = queries of sort workgroup wg (a contiguous slice of `slice` queries)
+// Slice of the queries handled by a sort workgroup.  Workgroups are dispatched to the 8
+// XCDs round-robin; slices are numbered so that each XCD takes kSortWgs / 8 consecutive
+// slices.  A bin's records are stored slice after slice, so neighbouring slices' short
+// runs share cache lines, which then fill up in one L2 instead of being written back
+// half-full from two.
+__device__ __forceinline__ int sort_slice() {
+  return (int)(blockIdx.x & 7) * (kSortWgs / 8) + (int)(blockIdx.x >> 3);
+}
+
+// counts[s][bin] = queries of slice s (a contiguous run of `slice` queries)
 // that fall in bin.
 __global__ __launch_bounds__(kSortThreads) void k_bin_count(ndgi_model m, BinGeom bg, const float* __restrict__ uvt,
                                                             int64_t n, int64_t slice, int32_t* __restrict__ counts) {
@@ -54,7 +64,8 @@ __global__ __launch_bounds__(kSortThreads) void k_bin_count(ndgi_model m, BinGeo
   const int nbins = bg.ntx * bg.nty;
   for (int i = threadIdx.x; i < nbins; i += kSortThreads) hist[i] = 0;
   __syncthreads();
-  const int64_t lo = (int64_t)blockIdx.x * slice, hi = min(n, lo + slice);
+  const int sl = sort_slice();
+  const int64_t lo = (int64_t)sl * slice, hi = min(n, lo + slice);
   // loads of kBatch queries are issued before any is used, so they are in flight together
   for (int64_t base = lo + threadIdx.x; base < hi; base += kSortThreads * kBatch) {
     float u[kBatch], v[kBatch];
@@ -69,7 +80,7 @@ __global__ __launch_bounds__(kSortThreads) void k_bin_count(ndgi_model m, BinGeo
       if (base + (int64_t)kSortThreads * k < hi) atomicAdd(&hist[query_bin(u[k], v[k], m, bg)], 1);
   }
   __syncthreads();
-  int32_t* row = counts + (int64_t)blockIdx.x * nbins;
+  int32_t* row = counts + (int64_t)sl * nbins;
   for (int i = threadIdx.x; i < nbins; i += kSortThreads) row[i] = hist[i];
 }
 
@@ -153,10 +164,11 @@ __global__ __launch_bounds__(kSortThreads) void k_bin_scatter(ndgi_model m, BinG
                                                               float4* __restrict__ sorted) {
   __shared__ int32_t pos[kMaxBins];
   const int nbins = bg.ntx * bg.nty;
-  const int32_t* row = counts + (int64_t)blockIdx.x * nbins;
+  const int sl = sort_slice();
+  const int32_t* row = counts + (int64_t)sl * nbins;
   for (int i = threadIdx.x; i < nbins; i += kSortThreads) pos[i] = start[i] + row[i];
   __syncthreads();
-  const int64_t lo = (int64_t)blockIdx.x * slice, hi = min(n, lo + slice);
+  const int64_t lo = (int64_t)sl * slice, hi = min(n, lo + slice);
   for (int64_t base = lo + threadIdx.x; base < hi; base += kSortThreads * kBatch) {
     float u[kBatch], v[kBatch], t[kBatch];
 #pragma unroll
@@ -230,7 +242,7 @@ __host__ __device__ __forceinline__ void node_window(int t0, int TS, int S, int 
   hi = min((int)floorf(qhi + 0.01f) + 1, G - 1);
 }
 
-constexpr int kGridLdsBytes = 48 * 1024;   // LDS for a tile's grid window over all keys
+constexpr int kGridLdsBytes = 40 * 1024;   // LDS for a tile's grid window over all keys
 
 // Item order: workgroups are dispatched to the 8 XCDs round-robin, so workgroup ids
 // x, x+8, ... share one L2.  Each XCD takes one contiguous eighth of the items (tiles in
@@ -297,15 +309,11 @@ __device__ __forceinline__ void region_rows(uint2* reg, const uint4 blk[4], int 
 // One pass of 64 sorted queries of a wave: two-phase decode, RGB to the original index.
 template <int PREC, int GDT, int R, typename GridFn>
 __device__ __forceinline__ void binned_pass(const Dec<PREC>& dec, const ndgi_model& m, const uint2* reg, int tx0,
-                                            int ty0, const float4& rec, bool live, float* feat, int lane,
-                                            GridFn grid, void* out) {
+                                            int ty0, const float4& rec, bool live, GridFn grid, void* out) {
   float sp[8], gr[8];
   spatial8_lds(reg, R, tx0, ty0, coord_axis(rec.x, m.W), coord_axis(rec.y, m.H), sp);
   grid(rec, gr);
-  wave_sync();
-  store_feats(feat, lane, sp, gr);
-  wave_sync();
-  const f4v acc = decode_feats<PREC>(dec, feat, lane >> 4, lane & 15);
+  const f4v acc = decode_regs<PREC>(dec, sp, gr);
   if (live)
     store_rgb<PREC>(out, (size_t)__builtin_bit_cast(uint32_t, rec.w), acc,
                     !(isfinite(rec.x) && isfinite(rec.y) && isfinite(rec.z)));
@@ -328,13 +336,9 @@ __global__ __launch_bounds__(256, (binned_waves<PREC, TSL>())) void k_decode_bin
   constexpr int FP = R / 4;                      // footprints per region side
   constexpr int kTasks = FP * FP * 2;            // (footprint, row pair)
   __shared__ uint2 reg[R * R];
-  __shared__ float feat_all[4 * 64 * kFeatStride];
   __shared__ uint16_t perm[kPiece];
-  // the key histogram lives only in the item prologue, when no wave uses its feature block
-  int32_t* khist = (int32_t*)feat_all;
-  static_assert(kMaxKeys * 4 <= 4 * 64 * kFeatStride * 4, "key histogram must fit the feature blocks");
+  __shared__ int32_t khist[kMaxKeys];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  float* feat = feat_all + wave * 64 * kFeatStride;
   Dec<PREC> dec;
   dec.load(m.mlp, m.mlp_dtype, lane);
   const uint32_t bw = (uint32_t)m.W >> 2, bh = (uint32_t)m.H >> 2;
@@ -370,7 +374,7 @@ __global__ __launch_bounds__(256, (binned_waves<PREC, TSL>())) void k_decode_bin
     for (int p0 = 64 * wave; p0 < I.cnt; p0 += 256) {
       const float4 rec = next;
       if (p0 + 256 < I.cnt) next = record(p0 + 256 + lane);
-      binned_pass<PREC, GDT, R>(dec, m, reg, I.tx0, I.ty0, rec, p0 + lane < I.cnt, feat, lane,
+      binned_pass<PREC, GDT, R>(dec, m, reg, I.tx0, I.ty0, rec, p0 + lane < I.cnt,
                                 [&](const float4& q, float* gr) { query_grid8<GDT>(m, q.x, q.y, q.z, gr); }, out);
     }
   }
@@ -446,12 +450,12 @@ __device__ __forceinline__ void stage_commit(const ndgi_model& m, const Item& I,
 }
 
 // Decode of the sorted queries with the tile's grid window (all keys) staged in LDS, for
-// 32-texel tiles whose window fits kGridLdsBytes.  The staging is double-buffered through
-// registers: while the queries of item i decode, each thread already holds its share of
-// item i+1's window, BC4 blocks and first query record in flight, and writes them to LDS
-// after the barrier that ends item i.
+// 32-texel tiles whose window fits kGridLdsBytes.  Per item the workgroup stages the window
+// and the decoded region (each thread's loads issued together, then written to LDS); the
+// query loop then reads only its records from HBM.  With about 50 KB of LDS, three
+// workgroups share a CU, so one workgroup's staging overlaps the others' decoding.
 template <int PREC, int GDT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_decode_binned_lds(
+__global__ __launch_bounds__(256) void k_decode_binned_lds(
     ndgi_model m, BinGeom bg, const float4* __restrict__ sorted, const int32_t* __restrict__ start,
     const int32_t* __restrict__ items, const int32_t* __restrict__ item_bin, void* __restrict__ out) {
   constexpr int TSL = 5, TS = 32, R = TS + 4, FP = R / 4;
@@ -459,45 +463,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   static_assert(kTasks <= 256, "one region task per thread");
   constexpr int kNodeU4 = GDT == NDGI_DTYPE_F16 ? 1 : 2;   // uint4 per grid node
   __shared__ uint2 reg[R * R];
-  __shared__ float feat_all[4 * 64 * kFeatStride];
   __shared__ u32x4 gwin[kWinU4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  float* feat = feat_all + wave * 64 * kFeatStride;
   Dec<PREC> dec;
   dec.load(m.mlp, m.mlp_dtype, lane);
   const ItemWalk walk = item_walk(items[bg.ntx * bg.nty]);
   // this thread's region task
   const int rp = threadIdx.x & 1, f = threadIdx.x >> 1;
   const int fy = f / FP, fx = f - FP * fy;
-
-  // staging registers for the next item
-  u32x4 wv[kWinPer], blk[4];
-  float4 rec0;
-  int it = walk.first;
-  Item cur{};
-  Win cw{};
-  if (it < walk.end) {
-    cur = item_at<TSL>(it, bg, start, items, item_bin);
-    cw = tile_window<TS>(m, cur);
-    stage_fetch<GDT, FP, kTasks>(m, cur, cw, sorted, wv, blk, rec0, fx, fy, wave, lane);
-  }
-  for (; it < walk.end; it += walk.step) {
+  for (int it = walk.first; it < walk.end; it += walk.step) {
+    const Item I = item_at<TSL>(it, bg, start, items, item_bin);
+    const Win w = tile_window<TS>(m, I);
+    u32x4 wv[kWinPer], blk[4];
+    float4 rec;
     __syncthreads();     // the previous item's readers of reg and gwin are done
-    stage_commit<GDT, R, kTasks>(m, cur, cw, wv, blk, gwin, reg, fx, fy, rp);
-    float4 next = rec0;
-    const Item I = cur;
-    const Win w = cw;
+    stage_fetch<GDT, FP, kTasks>(m, I, w, sorted, wv, blk, rec, fx, fy, wave, lane);
+    stage_commit<GDT, R, kTasks>(m, I, w, wv, blk, gwin, reg, fx, fy, rp);
     __syncthreads();     // reg and gwin complete
-    if (it + walk.step < walk.end) {     // start the next item's loads
-      cur = item_at<TSL>(it + walk.step, bg, start, items, item_bin);
-      cw = tile_window<TS>(m, cur);
-      stage_fetch<GDT, FP, kTasks>(m, cur, cw, sorted, wv, blk, rec0, fx, fy, wave, lane);
-    }
     for (int p0 = 64 * wave; p0 < I.cnt; p0 += 256) {
-      const float4 rec = next;
-      if (p0 + 256 < I.cnt) next = sorted[I.s_lo + min(p0 + 256 + lane, I.cnt - 1)];
+      const float4 cur = rec;
+      if (p0 + 256 < I.cnt) rec = sorted[I.s_lo + min(p0 + 256 + lane, I.cnt - 1)];
       // window-local node; the clamp only guards the LDS bounds
-      binned_pass<PREC, GDT, R>(dec, m, reg, I.tx0, I.ty0, rec, p0 + lane < I.cnt, feat, lane,
+      binned_pass<PREC, GDT, R>(dec, m, reg, I.tx0, I.ty0, cur, p0 + lane < I.cnt,
                                 [&](const float4& q, float* gr) {
                                   query_grid8_at<GDT>(m, q.x, q.y, q.z, [&](int key, int gy, int gx) {
                                     const int ly = min(max(gy - w.y0, 0), w.ny - 1);

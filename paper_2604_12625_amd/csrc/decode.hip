@@ -30,15 +30,12 @@ int launch_bc4_blocks(const uint8_t* blocks, int64_t n, uint8_t* out, hipStream_
 }
 
 // ------------------------------------------------------------------- query decode
-// Each wave takes passes of 64 consecutive queries (phase A: one query per lane into the
-// wave's LDS block; phase B: the decoder); 4 waves per workgroup; grid-stride.
+// Each wave takes passes of 64 consecutive queries (phase A: one query per lane; phase B:
+// the decoder after the register handoff); 4 waves per workgroup; grid-stride.
 template <int PREC, int GDT>
 __global__ __launch_bounds__(256) void k_decode_query(ndgi_model m, const float* __restrict__ uvt, int64_t n,
                                                        void* __restrict__ out) {
-  __shared__ float feat_all[4 * 64 * kFeatStride];
   const int lane = threadIdx.x & 63;
-  const int g = lane >> 4, j = lane & 15;
-  float* feat = feat_all + (threadIdx.x >> 6) * 64 * kFeatStride;
   Dec<PREC> dec;
   dec.load(m.mlp, m.mlp_dtype, lane);
   const int64_t passes = (n + 63) >> 6;
@@ -55,10 +52,7 @@ __global__ __launch_bounds__(256) void k_decode_query(ndgi_model m, const float*
     float sp[8], gr[8];
     spatial8_global(m, coord_axis(u, m.W), coord_axis(v, m.H), sp);
     query_grid8<GDT>(m, u, v, t, gr);
-    wave_sync();                      // the previous pass's phase B reads are done
-    store_feats(feat, lane, sp, gr);
-    wave_sync();
-    const f4v acc = decode_feats<PREC>(dec, feat, g, j);
+    const f4v acc = decode_regs<PREC>(dec, sp, gr);
     if (mine < n) store_rgb<PREC>(out, (size_t)mine, acc, !(isfinite(u) && isfinite(v) && isfinite(t)));
   }
 }

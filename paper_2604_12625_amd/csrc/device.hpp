@@ -366,6 +366,41 @@ __device__ __forceinline__ void spatial8_lds(const uint2* reg, int R, int tx0, i
   for (int c = 0; c < 8; ++c) x[c] *= (1.0f / 255.0f);
 }
 
+// Phase A -> B handoff in registers.  Lane l holds chunk c = {S_2c, S_2c+1, G_2c, G_2c+1}
+// of its own query in r[c].  Viewing the wave as 4 rows of 16 lanes, the handoff is a 4 x 4
+// transpose of chunks across rows: two v_permlane32_swap (rows 0,1 <-> 2,3) and two
+// v_permlane16_swap (rows 0 <-> 1, 2 <-> 3) per chunk element.  Afterwards lane (g, j)
+// holds in r[q] chunk g of query 16q + j, i.e. the decoder's K share for group q.
+__device__ __forceinline__ void swap32(float& a, float& b) {
+  const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  a = __uint_as_float(p[0]);
+  b = __uint_as_float(p[1]);
+}
+__device__ __forceinline__ void swap16(float& a, float& b) {
+  const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  a = __uint_as_float(p[0]);
+  b = __uint_as_float(p[1]);
+}
+__device__ __forceinline__ void transpose_chunks(const float sp[8], const float gr[8], float r[4][4]) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    r[c][0] = sp[2 * c];
+    r[c][1] = sp[2 * c + 1];
+    r[c][2] = gr[2 * c];
+    r[c][3] = gr[2 * c + 1];
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    swap32(r[0][e], r[2][e]);   // rows 2,3 of r[0] <-> rows 0,1 of r[2]
+    swap32(r[1][e], r[3][e]);
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    swap16(r[0][e], r[1][e]);   // odd rows of r[0] <-> even rows of r[1]
+    swap16(r[2][e], r[3][e]);
+  }
+}
+
 // Phase A store: this lane's 16 inputs into its row of the wave's block.
 __device__ __forceinline__ void store_feats(float* feat, int lane, const float s[8], const float gr[8]) {
   float4* r = (float4*)(feat + lane * kFeatStride);
@@ -631,6 +666,18 @@ template <> struct Dec<NDGI_PREC_F32> {
   __device__ __forceinline__ void group(const float f[4], int q, f4v& acc) const { dec32_group(d, f, q, acc); }
   __device__ __forceinline__ f4v bias3() const { return d.c3; }
 };
+
+// Phase B from registers: the decoder over the wave's 64 queries after the handoff; lane l
+// ends with the output-layer values of query l.
+template <int PREC>
+__device__ __forceinline__ f4v decode_regs(const Dec<PREC>& dec, const float sp[8], const float gr[8]) {
+  float r[4][4];
+  transpose_chunks(sp, gr, r);
+  f4v acc = dec.bias3();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) dec.group(r[q], q, acc);
+  return acc;
+}
 
 // Phase B: the decoder over the 64 queries of a wave's feature block; lane l ends with
 // the output-layer values of query l.
