@@ -18,9 +18,10 @@ written to be checked by eye against the paper (arXiv 2604.12625):
 * Supplementary Sec. D.2: tiled PSNR with the dynamic range taken per tile.
 * Tables 2-3: bits per pixel accounting.
 
-The concrete feature layout (an 8-channel BC4 spatial map plus an 8-channel
-FP16/FP32 grid at quarter resolution, a 16-32-32-3 ReLU decoder with exponential
-output) is the workload this library is built for; each place where the paper
+Two feature layouts are covered: an 8-channel BC4 spatial map plus an 8-channel
+FP16/FP32 grid at quarter resolution with a 16-32-32-3 ReLU decoder and exponential
+output, and the paper's hybrid layout (F_uv, F_ut, F_vt, F_uvt and gamma(t) into a
+16-h-h-3 GELU decoder, Sec. 3.3); each place where the paper
 does not fix a detail carries a "Reading" note.  Parity of the end-to-end decode
 is the composition of separately pinned parts (codec, interpolation, MLP); the
 trained quality of a model has no published value to pin against
@@ -275,6 +276,179 @@ def decode_pages(models: list, reqs: list, page: int, dst: np.ndarray, pitch: in
             bad += 1
             continue
         rgb = decode_page(md, px, py, t, page)
+        for j in range(page):
+            dst[off + j * pitch: off + j * pitch + page] = rgb[j]
+    return bad
+
+
+# --------------------------------------------------------------------------------------
+# Hybrid feature maps and the GELU decoder (Sec. 3.3, Eq. (4)-(5), Table 1, Table 3, Sec. 4)
+# --------------------------------------------------------------------------------------
+# A hybrid model holds four feature maps and a decoder:
+#   fuv  [H/4][W/4][4][8]       F_uv, W x H x 4 channels, BC4 blocks (one per channel)
+#   fuvt [S][Gv/4][Gu/4][4][8]  F_uvt, Gu x Gv x 4 channels in S time slices, each slice
+#                               block-compressed on its own (Sec. 3.4)
+#   fut  [Tt][U][2]             F_ut, 8-bit, U x Tt x 2 channels
+#   fvt  [Tt][V][2]             F_vt, 8-bit, V x Tt x 2 channels
+#   keys [n]                    times of the baked lightmaps (n = 0: uniform time)
+#   mlp                         packed [W1 h x 16 | b1 | W2 h x h | b2 | W3 3 x h | b3]
+# Readings (the paper gives the structure, not these details):
+# * every stored byte q stands for the feature value q / 255 (Eq. (6) puts features in
+#   [0, 1]; the 8-bit planes use the same scale);
+# * space: texel-centre bilinear with clamp-to-edge on every spatial axis, as for the
+#   other layout;
+# * time: t is clamped to [0, 1] (a day is not wrapped: the feature maps' time axes are
+#   learned over one interval); the lightmaps' key times (Sec. 3.1: possibly non-uniform)
+#   map t piecewise linearly to tau in [0, 1], key i going to i / (n - 1); the time axes
+#   of F_ut, F_vt and F_uvt hold their samples at tau = k / (N - 1) (their ends at the
+#   first and last key) and are interpolated linearly;
+# * gamma(t) takes the clamped t itself (Eq. (4));
+# * decoder inputs in the order of Eq. (4): [V_uvt (4), V_uv (4), V_ut (2), V_vt (2),
+#   gamma (4)]; hidden layers use the exact GELU x * Phi(x) (Sec. 4; the erf form is the
+#   PyTorch default), the output layer has no activation.
+HYB_IN = 16
+
+
+def hybrid_mlp_size(hidden: int) -> int:
+    return hidden * HYB_IN + hidden + hidden * hidden + hidden + N_OUT * hidden + N_OUT
+
+
+def unpack_hybrid_mlp(mlp, hidden: int) -> dict:
+    p = np.asarray(mlp).astype(np.float64).reshape(-1)
+    assert p.size == hybrid_mlp_size(hidden)
+    o1 = hidden * HYB_IN
+    o2 = o1 + hidden
+    o3 = o2 + hidden * hidden
+    o4 = o3 + hidden
+    o5 = o4 + N_OUT * hidden
+    return dict(W1=p[:o1].reshape(hidden, HYB_IN), b1=p[o1:o2], W2=p[o2:o3].reshape(hidden, hidden),
+                b2=p[o3:o4], W3=p[o4:o5].reshape(N_OUT, hidden), b3=p[o5:])
+
+
+def gelu(x: np.ndarray) -> np.ndarray:
+    """GELU(x) = x Phi(x), Phi the standard normal CDF = (1 + erf(x / sqrt 2)) / 2."""
+    from scipy.special import erf
+    x = np.asarray(x, dtype=np.float64)
+    return 0.5 * x * (1.0 + erf(x / np.sqrt(2.0)))
+
+
+def hybrid_mlp_forward(mlp, hidden: int, x: np.ndarray) -> np.ndarray:
+    """Decoder G_Phi of Eq. (4): two GELU hidden layers of width ``hidden``, linear output."""
+    P = unpack_hybrid_mlp(mlp, hidden)
+    h1 = gelu(x @ P["W1"].T + P["b1"])
+    h2 = gelu(h1 @ P["W2"].T + P["b2"])
+    return h2 @ P["W3"].T + P["b3"]
+
+
+def gamma_t(t: np.ndarray) -> np.ndarray:
+    """Positional encoding of time, Eq. (4): [sin(pi t), cos(pi t), sin(2 pi t), cos(2 pi t)]."""
+    t = np.asarray(t, dtype=np.float64)
+    return np.stack([np.sin(np.pi * t), np.cos(np.pi * t), np.sin(2 * np.pi * t), np.cos(2 * np.pi * t)], -1)
+
+
+def key_time_coord(t: np.ndarray, keys) -> np.ndarray:
+    """tau in [0, 1] for a clamped time t: piecewise linear through (keys[i], i / (n - 1));
+    t = tau with no key table."""
+    t = np.asarray(t, dtype=np.float64)
+    k = np.asarray(keys, dtype=np.float64).reshape(-1)
+    if k.size == 0:
+        return t
+    n = k.size
+    i = np.clip(np.searchsorted(k, t, side="right") - 1, 0, n - 2)
+    f = (t - k[i]) / (k[i + 1] - k[i])
+    return np.clip((i + f) / (n - 1), 0.0, 1.0)
+
+
+def _node_axis(tau: np.ndarray, N: int):
+    """Linear interpolation over N samples at tau = k / (N - 1): (i0, i1, w0, w1)."""
+    if N == 1:
+        z = np.zeros(np.shape(tau), dtype=np.int64)
+        return z, z, np.ones(np.shape(tau)), np.zeros(np.shape(tau))
+    p = tau * (N - 1)
+    i0 = np.minimum(np.floor(p).astype(np.int64), N - 2)
+    f = p - i0
+    return i0, i0 + 1, 1.0 - f, f
+
+
+def bc4_texels(blocks: np.ndarray, xs, ys) -> np.ndarray:
+    """Values of all channels of block-compressed texels (xs, ys): ``blocks`` is the
+    [..., C, 8] selection of the texels' footprints; returns [..., C] uint8."""
+    field = np.zeros(blocks.shape[:-1], dtype=np.int64)
+    for b in range(6):
+        field |= blocks[..., 2 + b].astype(np.int64) << (8 * b)
+    slot = (4 * (np.asarray(ys) & 3) + (np.asarray(xs) & 3))[..., None]
+    codes = (field >> (3 * slot)) & 7
+    return bc4_palette_value(blocks[..., 0], blocks[..., 1], codes)
+
+
+def hybrid_features(model: dict, u: np.ndarray, v: np.ndarray, t: np.ndarray) -> np.ndarray:
+    """The 16 decoder inputs at (u, v, t) (Eq. (4)), float64 -> [..., 16]."""
+    tc = np.clip(t, 0.0, 1.0)
+    tau = key_time_coord(tc, model["keys"])
+    # V_uvt: bilinear in each of the two slices around tau, then linear between them
+    Gu, Gv, S = model["Gu"], model["Gv"], model["S"]
+    x0, x1, wx0, wx1 = _axis(u, Gu)
+    y0, y1, wy0, wy1 = _axis(v, Gv)
+    s0, s1, ws0, ws1 = _node_axis(tau, S)
+    fuvt = model["fuvt"]
+    Vuvt = np.zeros(np.shape(u) + (4,))
+    for (ss, ws) in ((s0, ws0), (s1, ws1)):
+        for (yy, wy) in ((y0, wy0), (y1, wy1)):
+            for (xx, wx) in ((x0, wx0), (x1, wx1)):
+                tex = bc4_texels(fuvt[ss, yy >> 2, xx >> 2], xx, yy) / 255.0
+                Vuvt += (ws * wy * wx)[..., None] * tex
+    # V_uv: bilinear in the W x H map
+    x0, x1, wx0, wx1 = _axis(u, model["W"])
+    y0, y1, wy0, wy1 = _axis(v, model["H"])
+    fuv = model["fuv"]
+    Vuv = np.zeros(np.shape(u) + (4,))
+    for (yy, wy) in ((y0, wy0), (y1, wy1)):
+        for (xx, wx) in ((x0, wx0), (x1, wx1)):
+            Vuv += (wy * wx)[..., None] * (bc4_texels(fuv[yy >> 2, xx >> 2], xx, yy) / 255.0)
+    # V_ut, V_vt: bilinear on the (u, t) and (v, t) planes
+    k0, k1, wk0, wk1 = _node_axis(tau, model["Tt"])
+    planes = []
+    for (c, size, plane) in ((u, model["U"], model["fut"]), (v, model["V"], model["fvt"])):
+        a0, a1, wa0, wa1 = _axis(c, size)
+        P = np.zeros(np.shape(u) + (2,))
+        for (kk, wk) in ((k0, wk0), (k1, wk1)):
+            for (aa, wa) in ((a0, wa0), (a1, wa1)):
+                P += (wk * wa)[..., None] * (plane[kk, aa].astype(np.float64) / 255.0)
+        planes.append(P)
+    return np.concatenate([Vuvt, Vuv, planes[0], planes[1], gamma_t(tc)], axis=-1)
+
+
+def hybrid_decode_f64(model: dict, u, v, t) -> np.ndarray:
+    """I(u, v, t) = G_Phi(V_uvt, V_uv, V_ut, V_vt, gamma(t)) (Eq. (4)) -> [n][3]; a query
+    with a non-finite coordinate decodes to NaN."""
+    u = np.asarray(u, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    finite = np.isfinite(u) & np.isfinite(v) & np.isfinite(t)
+    x = hybrid_features(model, np.where(finite, u, 0.0), np.where(finite, v, 0.0), np.where(finite, t, 0.0))
+    rgb = hybrid_mlp_forward(model["mlp"], model["hidden"], x)
+    return np.where(finite[..., None], rgb, np.nan)
+
+
+def hybrid_decode(model: dict, uvt: np.ndarray) -> np.ndarray:
+    """Decode explicit float32 queries [n][3] of a hybrid model."""
+    q = np.asarray(uvt, dtype=np.float32).astype(np.float64).reshape(-1, 3)
+    return hybrid_decode_f64(model, q[:, 0], q[:, 1], q[:, 2])
+
+
+def hybrid_decode_pages(models: list, reqs: list, page: int, dst: np.ndarray, pitch: int) -> int:
+    """Page decode of hybrid models (same request convention as :func:`decode_pages`)."""
+    bad = 0
+    for (m, px, py, t, off) in reqs:
+        if not (0 <= m < len(models)):
+            bad += 1
+            continue
+        md = models[m]
+        if px < 0 or py < 0 or page * (px + 1) > md["W"] or page * (py + 1) > md["H"]:
+            bad += 1
+            continue
+        _, _, u, v = page_texels(md, px, py, page)
+        rgb = hybrid_decode_f64(md, u, v, np.full(u.shape, np.float64(np.float32(t))))
         for j in range(page):
             dst[off + j * pitch: off + j * pitch + page] = rgb[j]
     return bad

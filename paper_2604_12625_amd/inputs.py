@@ -13,6 +13,9 @@ The paper's lightmap dataset is not available; the synthetic workloads stand in 
 * random models: BC4 blocks with uniformly random bytes (so both BC4 modes and every
   selector occur), a grid with values uniform in [-1, 1], He-normal decoder weights
   with zero biases;
+* random hybrid models (the paper's four feature maps): random block bytes and 8-bit
+  planes, He-normal weights with small uniform biases, key times of hourly bakes plus
+  two around a light switch;
 * queries: texel centres of a map at given times, or (u, v, t) uniform in [0, 1);
 * virtual-texturing frames: maps with side 128 * round(2^U[1,5]) and page requests
   drawn Zipf(1.1) over a seeded ranking of the maps;
@@ -68,6 +71,63 @@ def random_model(W: int, H: int, Gw: int, Gh: int, T: int, grid_dtype=np.float32
                 bc4=random_bc4(W, H, g),
                 grid=random_grid(Gw, Gh, T, grid_dtype, g),
                 mlp=he_normal_mlp(mlp_dtype, g))
+
+
+# ------------------------------------------------------------ hybrid feature maps
+# The paper's own layout: F_uv (W x H x 4, block-compressed), F_ut (U x Tt x 2) and
+# F_vt (V x Tt x 2) at 8 bits, F_uvt (Gu x Gv x S slices x 4, each slice
+# block-compressed), a 16-h-h-3 decoder.  Profiles of a 128 x 128 tile model: F_uvt side
+# 16 (L), 32 (M), 64 (H) with hidden width 16, and side 32 with width 64 (M.64); 12 slices;
+# F_ut and F_vt 64 x 24.
+HYBRID_IN = 16
+HYBRID_PROFILES = {"L": (16, 16), "M": (32, 16), "H": (64, 16), "M.64": (32, 64)}
+
+
+def hybrid_mlp_size(hidden: int) -> int:
+    return hidden * HYBRID_IN + hidden + hidden * hidden + hidden + N_OUT * hidden + N_OUT
+
+
+def hybrid_mlp(hidden: int, dtype, g: np.random.Generator) -> np.ndarray:
+    """Packed [W1 h x 16 | b1 | W2 h x h | b2 | W3 3 x h | b3]; W ~ N(0, 2/fan_in),
+    b ~ U[-0.1, 0.1]."""
+    parts = []
+    for (fo, fi) in ((hidden, HYBRID_IN), (hidden, hidden), (N_OUT, hidden)):
+        parts.append(g.normal(0.0, math.sqrt(2.0 / fi), size=fo * fi))
+        parts.append(g.uniform(-0.1, 0.1, size=fo))
+    return np.concatenate(parts).astype(np.float32).astype(dtype)
+
+
+def lightmap_key_times(g: np.random.Generator, hourly: int = 24, extra: int = 2) -> np.ndarray:
+    """Key times of a day of baked lightmaps in [0, 1]: one per hour (h / hourly) plus
+    ``extra`` keys around a light-switch time drawn inside an hour, 0.004 apart
+    (strictly increasing, float32)."""
+    s = (g.integers(2, hourly - 2) + g.uniform(0.3, 0.7)) / hourly
+    extras = s + 0.004 * (np.arange(extra) - (extra - 1) / 2.0)
+    return np.sort(np.concatenate([np.arange(hourly) / hourly, extras])).astype(np.float32)
+
+
+def random_hybrid_model(W: int = 128, H: int = 128, profile: str = "M", slices: int = 12,
+                        plane=(64, 64, 24), mlp_dtype=np.float16, keys: bool = True,
+                        config: int = 0, index: int = 0, uvt_side=None) -> dict:
+    """A hybrid model with uniformly random block bytes and 8-bit planes.
+
+    ``plane`` = (U, V, Tt): F_ut is [Tt][U][2] and F_vt is [Tt][V][2] (uint8);
+    F_uv is [H/4][W/4][4][8] and F_uvt is [S][Gv/4][Gu/4][4][8] BC4 bytes.  ``keys``
+    attaches a non-uniform key-time table (:func:`lightmap_key_times`)."""
+    side, hidden = HYBRID_PROFILES[profile]
+    Gu, Gv = (side, side) if uvt_side is None else uvt_side
+    U, V, Tt = plane
+    g = rng(config, P_MODEL, index)
+    assert W % 4 == 0 and H % 4 == 0 and Gu % 4 == 0 and Gv % 4 == 0
+    return dict(
+        W=W, H=H, Gu=Gu, Gv=Gv, S=slices, U=U, V=V, Tt=Tt, hidden=hidden,
+        fuv=g.integers(0, 256, size=(H // 4, W // 4, 4, 8), dtype=np.uint8),
+        fuvt=g.integers(0, 256, size=(slices, Gv // 4, Gu // 4, 4, 8), dtype=np.uint8),
+        fut=g.integers(0, 256, size=(Tt, U, 2), dtype=np.uint8),
+        fvt=g.integers(0, 256, size=(Tt, V, 2), dtype=np.uint8),
+        keys=lightmap_key_times(g) if keys else np.zeros(0, np.float32),
+        mlp=hybrid_mlp(hidden, mlp_dtype, g),
+    )
 
 
 # ----------------------------------------------------------------------------- queries

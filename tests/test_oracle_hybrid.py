@@ -1,0 +1,182 @@
+"""Pins for the CPU reference of the hybrid layout (Sec. 3.3, Eq. (4)-(5)): each test
+checks it against something other than itself -- closed forms of gamma(t), printed
+values of the normal CDF behind GELU, the node values of each feature map at its sample
+points, exact reproduction of affine planes, the wiring of the decoder through
+single-input weights, and the pinned block codec."""
+import math
+import os
+
+import numpy as np
+
+from oracle import ndgi_oracle as O
+from paper_2604_12625_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _model(profile="M", keys=False, **kw):
+    return I.random_hybrid_model(profile=profile, keys=keys, config=97, **kw)
+
+
+def test_gamma_closed_forms():
+    r3, r2 = math.sqrt(3.0) / 2, math.sqrt(2.0) / 2
+    cases = {0.0: [0, 1, 0, 1], 1 / 6: [0.5, r3, r3, 0.5], 0.25: [r2, r2, 1, 0],
+             0.5: [1, 0, 0, -1], 0.75: [r2, -r2, -1, 0], 1.0: [0, -1, 0, 1]}
+    for t, want in cases.items():
+        np.testing.assert_allclose(O.gamma_t(np.array([t]))[0], want, atol=1e-15)
+
+
+def test_gelu_matches_normal_table():
+    rows = [[float(s) for s in line.split("|")] for line in open(os.path.join(GOLDEN, "normal_cdf.txt"))
+            if line.strip() and not line.startswith("#")]
+    assert len(rows) == 9
+    for x, phi in rows:
+        assert abs(O.gelu(np.array([x]))[0] - x * phi) < 2e-9 * max(1.0, abs(x))
+    # x Phi(x) - (-x) Phi(-x) = x because Phi(x) + Phi(-x) = 1
+    x = np.linspace(-6, 6, 101)
+    np.testing.assert_allclose(O.gelu(x) - O.gelu(-x), x, atol=1e-14)
+
+
+def test_key_time_coordinate():
+    t = np.linspace(0.0, 1.0, 41)
+    np.testing.assert_array_equal(O.key_time_coord(t, []), t)
+    np.testing.assert_allclose(O.key_time_coord(t, np.arange(11) / 10.0), t, atol=1e-15)
+    keys = np.array([0.0, 0.5, 0.6, 1.0])
+    got = O.key_time_coord(np.array([0.25, 0.5, 0.55, 0.6, 0.8, 1.0]), keys)
+    np.testing.assert_allclose(got, [1 / 6, 1 / 3, 0.5, 2 / 3, 5 / 6, 1.0], atol=1e-15)
+    # before the first and after the last key the coordinate clamps
+    np.testing.assert_array_equal(O.key_time_coord(np.array([0.0, 0.05, 0.95, 1.0]), [0.1, 0.9]),
+                                  [0.0, 0.0, 1.0, 1.0])
+
+
+def _decoded(blocks):
+    """[..., 4, 8] BC4 bytes -> [..., 4 channels, 16 texels] through the pinned codec."""
+    shp = blocks.shape[:-1]
+    return O.bc4_decode_blocks(blocks.reshape(-1, 8)).reshape(shp + (16,))
+
+
+def test_feature_maps_return_their_samples_at_sample_points():
+    m = _model()
+    g = np.random.default_rng(11)
+    n = 400
+    # F_uvt at texel centres of the Gu x Gv map and tau = k / (S - 1) (no key table)
+    S, Gu, Gv = m["S"], m["Gu"], m["Gv"]
+    k, y, x = g.integers(0, S, n), g.integers(0, Gv, n), g.integers(0, Gu, n)
+    f = O.hybrid_features(m, (x + 0.5) / Gu, (y + 0.5) / Gv, k / (S - 1))
+    dec = _decoded(m["fuvt"])                                  # [S][Gv/4][Gu/4][4][16]
+    want = dec[k, y >> 2, x >> 2, :, 4 * (y & 3) + (x & 3)] / 255.0
+    np.testing.assert_allclose(f[:, 0:4], want, rtol=0, atol=1e-14)
+    # F_uv at texel centres of the W x H map
+    W, H = m["W"], m["H"]
+    y, x = g.integers(0, H, n), g.integers(0, W, n)
+    f = O.hybrid_features(m, (x + 0.5) / W, (y + 0.5) / H, g.random(n))
+    dec = _decoded(m["fuv"])
+    np.testing.assert_allclose(f[:, 4:8], dec[y >> 2, x >> 2, :, 4 * (y & 3) + (x & 3)] / 255.0, atol=1e-14)
+    # F_ut and F_vt at their texel centres and tau = k / (Tt - 1)
+    U, V, Tt = m["U"], m["V"], m["Tt"]
+    k, a, b = g.integers(0, Tt, n), g.integers(0, U, n), g.integers(0, V, n)
+    f = O.hybrid_features(m, (a + 0.5) / U, (b + 0.5) / V, k / (Tt - 1))
+    np.testing.assert_allclose(f[:, 8:10], m["fut"][k, a] / 255.0, atol=1e-14)
+    np.testing.assert_allclose(f[:, 10:12], m["fvt"][k, b] / 255.0, atol=1e-14)
+    np.testing.assert_allclose(f[:, 12:16], O.gamma_t(k / (Tt - 1)), atol=1e-15)
+
+
+def test_planes_reproduce_affine_fields():
+    m = _model()
+    U, Tt = m["U"], m["Tt"]
+    k, a = np.meshgrid(np.arange(Tt), np.arange(U), indexing="ij")
+    m["fut"] = np.stack([10 + 2 * a + 3 * k, 200 - a - 2 * k], -1).astype(np.uint8)
+    g = np.random.default_rng(12)
+    u = g.uniform(1.0 / U, 1 - 1.0 / U, 500)
+    t = g.random(500)
+    f = O.hybrid_features(m, u, g.random(500), t)
+    pa, pk = u * U - 0.5, t * (Tt - 1)
+    np.testing.assert_allclose(f[:, 8] * 255, 10 + 2 * pa + 3 * pk, atol=1e-10)
+    np.testing.assert_allclose(f[:, 9] * 255, 200 - pa - 2 * pk, atol=1e-10)
+
+
+def test_uvt_slices_interpolate_linearly_in_time():
+    m = _model()
+    S, Gu, Gv = m["S"], m["Gu"], m["Gv"]
+    g = np.random.default_rng(13)
+    x, y = g.integers(0, Gu, 200), g.integers(0, Gv, 200)
+    k = g.integers(0, S - 1, 200)
+    w = g.random(200)
+    u, v = (x + 0.5) / Gu, (y + 0.5) / Gv
+    mid = O.hybrid_features(m, u, v, (k + w) / (S - 1))[:, 0:4]
+    a = O.hybrid_features(m, u, v, k / (S - 1))[:, 0:4]
+    b = O.hybrid_features(m, u, v, (k + 1) / (S - 1))[:, 0:4]
+    np.testing.assert_allclose(mid, (1 - w)[:, None] * a + w[:, None] * b, atol=1e-13)
+
+
+def test_key_table_warps_every_time_axis():
+    m = _model(keys=True)
+    keys = m["keys"].astype(np.float64)
+    n = keys.size
+    g = np.random.default_rng(14)
+    i = g.integers(0, n - 1, 100)
+    f = g.random(100)
+    t = keys[i] + f * (keys[i + 1] - keys[i])
+    u, v = g.random(100), g.random(100)
+    plain = dict(m, keys=np.zeros(0, np.float32))
+    got = O.hybrid_features(m, u, v, t)
+    want = O.hybrid_features(plain, u, v, (i + f) / (n - 1))
+    np.testing.assert_allclose(got[:, :12], want[:, :12], atol=1e-12)
+    # gamma stays on the time itself
+    np.testing.assert_allclose(got[:, 12:], O.gamma_t(t), atol=1e-15)
+
+
+def test_time_clamps_and_non_finite_queries():
+    m = _model(keys=True)
+    q = np.array([[0.3, 0.6, -0.5], [0.3, 0.6, 0.0], [0.3, 0.6, 1.5], [0.3, 0.6, 1.0],
+                  [np.nan, 0.5, 0.5], [0.5, 0.5, np.inf]], dtype=np.float32)
+    out = O.hybrid_decode(m, q)
+    np.testing.assert_array_equal(out[0], out[1])
+    np.testing.assert_array_equal(out[2], out[3])
+    assert np.isnan(out[4:]).all() and np.isfinite(out[:4]).all()
+
+
+def _select_mlp(hidden, j, perm=None):
+    """Decoder whose hidden unit p reads input j (layer 1), hidden-2 unit i reads hidden-1
+    unit perm[i], and output c reads hidden-2 unit c."""
+    P = np.zeros(O.hybrid_mlp_size(hidden))
+    o1 = hidden * 16
+    o3 = o1 + hidden + hidden * hidden
+    o5 = o3 + hidden + 3 * hidden
+    W1 = np.zeros((hidden, 16))
+    W1[:, j] = np.arange(1, hidden + 1) / hidden            # unit p: x_j * (p + 1) / hidden
+    W2 = np.zeros((hidden, hidden))
+    perm = np.arange(hidden) if perm is None else perm
+    W2[np.arange(hidden), perm] = 1.0
+    W3 = np.zeros((3, hidden))
+    W3[np.arange(3), np.arange(3)] = 1.0
+    P[:o1] = W1.ravel()
+    P[o1 + hidden:o1 + hidden + hidden * hidden] = W2.ravel()
+    P[o3 + hidden:o5] = W3.ravel()
+    P[o5:] = [0.5, -0.25, 0.0]
+    return P
+
+
+def test_decoder_wiring_and_orientation():
+    for hidden in (16, 64):
+        m = _model("M.64" if hidden == 64 else "M")
+        perm = np.roll(np.arange(hidden), -5)
+        m["mlp"] = _select_mlp(hidden, 13, perm)                  # input 13 = cos(pi t)
+        t = np.array([0.0, 1 / 3, 0.5, 0.9])
+        out = O.hybrid_decode_f64(m, np.full(4, 0.3), np.full(4, 0.7), t)
+        c = np.cos(np.pi * t)
+        for r in range(3):
+            scale = (perm[r] + 1) / hidden
+            np.testing.assert_allclose(out[:, r], O.gelu(O.gelu(c * scale)) + [0.5, -0.25, 0.0][r],
+                                       atol=1e-15)
+
+
+def test_hybrid_page_decode_equals_texel_centre_queries():
+    m = _model(keys=True)
+    t = np.float32(0.41)
+    dst = np.zeros((128 * 128, 3))
+    bad = O.hybrid_decode_pages([m], [(0, 0, 0, t, 0), (0, 1, 0, t, 0), (2, 0, 0, t, 0)], 128, dst, 128)
+    assert bad == 2
+    y, x = np.meshgrid(np.arange(128), np.arange(128), indexing="ij")
+    q = np.stack([((x + 0.5) / 128).ravel(), ((y + 0.5) / 128).ravel(), np.full(128 * 128, t)], 1)
+    np.testing.assert_allclose(dst, O.hybrid_decode(m, q.astype(np.float32)), rtol=1e-13, atol=1e-15)
