@@ -4,7 +4,8 @@
  * The method (arXiv 2604.12625) represents a set of time-varying lightmaps by feature
  * maps plus a small MLP: the lighting at (u, v, t) is I = H_Theta(u, v, t) (Sec. 3.1,
  * Eq. 3).  This library implements the data-parallel hot path of that representation
- * for one concrete layout:
+ * for two layouts: the paper's hybrid feature maps (section "hybrid layout" below) and
+ * this one:
  *
  *   spatial map  W x H texels, 8 channels, each channel BC4 block-compressed
  *                (two 8-bit endpoints and sixteen 3-bit selectors per 4x4 block;
@@ -251,6 +252,84 @@ int ndgi_train_step(ndgi_ctx* ctx, ndgi_train_state* state, const ndgi_batch* ba
 int ndgi_export(ndgi_ctx* ctx, const ndgi_train_state* state, uint8_t* bc4_out,
                 void* grid_out, int32_t grid_dtype, void* mlp_out, int32_t mlp_dtype,
                 hipStream_t stream);
+
+/* ---------------------------------------------------------------- hybrid layout */
+
+/* The paper's own feature layout (Sec. 3.3, Eq. 4-5; Table 1; Table 3), decoded by its
+ * GELU decoder (Sec. 4).  Four feature maps per model:
+ *   F_uv   W x H texels, 4 channels, one BC4 block per 4x4 footprint and channel
+ *          ([H/4][W/4][4][8 bytes], 32 bytes per footprint)
+ *   F_uvt  Gu x Gv texels x S time slices, 4 channels, each slice block-compressed on its
+ *          own (Sec. 3.4): [S][Gv/4][Gu/4][4][8 bytes]
+ *   F_ut   U x Tt texels, 2 channels, 8-bit: [Tt][U][2] bytes
+ *   F_vt   V x Tt texels, 2 channels, 8-bit: [Tt][V][2] bytes
+ * and a decoder 16 -> hidden -> hidden -> 3 (hidden 16 or 64; GELU x*Phi(x) on the hidden
+ * layers, no output activation), packed row-major as [W1 hidden x 16 | b1 | W2 hidden x
+ * hidden | b2 | W3 3 x hidden | b3] (ndgi_hybrid_mlp_size values).
+ * Sampling at (u, v, t):
+ *   - a stored byte q is the feature value q / 255;
+ *   - every spatial axis (W, H; Gu, Gv; U; V) is sampled at texel centres, bilinearly, with
+ *     clamp to the edge (as for ndgi_model);
+ *   - t is clamped to [0, 1].  With a key table (n_keys times k_0 < ... < k_{n-1} of the
+ *     baked lightmaps, Sec. 3.1) t maps piecewise linearly to tau, k_i -> i / (n - 1),
+ *     and tau clamps to [0, 1]; without one tau = t.  The time axes of F_uvt (S slices),
+ *     F_ut and F_vt (Tt rows) hold sample k at tau = k / (N - 1) and interpolate linearly;
+ *   - the decoder input is [V_uvt (4), V_uv (4), V_ut (2), V_vt (2), gamma(t) (4)] with
+ *     gamma(t) = [sin(pi t), cos(pi t), sin(2 pi t), cos(2 pi t)] of the clamped t (Eq. 4).
+ * 96 bytes, the same layout on host and device. */
+#define NDGI_HYBRID_IN 16
+#define NDGI_HYBRID_MAX_KEYS 256
+
+typedef struct ndgi_hybrid_model {
+    int32_t W, H;         /* F_uv size; multiples of 4, 4..16384                          */
+    int32_t Gu, Gv;       /* F_uvt size; multiples of 4, 4 <= Gu <= W, 4 <= Gv <= H       */
+    int32_t S;            /* F_uvt time slices, 1..1024                                   */
+    int32_t U, V;         /* F_ut / F_vt spatial size, 1 <= U <= W, 1 <= V <= H           */
+    int32_t Tt;           /* F_ut / F_vt time rows, 1..1024                               */
+    int32_t hidden;       /* decoder width: 16 or 64                                      */
+    int32_t mlp_dtype;    /* NDGI_DTYPE_F32 or NDGI_DTYPE_F16                             */
+    int32_t n_keys;       /* 0, or 2..NDGI_HYBRID_MAX_KEYS key times                      */
+    int32_t reserved0;    /* must be 0                                                    */
+    const uint8_t* fuv;   /* device [H/4][W/4][4][8]                                      */
+    const uint8_t* fuvt;  /* device [S][Gv/4][Gu/4][4][8]                                 */
+    const uint8_t* fut;   /* device [Tt][U][2]                                            */
+    const uint8_t* fvt;   /* device [Tt][V][2]                                            */
+    const float* keys;    /* device [n_keys], strictly increasing in [0, 1] (the caller
+                             guarantees the order; it is not checked)                     */
+    const void* mlp;      /* device [ndgi_hybrid_mlp_size(hidden)] in mlp_dtype            */
+} ndgi_hybrid_model;
+
+/* Number of packed decoder values for a hidden width (16 or 64); -1 otherwise. */
+int32_t ndgi_hybrid_mlp_size(int32_t hidden);
+
+/* Random-access decode of n queries of a hybrid model (Sec. 3.1 Eq. 3, Sec. 3.3 Eq. 4):
+ *   uvt: device float [n][3]; out: device [n][3] of float (NDGI_PREC_F32: FP32 features,
+ *   FP32 MFMA) or _Float16 (NDGI_PREC_F16: FP32 features, FP16 MFMA with FP32
+ *   accumulation, FP16 out).  A query with a non-finite coordinate decodes to NaN.
+ *   model: host pointer to a descriptor whose buffers are device memory.
+ * n = 0 is a no-op.  Errors: INVALID_ARG (descriptor out of the ranges above, n < 0, prec,
+ * NULL buffers). */
+int ndgi_hybrid_decode(ndgi_ctx* ctx, const ndgi_hybrid_model* model, const float* uvt, int64_t n,
+                       void* out, int32_t prec, hipStream_t stream);
+
+/* Virtual-texturing page decode of hybrid models (Sec. 3.5; supplementary Sec. C): the
+ * same request convention as ndgi_decode_pages (one persistent launch over all requests,
+ * request count read from device memory), with t clamped to [0, 1] and page a multiple of
+ * 32 in 32..4096.  Each map (one per-tile model in the paper's production setting) has its
+ * own descriptor and decoder.  A request whose model index or page is out of range, or
+ * whose descriptor breaks the ranges above, is skipped and sets NDGI_FLAG_BAD_PAGE_REQUEST.
+ * Errors: INVALID_ARG (sizes, prec, NULL pointers). */
+int ndgi_hybrid_decode_pages(ndgi_ctx* ctx, const ndgi_hybrid_model* models_dev, int32_t n_models,
+                             const ndgi_page_req* reqs_dev, const int32_t* n_reqs_dev, int32_t max_reqs,
+                             int32_t page, void* dst, int64_t dst_pitch, int32_t prec,
+                             hipStream_t stream);
+
+/* Same work launched as a HIP graph owned by the context (captured on the first call for
+ * an argument set, replayed afterwards), as ndgi_decode_pages_graph. */
+int ndgi_hybrid_decode_pages_graph(ndgi_ctx* ctx, const ndgi_hybrid_model* models_dev, int32_t n_models,
+                                   const ndgi_page_req* reqs_dev, const int32_t* n_reqs_dev,
+                                   int32_t max_reqs, int32_t page, void* dst, int64_t dst_pitch,
+                                   int32_t prec, hipStream_t stream);
 
 /* ---------------------------------------------------------------- evaluation */
 

@@ -29,6 +29,7 @@ FLAGS = [
 PER_FILE = {
     "decode.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
     "binned.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+    "hybrid.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
 }
 
 

@@ -71,6 +71,32 @@ static int check_pages(ndgi_ctx* ctx, const ndgi_model* models, int32_t n_models
   return NDGI_OK;
 }
 
+// Replay the graph captured for `key`, capturing it on first use: `launch(stream)` issues
+// the work on the context's capture stream.
+template <typename Launch>
+static int launch_graph(ndgi_ctx* c, const GraphKey& key, Launch launch) {
+  auto it = c->graphs.find(key);
+  hipStream_t s = std::get<10>(key);
+  if (it == c->graphs.end()) {
+    hipGraph_t graph = nullptr;
+    NDGI_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+    const int rc = launch(c->capture_stream);
+    hipError_t e = hipStreamEndCapture(c->capture_stream, &graph);
+    if (rc) {
+      if (graph) hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(NDGI_ERR_HIP, "pages graph: capture failed: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(NDGI_ERR_HIP, "pages graph: instantiate failed: %s", hipGetErrorString(e));
+    it = c->graphs.emplace(key, exec).first;
+  }
+  NDGI_HIP(hipGraphLaunch(it->second, s));
+  return NDGI_OK;
+}
+
 }  // namespace ndgi
 
 using namespace ndgi;
@@ -196,26 +222,66 @@ int ndgi_decode_pages_graph(ndgi_ctx* c, const ndgi_model* models, int32_t n_mod
   clear_error();
   int rc = check_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec);
   if (rc) return rc;
-  const GraphKey key{models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, s};
-  auto it = c->graphs.find(key);
-  if (it == c->graphs.end()) {
-    hipGraph_t graph = nullptr;
-    NDGI_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
-    rc = launch_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, c->capture_stream);
-    hipError_t e = hipStreamEndCapture(c->capture_stream, &graph);
-    if (rc) {
-      if (graph) hipGraphDestroy(graph);
-      return rc;
-    }
-    if (e != hipSuccess) return fail(NDGI_ERR_HIP, "decode_pages_graph: capture failed: %s", hipGetErrorString(e));
-    hipGraphExec_t exec = nullptr;
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
-    if (e != hipSuccess) return fail(NDGI_ERR_HIP, "decode_pages_graph: instantiate failed: %s", hipGetErrorString(e));
-    it = c->graphs.emplace(key, exec).first;
-  }
-  NDGI_HIP(hipGraphLaunch(it->second, s));
+  return launch_graph(c, GraphKey{0, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, s},
+                      [&](hipStream_t cs) {
+                        return launch_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, cs);
+                      });
+}
+
+int32_t ndgi_hybrid_mlp_size(int32_t hidden) {
+  if (hidden != 16 && hidden != 64) return -1;
+  return hidden * NDGI_HYBRID_IN + hidden + hidden * hidden + hidden + 3 * hidden + 3;
+}
+
+int ndgi_hybrid_decode(ndgi_ctx* c, const ndgi_hybrid_model* m, const float* uvt, int64_t n, void* out,
+                       int32_t prec, hipStream_t s) {
+  clear_error();
+  if (!c) return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode: ctx is NULL");
+  if (n < 0) return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode: n < 0");
+  if (prec != NDGI_PREC_F32 && prec != NDGI_PREC_F16)
+    return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode: bad prec %d", prec);
+  int rc = check_hybrid(m, "hybrid_decode");
+  if (rc) return rc;
+  if (n == 0) return NDGI_OK;
+  if (!uvt || !out) return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode: NULL query/output pointer");
+  return launch_hybrid_query(c, *m, uvt, n, out, prec, s);
+}
+
+static int check_hybrid_pages(ndgi_ctx* c, const ndgi_hybrid_model* models, int32_t n_models,
+                              const ndgi_page_req* reqs, const int32_t* n_reqs, int32_t max_reqs, int32_t page,
+                              void* dst, int64_t pitch, int32_t prec) {
+  if (!c) return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: ctx is NULL");
+  if (prec != NDGI_PREC_F32 && prec != NDGI_PREC_F16)
+    return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: bad prec %d", prec);
+  if (n_models < 0 || max_reqs < 0) return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: negative count");
+  if (page < 32 || page > 4096 || (page & 31))
+    return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: page=%d must be a multiple of 32 in [32, 4096]", page);
+  if (pitch < page) return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: dst_pitch=%lld < page", (long long)pitch);
+  if (!n_reqs || !dst || (n_models > 0 && !models) || (max_reqs > 0 && !reqs))
+    return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: NULL pointer");
   return NDGI_OK;
+}
+
+int ndgi_hybrid_decode_pages(ndgi_ctx* c, const ndgi_hybrid_model* models, int32_t n_models,
+                             const ndgi_page_req* reqs, const int32_t* n_reqs, int32_t max_reqs, int32_t page,
+                             void* dst, int64_t pitch, int32_t prec, hipStream_t s) {
+  clear_error();
+  int rc = check_hybrid_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec);
+  if (rc) return rc;
+  return launch_hybrid_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, s);
+}
+
+int ndgi_hybrid_decode_pages_graph(ndgi_ctx* c, const ndgi_hybrid_model* models, int32_t n_models,
+                                   const ndgi_page_req* reqs, const int32_t* n_reqs, int32_t max_reqs,
+                                   int32_t page, void* dst, int64_t pitch, int32_t prec, hipStream_t s) {
+  clear_error();
+  int rc = check_hybrid_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec);
+  if (rc) return rc;
+  return launch_graph(c, GraphKey{1, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, s},
+                      [&](hipStream_t cs) {
+                        return launch_hybrid_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch,
+                                                   prec, cs);
+                      });
 }
 
 int ndgi_set_launch(ndgi_ctx* c, int32_t tile_w, int32_t tile_h, int32_t waves_per_cu) {

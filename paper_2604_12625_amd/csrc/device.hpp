@@ -381,14 +381,8 @@ __device__ __forceinline__ void swap16(float& a, float& b) {
   a = __uint_as_float(p[0]);
   b = __uint_as_float(p[1]);
 }
-__device__ __forceinline__ void transpose_chunks(const float sp[8], const float gr[8], float r[4][4]) {
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    r[c][0] = sp[2 * c];
-    r[c][1] = sp[2 * c + 1];
-    r[c][2] = gr[2 * c];
-    r[c][3] = gr[2 * c + 1];
-  }
+// The transpose itself: r[c] of lane (row g, j) goes to r[g] of lane (row c, j).
+__device__ __forceinline__ void transpose_rows(float r[4][4]) {
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     swap32(r[0][e], r[2][e]);   // rows 2,3 of r[0] <-> rows 0,1 of r[2]
@@ -399,6 +393,16 @@ __device__ __forceinline__ void transpose_chunks(const float sp[8], const float 
     swap16(r[0][e], r[1][e]);   // odd rows of r[0] <-> even rows of r[1]
     swap16(r[2][e], r[3][e]);
   }
+}
+__device__ __forceinline__ void transpose_chunks(const float sp[8], const float gr[8], float r[4][4]) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    r[c][0] = sp[2 * c];
+    r[c][1] = sp[2 * c + 1];
+    r[c][2] = gr[2 * c];
+    r[c][3] = gr[2 * c + 1];
+  }
+  transpose_rows(r);
 }
 
 // Phase A store: this lane's 16 inputs into its row of the wave's block.

@@ -1,0 +1,558 @@
+// Decode of the paper's hybrid layout (Sec. 3.3, Eq. 4-5): F_uvt (4 channels in time
+// slices, BC4 per slice), F_uv (4 channels, BC4), F_ut and F_vt (2 channels each, 8-bit)
+// and gamma(t) feed a 16 -> h -> h -> 3 decoder with GELU hidden layers and a linear
+// output (Sec. 4), h = 16 or 64.
+//
+// Decoder on MFMA.  A wave decodes 64 texels per pass as 4 groups of 16.  After the
+// register handoff lane (g, j) holds decoder inputs 4g..4g+3 of texel 16q + j for group q
+// (chunk 0 = V_uvt, 1 = V_uv, 2 = V_ut and V_vt, 3 = gamma).  Hidden units are MFMA rows in
+// blocks of 16; the C layout of a block (lane holds rows 4g..4g+3 of column j) is the
+// lane's K share of that block for the next layer, so no data moves between layers.
+//  * FP16: one v_mfma_f32_16x16x32_f16 per (row block, K block).  K slots 0..3 of lane
+//    group g carry the FP16 value ("hi") of units 4g..4g+3 of the K block and slots 4..7
+//    their residual fp16(v - hi) ("lo"), so inputs and activations enter with about 22
+//    bits while the weights (exact in FP16) appear in both halves.
+//  * FP32: v_mfma_f32_16x16x4_f32, step r feeding unit 4g + r of the K block.
+// The weights in that K order (the MFMA A operands) are laid out once per model in an LDS
+// table of 16-byte lane entries: "chunk" = 64 lanes x 16 bytes (8 FP16 slots or 4 FP32
+// steps).  The output layer of group q writes rows 4q..4q+2 of one accumulator, so after 4
+// groups lane l owns the RGB of texel l of the pass.
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace ndgi {
+
+template <int HD>
+struct HybShape {
+  static constexpr int NB = HD / 16;                           // row blocks of a hidden layer
+  static constexpr int kL1 = 0, kL2 = NB, kL3 = NB + NB * NB;  // first chunk of each layer
+  static constexpr int kChunks = NB + NB * NB + 4 * NB;        // layer 3: one set per group
+  static constexpr int oW1 = 0, oB1 = HD * NDGI_HYBRID_IN, oW2 = oB1 + HD, oB2 = oW2 + HD * HD,
+                       oW3 = oB2 + HD, oB3 = oW3 + 3 * HD, kSize = oB3 + 3;
+};
+
+template <int HD>
+struct HybTab {
+  u4v a[HybShape<HD>::kChunks * 64];
+  float b1[HD], b2[HD];
+  float b3[4];
+};
+
+// Build the decoder table of a model (all threads of the workgroup; the caller
+// synchronises before use).
+template <int PREC, int HD, int MDT>
+__device__ void hyb_build_dt(HybTab<HD>& T, const void* mlp) {
+  using S = HybShape<HD>;
+  for (int idx = threadIdx.x; idx < S::kChunks * 64; idx += blockDim.x) {
+    const int c = idx >> 6, lane = idx & 63, g = lane >> 4, i = lane & 15;
+    int base, kbase;   // offset of the row in the packed vector (or -1 for a zero row), first unit
+    if (c < S::kL2) {
+      base = S::oW1 + (16 * c + i) * NDGI_HYBRID_IN;
+      kbase = 4 * g;
+    } else if (c < S::kL3) {
+      const int ob = (c - S::kL2) / S::NB, kb = (c - S::kL2) % S::NB;
+      base = S::oW2 + (16 * ob + i) * HD;
+      kbase = 16 * kb + 4 * g;
+    } else {
+      const int q = (c - S::kL3) / S::NB, kb = (c - S::kL3) % S::NB;
+      base = ((i >> 2) == q && (i & 3) < 3) ? S::oW3 + (i & 3) * HD : -1;
+      kbase = 16 * kb + 4 * g;
+    }
+    // loads are unconditional (clamped row), the zero rows select afterwards
+    const int row = base < 0 ? S::oW3 : base;
+    float w[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) w[r] = base < 0 ? 0.0f : ld<MDT>(mlp, row + kbase + r);
+    if constexpr (PREC == NDGI_PREC_F16) {
+      h8v h;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) h[e] = (_Float16)w[e & 3];
+      T.a[idx] = __builtin_bit_cast(u4v, h);
+    } else {
+      T.a[idx] = (u4v){__float_as_uint(w[0]), __float_as_uint(w[1]), __float_as_uint(w[2]), __float_as_uint(w[3])};
+    }
+  }
+  for (int j = threadIdx.x; j < HD; j += blockDim.x) {
+    T.b1[j] = ld<MDT>(mlp, S::oB1 + j);
+    T.b2[j] = ld<MDT>(mlp, S::oB2 + j);
+  }
+  if (threadIdx.x < 4) T.b3[threadIdx.x] = threadIdx.x < 3 ? ld<MDT>(mlp, S::oB3 + threadIdx.x) : 0.0f;
+}
+
+template <int PREC, int HD>
+__device__ void hyb_build(HybTab<HD>& T, const void* mlp, int mlp_dtype) {
+  if (mlp_dtype == NDGI_DTYPE_F16) hyb_build_dt<PREC, HD, NDGI_DTYPE_F16>(T, mlp);
+  else hyb_build_dt<PREC, HD, NDGI_DTYPE_F32>(T, mlp);
+}
+
+// GELU(x) = x Phi(x) = max(x, 0) - |x|/2 erfc(|x| / sqrt 2): both branches of the sign
+// are the same expression, with no cancellation for large |x|.
+//  * FP32 path: erfc by the Chebyshev fit of Press et al., Numerical Recipes (erfcc),
+//    relative error below 1.2e-7 for every argument;
+//  * FP16 path: erfc(z) = P(z)^-16 with the degree-6 P of Abramowitz & Stegun 7.1.28,
+//    absolute error at most 3e-7 (far below the FP16 rounding of the activations), one
+//    reciprocal and no exponential.
+template <int PREC>
+__device__ __forceinline__ float gelu(float x) {
+  const float z = fabsf(x) * 0.70710678118654752f;
+  float ec;
+  if constexpr (PREC == NDGI_PREC_F32) {
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, z, 1.0f));
+    float p = fmaf(t, 0.17087277f, -0.82215223f);
+    p = fmaf(t, p, 1.48851587f);
+    p = fmaf(t, p, -1.13520398f);
+    p = fmaf(t, p, 0.27886807f);
+    p = fmaf(t, p, -0.18628806f);
+    p = fmaf(t, p, 0.09678418f);
+    p = fmaf(t, p, 0.37409196f);
+    p = fmaf(t, p, 1.00002368f);
+    p = fmaf(t, p, -1.26551223f);
+    ec = t * __expf(fmaf(-z, z, p));
+  } else {
+    float p = fmaf(z, 4.30638e-5f, 2.765672e-4f);
+    p = fmaf(z, p, 1.520143e-4f);
+    p = fmaf(z, p, 9.2705272e-3f);
+    p = fmaf(z, p, 4.22820123e-2f);
+    p = fmaf(z, p, 7.05230784e-2f);
+    p = fmaf(z, p, 1.0f);
+    float r = __builtin_amdgcn_rcpf(p);
+    r *= r;
+    r *= r;
+    r *= r;
+    ec = r * r;
+  }
+  return fmaf(-0.5f * fabsf(x), ec, fmaxf(x, 0.0f));
+}
+
+// One group of 16 texels through the decoder; x = this lane's K share of layer 1 (inputs
+// 4g..4g+3); the output layer accumulates into acc.
+template <int PREC, int HD>
+__device__ __forceinline__ void hyb_group(const HybTab<HD>& T, const float x[4], int q, int lane, f4v& acc) {
+  using S = HybShape<HD>;
+  constexpr int NB = S::NB;
+  const int g = lane >> 4;
+  if constexpr (PREC == NDGI_PREC_F16) {
+    auto A = [&](int c) { return __builtin_bit_cast(h8v, T.a[c * 64 + lane]); };
+    const h8v X = split_inputs(x);
+    h8v H1[NB], H2[NB];
+#pragma unroll
+    for (int mb = 0; mb < NB; ++mb) {
+      const f4v p = __builtin_amdgcn_mfma_f32_16x16x32_f16(A(S::kL1 + mb), X, *(const f4v*)&T.b1[16 * mb + 4 * g],
+                                                           0, 0, 0);
+      const float h[4] = {gelu<PREC>(p[0]), gelu<PREC>(p[1]), gelu<PREC>(p[2]), gelu<PREC>(p[3])};
+      H1[mb] = split_inputs(h);
+    }
+#pragma unroll
+    for (int ob = 0; ob < NB; ++ob) {
+      f4v a = *(const f4v*)&T.b2[16 * ob + 4 * g];
+#pragma unroll
+      for (int kb = 0; kb < NB; ++kb) a = __builtin_amdgcn_mfma_f32_16x16x32_f16(A(S::kL2 + ob * NB + kb), H1[kb], a, 0, 0, 0);
+      const float h[4] = {gelu<PREC>(a[0]), gelu<PREC>(a[1]), gelu<PREC>(a[2]), gelu<PREC>(a[3])};
+      H2[ob] = split_inputs(h);
+    }
+#pragma unroll
+    for (int kb = 0; kb < NB; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(A(S::kL3 + q * NB + kb), H2[kb], acc, 0, 0, 0);
+  } else {
+    auto A = [&](int c) { return __builtin_bit_cast(f4v, T.a[c * 64 + lane]); };
+    float h1[NB][4], h2[NB][4];
+#pragma unroll
+    for (int mb = 0; mb < NB; ++mb) {
+      const f4v w = A(S::kL1 + mb);
+      f4v p = *(const f4v*)&T.b1[16 * mb + 4 * g];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) p = __builtin_amdgcn_mfma_f32_16x16x4f32(w[r], x[r], p, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h1[mb][r] = gelu<PREC>(p[r]);
+    }
+#pragma unroll
+    for (int ob = 0; ob < NB; ++ob) {
+      f4v a = *(const f4v*)&T.b2[16 * ob + 4 * g];
+#pragma unroll
+      for (int kb = 0; kb < NB; ++kb) {
+        const f4v w = A(S::kL2 + ob * NB + kb);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a = __builtin_amdgcn_mfma_f32_16x16x4f32(w[r], h1[kb][r], a, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h2[ob][r] = gelu<PREC>(a[r]);
+    }
+#pragma unroll
+    for (int kb = 0; kb < NB; ++kb) {
+      const f4v w = A(S::kL3 + q * NB + kb);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w[r], h2[kb][r], acc, 0, 0, 0);
+    }
+  }
+}
+
+// The decoder over a wave's 64 texels: r[c] holds chunk c of this lane's own texel on
+// entry; returns the output of the lane's texel.
+template <int PREC, int HD>
+__device__ __forceinline__ f4v hyb_decode(const HybTab<HD>& T, float r[4][4], int lane) {
+  transpose_rows(r);
+  f4v acc = *(const f4v*)T.b3;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) hyb_group<PREC, HD>(T, r[q], q, lane, acc);
+  return acc;
+}
+
+// Linear output (no activation); NaN for queries with a non-finite coordinate.
+template <int PREC>
+__device__ __forceinline__ void store_lin(void* out, size_t idx, const f4v& z, bool nan_out) {
+  float r = z[0], g = z[1], b = z[2];
+  if (nan_out) r = g = b = __builtin_nanf("");
+  if constexpr (PREC == NDGI_PREC_F16) {
+    _Float16* o = (_Float16*)out + idx * 3;
+    o[0] = (_Float16)r;
+    o[1] = (_Float16)g;
+    o[2] = (_Float16)b;
+  } else {
+    float* o = (float*)out + idx * 3;
+    o[0] = r;
+    o[1] = g;
+    o[2] = b;
+  }
+}
+
+// ---------------------------------------------------------------------- time axis
+__device__ __forceinline__ float clamp01(float t) { return fminf(fmaxf(t, 0.0f), 1.0f); }   // NaN -> 0
+
+// Time coordinate tau of a clamped t: piecewise linear through (key_i, i / (n - 1)), clamped
+// to [0, 1]; t itself without a key table.  The segment is the last key <= t (within
+// [0, n-2]), found by a fixed-step binary search.
+template <typename KeyAt>
+__device__ __forceinline__ float key_tau(float tc, int n, KeyAt key) {
+  if (n < 2) return tc;
+  int i = 0;
+  for (int step = NDGI_HYBRID_MAX_KEYS / 2; step > 0; step >>= 1) {
+    const int j = i + step;
+    if (key(min(j, n - 2)) <= tc && j <= n - 2) i = j;   // the read stays inside the table
+  }
+  const float k0 = key(i), k1 = key(i + 1);
+  const float f = (tc - k0) / (k1 - k0);
+  return clamp01(((float)i + f) / (float)(n - 1));
+}
+
+// Linear interpolation over N samples held at tau = k / (N - 1).
+struct NodeT { int i0, i1; float w0, w1; };
+__device__ __forceinline__ NodeT node_axis(float tau, int N) {
+  NodeT a;
+  if (N < 2) {
+    a.i0 = a.i1 = 0;
+    a.w0 = 1.0f;
+    a.w1 = 0.0f;
+    return a;
+  }
+  const float p = tau * (float)(N - 1);
+  a.i0 = min((int)floorf(p), N - 2);
+  a.i1 = a.i0 + 1;
+  a.w1 = p - (float)a.i0;
+  a.w0 = 1.0f - a.w1;
+  return a;
+}
+
+struct HybTime {
+  NodeT s;      // F_uvt slices
+  NodeT k;      // F_ut / F_vt rows
+  float g[4];   // gamma(t)
+};
+
+template <typename KeyAt>
+__device__ __forceinline__ HybTime hyb_time(const ndgi_hybrid_model& m, float t, KeyAt key) {
+  const float tc = clamp01(t);
+  const float tau = key_tau(tc, m.n_keys, key);
+  HybTime h;
+  h.s = node_axis(tau, m.S);
+  h.k = node_axis(tau, m.Tt);
+  float s, c;
+  sincospif(tc, &s, &c);
+  h.g[0] = s;
+  h.g[1] = c;
+  h.g[2] = 2.0f * s * c;
+  h.g[3] = fmaf(c, c, -s * s);
+  return h;
+}
+
+// ---------------------------------------------------------------------- feature maps
+// Four channels of texel slot `slot` of a 32-byte BC4 footprint (channel c in bytes 8c..8c+7).
+__device__ __forceinline__ void bc4_fp4(const uint8_t* fp, uint32_t slot, float v[4]) {
+  const u4v a = ((const u4v*)fp)[0], b = ((const u4v*)fp)[1];
+  v[0] = bc4_texel_f(a.x, a.y, slot);
+  v[1] = bc4_texel_f(a.z, a.w, slot);
+  v[2] = bc4_texel_f(b.x, b.y, slot);
+  v[3] = bc4_texel_f(b.z, b.w, slot);
+}
+
+// Bilinear sample (4 channels, values / 255) of a block-compressed map of bw footprints per
+// row starting at `base`, accumulated into x with weight ws.
+__device__ __forceinline__ void bc4_bilinear4(const uint8_t* base, uint32_t bw, const Axis& ax, const Axis& ay,
+                                              float ws, float x[4]) {
+  float w[4];
+  tap_weights(ax, ay, w);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t y = (uint32_t)((i & 2) ? ay.i1 : ay.i0), xx = (uint32_t)((i & 1) ? ax.i1 : ax.i0);
+    float v[4];
+    bc4_fp4(base + ((y >> 2) * bw + (xx >> 2)) * 32u, 4u * (y & 3u) + (xx & 3u), v);
+    const float wi = ws * w[i] * (1.0f / 255.0f);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) x[c] = fmaf(wi, v[c], x[c]);
+  }
+}
+
+// Two-channel 8-bit plane [N][size][2] sampled at coordinate c (texel centres) and rows k.
+__device__ __forceinline__ void plane2(const uint8_t* p, int size, const Axis& a, const NodeT& k, float& r0,
+                                       float& r1) {
+  const uint16_t* q = (const uint16_t*)p;
+  r0 = r1 = 0.0f;
+#pragma unroll
+  for (int kk = 0; kk < 2; ++kk) {
+    const uint32_t row = (uint32_t)(kk ? k.i1 : k.i0) * (uint32_t)size;
+    const float wk = (kk ? k.w1 : k.w0) * (1.0f / 255.0f);
+#pragma unroll
+    for (int aa = 0; aa < 2; ++aa) {
+      const uint32_t v = q[row + (uint32_t)(aa ? a.i1 : a.i0)];
+      const float w = wk * (aa ? a.w1 : a.w0);
+      r0 = fmaf(w, (float)(v & 0xffu), r0);
+      r1 = fmaf(w, (float)(v >> 8), r1);
+    }
+  }
+}
+
+// The 16 decoder inputs of an explicit query, as four chunks.
+__device__ __forceinline__ void hyb_query_feats(const ndgi_hybrid_model& m, float u, float v, const HybTime& ht,
+                                                float r[4][4]) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) r[0][c] = r[1][c] = 0.0f;
+  const Axis gx = coord_axis(u, m.Gu), gy = coord_axis(v, m.Gv);
+  const uint32_t gbw = (uint32_t)m.Gu >> 2, slice = gbw * ((uint32_t)m.Gv >> 2) * 32u;
+  bc4_bilinear4(m.fuvt + (uint32_t)ht.s.i0 * slice, gbw, gx, gy, ht.s.w0, r[0]);
+  bc4_bilinear4(m.fuvt + (uint32_t)ht.s.i1 * slice, gbw, gx, gy, ht.s.w1, r[0]);
+  bc4_bilinear4(m.fuv, (uint32_t)m.W >> 2, coord_axis(u, m.W), coord_axis(v, m.H), 1.0f, r[1]);
+  plane2(m.fut, m.U, coord_axis(u, m.U), ht.k, r[2][0], r[2][1]);
+  plane2(m.fvt, m.V, coord_axis(v, m.V), ht.k, r[2][2], r[2][3]);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) r[3][c] = ht.g[c];
+}
+
+// Descriptor ranges (host and device: page requests carry descriptors in device memory).
+__host__ __device__ inline bool hybrid_ok(const ndgi_hybrid_model& m) {
+  const bool dims = m.W >= 4 && m.H >= 4 && m.W <= 16384 && m.H <= 16384 && (m.W & 3) == 0 && (m.H & 3) == 0 &&
+                    m.Gu >= 4 && m.Gv >= 4 && m.Gu <= m.W && m.Gv <= m.H && (m.Gu & 3) == 0 && (m.Gv & 3) == 0 &&
+                    m.S >= 1 && m.S <= 1024 && m.U >= 1 && m.U <= m.W && m.V >= 1 && m.V <= m.H && m.Tt >= 1 &&
+                    m.Tt <= 1024;
+  const bool kinds = (m.hidden == 16 || m.hidden == 64) &&
+                     (m.mlp_dtype == NDGI_DTYPE_F32 || m.mlp_dtype == NDGI_DTYPE_F16) &&
+                     (m.n_keys == 0 || (m.n_keys >= 2 && m.n_keys <= NDGI_HYBRID_MAX_KEYS)) && m.reserved0 == 0;
+  const bool bufs = m.fuv && m.fuvt && m.fut && m.fvt && m.mlp && (m.n_keys == 0 || m.keys);
+  // F_uvt offsets are 32-bit: S * Gu * Gv * 2 bytes below 4 GiB
+  return dims && kinds && bufs && (uint64_t)m.S * (uint64_t)m.Gu * (uint64_t)m.Gv * 2u < (1ull << 32);
+}
+
+// ---------------------------------------------------------------------- query decode
+// Grid-stride passes of 64 consecutive queries per wave (one query per lane in the feature
+// phase, the decoder after the handoff); the decoder table and the key table are built
+// once per workgroup in LDS.
+template <int PREC, int HD>
+__global__ __launch_bounds__(256) void k_hybrid_query(ndgi_hybrid_model m, const float* __restrict__ uvt, int64_t n,
+                                                       void* __restrict__ out) {
+  __shared__ HybTab<HD> tab;
+  __shared__ float keys[NDGI_HYBRID_MAX_KEYS];
+  hyb_build<PREC, HD>(tab, m.mlp, m.mlp_dtype);
+  for (int i = threadIdx.x; i < m.n_keys; i += 256) keys[i] = m.keys[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t passes = (n + 63) >> 6;
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  for (int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); p < passes; p += nwaves) {
+    const int64_t mine = (p << 6) + lane;
+    const int64_t qi = mine < n ? mine : n - 1;
+    float u = uvt[qi * 3 + 0], v = uvt[qi * 3 + 1], t = uvt[qi * 3 + 2];
+    const bool bad = !(isfinite(u) && isfinite(v) && isfinite(t));
+    if (bad) u = v = t = 0.0f;
+    const HybTime ht = hyb_time(m, t, [&](int i) { return keys[i]; });
+    float r[4][4];
+    hyb_query_feats(m, u, v, ht, r);
+    const f4v acc = hyb_decode<PREC, HD>(tab, r, lane);
+    if (mine < n) store_lin<PREC>(out, (size_t)mine, acc, bad);
+  }
+}
+
+// ---------------------------------------------------------------------- page decode
+// Work item = (request, 32 x 32 sub-tile of its page), one workgroup per item, items
+// round-robin over a persistent grid.  Per item the workgroup stages in LDS:
+//  * the F_uvt nodes the sub-tile reads, decoded from both slices around tau and blended
+//    in time (at most 33 x 33 nodes, since Gu <= W and Gv <= H);
+//  * the F_ut row span and the F_vt column span it reads, blended in time;
+// then each pass of a wave decodes two rows of 32 texel centres: the F_uv texel straight
+// from its block (at a texel centre the bilinear weights are 1 and 0), the other maps from
+// LDS.  Texel-centre axes use exact integer arithmetic (texel_axis).
+constexpr int kHybSub = 32;
+constexpr int kHybWin = kHybSub + 1;
+
+template <int PREC, int HD>
+__global__ __launch_bounds__(256) void k_hybrid_pages(const ndgi_hybrid_model* __restrict__ models, int32_t n_models,
+                                                       const ndgi_page_req* __restrict__ reqs,
+                                                       const int32_t* __restrict__ n_reqs_dev, int32_t max_reqs,
+                                                       int32_t page, void* __restrict__ dst, int64_t pitch,
+                                                       uint32_t* __restrict__ flags) {
+  __shared__ HybTab<HD> tab;
+  __shared__ f4v win[kHybWin * kHybWin];
+  __shared__ float2 line_u[kHybWin], line_v[kHybWin];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int n_req = *n_reqs_dev;
+  n_req = n_req < 0 ? 0 : (n_req > max_reqs ? max_reqs : n_req);
+  const int side = page / kHybSub;
+  const int64_t per_req = (int64_t)side * side;
+  const int64_t total = (int64_t)n_req * per_req;
+  int cur = -1;
+  for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    const int r = (int)(it / per_req), s = (int)(it - (int64_t)r * per_req);
+    const ndgi_page_req rq = reqs[r];
+    bool ok = rq.model >= 0 && rq.model < n_models && rq.page_x >= 0 && rq.page_y >= 0;
+    ndgi_hybrid_model m = {};
+    if (ok) m = models[rq.model];
+    ok = ok && hybrid_ok(m) && (int64_t)page * (rq.page_x + 1) <= m.W && (int64_t)page * (rq.page_y + 1) <= m.H;
+    if (!ok) {
+      if (threadIdx.x == 0 && s == 0) atomicOr(flags, NDGI_FLAG_BAD_PAGE_REQUEST);
+      continue;
+    }
+    if (m.hidden != HD) continue;   // served by the launch of the other width
+    __syncthreads();                // the previous item's readers of the table and windows are done
+    if (rq.model != cur) {
+      hyb_build<PREC, HD>(tab, m.mlp, m.mlp_dtype);
+      cur = rq.model;
+    }
+    const bool bad_t = !isfinite(rq.t);
+    const HybTime ht = hyb_time(m, bad_t ? 0.0f : rq.t, [&](int i) { return m.keys[i]; });
+    const int px0 = page * rq.page_x, py0 = page * rq.page_y;
+    const int x0 = px0 + (s % side) * kHybSub, y0 = py0 + (s / side) * kHybSub;
+    // node spans of the sub-tile; clamped to the LDS window (never reached when Gu <= W)
+    const int wx0 = texel_axis<false>(x0, m.Gu, m.W).i0, wy0 = texel_axis<false>(y0, m.Gv, m.H).i0;
+    const int nwx = min(texel_axis<false>(x0 + kHybSub - 1, m.Gu, m.W).i1 - wx0 + 1, kHybWin);
+    const int nwy = min(texel_axis<false>(y0 + kHybSub - 1, m.Gv, m.H).i1 - wy0 + 1, kHybWin);
+    const int ua0 = texel_axis<false>(x0, m.U, m.W).i0, va0 = texel_axis<false>(y0, m.V, m.H).i0;
+    const int nua = min(texel_axis<false>(x0 + kHybSub - 1, m.U, m.W).i1 - ua0 + 1, kHybWin);
+    const int nva = min(texel_axis<false>(y0 + kHybSub - 1, m.V, m.H).i1 - va0 + 1, kHybWin);
+    {
+      const uint32_t gbw = (uint32_t)m.Gu >> 2, slice = gbw * ((uint32_t)m.Gv >> 2) * 32u;
+      const uint8_t* s0 = m.fuvt + (uint32_t)ht.s.i0 * slice;
+      const uint8_t* s1 = m.fuvt + (uint32_t)ht.s.i1 * slice;
+      for (int idx = threadIdx.x; idx < nwx * nwy; idx += 256) {
+        const uint32_t gy = (uint32_t)(wy0 + idx / nwx), gx = (uint32_t)(wx0 + idx % nwx);
+        const uint32_t off = ((gy >> 2) * gbw + (gx >> 2)) * 32u, slot = 4u * (gy & 3u) + (gx & 3u);
+        float a[4], b[4];
+        bc4_fp4(s0 + off, slot, a);
+        bc4_fp4(s1 + off, slot, b);
+        f4v o;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) o[c] = fmaf(ht.s.w1, b[c], ht.s.w0 * a[c]) * (1.0f / 255.0f);
+        win[idx] = o;
+      }
+      const uint16_t* fu = (const uint16_t*)m.fut;
+      const uint16_t* fv = (const uint16_t*)m.fvt;
+      const int t = threadIdx.x;
+      if (t < nua || (t >= 64 && t - 64 < nva)) {
+        const bool isu = t < 64;
+        const uint16_t* pl = isu ? fu : fv;
+        const uint32_t size = (uint32_t)(isu ? m.U : m.V), a = (uint32_t)(isu ? ua0 + t : va0 + t - 64);
+        const uint32_t q0 = pl[(uint32_t)ht.k.i0 * size + a], q1 = pl[(uint32_t)ht.k.i1 * size + a];
+        const float2 o = make_float2(fmaf(ht.k.w1, (float)(q1 & 0xffu), ht.k.w0 * (float)(q0 & 0xffu)) * (1.0f / 255.0f),
+                                     fmaf(ht.k.w1, (float)(q1 >> 8), ht.k.w0 * (float)(q0 >> 8)) * (1.0f / 255.0f));
+        if (isu) line_u[t] = o;
+        else line_v[t - 64] = o;
+      }
+    }
+    __syncthreads();                // table and windows complete
+    const int x = x0 + (lane & 31);
+    const Axis gx = texel_axis<false>(x, m.Gu, m.W), ux = texel_axis<false>(x, m.U, m.W);
+    const int gx0 = min(max(gx.i0 - wx0, 0), nwx - 1), gx1 = min(max(gx.i1 - wx0, 0), nwx - 1);
+    const float2 ut0 = line_u[min(max(ux.i0 - ua0, 0), nua - 1)], ut1 = line_u[min(max(ux.i1 - ua0, 0), nua - 1)];
+    const float2 vut = make_float2(fmaf(ux.w1, ut1.x, ux.w0 * ut0.x), fmaf(ux.w1, ut1.y, ux.w0 * ut0.y));
+    const uint32_t fbw = (uint32_t)m.W >> 2;
+    for (int p = wave; p < kHybSub * kHybSub / 64; p += 4) {
+      const int y = y0 + 2 * p + (lane >> 5);
+      float rr[4][4];
+      // V_uvt: bilinear over the staged nodes
+      const Axis gy = texel_axis<false>(y, m.Gv, m.H);
+      const int gy0 = min(max(gy.i0 - wy0, 0), nwy - 1), gy1 = min(max(gy.i1 - wy0, 0), nwy - 1);
+      const f4v c00 = win[gy0 * nwx + gx0], c01 = win[gy0 * nwx + gx1];
+      const f4v c10 = win[gy1 * nwx + gx0], c11 = win[gy1 * nwx + gx1];
+      float w[4];
+      tap_weights(gx, gy, w);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) rr[0][c] = fmaf(w[3], c11[c], fmaf(w[2], c10[c], fmaf(w[1], c01[c], w[0] * c00[c])));
+      // V_uv: the texel itself
+      float sv[4];
+      bc4_fp4(m.fuv + ((uint32_t)(y >> 2) * fbw + (uint32_t)(x >> 2)) * 32u, 4u * (uint32_t)(y & 3) + (uint32_t)(x & 3),
+              sv);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) rr[1][c] = sv[c] * (1.0f / 255.0f);
+      // V_ut (per column), V_vt (per row)
+      const Axis vy = texel_axis<false>(y, m.V, m.H);
+      const float2 vt0 = line_v[min(max(vy.i0 - va0, 0), nva - 1)], vt1 = line_v[min(max(vy.i1 - va0, 0), nva - 1)];
+      rr[2][0] = vut.x;
+      rr[2][1] = vut.y;
+      rr[2][2] = fmaf(vy.w1, vt1.x, vy.w0 * vt0.x);
+      rr[2][3] = fmaf(vy.w1, vt1.y, vy.w0 * vt0.y);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) rr[3][c] = ht.g[c];
+      const f4v acc = hyb_decode<PREC, HD>(tab, rr, lane);
+      store_lin<PREC>(dst, (size_t)(rq.dst_offset + (int64_t)(y - py0) * pitch + (x - px0)), acc, bad_t);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------- host side
+int check_hybrid(const ndgi_hybrid_model* m, const char* who) {
+  if (!m) return fail(NDGI_ERR_INVALID_ARG, "%s: model is NULL", who);
+  if (!hybrid_ok(*m))
+    return fail(NDGI_ERR_INVALID_ARG,
+                "%s: hybrid descriptor out of range (W %d H %d Gu %d Gv %d S %d U %d V %d Tt %d hidden %d "
+                "mlp_dtype %d n_keys %d, or a NULL buffer)",
+                who, m->W, m->H, m->Gu, m->Gv, m->S, m->U, m->V, m->Tt, m->hidden, m->mlp_dtype, m->n_keys);
+  return NDGI_OK;
+}
+
+int launch_hybrid_query(ndgi_ctx* ctx, const ndgi_hybrid_model& m, const float* uvt, int64_t n, void* out, int prec,
+                        hipStream_t s) {
+  if (n == 0) return NDGI_OK;
+  const int64_t want = ((n + 63) / 64 + 3) / 4;
+#define NDGI_HQ(P, HD)                                                                           \
+  do {                                                                                           \
+    int64_t wgs = resident_wgs(ctx, (const void*)k_hybrid_query<P, HD>);                         \
+    if (wgs > want) wgs = want;                                                                  \
+    hipLaunchKernelGGL((k_hybrid_query<P, HD>), dim3((unsigned)wgs), dim3(256), 0, s, m, uvt, n, out); \
+  } while (0)
+  if (prec == NDGI_PREC_F16) {
+    if (m.hidden == 16) NDGI_HQ(NDGI_PREC_F16, 16);
+    else NDGI_HQ(NDGI_PREC_F16, 64);
+  } else {
+    if (m.hidden == 16) NDGI_HQ(NDGI_PREC_F32, 16);
+    else NDGI_HQ(NDGI_PREC_F32, 64);
+  }
+#undef NDGI_HQ
+  NDGI_HIP(hipGetLastError());
+  return NDGI_OK;
+}
+
+int launch_hybrid_pages(ndgi_ctx* ctx, const ndgi_hybrid_model* models, int32_t n_models, const ndgi_page_req* reqs,
+                        const int32_t* n_reqs, int32_t max_reqs, int32_t page, void* dst, int64_t pitch, int prec,
+                        hipStream_t s) {
+  // one launch per decoder width; each skips the requests of the other
+#define NDGI_HP(P, HD)                                                                                           \
+  hipLaunchKernelGGL((k_hybrid_pages<P, HD>), dim3(resident_wgs(ctx, (const void*)k_hybrid_pages<P, HD>)), dim3(256), \
+                     0, s, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, ctx->flags_dev)
+  if (prec == NDGI_PREC_F16) {
+    NDGI_HP(NDGI_PREC_F16, 16);
+    NDGI_HP(NDGI_PREC_F16, 64);
+  } else {
+    NDGI_HP(NDGI_PREC_F32, 16);
+    NDGI_HP(NDGI_PREC_F32, 64);
+  }
+#undef NDGI_HP
+  NDGI_HIP(hipGetLastError());
+  return NDGI_OK;
+}
+
+}  // namespace ndgi

@@ -22,7 +22,8 @@ void clear_error();
     if (e_ != hipSuccess) return ::ndgi::fail(NDGI_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-using GraphKey = std::tuple<const void*, int32_t, const void*, const void*, int32_t, int32_t,
+// (layout kind, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, stream)
+using GraphKey = std::tuple<int, const void*, int32_t, const void*, const void*, int32_t, int32_t,
                             void*, int64_t, int32_t, hipStream_t>;
 
 // Workgroups of 256 threads that one launch may keep resident: CUs x the kernel's
@@ -61,4 +62,10 @@ int launch_bc4_blocks(const uint8_t* blocks, int64_t n, uint8_t* out, hipStream_
 int binned_workspace(const ndgi_model& m, int64_t n, int64_t* bytes);
 int launch_decode_binned(ndgi_ctx* ctx, const ndgi_model& m, const float* uvt, int64_t n, void* out, int prec,
                          void* ws, int64_t ws_bytes, hipStream_t s);
+int check_hybrid(const ndgi_hybrid_model* m, const char* who);
+int launch_hybrid_query(ndgi_ctx* ctx, const ndgi_hybrid_model& m, const float* uvt, int64_t n, void* out, int prec,
+                        hipStream_t s);
+int launch_hybrid_pages(ndgi_ctx* ctx, const ndgi_hybrid_model* models, int32_t n_models, const ndgi_page_req* reqs,
+                        const int32_t* n_reqs, int32_t max_reqs, int32_t page, void* dst, int64_t pitch, int prec,
+                        hipStream_t s);
 }  // namespace ndgi

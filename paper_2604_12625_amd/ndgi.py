@@ -25,6 +25,8 @@ EXPORTED = (
     "ndgi_bc4_decode_blocks", "ndgi_decode", "ndgi_decode_pages", "ndgi_decode_pages_graph",
     "ndgi_set_launch", "ndgi_train_param_count", "ndgi_train_step", "ndgi_export",
     "ndgi_tile_stats", "ndgi_decode_binned_workspace", "ndgi_decode_binned",
+    "ndgi_hybrid_mlp_size", "ndgi_hybrid_decode", "ndgi_hybrid_decode_pages",
+    "ndgi_hybrid_decode_pages_graph",
 )
 
 
@@ -54,7 +56,15 @@ class NdgiBatch(C.Structure):
                 ("pred", C.c_void_p), ("grad_pred", C.c_void_p)]
 
 
-assert C.sizeof(NdgiModel) == 64 and C.sizeof(NdgiPageReq) == 24
+class NdgiHybridModel(C.Structure):
+    _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("Gu", C.c_int32), ("Gv", C.c_int32),
+                ("S", C.c_int32), ("U", C.c_int32), ("V", C.c_int32), ("Tt", C.c_int32),
+                ("hidden", C.c_int32), ("mlp_dtype", C.c_int32), ("n_keys", C.c_int32),
+                ("reserved0", C.c_int32), ("fuv", C.c_void_p), ("fuvt", C.c_void_p),
+                ("fut", C.c_void_p), ("fvt", C.c_void_p), ("keys", C.c_void_p), ("mlp", C.c_void_p)]
+
+
+assert C.sizeof(NdgiModel) == 64 and C.sizeof(NdgiPageReq) == 24 and C.sizeof(NdgiHybridModel) == 96
 
 
 class NdgiError(RuntimeError):
@@ -90,6 +100,11 @@ def lib():
         L.ndgi_tile_stats.argtypes = [vp, vp, i32, vp, i32, i32, i32, vp, vp]
         L.ndgi_decode_binned_workspace.argtypes = [C.POINTER(NdgiModel), i64, C.POINTER(i64)]
         L.ndgi_decode_binned.argtypes = [vp, C.POINTER(NdgiModel), vp, i64, vp, i32, vp, i64, vp]
+        L.ndgi_hybrid_mlp_size.argtypes = [i32]
+        L.ndgi_hybrid_mlp_size.restype = i32
+        L.ndgi_hybrid_decode.argtypes = [vp, C.POINTER(NdgiHybridModel), vp, i64, vp, i32, vp]
+        L.ndgi_hybrid_decode_pages.argtypes = pages
+        L.ndgi_hybrid_decode_pages_graph.argtypes = pages
         _lib = L
     return _lib
 
@@ -134,6 +149,36 @@ class DeviceModel:
 
     def desc_bytes(self) -> bytes:
         return bytes(self.desc)
+
+
+class HybridModel:
+    """A model in the paper's hybrid layout (F_uv, F_uvt, F_ut, F_vt, key times, decoder)
+    whose arrays live in device memory (torch tensors)."""
+
+    def __init__(self, W, H, Gu, Gv, S, U, V, Tt, hidden, fuv, fuvt, fut, fvt, keys, mlp):
+        import torch
+        self.arrays = [a.contiguous() for a in (fuv, fuvt, fut, fvt, keys, mlp)]
+        fuv, fuvt, fut, fvt, keys, mlp = self.arrays
+        dt = {torch.float32: DTYPE_F32, torch.float16: DTYPE_F16}
+        nk = keys.numel()
+        self.desc = NdgiHybridModel(int(W), int(H), int(Gu), int(Gv), int(S), int(U), int(V), int(Tt),
+                                    int(hidden), dt[mlp.dtype], nk, 0, fuv.data_ptr(), fuvt.data_ptr(),
+                                    fut.data_ptr(), fvt.data_ptr(), keys.data_ptr() if nk else None,
+                                    mlp.data_ptr())
+
+    @classmethod
+    def from_numpy(cls, m: dict, device="cuda"):
+        import torch
+        t = {k: torch.from_numpy(m[k]).to(device) for k in ("fuv", "fuvt", "fut", "fvt", "keys", "mlp")}
+        return cls(m["W"], m["H"], m["Gu"], m["Gv"], m["S"], m["U"], m["V"], m["Tt"], m["hidden"],
+                   t["fuv"], t["fuvt"], t["fut"], t["fvt"], t["keys"].to(torch.float32), t["mlp"])
+
+    def desc_bytes(self) -> bytes:
+        return bytes(self.desc)
+
+
+def hybrid_mlp_size(hidden: int) -> int:
+    return int(lib().ndgi_hybrid_mlp_size(hidden))
 
 
 class Context:
@@ -195,6 +240,23 @@ class Context:
                 page, _ptr(dst), pitch, prec, _stream(stream)), "ndgi_decode_pages")
         return dst
 
+    def hybrid_decode(self, model: HybridModel, uvt, prec=PREC_F16, out=None, stream=None):
+        import torch
+        n = uvt.shape[0]
+        if out is None:
+            out = torch.empty((n, 3), dtype=torch.float16 if prec == PREC_F16 else torch.float32,
+                              device=uvt.device)
+        check(lib().ndgi_hybrid_decode(self.h, C.byref(model.desc), _ptr(uvt), n, _ptr(out), prec,
+                                       _stream(stream)), "ndgi_hybrid_decode")
+        return out
+
+    def hybrid_decode_pages(self, models_dev, n_models, reqs_dev, n_reqs_dev, max_reqs, page, dst,
+                            pitch, prec=PREC_F16, graph=False, stream=None):
+        f = lib().ndgi_hybrid_decode_pages_graph if graph else lib().ndgi_hybrid_decode_pages
+        check(f(self.h, _ptr(models_dev), n_models, _ptr(reqs_dev), _ptr(n_reqs_dev), max_reqs,
+                page, _ptr(dst), pitch, prec, _stream(stream)), "ndgi_hybrid_decode_pages")
+        return dst
+
     def set_launch(self, tile_w, tile_h, waves_per_cu):
         check(lib().ndgi_set_launch(self.h, tile_w, tile_h, waves_per_cu), "ndgi_set_launch")
 
@@ -227,7 +289,8 @@ def bc4_decode_blocks(blocks, out=None, stream=None):
 
 
 def models_array(models, device="cuda"):
-    """Device array of ndgi_model descriptors (keeps no reference to the models)."""
+    """Device array of ndgi_model (or ndgi_hybrid_model) descriptors (keeps no reference to
+    the models)."""
     import torch
     raw = b"".join(m.desc_bytes() for m in models)
     return torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)

@@ -70,3 +70,13 @@ def test_binned_workspace_size_query():
     assert b"8192" in L.ndgi_last_error() or b"tiles" in L.ndgi_last_error()
     assert L.ndgi_decode_binned_workspace(ctypes.byref(m), -1, ctypes.byref(b)) == ndgi.ERR_INVALID_ARG
     assert L.ndgi_decode_binned_workspace(ctypes.byref(m), 1 << 31, ctypes.byref(b)) == ndgi.ERR_INVALID_ARG
+
+
+def test_hybrid_mlp_size_is_host_arithmetic():
+    """Packed decoder lengths of the hybrid layout: 16-h-h-3 with biases."""
+    from paper_2604_12625_amd import ndgi
+    if not os.path.exists(ndgi.LIB_PATH):
+        pytest.skip("libndgi.so not built (run __graft_entry__.build())")
+    assert ndgi.hybrid_mlp_size(16) == 16 * 16 + 16 + 16 * 16 + 16 + 3 * 16 + 3 == 595
+    assert ndgi.hybrid_mlp_size(64) == 64 * 16 + 64 + 64 * 64 + 64 + 3 * 64 + 3 == 5443
+    assert ndgi.hybrid_mlp_size(32) == -1

@@ -1,0 +1,249 @@
+"""GPU parity of the hybrid-layout decode (Sec. 3.3, Eq. 4: F_uvt, F_uv, F_ut, F_vt,
+gamma(t) into the GELU decoder) against the CPU oracle, through the C ABI.
+
+The decoder output is linear, so a plain relative error is undefined where the output
+crosses zero.  The statistic is |gpu - oracle| / max(|oracle|, rms), with rms the root mean
+square of the oracle's outputs over the compared set: a relative error for outputs of
+typical size and an error relative to the output scale near zero.  Bounds: 2e-3 on the
+FP16 path, 1e-5 on the FP32 path (max over the compared set)."""
+import numpy as np
+import pytest
+
+from oracle import ndgi_oracle as O
+from paper_2604_12625_amd import inputs as I
+from tests.gpu_util import torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+TOL = {1: 2e-3, 0: 1e-5}
+
+
+def scaled_err(gpu, ref):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    rms = np.sqrt(np.mean(ref[np.isfinite(ref)] ** 2))
+    return np.abs(gpu - ref) / np.maximum(np.abs(ref), rms)
+
+
+def assert_close(gpu, ref, tol, what=""):
+    e = scaled_err(gpu, ref)
+    worst = float(np.max(e)) if e.size else 0.0
+    assert worst <= tol, f"{what}: max scaled err {worst:.3e} > {tol:.1e} (p99.9 {np.quantile(e, 0.999):.3e})"
+    return worst
+
+
+@pytest.fixture(scope="module")
+def N():
+    torch_cuda()
+    from paper_2604_12625_amd import ndgi
+    return ndgi
+
+
+@pytest.fixture(scope="module")
+def ctx(N):
+    c = N.Context(0)
+    yield c
+    c.close()
+
+
+def _dec(N, ctx, m, q, prec):
+    import torch
+    hm = N.HybridModel.from_numpy(m)
+    out = ctx.hybrid_decode(hm, torch.from_numpy(q).cuda(), prec)
+    torch.cuda.synchronize()
+    return out.float().cpu().numpy()
+
+
+@pytest.mark.parametrize("profile", ["L", "M", "H", "M.64"])
+@pytest.mark.parametrize("prec", [1, 0])
+def test_hybrid_queries_match_oracle(N, ctx, profile, prec):
+    m = I.random_hybrid_model(profile=profile, config=40)
+    q = I.uniform_queries(4096 + 37, I.rng(40, I.P_QUERY))
+    assert_close(_dec(N, ctx, m, q, prec), O.hybrid_decode(m, q), TOL[prec], f"{profile} prec {prec}")
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_hybrid_fp32_weights_no_keys_single_slice(N, ctx, prec):
+    m = I.random_hybrid_model(192, 96, profile="M", slices=1, plane=(48, 96, 1), mlp_dtype=np.float32,
+                              keys=False, config=41, uvt_side=(24, 16))
+    q = I.uniform_queries(3000, I.rng(41, I.P_QUERY))
+    assert_close(_dec(N, ctx, m, q, prec), O.hybrid_decode(m, q), TOL[prec], "S = 1, Tt = 1")
+    m = I.random_hybrid_model(256, 128, profile="M.64", slices=5, plane=(256, 3, 7), mlp_dtype=np.float32,
+                              keys=False, config=42, uvt_side=(256, 128))
+    q = I.uniform_queries(3000, I.rng(42, I.P_QUERY))
+    assert_close(_dec(N, ctx, m, q, prec), O.hybrid_decode(m, q), TOL[prec], "full-res F_uvt")
+
+
+def test_hybrid_edges_clamp_time_and_nan(N, ctx):
+    m = I.random_hybrid_model(profile="M", config=43)
+    q = np.array([[-0.5, 0.5, 0.2], [1.7, 0.5, 0.2], [0.5, -3.0, 0.2], [0.5, 9.0, 0.2],
+                  [0.3, 0.6, -0.5], [0.3, 0.6, 1.5], [0.3, 0.6, 0.0], [0.3, 0.6, 1.0],
+                  [0.3, 0.6, float(m["keys"][3])], [0.3, 0.6, float(m["keys"][-1])],
+                  [np.nan, 0.5, 0.5], [0.5, np.inf, 0.5], [0.5, 0.5, -np.inf]], dtype=np.float32)
+    for prec in (1, 0):
+        got = _dec(N, ctx, m, q, prec)
+        ref = O.hybrid_decode(m, q)
+        assert np.isnan(got[-3:]).all()
+        assert_close(got[:-3], ref[:-3], TOL[prec], f"edges prec {prec}")
+
+
+@pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 100_003])
+def test_hybrid_ragged_counts(N, ctx, n):
+    import torch
+    m = I.random_hybrid_model(profile="M.64", config=44)
+    q = I.uniform_queries(max(n, 1), I.rng(44, I.P_QUERY, n))[:n]
+    hm = N.HybridModel.from_numpy(m)
+    out = torch.full((n + 5, 3), -7.0, dtype=torch.float16, device="cuda")
+    ctx.hybrid_decode(hm, torch.from_numpy(q).cuda(), 1, out=out[:n] if n else out[:0])
+    torch.cuda.synchronize()
+    o = out.float().cpu().numpy()
+    np.testing.assert_array_equal(o[n:], -7.0)
+    if n:
+        sel = np.arange(n) if n < 5000 else np.random.default_rng(n).integers(0, n, 5000)
+        assert_close(o[sel], O.hybrid_decode(m, q[sel]), TOL[1], f"n={n}")
+
+
+def test_hybrid_argument_errors(N, ctx):
+    import torch
+    m = I.random_hybrid_model(profile="M", config=45)
+    hm = N.HybridModel.from_numpy(m)
+    q = torch.zeros((4, 3), dtype=torch.float32, device="cuda")
+    for field, val in (("hidden", 32), ("Gu", 256), ("U", 0), ("S", 0), ("n_keys", 1), ("n_keys", 300),
+                       ("W", 130), ("reserved0", 1), ("mlp_dtype", 7)):
+        bad = N.HybridModel.from_numpy(m)
+        setattr(bad.desc, field, val)
+        with pytest.raises(N.NdgiError):
+            ctx.hybrid_decode(bad, q, 1)
+    with pytest.raises(N.NdgiError):
+        ctx.hybrid_decode(hm, q, 5)
+    assert ctx.hybrid_decode(hm, q[:0], 1).shape == (0, 3)
+
+
+# ------------------------------------------------------------------------------ pages
+def _hyb_vt(seed):
+    """Eight per-tile models (all four profiles, mixed widths) plus two 256^2 maps; page
+    requests over them, some invalid (model index or page out of range)."""
+    models = [I.random_hybrid_model(profile=p, config=50 + seed, index=i, keys=(i % 3 != 0))
+              for i, p in enumerate(["L", "M", "H", "M.64", "M", "L", "M.64", "H"])]
+    models.append(I.random_hybrid_model(256, 256, profile="M", plane=(128, 128, 24), config=50 + seed, index=8,
+                                        uvt_side=(64, 64)))
+    models.append(I.random_hybrid_model(256, 256, profile="M.64", plane=(128, 128, 24), config=50 + seed,
+                                        index=9, uvt_side=(64, 64)))
+    g = np.random.default_rng(seed)
+    reqs = []
+    for r in range(40):
+        mi = int(g.integers(0, len(models)))
+        n = models[mi]["W"] // 128
+        px, py = int(g.integers(0, n)), int(g.integers(0, n))
+        reqs.append((mi, px, py, float(np.float32(g.random() * 1.2 - 0.1)), (r // 8) * 128 * 1024 + (r % 8) * 128))
+    reqs[5] = (len(models) + 3, 0, 0, 0.5, reqs[5][4])       # model out of range
+    reqs[11] = (1, 1, 0, 0.5, reqs[11][4])                   # page outside a 128^2 map
+    reqs[17] = (8, 0, 2, 0.5, reqs[17][4])                   # page outside a 256^2 map
+    return models, reqs
+
+
+def _run_hpages(N, ctx, models, reqs, prec, graph=False):
+    import torch
+    hms = [N.HybridModel.from_numpy(m) for m in models]
+    marr = N.models_array(hms)
+    r = np.array(reqs, dtype=object)
+    rq = N.page_requests(r[:, 0].astype(np.int32), r[:, 1].astype(np.int32), r[:, 2].astype(np.int32),
+                         r[:, 3].astype(np.float32), r[:, 4].astype(np.int64))
+    nreq = torch.tensor([len(reqs)], dtype=torch.int32, device="cuda")
+    rows = (len(reqs) + 7) // 8 * 128
+    dt = torch.float16 if prec else torch.float32
+    dst = torch.full((rows * 1024, 3), -7.0, dtype=dt, device="cuda")
+    ctx.hybrid_decode_pages(marr, len(models), rq, nreq, len(reqs), 128, dst, 1024, prec, graph=graph)
+    torch.cuda.synchronize()
+    return dst.float().cpu().numpy(), (hms, marr, rq, nreq, dst)
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_hybrid_pages_many_models_and_bad_requests(N, ctx, prec):
+    models, reqs = _hyb_vt(3)
+    out, _ = _run_hpages(N, ctx, models, reqs, prec)
+    assert ctx.error_flags() & N.FLAG_BAD_PAGE_REQUEST
+    ref = np.full(out.shape, -7.0)
+    assert O.hybrid_decode_pages(models, reqs, 128, ref, 1024) == 3
+    valid = ref[:, 0] != -7.0
+    assert_close(out[valid], ref[valid], TOL[prec], "hybrid pages")
+    np.testing.assert_array_equal(out[~valid], -7.0)
+
+
+def test_hybrid_pages_graph_replay_with_new_requests(N, ctx):
+    models, reqs = _hyb_vt(4)
+    reqs = [r for i, r in enumerate(reqs) if i not in (5, 11, 17)][:24]
+    reqs = [(m, px, py, t, (r // 8) * 128 * 1024 + (r % 8) * 128) for r, (m, px, py, t, _) in enumerate(reqs)]
+    out1, keep = _run_hpages(N, ctx, models, reqs, 1, graph=True)
+    hms, marr, rq, nreq, dst = keep
+    ref = np.full(out1.shape, -7.0)
+    O.hybrid_decode_pages(models, reqs, 128, ref, 1024)
+    v = ref[:, 0] != -7.0
+    assert_close(out1[v], ref[v], TOL[1], "graph #1")
+    reqs2 = [(m, px, py, float(np.float32((t + 0.37) % 1.0)), off) for (m, px, py, t, off) in reqs]
+    r = np.array(reqs2, dtype=object)
+    rq.copy_(N.page_requests(r[:, 0].astype(np.int32), r[:, 1].astype(np.int32), r[:, 2].astype(np.int32),
+                             r[:, 3].astype(np.float32), r[:, 4].astype(np.int64)))
+    nreq.fill_(16)
+    import torch
+    for _ in range(3):
+        dst.fill_(-7.0)
+        ctx.hybrid_decode_pages(marr, len(models), rq, nreq, len(reqs), 128, dst, 1024, 1, graph=True)
+        torch.cuda.synchronize()
+        out2 = dst.float().cpu().numpy()
+        ref2 = np.full(out1.shape, -7.0)
+        O.hybrid_decode_pages(models, reqs2[:16], 128, ref2, 1024)
+        v = ref2[:, 0] != -7.0
+        assert_close(out2[v], ref2[v], TOL[1], "graph replay")
+        np.testing.assert_array_equal(out2[~v], -7.0)
+
+
+def test_hybrid_pages_nan_time_and_page_size(N, ctx):
+    import torch
+    models, reqs = _hyb_vt(5)
+    reqs = [(1, 0, 0, float("nan"), 0), (2, 0, 0, 0.25, 128)]
+    out, _ = _run_hpages(N, ctx, models, reqs, 1)
+    assert np.isnan(out.reshape(128, 1024, 3)[:, :128]).all()
+    ref = np.full(out.shape, -7.0)
+    O.hybrid_decode_pages(models, reqs[1:], 128, ref, 1024)
+    v = ref[:, 0] != -7.0
+    assert_close(out[v], ref[v], TOL[1], "page next to a NaN page")
+    hm = N.HybridModel.from_numpy(models[0])
+    marr = N.models_array([hm])
+    rq = N.page_requests([0], [0], [0], [0.5], [0])
+    nreq = torch.tensor([1], dtype=torch.int32, device="cuda")
+    dst = torch.empty((128 * 128, 3), dtype=torch.float16, device="cuda")
+    for page in (16, 48, 8192):
+        with pytest.raises(N.NdgiError):
+            ctx.hybrid_decode_pages(marr, 1, rq, nreq, 1, page, dst, 128, 1)
+
+
+@pytest.mark.parametrize("profile", ["M", "M.64"])
+def test_hybrid_1024_map_of_tile_models_sampled(N, ctx, profile):
+    """A 1024 x 1024 lightmap as 64 per-tile models of 128 x 128 texels (the paper's
+    production setting), decoded at one t through the page decoder at its real size and
+    checked on sampled texels."""
+    import torch
+    models = [I.random_hybrid_model(profile=profile, config=46, index=i) for i in range(64)]
+    hms = [N.HybridModel.from_numpy(m) for m in models]
+    marr = N.models_array(hms)
+    t = 0.6180339
+    idx = np.arange(64)
+    rq = N.page_requests(idx.astype(np.int32), np.zeros(64, np.int32), np.zeros(64, np.int32),
+                         np.full(64, t, np.float32), ((idx // 8) * 128 * 1024 + (idx % 8) * 128).astype(np.int64))
+    nreq = torch.tensor([64], dtype=torch.int32, device="cuda")
+    g = np.random.default_rng(47)
+    sel = g.integers(0, 1024 * 1024, 4096)
+    xs, ys = sel % 1024, sel // 1024
+    tile = (ys // 128) * 8 + xs // 128
+    ref = np.zeros((sel.size, 3))
+    for k in np.unique(tile):
+        s = tile == k
+        ref[s] = O.hybrid_decode_f64(models[k], (xs[s] % 128 + 0.5) / 128, (ys[s] % 128 + 0.5) / 128,
+                                     np.full(s.sum(), np.float64(np.float32(t))))
+    for prec in (1, 0):
+        dst = torch.empty((1024 * 1024, 3), dtype=torch.float16 if prec else torch.float32, device="cuda")
+        ctx.hybrid_decode_pages(marr, 64, rq, nreq, 64, 128, dst, 1024, prec)
+        got = dst[torch.from_numpy(sel).cuda()].float().cpu().numpy()
+        assert_close(got, ref, TOL[prec], f"{profile} 1024^2 prec {prec}")
+    assert ctx.error_flags() == 0
