@@ -7,7 +7,8 @@ the persistent page decoder (1024 pages of 128^2), then 16,000,000 uniformly ran
 before the timed region.  The same JSON line also reports the FP32 path on the same
 step, a 32-map virtual-texturing frame (p50 / p99), the training step with BC simulation
 (1024^2 x 24, 2^18 samples), the roofline of the dominant kernel and the CPU oracle
-timed on a bounded sample.
+timed on a bounded sample, and the paper's own hybrid layout (a 1024^2 lightmap of 64
+per-tile models, each profile of Table 3) beside the paper's Table 5 latencies.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c2|c5]
 """
@@ -212,6 +213,50 @@ def run_c3(args, torch, N, I, ctx, frames=110, warm=10):
                 maps=[int(s) for s in sides])
 
 
+# Decode latency of a 1024 x 1024 lightmap reported for the paper's profiles on an RTX 4060
+# (Table 5), quoted beside the measurement as context (other hardware, not a target).
+PAPER_TABLE5_MS = {"L": 0.201, "M": 0.203, "M.64": 0.314}
+
+
+def run_hybrid(args, torch, N, I, ctx, reps=30, warm=5):
+    """The paper's own layout and decoder: a 1024 x 1024 lightmap as 64 per-tile models of
+    128 x 128 texels (F_uv 128^2 x 4 BC4, F_ut / F_vt 64 x 24 x 2 8-bit, F_uvt side^2 x 12 x 4
+    BC4, 26 key times), all 64 pages decoded at one t in one persistent launch, for each
+    profile of Table 3 and both precisions."""
+    import numpy as np
+    out = {}
+    idx = np.arange(64)
+    offs = ((idx // 8) * 128 * 1024 + (idx % 8) * 128).astype(np.int64)
+    for prof in ("L", "M", "H", "M.64"):
+        models = [N.HybridModel.from_numpy(I.random_hybrid_model(profile=prof, config=6, index=i)) for i in range(64)]
+        marr = N.models_array(models)
+        rq = N.page_requests(idx.astype(np.int32), np.zeros(64, np.int32), np.zeros(64, np.int32),
+                             np.full(64, 0.4375, np.float32), offs)
+        nreq = torch.tensor([64], dtype=torch.int32, device="cuda")
+        row = {}
+        for prec, name in ((N.PREC_F16, "f16"), (N.PREC_F32, "f32")):
+            dst = torch.empty((1024 * 1024, 3), dtype=torch.float16 if prec == N.PREC_F16 else torch.float32,
+                              device="cuda")
+            widths = 2 if I.HYBRID_PROFILES[prof][1] == 64 else 1
+            for _ in range(warm):
+                ctx.hybrid_decode_pages(marr, 64, rq, nreq, 64, 128, dst, 1024, prec, widths=widths)
+            tm = Timer(torch)
+            for _ in range(reps):
+                e = tm.start()
+                ctx.hybrid_decode_pages(marr, 64, rq, nreq, 64, 128, dst, 1024, prec, widths=widths)
+                tm.stop(e)
+            torch.cuda.synchronize()
+            ms = sorted(tm.ms())[reps // 2]
+            row[f"{name}_ms"] = ms
+            row[f"{name}_texels_per_s"] = 1024 * 1024 / (ms * 1e-3)
+        if prof in PAPER_TABLE5_MS:
+            row["paper_rtx4060_ms"] = PAPER_TABLE5_MS[prof]
+        log(f"hybrid 1024^2 {prof}: FP16 {row['f16_ms'] * 1e3:.1f} us, FP32 {row['f32_ms'] * 1e3:.1f} us")
+        out[prof] = row
+    assert ctx.error_flags() == 0
+    return out
+
+
 def run_c4(args, torch, N, I, ctx, steps=None, warm=3):
     """Training step with BC simulation: 1024^2 x 24 target, 2^18 samples, Adam."""
     import numpy as np
@@ -285,7 +330,8 @@ def main():
     ap.add_argument("--random-path", default="binned", choices=["binned", "direct"],
                     help="decode of the random queries: tile-binned (default) or in arrival order")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--headline-only", action="store_true", help="skip the VT and training legs")
+    ap.add_argument("--headline-only", action="store_true", help="skip the VT, hybrid and training legs")
+    ap.add_argument("--hybrid-only", action="store_true", help="only the hybrid-layout decode leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -309,6 +355,9 @@ def main():
         print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4, "launches": 5}))
         return
     ctx = N.Context(0)
+    if args.hybrid_only:
+        print(json.dumps({"hybrid_1024_tiles": run_hybrid(args, torch, N, I, ctx)}), flush=True)
+        return
     if args.workload == "c5":
         from paper_2604_12625_amd.large import run_c5
         print(json.dumps(run_c5(args, torch, N, I, ctx)), flush=True)
@@ -359,6 +408,7 @@ def main():
         ctx3 = N.Context(0)
         res["vt_frame"] = run_c3(args, torch, N, I, ctx3)
         ctx3.close()
+        res["hybrid_1024_tiles"] = run_hybrid(args, torch, N, I, ctx)
         c4 = run_c4(args, torch, N, I, ctx)
         res["train_texels_per_s"] = c4["samples_per_s"]
         res["train"] = c4

@@ -313,15 +313,18 @@ int ndgi_hybrid_decode(ndgi_ctx* ctx, const ndgi_hybrid_model* model, const floa
                        void* out, int32_t prec, hipStream_t stream);
 
 /* Virtual-texturing page decode of hybrid models (Sec. 3.5; supplementary Sec. C): the
- * same request convention as ndgi_decode_pages (one persistent launch over all requests,
- * request count read from device memory), with t clamped to [0, 1] and page a multiple of
- * 32 in 32..4096.  Each map (one per-tile model in the paper's production setting) has its
- * own descriptor and decoder.  A request whose model index or page is out of range, or
- * whose descriptor breaks the ranges above, is skipped and sets NDGI_FLAG_BAD_PAGE_REQUEST.
- * Errors: INVALID_ARG (sizes, prec, NULL pointers). */
+ * same request convention as ndgi_decode_pages (request count read from device memory),
+ * with t clamped to [0, 1] and page a multiple of 32 in 32..4096.  Each map (one per-tile
+ * model in the paper's production setting) has its own descriptor and decoder.
+ *   widths: decoder widths among the requests' models, bit 0 = hidden 16, bit 1 = hidden
+ *           64, 0 = either.  One persistent launch runs per width named; naming only the
+ *           width in use saves the launch of the other.
+ * A request whose model index or page is out of range, whose descriptor breaks the ranges
+ * above, or whose decoder width is not in `widths`, is skipped and sets
+ * NDGI_FLAG_BAD_PAGE_REQUEST.  Errors: INVALID_ARG (sizes, prec, widths, NULL pointers). */
 int ndgi_hybrid_decode_pages(ndgi_ctx* ctx, const ndgi_hybrid_model* models_dev, int32_t n_models,
                              const ndgi_page_req* reqs_dev, const int32_t* n_reqs_dev, int32_t max_reqs,
-                             int32_t page, void* dst, int64_t dst_pitch, int32_t prec,
+                             int32_t page, void* dst, int64_t dst_pitch, int32_t prec, int32_t widths,
                              hipStream_t stream);
 
 /* Same work launched as a HIP graph owned by the context (captured on the first call for
@@ -329,7 +332,7 @@ int ndgi_hybrid_decode_pages(ndgi_ctx* ctx, const ndgi_hybrid_model* models_dev,
 int ndgi_hybrid_decode_pages_graph(ndgi_ctx* ctx, const ndgi_hybrid_model* models_dev, int32_t n_models,
                                    const ndgi_page_req* reqs_dev, const int32_t* n_reqs_dev,
                                    int32_t max_reqs, int32_t page, void* dst, int64_t dst_pitch,
-                                   int32_t prec, hipStream_t stream);
+                                   int32_t prec, int32_t widths, hipStream_t stream);
 
 /* ---------------------------------------------------------------- evaluation */
 

@@ -249,8 +249,9 @@ int ndgi_hybrid_decode(ndgi_ctx* c, const ndgi_hybrid_model* m, const float* uvt
 
 static int check_hybrid_pages(ndgi_ctx* c, const ndgi_hybrid_model* models, int32_t n_models,
                               const ndgi_page_req* reqs, const int32_t* n_reqs, int32_t max_reqs, int32_t page,
-                              void* dst, int64_t pitch, int32_t prec) {
+                              void* dst, int64_t pitch, int32_t prec, int32_t widths) {
   if (!c) return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: ctx is NULL");
+  if (widths < 0 || widths > 3) return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: widths=%d not in 0..3", widths);
   if (prec != NDGI_PREC_F32 && prec != NDGI_PREC_F16)
     return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: bad prec %d", prec);
   if (n_models < 0 || max_reqs < 0) return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: negative count");
@@ -264,23 +265,24 @@ static int check_hybrid_pages(ndgi_ctx* c, const ndgi_hybrid_model* models, int3
 
 int ndgi_hybrid_decode_pages(ndgi_ctx* c, const ndgi_hybrid_model* models, int32_t n_models,
                              const ndgi_page_req* reqs, const int32_t* n_reqs, int32_t max_reqs, int32_t page,
-                             void* dst, int64_t pitch, int32_t prec, hipStream_t s) {
+                             void* dst, int64_t pitch, int32_t prec, int32_t widths, hipStream_t s) {
   clear_error();
-  int rc = check_hybrid_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec);
+  int rc = check_hybrid_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, widths);
   if (rc) return rc;
-  return launch_hybrid_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, s);
+  return launch_hybrid_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, widths, s);
 }
 
 int ndgi_hybrid_decode_pages_graph(ndgi_ctx* c, const ndgi_hybrid_model* models, int32_t n_models,
                                    const ndgi_page_req* reqs, const int32_t* n_reqs, int32_t max_reqs,
-                                   int32_t page, void* dst, int64_t pitch, int32_t prec, hipStream_t s) {
+                                   int32_t page, void* dst, int64_t pitch, int32_t prec, int32_t widths,
+                                   hipStream_t s) {
   clear_error();
-  int rc = check_hybrid_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec);
+  int rc = check_hybrid_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, widths);
   if (rc) return rc;
-  return launch_graph(c, GraphKey{1, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, s},
+  return launch_graph(c, GraphKey{1 + widths, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, s},
                       [&](hipStream_t cs) {
                         return launch_hybrid_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch,
-                                                   prec, cs);
+                                                   prec, widths, cs);
                       });
 }
 

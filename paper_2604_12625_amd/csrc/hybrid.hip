@@ -15,8 +15,9 @@
 //  * FP32: v_mfma_f32_16x16x4_f32, step r feeding unit 4g + r of the K block.
 // The weights in that K order (the MFMA A operands) are laid out once per model in an LDS
 // table of 16-byte lane entries: "chunk" = 64 lanes x 16 bytes (8 FP16 slots or 4 FP32
-// steps).  The output layer of group q writes rows 4q..4q+2 of one accumulator, so after 4
-// groups lane l owns the RGB of texel l of the pass.
+// steps); the output layer's chunk holds W3 on rows 4k..4k+2 of every row quad k, and group
+// q keeps quad q only, so the 4 groups write rows 4q..4q+2 of one accumulator and after
+// them lane l owns the RGB of texel l of the pass.
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -26,7 +27,7 @@ template <int HD>
 struct HybShape {
   static constexpr int NB = HD / 16;                           // row blocks of a hidden layer
   static constexpr int kL1 = 0, kL2 = NB, kL3 = NB + NB * NB;  // first chunk of each layer
-  static constexpr int kChunks = NB + NB * NB + 4 * NB;        // layer 3: one set per group
+  static constexpr int kChunks = NB + NB * NB + NB;
   static constexpr int oW1 = 0, oB1 = HD * NDGI_HYBRID_IN, oW2 = oB1 + HD, oB2 = oW2 + HD * HD,
                        oW3 = oB2 + HD, oB3 = oW3 + 3 * HD, kSize = oB3 + 3;
 };
@@ -54,8 +55,9 @@ __device__ void hyb_build_dt(HybTab<HD>& T, const void* mlp) {
       base = S::oW2 + (16 * ob + i) * HD;
       kbase = 16 * kb + 4 * g;
     } else {
-      const int q = (c - S::kL3) / S::NB, kb = (c - S::kL3) % S::NB;
-      base = ((i >> 2) == q && (i & 3) < 3) ? S::oW3 + (i & 3) * HD : -1;
+      // output row (i & 3) on every row quad; hyb_group keeps quad q for group q
+      const int kb = c - S::kL3;
+      base = (i & 3) < 3 ? S::oW3 + (i & 3) * HD : -1;
       kbase = 16 * kb + 4 * g;
     }
     // loads are unconditional (clamped row), the zero rows select afterwards
@@ -85,43 +87,56 @@ __device__ void hyb_build(HybTab<HD>& T, const void* mlp, int mlp_dtype) {
   else hyb_build_dt<PREC, HD, NDGI_DTYPE_F32>(T, mlp);
 }
 
-// GELU(x) = x Phi(x) = max(x, 0) - |x|/2 erfc(|x| / sqrt 2): both branches of the sign
-// are the same expression, with no cancellation for large |x|.
+// GELU(x) = x Phi(x) = max(x, 0) - |x| * erfc(|x| / sqrt 2) / 2: both signs are the same
+// expression, with no cancellation for large |x|.  The factor 1/2 and the argument scale
+// 1/sqrt 2 are folded into the constants below.
 //  * FP32 path: erfc by the Chebyshev fit of Press et al., Numerical Recipes (erfcc),
-//    relative error below 1.2e-7 for every argument;
+//    relative error below 1.2e-7 for every argument: erfc(z) = t exp(-z^2 + p(t)) with
+//    t = 1 / (1 + z/2); here exp runs in base 2 with log2(e) folded into p and ln(1/2)
+//    added to its constant term;
 //  * FP16 path: erfc(z) = P(z)^-16 with the degree-6 P of Abramowitz & Stegun 7.1.28,
 //    absolute error at most 3e-7 (far below the FP16 rounding of the activations), one
-//    reciprocal and no exponential.
+//    reciprocal and no exponential; P is taken in |x| and scaled by 2^(1/16), so that the
+//    16th power of its reciprocal is erfc / 2.
+namespace gelu_k {
+constexpr double kLog2e = 1.4426950408889634, kRs2 = 0.70710678118654752, kLn2 = 0.69314718055994531;
+constexpr double kS16 = 1.0442737824274138;   // 2^(1/16)
+// Numerical Recipes erfcc coefficients, innermost first, then the constant term
+constexpr double kNR[10] = {0.17087277, -0.82215223, 1.48851587, -1.13520398, 0.27886807,
+                            -0.18628806, 0.09678418, 0.37409196, 1.00002368, -1.26551223};
+// Abramowitz & Stegun 7.1.28: a6 .. a1
+constexpr double kAS[6] = {0.0000430638, 0.0002765672, 0.0001520143, 0.0092705272, 0.0422820123, 0.0705230784};
+constexpr float nr_c(int i) { return (float)(kLog2e * (i == 9 ? kNR[9] - kLn2 : kNR[i])); }
+constexpr double pw(double x, int k) { return k == 0 ? 1.0 : x * pw(x, k - 1); }
+constexpr float as_c(int i) { return (float)(kS16 * kAS[i] * pw(kRs2, 6 - i)); }   // coefficient of |x|^(6-i)
+// evaluated by the compiler (constexpr variables), never on the device
+constexpr float kNRf[10] = {nr_c(0), nr_c(1), nr_c(2), nr_c(3), nr_c(4), nr_c(5), nr_c(6), nr_c(7), nr_c(8), nr_c(9)};
+constexpr float kASf[6] = {as_c(0), as_c(1), as_c(2), as_c(3), as_c(4), as_c(5)};
+}  // namespace gelu_k
+
 template <int PREC>
 __device__ __forceinline__ float gelu(float x) {
-  const float z = fabsf(x) * 0.70710678118654752f;
-  float ec;
+  using namespace gelu_k;
+  const float ax = fabsf(x);
+  float half_erfc;
   if constexpr (PREC == NDGI_PREC_F32) {
-    const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, z, 1.0f));
-    float p = fmaf(t, 0.17087277f, -0.82215223f);
-    p = fmaf(t, p, 1.48851587f);
-    p = fmaf(t, p, -1.13520398f);
-    p = fmaf(t, p, 0.27886807f);
-    p = fmaf(t, p, -0.18628806f);
-    p = fmaf(t, p, 0.09678418f);
-    p = fmaf(t, p, 0.37409196f);
-    p = fmaf(t, p, 1.00002368f);
-    p = fmaf(t, p, -1.26551223f);
-    ec = t * __expf(fmaf(-z, z, p));
+    const float t = __builtin_amdgcn_rcpf(fmaf((float)(0.5 * kRs2), ax, 1.0f));
+    float p = fmaf(t, kNRf[0], kNRf[1]);
+#pragma unroll
+    for (int i = 2; i < 10; ++i) p = fmaf(t, p, kNRf[i]);
+    half_erfc = t * __builtin_amdgcn_exp2f(fmaf(x * x, (float)(-0.5 * kLog2e), p));
   } else {
-    float p = fmaf(z, 4.30638e-5f, 2.765672e-4f);
-    p = fmaf(z, p, 1.520143e-4f);
-    p = fmaf(z, p, 9.2705272e-3f);
-    p = fmaf(z, p, 4.22820123e-2f);
-    p = fmaf(z, p, 7.05230784e-2f);
-    p = fmaf(z, p, 1.0f);
+    float p = fmaf(ax, kASf[0], kASf[1]);
+#pragma unroll
+    for (int i = 2; i < 6; ++i) p = fmaf(ax, p, kASf[i]);
+    p = fmaf(ax, p, (float)kS16);
     float r = __builtin_amdgcn_rcpf(p);
     r *= r;
     r *= r;
     r *= r;
-    ec = r * r;
+    half_erfc = r * r;
   }
-  return fmaf(-0.5f * fabsf(x), ec, fmaxf(x, 0.0f));
+  return fmaf(-ax, half_erfc, fmaxf(x, 0.0f));
 }
 
 // One group of 16 texels through the decoder; x = this lane's K share of layer 1 (inputs
@@ -131,6 +146,7 @@ __device__ __forceinline__ void hyb_group(const HybTab<HD>& T, const float x[4],
   using S = HybShape<HD>;
   constexpr int NB = S::NB;
   const int g = lane >> 4;
+  const bool own = ((lane & 15) >> 2) == q;   // A rows 4q..4q+2 carry the output layer of group q
   if constexpr (PREC == NDGI_PREC_F16) {
     auto A = [&](int c) { return __builtin_bit_cast(h8v, T.a[c * 64 + lane]); };
     const h8v X = split_inputs(x);
@@ -151,7 +167,10 @@ __device__ __forceinline__ void hyb_group(const HybTab<HD>& T, const float x[4],
       H2[ob] = split_inputs(h);
     }
 #pragma unroll
-    for (int kb = 0; kb < NB; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(A(S::kL3 + q * NB + kb), H2[kb], acc, 0, 0, 0);
+    for (int kb = 0; kb < NB; ++kb) {
+      const h8v a3 = own ? A(S::kL3 + kb) : (h8v){0, 0, 0, 0, 0, 0, 0, 0};
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a3, H2[kb], acc, 0, 0, 0);
+    }
   } else {
     auto A = [&](int c) { return __builtin_bit_cast(f4v, T.a[c * 64 + lane]); };
     float h1[NB][4], h2[NB][4];
@@ -178,7 +197,7 @@ __device__ __forceinline__ void hyb_group(const HybTab<HD>& T, const float x[4],
     }
 #pragma unroll
     for (int kb = 0; kb < NB; ++kb) {
-      const f4v w = A(S::kL3 + q * NB + kb);
+      const f4v w = own ? A(S::kL3 + kb) : (f4v){0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w[r], h2[kb][r], acc, 0, 0, 0);
     }
@@ -192,7 +211,11 @@ __device__ __forceinline__ f4v hyb_decode(const HybTab<HD>& T, float r[4][4], in
   transpose_rows(r);
   f4v acc = *(const f4v*)T.b3;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) hyb_group<PREC, HD>(T, r[q], q, lane, acc);
+  for (int q = 0; q < 4; ++q) {
+    hyb_group<PREC, HD>(T, r[q], q, lane, acc);
+    // groups are not interleaved: each one's activations are dead before the next starts
+    __builtin_amdgcn_sched_barrier(0);
+  }
   return acc;
 }
 
@@ -277,6 +300,13 @@ __device__ __forceinline__ HybTime hyb_time(const ndgi_hybrid_model& m, float t,
 // Four channels of texel slot `slot` of a 32-byte BC4 footprint (channel c in bytes 8c..8c+7).
 __device__ __forceinline__ void bc4_fp4(const uint8_t* fp, uint32_t slot, float v[4]) {
   const u4v a = ((const u4v*)fp)[0], b = ((const u4v*)fp)[1];
+  v[0] = bc4_texel_f(a.x, a.y, slot);
+  v[1] = bc4_texel_f(a.z, a.w, slot);
+  v[2] = bc4_texel_f(b.x, b.y, slot);
+  v[3] = bc4_texel_f(b.z, b.w, slot);
+}
+
+__device__ __forceinline__ void bc4_fp4_regs(const u4v& a, const u4v& b, uint32_t slot, float v[4]) {
   v[0] = bc4_texel_f(a.x, a.y, slot);
   v[1] = bc4_texel_f(a.z, a.w, slot);
   v[2] = bc4_texel_f(b.x, b.y, slot);
@@ -379,8 +409,8 @@ __global__ __launch_bounds__(256) void k_hybrid_query(ndgi_hybrid_model m, const
 }
 
 // ---------------------------------------------------------------------- page decode
-// Work item = (request, 32 x 32 sub-tile of its page), one workgroup per item, items
-// round-robin over a persistent grid.  Per item the workgroup stages in LDS:
+// Work item = (request, 32 x 32 sub-tile of its page), one workgroup per item over a
+// persistent grid.  Per item the workgroup stages in LDS:
 //  * the F_uvt nodes the sub-tile reads, decoded from both slices around tau and blended
 //    in time (at most 33 x 33 nodes, since Gu <= W and Gv <= H);
 //  * the F_ut row span and the F_vt column span it reads, blended in time;
@@ -395,36 +425,46 @@ __global__ __launch_bounds__(256) void k_hybrid_pages(const ndgi_hybrid_model* _
                                                        const ndgi_page_req* __restrict__ reqs,
                                                        const int32_t* __restrict__ n_reqs_dev, int32_t max_reqs,
                                                        int32_t page, void* __restrict__ dst, int64_t pitch,
-                                                       uint32_t* __restrict__ flags) {
+                                                       int32_t widths, uint32_t* __restrict__ flags) {
   __shared__ HybTab<HD> tab;
   __shared__ f4v win[kHybWin * kHybWin];
   __shared__ float2 line_u[kHybWin], line_v[kHybWin];
+  __shared__ float skeys[NDGI_HYBRID_MAX_KEYS];
+  __shared__ int4 rows_g[kHybSub], rows_v[kHybSub];   // per sub-tile row: window taps and weight
+  static_assert(NDGI_HYBRID_MAX_KEYS <= 256, "one key per thread");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int n_req = *n_reqs_dev;
   n_req = n_req < 0 ? 0 : (n_req > max_reqs ? max_reqs : n_req);
   const int side = page / kHybSub;
   const int64_t per_req = (int64_t)side * side;
   const int64_t total = (int64_t)n_req * per_req;
+  // each workgroup takes a contiguous run of items (equal cost), so consecutive items
+  // mostly share a request and its decoder table
+  const int64_t chunk = (total + gridDim.x - 1) / gridDim.x;
+  const int64_t it_end = min(total, ((int64_t)blockIdx.x + 1) * chunk);
   int cur = -1;
-  for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+  for (int64_t it = (int64_t)blockIdx.x * chunk; it < it_end; ++it) {
     const int r = (int)(it / per_req), s = (int)(it - (int64_t)r * per_req);
     const ndgi_page_req rq = reqs[r];
     bool ok = rq.model >= 0 && rq.model < n_models && rq.page_x >= 0 && rq.page_y >= 0;
     ndgi_hybrid_model m = {};
     if (ok) m = models[rq.model];
-    ok = ok && hybrid_ok(m) && (int64_t)page * (rq.page_x + 1) <= m.W && (int64_t)page * (rq.page_y + 1) <= m.H;
+    ok = ok && hybrid_ok(m) && (int64_t)page * (rq.page_x + 1) <= m.W && (int64_t)page * (rq.page_y + 1) <= m.H &&
+         (widths & (m.hidden == 16 ? 1 : 2)) != 0;
     if (!ok) {
       if (threadIdx.x == 0 && s == 0) atomicOr(flags, NDGI_FLAG_BAD_PAGE_REQUEST);
       continue;
     }
     if (m.hidden != HD) continue;   // served by the launch of the other width
     __syncthreads();                // the previous item's readers of the table and windows are done
-    if (rq.model != cur) {
+    if (rq.model != cur) {          // new model: its decoder table and key times into LDS
       hyb_build<PREC, HD>(tab, m.mlp, m.mlp_dtype);
+      if ((int)threadIdx.x < m.n_keys) skeys[threadIdx.x] = m.keys[threadIdx.x];
       cur = rq.model;
+      __syncthreads();
     }
     const bool bad_t = !isfinite(rq.t);
-    const HybTime ht = hyb_time(m, bad_t ? 0.0f : rq.t, [&](int i) { return m.keys[i]; });
+    const HybTime ht = hyb_time(m, bad_t ? 0.0f : rq.t, [&](int i) { return skeys[i]; });
     const int px0 = page * rq.page_x, py0 = page * rq.page_y;
     const int x0 = px0 + (s % side) * kHybSub, y0 = py0 + (s / side) * kHybSub;
     // node spans of the sub-tile; clamped to the LDS window (never reached when Gu <= W)
@@ -462,6 +502,15 @@ __global__ __launch_bounds__(256) void k_hybrid_pages(const ndgi_hybrid_model* _
         if (isu) line_u[t] = o;
         else line_v[t - 64] = o;
       }
+      if (t >= 128 && t < 128 + 2 * kHybSub) {   // the axes of the sub-tile's rows
+        const int j = (t - 128) & (kHybSub - 1);
+        const bool isg = t < 128 + kHybSub;
+        const Axis a = isg ? texel_axis<false>(y0 + j, m.Gv, m.H) : texel_axis<false>(y0 + j, m.V, m.H);
+        const int o0 = isg ? wy0 : va0, nn = isg ? nwy : nva;
+        const int4 e = make_int4(min(max(a.i0 - o0, 0), nn - 1), min(max(a.i1 - o0, 0), nn - 1), __float_as_int(a.w1), 0);
+        if (isg) rows_g[j] = e;
+        else rows_v[j] = e;
+      }
     }
     __syncthreads();                // table and windows complete
     const int x = x0 + (lane & 31);
@@ -470,31 +519,38 @@ __global__ __launch_bounds__(256) void k_hybrid_pages(const ndgi_hybrid_model* _
     const float2 ut0 = line_u[min(max(ux.i0 - ua0, 0), nua - 1)], ut1 = line_u[min(max(ux.i1 - ua0, 0), nua - 1)];
     const float2 vut = make_float2(fmaf(ux.w1, ut1.x, ux.w0 * ut0.x), fmaf(ux.w1, ut1.y, ux.w0 * ut0.y));
     const uint32_t fbw = (uint32_t)m.W >> 2;
+    // the F_uv footprint of the next pass is loaded while this one decodes
+    auto fp_of = [&](int p) { return m.fuv + ((uint32_t)((y0 + 2 * p + (lane >> 5)) >> 2) * fbw + (uint32_t)(x >> 2)) * 32u; };
+    u4v fa = ((const u4v*)fp_of(wave))[0], fb = ((const u4v*)fp_of(wave))[1];
     for (int p = wave; p < kHybSub * kHybSub / 64; p += 4) {
-      const int y = y0 + 2 * p + (lane >> 5);
+      const int j = 2 * p + (lane >> 5), y = y0 + j;
+      const u4v ca = fa, cb = fb;
+      if (p + 4 < kHybSub * kHybSub / 64) {
+        fa = ((const u4v*)fp_of(p + 4))[0];
+        fb = ((const u4v*)fp_of(p + 4))[1];
+      }
       float rr[4][4];
       // V_uvt: bilinear over the staged nodes
-      const Axis gy = texel_axis<false>(y, m.Gv, m.H);
-      const int gy0 = min(max(gy.i0 - wy0, 0), nwy - 1), gy1 = min(max(gy.i1 - wy0, 0), nwy - 1);
-      const f4v c00 = win[gy0 * nwx + gx0], c01 = win[gy0 * nwx + gx1];
-      const f4v c10 = win[gy1 * nwx + gx0], c11 = win[gy1 * nwx + gx1];
-      float w[4];
-      tap_weights(gx, gy, w);
+      const int4 ag = rows_g[j];
+      const float gyw1 = __int_as_float(ag.z);
+      const f4v c00 = win[ag.x * nwx + gx0], c01 = win[ag.x * nwx + gx1];
+      const f4v c10 = win[ag.y * nwx + gx0], c11 = win[ag.y * nwx + gx1];
+      const float w[4] = {(1.0f - gyw1) * gx.w0, (1.0f - gyw1) * gx.w1, gyw1 * gx.w0, gyw1 * gx.w1};
 #pragma unroll
       for (int c = 0; c < 4; ++c) rr[0][c] = fmaf(w[3], c11[c], fmaf(w[2], c10[c], fmaf(w[1], c01[c], w[0] * c00[c])));
       // V_uv: the texel itself
       float sv[4];
-      bc4_fp4(m.fuv + ((uint32_t)(y >> 2) * fbw + (uint32_t)(x >> 2)) * 32u, 4u * (uint32_t)(y & 3) + (uint32_t)(x & 3),
-              sv);
+      bc4_fp4_regs(ca, cb, 4u * (uint32_t)(y & 3) + (uint32_t)(x & 3), sv);
 #pragma unroll
       for (int c = 0; c < 4; ++c) rr[1][c] = sv[c] * (1.0f / 255.0f);
       // V_ut (per column), V_vt (per row)
-      const Axis vy = texel_axis<false>(y, m.V, m.H);
-      const float2 vt0 = line_v[min(max(vy.i0 - va0, 0), nva - 1)], vt1 = line_v[min(max(vy.i1 - va0, 0), nva - 1)];
+      const int4 av = rows_v[j];
+      const float vyw1 = __int_as_float(av.z), vyw0 = 1.0f - vyw1;
+      const float2 vt0 = line_v[av.x], vt1 = line_v[av.y];
       rr[2][0] = vut.x;
       rr[2][1] = vut.y;
-      rr[2][2] = fmaf(vy.w1, vt1.x, vy.w0 * vt0.x);
-      rr[2][3] = fmaf(vy.w1, vt1.y, vy.w0 * vt0.y);
+      rr[2][2] = fmaf(vyw1, vt1.x, vyw0 * vt0.x);
+      rr[2][3] = fmaf(vyw1, vt1.y, vyw0 * vt0.y);
 #pragma unroll
       for (int c = 0; c < 4; ++c) rr[3][c] = ht.g[c];
       const f4v acc = hyb_decode<PREC, HD>(tab, rr, lane);
@@ -538,17 +594,18 @@ int launch_hybrid_query(ndgi_ctx* ctx, const ndgi_hybrid_model& m, const float* 
 
 int launch_hybrid_pages(ndgi_ctx* ctx, const ndgi_hybrid_model* models, int32_t n_models, const ndgi_page_req* reqs,
                         const int32_t* n_reqs, int32_t max_reqs, int32_t page, void* dst, int64_t pitch, int prec,
-                        hipStream_t s) {
-  // one launch per decoder width; each skips the requests of the other
+                        int32_t widths, hipStream_t s) {
+  // one launch per decoder width present; each skips the requests of the other
+  if (widths == 0) widths = 3;
 #define NDGI_HP(P, HD)                                                                                           \
   hipLaunchKernelGGL((k_hybrid_pages<P, HD>), dim3(resident_wgs(ctx, (const void*)k_hybrid_pages<P, HD>)), dim3(256), \
-                     0, s, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, ctx->flags_dev)
+                     0, s, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, widths, ctx->flags_dev)
   if (prec == NDGI_PREC_F16) {
-    NDGI_HP(NDGI_PREC_F16, 16);
-    NDGI_HP(NDGI_PREC_F16, 64);
+    if (widths & 1) NDGI_HP(NDGI_PREC_F16, 16);
+    if (widths & 2) NDGI_HP(NDGI_PREC_F16, 64);
   } else {
-    NDGI_HP(NDGI_PREC_F32, 16);
-    NDGI_HP(NDGI_PREC_F32, 64);
+    if (widths & 1) NDGI_HP(NDGI_PREC_F32, 16);
+    if (widths & 2) NDGI_HP(NDGI_PREC_F32, 64);
   }
 #undef NDGI_HP
   NDGI_HIP(hipGetLastError());

@@ -142,7 +142,7 @@ def _hyb_vt(seed):
     return models, reqs
 
 
-def _run_hpages(N, ctx, models, reqs, prec, graph=False):
+def _run_hpages(N, ctx, models, reqs, prec, graph=False, widths=0):
     import torch
     hms = [N.HybridModel.from_numpy(m) for m in models]
     marr = N.models_array(hms)
@@ -153,7 +153,7 @@ def _run_hpages(N, ctx, models, reqs, prec, graph=False):
     rows = (len(reqs) + 7) // 8 * 128
     dt = torch.float16 if prec else torch.float32
     dst = torch.full((rows * 1024, 3), -7.0, dtype=dt, device="cuda")
-    ctx.hybrid_decode_pages(marr, len(models), rq, nreq, len(reqs), 128, dst, 1024, prec, graph=graph)
+    ctx.hybrid_decode_pages(marr, len(models), rq, nreq, len(reqs), 128, dst, 1024, prec, widths=widths, graph=graph)
     torch.cuda.synchronize()
     return dst.float().cpu().numpy(), (hms, marr, rq, nreq, dst)
 
@@ -168,6 +168,24 @@ def test_hybrid_pages_many_models_and_bad_requests(N, ctx, prec):
     valid = ref[:, 0] != -7.0
     assert_close(out[valid], ref[valid], TOL[prec], "hybrid pages")
     np.testing.assert_array_equal(out[~valid], -7.0)
+
+
+def test_hybrid_pages_width_mask(N, ctx):
+    """Naming only width 16 skips and flags the requests of width-64 models; the rest
+    decode as with both widths."""
+    models, reqs = _hyb_vt(6)
+    out, _ = _run_hpages(N, ctx, models, reqs, 1, widths=1)
+    assert ctx.error_flags() & N.FLAG_BAD_PAGE_REQUEST
+    narrow = [r if (0 <= r[0] < len(models) and models[r[0]]["hidden"] == 16) else (len(models), 0, 0, 0.0, r[4])
+              for r in reqs]
+    ref = np.full(out.shape, -7.0)
+    O.hybrid_decode_pages(models, narrow, 128, ref, 1024)
+    valid = ref[:, 0] != -7.0
+    assert valid.any() and not valid.all()
+    assert_close(out[valid], ref[valid], TOL[1], "width 16 only")
+    np.testing.assert_array_equal(out[~valid], -7.0)
+    with pytest.raises(N.NdgiError):
+        _run_hpages(N, ctx, models, reqs, 1, widths=4)
 
 
 def test_hybrid_pages_graph_replay_with_new_requests(N, ctx):
@@ -243,7 +261,7 @@ def test_hybrid_1024_map_of_tile_models_sampled(N, ctx, profile):
                                      np.full(s.sum(), np.float64(np.float32(t))))
     for prec in (1, 0):
         dst = torch.empty((1024 * 1024, 3), dtype=torch.float16 if prec else torch.float32, device="cuda")
-        ctx.hybrid_decode_pages(marr, 64, rq, nreq, 64, 128, dst, 1024, prec)
+        ctx.hybrid_decode_pages(marr, 64, rq, nreq, 64, 128, dst, 1024, prec, widths=1 if profile == "M" else 2)
         got = dst[torch.from_numpy(sel).cuda()].float().cpu().numpy()
         assert_close(got, ref, TOL[prec], f"{profile} 1024^2 prec {prec}")
     assert ctx.error_flags() == 0
