@@ -84,62 +84,102 @@ __global__ __launch_bounds__(kSortThreads) void k_bin_count(ndgi_model m, BinGeo
   for (int i = threadIdx.x; i < nbins; i += kSortThreads) row[i] = hist[i];
 }
 
-// Per bin (one thread each): exclusive prefix of counts over the sort workgroups, in
-// place, and the bin's total into start[bin].  Loads go 16 rows at a time so that many
-// are in flight.
+// Per bin: exclusive prefix of counts over the sort workgroups, in place, and the bin's
+// total into start[bin].  A workgroup takes 64 bins; its four waves each take a quarter of
+// the sort rows, with all of a thread's loads issued together, and the quarter sums are
+// combined through LDS.
+constexpr int kColBins = 64, kColRows = kSortWgs / 4;
 __global__ __launch_bounds__(256) void k_bin_colscan(int32_t* __restrict__ counts, int nbins,
                                                      int32_t* __restrict__ start) {
-  const int b = blockIdx.x * 256 + threadIdx.x;
-  if (b >= nbins) return;
+  __shared__ int32_t part[4][kColBins];
+  const int bl = threadIdx.x & (kColBins - 1), pr = threadIdx.x / kColBins;
+  const int b = blockIdx.x * kColBins + bl;
+  const bool live = b < nbins;
+  const int bc = live ? b : nbins - 1;
+  int32_t c[kColRows];
+#pragma unroll
+  for (int r = 0; r < kColRows; ++r) c[r] = counts[(int64_t)(pr * kColRows + r) * nbins + bc];
+  int32_t s = 0;
+#pragma unroll
+  for (int r = 0; r < kColRows; ++r) s += c[r];
+  part[pr][bl] = s;
+  __syncthreads();
   int32_t run = 0;
-  static_assert(kSortWgs % 16 == 0, "column scan works in groups of 16 rows");
-  for (int w0 = 0; w0 < kSortWgs; w0 += 16) {
-    int32_t c[16];
+  for (int q = 0; q < pr; ++q) run += part[q][bl];
+  if (!live) return;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) c[r] = counts[(int64_t)(w0 + r) * nbins + b];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      counts[(int64_t)(w0 + r) * nbins + b] = run;
-      run += c[r];
-    }
+  for (int r = 0; r < kColRows; ++r) {
+    counts[(int64_t)(pr * kColRows + r) * nbins + b] = run;
+    run += c[r];
   }
-  start[b] = run;
+  if (pr == 3) start[b] = run;
 }
 
 // start[0..nbins) := exclusive prefix of the bin totals, start[nbins] := n;
 // items[b] := exclusive prefix of the work items per bin (ceil(count / kPiece)),
-// items[nbins] := total; item_bin[i] := the bin of work item i.  One workgroup of 1024 threads: the totals are staged in LDS
-// with coalesced loads, each thread scans a run of bins, the run sums are scanned across
-// the workgroup.
+// items[nbins] := total; item_bin[i] := the bin of work item i.  One workgroup of 1024
+// threads: the totals are staged in LDS with coalesced loads, each thread scans a run of 16
+// bins (the LDS array has one pad word per 16 so that the runs of a wave's lanes sit in
+// different banks), and the run sums are scanned across the workgroup with wave shuffles.
+__device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
+
 __global__ __launch_bounds__(1024) void k_bin_starts(int32_t* __restrict__ start, int32_t* __restrict__ items,
                                                      int32_t* __restrict__ item_bin, int nbins, int32_t n) {
-  __shared__ int32_t tot[kMaxBins];
-  __shared__ int32_t sh[1024], shi[1024];
-  for (int i = threadIdx.x; i < nbins; i += 1024) tot[i] = start[i];
+  __shared__ int32_t tot[kMaxBins + kMaxBins / 16];
+  __shared__ int32_t wsum[16], wsumi[16];
+  constexpr int kPer = kMaxBins / 1024;
+  static_assert(kPer == 16, "one run of 16 bins per thread");
+  {
+    int32_t v[kPer];   // every load of a thread in flight together
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) v[k] = start[min((int)threadIdx.x + 1024 * k, nbins - 1)];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+      if ((int)threadIdx.x + 1024 * k < nbins) tot[pad16(threadIdx.x + 1024 * k)] = v[k];
+  }
   __syncthreads();
-  const int per = (nbins + 1023) / 1024;
-  const int lo = threadIdx.x * per, hi = min(nbins, lo + per);
+  const int lo = threadIdx.x * kPer, hi = min(nbins, lo + kPer);
   int32_t s = 0, si = 0;
   for (int i = lo; i < hi; ++i) {
-    s += tot[i];
-    si += (tot[i] + kPiece - 1) / kPiece;
+    const int32_t c = tot[pad16(i)];
+    s += c;
+    si += (c + kPiece - 1) / kPiece;
   }
-  sh[threadIdx.x] = s;
-  shi[threadIdx.x] = si;
+  // workgroup-wide inclusive scan of (s, si): within each wave, then over the 16 wave sums
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int32_t incl = s, incli = si;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t o = __shfl_up(incl, off, 64), oi = __shfl_up(incli, off, 64);
+    if (lane >= off) {
+      incl += o;
+      incli += oi;
+    }
+  }
+  if (lane == 63) {
+    wsum[wave] = incl;
+    wsumi[wave] = incli;
+  }
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int32_t a = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
-    const int32_t b = (int)threadIdx.x >= off ? shi[threadIdx.x - off] : 0;
-    __syncthreads();
-    sh[threadIdx.x] += a;
-    shi[threadIdx.x] += b;
-    __syncthreads();
+  if (wave == 0 && lane < 16) {
+    int32_t w = wsum[lane], wi = wsumi[lane];
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      const int32_t o = __shfl_up(w, off, 64), oi = __shfl_up(wi, off, 64);
+      if (lane >= off) {
+        w += o;
+        wi += oi;
+      }
+    }
+    wsum[lane] = w - wsum[lane];     // exclusive prefix of the wave sums
+    wsumi[lane] = wi - wsumi[lane];
   }
-  int32_t run = sh[threadIdx.x] - s, runi = shi[threadIdx.x] - si;
+  __syncthreads();
+  int32_t run = wsum[wave] + incl - s, runi = wsumi[wave] + incli - si;
   // each thread rewrites only its own run of tot: totals become exclusive prefixes
   for (int i = lo; i < hi; ++i) {
-    const int32_t c = tot[i];
-    tot[i] = run;
+    const int32_t c = tot[pad16(i)];
+    tot[pad16(i)] = run;
     items[i] = runi;
     const int32_t pieces = (c + kPiece - 1) / kPiece;
     for (int k = 0; k < pieces; ++k) item_bin[runi + k] = i;
@@ -151,7 +191,9 @@ __global__ __launch_bounds__(1024) void k_bin_starts(int32_t* __restrict__ start
     items[nbins] = runi;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < nbins; i += 1024) start[i] = tot[i];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    if ((int)threadIdx.x + 1024 * k < nbins) start[threadIdx.x + 1024 * k] = tot[pad16(threadIdx.x + 1024 * k)];
 }
 
 // Scatter: every query of sort workgroup wg goes to the next free slot of its bin; a
@@ -560,7 +602,7 @@ int launch_decode_binned(ndgi_ctx* ctx, const ndgi_model& m, const float* uvt, i
   float4* sorted = (float4*)((char*)ws + L.sorted_off);
   const int64_t slice = (n + kSortWgs - 1) / kSortWgs;
   hipLaunchKernelGGL(k_bin_count, dim3(kSortWgs), dim3(kSortThreads), 0, s, m, L.bg, uvt, n, slice, counts);
-  hipLaunchKernelGGL(k_bin_colscan, dim3((L.nbins + 255) / 256), dim3(256), 0, s, counts, L.nbins, start);
+  hipLaunchKernelGGL(k_bin_colscan, dim3((L.nbins + kColBins - 1) / kColBins), dim3(256), 0, s, counts, L.nbins, start);
   hipLaunchKernelGGL(k_bin_starts, dim3(1), dim3(1024), 0, s, start, items, item_bin, L.nbins, (int32_t)n);
   hipLaunchKernelGGL(k_bin_scatter, dim3(kSortWgs), dim3(kSortThreads), 0, s, m, L.bg, uvt, n, slice, counts, start,
                      sorted);
