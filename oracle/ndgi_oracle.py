@@ -634,21 +634,21 @@ def train_step(state: dict, opt: dict, xs, ys, ks, target):
 # --------------------------------------------------------------------------------------
 
 def export_bc4(endpoints: np.ndarray, weights: np.ndarray) -> np.ndarray:
-    """Encode the BC-simulated spatial map as BC4 blocks [H/4][W/4][8][8] uint8.
+    """Encode a BC-simulated map as BC4 blocks [H/4][W/4][C][8] uint8 (C channels).
 
     Reading (one of several encodings that decode identically): with E1 > E2 the block
     is (e0, e1) = (E1, E2) in 8-value mode and weight J maps to code 0 (J = 0), 1 (J = 7)
     or J + 1; with E1 < E2 the endpoints swap and J becomes 7 - J; with E1 = E2 the block
     is (E, E) in 6-value mode with every code 0.
     """
-    Hb, Wb = endpoints.shape[0], endpoints.shape[1]
-    E1 = quantise_endpoint(endpoints[..., 0])        # [Hb][Wb][8]
+    Hb, Wb, C = endpoints.shape[0], endpoints.shape[1], endpoints.shape[2]
+    E1 = quantise_endpoint(endpoints[..., 0])        # [Hb][Wb][C]
     E2 = quantise_endpoint(endpoints[..., 1])
-    J = quantise_weight(weights)                     # [H][W][8]
-    out = np.zeros((Hb, Wb, N_SPATIAL, 8), dtype=np.uint8)
+    J = quantise_weight(weights)                     # [H][W][C]
+    out = np.zeros((Hb, Wb, C, 8), dtype=np.uint8)
     for by in range(Hb):
         for bx in range(Wb):
-            for c in range(N_SPATIAL):
+            for c in range(C):
                 a, b = int(E1[by, bx, c]), int(E2[by, bx, c])
                 field = 0
                 for s in range(16):
@@ -665,6 +665,223 @@ def export_bc4(endpoints: np.ndarray, weights: np.ndarray) -> np.ndarray:
                 for k in range(6):
                     out[by, bx, c, 2 + k] = (field >> (8 * k)) & 0xFF
     return out
+
+
+# --------------------------------------------------------------------------------------
+# Training of the hybrid layout (Sec. 3.4, Eq. 6-8; Sec. 4)
+# --------------------------------------------------------------------------------------
+# State (float32 master copies, one array per key):
+#   fuv_ep [H/4][W/4][4][2], fuv_w [H][W][4]            F_uv under BC simulation
+#   fuvt_ep [S][Gv/4][Gu/4][4][2], fuvt_w [S][Gv][Gu][4]  F_uvt slices under BC simulation
+#   fut [Tt][U][2], fvt [Tt][V][2]                       8-bit planes (trained in float)
+#   mlp [hybrid_mlp_size(hidden)]
+# A training sample is texel (x, y) of baked frame i (time keys[i], or i / (n - 1) with no
+# key table), so tau = i / (n - 1).  Readings:
+# * flags: BCSIM quantises F_uv / F_uvt to the decodable 8-bit endpoints and 3-bit weights
+#   (R12) with the straight-through gradient (R14); without it the features are the plain
+#   Eq. (7) lerp (the ablation of the simulation).  NOISE adds U(-1/2, 1/2) / 256 to each of
+#   the 12 sampled map values (Eq. 8 for V_ut and V_vt; the paper adds noise to V_uvt and
+#   V_uv after the simulation as well).  QPLANES feeds F_ut / F_vt rounded to 8 bits, the
+#   values a decode sees (used to fine-tune the decoder on frozen features, Sec. 4).
+# * the noise of sample s, channel c in step `step` is a counter-based draw: the 64-bit
+#   SplitMix64 output function (Steele, Lea, Flood 2014) applied to
+#   seed * 0x9E3779B97F4A7C15 + step * 2^32 + s * 16 + c; its top 24 bits / 2^24 - 1/2.
+HT_BCSIM, HT_NOISE, HT_QPLANES = 1, 2, 4
+NOISE_ALPHA = 1.0 / 256.0
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(x):
+    """SplitMix64 output function on uint64 (numpy arrays wrap modulo 2^64)."""
+    x = np.asarray(x, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        x = x + np.uint64(0x9E3779B97F4A7C15)
+        x = (x ^ (x >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        x = (x ^ (x >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return x ^ (x >> np.uint64(31))
+
+
+def hybrid_noise(seed: int, step: int, s, c) -> np.ndarray:
+    """U(-1/2, 1/2) draws of samples s, channels c (broadcast) in one step."""
+    base = np.uint64((seed * 0x9E3779B97F4A7C15 + (step << 32)) & _M64)
+    with np.errstate(over="ignore"):
+        ctr = base + (np.asarray(s, dtype=np.uint64) * np.uint64(16) + np.asarray(c, dtype=np.uint64))
+    top = (splitmix64(ctr) >> np.uint64(40)).astype(np.float64)
+    return top / float(1 << 24) - 0.5
+
+
+def _bc_texels(ep, wt, sl, ys, xs, bcsim: bool):
+    """4-channel texels of a BC-simulated map at (ys, xs) (and slice sl, or None):
+    (value in [0, 1], d/de1, d/de2, d/dw) per channel."""
+    if sl is None:
+        e = ep[ys >> 2, xs >> 2]            # [..., 4, 2]
+        w = wt[ys, xs]                      # [..., 4]
+    else:
+        e = ep[sl, ys >> 2, xs >> 2]
+        w = wt[sl, ys, xs]
+    if bcsim:
+        E1 = quantise_endpoint(e[..., 0]).astype(np.float64)
+        E2 = quantise_endpoint(e[..., 1]).astype(np.float64)
+        J = quantise_weight(w).astype(np.float64)
+        val = bcsim_value(E1.astype(np.int64), E2.astype(np.int64), J.astype(np.int64)) / 255.0
+        return val, 1.0 - J / 7.0, J / 7.0, (E2 - E1) / 255.0
+    e1 = e[..., 0].astype(np.float64)
+    e2 = e[..., 1].astype(np.float64)
+    w = w.astype(np.float64)
+    return (1.0 - w) * e1 + w * e2, 1.0 - w, w, e2 - e1
+
+
+def hybrid_train_forward(state: dict, xs, ys, fs, flags: int, seed: int = 0, step: int = 0,
+                         need_cache: bool = False):
+    """Decoder output at training samples (texel (x, y) of frame f) -> [B][3]."""
+    d = state["dims"]
+    xs = np.asarray(xs, dtype=np.int64)
+    ys = np.asarray(ys, dtype=np.int64)
+    fs = np.asarray(fs, dtype=np.int64)
+    nf = d["frames"]
+    tau = fs / (nf - 1) if nf > 1 else np.zeros(fs.shape)
+    keys = np.asarray(d["keys"], dtype=np.float64)
+    t = keys[fs] if keys.size else tau
+    bc = bool(flags & HT_BCSIM)
+    u = (xs + 0.5) / d["W"]
+    v = (ys + 0.5) / d["H"]
+    taps = {}
+    # V_uvt
+    gx0, gx1, wx0, wx1 = _axis(u, d["Gu"])
+    gy0, gy1, wy0, wy1 = _axis(v, d["Gv"])
+    s0, s1, ws0, ws1 = _node_axis(tau, d["S"])
+    Vuvt = np.zeros(xs.shape + (4,))
+    taps["uvt"] = []
+    for (ss, ws) in ((s0, ws0), (s1, ws1)):
+        for (yy, wy) in ((gy0, wy0), (gy1, wy1)):
+            for (xx, wx) in ((gx0, wx0), (gx1, wx1)):
+                val, d1, d2, dw = _bc_texels(state["fuvt_ep"], state["fuvt_w"], ss, yy, xx, bc)
+                w = ws * wy * wx
+                Vuvt += w[..., None] * val
+                taps["uvt"].append((ss, yy, xx, w, d1, d2, dw))
+    # V_uv: the texel itself
+    val, d1, d2, dw = _bc_texels(state["fuv_ep"], state["fuv_w"], None, ys, xs, bc)
+    Vuv = val
+    taps["uv"] = (d1, d2, dw)
+    # planes
+    k0, k1, wk0, wk1 = _node_axis(tau, d["Tt"])
+    planes = []
+    taps["planes"] = []
+    for (c, size, key) in ((u, d["U"], "fut"), (v, d["V"], "fvt")):
+        a0, a1, wa0, wa1 = _axis(c, size)
+        P = np.zeros(xs.shape + (2,))
+        arr = np.asarray(state[key], dtype=np.float64)
+        if flags & HT_QPLANES:
+            arr = np.rint(np.float32(255.0) * np.asarray(state[key], dtype=np.float32)).astype(np.float64) / 255.0
+        lst = []
+        for (kk, wk) in ((k0, wk0), (k1, wk1)):
+            for (aa, wa) in ((a0, wa0), (a1, wa1)):
+                P += (wk * wa)[..., None] * arr[kk, aa]
+                lst.append((kk, aa, wk * wa))
+        planes.append(P)
+        taps["planes"].append(lst)
+    x = np.concatenate([Vuvt, Vuv, planes[0], planes[1], gamma_t(t)], axis=-1)
+    if flags & HT_NOISE:
+        sidx = np.arange(xs.size).reshape(xs.shape)
+        x[..., :12] += NOISE_ALPHA * hybrid_noise(seed, step, sidx[..., None], np.arange(12))
+    P = unpack_hybrid_mlp(state["mlp"], d["hidden"])
+    a1 = x @ P["W1"].T + P["b1"]
+    h1 = gelu(a1)
+    a2 = h1 @ P["W2"].T + P["b2"]
+    h2 = gelu(a2)
+    out = h2 @ P["W3"].T + P["b3"]
+    if not need_cache:
+        return out
+    return out, dict(x=x, a1=a1, h1=h1, a2=a2, h2=h2, P=P, taps=taps)
+
+
+def gelu_grad(a: np.ndarray) -> np.ndarray:
+    """d GELU / da = Phi(a) + a phi(a)."""
+    from scipy.special import erf
+    a = np.asarray(a, dtype=np.float64)
+    return 0.5 * (1.0 + erf(a / np.sqrt(2.0))) + a * np.exp(-0.5 * a * a) / np.sqrt(2.0 * np.pi)
+
+
+def hybrid_train_grads(state: dict, xs, ys, fs, target, flags: int, seed: int = 0, step: int = 0):
+    """L2 loss (mean over samples and channels) and its gradients for every state array."""
+    d = state["dims"]
+    out, c = hybrid_train_forward(state, xs, ys, fs, flags, seed, step, need_cache=True)
+    target = np.asarray(target, dtype=np.float64)
+    n = out.size
+    loss = float(np.sum((out - target) ** 2) / n)
+    P = c["P"]
+    dout = (2.0 / n) * (out - target)
+    gW3, gb3 = dout.T @ c["h2"], dout.sum(0)
+    da2 = (dout @ P["W3"]) * gelu_grad(c["a2"])
+    gW2, gb2 = da2.T @ c["h1"], da2.sum(0)
+    da1 = (da2 @ P["W2"]) * gelu_grad(c["a1"])
+    gW1, gb1 = da1.T @ c["x"], da1.sum(0)
+    dx = da1 @ P["W1"]
+    g = {k: np.zeros(np.asarray(state[k]).shape) for k in ("fuv_ep", "fuv_w", "fuvt_ep", "fuvt_w", "fut", "fvt")}
+    g["mlp"] = np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3.ravel(), gb3])
+    xs = np.asarray(xs, dtype=np.int64)
+    ys = np.asarray(ys, dtype=np.int64)
+    ch = np.arange(4)[None, :]
+    for (ss, yy, xx, w, d1, d2, dw) in c["taps"]["uvt"]:
+        dv = w[:, None] * dx[:, 0:4]
+        sl, by, bx = ss[:, None], (yy >> 2)[:, None], (xx >> 2)[:, None]
+        np.add.at(g["fuvt_ep"], (sl, by, bx, ch, 0), dv * d1)
+        np.add.at(g["fuvt_ep"], (sl, by, bx, ch, 1), dv * d2)
+        np.add.at(g["fuvt_w"], (sl, yy[:, None], xx[:, None], ch), dv * dw)
+    d1, d2, dw = c["taps"]["uv"]
+    dv = dx[:, 4:8]
+    np.add.at(g["fuv_ep"], ((ys >> 2)[:, None], (xs >> 2)[:, None], ch, 0), dv * d1)
+    np.add.at(g["fuv_ep"], ((ys >> 2)[:, None], (xs >> 2)[:, None], ch, 1), dv * d2)
+    np.add.at(g["fuv_w"], (ys[:, None], xs[:, None], ch), dv * dw)
+    for pi, key in enumerate(("fut", "fvt")):
+        dv = dx[:, 8 + 2 * pi: 10 + 2 * pi]
+        for (kk, aa, w) in c["taps"]["planes"][pi]:
+            np.add.at(g[key], (kk[:, None], aa[:, None], np.arange(2)[None, :]), w[:, None] * dv)
+    return loss, g
+
+
+HYB_KEYS = ("fuv_ep", "fuv_w", "fuvt_ep", "fuvt_w", "fut", "fvt", "mlp")
+
+
+def hybrid_train_step(state: dict, opt: dict, xs, ys, fs, target, flags: int, seed: int = 0):
+    """Forward, L2 loss, backward, Adam on every array (lr_feat for the feature maps,
+    lr_mlp for the decoder), feature maps projected to [0, 1].  Returns the loss."""
+    loss, g = hybrid_train_grads(state, xs, ys, fs, target, flags, seed, opt["step"])
+    opt["step"] += 1
+    for key in HYB_KEYS:
+        lr = opt["lr_mlp"] if key == "mlp" else opt["lr_feat"]
+        p, m, v = adam_update(state[key], g[key], opt["m"][key], opt["v"][key], opt["step"], lr)
+        if key != "mlp":
+            p = np.clip(p, 0.0, 1.0)
+        state[key], opt["m"][key], opt["v"][key] = p, m, v
+    return loss
+
+
+def hybrid_normalise_target(target: np.ndarray, gamma: float):
+    """Sec. 4 preprocessing: gamma correction y^(1/gamma), then per frame and channel
+    division by the mean.  target [n][H][W][3] (FP16 values read exactly) -> (normalised
+    [n][H][W][3], means [n][3])."""
+    y = np.asarray(target, dtype=np.float64) ** (1.0 / gamma)
+    means = y.mean(axis=(1, 2))
+    return y / means[:, None, None, :], means
+
+
+def hybrid_restore(pred: np.ndarray, mean3, gamma: float) -> np.ndarray:
+    """Inverse of the preprocessing for one frame: (pred * mean)^gamma (negative products
+    clamp to 0)."""
+    return np.maximum(np.asarray(pred, dtype=np.float64) * np.asarray(mean3, dtype=np.float64), 0.0) ** gamma
+
+
+def hybrid_export(state: dict) -> dict:
+    """Decodable hybrid model of a trained state: BC4 blocks of F_uv and of each F_uvt
+    slice (export_bc4), planes rounded to 8 bits (rint of the float32 product 255 v)."""
+    d = state["dims"]
+    fuvt = np.stack([export_bc4(state["fuvt_ep"][s], state["fuvt_w"][s]) for s in range(d["S"])])
+    q = lambda a: np.rint(np.float32(255.0) * np.asarray(a, dtype=np.float32)).astype(np.uint8)
+    return dict(W=d["W"], H=d["H"], Gu=d["Gu"], Gv=d["Gv"], S=d["S"], U=d["U"], V=d["V"], Tt=d["Tt"],
+                hidden=d["hidden"], fuv=export_bc4(state["fuv_ep"], state["fuv_w"]), fuvt=fuvt,
+                fut=q(state["fut"]), fvt=q(state["fvt"]), keys=np.asarray(d["keys"], dtype=np.float32),
+                mlp=np.asarray(state["mlp"], dtype=np.float32))
 
 
 # --------------------------------------------------------------------------------------

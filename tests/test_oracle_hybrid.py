@@ -180,3 +180,111 @@ def test_hybrid_page_decode_equals_texel_centre_queries():
     y, x = np.meshgrid(np.arange(128), np.arange(128), indexing="ij")
     q = np.stack([((x + 0.5) / 128).ravel(), ((y + 0.5) / 128).ravel(), np.full(128 * 128, t)], 1)
     np.testing.assert_allclose(dst, O.hybrid_decode(m, q.astype(np.float32)), rtol=1e-13, atol=1e-15)
+
+
+# ----------------------------------------------------------------- hybrid training pins
+def tiny_hybrid_state(hidden=16, seed=0, frames=3, keys=True, on_grid=False):
+    """A small trainable hybrid state: 8 x 8 map, F_uvt 4 x 4 x 3, planes 4 x 3."""
+    g = np.random.default_rng(seed)
+    W = H = 8
+    Gu = Gv = 4
+    S, U, V, Tt = 3, 4, 4, 3
+    kt = np.sort(g.uniform(0, 1, frames)).astype(np.float32) if keys else np.zeros(0, np.float32)
+    st = dict(dims=dict(W=W, H=H, Gu=Gu, Gv=Gv, S=S, U=U, V=V, Tt=Tt, hidden=hidden, frames=frames, keys=kt))
+    st["fuv_ep"] = g.uniform(0, 1, (H // 4, W // 4, 4, 2))
+    st["fuv_w"] = g.uniform(0, 1, (H, W, 4))
+    st["fuvt_ep"] = g.uniform(0, 1, (S, Gv // 4, Gu // 4, 4, 2))
+    st["fuvt_w"] = g.uniform(0, 1, (S, Gv, Gu, 4))
+    if on_grid:
+        # endpoints on the 8-bit grid and weights 0 or 1: the simulated value equals the lerp
+        for k in ("fuv_ep", "fuvt_ep"):
+            st[k] = g.integers(0, 256, st[k].shape) / 255.0
+        for k in ("fuv_w", "fuvt_w"):
+            st[k] = g.integers(0, 2, st[k].shape).astype(np.float64)
+    st["fut"] = g.uniform(0, 1, (Tt, U, 2))
+    st["fvt"] = g.uniform(0, 1, (Tt, V, 2))
+    st["mlp"] = I.hybrid_mlp(hidden, np.float64, g)
+    for k in O.HYB_KEYS:
+        st[k] = np.asarray(st[k], dtype=np.float64)
+    return st
+
+
+def _batch(st, n, seed):
+    g = np.random.default_rng(seed)
+    d = st["dims"]
+    return g.integers(0, d["W"], n), g.integers(0, d["H"], n), g.integers(0, d["frames"], n), g.normal(0, 1, (n, 3))
+
+
+def test_splitmix64_published_outputs_and_noise_range():
+    # the generator's first two outputs from state 0 (reference implementation of SplitMix64)
+    assert int(O.splitmix64(0)) == 0xE220A8397B1DCDAF
+    assert int(O.splitmix64(0x9E3779B97F4A7C15)) == 0x6E789E6AA1B965F4
+    z = O.hybrid_noise(7, 3, np.arange(20000)[:, None], np.arange(12)[None, :])
+    assert z.min() >= -0.5 and z.max() < 0.5
+    assert abs(z.mean()) < 5e-3 and abs(z.var() - 1 / 12) < 2e-3
+    assert not np.array_equal(z, O.hybrid_noise(7, 4, np.arange(20000)[:, None], np.arange(12)[None, :]))
+
+
+def _fd_check(st, xs, ys, fs, tgt, flags, keys, h=1e-6, n_probe=12, seed=5):
+    loss, g = O.hybrid_train_grads(st, xs, ys, fs, tgt, flags, seed=9, step=2)
+    rng = np.random.default_rng(seed)
+    for key in keys:
+        a = st[key]
+        flat = a.reshape(-1)
+        gflat = g[key].reshape(-1)
+        idx = np.argsort(-np.abs(gflat))[:n_probe // 2]
+        idx = np.concatenate([idx, rng.integers(0, flat.size, n_probe - idx.size)])
+        for i in idx:
+            old = flat[i]
+            flat[i] = old + h
+            lp = O.hybrid_train_grads(st, xs, ys, fs, tgt, flags, seed=9, step=2)[0]
+            flat[i] = old - h
+            lm = O.hybrid_train_grads(st, xs, ys, fs, tgt, flags, seed=9, step=2)[0]
+            flat[i] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - gflat[i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (key, int(i), fd, gflat[i])
+
+
+def test_hybrid_gradients_match_finite_differences():
+    for hidden in (16, 64):
+        st = tiny_hybrid_state(hidden, seed=hidden)
+        xs, ys, fs, tgt = _batch(st, 40, seed=hidden + 1)
+        # continuous features (no simulation): every array; with noise on, fixed draws
+        _fd_check(st, xs, ys, fs, tgt, O.HT_NOISE, O.HYB_KEYS)
+        # under the simulation the decoder and the planes still have exact derivatives
+        _fd_check(st, xs, ys, fs, tgt, O.HT_BCSIM | O.HT_NOISE, ("mlp", "fut", "fvt"))
+
+
+def test_straight_through_gradient_is_the_lerp_gradient_on_the_grid():
+    st = tiny_hybrid_state(16, seed=3, on_grid=True)
+    xs, ys, fs, tgt = _batch(st, 50, seed=4)
+    l1, g1 = O.hybrid_train_grads(st, xs, ys, fs, tgt, O.HT_BCSIM)
+    l0, g0 = O.hybrid_train_grads(st, xs, ys, fs, tgt, 0)
+    assert abs(l1 - l0) < 1e-12
+    for k in O.HYB_KEYS:
+        np.testing.assert_allclose(g1[k], g0[k], atol=1e-12)
+
+
+def test_export_decodes_to_the_simulated_forward():
+    st = tiny_hybrid_state(64, seed=6)
+    for k in ("fut", "fvt"):
+        st[k] = np.asarray(st[k], dtype=np.float32).astype(np.float64)
+    m = O.hybrid_export(st)
+    d = st["dims"]
+    y, x = np.meshgrid(np.arange(d["H"]), np.arange(d["W"]), indexing="ij")
+    for f in range(d["frames"]):
+        n = x.size
+        fwd = O.hybrid_train_forward(st, x.ravel(), y.ravel(), np.full(n, f), O.HT_BCSIM | O.HT_QPLANES)
+        t = np.full(n, np.float64(d["keys"][f]))
+        dec = O.hybrid_decode_f64(m, (x.ravel() + 0.5) / d["W"], (y.ravel() + 0.5) / d["H"], t)
+        np.testing.assert_allclose(dec, fwd, rtol=0, atol=1e-12)
+
+
+def test_target_normalisation_closed_form():
+    tgt = np.stack([np.full((4, 4, 3), 2.0), np.full((4, 4, 3), 0.5)])
+    tgt[1, :, :, 2] = 8.0
+    y, means = O.hybrid_normalise_target(tgt, 2.2)
+    np.testing.assert_allclose(y, 1.0, atol=1e-15)
+    np.testing.assert_allclose(means[0], 2.0 ** (1 / 2.2), rtol=1e-15)
+    np.testing.assert_allclose(means[1], [0.5 ** (1 / 2.2), 0.5 ** (1 / 2.2), 8.0 ** (1 / 2.2)], rtol=1e-15)
+    np.testing.assert_allclose(O.hybrid_restore(y[1, 0, 0], means[1], 2.2), [0.5, 0.5, 8.0], rtol=1e-14)
