@@ -334,6 +334,81 @@ int ndgi_hybrid_decode_pages_graph(ndgi_ctx* ctx, const ndgi_hybrid_model* model
                                    int32_t max_reqs, int32_t page, void* dst, int64_t dst_pitch,
                                    int32_t prec, int32_t widths, hipStream_t stream);
 
+/* Trainable state of a hybrid model (Sec. 3.4, Eq. 6-8; Sec. 4).  One flat float32 layout
+ * shared by params, grads, adam_m, adam_v:
+ *   [ F_uv endpoints [H/4][W/4][4][2] | F_uv weights [H][W][4]
+ *   | F_uvt endpoints [S][Gv/4][Gu/4][4][2] | F_uvt weights [S][Gv][Gu][4]
+ *   | F_ut [Tt][U][2] | F_vt [Tt][V][2] | decoder [ndgi_hybrid_mlp_size(hidden)] ]
+ * (ndgi_hybrid_train_param_count values).  Sizes as ndgi_hybrid_model, with W, H <= 4096.
+ * A training sample is texel (x, y) of baked frame f: t = keys[f] (keys given) or
+ * f / (frames - 1), and tau = f / (frames - 1). */
+typedef struct ndgi_hybrid_train_state {
+    int32_t W, H, Gu, Gv, S, U, V, Tt, hidden;
+    int32_t frames;           /* baked frames of the target, 1..256                       */
+    const float* keys;        /* device [frames] frame times, or NULL (uniform)           */
+    float* params;
+    float* grads;
+    float* adam_m;
+    float* adam_v;
+    int64_t step;             /* Adam steps taken; ADAM and FUSED increment it            */
+    float lr_feat, lr_mlp;    /* Adam learning rates of the feature maps / the decoder    */
+    float beta1, beta2, eps;
+    uint32_t seed;            /* seed of the noise draws                                  */
+} ndgi_hybrid_train_state;
+
+typedef struct ndgi_hybrid_batch {
+    const uint32_t* samples;  /* device [n]: x | y << 12 | f << 24                        */
+    int64_t n;                /* 1 .. 2^31 - 1                                            */
+    const float* target;      /* device [frames][H][W][3] preprocessed target (LOSS_GRAD,
+                                 FUSED; see ndgi_hybrid_normalize_target)                 */
+    float* pred;              /* device [n][3] (FORWARD)                                  */
+} ndgi_hybrid_batch;
+
+/* Feature flags of a hybrid training step:
+ *   BCSIM   F_uv and F_uvt under BC simulation: E = rint(fl32(255 e)), J = rint(fl32(7 w)),
+ *           value floor(((7-J) E1 + J E2 + 3)/7) / 255, straight-through gradient of Eq. 7
+ *           at (E/255, J/7); without it the plain Eq. 7 lerp (the simulation's ablation).
+ *   NOISE   U(-1/2, 1/2) / 256 added to each of the 12 sampled map values (Eq. 8); draw c of
+ *           sample s in a step is the SplitMix64 output of seed * 0x9E3779B97F4A7C15 +
+ *           step * 2^32 + 16 s + c, top 24 bits / 2^24 - 1/2.
+ *   QPLANES F_ut and F_vt rounded to 8 bits as a decode sees them (decoder fine-tune on
+ *           frozen features: lr_feat = 0). */
+#define NDGI_HTRAIN_BCSIM   1
+#define NDGI_HTRAIN_NOISE   2
+#define NDGI_HTRAIN_QPLANES 4
+
+/* Total float parameters of a hybrid state; -1 for sizes out of range. */
+int64_t ndgi_hybrid_train_param_count(int32_t W, int32_t H, int32_t Gu, int32_t Gv, int32_t S, int32_t U,
+                                      int32_t V, int32_t Tt, int32_t hidden);
+
+/* One hybrid training operation: mode NDGI_TRAIN_FORWARD (pred), NDGI_TRAIN_LOSS_GRAD
+ * (*loss_dev = mean over samples and channels of (pred - target)^2, FP64; grads +=), FUSED
+ * (LOSS_GRAD then ADAM), ADAM (dense Adam, PyTorch semantics, feature maps projected to
+ * [0, 1], grads zeroed, step += 1), ZERO_GRAD.  flags: NDGI_HTRAIN_*.  Errors: INVALID_ARG. */
+int ndgi_hybrid_train_step(ndgi_ctx* ctx, ndgi_hybrid_train_state* state, const ndgi_hybrid_batch* batch,
+                           int32_t mode, int32_t flags, double* loss_dev, hipStream_t stream);
+
+/* Export a trained state as a decodable hybrid model (Sec. 3.4 last paragraph): BC4 blocks of
+ * F_uv ([H/4][W/4][4][8]) and of every F_uvt slice ([S][Gv/4][Gu/4][4][8]) in the encoding of
+ * ndgi_export, planes rounded to 8 bits (rint of fl32(255 v)), decoder converted to
+ * mlp_dtype.  The decode of the export at a training sample equals the FORWARD with
+ * BCSIM | QPLANES.  Errors: INVALID_ARG. */
+int ndgi_hybrid_export(ndgi_ctx* ctx, const ndgi_hybrid_train_state* state, uint8_t* fuv_out,
+                       uint8_t* fuvt_out, uint8_t* fut_out, uint8_t* fvt_out, void* mlp_out,
+                       int32_t mlp_dtype, hipStream_t stream);
+
+/* Target preprocessing of Sec. 4: y^(1/gamma) per texel and channel, divided per frame and
+ * channel by its mean.  target: device FP16 bits [frames][H][W][3]; out: device float, same
+ * shape; means: device double [frames][3] (the means, for ndgi_hybrid_restore).
+ * Errors: INVALID_ARG. */
+int ndgi_hybrid_normalize_target(ndgi_ctx* ctx, const uint16_t* target, int32_t frames, int32_t W,
+                                 int32_t H, float gamma, float* out, double* means, hipStream_t stream);
+
+/* Inverse for one decoded frame: out = max(pred * mean, 0)^gamma, pred [texels][3] of
+ * pred_dtype, mean3 device double [3], out device float [texels][3]. */
+int ndgi_hybrid_restore(ndgi_ctx* ctx, const void* pred, int32_t pred_dtype, int64_t texels,
+                        const double* mean3, float gamma, float* out, hipStream_t stream);
+
 /* ---------------------------------------------------------------- evaluation */
 
 /* Per-tile statistics for the tiled PSNR of supplementary Sec. D.2, in FP64.

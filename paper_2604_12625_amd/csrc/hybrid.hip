@@ -18,19 +18,10 @@
 // steps); the output layer's chunk holds W3 on rows 4k..4k+2 of every row quad k, and group
 // q keeps quad q only, so the 4 groups write rows 4q..4q+2 of one accumulator and after
 // them lane l owns the RGB of texel l of the pass.
-#include "device.hpp"
+#include "hybrid.hpp"
 #include "internal.hpp"
 
 namespace ndgi {
-
-template <int HD>
-struct HybShape {
-  static constexpr int NB = HD / 16;                           // row blocks of a hidden layer
-  static constexpr int kL1 = 0, kL2 = NB, kL3 = NB + NB * NB;  // first chunk of each layer
-  static constexpr int kChunks = NB + NB * NB + NB;
-  static constexpr int oW1 = 0, oB1 = HD * NDGI_HYBRID_IN, oW2 = oB1 + HD, oB2 = oW2 + HD * HD,
-                       oW3 = oB2 + HD, oB3 = oW3 + 3 * HD, kSize = oB3 + 3;
-};
 
 template <int HD>
 struct HybTab {
@@ -85,58 +76,6 @@ template <int PREC, int HD>
 __device__ void hyb_build(HybTab<HD>& T, const void* mlp, int mlp_dtype) {
   if (mlp_dtype == NDGI_DTYPE_F16) hyb_build_dt<PREC, HD, NDGI_DTYPE_F16>(T, mlp);
   else hyb_build_dt<PREC, HD, NDGI_DTYPE_F32>(T, mlp);
-}
-
-// GELU(x) = x Phi(x) = max(x, 0) - |x| * erfc(|x| / sqrt 2) / 2: both signs are the same
-// expression, with no cancellation for large |x|.  The factor 1/2 and the argument scale
-// 1/sqrt 2 are folded into the constants below.
-//  * FP32 path: erfc by the Chebyshev fit of Press et al., Numerical Recipes (erfcc),
-//    relative error below 1.2e-7 for every argument: erfc(z) = t exp(-z^2 + p(t)) with
-//    t = 1 / (1 + z/2); here exp runs in base 2 with log2(e) folded into p and ln(1/2)
-//    added to its constant term;
-//  * FP16 path: erfc(z) = P(z)^-16 with the degree-6 P of Abramowitz & Stegun 7.1.28,
-//    absolute error at most 3e-7 (far below the FP16 rounding of the activations), one
-//    reciprocal and no exponential; P is taken in |x| and scaled by 2^(1/16), so that the
-//    16th power of its reciprocal is erfc / 2.
-namespace gelu_k {
-constexpr double kLog2e = 1.4426950408889634, kRs2 = 0.70710678118654752, kLn2 = 0.69314718055994531;
-constexpr double kS16 = 1.0442737824274138;   // 2^(1/16)
-// Numerical Recipes erfcc coefficients, innermost first, then the constant term
-constexpr double kNR[10] = {0.17087277, -0.82215223, 1.48851587, -1.13520398, 0.27886807,
-                            -0.18628806, 0.09678418, 0.37409196, 1.00002368, -1.26551223};
-// Abramowitz & Stegun 7.1.28: a6 .. a1
-constexpr double kAS[6] = {0.0000430638, 0.0002765672, 0.0001520143, 0.0092705272, 0.0422820123, 0.0705230784};
-constexpr float nr_c(int i) { return (float)(kLog2e * (i == 9 ? kNR[9] - kLn2 : kNR[i])); }
-constexpr double pw(double x, int k) { return k == 0 ? 1.0 : x * pw(x, k - 1); }
-constexpr float as_c(int i) { return (float)(kS16 * kAS[i] * pw(kRs2, 6 - i)); }   // coefficient of |x|^(6-i)
-// evaluated by the compiler (constexpr variables), never on the device
-constexpr float kNRf[10] = {nr_c(0), nr_c(1), nr_c(2), nr_c(3), nr_c(4), nr_c(5), nr_c(6), nr_c(7), nr_c(8), nr_c(9)};
-constexpr float kASf[6] = {as_c(0), as_c(1), as_c(2), as_c(3), as_c(4), as_c(5)};
-}  // namespace gelu_k
-
-template <int PREC>
-__device__ __forceinline__ float gelu(float x) {
-  using namespace gelu_k;
-  const float ax = fabsf(x);
-  float half_erfc;
-  if constexpr (PREC == NDGI_PREC_F32) {
-    const float t = __builtin_amdgcn_rcpf(fmaf((float)(0.5 * kRs2), ax, 1.0f));
-    float p = fmaf(t, kNRf[0], kNRf[1]);
-#pragma unroll
-    for (int i = 2; i < 10; ++i) p = fmaf(t, p, kNRf[i]);
-    half_erfc = t * __builtin_amdgcn_exp2f(fmaf(x * x, (float)(-0.5 * kLog2e), p));
-  } else {
-    float p = fmaf(ax, kASf[0], kASf[1]);
-#pragma unroll
-    for (int i = 2; i < 6; ++i) p = fmaf(ax, p, kASf[i]);
-    p = fmaf(ax, p, (float)kS16);
-    float r = __builtin_amdgcn_rcpf(p);
-    r *= r;
-    r *= r;
-    r *= r;
-    half_erfc = r * r;
-  }
-  return fmaf(-ax, half_erfc, fmaxf(x, 0.0f));
 }
 
 // One group of 16 texels through the decoder; x = this lane's K share of layer 1 (inputs
@@ -238,42 +177,6 @@ __device__ __forceinline__ void store_lin(void* out, size_t idx, const f4v& z, b
 }
 
 // ---------------------------------------------------------------------- time axis
-__device__ __forceinline__ float clamp01(float t) { return fminf(fmaxf(t, 0.0f), 1.0f); }   // NaN -> 0
-
-// Time coordinate tau of a clamped t: piecewise linear through (key_i, i / (n - 1)), clamped
-// to [0, 1]; t itself without a key table.  The segment is the last key <= t (within
-// [0, n-2]), found by a fixed-step binary search.
-template <typename KeyAt>
-__device__ __forceinline__ float key_tau(float tc, int n, KeyAt key) {
-  if (n < 2) return tc;
-  int i = 0;
-  for (int step = NDGI_HYBRID_MAX_KEYS / 2; step > 0; step >>= 1) {
-    const int j = i + step;
-    if (key(min(j, n - 2)) <= tc && j <= n - 2) i = j;   // the read stays inside the table
-  }
-  const float k0 = key(i), k1 = key(i + 1);
-  const float f = (tc - k0) / (k1 - k0);
-  return clamp01(((float)i + f) / (float)(n - 1));
-}
-
-// Linear interpolation over N samples held at tau = k / (N - 1).
-struct NodeT { int i0, i1; float w0, w1; };
-__device__ __forceinline__ NodeT node_axis(float tau, int N) {
-  NodeT a;
-  if (N < 2) {
-    a.i0 = a.i1 = 0;
-    a.w0 = 1.0f;
-    a.w1 = 0.0f;
-    return a;
-  }
-  const float p = tau * (float)(N - 1);
-  a.i0 = min((int)floorf(p), N - 2);
-  a.i1 = a.i0 + 1;
-  a.w1 = p - (float)a.i0;
-  a.w0 = 1.0f - a.w1;
-  return a;
-}
-
 struct HybTime {
   NodeT s;      // F_uvt slices
   NodeT k;      // F_ut / F_vt rows

@@ -1,0 +1,560 @@
+// Training of the hybrid layout (Sec. 3.4, Eq. 6-8; Sec. 4): BC simulation of F_uv and of
+// each F_uvt slice, 8-bit planes F_ut / F_vt trained in float with uniform noise standing
+// in for their quantisation, the GELU decoder, L2 loss in FP64, gradients, Adam (shared
+// with the other layout), export to a decodable model, and the target preprocessing
+// (gamma, per-frame mean) with its inverse.
+//
+// One sample per lane.  A training sample is texel (x, y) of baked frame f, so its texel
+// centre and frame time fix every interpolation weight.  The decoder runs in FP32 on the
+// VALU from weights staged in LDS (hidden 16 or 64); the weight gradients are the sums
+// over samples of outer products, reduced across the wave with lane shuffles and added to
+// the gradient array by one lane; feature gradients go out as float atomics.
+#include "hybrid.hpp"
+#include "internal.hpp"
+
+namespace ndgi {
+
+__device__ __forceinline__ float half_bits_f(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
+
+struct HybTrainDims {
+  int W, H, Gu, Gv, S, U, V, Tt, hidden, frames;
+  int64_t o_uvw, o_tep, o_tw, o_ut, o_vt, o_mlp, n;   // segment offsets (F_uv endpoints at 0), total
+};
+
+static HybTrainDims htd_of(const ndgi_hybrid_train_state* st) {
+  HybTrainDims d;
+  d.W = st->W;
+  d.H = st->H;
+  d.Gu = st->Gu;
+  d.Gv = st->Gv;
+  d.S = st->S;
+  d.U = st->U;
+  d.V = st->V;
+  d.Tt = st->Tt;
+  d.hidden = st->hidden;
+  d.frames = st->frames;
+  d.o_uvw = (int64_t)(d.H / 4) * (d.W / 4) * 4 * 2;
+  d.o_tep = d.o_uvw + (int64_t)d.H * d.W * 4;
+  d.o_tw = d.o_tep + (int64_t)d.S * (d.Gv / 4) * (d.Gu / 4) * 4 * 2;
+  d.o_ut = d.o_tw + (int64_t)d.S * d.Gv * d.Gu * 4;
+  d.o_vt = d.o_ut + (int64_t)d.Tt * d.U * 2;
+  d.o_mlp = d.o_vt + (int64_t)d.Tt * d.V * 2;
+  d.n = d.o_mlp + ndgi_hybrid_mlp_size(d.hidden);
+  return d;
+}
+
+// Counter-based uniform draw in [-1/2, 1/2): the SplitMix64 output function (Steele, Lea,
+// Flood 2014) of base + counter, top 24 bits.  Exact in FP32.
+__device__ __forceinline__ float hyb_noise(uint64_t base, uint64_t ctr) {
+  uint64_t x = base + ctr + 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  x ^= x >> 31;
+  return (float)(uint32_t)(x >> 40) * (1.0f / 16777216.0f) - 0.5f;
+}
+
+// One 4-channel texel of a BC-simulated map: ep = the footprint's [4][2] endpoints,
+// w = the texel's 4 weights.  With the simulation: E = rint(fl32(255 e)), J = rint(fl32(7 w)),
+// value floor(((7-J) E1 + J E2 + 3) / 7) / 255 and the straight-through derivatives of
+// Eq. 7 at (E/255, J/7); without it, Eq. 7 itself.
+struct BcTex { float v[4], d1[4], d2[4], dw[4]; };
+__device__ __forceinline__ BcTex bc_texel(const float* __restrict__ ep, const float* __restrict__ w, bool bcsim) {
+#pragma clang fp contract(off)
+  BcTex r;
+  const float4 ea = *(const float4*)ep, eb = *(const float4*)(ep + 4);
+  const float4 wv = *(const float4*)w;
+  const float e1[4] = {ea.x, ea.z, eb.x, eb.z}, e2[4] = {ea.y, ea.w, eb.y, eb.w}, ww[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (bcsim) {
+      const int E1 = (int)rintf(255.0f * e1[c]), E2 = (int)rintf(255.0f * e2[c]), J = (int)rintf(7.0f * ww[c]);
+      r.v[c] = (float)(((7 - J) * E1 + J * E2 + 3) / 7) * (1.0f / 255.0f);
+      r.d1[c] = 1.0f - (float)J * (1.0f / 7.0f);
+      r.d2[c] = (float)J * (1.0f / 7.0f);
+      r.dw[c] = (float)(E2 - E1) * (1.0f / 255.0f);
+    } else {
+      r.v[c] = (1.0f - ww[c]) * e1[c] + ww[c] * e2[c];
+      r.d1[c] = 1.0f - ww[c];
+      r.d2[c] = ww[c];
+      r.dw[c] = e2[c] - e1[c];
+    }
+  }
+  return r;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the wave of a per-lane gradient term, added to g[idx] by lane 0.
+__device__ __forceinline__ void wave_grad(float* __restrict__ g, int64_t idx, float v, int lane) {
+  v = wave_sum(v);
+  if (lane == 0) atomicAdd(g + idx, v);
+}
+
+constexpr int kHtWaves = 4;
+
+// MODE: NDGI_TRAIN_FORWARD writes pred; NDGI_TRAIN_LOSS_GRAD adds the loss and gradients.
+template <int HD, int MODE>
+__global__ __launch_bounds__(256) void k_hybrid_train(HybTrainDims d, const float* __restrict__ P, float* __restrict__ G,
+                                                       const float* __restrict__ keys,
+                                                       const uint32_t* __restrict__ samples, int64_t n,
+                                                       const float* __restrict__ target, float* __restrict__ pred,
+                                                       int flags, uint64_t noise_base, float inv3n,
+                                                       double* __restrict__ loss_acc) {
+  using Sh = HybShape<HD>;
+  __shared__ float sw[Sh::kSize];
+  const float* mlp = P + d.o_mlp;
+  for (int i = threadIdx.x; i < Sh::kSize; i += 256) sw[i] = mlp[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const bool bcsim = flags & NDGI_HTRAIN_BCSIM, noise = flags & NDGI_HTRAIN_NOISE, qplanes = flags & NDGI_HTRAIN_QPLANES;
+  float* gm = G + d.o_mlp;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  const int64_t rounds = (n + stride - 1) / stride;   // every lane runs the same rounds (wave reductions)
+  for (int64_t r = 0; r < rounds; ++r) {
+    const int64_t s = r * stride + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool live = s < n;
+    const uint32_t word = samples[live ? s : 0];
+    const int x = min((int)(word & 0xfffu), d.W - 1), y = min((int)((word >> 12) & 0xfffu), d.H - 1);
+    const int f = min((int)(word >> 24), d.frames - 1);
+    const float tau = d.frames > 1 ? (float)f / (float)(d.frames - 1) : 0.0f;
+    const float t = keys ? keys[f] : tau;
+    // ---- features
+    float xin[16];
+    const Axis gx = texel_axis<false>(x, d.Gu, d.W), gy = texel_axis<false>(y, d.Gv, d.H);
+    const NodeT ns = node_axis(tau, d.S), nk = node_axis(tau, d.Tt);
+    float tw[4];
+    tap_weights(gx, gy, tw);
+    const int txs[4] = {gx.i0, gx.i1, gx.i0, gx.i1}, tys[4] = {gy.i0, gy.i0, gy.i1, gy.i1};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) xin[c] = 0.0f;
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const int si = sl ? ns.i1 : ns.i0;
+      const float ws = sl ? ns.w1 : ns.w0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t fp = ((int64_t)si * (d.Gv / 4) + (tys[i] >> 2)) * (d.Gu / 4) + (txs[i] >> 2);
+        const BcTex b = bc_texel(P + d.o_tep + fp * 8, P + d.o_tw + (((int64_t)si * d.Gv + tys[i]) * d.Gu + txs[i]) * 4, bcsim);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) xin[c] = fmaf(ws * tw[i], b.v[c], xin[c]);
+      }
+    }
+    const int64_t fpu = (int64_t)(y >> 2) * (d.W / 4) + (x >> 2);
+    const BcTex bu = bc_texel(P + fpu * 8, P + d.o_uvw + ((int64_t)y * d.W + x) * 4, bcsim);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) xin[4 + c] = bu.v[c];
+    const Axis pu = texel_axis<false>(x, d.U, d.W), pv = texel_axis<false>(y, d.V, d.H);
+    auto plane_at = [&](int64_t off, int size, int k, int a, int c) {
+      const float v = P[off + ((int64_t)k * size + a) * 2 + c];
+      return qplanes ? rintf(__fmul_rn(255.0f, v)) * (1.0f / 255.0f) : v;
+    };
+#pragma unroll
+    for (int pl = 0; pl < 2; ++pl) {
+      const int64_t off = pl ? d.o_vt : d.o_ut;
+      const int size = pl ? d.V : d.U;
+      const Axis& a = pl ? pv : pu;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+          for (int aa = 0; aa < 2; ++aa)
+            acc = fmaf((kk ? nk.w1 : nk.w0) * (aa ? a.w1 : a.w0),
+                       plane_at(off, size, kk ? nk.i1 : nk.i0, aa ? a.i1 : a.i0, c), acc);
+        xin[8 + 2 * pl + c] = acc;
+      }
+    }
+    if (noise) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) xin[c] += (1.0f / 256.0f) * hyb_noise(noise_base, (uint64_t)s * 16u + (uint64_t)c);
+    }
+    {
+      float sn, cs;
+      sincospif(t, &sn, &cs);
+      xin[12] = sn;
+      xin[13] = cs;
+      xin[14] = 2.0f * sn * cs;
+      xin[15] = fmaf(cs, cs, -sn * sn);
+    }
+    // ---- decoder forward (pre-activations kept; activations recomputed when needed)
+    float a1[HD], a2[HD];
+#pragma unroll
+    for (int j = 0; j < HD; ++j) {
+      float acc = sw[Sh::oB1 + j];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc = fmaf(sw[Sh::oW1 + j * 16 + i], xin[i], acc);
+      a1[j] = acc;
+    }
+#pragma unroll
+    for (int j = 0; j < HD; ++j) a2[j] = sw[Sh::oB2 + j];
+#pragma unroll
+    for (int k = 0; k < HD; ++k) {
+      const float h = gelu<NDGI_PREC_F32>(a1[k]);
+#pragma unroll
+      for (int j = 0; j < HD; ++j) a2[j] = fmaf(sw[Sh::oW2 + j * HD + k], h, a2[j]);
+    }
+    float out[3] = {sw[Sh::oB3], sw[Sh::oB3 + 1], sw[Sh::oB3 + 2]};
+#pragma unroll
+    for (int j = 0; j < HD; ++j) {
+      const float h = gelu<NDGI_PREC_F32>(a2[j]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) out[c] = fmaf(sw[Sh::oW3 + c * HD + j], h, out[c]);
+    }
+    if constexpr (MODE == NDGI_TRAIN_FORWARD) {
+      if (live) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pred[s * 3 + c] = out[c];
+      }
+      continue;
+    } else {
+      // ---- loss and output gradient
+      float dout[3];
+      double sq = 0.0;
+      const int64_t ti = (((int64_t)f * d.H + y) * d.W + x) * 3;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float e = live ? out[c] - target[ti + c] : 0.0f;
+        sq += (double)e * (double)e;
+        dout[c] = 2.0f * inv3n * e;
+      }
+      sq = wave_sum_d(sq);
+      if (lane == 0) atomicAdd(loss_acc, sq * (double)inv3n);
+      // ---- decoder backward: layer 3
+#pragma unroll
+      for (int c = 0; c < 3; ++c) wave_grad(gm, Sh::oB3 + c, dout[c], lane);
+#pragma unroll
+      for (int j = 0; j < HD; ++j) {
+        const float h = gelu<NDGI_PREC_F32>(a2[j]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) wave_grad(gm, Sh::oW3 + c * HD + j, dout[c] * h, lane);
+        float dh = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dh = fmaf(sw[Sh::oW3 + c * HD + j], dout[c], dh);
+        a2[j] = dh * gelu_grad(a2[j]);   // a2 now holds d loss / d a2
+      }
+      // layer 2, then layer 1's pre-activation gradient (a1 is overwritten by it)
+#pragma unroll
+      for (int j = 0; j < HD; ++j) wave_grad(gm, Sh::oB2 + j, a2[j], lane);
+#pragma unroll
+      for (int k = 0; k < HD; ++k) {
+        const float h = gelu<NDGI_PREC_F32>(a1[k]);
+        float dh = 0.0f;
+#pragma unroll
+        for (int j = 0; j < HD; ++j) {
+          wave_grad(gm, Sh::oW2 + j * HD + k, a2[j] * h, lane);
+          dh = fmaf(sw[Sh::oW2 + j * HD + k], a2[j], dh);
+        }
+        a1[k] = dh * gelu_grad(a1[k]);
+      }
+      float dx[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) dx[i] = 0.0f;
+#pragma unroll
+      for (int k = 0; k < HD; ++k) {
+        wave_grad(gm, Sh::oB1 + k, a1[k], lane);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          wave_grad(gm, Sh::oW1 + k * 16 + i, a1[k] * xin[i], lane);
+          dx[i] = fmaf(sw[Sh::oW1 + k * 16 + i], a1[k], dx[i]);
+        }
+      }
+      if (!live) continue;
+      // ---- feature gradients (straight-through for the simulated maps)
+#pragma unroll
+      for (int sl = 0; sl < 2; ++sl) {
+        const int si = sl ? ns.i1 : ns.i0;
+        const float ws = sl ? ns.w1 : ns.w0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int64_t fp = ((int64_t)si * (d.Gv / 4) + (tys[i] >> 2)) * (d.Gu / 4) + (txs[i] >> 2);
+          const int64_t wi = (((int64_t)si * d.Gv + tys[i]) * d.Gu + txs[i]) * 4;
+          const BcTex b = bc_texel(P + d.o_tep + fp * 8, P + d.o_tw + wi, bcsim);
+          const float wt = ws * tw[i];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const float dv = wt * dx[c];
+            atomicAdd(G + d.o_tep + fp * 8 + 2 * c, dv * b.d1[c]);
+            atomicAdd(G + d.o_tep + fp * 8 + 2 * c + 1, dv * b.d2[c]);
+            atomicAdd(G + d.o_tw + wi + c, dv * b.dw[c]);
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        atomicAdd(G + fpu * 8 + 2 * c, dx[4 + c] * bu.d1[c]);
+        atomicAdd(G + fpu * 8 + 2 * c + 1, dx[4 + c] * bu.d2[c]);
+        atomicAdd(G + d.o_uvw + ((int64_t)y * d.W + x) * 4 + c, dx[4 + c] * bu.dw[c]);
+      }
+#pragma unroll
+      for (int pl = 0; pl < 2; ++pl) {
+        const int64_t off = pl ? d.o_vt : d.o_ut;
+        const int size = pl ? d.V : d.U;
+        const Axis& a = pl ? pv : pu;
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+          for (int aa = 0; aa < 2; ++aa) {
+            const float w = (kk ? nk.w1 : nk.w0) * (aa ? a.w1 : a.w0);
+            const int64_t idx = off + ((int64_t)(kk ? nk.i1 : nk.i0) * size + (aa ? a.i1 : a.i0)) * 2;
+            atomicAdd(G + idx, w * dx[8 + 2 * pl]);
+            atomicAdd(G + idx + 1, w * dx[9 + 2 * pl]);
+          }
+      }
+    }
+  }
+}
+
+__global__ void k_zero_d(double* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0.0;
+}
+
+// Export of a C-channel BC-simulated map ([H/4][W/4][C][2] endpoints, [H][W][C] weights) to
+// BC4 blocks [H/4][W/4][C][8], the encoding of the other layout's export.
+__global__ __launch_bounds__(256) void k_export_bc4c(const float* __restrict__ ep, const float* __restrict__ wts, int W,
+                                                      int H, int C, int64_t nb, uint8_t* __restrict__ out) {
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(b % C);
+    const int64_t blk = b / C;
+    const int64_t per = (int64_t)(H >> 2) * (W >> 2);
+    const int64_t sl = blk / per, rem = blk - sl * per;
+    const int bx = (int)(rem % (W >> 2)), by = (int)(rem / (W >> 2));
+    const float2 e = *(const float2*)(ep + b * 2);
+    const int E1 = (int)rintf(__fmul_rn(255.0f, e.x)), E2 = (int)rintf(__fmul_rn(255.0f, e.y));
+    uint64_t sel = 0;
+    for (int s = 0; s < 16; ++s) {
+      const int x = 4 * bx + (s & 3), y = 4 * by + (s >> 2);
+      const int J = (int)rintf(__fmul_rn(7.0f, wts[((sl * H + y) * W + x) * C + c]));
+      int code = 0;
+      if (E1 != E2) {
+        const int jj = E1 > E2 ? J : 7 - J;
+        code = jj == 0 ? 0 : (jj == 7 ? 1 : jj + 1);
+      }
+      sel |= (uint64_t)code << (3 * s);
+    }
+    const uint32_t e0 = (uint32_t)(E1 >= E2 ? E1 : E2), e1 = (uint32_t)(E1 >= E2 ? E2 : E1);
+    *(uint2*)(out + b * 8) = make_uint2(e0 | (e1 << 8) | (uint32_t)((sel & 0xffffu) << 16), (uint32_t)(sel >> 16));
+  }
+}
+
+// 8-bit planes: q = rint(fl32(255 v)) of values already projected to [0, 1].
+__global__ __launch_bounds__(256) void k_quant8(const float* __restrict__ src, uint8_t* __restrict__ dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (uint8_t)min(max((int)rintf(__fmul_rn(255.0f, src[i])), 0), 255);
+}
+
+// Target preprocessing (Sec. 4): y^(1/gamma) per texel and channel; per frame and channel the
+// FP64 sum, then division by the mean.  One workgroup per (frame, 64K-texel chunk).
+constexpr int kNormChunk = 65536;
+__global__ __launch_bounds__(256) void k_norm_sum(const uint16_t* __restrict__ tgt, int64_t texels, float inv_gamma,
+                                                   double* __restrict__ sums) {
+  const int f = blockIdx.y;
+  const int64_t lo = (int64_t)blockIdx.x * kNormChunk, hi = min(texels, lo + kNormChunk);
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      acc[c] += (double)powf(half_bits_f(tgt[((int64_t)f * texels + i) * 3 + c]), inv_gamma);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double v = wave_sum_d(acc[c]);
+    if ((threadIdx.x & 63) == 0) atomicAdd(sums + f * 3 + c, v);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_norm_apply(const uint16_t* __restrict__ tgt, int64_t texels, int frames,
+                                                     float inv_gamma, double* __restrict__ sums,
+                                                     float* __restrict__ out) {
+  const int64_t total = (int64_t)frames * texels * 3;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t f = i / (texels * 3);
+    const int c = (int)(i % 3);
+    const double mean = sums[f * 3 + c] / (double)texels;
+    out[i] = (float)((double)powf(half_bits_f(tgt[i]), inv_gamma) / mean);
+  }
+}
+
+__global__ void k_norm_means(double* sums, int n, int64_t texels) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) sums[i] /= (double)texels;
+}
+
+// Inverse for one decoded frame: max(pred * mean, 0)^gamma.
+__global__ __launch_bounds__(256) void k_restore(const void* __restrict__ pred, int pdt, int64_t texels,
+                                                  const double* __restrict__ mean3, float gamma, float* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < texels * 3; i += (int64_t)gridDim.x * blockDim.x) {
+    const float p = pdt == NDGI_DTYPE_F16 ? (float)((const _Float16*)pred)[i] : ((const float*)pred)[i];
+    const float v = p * (float)mean3[i % 3];
+    out[i] = v > 0.0f ? powf(v, gamma) : 0.0f;
+  }
+}
+
+static int grid_of(int64_t n, int cap) {
+  const int64_t w = (n + 255) / 256;
+  return (int)(w < cap ? (w < 1 ? 1 : w) : cap);
+}
+
+static int check_htrain(const ndgi_hybrid_train_state* st, const char* who) {
+  if (!st) return fail(NDGI_ERR_INVALID_ARG, "%s: state is NULL", who);
+  ndgi_hybrid_model m = {};
+  m.W = st->W;
+  m.H = st->H;
+  m.Gu = st->Gu;
+  m.Gv = st->Gv;
+  m.S = st->S;
+  m.U = st->U;
+  m.V = st->V;
+  m.Tt = st->Tt;
+  m.hidden = st->hidden;
+  m.mlp_dtype = NDGI_DTYPE_F32;
+  m.fuv = m.fuvt = m.fut = m.fvt = (const uint8_t*)st->params;
+  m.mlp = st->params;
+  if (!st->params || !st->grads) return fail(NDGI_ERR_INVALID_ARG, "%s: NULL params/grads", who);
+  int rc = check_hybrid(&m, who);
+  if (rc) return rc;
+  if (st->W > 4096 || st->H > 4096) return fail(NDGI_ERR_INVALID_ARG, "%s: W, H above 4096", who);
+  if (st->frames < 1 || st->frames > 256) return fail(NDGI_ERR_INVALID_ARG, "%s: frames=%d not in 1..256", who, st->frames);
+  return NDGI_OK;
+}
+
+}  // namespace ndgi
+
+using namespace ndgi;
+
+extern "C" {
+
+int64_t ndgi_hybrid_train_param_count(int32_t W, int32_t H, int32_t Gu, int32_t Gv, int32_t S, int32_t U, int32_t V,
+                                      int32_t Tt, int32_t hidden) {
+  if (ndgi_hybrid_mlp_size(hidden) < 0 || W < 4 || H < 4 || Gu < 4 || Gv < 4 || S < 1 || U < 1 || V < 1 || Tt < 1)
+    return -1;
+  ndgi_hybrid_train_state st = {};
+  st.W = W;
+  st.H = H;
+  st.Gu = Gu;
+  st.Gv = Gv;
+  st.S = S;
+  st.U = U;
+  st.V = V;
+  st.Tt = Tt;
+  st.hidden = hidden;
+  st.frames = 1;
+  return htd_of(&st).n;
+}
+
+int ndgi_hybrid_train_step(ndgi_ctx* c, ndgi_hybrid_train_state* st, const ndgi_hybrid_batch* b, int32_t mode,
+                           int32_t flags, double* loss_dev, hipStream_t s) {
+  clear_error();
+  if (!c) return fail(NDGI_ERR_INVALID_ARG, "hybrid_train_step: ctx is NULL");
+  int rc = check_htrain(st, "hybrid_train_step");
+  if (rc) return rc;
+  if (mode != NDGI_TRAIN_FORWARD && mode != NDGI_TRAIN_LOSS_GRAD && mode != NDGI_TRAIN_FUSED &&
+      mode != NDGI_TRAIN_ADAM && mode != NDGI_TRAIN_ZERO_GRAD)
+    return fail(NDGI_ERR_INVALID_ARG, "hybrid_train_step: unsupported mode %d", mode);
+  if (flags & ~(NDGI_HTRAIN_BCSIM | NDGI_HTRAIN_NOISE | NDGI_HTRAIN_QPLANES))
+    return fail(NDGI_ERR_INVALID_ARG, "hybrid_train_step: unknown flags 0x%x", flags);
+  const HybTrainDims d = htd_of(st);
+  if (mode == NDGI_TRAIN_ZERO_GRAD) return launch_fill_zero(c, st->grads, d.n, s);
+  const bool needs_batch = mode != NDGI_TRAIN_ADAM;
+  if (needs_batch) {
+    if (!b || !b->samples || b->n < 1 || b->n > INT32_MAX)
+      return fail(NDGI_ERR_INVALID_ARG, "hybrid_train_step: batch of 1..2^31-1 samples needed");
+    if (mode == NDGI_TRAIN_FORWARD && !b->pred) return fail(NDGI_ERR_INVALID_ARG, "hybrid_train_step: FORWARD needs pred");
+    if (mode != NDGI_TRAIN_FORWARD && (!b->target || !loss_dev))
+      return fail(NDGI_ERR_INVALID_ARG, "hybrid_train_step: LOSS_GRAD/FUSED need target and loss_dev");
+  }
+  if ((mode == NDGI_TRAIN_ADAM || mode == NDGI_TRAIN_FUSED) && (!st->adam_m || !st->adam_v))
+    return fail(NDGI_ERR_INVALID_ARG, "hybrid_train_step: Adam needs adam_m, adam_v");
+  if (needs_batch) {
+    const uint64_t base = (uint64_t)st->seed * 0x9E3779B97F4A7C15ull + ((uint64_t)st->step << 32);
+    const float inv3n = (float)(1.0 / (3.0 * (double)b->n));
+    int64_t wgs = (b->n + 255) / 256;
+    const int64_t cap = (int64_t)c->n_cu * 4;
+    if (wgs > cap) wgs = cap;
+    if (mode != NDGI_TRAIN_FORWARD) hipLaunchKernelGGL(k_zero_d, dim3(1), dim3(64), 0, s, loss_dev, 1);
+#define NDGI_HT(HD, M)                                                                                       \
+  hipLaunchKernelGGL((k_hybrid_train<HD, M>), dim3((unsigned)wgs), dim3(256), 0, s, d, st->params, st->grads, \
+                     st->keys, b->samples, b->n, b->target, b->pred, flags, base, inv3n, loss_dev)
+    if (mode == NDGI_TRAIN_FORWARD) {
+      if (d.hidden == 16) NDGI_HT(16, NDGI_TRAIN_FORWARD);
+      else NDGI_HT(64, NDGI_TRAIN_FORWARD);
+    } else {
+      if (d.hidden == 16) NDGI_HT(16, NDGI_TRAIN_LOSS_GRAD);
+      else NDGI_HT(64, NDGI_TRAIN_LOSS_GRAD);
+    }
+#undef NDGI_HT
+    NDGI_HIP(hipGetLastError());
+  }
+  if (mode == NDGI_TRAIN_ADAM || mode == NDGI_TRAIN_FUSED) {
+    // every feature map is projected to [0, 1]; the decoder is not
+    rc = launch_adam(c, st->params, st->grads, st->adam_m, st->adam_v, d.n, d.o_mlp, d.o_mlp, st->lr_feat,
+                     st->lr_mlp, st->beta1, st->beta2, st->eps, st->step + 1, s);
+    if (rc) return rc;
+    st->step += 1;
+  }
+  return NDGI_OK;
+}
+
+int ndgi_hybrid_export(ndgi_ctx* c, const ndgi_hybrid_train_state* st, uint8_t* fuv_out, uint8_t* fuvt_out,
+                       uint8_t* fut_out, uint8_t* fvt_out, void* mlp_out, int32_t mlp_dtype, hipStream_t s) {
+  clear_error();
+  if (!c) return fail(NDGI_ERR_INVALID_ARG, "hybrid_export: ctx is NULL");
+  int rc = check_htrain(st, "hybrid_export");
+  if (rc) return rc;
+  if (!fuv_out || !fuvt_out || !fut_out || !fvt_out || !mlp_out)
+    return fail(NDGI_ERR_INVALID_ARG, "hybrid_export: NULL output");
+  if (mlp_dtype != NDGI_DTYPE_F32 && mlp_dtype != NDGI_DTYPE_F16)
+    return fail(NDGI_ERR_INVALID_ARG, "hybrid_export: bad dtype");
+  const HybTrainDims d = htd_of(st);
+  const int64_t nb_uv = (int64_t)(d.H / 4) * (d.W / 4) * 4, nb_uvt = (int64_t)d.S * (d.Gv / 4) * (d.Gu / 4) * 4;
+  hipLaunchKernelGGL(k_export_bc4c, dim3(grid_of(nb_uv, c->n_cu * 16)), dim3(256), 0, s, st->params,
+                     st->params + d.o_uvw, d.W, d.H, 4, nb_uv, fuv_out);
+  hipLaunchKernelGGL(k_export_bc4c, dim3(grid_of(nb_uvt, c->n_cu * 16)), dim3(256), 0, s, st->params + d.o_tep,
+                     st->params + d.o_tw, d.Gu, d.Gv, 4, nb_uvt, fuvt_out);
+  hipLaunchKernelGGL(k_quant8, dim3(grid_of((int64_t)d.Tt * d.U * 2, 1024)), dim3(256), 0, s, st->params + d.o_ut,
+                     fut_out, (int64_t)d.Tt * d.U * 2);
+  hipLaunchKernelGGL(k_quant8, dim3(grid_of((int64_t)d.Tt * d.V * 2, 1024)), dim3(256), 0, s, st->params + d.o_vt,
+                     fvt_out, (int64_t)d.Tt * d.V * 2);
+  NDGI_HIP(hipGetLastError());
+  return launch_convert(c, st->params + d.o_mlp, mlp_out, mlp_dtype, d.n - d.o_mlp, s);
+}
+
+int ndgi_hybrid_normalize_target(ndgi_ctx* c, const uint16_t* target, int32_t frames, int32_t W, int32_t H,
+                                 float gamma, float* out, double* means, hipStream_t s) {
+  clear_error();
+  if (!c || !target || !out || !means) return fail(NDGI_ERR_INVALID_ARG, "hybrid_normalize_target: NULL argument");
+  if (frames < 1 || frames > 65535 || W < 1 || H < 1 || !(gamma > 0.0f))
+    return fail(NDGI_ERR_INVALID_ARG, "hybrid_normalize_target: bad sizes or gamma");
+  const int64_t texels = (int64_t)W * H;
+  for (int i = 0; i < frames * 3; i += 64)
+    hipLaunchKernelGGL(k_zero_d, dim3(1), dim3(64), 0, s, means + i, min(64, frames * 3 - i));
+  hipLaunchKernelGGL(k_norm_sum, dim3((unsigned)((texels + kNormChunk - 1) / kNormChunk), frames), dim3(256), 0, s,
+                     target, texels, 1.0f / gamma, means);
+  hipLaunchKernelGGL(k_norm_apply, dim3(grid_of(texels * 3 * frames, c->n_cu * 16)), dim3(256), 0, s, target, texels,
+                     frames, 1.0f / gamma, means, out);
+  hipLaunchKernelGGL(k_norm_means, dim3(1), dim3(256), 0, s, means, frames * 3, texels);
+  NDGI_HIP(hipGetLastError());
+  return NDGI_OK;
+}
+
+int ndgi_hybrid_restore(ndgi_ctx* c, const void* pred, int32_t pred_dtype, int64_t texels, const double* mean3,
+                        float gamma, float* out, hipStream_t s) {
+  clear_error();
+  if (!c || !pred || !mean3 || !out) return fail(NDGI_ERR_INVALID_ARG, "hybrid_restore: NULL argument");
+  if (texels < 0 || !(gamma > 0.0f) || (pred_dtype != NDGI_DTYPE_F32 && pred_dtype != NDGI_DTYPE_F16))
+    return fail(NDGI_ERR_INVALID_ARG, "hybrid_restore: bad arguments");
+  if (texels == 0) return NDGI_OK;
+  hipLaunchKernelGGL(k_restore, dim3(grid_of(texels * 3, c->n_cu * 16)), dim3(256), 0, s, pred, pred_dtype, texels,
+                     mean3, gamma, out);
+  NDGI_HIP(hipGetLastError());
+  return NDGI_OK;
+}
+
+}  // extern "C"

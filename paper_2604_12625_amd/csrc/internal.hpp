@@ -63,6 +63,10 @@ int binned_workspace(const ndgi_model& m, int64_t n, int64_t* bytes);
 int launch_decode_binned(ndgi_ctx* ctx, const ndgi_model& m, const float* uvt, int64_t n, void* out, int prec,
                          void* ws, int64_t ws_bytes, hipStream_t s);
 int check_hybrid(const ndgi_hybrid_model* m, const char* who);
+int launch_adam(ndgi_ctx* c, float* p, float* g, float* m, float* v, int64_t n, int64_t clamp_end, int64_t off_mlp,
+                float lr_feat, float lr_mlp, float beta1, float beta2, float eps, int64_t step, hipStream_t s);
+int launch_fill_zero(ndgi_ctx* c, float* p, int64_t n, hipStream_t s);
+int launch_convert(ndgi_ctx* c, const float* src, void* dst, int dt, int64_t n, hipStream_t s);
 int launch_hybrid_query(ndgi_ctx* ctx, const ndgi_hybrid_model& m, const float* uvt, int64_t n, void* out, int prec,
                         hipStream_t s);
 int launch_hybrid_pages(ndgi_ctx* ctx, const ndgi_hybrid_model* models, int32_t n_models, const ndgi_page_req* reqs,

@@ -562,6 +562,33 @@ static int grid_for(int64_t n, int cap) {
   return (int)(w < cap ? (w < 1 ? 1 : w) : cap);
 }
 
+// Host launchers of the dense kernels, shared with the hybrid-layout trainer.
+namespace ndgi {
+int launch_adam(ndgi_ctx* c, float* p, float* g, float* m, float* v, int64_t n, int64_t clamp_end, int64_t off_mlp,
+                float lr_feat, float lr_mlp, float beta1, float beta2, float eps, int64_t step, hipStream_t s) {
+  const double bc1 = 1.0 - pow((double)beta1, (double)step);
+  const double bc2 = 1.0 - pow((double)beta2, (double)step);
+  const float sf = (float)((double)lr_feat / bc1), sm = (float)((double)lr_mlp / bc1);
+  const float isb = (float)(1.0 / sqrt(bc2));
+  hipLaunchKernelGGL(k_adam, dim3(grid_for((n + 3) / 4, c->n_cu * 16)), dim3(256), 0, s, p, g, m, v, n, clamp_end,
+                     off_mlp, 1.0f, 1.0f, beta1, beta2, eps, sf, sm, isb);
+  NDGI_HIP(hipGetLastError());
+  return NDGI_OK;
+}
+
+int launch_fill_zero(ndgi_ctx* c, float* p, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(n, c->n_cu * 16)), dim3(256), 0, s, p, n);
+  NDGI_HIP(hipGetLastError());
+  return NDGI_OK;
+}
+
+int launch_convert(ndgi_ctx* c, const float* src, void* dst, int dt, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_convert, dim3(grid_for(n, c->n_cu * 16)), dim3(256), 0, s, src, dst, dt, n);
+  NDGI_HIP(hipGetLastError());
+  return NDGI_OK;
+}
+}  // namespace ndgi
+
 extern "C" {
 
 int64_t ndgi_train_param_count(int32_t W, int32_t H, int32_t Gw, int32_t Gh, int32_t T) {

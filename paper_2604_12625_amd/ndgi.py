@@ -26,8 +26,10 @@ EXPORTED = (
     "ndgi_set_launch", "ndgi_train_param_count", "ndgi_train_step", "ndgi_export",
     "ndgi_tile_stats", "ndgi_decode_binned_workspace", "ndgi_decode_binned",
     "ndgi_hybrid_mlp_size", "ndgi_hybrid_decode", "ndgi_hybrid_decode_pages",
-    "ndgi_hybrid_decode_pages_graph",
+    "ndgi_hybrid_decode_pages_graph", "ndgi_hybrid_train_param_count", "ndgi_hybrid_train_step",
+    "ndgi_hybrid_export", "ndgi_hybrid_normalize_target", "ndgi_hybrid_restore",
 )
+HTRAIN_BCSIM, HTRAIN_NOISE, HTRAIN_QPLANES = 1, 2, 4
 
 
 class NdgiModel(C.Structure):
@@ -64,7 +66,22 @@ class NdgiHybridModel(C.Structure):
                 ("fut", C.c_void_p), ("fvt", C.c_void_p), ("keys", C.c_void_p), ("mlp", C.c_void_p)]
 
 
+class NdgiHybridTrainState(C.Structure):
+    _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("Gu", C.c_int32), ("Gv", C.c_int32),
+                ("S", C.c_int32), ("U", C.c_int32), ("V", C.c_int32), ("Tt", C.c_int32),
+                ("hidden", C.c_int32), ("frames", C.c_int32), ("keys", C.c_void_p),
+                ("params", C.c_void_p), ("grads", C.c_void_p), ("adam_m", C.c_void_p),
+                ("adam_v", C.c_void_p), ("step", C.c_int64), ("lr_feat", C.c_float),
+                ("lr_mlp", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float), ("seed", C.c_uint32)]
+
+
+class NdgiHybridBatch(C.Structure):
+    _fields_ = [("samples", C.c_void_p), ("n", C.c_int64), ("target", C.c_void_p), ("pred", C.c_void_p)]
+
+
 assert C.sizeof(NdgiModel) == 64 and C.sizeof(NdgiPageReq) == 24 and C.sizeof(NdgiHybridModel) == 96
+assert C.sizeof(NdgiHybridTrainState) == 112 and C.sizeof(NdgiHybridBatch) == 32
 
 
 class NdgiError(RuntimeError):
@@ -106,6 +123,13 @@ def lib():
         hpages = [vp, vp, i32, vp, vp, i32, i32, vp, i64, i32, i32, vp]
         L.ndgi_hybrid_decode_pages.argtypes = hpages
         L.ndgi_hybrid_decode_pages_graph.argtypes = hpages
+        L.ndgi_hybrid_train_param_count.argtypes = [i32] * 9
+        L.ndgi_hybrid_train_param_count.restype = i64
+        L.ndgi_hybrid_train_step.argtypes = [vp, C.POINTER(NdgiHybridTrainState), C.POINTER(NdgiHybridBatch), i32,
+                                             i32, vp, vp]
+        L.ndgi_hybrid_export.argtypes = [vp, C.POINTER(NdgiHybridTrainState), vp, vp, vp, vp, vp, i32, vp]
+        L.ndgi_hybrid_normalize_target.argtypes = [vp, vp, i32, i32, i32, C.c_float, vp, vp, vp]
+        L.ndgi_hybrid_restore.argtypes = [vp, vp, i32, i64, vp, C.c_float, vp, vp]
         _lib = L
     return _lib
 

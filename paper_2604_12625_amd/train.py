@@ -155,3 +155,115 @@ def smoke_train_step(ctx: N.Context):
     err = np.max(np.abs(gm - ref["mlp"])) / np.max(np.abs(ref["mlp"]))
     assert err <= 1e-4, err
     print(f"smoke train: loss {loss:.6e} (oracle {ref_loss:.6e}), decoder grad err {err:.2e}")
+
+
+HYB_KEYS = ("fuv_ep", "fuv_w", "fuvt_ep", "fuvt_w", "fut", "fvt", "mlp")
+
+
+class HybridTrainer:
+    """Trainable hybrid-layout state in device memory (ndgi_hybrid_train_step): flat float32
+    params / grads / Adam m, v with the layout [F_uv endpoints | F_uv weights | F_uvt
+    endpoints | F_uvt weights | F_ut | F_vt | decoder]."""
+
+    def __init__(self, ctx: N.Context, init: dict, lr_feat=1e-3, lr_mlp=1e-3, betas=(0.9, 0.999), eps=1e-8,
+                 seed=0, device="cuda"):
+        import torch
+        d = init["dims"]
+        self.ctx, self.d = ctx, dict(d)
+        dims = [d[k] for k in ("W", "H", "Gu", "Gv", "S", "U", "V", "Tt", "hidden")]
+        n = int(N.lib().ndgi_hybrid_train_param_count(*dims))
+        self.n_params = n
+        flat = np.concatenate([np.asarray(init[k], dtype=np.float32).ravel() for k in HYB_KEYS])
+        assert flat.size == n, (flat.size, n)
+        self.params = torch.from_numpy(flat).to(device)
+        self.grads = torch.zeros(n, dtype=torch.float32, device=device)
+        self.m = torch.zeros(n, dtype=torch.float32, device=device)
+        self.v = torch.zeros(n, dtype=torch.float32, device=device)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=device)
+        keys = np.asarray(d.get("keys", []), dtype=np.float32)
+        self.keys = torch.from_numpy(keys).to(device) if keys.size else None
+        self.state = N.NdgiHybridTrainState(*dims, int(d["frames"]), N._ptr(self.keys), self.params.data_ptr(),
+                                            self.grads.data_ptr(), self.m.data_ptr(), self.v.data_ptr(), 0,
+                                            float(lr_feat), float(lr_mlp), float(betas[0]), float(betas[1]),
+                                            float(eps), int(seed))
+
+    def split(self, flat) -> dict:
+        d = self.d
+        shapes = dict(fuv_ep=(d["H"] // 4, d["W"] // 4, 4, 2), fuv_w=(d["H"], d["W"], 4),
+                      fuvt_ep=(d["S"], d["Gv"] // 4, d["Gu"] // 4, 4, 2), fuvt_w=(d["S"], d["Gv"], d["Gu"], 4),
+                      fut=(d["Tt"], d["U"], 2), fvt=(d["Tt"], d["V"], 2), mlp=(-1,))
+        out, o = {}, 0
+        for k in HYB_KEYS:
+            cnt = int(np.prod(shapes[k])) if k != "mlp" else flat.numel() - o
+            out[k] = flat[o:o + cnt].view(*shapes[k])
+            o += cnt
+        return out
+
+    def _run(self, mode, flags, samples=None, target=None, pred=None, stream=None):
+        b = N.NdgiHybridBatch(N._ptr(samples), 0 if samples is None else samples.shape[0], N._ptr(target),
+                              N._ptr(pred))
+        N.check(N.lib().ndgi_hybrid_train_step(self.ctx.h, C.byref(self.state), C.byref(b), mode, flags,
+                                               self.loss.data_ptr(), N._stream(stream)), "ndgi_hybrid_train_step")
+
+    def set_lr(self, lr_feat=None, lr_mlp=None):
+        if lr_feat is not None:
+            self.state.lr_feat = float(lr_feat)
+        if lr_mlp is not None:
+            self.state.lr_mlp = float(lr_mlp)
+
+    def forward(self, samples, flags, pred=None):
+        import torch
+        if pred is None:
+            pred = torch.empty((samples.shape[0], 3), dtype=torch.float32, device=samples.device)
+        self._run(N.TRAIN_FORWARD, flags, samples, pred=pred)
+        return pred
+
+    def loss_grad(self, samples, target, flags):
+        self._run(N.TRAIN_LOSS_GRAD, flags, samples, target=target)
+        return self.loss
+
+    def step(self, samples, target, flags):
+        self._run(N.TRAIN_FUSED, flags, samples, target=target)
+        return self.loss
+
+    def zero_grad(self):
+        self._run(N.TRAIN_ZERO_GRAD, 0)
+
+    def export(self, mlp_dtype=N.DTYPE_F16) -> N.HybridModel:
+        import torch
+        d, dev = self.d, self.params.device
+        fuv = torch.empty((d["H"] // 4, d["W"] // 4, 4, 8), dtype=torch.uint8, device=dev)
+        fuvt = torch.empty((d["S"], d["Gv"] // 4, d["Gu"] // 4, 4, 8), dtype=torch.uint8, device=dev)
+        fut = torch.empty((d["Tt"], d["U"], 2), dtype=torch.uint8, device=dev)
+        fvt = torch.empty((d["Tt"], d["V"], 2), dtype=torch.uint8, device=dev)
+        mlp = torch.empty(N.hybrid_mlp_size(d["hidden"]), dtype=torch.float16 if mlp_dtype == N.DTYPE_F16
+                          else torch.float32, device=dev)
+        N.check(N.lib().ndgi_hybrid_export(self.ctx.h, C.byref(self.state), fuv.data_ptr(), fuvt.data_ptr(),
+                                           fut.data_ptr(), fvt.data_ptr(), mlp.data_ptr(), mlp_dtype,
+                                           N._stream(None)), "ndgi_hybrid_export")
+        keys = self.keys if self.keys is not None else torch.zeros(0, dtype=torch.float32, device=dev)
+        return N.HybridModel(d["W"], d["H"], d["Gu"], d["Gv"], d["S"], d["U"], d["V"], d["Tt"], d["hidden"],
+                             fuv, fuvt, fut, fvt, keys, mlp)
+
+
+def hybrid_normalize_target(ctx: N.Context, target_bits, gamma=2.2):
+    """(normalised float target [n][H][W][3], means [n][3] float64) of an FP16 target."""
+    import torch
+    n, H, W = target_bits.shape[0], target_bits.shape[1], target_bits.shape[2]
+    out = torch.empty((n, H, W, 3), dtype=torch.float32, device=target_bits.device)
+    means = torch.empty((n, 3), dtype=torch.float64, device=target_bits.device)
+    N.check(N.lib().ndgi_hybrid_normalize_target(ctx.h, target_bits.data_ptr(), n, W, H, float(gamma),
+                                                 out.data_ptr(), means.data_ptr(), N._stream(None)),
+            "ndgi_hybrid_normalize_target")
+    return out, means
+
+
+def hybrid_restore(ctx: N.Context, pred, mean3, gamma=2.2, out=None):
+    import torch
+    texels = pred.shape[0]
+    if out is None:
+        out = torch.empty((texels, 3), dtype=torch.float32, device=pred.device)
+    pdt = N.DTYPE_F16 if pred.dtype == torch.float16 else N.DTYPE_F32
+    N.check(N.lib().ndgi_hybrid_restore(ctx.h, pred.data_ptr(), pdt, texels, mean3.data_ptr(), float(gamma),
+                                        out.data_ptr(), N._stream(None)), "ndgi_hybrid_restore")
+    return out

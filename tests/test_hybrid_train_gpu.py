@@ -1,0 +1,151 @@
+"""GPU parity of the hybrid-layout training path (ndgi_hybrid_train_step, ndgi_hybrid_export,
+the target preprocessing) against the CPU oracle, through the C ABI.
+
+Bounds: forward outputs and the loss within 1e-5 relative (FP32 on the GPU against FP64);
+gradients within 1e-4 relative plus 1e-6 of the array's largest entry (FP32 atomics and
+wave reductions reorder the sums); export bytes bit-exact."""
+import numpy as np
+import pytest
+
+from oracle import ndgi_oracle as O
+from paper_2604_12625_amd import inputs as I
+from tests.gpu_util import torch_cuda
+from tests.test_oracle_hybrid import tiny_hybrid_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def N():
+    torch_cuda()
+    from paper_2604_12625_amd import ndgi
+    return ndgi
+
+
+@pytest.fixture(scope="module")
+def ctx(N):
+    c = N.Context(0)
+    yield c
+    c.close()
+
+
+def _state(hidden, seed, frames=3, keys=True, on_grid=False, bigger=False):
+    st = tiny_hybrid_state(hidden, seed=seed, frames=frames, keys=keys, on_grid=on_grid)
+    if bigger:   # a 64 x 48 map, F_uvt 16 x 12 x 5, planes 32 x 4 and 48 x 4
+        g = np.random.default_rng(seed + 100)
+        d = dict(st["dims"], W=64, H=48, Gu=16, Gv=12, S=5, U=32, V=48, Tt=4)
+        st = dict(dims=d)
+        st["fuv_ep"] = g.uniform(0, 1, (12, 16, 4, 2))
+        st["fuv_w"] = g.uniform(0, 1, (48, 64, 4))
+        st["fuvt_ep"] = g.uniform(0, 1, (5, 3, 4, 4, 2))
+        st["fuvt_w"] = g.uniform(0, 1, (5, 12, 16, 4))
+        st["fut"] = g.uniform(0, 1, (4, 32, 2))
+        st["fvt"] = g.uniform(0, 1, (4, 48, 2))
+        st["mlp"] = I.hybrid_mlp(hidden, np.float64, g)
+    # the GPU holds float32 masters: the oracle reads the same values
+    for k in O.HYB_KEYS:
+        st[k] = np.asarray(st[k], dtype=np.float32).astype(np.float64)
+    return st
+
+
+def _samples(st, n, seed):
+    g = np.random.default_rng(seed)
+    d = st["dims"]
+    x, y, f = g.integers(0, d["W"], n), g.integers(0, d["H"], n), g.integers(0, d["frames"], n)
+    tgt = g.normal(0.5, 0.5, (d["frames"], d["H"], d["W"], 3)).astype(np.float32)
+    return x, y, f, tgt
+
+
+def _dev(N, x, y, f, tgt):
+    import torch
+    smp = torch.from_numpy(I.pack_samples(x, y, f).view(np.int32)).cuda()
+    return smp, torch.from_numpy(tgt).cuda()
+
+
+def _close(got, ref, rel, what, floor=1e-6):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    tol = rel * np.abs(ref) + floor * max(float(np.max(np.abs(ref))), 1e-30)
+    bad = np.abs(got - ref) > tol
+    assert not bad.any(), f"{what}: {int(bad.sum())} of {bad.size} off, worst {np.max(np.abs(got - ref) - tol):.3e}"
+
+
+@pytest.mark.parametrize("hidden", [16, 64])
+@pytest.mark.parametrize("flags", [0, 1 | 2, 1 | 4])
+@pytest.mark.parametrize("bigger", [False, True])
+def test_hybrid_loss_grad_and_forward_match_oracle(N, ctx, hidden, flags, bigger):
+    from paper_2604_12625_amd.train import HybridTrainer
+    st = _state(hidden, seed=hidden + flags, bigger=bigger)
+    x, y, f, tgt = _samples(st, 700, seed=7 + flags)
+    smp, tg = _dev(N, x, y, f, tgt)
+    tr = HybridTrainer(ctx, st, seed=11)
+    pred = tr.forward(smp, flags).cpu().numpy()
+    ref_pred = O.hybrid_train_forward(st, x, y, f, flags, seed=11, step=0)
+    _close(pred, ref_pred, 1e-5, "forward", floor=1e-6)
+    tr.zero_grad()
+    loss = float(tr.loss_grad(smp, tg, flags).item())
+    ref_loss, ref_g = O.hybrid_train_grads(st, x, y, f, tgt[f, y, x], flags, seed=11, step=0)
+    assert abs(loss - ref_loss) <= 1e-5 * abs(ref_loss), (loss, ref_loss)
+    got = tr.split(tr.grads)
+    for k in O.HYB_KEYS:
+        _close(got[k].cpu().numpy(), ref_g[k], 1e-4, k)
+
+
+def test_hybrid_adam_steps_match_oracle(N, ctx):
+    from paper_2604_12625_amd.train import HybridTrainer
+    st = _state(16, seed=3)
+    ref = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in st.items()}
+    opt = dict(step=0, lr_feat=1e-2, lr_mlp=1e-3, m={k: 0.0 for k in O.HYB_KEYS}, v={k: 0.0 for k in O.HYB_KEYS})
+    tr = HybridTrainer(ctx, st, lr_feat=1e-2, lr_mlp=1e-3, seed=5)
+    flags = 1 | 2
+    for it in range(3):
+        x, y, f, tgt = _samples(st, 500, seed=20 + it)
+        smp, tg = _dev(N, x, y, f, tgt)
+        loss = float(tr.step(smp, tg, flags).item())
+        ref_loss = O.hybrid_train_step(ref, opt, x, y, f, tgt[f, y, x], flags, seed=5)
+        assert abs(loss - ref_loss) <= 1e-4 * abs(ref_loss), (it, loss, ref_loss)
+    assert tr.state.step == 3
+    got = tr.split(tr.params)
+    for k in O.HYB_KEYS:
+        g = got[k].cpu().numpy().astype(np.float64)
+        # after Adam an FP32 and an FP64 master can round to different 8-bit endpoints at a
+        # quantisation boundary: an lr-scaled absolute floor, as for the other layout
+        diff = np.abs(g - ref[k])
+        tol = 1e-4 * np.abs(ref[k]) + 3e-3 * (1e-2 if k != "mlp" else 1e-3)
+        assert np.mean(diff > tol) <= 1e-3, (k, float(diff.max()))
+
+
+def test_hybrid_export_is_exact_and_decodes_to_the_simulated_forward(N, ctx):
+    import torch
+    from paper_2604_12625_amd.train import HybridTrainer
+    st = _state(64, seed=8, bigger=True)
+    tr = HybridTrainer(ctx, st)
+    hm = tr.export(N.DTYPE_F32)
+    ref = O.hybrid_export(st)
+    for k in ("fuv", "fuvt", "fut", "fvt"):
+        np.testing.assert_array_equal(getattr(hm, "arrays")[("fuv", "fuvt", "fut", "fvt").index(k)].cpu().numpy(),
+                                      ref[k], err_msg=k)
+    d = st["dims"]
+    g = np.random.default_rng(9)
+    n = 3000
+    x, y, f = g.integers(0, d["W"], n), g.integers(0, d["H"], n), g.integers(0, d["frames"], n)
+    fwd = O.hybrid_train_forward(st, x, y, f, 1 | 4)
+    t = np.asarray(d["keys"], dtype=np.float32)[f]
+    q = np.stack([(x + 0.5) / d["W"], (y + 0.5) / d["H"], t], 1).astype(np.float32)
+    out = ctx.hybrid_decode(hm, torch.from_numpy(q).cuda(), N.PREC_F32).cpu().numpy()
+    rms = np.sqrt(np.mean(fwd ** 2))
+    assert np.max(np.abs(out - fwd) / np.maximum(np.abs(fwd), rms)) <= 1e-5
+
+
+def test_target_normalisation_and_restore(N, ctx):
+    import torch
+    from paper_2604_12625_amd.train import hybrid_normalize_target, hybrid_restore
+    g = np.random.default_rng(12)
+    tgt = g.uniform(0.01, 5.0, (4, 40, 24, 3)).astype(np.float16)
+    out, means = hybrid_normalize_target(ctx, torch.from_numpy(tgt.view(np.int16)).cuda(), 2.2)
+    ref, ref_means = O.hybrid_normalise_target(tgt.astype(np.float64), 2.2)
+    _close(out.cpu().numpy(), ref, 1e-5, "normalised target")
+    _close(means.cpu().numpy(), ref_means, 1e-6, "means")
+    back = hybrid_restore(ctx, out[2].reshape(-1, 3), means[2], 2.2).cpu().numpy()
+    _close(back, O.hybrid_restore(ref[2].reshape(-1, 3), ref_means[2], 2.2), 1e-5, "restore")
+    _close(back, tgt[2].reshape(-1, 3).astype(np.float64), 1e-5, "round trip")
