@@ -1,0 +1,133 @@
+"""Fit of the paper's hybrid layout to a temporal lightmap with its training recipe (Sec. 3.4,
+Sec. 4), all on the GPU kernels, then export, decode and score.
+
+Target: a 128 x 128 tile (the paper trains one model per VT tile) cut from the synthetic
+1024^2 temporal lightmap, baked at 26 key times (24 hourly plus two around a light switch,
+like the paper's sets), FP16.  Preprocessing: gamma 2.2 and per-frame, per-channel mean
+normalisation.  Training: Adam at the paper's learning rate 1e-3 and batch 2^12 texel
+samples; phase 1 with BC simulation of F_uv / F_uvt and noise on the sampled features;
+phase 2 fine-tunes the decoder on frozen features as a decode sees them.  Export (BC4
+blocks, 8-bit planes, FP16 decoder), decode of all 26 frames through the page decoder at
+their key times (FP16 and FP32 paths), inverse preprocessing, tiled PSNR (one 128^2 tile
+per frame).  The same run without the BC simulation in phase 1 is the simulation's
+ablation (Table 7 of the paper, on synthetic data).
+"""
+from __future__ import annotations
+
+import sys
+import time
+
+import numpy as np
+
+TILE = 128
+GAMMA = 2.2
+BATCH = 1 << 12
+LR = 1e-3
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def tile_target(torch, I, keys, x0=384, y0=512, scene_side=1024, seed=6):
+    """[frames][TILE][TILE][3] FP16 target: a tile of the synthetic scene at the key times."""
+    scene = I.light_scene(scene_side, scene_side, I.rng(seed, I.P_TARGET))
+    frames = []
+    for t in keys:
+        f = I.scene_frame_torch(scene, float(t), device="cuda", rows=(y0, y0 + TILE))
+        frames.append(f[:, x0:x0 + TILE].to(torch.float16))
+    return torch.stack(frames).contiguous()
+
+
+def fit(torch, N, I, ctx, init, target_bits, steps1, steps2, bcsim: bool, seed=0):
+    from .train import HybridTrainer, hybrid_normalize_target
+    frames = target_bits.shape[0]
+    tgt, means = hybrid_normalize_target(ctx, target_bits.view(torch.int16), GAMMA)
+    tr = HybridTrainer(ctx, init, lr_feat=LR, lr_mlp=LR, seed=seed)
+    smp = torch.stack([I.train_samples_torch(BATCH, TILE, TILE, frames, seed=70_000 + i)
+                       for i in range(steps1 + steps2)])
+    f1 = (N.HTRAIN_BCSIM if bcsim else 0) | N.HTRAIN_NOISE
+    f2 = N.HTRAIN_BCSIM | N.HTRAIN_QPLANES
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(steps1):
+        tr.step(smp[i], tgt, f1)
+        if (i + 1) % 1000 == 0:
+            losses.append((i + 1, float(tr.loss.item())))
+    e1.record()
+    e1.synchronize()
+    ms1 = e0.elapsed_time(e1)
+    tr.set_lr(lr_feat=0.0)
+    for i in range(steps1, steps1 + steps2):
+        tr.step(smp[i], tgt, f2)
+    torch.cuda.synchronize()
+    losses.append((steps1 + steps2, float(tr.loss.item())))
+    wall = time.perf_counter() - t0
+    return tr, means, dict(train_ms_per_step=ms1 / steps1, wall_s=wall, loss_curve=losses, flags_phase1=f1,
+                           flags_phase2=f2, n_params=int(tr.n_params))
+
+
+def score(torch, N, ctx, tr, means, target_bits, keys):
+    """Tiled PSNR of the exported model's decode (FP16 and FP32 paths) against the target."""
+    from .train import hybrid_restore
+    frames = target_bits.shape[0]
+    hm = tr.export(N.DTYPE_F16)
+    marr = N.models_array([hm])
+    rq = N.page_requests(np.zeros(frames, np.int32), np.zeros(frames, np.int32), np.zeros(frames, np.int32),
+                         np.asarray(keys, np.float32), (np.arange(frames) * TILE * TILE).astype(np.int64))
+    nreq = torch.tensor([frames], dtype=torch.int32, device="cuda")
+    width = 2 if tr.d["hidden"] == 64 else 1
+    out = {}
+    for prec, name in ((N.PREC_F16, "f16"), (N.PREC_F32, "f32")):
+        dst = torch.empty((frames * TILE * TILE, 3), dtype=torch.float16 if prec == N.PREC_F16 else torch.float32,
+                          device="cuda")
+        ctx.hybrid_decode_pages(marr, 1, rq, nreq, frames, TILE, dst, TILE, prec, widths=width)
+        stats = []
+        for f in range(frames):
+            rec = hybrid_restore(ctx, dst[f * TILE * TILE:(f + 1) * TILE * TILE], means[f], GAMMA)
+            stats.append(ctx.tile_stats(rec, target_bits[f].view(torch.int16), TILE, TILE, TILE).cpu().numpy())
+        tiled, glob = N.psnr_from_stats(stats, TILE, TILE, TILE)
+        out[name] = dict(psnr_tiled_db=tiled, psnr_global_db=glob)
+    assert ctx.error_flags() == 0
+    return out
+
+
+def run_hfit(args, torch, N, I, ctx, profile="M", steps1=4000, steps2=1000):
+    keys = I.lightmap_key_times(I.rng(6, I.P_MODEL, 1))
+    target = tile_target(torch, I, keys)
+    init = I.hybrid_train_init(TILE, TILE, profile, len(keys), keys, I.rng(6, I.P_INIT))
+    side, hidden = I.HYBRID_PROFILES[profile]
+    runs = {}
+    for name, bc in (("recipe", True), ("without_bc_simulation", False)):
+        tr, means, info = fit(torch, N, I, ctx, init, target, steps1, steps2, bc)
+        info["decode"] = score(torch, N, ctx, tr, means, target, keys)
+        runs[name] = info
+        _log(f"hybrid fit {profile} {name}: {info['train_ms_per_step']:.3f} ms/step, loss {info['loss_curve'][-1][1]:.4e}, "
+             f"PSNR FP16 {info['decode']['f16']['psnr_tiled_db']:.2f} dB, FP32 {info['decode']['f32']['psnr_tiled_db']:.2f} dB")
+    return {
+        "metric": "hybrid-layout fit: tiled PSNR after export, train ms/step",
+        "config": {"workload": f"one {TILE}x{TILE} tile of the synthetic 1024^2 temporal lightmap at 26 key times; "
+                               f"profile {profile} (F_uvt {side}^2 x 12 x 4, hidden {hidden}); batch {BATCH}, Adam "
+                               f"lr {LR}; {steps1} steps with BC simulation and noise, {steps2} decoder fine-tune "
+                               "steps on frozen features; gamma 2.2 + per-frame mean normalisation"},
+        "data": "synthetic",
+        "train_params": int(runs["recipe"].get("n_params", 0)) or None,
+        "bits_per_texel_bc4": bits_per_texel_hybrid(TILE, TILE, len(keys), side, 12, (64, 64, 24), hidden, 16),
+        "bits_per_texel_bc7_accounting": bits_per_texel_hybrid(TILE, TILE, len(keys), side, 12, (64, 64, 24),
+                                                               hidden, 8),
+        "runs": runs,
+    }
+
+
+def bits_per_texel_hybrid(W, H, frames, side, slices, plane, hidden, uv_bits_per_texel):
+    """Stored bits per texel per frame of a hybrid model: F_uv and the F_uvt slices at
+    `uv_bits_per_texel` (16 for four BC4 channels, 8 for the paper's BC7), 8-bit planes,
+    FP16 decoder."""
+    U, V, Tt = plane
+    mlp = hidden * 16 + hidden + hidden * hidden + hidden + 3 * hidden + 3
+    bits = W * H * uv_bits_per_texel + side * side * slices * uv_bits_per_texel + (U + V) * Tt * 2 * 8 + mlp * 16
+    return bits / (W * H * frames)

@@ -130,6 +130,32 @@ def random_hybrid_model(W: int = 128, H: int = 128, profile: str = "M", slices: 
     )
 
 
+def hybrid_train_init(W: int, H: int, profile: str, frames: int, keys, g: np.random.Generator,
+                      slices: int = 12, plane=(64, 64, 24)) -> dict:
+    """Initial trainable hybrid state (float32): endpoints e1 ~ U[0, 0.5), e2 ~ U[0.5, 1],
+    weights and planes ~ U[0, 1], He-normal decoder with zero biases except b3 = 1 (the
+    normalised target has mean 1 in every channel)."""
+    side, hidden = HYBRID_PROFILES[profile]
+    U, V, Tt = plane
+
+    def ep(shape):
+        return np.stack([g.uniform(0.0, 0.5, shape), g.uniform(0.5, 1.0, shape)], axis=-1).astype(np.float32)
+
+    mlp = hybrid_mlp(hidden, np.float32, g)
+    o1 = hidden * HYBRID_IN                     # b1
+    o2 = o1 + hidden + hidden * hidden          # b2
+    mlp[o1:o1 + hidden] = 0.0
+    mlp[o2:o2 + hidden] = 0.0
+    mlp[-3:] = 1.0                              # b3
+    return dict(dims=dict(W=W, H=H, Gu=side, Gv=side, S=slices, U=U, V=V, Tt=Tt, hidden=hidden, frames=frames,
+                          keys=np.asarray(keys, dtype=np.float32)),
+                fuv_ep=ep((H // 4, W // 4, 4)), fuv_w=g.uniform(0, 1, (H, W, 4)).astype(np.float32),
+                fuvt_ep=ep((slices, side // 4, side // 4, 4)),
+                fuvt_w=g.uniform(0, 1, (slices, side, side, 4)).astype(np.float32),
+                fut=g.uniform(0, 1, (Tt, U, 2)).astype(np.float32), fvt=g.uniform(0, 1, (Tt, V, 2)).astype(np.float32),
+                mlp=mlp)
+
+
 # ----------------------------------------------------------------------------- queries
 
 def texel_centre_queries(W: int, H: int, ts) -> np.ndarray:
