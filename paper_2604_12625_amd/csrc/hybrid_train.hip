@@ -99,11 +99,11 @@ __device__ __forceinline__ void wave_grad(float* __restrict__ g, int64_t idx, fl
   if (lane == 0) atomicAdd(g + idx, v);
 }
 
-constexpr int kHtWaves = 4;
+constexpr int kHtThreads = 64;   // one wave per workgroup: small batches still spread over the CUs
 
 // MODE: NDGI_TRAIN_FORWARD writes pred; NDGI_TRAIN_LOSS_GRAD adds the loss and gradients.
 template <int HD, int MODE>
-__global__ __launch_bounds__(256) void k_hybrid_train(HybTrainDims d, const float* __restrict__ P, float* __restrict__ G,
+__global__ __launch_bounds__(kHtThreads) void k_hybrid_train(HybTrainDims d, const float* __restrict__ P, float* __restrict__ G,
                                                        const float* __restrict__ keys,
                                                        const uint32_t* __restrict__ samples, int64_t n,
                                                        const float* __restrict__ target, float* __restrict__ pred,
@@ -112,15 +112,15 @@ __global__ __launch_bounds__(256) void k_hybrid_train(HybTrainDims d, const floa
   using Sh = HybShape<HD>;
   __shared__ float sw[Sh::kSize];
   const float* mlp = P + d.o_mlp;
-  for (int i = threadIdx.x; i < Sh::kSize; i += 256) sw[i] = mlp[i];
+  for (int i = threadIdx.x; i < Sh::kSize; i += kHtThreads) sw[i] = mlp[i];
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const bool bcsim = flags & NDGI_HTRAIN_BCSIM, noise = flags & NDGI_HTRAIN_NOISE, qplanes = flags & NDGI_HTRAIN_QPLANES;
   float* gm = G + d.o_mlp;
-  const int64_t stride = (int64_t)gridDim.x * 256;
+  const int64_t stride = (int64_t)gridDim.x * kHtThreads;
   const int64_t rounds = (n + stride - 1) / stride;   // every lane runs the same rounds (wave reductions)
   for (int64_t r = 0; r < rounds; ++r) {
-    const int64_t s = r * stride + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t s = r * stride + (int64_t)blockIdx.x * kHtThreads + threadIdx.x;
     const bool live = s < n;
     const uint32_t word = samples[live ? s : 0];
     const int x = min((int)(word & 0xfffu), d.W - 1), y = min((int)((word >> 12) & 0xfffu), d.H - 1);
@@ -475,12 +475,12 @@ int ndgi_hybrid_train_step(ndgi_ctx* c, ndgi_hybrid_train_state* st, const ndgi_
   if (needs_batch) {
     const uint64_t base = (uint64_t)st->seed * 0x9E3779B97F4A7C15ull + ((uint64_t)st->step << 32);
     const float inv3n = (float)(1.0 / (3.0 * (double)b->n));
-    int64_t wgs = (b->n + 255) / 256;
-    const int64_t cap = (int64_t)c->n_cu * 4;
+    int64_t wgs = (b->n + kHtThreads - 1) / kHtThreads;
+    const int64_t cap = (int64_t)c->n_cu * 8;
     if (wgs > cap) wgs = cap;
     if (mode != NDGI_TRAIN_FORWARD) hipLaunchKernelGGL(k_zero_d, dim3(1), dim3(64), 0, s, loss_dev, 1);
 #define NDGI_HT(HD, M)                                                                                       \
-  hipLaunchKernelGGL((k_hybrid_train<HD, M>), dim3((unsigned)wgs), dim3(256), 0, s, d, st->params, st->grads, \
+  hipLaunchKernelGGL((k_hybrid_train<HD, M>), dim3((unsigned)wgs), dim3(kHtThreads), 0, s, d, st->params, st->grads, \
                      st->keys, b->samples, b->n, b->target, b->pred, flags, base, inv3n, loss_dev)
     if (mode == NDGI_TRAIN_FORWARD) {
       if (d.hidden == 16) NDGI_HT(16, NDGI_TRAIN_FORWARD);
