@@ -334,17 +334,23 @@ int ndgi_hybrid_decode_pages_graph(ndgi_ctx* ctx, const ndgi_hybrid_model* model
                                    int32_t max_reqs, int32_t page, void* dst, int64_t dst_pitch,
                                    int32_t prec, int32_t widths, hipStream_t stream);
 
-/* Trainable state of a hybrid model (Sec. 3.4, Eq. 6-8; Sec. 4).  One flat float32 layout
- * shared by params, grads, adam_m, adam_v:
+/* Trainable state of n_models hybrid models of equal sizes (Sec. 3.4, Eq. 6-8; Sec. 4; the
+ * paper trains one model per virtual-texture tile).  Per model the feature block is
  *   [ F_uv endpoints [H/4][W/4][4][2] | F_uv weights [H][W][4]
  *   | F_uvt endpoints [S][Gv/4][Gu/4][4][2] | F_uvt weights [S][Gv][Gu][4]
- *   | F_ut [Tt][U][2] | F_vt [Tt][V][2] | decoder [ndgi_hybrid_mlp_size(hidden)] ]
- * (ndgi_hybrid_train_param_count values).  Sizes as ndgi_hybrid_model, with W, H <= 4096.
- * A training sample is texel (x, y) of baked frame f: t = keys[f] (keys given) or
- * f / (frames - 1), and tau = f / (frames - 1). */
+ *   | F_ut [Tt][U][2] | F_vt [Tt][V][2] ]
+ * and the decoder block [ndgi_hybrid_mlp_size(hidden)]; params, grads, adam_m and adam_v
+ * hold all feature blocks, model after model, then all decoder blocks:
+ * n_models * ndgi_hybrid_train_param_count values.  Sizes as ndgi_hybrid_model, with W, H
+ * <= 4096.  A training sample is texel (x, y) of baked frame f: t = keys[f] (keys given) or
+ * f / (frames - 1), and tau = f / (frames - 1); model m's samples are batch entries
+ * [m * per_model, (m + 1) * per_model) and its target is target[m]. */
 typedef struct ndgi_hybrid_train_state {
     int32_t W, H, Gu, Gv, S, U, V, Tt, hidden;
     int32_t frames;           /* baked frames of the target, 1..256                       */
+    int32_t n_models;         /* models trained together (one per tile), >= 1             */
+    int32_t per_model;        /* samples per model in a batch; with n_models > 1 a multiple
+                                 of 64 and n = n_models * per_model (ignored for 1 model)  */
     const float* keys;        /* device [frames] frame times, or NULL (uniform)           */
     float* params;
     float* grads;
@@ -359,8 +365,8 @@ typedef struct ndgi_hybrid_train_state {
 typedef struct ndgi_hybrid_batch {
     const uint32_t* samples;  /* device [n]: x | y << 12 | f << 24                        */
     int64_t n;                /* 1 .. 2^31 - 1                                            */
-    const float* target;      /* device [frames][H][W][3] preprocessed target (LOSS_GRAD,
-                                 FUSED; see ndgi_hybrid_normalize_target)                 */
+    const float* target;      /* device [n_models][frames][H][W][3] preprocessed target
+                                 (LOSS_GRAD, FUSED; see ndgi_hybrid_normalize_target)     */
     float* pred;              /* device [n][3] (FORWARD)                                  */
 } ndgi_hybrid_batch;
 
@@ -377,7 +383,7 @@ typedef struct ndgi_hybrid_batch {
 #define NDGI_HTRAIN_NOISE   2
 #define NDGI_HTRAIN_QPLANES 4
 
-/* Total float parameters of a hybrid state; -1 for sizes out of range. */
+/* Float parameters of one model of a hybrid state; -1 for sizes out of range. */
 int64_t ndgi_hybrid_train_param_count(int32_t W, int32_t H, int32_t Gu, int32_t Gv, int32_t S, int32_t U,
                                       int32_t V, int32_t Tt, int32_t hidden);
 
@@ -388,14 +394,15 @@ int64_t ndgi_hybrid_train_param_count(int32_t W, int32_t H, int32_t Gu, int32_t 
 int ndgi_hybrid_train_step(ndgi_ctx* ctx, ndgi_hybrid_train_state* state, const ndgi_hybrid_batch* batch,
                            int32_t mode, int32_t flags, double* loss_dev, hipStream_t stream);
 
-/* Export a trained state as a decodable hybrid model (Sec. 3.4 last paragraph): BC4 blocks of
+/* Export model `model` of a trained state as a decodable hybrid model (Sec. 3.4 last
+ * paragraph): BC4 blocks of
  * F_uv ([H/4][W/4][4][8]) and of every F_uvt slice ([S][Gv/4][Gu/4][4][8]) in the encoding of
  * ndgi_export, planes rounded to 8 bits (rint of fl32(255 v)), decoder converted to
  * mlp_dtype.  The decode of the export at a training sample equals the FORWARD with
  * BCSIM | QPLANES.  Errors: INVALID_ARG. */
-int ndgi_hybrid_export(ndgi_ctx* ctx, const ndgi_hybrid_train_state* state, uint8_t* fuv_out,
-                       uint8_t* fuvt_out, uint8_t* fut_out, uint8_t* fvt_out, void* mlp_out,
-                       int32_t mlp_dtype, hipStream_t stream);
+int ndgi_hybrid_export(ndgi_ctx* ctx, const ndgi_hybrid_train_state* state, int32_t model,
+                       uint8_t* fuv_out, uint8_t* fuvt_out, uint8_t* fut_out, uint8_t* fvt_out,
+                       void* mlp_out, int32_t mlp_dtype, hipStream_t stream);
 
 /* Target preprocessing of Sec. 4: y^(1/gamma) per texel and channel, divided per frame and
  * channel by its mean.  target: device FP16 bits [frames][H][W][3]; out: device float, same

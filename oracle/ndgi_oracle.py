@@ -732,8 +732,9 @@ def _bc_texels(ep, wt, sl, ys, xs, bcsim: bool):
 
 
 def hybrid_train_forward(state: dict, xs, ys, fs, flags: int, seed: int = 0, step: int = 0,
-                         need_cache: bool = False):
-    """Decoder output at training samples (texel (x, y) of frame f) -> [B][3]."""
+                         need_cache: bool = False, s_offset: int = 0):
+    """Decoder output at training samples (texel (x, y) of frame f) -> [B][3].  The noise
+    counter of sample j is s_offset + j (its position in the whole batch)."""
     d = state["dims"]
     xs = np.asarray(xs, dtype=np.int64)
     ys = np.asarray(ys, dtype=np.int64)
@@ -782,7 +783,7 @@ def hybrid_train_forward(state: dict, xs, ys, fs, flags: int, seed: int = 0, ste
         taps["planes"].append(lst)
     x = np.concatenate([Vuvt, Vuv, planes[0], planes[1], gamma_t(t)], axis=-1)
     if flags & HT_NOISE:
-        sidx = np.arange(xs.size).reshape(xs.shape)
+        sidx = s_offset + np.arange(xs.size).reshape(xs.shape)
         x[..., :12] += NOISE_ALPHA * hybrid_noise(seed, step, sidx[..., None], np.arange(12))
     P = unpack_hybrid_mlp(state["mlp"], d["hidden"])
     a1 = x @ P["W1"].T + P["b1"]
@@ -802,12 +803,15 @@ def gelu_grad(a: np.ndarray) -> np.ndarray:
     return 0.5 * (1.0 + erf(a / np.sqrt(2.0))) + a * np.exp(-0.5 * a * a) / np.sqrt(2.0 * np.pi)
 
 
-def hybrid_train_grads(state: dict, xs, ys, fs, target, flags: int, seed: int = 0, step: int = 0):
-    """L2 loss (mean over samples and channels) and its gradients for every state array."""
+def hybrid_train_grads(state: dict, xs, ys, fs, target, flags: int, seed: int = 0, step: int = 0,
+                       s_offset: int = 0, n_total: int | None = None):
+    """L2 loss (mean over samples and channels) and its gradients for every state array.
+    With several models trained together the mean runs over all n_total samples of the
+    batch; this model's samples start at position s_offset."""
     d = state["dims"]
-    out, c = hybrid_train_forward(state, xs, ys, fs, flags, seed, step, need_cache=True)
+    out, c = hybrid_train_forward(state, xs, ys, fs, flags, seed, step, need_cache=True, s_offset=s_offset)
     target = np.asarray(target, dtype=np.float64)
-    n = out.size
+    n = out.size if n_total is None else 3 * n_total
     loss = float(np.sum((out - target) ** 2) / n)
     P = c["P"]
     dout = (2.0 / n) * (out - target)

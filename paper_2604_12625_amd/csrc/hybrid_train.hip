@@ -5,7 +5,10 @@
 // (gamma, per-frame mean) with its inverse.
 //
 // One sample per lane.  A training sample is texel (x, y) of baked frame f, so its texel
-// centre and frame time fix every interpolation weight.  The decoder runs in FP32 on the
+// centre and frame time fix every interpolation weight.  One launch trains any number of
+// models of the same sizes (the paper trains one model per virtual-texture tile): each
+// model owns a contiguous run of the batch, so every wave's samples share one model and its
+// decoder in LDS.  The decoder runs in FP32 on the
 // VALU from weights staged in LDS (hidden 16 or 64); the weight gradients are the sums
 // over samples of outer products, reduced across the wave with lane shuffles and added to
 // the gradient array by one lane; feature gradients go out as float atomics.
@@ -16,9 +19,13 @@ namespace ndgi {
 
 __device__ __forceinline__ float half_bits_f(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
 
+// Sizes and segment offsets of one model (feature offsets relative to the model's feature
+// block, F_uv endpoints first); the M models of a launch keep their feature blocks side by
+// side, then their decoders: [M x o_mlp | M x (n - o_mlp)].
 struct HybTrainDims {
   int W, H, Gu, Gv, S, U, V, Tt, hidden, frames;
-  int64_t o_uvw, o_tep, o_tw, o_ut, o_vt, o_mlp, n;   // segment offsets (F_uv endpoints at 0), total
+  int M, Bm;                                          // models, samples per model
+  int64_t o_uvw, o_tep, o_tw, o_ut, o_vt, o_mlp, n;   // segment offsets, parameters per model
 };
 
 static HybTrainDims htd_of(const ndgi_hybrid_train_state* st) {
@@ -33,6 +40,8 @@ static HybTrainDims htd_of(const ndgi_hybrid_train_state* st) {
   d.Tt = st->Tt;
   d.hidden = st->hidden;
   d.frames = st->frames;
+  d.M = st->n_models < 1 ? 1 : st->n_models;
+  d.Bm = st->per_model;
   d.o_uvw = (int64_t)(d.H / 4) * (d.W / 4) * 4 * 2;
   d.o_tep = d.o_uvw + (int64_t)d.H * d.W * 4;
   d.o_tw = d.o_tep + (int64_t)d.S * (d.Gv / 4) * (d.Gu / 4) * 4 * 2;
@@ -103,25 +112,37 @@ constexpr int kHtThreads = 64;   // one wave per workgroup: small batches still 
 
 // MODE: NDGI_TRAIN_FORWARD writes pred; NDGI_TRAIN_LOSS_GRAD adds the loss and gradients.
 template <int HD, int MODE>
-__global__ __launch_bounds__(kHtThreads) void k_hybrid_train(HybTrainDims d, const float* __restrict__ P, float* __restrict__ G,
+__global__ __launch_bounds__(kHtThreads) void k_hybrid_train(HybTrainDims d, const float* __restrict__ Pall,
+                                                              float* __restrict__ Gall,
                                                        const float* __restrict__ keys,
                                                        const uint32_t* __restrict__ samples, int64_t n,
                                                        const float* __restrict__ target, float* __restrict__ pred,
                                                        int flags, uint64_t noise_base, float inv3n,
                                                        double* __restrict__ loss_acc) {
   using Sh = HybShape<HD>;
+  static_assert(kHtThreads == 64, "one wave per workgroup: its samples belong to one model");
   __shared__ float sw[Sh::kSize];
-  const float* mlp = P + d.o_mlp;
-  for (int i = threadIdx.x; i < Sh::kSize; i += kHtThreads) sw[i] = mlp[i];
-  __syncthreads();
   const int lane = threadIdx.x & 63;
   const bool bcsim = flags & NDGI_HTRAIN_BCSIM, noise = flags & NDGI_HTRAIN_NOISE, qplanes = flags & NDGI_HTRAIN_QPLANES;
-  float* gm = G + d.o_mlp;
   const int64_t stride = (int64_t)gridDim.x * kHtThreads;
   const int64_t rounds = (n + stride - 1) / stride;   // every lane runs the same rounds (wave reductions)
+  int cur = -1;
   for (int64_t r = 0; r < rounds; ++r) {
-    const int64_t s = r * stride + (int64_t)blockIdx.x * kHtThreads + threadIdx.x;
+    const int64_t s0 = r * stride + (int64_t)blockIdx.x * kHtThreads;
+    const int64_t s = s0 + threadIdx.x;
     const bool live = s < n;
+    // the wave's 64 samples belong to one model (the host checks that Bm is a multiple of 64)
+    const int m = (int)min(s0 / d.Bm, (int64_t)d.M - 1);
+    const float* P = Pall + (int64_t)m * d.o_mlp;
+    float* G = Gall + (int64_t)m * d.o_mlp;
+    const int64_t mlp_off = (int64_t)d.M * d.o_mlp + (int64_t)m * (d.n - d.o_mlp);
+    float* gm = Gall + mlp_off;
+    if (m != cur) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < Sh::kSize; i += kHtThreads) sw[i] = Pall[mlp_off + i];
+      __syncthreads();
+      cur = m;
+    }
     const uint32_t word = samples[live ? s : 0];
     const int x = min((int)(word & 0xfffu), d.W - 1), y = min((int)((word >> 12) & 0xfffu), d.H - 1);
     const int f = min((int)(word >> 24), d.frames - 1);
@@ -220,7 +241,7 @@ __global__ __launch_bounds__(kHtThreads) void k_hybrid_train(HybTrainDims d, con
       // ---- loss and output gradient
       float dout[3];
       double sq = 0.0;
-      const int64_t ti = (((int64_t)f * d.H + y) * d.W + x) * 3;
+      const int64_t ti = ((((int64_t)m * d.frames + f) * d.H + y) * d.W + x) * 3;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const float e = live ? out[c] - target[ti + c] : 0.0f;
@@ -422,6 +443,7 @@ static int check_htrain(const ndgi_hybrid_train_state* st, const char* who) {
   if (rc) return rc;
   if (st->W > 4096 || st->H > 4096) return fail(NDGI_ERR_INVALID_ARG, "%s: W, H above 4096", who);
   if (st->frames < 1 || st->frames > 256) return fail(NDGI_ERR_INVALID_ARG, "%s: frames=%d not in 1..256", who, st->frames);
+  if (st->n_models < 1) return fail(NDGI_ERR_INVALID_ARG, "%s: n_models=%d < 1", who, st->n_models);
   return NDGI_OK;
 }
 
@@ -461,7 +483,8 @@ int ndgi_hybrid_train_step(ndgi_ctx* c, ndgi_hybrid_train_state* st, const ndgi_
   if (flags & ~(NDGI_HTRAIN_BCSIM | NDGI_HTRAIN_NOISE | NDGI_HTRAIN_QPLANES))
     return fail(NDGI_ERR_INVALID_ARG, "hybrid_train_step: unknown flags 0x%x", flags);
   const HybTrainDims d = htd_of(st);
-  if (mode == NDGI_TRAIN_ZERO_GRAD) return launch_fill_zero(c, st->grads, d.n, s);
+  const int64_t total = (int64_t)d.M * d.n;
+  if (mode == NDGI_TRAIN_ZERO_GRAD) return launch_fill_zero(c, st->grads, total, s);
   const bool needs_batch = mode != NDGI_TRAIN_ADAM;
   if (needs_batch) {
     if (!b || !b->samples || b->n < 1 || b->n > INT32_MAX)
@@ -469,10 +492,15 @@ int ndgi_hybrid_train_step(ndgi_ctx* c, ndgi_hybrid_train_state* st, const ndgi_
     if (mode == NDGI_TRAIN_FORWARD && !b->pred) return fail(NDGI_ERR_INVALID_ARG, "hybrid_train_step: FORWARD needs pred");
     if (mode != NDGI_TRAIN_FORWARD && (!b->target || !loss_dev))
       return fail(NDGI_ERR_INVALID_ARG, "hybrid_train_step: LOSS_GRAD/FUSED need target and loss_dev");
+    if (d.M > 1 && (d.Bm < 64 || d.Bm % 64 || (int64_t)d.Bm * d.M != b->n))
+      return fail(NDGI_ERR_INVALID_ARG,
+                  "hybrid_train_step: %d models need per_model a multiple of 64 with n = n_models * per_model", d.M);
   }
   if ((mode == NDGI_TRAIN_ADAM || mode == NDGI_TRAIN_FUSED) && (!st->adam_m || !st->adam_v))
     return fail(NDGI_ERR_INVALID_ARG, "hybrid_train_step: Adam needs adam_m, adam_v");
   if (needs_batch) {
+    HybTrainDims dl = d;
+    if (dl.M == 1) dl.Bm = (int)b->n;
     const uint64_t base = (uint64_t)st->seed * 0x9E3779B97F4A7C15ull + ((uint64_t)st->step << 32);
     const float inv3n = (float)(1.0 / (3.0 * (double)b->n));
     int64_t wgs = (b->n + kHtThreads - 1) / kHtThreads;
@@ -480,7 +508,7 @@ int ndgi_hybrid_train_step(ndgi_ctx* c, ndgi_hybrid_train_state* st, const ndgi_
     if (wgs > cap) wgs = cap;
     if (mode != NDGI_TRAIN_FORWARD) hipLaunchKernelGGL(k_zero_d, dim3(1), dim3(64), 0, s, loss_dev, 1);
 #define NDGI_HT(HD, M)                                                                                       \
-  hipLaunchKernelGGL((k_hybrid_train<HD, M>), dim3((unsigned)wgs), dim3(kHtThreads), 0, s, d, st->params, st->grads, \
+  hipLaunchKernelGGL((k_hybrid_train<HD, M>), dim3((unsigned)wgs), dim3(kHtThreads), 0, s, dl, st->params, st->grads, \
                      st->keys, b->samples, b->n, b->target, b->pred, flags, base, inv3n, loss_dev)
     if (mode == NDGI_TRAIN_FORWARD) {
       if (d.hidden == 16) NDGI_HT(16, NDGI_TRAIN_FORWARD);
@@ -494,7 +522,8 @@ int ndgi_hybrid_train_step(ndgi_ctx* c, ndgi_hybrid_train_state* st, const ndgi_
   }
   if (mode == NDGI_TRAIN_ADAM || mode == NDGI_TRAIN_FUSED) {
     // every feature map is projected to [0, 1]; the decoder is not
-    rc = launch_adam(c, st->params, st->grads, st->adam_m, st->adam_v, d.n, d.o_mlp, d.o_mlp, st->lr_feat,
+    rc = launch_adam(c, st->params, st->grads, st->adam_m, st->adam_v, total, (int64_t)d.M * d.o_mlp,
+                     (int64_t)d.M * d.o_mlp, st->lr_feat,
                      st->lr_mlp, st->beta1, st->beta2, st->eps, st->step + 1, s);
     if (rc) return rc;
     st->step += 1;
@@ -502,8 +531,9 @@ int ndgi_hybrid_train_step(ndgi_ctx* c, ndgi_hybrid_train_state* st, const ndgi_
   return NDGI_OK;
 }
 
-int ndgi_hybrid_export(ndgi_ctx* c, const ndgi_hybrid_train_state* st, uint8_t* fuv_out, uint8_t* fuvt_out,
-                       uint8_t* fut_out, uint8_t* fvt_out, void* mlp_out, int32_t mlp_dtype, hipStream_t s) {
+int ndgi_hybrid_export(ndgi_ctx* c, const ndgi_hybrid_train_state* st, int32_t model, uint8_t* fuv_out,
+                       uint8_t* fuvt_out, uint8_t* fut_out, uint8_t* fvt_out, void* mlp_out, int32_t mlp_dtype,
+                       hipStream_t s) {
   clear_error();
   if (!c) return fail(NDGI_ERR_INVALID_ARG, "hybrid_export: ctx is NULL");
   int rc = check_htrain(st, "hybrid_export");
@@ -513,17 +543,20 @@ int ndgi_hybrid_export(ndgi_ctx* c, const ndgi_hybrid_train_state* st, uint8_t* 
   if (mlp_dtype != NDGI_DTYPE_F32 && mlp_dtype != NDGI_DTYPE_F16)
     return fail(NDGI_ERR_INVALID_ARG, "hybrid_export: bad dtype");
   const HybTrainDims d = htd_of(st);
+  if (model < 0 || model >= d.M) return fail(NDGI_ERR_INVALID_ARG, "hybrid_export: model %d of %d", model, d.M);
+  const float* P = st->params + (int64_t)model * d.o_mlp;
+  const float* mlp = st->params + (int64_t)d.M * d.o_mlp + (int64_t)model * (d.n - d.o_mlp);
   const int64_t nb_uv = (int64_t)(d.H / 4) * (d.W / 4) * 4, nb_uvt = (int64_t)d.S * (d.Gv / 4) * (d.Gu / 4) * 4;
-  hipLaunchKernelGGL(k_export_bc4c, dim3(grid_of(nb_uv, c->n_cu * 16)), dim3(256), 0, s, st->params,
-                     st->params + d.o_uvw, d.W, d.H, 4, nb_uv, fuv_out);
-  hipLaunchKernelGGL(k_export_bc4c, dim3(grid_of(nb_uvt, c->n_cu * 16)), dim3(256), 0, s, st->params + d.o_tep,
-                     st->params + d.o_tw, d.Gu, d.Gv, 4, nb_uvt, fuvt_out);
-  hipLaunchKernelGGL(k_quant8, dim3(grid_of((int64_t)d.Tt * d.U * 2, 1024)), dim3(256), 0, s, st->params + d.o_ut,
-                     fut_out, (int64_t)d.Tt * d.U * 2);
-  hipLaunchKernelGGL(k_quant8, dim3(grid_of((int64_t)d.Tt * d.V * 2, 1024)), dim3(256), 0, s, st->params + d.o_vt,
-                     fvt_out, (int64_t)d.Tt * d.V * 2);
+  hipLaunchKernelGGL(k_export_bc4c, dim3(grid_of(nb_uv, c->n_cu * 16)), dim3(256), 0, s, P, P + d.o_uvw, d.W, d.H,
+                     4, nb_uv, fuv_out);
+  hipLaunchKernelGGL(k_export_bc4c, dim3(grid_of(nb_uvt, c->n_cu * 16)), dim3(256), 0, s, P + d.o_tep, P + d.o_tw,
+                     d.Gu, d.Gv, 4, nb_uvt, fuvt_out);
+  hipLaunchKernelGGL(k_quant8, dim3(grid_of((int64_t)d.Tt * d.U * 2, 1024)), dim3(256), 0, s, P + d.o_ut, fut_out,
+                     (int64_t)d.Tt * d.U * 2);
+  hipLaunchKernelGGL(k_quant8, dim3(grid_of((int64_t)d.Tt * d.V * 2, 1024)), dim3(256), 0, s, P + d.o_vt, fvt_out,
+                     (int64_t)d.Tt * d.V * 2);
   NDGI_HIP(hipGetLastError());
-  return launch_convert(c, st->params + d.o_mlp, mlp_out, mlp_dtype, d.n - d.o_mlp, s);
+  return launch_convert(c, mlp, mlp_out, mlp_dtype, d.n - d.o_mlp, s);
 }
 
 int ndgi_hybrid_normalize_target(ndgi_ctx* c, const uint16_t* target, int32_t frames, int32_t W, int32_t H,

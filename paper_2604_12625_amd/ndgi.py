@@ -69,7 +69,8 @@ class NdgiHybridModel(C.Structure):
 class NdgiHybridTrainState(C.Structure):
     _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("Gu", C.c_int32), ("Gv", C.c_int32),
                 ("S", C.c_int32), ("U", C.c_int32), ("V", C.c_int32), ("Tt", C.c_int32),
-                ("hidden", C.c_int32), ("frames", C.c_int32), ("keys", C.c_void_p),
+                ("hidden", C.c_int32), ("frames", C.c_int32), ("n_models", C.c_int32),
+                ("per_model", C.c_int32), ("keys", C.c_void_p),
                 ("params", C.c_void_p), ("grads", C.c_void_p), ("adam_m", C.c_void_p),
                 ("adam_v", C.c_void_p), ("step", C.c_int64), ("lr_feat", C.c_float),
                 ("lr_mlp", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
@@ -81,7 +82,7 @@ class NdgiHybridBatch(C.Structure):
 
 
 assert C.sizeof(NdgiModel) == 64 and C.sizeof(NdgiPageReq) == 24 and C.sizeof(NdgiHybridModel) == 96
-assert C.sizeof(NdgiHybridTrainState) == 112 and C.sizeof(NdgiHybridBatch) == 32
+assert C.sizeof(NdgiHybridTrainState) == 120 and C.sizeof(NdgiHybridBatch) == 32
 
 
 class NdgiError(RuntimeError):
@@ -127,7 +128,7 @@ def lib():
         L.ndgi_hybrid_train_param_count.restype = i64
         L.ndgi_hybrid_train_step.argtypes = [vp, C.POINTER(NdgiHybridTrainState), C.POINTER(NdgiHybridBatch), i32,
                                              i32, vp, vp]
-        L.ndgi_hybrid_export.argtypes = [vp, C.POINTER(NdgiHybridTrainState), vp, vp, vp, vp, vp, i32, vp]
+        L.ndgi_hybrid_export.argtypes = [vp, C.POINTER(NdgiHybridTrainState), i32, vp, vp, vp, vp, vp, i32, vp]
         L.ndgi_hybrid_normalize_target.argtypes = [vp, vp, i32, i32, i32, C.c_float, vp, vp, vp]
         L.ndgi_hybrid_restore.argtypes = [vp, vp, i32, i64, vp, C.c_float, vp, vp]
         _lib = L

@@ -161,42 +161,51 @@ HYB_KEYS = ("fuv_ep", "fuv_w", "fuvt_ep", "fuvt_w", "fut", "fvt", "mlp")
 
 
 class HybridTrainer:
-    """Trainable hybrid-layout state in device memory (ndgi_hybrid_train_step): flat float32
-    params / grads / Adam m, v with the layout [F_uv endpoints | F_uv weights | F_uvt
-    endpoints | F_uvt weights | F_ut | F_vt | decoder]."""
+    """Trainable hybrid-layout state of one or more models of equal sizes in device memory
+    (ndgi_hybrid_train_step): flat float32 params / grads / Adam m, v holding every model's
+    feature block [F_uv endpoints | F_uv weights | F_uvt endpoints | F_uvt weights | F_ut |
+    F_vt], model after model, then every model's decoder."""
 
-    def __init__(self, ctx: N.Context, init: dict, lr_feat=1e-3, lr_mlp=1e-3, betas=(0.9, 0.999), eps=1e-8,
-                 seed=0, device="cuda"):
+    def __init__(self, ctx: N.Context, init, lr_feat=1e-3, lr_mlp=1e-3, betas=(0.9, 0.999), eps=1e-8,
+                 seed=0, per_model=0, device="cuda"):
         import torch
-        d = init["dims"]
-        self.ctx, self.d = ctx, dict(d)
+        inits = init if isinstance(init, (list, tuple)) else [init]
+        d = inits[0]["dims"]
+        self.ctx, self.d, self.M = ctx, dict(d), len(inits)
         dims = [d[k] for k in ("W", "H", "Gu", "Gv", "S", "U", "V", "Tt", "hidden")]
         n = int(N.lib().ndgi_hybrid_train_param_count(*dims))
-        self.n_params = n
-        flat = np.concatenate([np.asarray(init[k], dtype=np.float32).ravel() for k in HYB_KEYS])
-        assert flat.size == n, (flat.size, n)
+        self.n_params = n * self.M
+        feats = [np.concatenate([np.asarray(m[k], dtype=np.float32).ravel() for k in HYB_KEYS[:-1]]) for m in inits]
+        mlps = [np.asarray(m["mlp"], dtype=np.float32).ravel() for m in inits]
+        self.n_feat = feats[0].size
+        flat = np.concatenate(feats + mlps)
+        assert flat.size == self.n_params, (flat.size, self.n_params)
         self.params = torch.from_numpy(flat).to(device)
-        self.grads = torch.zeros(n, dtype=torch.float32, device=device)
-        self.m = torch.zeros(n, dtype=torch.float32, device=device)
-        self.v = torch.zeros(n, dtype=torch.float32, device=device)
+        self.grads = torch.zeros_like(self.params)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
         self.loss = torch.zeros(1, dtype=torch.float64, device=device)
         keys = np.asarray(d.get("keys", []), dtype=np.float32)
         self.keys = torch.from_numpy(keys).to(device) if keys.size else None
-        self.state = N.NdgiHybridTrainState(*dims, int(d["frames"]), N._ptr(self.keys), self.params.data_ptr(),
-                                            self.grads.data_ptr(), self.m.data_ptr(), self.v.data_ptr(), 0,
-                                            float(lr_feat), float(lr_mlp), float(betas[0]), float(betas[1]),
-                                            float(eps), int(seed))
+        self.state = N.NdgiHybridTrainState(*dims, int(d["frames"]), self.M, int(per_model), N._ptr(self.keys),
+                                            self.params.data_ptr(), self.grads.data_ptr(), self.m.data_ptr(),
+                                            self.v.data_ptr(), 0, float(lr_feat), float(lr_mlp), float(betas[0]),
+                                            float(betas[1]), float(eps), int(seed))
 
-    def split(self, flat) -> dict:
+    def split(self, flat, model=0) -> dict:
+        """Views of one model's arrays in a flat [params | grads | m | v]-shaped tensor."""
         d = self.d
         shapes = dict(fuv_ep=(d["H"] // 4, d["W"] // 4, 4, 2), fuv_w=(d["H"], d["W"], 4),
                       fuvt_ep=(d["S"], d["Gv"] // 4, d["Gu"] // 4, 4, 2), fuvt_w=(d["S"], d["Gv"], d["Gu"], 4),
-                      fut=(d["Tt"], d["U"], 2), fvt=(d["Tt"], d["V"], 2), mlp=(-1,))
-        out, o = {}, 0
-        for k in HYB_KEYS:
-            cnt = int(np.prod(shapes[k])) if k != "mlp" else flat.numel() - o
+                      fut=(d["Tt"], d["U"], 2), fvt=(d["Tt"], d["V"], 2))
+        out, o = {}, model * self.n_feat
+        for k in HYB_KEYS[:-1]:
+            cnt = int(np.prod(shapes[k]))
             out[k] = flat[o:o + cnt].view(*shapes[k])
             o += cnt
+        ms = N.hybrid_mlp_size(d["hidden"])
+        o = self.M * self.n_feat + model * ms
+        out["mlp"] = flat[o:o + ms]
         return out
 
     def _run(self, mode, flags, samples=None, target=None, pred=None, stream=None):
@@ -229,7 +238,7 @@ class HybridTrainer:
     def zero_grad(self):
         self._run(N.TRAIN_ZERO_GRAD, 0)
 
-    def export(self, mlp_dtype=N.DTYPE_F16) -> N.HybridModel:
+    def export(self, mlp_dtype=N.DTYPE_F16, model=0) -> N.HybridModel:
         import torch
         d, dev = self.d, self.params.device
         fuv = torch.empty((d["H"] // 4, d["W"] // 4, 4, 8), dtype=torch.uint8, device=dev)
@@ -238,7 +247,7 @@ class HybridTrainer:
         fvt = torch.empty((d["Tt"], d["V"], 2), dtype=torch.uint8, device=dev)
         mlp = torch.empty(N.hybrid_mlp_size(d["hidden"]), dtype=torch.float16 if mlp_dtype == N.DTYPE_F16
                           else torch.float32, device=dev)
-        N.check(N.lib().ndgi_hybrid_export(self.ctx.h, C.byref(self.state), fuv.data_ptr(), fuvt.data_ptr(),
+        N.check(N.lib().ndgi_hybrid_export(self.ctx.h, C.byref(self.state), model, fuv.data_ptr(), fuvt.data_ptr(),
                                            fut.data_ptr(), fvt.data_ptr(), mlp.data_ptr(), mlp_dtype,
                                            N._stream(None)), "ndgi_hybrid_export")
         keys = self.keys if self.keys is not None else torch.zeros(0, dtype=torch.float32, device=dev)

@@ -149,3 +149,38 @@ def test_target_normalisation_and_restore(N, ctx):
     back = hybrid_restore(ctx, out[2].reshape(-1, 3), means[2], 2.2).cpu().numpy()
     _close(back, O.hybrid_restore(ref[2].reshape(-1, 3), ref_means[2], 2.2), 1e-5, "restore")
     _close(back, tgt[2].reshape(-1, 3).astype(np.float64), 1e-5, "round trip")
+
+
+@pytest.mark.parametrize("hidden", [16, 64])
+def test_many_models_in_one_launch(N, ctx, hidden):
+    """Three models trained together: each model's gradients are its own samples' gradients
+    of the loss averaged over the whole batch; Adam runs per element, so a fused step equals
+    three independent oracle steps with that mean."""
+    from paper_2604_12625_amd.train import HybridTrainer
+    M, Bm = 3, 128
+    sts = [_state(hidden, seed=40 + i) for i in range(M)]
+    for st in sts[1:]:
+        st["dims"] = sts[0]["dims"]          # models trained together share sizes and key times
+    g = np.random.default_rng(41)
+    d = sts[0]["dims"]
+    xs, ys, fs = (g.integers(0, d["W"], M * Bm), g.integers(0, d["H"], M * Bm), g.integers(0, d["frames"], M * Bm))
+    tgt = g.normal(0.5, 0.5, (M, d["frames"], d["H"], d["W"], 3)).astype(np.float32)
+    smp, tg = _dev(N, xs, ys, fs, tgt)
+    flags = 1 | 2
+    tr = HybridTrainer(ctx, sts, seed=13, per_model=Bm)
+    tr.zero_grad()
+    loss = float(tr.loss_grad(smp, tg, flags).item())
+    ref_loss = 0.0
+    for m in range(M):
+        sl = slice(m * Bm, (m + 1) * Bm)
+        lm, gm = O.hybrid_train_grads(sts[m], xs[sl], ys[sl], fs[sl], tgt[m][fs[sl], ys[sl], xs[sl]], flags, seed=13,
+                                      step=0, s_offset=m * Bm, n_total=M * Bm)
+        ref_loss += lm
+        got = tr.split(tr.grads, m)
+        for k in O.HYB_KEYS:
+            _close(got[k].cpu().numpy(), gm[k], 1e-4, f"model {m} {k}")
+    assert abs(loss - ref_loss) <= 1e-5 * abs(ref_loss), (loss, ref_loss)
+    # a bad per-model count is rejected
+    tr2 = HybridTrainer(ctx, sts, seed=13, per_model=100)
+    with pytest.raises(N.NdgiError):
+        tr2.loss_grad(smp, tg, flags)
