@@ -28,21 +28,28 @@ constexpr int kMaxKeys = 1024;      // largest T the host accepts
 struct BinGeom {
   int ts_log2;      // tile side = 1 << ts_log2 texels (5 or 6)
   int ntx, nty;     // tiles per row / column
+  int galign;       // 1: tiles of 8 x 8 grid cells (grid at a quarter of the texel resolution)
 };
 
-static bool bin_geom(int W, int H, BinGeom& g) {
+static bool bin_geom(const ndgi_model& m, BinGeom& g) {
   for (g.ts_log2 = 5; g.ts_log2 <= 6; ++g.ts_log2) {
-    g.ntx = (W + (1 << g.ts_log2) - 1) >> g.ts_log2;
-    g.nty = (H + (1 << g.ts_log2) - 1) >> g.ts_log2;
+    g.galign = g.ts_log2 == 5 && m.W == 4 * m.Gw && m.H == 4 * m.Gh;
+    g.ntx = g.galign ? (m.Gw + 7) >> 3 : (m.W + (1 << g.ts_log2) - 1) >> g.ts_log2;
+    g.nty = g.galign ? (m.Gh + 7) >> 3 : (m.H + (1 << g.ts_log2) - 1) >> g.ts_log2;
     if ((int64_t)g.ntx * g.nty <= kMaxBins) return true;
   }
   return false;
 }
 
-// Tile of a query: the one holding the clamped upper-left texel of its bilinear footprint
-// (coordinates outside the map, and NaN, clamp to an edge texel as the decode does), so
-// the footprint lies inside the tile plus one texel to the right and below.
+// Tile of a query.  Texel tiles: the tile holding the clamped upper-left texel of its
+// bilinear footprint (coordinates outside the map, and NaN, clamp to an edge texel as the
+// decode does), so the footprint lies inside the tile plus one texel to the right and
+// below.  Grid-aligned tiles (grid at a quarter of the texel resolution): the tile of 8 x 8
+// cells holding the upper-left grid node of the query, so the query reads nodes 8k..8k+8
+// of each axis (9, where a texel tile's 32 texels reach 10) and texels 32k+1..32k+34 (the
+// region of the texel tile 32k..32k+31 plus its halo).
 __device__ __forceinline__ int query_bin(float u, float v, const ndgi_model& m, const BinGeom& bg) {
+  if (bg.galign) return (coord_axis(v, m.Gh).i0 >> 3) * bg.ntx + (coord_axis(u, m.Gw).i0 >> 3);
   const Axis ax = coord_axis(u, m.W), ay = coord_axis(v, m.H);
   return (ay.i0 >> bg.ts_log2) * bg.ntx + (ax.i0 >> bg.ts_log2);
 }
@@ -427,8 +434,15 @@ struct Win {
   int x0, y0, nx, ny;
 };
 template <int TS>
-__device__ __forceinline__ Win tile_window(const ndgi_model& m, const Item& I) {
+__device__ __forceinline__ Win tile_window(const ndgi_model& m, const BinGeom& bg, const Item& I) {
   Win w;
+  if (bg.galign) {   // nodes 8k..8k+8 (tile origin 32k texels)
+    w.x0 = I.tx0 >> 2;
+    w.y0 = I.ty0 >> 2;
+    w.nx = min(9, m.Gw - w.x0);
+    w.ny = min(9, m.Gh - w.y0);
+    return w;
+  }
   int x1, y1;
   node_window(I.tx0, TS, m.W, m.Gw, w.x0, x1);
   node_window(I.ty0, TS, m.H, m.Gh, w.y0, y1);
@@ -515,7 +529,7 @@ __global__ __launch_bounds__(256) void k_decode_binned_lds(
   const int fy = f / FP, fx = f - FP * fy;
   for (int it = walk.first; it < walk.end; it += walk.step) {
     const Item I = item_at<TSL>(it, bg, start, items, item_bin);
-    const Win w = tile_window<TS>(m, I);
+    const Win w = tile_window<TS>(m, bg, I);
     u32x4 wv[kWinPer], blk[4];
     float4 rec;
     __syncthreads();     // the previous item's readers of reg and gwin are done
@@ -541,6 +555,8 @@ __global__ __launch_bounds__(256) void k_decode_binned_lds(
 // Largest grid window (in uint4) of any tile of the map, by the kernel's own arithmetic.
 static int64_t max_window_u4(const ndgi_model& m, const BinGeom& bg) {
   const int TS = 1 << bg.ts_log2;
+  const int64_t node_u4 = m.grid_dtype == NDGI_DTYPE_F16 ? 1 : 2;
+  if (bg.galign) return (int64_t)std::min(9, m.Gw) * std::min(9, m.Gh) * m.T * node_u4;
   int mx = 0, my = 0, lo, hi;
   for (int t = 0; t < bg.ntx; ++t) {
     node_window(t * TS, TS, m.W, m.Gw, lo, hi);
@@ -563,7 +579,7 @@ struct BinnedLayout {
 static int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 
 static bool binned_layout(const ndgi_model& m, int64_t n, BinnedLayout& L) {
-  if (!bin_geom(m.W, m.H, L.bg)) return false;
+  if (!bin_geom(m, L.bg)) return false;
   L.nbins = L.bg.ntx * L.bg.nty;
   L.counts_off = 0;
   L.start_off = align256((int64_t)kSortWgs * L.nbins * 4);

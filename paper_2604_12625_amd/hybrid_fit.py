@@ -131,3 +131,81 @@ def bits_per_texel_hybrid(W, H, frames, side, slices, plane, hidden, uv_bits_per
     mlp = hidden * 16 + hidden + hidden * hidden + hidden + 3 * hidden + 3
     bits = W * H * uv_bits_per_texel + side * side * slices * uv_bits_per_texel + (U + V) * Tt * 2 * 8 + mlp * 16
     return bits / (W * H * frames)
+
+
+def run_hfit_map(args, torch, N, I, ctx, profile="M", side=1024, steps1=3000, steps2=1000):
+    """The paper's production setting: a side x side lightmap as (side/128)^2 per-tile models,
+    trained together in one launch per step (4096 samples per model), exported, and decoded
+    for all 26 frames through the page decoder (one request per tile and frame, one launch)."""
+    from .train import HybridTrainer, hybrid_normalize_target, hybrid_restore
+    keys = I.lightmap_key_times(I.rng(6, I.P_MODEL, 1))
+    frames = len(keys)
+    nt = side // TILE
+    M = nt * nt
+    scene = I.light_scene(side, side, I.rng(7, I.P_TARGET))
+    full = torch.stack([I.scene_frame_torch(scene, float(t), device="cuda").to(torch.float16) for t in keys])
+    # tile-major target [M][frames][TILE][TILE][3]
+    tiles = full.view(frames, nt, TILE, nt, TILE, 3).permute(1, 3, 0, 2, 4, 5).reshape(M, frames, TILE, TILE, 3)
+    tiles = tiles.contiguous()
+    tgt, means = hybrid_normalize_target(ctx, tiles.view(M * frames, TILE, TILE, 3).view(torch.int16), GAMMA)
+    inits = [I.hybrid_train_init(TILE, TILE, profile, frames, keys, I.rng(7, I.P_INIT, m)) for m in range(M)]
+    tr = HybridTrainer(ctx, inits, lr_feat=LR, lr_mlp=LR, seed=1, per_model=BATCH)
+    _log(f"hybrid map: {M} tile models, {tr.n_params / 1e6:.2f} M parameters")
+    n_steps = steps1 + steps2
+    f1, f2 = N.HTRAIN_BCSIM | N.HTRAIN_NOISE, N.HTRAIN_BCSIM | N.HTRAIN_QPLANES
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    losses = []
+    torch.cuda.synchronize()
+    e0.record()
+    for i in range(n_steps):
+        if i == steps1:
+            tr.set_lr(lr_feat=0.0)
+        smp = I.train_samples_torch(M * BATCH, TILE, TILE, frames, seed=90_000 + i)
+        tr.step(smp, tgt, f1 if i < steps1 else f2)
+        if (i + 1) % 1000 == 0:
+            losses.append((i + 1, float(tr.loss.item())))
+    e1.record()
+    e1.synchronize()
+    train_ms = e0.elapsed_time(e1)
+    # export every tile model and decode all frames in one page launch
+    models = [tr.export(N.DTYPE_F16, model=m) for m in range(M)]
+    marr = N.models_array(models)
+    mi = np.repeat(np.arange(M), frames).astype(np.int32)
+    fi = np.tile(np.arange(frames), M)
+    rq = N.page_requests(mi, np.zeros(M * frames, np.int32), np.zeros(M * frames, np.int32),
+                         np.asarray(keys, np.float32)[fi], (np.arange(M * frames) * TILE * TILE).astype(np.int64))
+    nreq = torch.tensor([M * frames], dtype=torch.int32, device="cuda")
+    width = 2 if I.HYBRID_PROFILES[profile][1] == 64 else 1
+    out = {}
+    for prec, name in ((N.PREC_F16, "f16"), (N.PREC_F32, "f32")):
+        dst = torch.empty((M * frames * TILE * TILE, 3), dtype=torch.float16 if prec == N.PREC_F16 else torch.float32,
+                          device="cuda")
+        ctx.hybrid_decode_pages(marr, M, rq, nreq, M * frames, TILE, dst, TILE, prec, widths=width)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        ctx.hybrid_decode_pages(marr, M, rq, nreq, M * frames, TILE, dst, TILE, prec, widths=width)
+        ev1.record()
+        ev1.synchronize()
+        stats = []
+        for k in range(M * frames):
+            rec = hybrid_restore(ctx, dst[k * TILE * TILE:(k + 1) * TILE * TILE], means[k], GAMMA)
+            stats.append(ctx.tile_stats(rec, tiles.view(M * frames, TILE, TILE, 3)[k].view(torch.int16), TILE, TILE,
+                                        TILE).cpu().numpy())
+        tiled, glob = N.psnr_from_stats(stats, TILE, TILE, TILE)
+        out[name] = dict(psnr_tiled_db=tiled, psnr_global_db=glob, decode_all_frames_ms=ev0.elapsed_time(ev1))
+        _log(f"hybrid map {name}: PSNR tiled {tiled:.2f} dB, decode of {frames} frames {out[name]['decode_all_frames_ms']:.3f} ms")
+    assert ctx.error_flags() == 0
+    s_uvt, hidden = I.HYBRID_PROFILES[profile]
+    return {
+        "metric": "hybrid-layout map fit: per-tile models trained together, tiled PSNR after export",
+        "config": {"workload": f"{side}x{side} synthetic temporal lightmap at 26 key times as {M} tile models of "
+                               f"{TILE}^2, profile {profile}; batch {BATCH} per model, Adam lr {LR}; {steps1} steps with "
+                               f"BC simulation and noise, {steps2} decoder fine-tune steps"},
+        "data": "synthetic", "models": M, "train_params": int(tr.n_params),
+        "train_ms_per_step": train_ms / n_steps, "train_samples_per_s": M * BATCH * n_steps / (train_ms * 1e-3),
+        "loss_curve": losses, "decode": out,
+        "bits_per_texel_bc4": bits_per_texel_hybrid(TILE, TILE, frames, s_uvt, 12, (64, 64, 24), hidden, 16),
+        "bits_per_texel_bc7_accounting": bits_per_texel_hybrid(TILE, TILE, frames, s_uvt, 12, (64, 64, 24), hidden, 8),
+    }

@@ -130,11 +130,13 @@ BAD_Q = np.array([[np.nan, 0.5, 0.2], [0.5, np.inf, 0.2], [0.5, 0.5, -np.inf],
 
 @pytest.mark.parametrize("prec,tol", [(1, TOL16), (0, TOL32)])
 @pytest.mark.parametrize("grid_dt", [np.float16, np.float32])
-def test_binned_equals_direct_and_oracle(N, ctx, prec, tol, grid_dt):
-    """Several 32x32 tiles with a ragged edge (200 x 148 texels), all texel centres at one
-    time, random queries, out-of-range and non-finite queries: the binned decode gives
-    the direct decode's bits and the oracle's values."""
-    m = I.random_model(200, 148, 50, 37, 12, grid_dt, np.float16, config=54)
+@pytest.mark.parametrize("grid", [(50, 37), (70, 30)])
+def test_binned_equals_direct_and_oracle(N, ctx, prec, tol, grid_dt, grid):
+    """Several tiles with a ragged edge (200 x 148 texels), all texel centres at one time,
+    random queries, out-of-range and non-finite queries: the binned decode gives the direct
+    decode's bits and the oracle's values.  A 50 x 37 grid (a quarter of the texel
+    resolution) bins by 8 x 8 grid cells, a 70 x 30 grid by 32 x 32 texel tiles."""
+    m = I.random_model(200, 148, grid[0], grid[1], 12, grid_dt, np.float16, config=54)
     q = np.concatenate([I.texel_centre_queries(200, 148, [0.37]),
                         I.uniform_queries(50001, I.rng(54, I.P_QUERY)), EDGE_Q, BAD_Q])
     direct = _dec(N, ctx, m, q, prec)
