@@ -10,7 +10,7 @@ step, a 32-map virtual-texturing frame (p50 / p99), the training step with BC si
 timed on a bounded sample, and the paper's own hybrid layout (a 1024^2 lightmap of 64
 per-tile models, each profile of Table 3) beside the paper's Table 5 latencies.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c2|c5|hfit] [--hybrid-only]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c2|c5|hfit|hmap] [--hybrid-only]
 """
 from __future__ import annotations
 
@@ -325,7 +325,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c5", "hfit"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c5", "hfit", "hmap"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--random-path", default="binned", choices=["binned", "direct"],
                     help="decode of the random queries: tile-binned (default) or in arrival order")
@@ -357,6 +357,10 @@ def main():
     ctx = N.Context(0)
     if args.hybrid_only:
         print(json.dumps({"hybrid_1024_tiles": run_hybrid(args, torch, N, I, ctx)}), flush=True)
+        return
+    if args.workload == "hmap":
+        from paper_2604_12625_amd.hybrid_fit import run_hfit_map
+        print(json.dumps(run_hfit_map(args, torch, N, I, ctx)), flush=True)
         return
     if args.workload == "hfit":
         from paper_2604_12625_amd.hybrid_fit import run_hfit

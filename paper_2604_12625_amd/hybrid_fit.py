@@ -133,7 +133,7 @@ def bits_per_texel_hybrid(W, H, frames, side, slices, plane, hidden, uv_bits_per
     return bits / (W * H * frames)
 
 
-def run_hfit_map(args, torch, N, I, ctx, profile="M", side=1024, steps1=3000, steps2=1000):
+def run_hfit_map(args, torch, N, I, ctx, profile="M", side=1024, steps1=6000, steps2=2000):
     """The paper's production setting: a side x side lightmap as (side/128)^2 per-tile models,
     trained together in one launch per step (4096 samples per model), exported, and decoded
     for all 26 frames through the page decoder (one request per tile and frame, one launch)."""
