@@ -282,12 +282,120 @@ def decode_pages(models: list, reqs: list, page: int, dst: np.ndarray, pitch: in
 
 
 # --------------------------------------------------------------------------------------
+# BC7 mode 6 (the single-subset RGBA mode): one interpolation weight per texel shared by 4
+# channels, as Eq. (6)-(7) write it (w_p in [0, 1] per pixel, e1, e2 in [0, 1]^k)
+# --------------------------------------------------------------------------------------
+# A 16-byte block read as a 128-bit little-endian integer: bits 0..6 hold the mode (mode 6:
+# bit 6 set, bits 0..5 clear); then 7-bit endpoint values R0 R1 G0 G1 B0 B1 A0 A1 (bits
+# 7..62); p-bits P0 (bit 63) and P1 (bit 64); then the texel indices, texel 0 with 3 bits
+# (65..67, its top bit implied 0) and texel i >= 1 with 4 bits at 64 + 4 i.  Endpoint k of
+# channel c is the 8-bit value (v << 1) | P_k; texel value ((64 - w) E0 + w E1 + 32) >> 6
+# with w from the format's 4-bit weight table.
+BC7_WEIGHTS4 = (0, 4, 9, 13, 17, 21, 26, 30, 34, 38, 43, 47, 51, 55, 60, 64)
+
+
+def bc7m6_fields(block):
+    """(E0 [4], E1 [4], idx [16]) of one mode-6 block (bytes) as python ints."""
+    b = int.from_bytes(bytes(np.asarray(block, dtype=np.uint8)), "little")
+    assert b & 0x7F == 0x40, "not a mode 6 block"
+    v = [(b >> (7 + 7 * k)) & 0x7F for k in range(8)]
+    p0, p1 = (b >> 63) & 1, (b >> 64) & 1
+    E0 = [(v[2 * c] << 1) | p0 for c in range(4)]
+    E1 = [(v[2 * c + 1] << 1) | p1 for c in range(4)]
+    idx = [(b >> 65) & 7] + [(b >> (64 + 4 * i)) & 0xF for i in range(1, 16)]
+    return E0, E1, idx
+
+
+def bc7m6_decode_block(block) -> np.ndarray:
+    """[16 texels][4 channels] uint8 of one mode-6 block (texel s = 4 * row + col)."""
+    E0, E1, idx = bc7m6_fields(block)
+    out = np.zeros((16, 4), dtype=np.uint8)
+    for s_ in range(16):
+        w = BC7_WEIGHTS4[idx[s_]]
+        for c in range(4):
+            out[s_, c] = ((64 - w) * E0[c] + w * E1[c] + 32) >> 6
+    return out
+
+
+def bc7_texels(blocks: np.ndarray, xs, ys) -> np.ndarray:
+    """Vectorised decode of texels (xs, ys) from their selected 16-byte blocks [..., 16] -> [..., 4]."""
+    blocks = np.asarray(blocks, dtype=np.uint8)
+    lo = np.zeros(blocks.shape[:-1], dtype=np.uint64)
+    hi = np.zeros(blocks.shape[:-1], dtype=np.uint64)
+    for k in range(8):
+        lo |= blocks[..., k].astype(np.uint64) << np.uint64(8 * k)
+        hi |= blocks[..., 8 + k].astype(np.uint64) << np.uint64(8 * k)
+    v = [((lo >> np.uint64(7 + 7 * k)) & np.uint64(0x7F)).astype(np.int64) for k in range(8)]
+    p0 = ((lo >> np.uint64(63)) & np.uint64(1)).astype(np.int64)
+    p1 = (hi & np.uint64(1)).astype(np.int64)
+    slot = (4 * (np.asarray(ys) & 3) + (np.asarray(xs) & 3)).astype(np.uint64)
+    idx = np.where(slot == 0, (hi >> np.uint64(1)) & np.uint64(7), (hi >> (np.uint64(4) * slot)) & np.uint64(0xF))
+    w = np.asarray(BC7_WEIGHTS4, dtype=np.int64)[idx.astype(np.int64)]
+    out = np.stack([((64 - w) * ((v[2 * c] << 1) | p0) + w * ((v[2 * c + 1] << 1) | p1) + 32) >> 6
+                    for c in range(4)], axis=-1)
+    return out.astype(np.uint8)
+
+
+def bc7_quantise_endpoint(e4):
+    """Mode-6 endpoint of 4 channel values in [0, 1] (last axis): the p-bit and 7-bit values
+    whose 8-bit values (v << 1) | p are nearest to x = fl32(255 e) in summed squared error
+    (v = rint((x - p) / 2) clamped to 0..127; ties keep p = 0).  Returns (E [..., 4], v7, p)."""
+    x = (np.float32(255.0) * np.asarray(e4, dtype=np.float32)).astype(np.float64)
+    cand = []
+    for p in (0, 1):
+        v7 = np.clip(np.rint((x - p) / 2.0), 0, 127).astype(np.int64)
+        E = 2 * v7 + p
+        cand.append((E, v7, ((E - x) ** 2).sum(-1)))
+    take1 = cand[1][2] < cand[0][2]
+    E = np.where(take1[..., None], cand[1][0], cand[0][0])
+    v7 = np.where(take1[..., None], cand[1][1], cand[0][1])
+    return E, v7, take1.astype(np.int64)
+
+
+def quantise_weight4(w):
+    """4-bit BC7 index J = round-half-even(fl32(15 * w))."""
+    return np.rint(np.float32(15.0) * np.asarray(w, dtype=np.float32)).astype(np.int64)
+
+
+def export_bc7(endpoints: np.ndarray, weights: np.ndarray) -> np.ndarray:
+    """Encode a BC7-simulated 4-channel map ([Hb][Wb][4][2] endpoints, [H][W] weights) as mode-6
+    blocks [Hb][Wb][16].  Reading (the decode equals the simulation bit for bit): endpoints
+    quantised by bc7_quantise_endpoint, index J = quantise_weight4(w); when texel 0's index
+    has its top bit set the endpoints swap and every index becomes 15 - J (the weight table is
+    symmetric, w(15 - J) = 64 - w(J))."""
+    Hb, Wb = endpoints.shape[0], endpoints.shape[1]
+    E0, v0, p0 = bc7_quantise_endpoint(endpoints[..., 0])
+    E1, v1, p1 = bc7_quantise_endpoint(endpoints[..., 1])
+    J = quantise_weight4(weights)
+    out = np.zeros((Hb, Wb, 16), dtype=np.uint8)
+    for by in range(Hb):
+        for bx in range(Wb):
+            a, b, pa, pb = v0[by, bx], v1[by, bx], int(p0[by, bx]), int(p1[by, bx])
+            idx = [int(J[4 * by + s_ // 4, 4 * bx + s_ % 4]) for s_ in range(16)]
+            if idx[0] >= 8:
+                a, b, pa, pb = b, a, pb, pa
+                idx = [15 - j for j in idx]
+            bits = 0x40
+            for c in range(4):
+                bits |= int(a[c]) << (7 + 14 * c)
+                bits |= int(b[c]) << (14 + 14 * c)
+            bits |= pa << 63
+            bits |= pb << 64
+            bits |= idx[0] << 65
+            for i in range(1, 16):
+                bits |= idx[i] << (64 + 4 * i)
+            out[by, bx] = np.frombuffer(bits.to_bytes(16, "little"), dtype=np.uint8)
+    return out
+
+
+# --------------------------------------------------------------------------------------
 # Hybrid feature maps and the GELU decoder (Sec. 3.3, Eq. (4)-(5), Table 1, Table 3, Sec. 4)
 # --------------------------------------------------------------------------------------
 # A hybrid model holds four feature maps and a decoder:
-#   fuv  [H/4][W/4][4][8]       F_uv, W x H x 4 channels, BC4 blocks (one per channel)
+#   fuv  [H/4][W/4][4][8]       F_uv, W x H x 4 channels, BC4 blocks (one per channel), or
+#        [H/4][W/4][16]         with codec 1 one BC7 mode-6 block per footprint
 #   fuvt [S][Gv/4][Gu/4][4][8]  F_uvt, Gu x Gv x 4 channels in S time slices, each slice
-#                               block-compressed on its own (Sec. 3.4)
+#                               block-compressed on its own (Sec. 3.4); [..][16] for codec 1
 #   fut  [Tt][U][2]             F_ut, 8-bit, U x Tt x 2 channels
 #   fvt  [Tt][V][2]             F_vt, 8-bit, V x Tt x 2 channels
 #   keys [n]                    times of the baked lightmaps (n = 0: uniform time)
@@ -381,6 +489,14 @@ def bc4_texels(blocks: np.ndarray, xs, ys) -> np.ndarray:
     return bc4_palette_value(blocks[..., 0], blocks[..., 1], codes)
 
 
+def _hyb_tex(model: dict, blocks, xs, ys) -> np.ndarray:
+    """4-channel texel values / 255 of the selected footprints: BC4 per channel ([..., 4, 8]
+    bytes, codec 0) or BC7 mode 6 ([..., 16] bytes, codec 1)."""
+    if model.get("codec", 0) == 1:
+        return bc7_texels(blocks, xs, ys) / 255.0
+    return bc4_texels(blocks, xs, ys) / 255.0
+
+
 def hybrid_features(model: dict, u: np.ndarray, v: np.ndarray, t: np.ndarray) -> np.ndarray:
     """The 16 decoder inputs at (u, v, t) (Eq. (4)), float64 -> [..., 16]."""
     tc = np.clip(t, 0.0, 1.0)
@@ -395,7 +511,7 @@ def hybrid_features(model: dict, u: np.ndarray, v: np.ndarray, t: np.ndarray) ->
     for (ss, ws) in ((s0, ws0), (s1, ws1)):
         for (yy, wy) in ((y0, wy0), (y1, wy1)):
             for (xx, wx) in ((x0, wx0), (x1, wx1)):
-                tex = bc4_texels(fuvt[ss, yy >> 2, xx >> 2], xx, yy) / 255.0
+                tex = _hyb_tex(model, fuvt[ss, yy >> 2, xx >> 2], xx, yy)
                 Vuvt += (ws * wy * wx)[..., None] * tex
     # V_uv: bilinear in the W x H map
     x0, x1, wx0, wx1 = _axis(u, model["W"])
@@ -404,7 +520,7 @@ def hybrid_features(model: dict, u: np.ndarray, v: np.ndarray, t: np.ndarray) ->
     Vuv = np.zeros(np.shape(u) + (4,))
     for (yy, wy) in ((y0, wy0), (y1, wy1)):
         for (xx, wx) in ((x0, wx0), (x1, wx1)):
-            Vuv += (wy * wx)[..., None] * (bc4_texels(fuv[yy >> 2, xx >> 2], xx, yy) / 255.0)
+            Vuv += (wy * wx)[..., None] * _hyb_tex(model, fuv[yy >> 2, xx >> 2], xx, yy)
     # V_ut, V_vt: bilinear on the (u, t) and (v, t) planes
     k0, k1, wk0, wk1 = _node_axis(tau, model["Tt"])
     planes = []
@@ -710,15 +826,26 @@ def hybrid_noise(seed: int, step: int, s, c) -> np.ndarray:
     return top / float(1 << 24) - 0.5
 
 
-def _bc_texels(ep, wt, sl, ys, xs, bcsim: bool):
+def _bc_texels(ep, wt, sl, ys, xs, bcsim: bool, codec: int = 0):
     """4-channel texels of a BC-simulated map at (ys, xs) (and slice sl, or None):
-    (value in [0, 1], d/de1, d/de2, d/dw) per channel."""
+    (value in [0, 1], d/de1, d/de2, d/dw) per channel.  codec 0: one weight per channel
+    (BC4 per channel); codec 1: one weight per texel shared by the 4 channels (BC7 mode 6,
+    Eq. (6)), whose gradient is the sum over channels of dw."""
     if sl is None:
         e = ep[ys >> 2, xs >> 2]            # [..., 4, 2]
-        w = wt[ys, xs]                      # [..., 4]
+        w = wt[ys, xs]                      # [..., 4] or [...]
     else:
         e = ep[sl, ys >> 2, xs >> 2]
         w = wt[sl, ys, xs]
+    if codec == 1:
+        w = np.repeat(np.asarray(w)[..., None], 4, axis=-1)
+        if bcsim:
+            E1 = bc7_quantise_endpoint(e[..., 0])[0].astype(np.float64)
+            E2 = bc7_quantise_endpoint(e[..., 1])[0].astype(np.float64)
+            J = quantise_weight4(w)
+            wj = np.asarray(BC7_WEIGHTS4, dtype=np.int64)[J].astype(np.float64)
+            val = np.floor(((64 - wj) * E1 + wj * E2 + 32) / 64) / 255.0
+            return val, 1.0 - wj / 64.0, wj / 64.0, (E2 - E1) / 255.0
     if bcsim:
         E1 = quantise_endpoint(e[..., 0]).astype(np.float64)
         E2 = quantise_endpoint(e[..., 1]).astype(np.float64)
@@ -744,6 +871,7 @@ def hybrid_train_forward(state: dict, xs, ys, fs, flags: int, seed: int = 0, ste
     keys = np.asarray(d["keys"], dtype=np.float64)
     t = keys[fs] if keys.size else tau
     bc = bool(flags & HT_BCSIM)
+    codec = d.get("codec", 0)
     u = (xs + 0.5) / d["W"]
     v = (ys + 0.5) / d["H"]
     taps = {}
@@ -756,12 +884,12 @@ def hybrid_train_forward(state: dict, xs, ys, fs, flags: int, seed: int = 0, ste
     for (ss, ws) in ((s0, ws0), (s1, ws1)):
         for (yy, wy) in ((gy0, wy0), (gy1, wy1)):
             for (xx, wx) in ((gx0, wx0), (gx1, wx1)):
-                val, d1, d2, dw = _bc_texels(state["fuvt_ep"], state["fuvt_w"], ss, yy, xx, bc)
+                val, d1, d2, dw = _bc_texels(state["fuvt_ep"], state["fuvt_w"], ss, yy, xx, bc, codec)
                 w = ws * wy * wx
                 Vuvt += w[..., None] * val
                 taps["uvt"].append((ss, yy, xx, w, d1, d2, dw))
     # V_uv: the texel itself
-    val, d1, d2, dw = _bc_texels(state["fuv_ep"], state["fuv_w"], None, ys, xs, bc)
+    val, d1, d2, dw = _bc_texels(state["fuv_ep"], state["fuv_w"], None, ys, xs, bc, codec)
     Vuv = val
     taps["uv"] = (d1, d2, dw)
     # planes
@@ -809,6 +937,7 @@ def hybrid_train_grads(state: dict, xs, ys, fs, target, flags: int, seed: int = 
     With several models trained together the mean runs over all n_total samples of the
     batch; this model's samples start at position s_offset."""
     d = state["dims"]
+    codec = d.get("codec", 0)
     out, c = hybrid_train_forward(state, xs, ys, fs, flags, seed, step, need_cache=True, s_offset=s_offset)
     target = np.asarray(target, dtype=np.float64)
     n = out.size if n_total is None else 3 * n_total
@@ -831,12 +960,18 @@ def hybrid_train_grads(state: dict, xs, ys, fs, target, flags: int, seed: int = 
         sl, by, bx = ss[:, None], (yy >> 2)[:, None], (xx >> 2)[:, None]
         np.add.at(g["fuvt_ep"], (sl, by, bx, ch, 0), dv * d1)
         np.add.at(g["fuvt_ep"], (sl, by, bx, ch, 1), dv * d2)
-        np.add.at(g["fuvt_w"], (sl, yy[:, None], xx[:, None], ch), dv * dw)
+        if codec == 1:
+            np.add.at(g["fuvt_w"], (ss, yy, xx), (dv * dw).sum(-1))
+        else:
+            np.add.at(g["fuvt_w"], (sl, yy[:, None], xx[:, None], ch), dv * dw)
     d1, d2, dw = c["taps"]["uv"]
     dv = dx[:, 4:8]
     np.add.at(g["fuv_ep"], ((ys >> 2)[:, None], (xs >> 2)[:, None], ch, 0), dv * d1)
     np.add.at(g["fuv_ep"], ((ys >> 2)[:, None], (xs >> 2)[:, None], ch, 1), dv * d2)
-    np.add.at(g["fuv_w"], (ys[:, None], xs[:, None], ch), dv * dw)
+    if codec == 1:
+        np.add.at(g["fuv_w"], (ys, xs), (dv * dw).sum(-1))
+    else:
+        np.add.at(g["fuv_w"], (ys[:, None], xs[:, None], ch), dv * dw)
     for pi, key in enumerate(("fut", "fvt")):
         dv = dx[:, 8 + 2 * pi: 10 + 2 * pi]
         for (kk, aa, w) in c["taps"]["planes"][pi]:
@@ -880,10 +1015,12 @@ def hybrid_export(state: dict) -> dict:
     """Decodable hybrid model of a trained state: BC4 blocks of F_uv and of each F_uvt
     slice (export_bc4), planes rounded to 8 bits (rint of the float32 product 255 v)."""
     d = state["dims"]
-    fuvt = np.stack([export_bc4(state["fuvt_ep"][s], state["fuvt_w"][s]) for s in range(d["S"])])
+    codec = d.get("codec", 0)
+    enc = export_bc7 if codec == 1 else export_bc4
+    fuvt = np.stack([enc(state["fuvt_ep"][s], state["fuvt_w"][s]) for s in range(d["S"])])
     q = lambda a: np.rint(np.float32(255.0) * np.asarray(a, dtype=np.float32)).astype(np.uint8)
     return dict(W=d["W"], H=d["H"], Gu=d["Gu"], Gv=d["Gv"], S=d["S"], U=d["U"], V=d["V"], Tt=d["Tt"],
-                hidden=d["hidden"], fuv=export_bc4(state["fuv_ep"], state["fuv_w"]), fuvt=fuvt,
+                hidden=d["hidden"], codec=codec, fuv=enc(state["fuv_ep"], state["fuv_w"]), fuvt=fuvt,
                 fut=q(state["fut"]), fvt=q(state["fvt"]), keys=np.asarray(d["keys"], dtype=np.float32),
                 mlp=np.asarray(state["mlp"], dtype=np.float32))
 

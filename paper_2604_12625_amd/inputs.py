@@ -106,23 +106,37 @@ def lightmap_key_times(g: np.random.Generator, hourly: int = 24, extra: int = 2)
     return np.sort(np.concatenate([np.arange(hourly) / hourly, extras])).astype(np.float32)
 
 
+def random_bc7m6(shape, g: np.random.Generator) -> np.ndarray:
+    """Random BC7 mode-6 blocks [*shape][16]: uniform bytes with the mode bits set (bits 0..6
+    of byte 0 = 1000000b; bit 7 belongs to the first endpoint value)."""
+    b = g.integers(0, 256, size=tuple(shape) + (16,), dtype=np.uint8)
+    b[..., 0] = (b[..., 0] & 0x80) | 0x40
+    return b
+
+
 def random_hybrid_model(W: int = 128, H: int = 128, profile: str = "M", slices: int = 12,
                         plane=(64, 64, 24), mlp_dtype=np.float16, keys: bool = True,
-                        config: int = 0, index: int = 0, uvt_side=None) -> dict:
+                        config: int = 0, index: int = 0, uvt_side=None, codec: int = 0) -> dict:
     """A hybrid model with uniformly random block bytes and 8-bit planes.
 
     ``plane`` = (U, V, Tt): F_ut is [Tt][U][2] and F_vt is [Tt][V][2] (uint8);
-    F_uv is [H/4][W/4][4][8] and F_uvt is [S][Gv/4][Gu/4][4][8] BC4 bytes.  ``keys``
-    attaches a non-uniform key-time table (:func:`lightmap_key_times`)."""
+    F_uv is [H/4][W/4][4][8] and F_uvt is [S][Gv/4][Gu/4][4][8] BC4 bytes (codec 0), or
+    one 16-byte BC7 mode-6 block per footprint (codec 1).  ``keys`` attaches a non-uniform
+    key-time table (:func:`lightmap_key_times`)."""
     side, hidden = HYBRID_PROFILES[profile]
     Gu, Gv = (side, side) if uvt_side is None else uvt_side
     U, V, Tt = plane
     g = rng(config, P_MODEL, index)
     assert W % 4 == 0 and H % 4 == 0 and Gu % 4 == 0 and Gv % 4 == 0
+
+    def blocks(shape):
+        return random_bc7m6(shape, g) if codec == 1 else g.integers(0, 256, size=tuple(shape) + (4, 8),
+                                                                       dtype=np.uint8)
+
     return dict(
-        W=W, H=H, Gu=Gu, Gv=Gv, S=slices, U=U, V=V, Tt=Tt, hidden=hidden,
-        fuv=g.integers(0, 256, size=(H // 4, W // 4, 4, 8), dtype=np.uint8),
-        fuvt=g.integers(0, 256, size=(slices, Gv // 4, Gu // 4, 4, 8), dtype=np.uint8),
+        W=W, H=H, Gu=Gu, Gv=Gv, S=slices, U=U, V=V, Tt=Tt, hidden=hidden, codec=codec,
+        fuv=blocks((H // 4, W // 4)),
+        fuvt=blocks((slices, Gv // 4, Gu // 4)),
         fut=g.integers(0, 256, size=(Tt, U, 2), dtype=np.uint8),
         fvt=g.integers(0, 256, size=(Tt, V, 2), dtype=np.uint8),
         keys=lightmap_key_times(g) if keys else np.zeros(0, np.float32),
@@ -131,7 +145,7 @@ def random_hybrid_model(W: int = 128, H: int = 128, profile: str = "M", slices: 
 
 
 def hybrid_train_init(W: int, H: int, profile: str, frames: int, keys, g: np.random.Generator,
-                      slices: int = 12, plane=(64, 64, 24)) -> dict:
+                      slices: int = 12, plane=(64, 64, 24), codec: int = 0) -> dict:
     """Initial trainable hybrid state (float32): endpoints e1 ~ U[0, 0.5), e2 ~ U[0.5, 1],
     weights and planes ~ U[0, 1], He-normal decoder with zero biases except b3 = 1 (the
     normalised target has mean 1 in every channel)."""
@@ -147,11 +161,12 @@ def hybrid_train_init(W: int, H: int, profile: str, frames: int, keys, g: np.ran
     mlp[o1:o1 + hidden] = 0.0
     mlp[o2:o2 + hidden] = 0.0
     mlp[-3:] = 1.0                              # b3
+    cw = () if codec == 1 else (4,)     # one weight per texel (BC7) or per texel and channel (BC4)
     return dict(dims=dict(W=W, H=H, Gu=side, Gv=side, S=slices, U=U, V=V, Tt=Tt, hidden=hidden, frames=frames,
-                          keys=np.asarray(keys, dtype=np.float32)),
-                fuv_ep=ep((H // 4, W // 4, 4)), fuv_w=g.uniform(0, 1, (H, W, 4)).astype(np.float32),
+                          keys=np.asarray(keys, dtype=np.float32), codec=codec),
+                fuv_ep=ep((H // 4, W // 4, 4)), fuv_w=g.uniform(0, 1, (H, W) + cw).astype(np.float32),
                 fuvt_ep=ep((slices, side // 4, side // 4, 4)),
-                fuvt_w=g.uniform(0, 1, (slices, side, side, 4)).astype(np.float32),
+                fuvt_w=g.uniform(0, 1, (slices, side, side) + cw).astype(np.float32),
                 fut=g.uniform(0, 1, (Tt, U, 2)).astype(np.float32), fvt=g.uniform(0, 1, (Tt, V, 2)).astype(np.float32),
                 mlp=mlp)
 

@@ -288,3 +288,101 @@ def test_target_normalisation_closed_form():
     np.testing.assert_allclose(means[0], 2.0 ** (1 / 2.2), rtol=1e-15)
     np.testing.assert_allclose(means[1], [0.5 ** (1 / 2.2), 0.5 ** (1 / 2.2), 8.0 ** (1 / 2.2)], rtol=1e-15)
     np.testing.assert_allclose(O.hybrid_restore(y[1, 0, 0], means[1], 2.2), [0.5, 0.5, 8.0], rtol=1e-14)
+
+
+# ------------------------------------------------------------------------ BC7 mode 6
+def _golden_bc7():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "bc7_mode6_blocks.txt")):
+        if line.strip() and not line.startswith("#"):
+            a, b = line.split("|")
+            vals = np.array([int(x) for x in b.split()], dtype=np.uint8).reshape(4, 16).T   # [texel][channel]
+            rows.append((np.array([int(h, 16) for h in a.split()], dtype=np.uint8), vals))
+    return rows
+
+
+def test_bc7_golden_blocks():
+    rows = _golden_bc7()
+    assert len(rows) == 3
+    ys, xs = np.meshgrid(np.arange(4), np.arange(4), indexing="ij")
+    for blk, want in rows:
+        np.testing.assert_array_equal(O.bc7m6_decode_block(blk), want)
+        got = O.bc7_texels(np.repeat(blk[None], 16, 0), xs.ravel(), ys.ravel())
+        np.testing.assert_array_equal(got, want)
+
+
+def test_bc7_equal_endpoints_and_symmetric_weights():
+    g = np.random.default_rng(30)
+    for _ in range(200):
+        blk = I.random_bc7m6((), g)
+        E0, E1, idx = O.bc7m6_fields(blk)
+        dec = O.bc7m6_decode_block(blk)
+        # weights are symmetric: swapping the endpoints and replacing index j by 15 - j leaves
+        # every texel unchanged (the reading the export's anchor rule relies on)
+        for s_ in range(16):
+            w, w2 = O.BC7_WEIGHTS4[idx[s_]], O.BC7_WEIGHTS4[15 - idx[s_]]
+            assert w + w2 == 64
+            for c in range(4):
+                assert dec[s_, c] == ((64 - w2) * E1[c] + w2 * E0[c] + 32) >> 6
+                lo, hi = min(E0[c], E1[c]), max(E0[c], E1[c])
+                assert lo <= dec[s_, c] <= hi
+
+
+def test_bc7_export_decodes_to_the_simulation():
+    g = np.random.default_rng(31)
+    ep = g.uniform(0, 1, (3, 5, 4, 2))
+    w = g.uniform(0, 1, (12, 20))
+    w[0, 0] = 0.99          # anchor index >= 8 in block (0, 0): the export swaps
+    w[4, 4] = 0.01
+    blocks = O.export_bc7(ep, w)
+    E1 = O.bc7_quantise_endpoint(ep[..., 0])[0]
+    E2 = O.bc7_quantise_endpoint(ep[..., 1])[0]
+    J = O.quantise_weight4(w)
+    for by in range(3):
+        for bx in range(5):
+            dec = O.bc7m6_decode_block(blocks[by, bx])
+            for s_ in range(16):
+                y, x = 4 * by + s_ // 4, 4 * bx + s_ % 4
+                wj = O.BC7_WEIGHTS4[J[y, x]]
+                want = ((64 - wj) * E1[by, bx] + wj * E2[by, bx] + 32) >> 6
+                np.testing.assert_array_equal(dec[s_], want)
+    assert O.bc7m6_fields(blocks[0, 0])[2][0] < 8
+
+
+def test_bc7_pbit_quantisation():
+    # all four channels sit on odd 8-bit values: p = 1 reproduces them exactly
+    e = np.array([[13, 201, 77, 255]]) / 255.0
+    E, v7, p = O.bc7_quantise_endpoint(e)
+    assert p[0] == 1 and list(E[0]) == [13, 201, 77, 255]
+    e = np.array([[12, 200, 76, 254]]) / 255.0
+    E, v7, p = O.bc7_quantise_endpoint(e)
+    assert p[0] == 0 and list(E[0]) == [12, 200, 76, 254]
+    # mixed parities: every channel within 1 of its target
+    g = np.random.default_rng(32)
+    e = g.uniform(0, 1, (1000, 4))
+    E, v7, p = O.bc7_quantise_endpoint(e)
+    assert np.all(np.abs(E - np.float32(255) * e.astype(np.float32)) <= 1.0 + 1e-6)
+    assert np.all(E == 2 * v7 + p[:, None])
+
+
+def test_bc7_hybrid_gradients_and_export():
+    st = tiny_hybrid_state(16, seed=33)
+    st["dims"] = dict(st["dims"], codec=1)
+    g = np.random.default_rng(34)
+    st["fuv_w"] = g.uniform(0, 1, st["fuv_w"].shape[:2])
+    st["fuvt_w"] = g.uniform(0, 1, st["fuvt_w"].shape[:3])
+    xs, ys, fs, tgt = _batch(st, 40, seed=35)
+    _fd_check(st, xs, ys, fs, tgt, O.HT_NOISE, O.HYB_KEYS)
+    _fd_check(st, xs, ys, fs, tgt, O.HT_BCSIM | O.HT_NOISE, ("mlp", "fut", "fvt"))
+    for k in ("fut", "fvt"):
+        st[k] = np.asarray(st[k], dtype=np.float32).astype(np.float64)
+    m = O.hybrid_export(st)
+    assert m["fuv"].shape == (2, 2, 16) and m["codec"] == 1
+    d = st["dims"]
+    y, x = np.meshgrid(np.arange(d["H"]), np.arange(d["W"]), indexing="ij")
+    for f in range(d["frames"]):
+        n = x.size
+        fwd = O.hybrid_train_forward(st, x.ravel(), y.ravel(), np.full(n, f), O.HT_BCSIM | O.HT_QPLANES)
+        dec = O.hybrid_decode_f64(m, (x.ravel() + 0.5) / d["W"], (y.ravel() + 0.5) / d["H"],
+                                  np.full(n, np.float64(d["keys"][f])))
+        np.testing.assert_allclose(dec, fwd, rtol=0, atol=1e-12)
