@@ -257,10 +257,10 @@ int ndgi_export(ndgi_ctx* ctx, const ndgi_train_state* state, uint8_t* bc4_out,
 
 /* The paper's own feature layout (Sec. 3.3, Eq. 4-5; Table 1; Table 3), decoded by its
  * GELU decoder (Sec. 4).  Four feature maps per model:
- *   F_uv   W x H texels, 4 channels, one BC4 block per 4x4 footprint and channel
- *          ([H/4][W/4][4][8 bytes], 32 bytes per footprint)
+ *   F_uv   W x H texels, 4 channels, block-compressed per 4x4 footprint (codec below:
+ *          [H/4][W/4][4][8 bytes] BC4 or [H/4][W/4][16 bytes] BC7 mode 6)
  *   F_uvt  Gu x Gv texels x S time slices, 4 channels, each slice block-compressed on its
- *          own (Sec. 3.4): [S][Gv/4][Gu/4][4][8 bytes]
+ *          own (Sec. 3.4): [S][Gv/4][Gu/4] footprints as for F_uv
  *   F_ut   U x Tt texels, 2 channels, 8-bit: [Tt][U][2] bytes
  *   F_vt   V x Tt texels, 2 channels, 8-bit: [Tt][V][2] bytes
  * and a decoder 16 -> hidden -> hidden -> 3 (hidden 16 or 64; GELU x*Phi(x) on the hidden
@@ -279,6 +279,14 @@ int ndgi_export(ndgi_ctx* ctx, const ndgi_train_state* state, uint8_t* bc4_out,
  * 96 bytes, the same layout on host and device. */
 #define NDGI_HYBRID_IN 16
 #define NDGI_HYBRID_MAX_KEYS 256
+/* Block formats of F_uv and F_uvt:
+ *   NDGI_CODEC_BC4  one BC4 block per channel (8 bytes per 4x4 footprint and channel: a weight
+ *                   per texel and channel), 16 bits per texel for the 4 channels;
+ *   NDGI_CODEC_BC7  one BC7 mode-6 block per footprint (16 bytes: 7-bit RGBA endpoints with a
+ *                   p-bit each, one 4-bit index per texel shared by the 4 channels, as Eq. 6
+ *                   writes the simulation), 8 bits per texel - the rate of the paper's Table 3. */
+#define NDGI_CODEC_BC4 0
+#define NDGI_CODEC_BC7 1
 
 typedef struct ndgi_hybrid_model {
     int32_t W, H;         /* F_uv size; multiples of 4, 4..16384                          */
@@ -289,9 +297,9 @@ typedef struct ndgi_hybrid_model {
     int32_t hidden;       /* decoder width: 16 or 64                                      */
     int32_t mlp_dtype;    /* NDGI_DTYPE_F32 or NDGI_DTYPE_F16                             */
     int32_t n_keys;       /* 0, or 2..NDGI_HYBRID_MAX_KEYS key times                      */
-    int32_t reserved0;    /* must be 0                                                    */
-    const uint8_t* fuv;   /* device [H/4][W/4][4][8]                                      */
-    const uint8_t* fuvt;  /* device [S][Gv/4][Gu/4][4][8]                                 */
+    int32_t codec;        /* NDGI_CODEC_BC4 or NDGI_CODEC_BC7 (block format of F_uv, F_uvt) */
+    const uint8_t* fuv;   /* device [H/4][W/4][4][8] (BC4) or [H/4][W/4][16] (BC7)        */
+    const uint8_t* fuvt;  /* device [S][Gv/4][Gu/4][4][8] (BC4) or [S][Gv/4][Gu/4][16]   */
     const uint8_t* fut;   /* device [Tt][U][2]                                            */
     const uint8_t* fvt;   /* device [Tt][V][2]                                            */
     const float* keys;    /* device [n_keys], strictly increasing in [0, 1] (the caller
@@ -339,7 +347,8 @@ int ndgi_hybrid_decode_pages_graph(ndgi_ctx* ctx, const ndgi_hybrid_model* model
  *   [ F_uv endpoints [H/4][W/4][4][2] | F_uv weights [H][W][4]
  *   | F_uvt endpoints [S][Gv/4][Gu/4][4][2] | F_uvt weights [S][Gv][Gu][4]
  *   | F_ut [Tt][U][2] | F_vt [Tt][V][2] ]
- * and the decoder block [ndgi_hybrid_mlp_size(hidden)]; params, grads, adam_m and adam_v
+ * (weights [H][W] and [S][Gv][Gu] with codec NDGI_CODEC_BC7) and the decoder block
+ * [ndgi_hybrid_mlp_size(hidden)]; params, grads, adam_m and adam_v
  * hold all feature blocks, model after model, then all decoder blocks:
  * n_models * ndgi_hybrid_train_param_count values.  Sizes as ndgi_hybrid_model, with W, H
  * <= 4096.  A training sample is texel (x, y) of baked frame f: t = keys[f] (keys given) or
@@ -351,6 +360,9 @@ typedef struct ndgi_hybrid_train_state {
     int32_t n_models;         /* models trained together (one per tile), >= 1             */
     int32_t per_model;        /* samples per model in a batch; with n_models > 1 a multiple
                                  of 64 and n = n_models * per_model (ignored for 1 model)  */
+    int32_t codec;            /* NDGI_CODEC_BC4: a weight per texel and channel;
+                                 NDGI_CODEC_BC7: one weight per texel (Eq. 6)             */
+    int32_t reserved0;        /* must be 0                                                */
     const float* keys;        /* device [frames] frame times, or NULL (uniform)           */
     float* params;
     float* grads;
@@ -374,6 +386,10 @@ typedef struct ndgi_hybrid_batch {
  *   BCSIM   F_uv and F_uvt under BC simulation: E = rint(fl32(255 e)), J = rint(fl32(7 w)),
  *           value floor(((7-J) E1 + J E2 + 3)/7) / 255, straight-through gradient of Eq. 7
  *           at (E/255, J/7); without it the plain Eq. 7 lerp (the simulation's ablation).
+ *           With codec NDGI_CODEC_BC7 each endpoint takes the mode-6 7-bit values and p-bit
+ *           E = 2 v + p nearest to fl32(255 e) in summed squared error (v = rint((x - p)/2)
+ *           clamped to 0..127, ties p = 0), J = rint(fl32(15 w)), weight wt = (64 J + 7)/15,
+ *           value ((64 - wt) E1 + wt E2 + 32) >> 6 / 255, gradient at (E/255, wt/64).
  *   NOISE   U(-1/2, 1/2) / 256 added to each of the 12 sampled map values (Eq. 8); draw c of
  *           sample s in a step is the SplitMix64 output of seed * 0x9E3779B97F4A7C15 +
  *           step * 2^32 + 16 s + c, top 24 bits / 2^24 - 1/2.
@@ -385,7 +401,7 @@ typedef struct ndgi_hybrid_batch {
 
 /* Float parameters of one model of a hybrid state; -1 for sizes out of range. */
 int64_t ndgi_hybrid_train_param_count(int32_t W, int32_t H, int32_t Gu, int32_t Gv, int32_t S, int32_t U,
-                                      int32_t V, int32_t Tt, int32_t hidden);
+                                      int32_t V, int32_t Tt, int32_t hidden, int32_t codec);
 
 /* One hybrid training operation: mode NDGI_TRAIN_FORWARD (pred), NDGI_TRAIN_LOSS_GRAD
  * (*loss_dev = mean over samples and channels of (pred - target)^2, FP64; grads +=), FUSED
@@ -395,9 +411,10 @@ int ndgi_hybrid_train_step(ndgi_ctx* ctx, ndgi_hybrid_train_state* state, const 
                            int32_t mode, int32_t flags, double* loss_dev, hipStream_t stream);
 
 /* Export model `model` of a trained state as a decodable hybrid model (Sec. 3.4 last
- * paragraph): BC4 blocks of
- * F_uv ([H/4][W/4][4][8]) and of every F_uvt slice ([S][Gv/4][Gu/4][4][8]) in the encoding of
- * ndgi_export, planes rounded to 8 bits (rint of fl32(255 v)), decoder converted to
+ * paragraph): blocks of F_uv and of every F_uvt slice in the state's codec (BC4:
+ * [H/4][W/4][4][8] and [S][Gv/4][Gu/4][4][8] in the encoding of ndgi_export; BC7 mode 6:
+ * [H/4][W/4][16] and [S][Gv/4][Gu/4][16], endpoints and indices of the simulation, the
+ * endpoints swapped and every index J replaced by 15 - J when texel 0's would be >= 8), planes rounded to 8 bits (rint of fl32(255 v)), decoder converted to
  * mlp_dtype.  The decode of the export at a training sample equals the FORWARD with
  * BCSIM | QPLANES.  Errors: INVALID_ARG. */
 int ndgi_hybrid_export(ndgi_ctx* ctx, const ndgi_hybrid_train_state* state, int32_t model,

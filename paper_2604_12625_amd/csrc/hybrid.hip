@@ -1,5 +1,6 @@
 // Decode of the paper's hybrid layout (Sec. 3.3, Eq. 4-5): F_uvt (4 channels in time
-// slices, BC4 per slice), F_uv (4 channels, BC4), F_ut and F_vt (2 channels each, 8-bit)
+// slices, each slice block-compressed), F_uv (4 channels, block-compressed: BC4 per channel
+// or BC7 mode 6), F_ut and F_vt (2 channels each, 8-bit)
 // and gamma(t) feed a 16 -> h -> h -> 3 decoder with GELU hidden layers and a linear
 // output (Sec. 4), h = 16 or 64.
 //
@@ -216,17 +217,42 @@ __device__ __forceinline__ void bc4_fp4_regs(const u4v& a, const u4v& b, uint32_
   v[3] = bc4_texel_f(b.z, b.w, slot);
 }
 
+// Four channels of texel `slot` of a BC7 mode-6 block (b = the 16 bytes as a 128-bit
+// little-endian value): 7-bit endpoint values R0 R1 G0 G1 B0 B1 A0 A1 at bits 7..62, p-bits
+// at 63 and 64, texel 0's 3-bit index at 65..67 and texel i's 4-bit index at 64 + 4 i;
+// endpoint (v << 1) | p, texel ((64 - w) E0 + w E1 + 32) >> 6.  The weight is
+// (64 J + 7) / 15, which equals the format's 4-bit weight table at every index J.
+__device__ __forceinline__ void bc7_fp4_regs(const u4v& b, uint32_t slot, float v[4]) {
+  const uint64_t lo = ((uint64_t)b.y << 32) | b.x, hi = ((uint64_t)b.w << 32) | b.z;
+  const uint32_t p0 = (uint32_t)(lo >> 63), p1 = (uint32_t)hi & 1u;
+  const uint32_t j = slot ? (uint32_t)(hi >> (4u * slot)) & 15u : (uint32_t)(hi >> 1) & 7u;
+  const uint32_t w = (64u * j + 7u) / 15u;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const uint32_t e0 = (((uint32_t)(lo >> (7 + 14 * c)) & 127u) << 1) | p0;
+    const uint32_t e1 = (((uint32_t)(lo >> (14 + 14 * c)) & 127u) << 1) | p1;
+    v[c] = (float)(((64u - w) * e0 + w * e1 + 32u) >> 6);
+  }
+}
+
+// Four channels (0..255) of texel `slot` of a footprint: 32 bytes of BC4 (codec 0) or one
+// 16-byte BC7 mode-6 block (codec 1).
+__device__ __forceinline__ void fp4(const uint8_t* fp, int codec, uint32_t slot, float v[4]) {
+  if (codec) bc7_fp4_regs(*(const u4v*)fp, slot, v);
+  else bc4_fp4(fp, slot, v);
+}
+
 // Bilinear sample (4 channels, values / 255) of a block-compressed map of bw footprints per
-// row starting at `base`, accumulated into x with weight ws.
-__device__ __forceinline__ void bc4_bilinear4(const uint8_t* base, uint32_t bw, const Axis& ax, const Axis& ay,
-                                              float ws, float x[4]) {
+// row starting at `base` (fpb bytes per footprint), accumulated into x with weight ws.
+__device__ __forceinline__ void bc_bilinear4(const uint8_t* base, uint32_t bw, uint32_t fpb, int codec,
+                                             const Axis& ax, const Axis& ay, float ws, float x[4]) {
   float w[4];
   tap_weights(ax, ay, w);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const uint32_t y = (uint32_t)((i & 2) ? ay.i1 : ay.i0), xx = (uint32_t)((i & 1) ? ax.i1 : ax.i0);
     float v[4];
-    bc4_fp4(base + ((y >> 2) * bw + (xx >> 2)) * 32u, 4u * (y & 3u) + (xx & 3u), v);
+    fp4(base + ((y >> 2) * bw + (xx >> 2)) * fpb, codec, 4u * (y & 3u) + (xx & 3u), v);
     const float wi = ws * w[i] * (1.0f / 255.0f);
 #pragma unroll
     for (int c = 0; c < 4; ++c) x[c] = fmaf(wi, v[c], x[c]);
@@ -252,16 +278,19 @@ __device__ __forceinline__ void plane2(const uint8_t* p, int size, const Axis& a
   }
 }
 
-// The 16 decoder inputs of an explicit query, as four chunks.
+// The 16 decoder inputs of an explicit query, as four chunks (CD: the codec, fixed per
+// launch so that each instance carries one block decoder).
+template <int CD>
 __device__ __forceinline__ void hyb_query_feats(const ndgi_hybrid_model& m, float u, float v, const HybTime& ht,
                                                 float r[4][4]) {
 #pragma unroll
   for (int c = 0; c < 4; ++c) r[0][c] = r[1][c] = 0.0f;
   const Axis gx = coord_axis(u, m.Gu), gy = coord_axis(v, m.Gv);
-  const uint32_t gbw = (uint32_t)m.Gu >> 2, slice = gbw * ((uint32_t)m.Gv >> 2) * 32u;
-  bc4_bilinear4(m.fuvt + (uint32_t)ht.s.i0 * slice, gbw, gx, gy, ht.s.w0, r[0]);
-  bc4_bilinear4(m.fuvt + (uint32_t)ht.s.i1 * slice, gbw, gx, gy, ht.s.w1, r[0]);
-  bc4_bilinear4(m.fuv, (uint32_t)m.W >> 2, coord_axis(u, m.W), coord_axis(v, m.H), 1.0f, r[1]);
+  constexpr uint32_t fpb = CD ? 16u : 32u;
+  const uint32_t gbw = (uint32_t)m.Gu >> 2, slice = gbw * ((uint32_t)m.Gv >> 2) * fpb;
+  bc_bilinear4(m.fuvt + (uint32_t)ht.s.i0 * slice, gbw, fpb, CD, gx, gy, ht.s.w0, r[0]);
+  bc_bilinear4(m.fuvt + (uint32_t)ht.s.i1 * slice, gbw, fpb, CD, gx, gy, ht.s.w1, r[0]);
+  bc_bilinear4(m.fuv, (uint32_t)m.W >> 2, fpb, CD, coord_axis(u, m.W), coord_axis(v, m.H), 1.0f, r[1]);
   plane2(m.fut, m.U, coord_axis(u, m.U), ht.k, r[2][0], r[2][1]);
   plane2(m.fvt, m.V, coord_axis(v, m.V), ht.k, r[2][2], r[2][3]);
 #pragma unroll
@@ -276,9 +305,10 @@ __host__ __device__ inline bool hybrid_ok(const ndgi_hybrid_model& m) {
                     m.Tt <= 1024;
   const bool kinds = (m.hidden == 16 || m.hidden == 64) &&
                      (m.mlp_dtype == NDGI_DTYPE_F32 || m.mlp_dtype == NDGI_DTYPE_F16) &&
-                     (m.n_keys == 0 || (m.n_keys >= 2 && m.n_keys <= NDGI_HYBRID_MAX_KEYS)) && m.reserved0 == 0;
+                     (m.n_keys == 0 || (m.n_keys >= 2 && m.n_keys <= NDGI_HYBRID_MAX_KEYS)) &&
+                     (m.codec == NDGI_CODEC_BC4 || m.codec == NDGI_CODEC_BC7);
   const bool bufs = m.fuv && m.fuvt && m.fut && m.fvt && m.mlp && (m.n_keys == 0 || m.keys);
-  // F_uvt offsets are 32-bit: S * Gu * Gv * 2 bytes below 4 GiB
+  // F_uvt offsets are 32-bit: S * Gu * Gv * (2 or 1) bytes below 4 GiB
   return dims && kinds && bufs && (uint64_t)m.S * (uint64_t)m.Gu * (uint64_t)m.Gv * 2u < (1ull << 32);
 }
 
@@ -286,7 +316,7 @@ __host__ __device__ inline bool hybrid_ok(const ndgi_hybrid_model& m) {
 // Grid-stride passes of 64 consecutive queries per wave (one query per lane in the feature
 // phase, the decoder after the handoff); the decoder table and the key table are built
 // once per workgroup in LDS.
-template <int PREC, int HD>
+template <int PREC, int HD, int CD>
 __global__ __launch_bounds__(256) void k_hybrid_query(ndgi_hybrid_model m, const float* __restrict__ uvt, int64_t n,
                                                        void* __restrict__ out) {
   __shared__ HybTab<HD> tab;
@@ -305,7 +335,7 @@ __global__ __launch_bounds__(256) void k_hybrid_query(ndgi_hybrid_model m, const
     if (bad) u = v = t = 0.0f;
     const HybTime ht = hyb_time(m, t, [&](int i) { return keys[i]; });
     float r[4][4];
-    hyb_query_feats(m, u, v, ht, r);
+    hyb_query_feats<CD>(m, u, v, ht, r);
     const f4v acc = hyb_decode<PREC, HD>(tab, r, lane);
     if (mine < n) store_lin<PREC>(out, (size_t)mine, acc, bad);
   }
@@ -378,15 +408,16 @@ __global__ __launch_bounds__(256) void k_hybrid_pages(const ndgi_hybrid_model* _
     const int nua = min(texel_axis<false>(x0 + kHybSub - 1, m.U, m.W).i1 - ua0 + 1, kHybWin);
     const int nva = min(texel_axis<false>(y0 + kHybSub - 1, m.V, m.H).i1 - va0 + 1, kHybWin);
     {
-      const uint32_t gbw = (uint32_t)m.Gu >> 2, slice = gbw * ((uint32_t)m.Gv >> 2) * 32u;
+      const uint32_t fpb = m.codec ? 16u : 32u;
+      const uint32_t gbw = (uint32_t)m.Gu >> 2, slice = gbw * ((uint32_t)m.Gv >> 2) * fpb;
       const uint8_t* s0 = m.fuvt + (uint32_t)ht.s.i0 * slice;
       const uint8_t* s1 = m.fuvt + (uint32_t)ht.s.i1 * slice;
       for (int idx = threadIdx.x; idx < nwx * nwy; idx += 256) {
         const uint32_t gy = (uint32_t)(wy0 + idx / nwx), gx = (uint32_t)(wx0 + idx % nwx);
-        const uint32_t off = ((gy >> 2) * gbw + (gx >> 2)) * 32u, slot = 4u * (gy & 3u) + (gx & 3u);
+        const uint32_t off = ((gy >> 2) * gbw + (gx >> 2)) * fpb, slot = 4u * (gy & 3u) + (gx & 3u);
         float a[4], b[4];
-        bc4_fp4(s0 + off, slot, a);
-        bc4_fp4(s1 + off, slot, b);
+        fp4(s0 + off, m.codec, slot, a);
+        fp4(s1 + off, m.codec, slot, b);
         f4v o;
 #pragma unroll
         for (int c = 0; c < 4; ++c) o[c] = fmaf(ht.s.w1, b[c], ht.s.w0 * a[c]) * (1.0f / 255.0f);
@@ -423,14 +454,16 @@ __global__ __launch_bounds__(256) void k_hybrid_pages(const ndgi_hybrid_model* _
     const float2 vut = make_float2(fmaf(ux.w1, ut1.x, ux.w0 * ut0.x), fmaf(ux.w1, ut1.y, ux.w0 * ut0.y));
     const uint32_t fbw = (uint32_t)m.W >> 2;
     // the F_uv footprint of the next pass is loaded while this one decodes
-    auto fp_of = [&](int p) { return m.fuv + ((uint32_t)((y0 + 2 * p + (lane >> 5)) >> 2) * fbw + (uint32_t)(x >> 2)) * 32u; };
-    u4v fa = ((const u4v*)fp_of(wave))[0], fb = ((const u4v*)fp_of(wave))[1];
+    const uint32_t ffb = m.codec ? 16u : 32u;
+    auto fp_of = [&](int p) { return m.fuv + ((uint32_t)((y0 + 2 * p + (lane >> 5)) >> 2) * fbw + (uint32_t)(x >> 2)) * ffb; };
+    // a BC7 footprint is one 16-byte block (fb unused)
+    u4v fa = ((const u4v*)fp_of(wave))[0], fb = m.codec ? fa : ((const u4v*)fp_of(wave))[1];
     for (int p = wave; p < kHybSub * kHybSub / 64; p += 4) {
       const int j = 2 * p + (lane >> 5), y = y0 + j;
       const u4v ca = fa, cb = fb;
       if (p + 4 < kHybSub * kHybSub / 64) {
         fa = ((const u4v*)fp_of(p + 4))[0];
-        fb = ((const u4v*)fp_of(p + 4))[1];
+        fb = m.codec ? fa : ((const u4v*)fp_of(p + 4))[1];
       }
       float rr[4][4];
       // V_uvt: bilinear over the staged nodes
@@ -443,7 +476,8 @@ __global__ __launch_bounds__(256) void k_hybrid_pages(const ndgi_hybrid_model* _
       for (int c = 0; c < 4; ++c) rr[0][c] = fmaf(w[3], c11[c], fmaf(w[2], c10[c], fmaf(w[1], c01[c], w[0] * c00[c])));
       // V_uv: the texel itself
       float sv[4];
-      bc4_fp4_regs(ca, cb, 4u * (uint32_t)(y & 3) + (uint32_t)(x & 3), sv);
+      if (m.codec) bc7_fp4_regs(ca, 4u * (uint32_t)(y & 3) + (uint32_t)(x & 3), sv);
+      else bc4_fp4_regs(ca, cb, 4u * (uint32_t)(y & 3) + (uint32_t)(x & 3), sv);
 #pragma unroll
       for (int c = 0; c < 4; ++c) rr[1][c] = sv[c] * (1.0f / 255.0f);
       // V_ut (per column), V_vt (per row)
@@ -477,19 +511,27 @@ int launch_hybrid_query(ndgi_ctx* ctx, const ndgi_hybrid_model& m, const float* 
                         hipStream_t s) {
   if (n == 0) return NDGI_OK;
   const int64_t want = ((n + 63) / 64 + 3) / 4;
-#define NDGI_HQ(P, HD)                                                                           \
+#define NDGI_HQ(P, HD, CD)                                                                       \
   do {                                                                                           \
-    int64_t wgs = resident_wgs(ctx, (const void*)k_hybrid_query<P, HD>);                         \
+    int64_t wgs = resident_wgs(ctx, (const void*)k_hybrid_query<P, HD, CD>);                     \
     if (wgs > want) wgs = want;                                                                  \
-    hipLaunchKernelGGL((k_hybrid_query<P, HD>), dim3((unsigned)wgs), dim3(256), 0, s, m, uvt, n, out); \
+    hipLaunchKernelGGL((k_hybrid_query<P, HD, CD>), dim3((unsigned)wgs), dim3(256), 0, s, m, uvt, n, out); \
+  } while (0)
+#define NDGI_HQ_CD(P, HD)                  \
+  do {                                     \
+    if (m.codec == NDGI_CODEC_BC7)         \
+      NDGI_HQ(P, HD, NDGI_CODEC_BC7);      \
+    else                                   \
+      NDGI_HQ(P, HD, NDGI_CODEC_BC4);      \
   } while (0)
   if (prec == NDGI_PREC_F16) {
-    if (m.hidden == 16) NDGI_HQ(NDGI_PREC_F16, 16);
-    else NDGI_HQ(NDGI_PREC_F16, 64);
+    if (m.hidden == 16) NDGI_HQ_CD(NDGI_PREC_F16, 16);
+    else NDGI_HQ_CD(NDGI_PREC_F16, 64);
   } else {
-    if (m.hidden == 16) NDGI_HQ(NDGI_PREC_F32, 16);
-    else NDGI_HQ(NDGI_PREC_F32, 64);
+    if (m.hidden == 16) NDGI_HQ_CD(NDGI_PREC_F32, 16);
+    else NDGI_HQ_CD(NDGI_PREC_F32, 64);
   }
+#undef NDGI_HQ_CD
 #undef NDGI_HQ
   NDGI_HIP(hipGetLastError());
   return NDGI_OK;

@@ -25,6 +25,7 @@ __device__ __forceinline__ float half_bits_f(uint16_t b) { return (float)__built
 struct HybTrainDims {
   int W, H, Gu, Gv, S, U, V, Tt, hidden, frames;
   int M, Bm;                                          // models, samples per model
+  int codec, cw;                                      // block format; weights per texel (4 or 1)
   int64_t o_uvw, o_tep, o_tw, o_ut, o_vt, o_mlp, n;   // segment offsets, parameters per model
 };
 
@@ -42,10 +43,12 @@ static HybTrainDims htd_of(const ndgi_hybrid_train_state* st) {
   d.frames = st->frames;
   d.M = st->n_models < 1 ? 1 : st->n_models;
   d.Bm = st->per_model;
+  d.codec = st->codec;
+  d.cw = d.codec == NDGI_CODEC_BC7 ? 1 : 4;
   d.o_uvw = (int64_t)(d.H / 4) * (d.W / 4) * 4 * 2;
-  d.o_tep = d.o_uvw + (int64_t)d.H * d.W * 4;
+  d.o_tep = d.o_uvw + (int64_t)d.H * d.W * d.cw;
   d.o_tw = d.o_tep + (int64_t)d.S * (d.Gv / 4) * (d.Gu / 4) * 4 * 2;
-  d.o_ut = d.o_tw + (int64_t)d.S * d.Gv * d.Gu * 4;
+  d.o_ut = d.o_tw + (int64_t)d.S * d.Gv * d.Gu * d.cw;
   d.o_vt = d.o_ut + (int64_t)d.Tt * d.U * 2;
   d.o_mlp = d.o_vt + (int64_t)d.Tt * d.V * 2;
   d.n = d.o_mlp + ndgi_hybrid_mlp_size(d.hidden);
@@ -89,6 +92,68 @@ __device__ __forceinline__ BcTex bc_texel(const float* __restrict__ ep, const fl
     }
   }
   return r;
+}
+
+// The same for the BC7 simulation (codec 1): one weight w per texel shared by the 4
+// channels.  Each endpoint takes the 7-bit values and p-bit of BC7 mode 6 nearest to
+// x = fl32(255 e) in summed squared error (v = rint((x - p) / 2) clamped to 0..127, E = 2 v + p;
+// ties keep p = 0; the errors are compared exactly, in FP64); J = rint(fl32(15 w)) with
+// weight (64 J + 7) / 15 (the format's table); value ((64 - w) E1 + w E2 + 32) >> 6 / 255;
+// straight-through derivatives of Eq. 7 at (E/255, w/64).  dw[c] is the channel's share of
+// the shared weight's derivative.
+__device__ __forceinline__ void bc7_endpoint(const float e[4], int E[4]) {
+#pragma clang fp contract(off)
+  double err[2] = {0.0, 0.0};
+  int Ep[2][4];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const float x = 255.0f * e[c];
+      const int v = min(max((int)rintf((x - (float)p) * 0.5f), 0), 127);
+      Ep[p][c] = 2 * v + p;
+      const double dd = (double)Ep[p][c] - (double)x;
+      err[p] += dd * dd;
+    }
+  const int p = err[1] < err[0] ? 1 : 0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) E[c] = p ? Ep[1][c] : Ep[0][c];
+}
+
+__device__ __forceinline__ BcTex bc7_texel(const float* __restrict__ ep, float w, bool bcsim) {
+#pragma clang fp contract(off)
+  BcTex r;
+  const float4 ea = *(const float4*)ep, eb = *(const float4*)(ep + 4);
+  const float e1[4] = {ea.x, ea.z, eb.x, eb.z}, e2[4] = {ea.y, ea.w, eb.y, eb.w};
+  if (bcsim) {
+    int E1[4], E2[4];
+    bc7_endpoint(e1, E1);
+    bc7_endpoint(e2, E2);
+    const int J = (int)rintf(15.0f * w);
+    const int wt = (64 * J + 7) / 15;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      r.v[c] = (float)(((64 - wt) * E1[c] + wt * E2[c] + 32) >> 6) * (1.0f / 255.0f);
+      r.d1[c] = 1.0f - (float)wt * (1.0f / 64.0f);
+      r.d2[c] = (float)wt * (1.0f / 64.0f);
+      r.dw[c] = (float)(E2[c] - E1[c]) * (1.0f / 255.0f);
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      r.v[c] = (1.0f - w) * e1[c] + w * e2[c];
+      r.d1[c] = 1.0f - w;
+      r.d2[c] = w;
+      r.dw[c] = e2[c] - e1[c];
+    }
+  }
+  return r;
+}
+
+// Texel of either codec: weights at w (4 per texel for BC4, 1 for BC7).
+__device__ __forceinline__ BcTex sim_texel(const float* __restrict__ ep, const float* __restrict__ w, bool bcsim,
+                                           int codec) {
+  return codec ? bc7_texel(ep, *w, bcsim) : bc_texel(ep, w, bcsim);
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -164,13 +229,14 @@ __global__ __launch_bounds__(kHtThreads) void k_hybrid_train(HybTrainDims d, con
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int64_t fp = ((int64_t)si * (d.Gv / 4) + (tys[i] >> 2)) * (d.Gu / 4) + (txs[i] >> 2);
-        const BcTex b = bc_texel(P + d.o_tep + fp * 8, P + d.o_tw + (((int64_t)si * d.Gv + tys[i]) * d.Gu + txs[i]) * 4, bcsim);
+        const BcTex b = sim_texel(P + d.o_tep + fp * 8, P + d.o_tw + (((int64_t)si * d.Gv + tys[i]) * d.Gu + txs[i]) * d.cw,
+                                  bcsim, d.codec);
 #pragma unroll
         for (int c = 0; c < 4; ++c) xin[c] = fmaf(ws * tw[i], b.v[c], xin[c]);
       }
     }
     const int64_t fpu = (int64_t)(y >> 2) * (d.W / 4) + (x >> 2);
-    const BcTex bu = bc_texel(P + fpu * 8, P + d.o_uvw + ((int64_t)y * d.W + x) * 4, bcsim);
+    const BcTex bu = sim_texel(P + fpu * 8, P + d.o_uvw + ((int64_t)y * d.W + x) * d.cw, bcsim, d.codec);
 #pragma unroll
     for (int c = 0; c < 4; ++c) xin[4 + c] = bu.v[c];
     const Axis pu = texel_axis<false>(x, d.U, d.W), pv = texel_axis<false>(y, d.V, d.H);
@@ -298,24 +364,29 @@ __global__ __launch_bounds__(kHtThreads) void k_hybrid_train(HybTrainDims d, con
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int64_t fp = ((int64_t)si * (d.Gv / 4) + (tys[i] >> 2)) * (d.Gu / 4) + (txs[i] >> 2);
-          const int64_t wi = (((int64_t)si * d.Gv + tys[i]) * d.Gu + txs[i]) * 4;
-          const BcTex b = bc_texel(P + d.o_tep + fp * 8, P + d.o_tw + wi, bcsim);
+          const int64_t wi = (((int64_t)si * d.Gv + tys[i]) * d.Gu + txs[i]) * d.cw;
+          const BcTex b = sim_texel(P + d.o_tep + fp * 8, P + d.o_tw + wi, bcsim, d.codec);
           const float wt = ws * tw[i];
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
             const float dv = wt * dx[c];
             atomicAdd(G + d.o_tep + fp * 8 + 2 * c, dv * b.d1[c]);
             atomicAdd(G + d.o_tep + fp * 8 + 2 * c + 1, dv * b.d2[c]);
-            atomicAdd(G + d.o_tw + wi + c, dv * b.dw[c]);
+            if (!d.codec) atomicAdd(G + d.o_tw + wi + c, dv * b.dw[c]);
           }
+          if (d.codec)
+            atomicAdd(G + d.o_tw + wi, wt * (dx[0] * b.dw[0] + dx[1] * b.dw[1] + dx[2] * b.dw[2] + dx[3] * b.dw[3]));
         }
       }
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         atomicAdd(G + fpu * 8 + 2 * c, dx[4 + c] * bu.d1[c]);
         atomicAdd(G + fpu * 8 + 2 * c + 1, dx[4 + c] * bu.d2[c]);
-        atomicAdd(G + d.o_uvw + ((int64_t)y * d.W + x) * 4 + c, dx[4 + c] * bu.dw[c]);
+        if (!d.codec) atomicAdd(G + d.o_uvw + ((int64_t)y * d.W + x) * 4 + c, dx[4 + c] * bu.dw[c]);
       }
+      if (d.codec)
+        atomicAdd(G + d.o_uvw + (int64_t)y * d.W + x,
+                  dx[4] * bu.dw[0] + dx[5] * bu.dw[1] + dx[6] * bu.dw[2] + dx[7] * bu.dw[3]);
 #pragma unroll
       for (int pl = 0; pl < 2; ++pl) {
         const int64_t off = pl ? d.o_vt : d.o_ut;
@@ -364,6 +435,43 @@ __global__ __launch_bounds__(256) void k_export_bc4c(const float* __restrict__ e
     }
     const uint32_t e0 = (uint32_t)(E1 >= E2 ? E1 : E2), e1 = (uint32_t)(E1 >= E2 ? E2 : E1);
     *(uint2*)(out + b * 8) = make_uint2(e0 | (e1 << 8) | (uint32_t)((sel & 0xffffu) << 16), (uint32_t)(sel >> 16));
+  }
+}
+
+// Export of a BC7-simulated 4-channel map ([..][H/4][W/4][4][2] endpoints, [..][H][W] weights)
+// to mode-6 blocks [..][H/4][W/4][16]: endpoints as in the simulation, J = rint(fl32(15 w));
+// when texel 0's index has its top bit set the endpoints swap and every index becomes
+// 15 - J (the weight table is symmetric), so the decode equals the simulation.
+__global__ __launch_bounds__(256) void k_export_bc7(const float* __restrict__ ep, const float* __restrict__ wts, int W,
+                                                     int H, int64_t nb, uint8_t* __restrict__ out) {
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t per = (int64_t)(H >> 2) * (W >> 2);
+    const int64_t sl = b / per, rem = b - sl * per;
+    const int bx = (int)(rem % (W >> 2)), by = (int)(rem / (W >> 2));
+    const float4 ea = *(const float4*)(ep + b * 8), eb = *(const float4*)(ep + b * 8 + 4);
+    const float e1[4] = {ea.x, ea.z, eb.x, eb.z}, e2[4] = {ea.y, ea.w, eb.y, eb.w};
+    int E[2][4];
+    bc7_endpoint(e1, E[0]);
+    bc7_endpoint(e2, E[1]);
+    int J[16];
+    for (int s = 0; s < 16; ++s) {
+      const int x = 4 * bx + (s & 3), y = 4 * by + (s >> 2);
+      J[s] = (int)rintf(__fmul_rn(15.0f, wts[(sl * H + y) * W + x]));
+    }
+    const bool swap = J[0] >= 8;
+    uint64_t lo = 0x40, hi = 0;
+    for (int c = 0; c < 4; ++c) {
+      const int a = E[swap ? 1 : 0][c], z = E[swap ? 0 : 1][c];
+      lo |= (uint64_t)(a >> 1) << (7 + 14 * c);
+      lo |= (uint64_t)(z >> 1) << (14 + 14 * c);
+    }
+    lo |= (uint64_t)(E[swap ? 1 : 0][0] & 1) << 63;
+    hi |= (uint64_t)(E[swap ? 0 : 1][0] & 1);
+    for (int s = 0; s < 16; ++s) {
+      const uint64_t j = (uint64_t)(swap ? 15 - J[s] : J[s]);
+      hi |= s ? j << (4 * s) : j << 1;
+    }
+    *(u4v*)(out + b * 16) = (u4v){(uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32)};
   }
 }
 
@@ -436,6 +544,7 @@ static int check_htrain(const ndgi_hybrid_train_state* st, const char* who) {
   m.Tt = st->Tt;
   m.hidden = st->hidden;
   m.mlp_dtype = NDGI_DTYPE_F32;
+  m.codec = st->codec;
   m.fuv = m.fuvt = m.fut = m.fvt = (const uint8_t*)st->params;
   m.mlp = st->params;
   if (!st->params || !st->grads) return fail(NDGI_ERR_INVALID_ARG, "%s: NULL params/grads", who);
@@ -444,6 +553,7 @@ static int check_htrain(const ndgi_hybrid_train_state* st, const char* who) {
   if (st->W > 4096 || st->H > 4096) return fail(NDGI_ERR_INVALID_ARG, "%s: W, H above 4096", who);
   if (st->frames < 1 || st->frames > 256) return fail(NDGI_ERR_INVALID_ARG, "%s: frames=%d not in 1..256", who, st->frames);
   if (st->n_models < 1) return fail(NDGI_ERR_INVALID_ARG, "%s: n_models=%d < 1", who, st->n_models);
+  if (st->reserved0) return fail(NDGI_ERR_INVALID_ARG, "%s: reserved0 must be 0", who);
   return NDGI_OK;
 }
 
@@ -454,8 +564,9 @@ using namespace ndgi;
 extern "C" {
 
 int64_t ndgi_hybrid_train_param_count(int32_t W, int32_t H, int32_t Gu, int32_t Gv, int32_t S, int32_t U, int32_t V,
-                                      int32_t Tt, int32_t hidden) {
-  if (ndgi_hybrid_mlp_size(hidden) < 0 || W < 4 || H < 4 || Gu < 4 || Gv < 4 || S < 1 || U < 1 || V < 1 || Tt < 1)
+                                      int32_t Tt, int32_t hidden, int32_t codec) {
+  if (ndgi_hybrid_mlp_size(hidden) < 0 || W < 4 || H < 4 || Gu < 4 || Gv < 4 || S < 1 || U < 1 || V < 1 || Tt < 1 ||
+      (codec != NDGI_CODEC_BC4 && codec != NDGI_CODEC_BC7))
     return -1;
   ndgi_hybrid_train_state st = {};
   st.W = W;
@@ -467,6 +578,7 @@ int64_t ndgi_hybrid_train_param_count(int32_t W, int32_t H, int32_t Gu, int32_t 
   st.V = V;
   st.Tt = Tt;
   st.hidden = hidden;
+  st.codec = codec;
   st.frames = 1;
   return htd_of(&st).n;
 }
@@ -547,10 +659,18 @@ int ndgi_hybrid_export(ndgi_ctx* c, const ndgi_hybrid_train_state* st, int32_t m
   const float* P = st->params + (int64_t)model * d.o_mlp;
   const float* mlp = st->params + (int64_t)d.M * d.o_mlp + (int64_t)model * (d.n - d.o_mlp);
   const int64_t nb_uv = (int64_t)(d.H / 4) * (d.W / 4) * 4, nb_uvt = (int64_t)d.S * (d.Gv / 4) * (d.Gu / 4) * 4;
-  hipLaunchKernelGGL(k_export_bc4c, dim3(grid_of(nb_uv, c->n_cu * 16)), dim3(256), 0, s, P, P + d.o_uvw, d.W, d.H,
-                     4, nb_uv, fuv_out);
-  hipLaunchKernelGGL(k_export_bc4c, dim3(grid_of(nb_uvt, c->n_cu * 16)), dim3(256), 0, s, P + d.o_tep, P + d.o_tw,
-                     d.Gu, d.Gv, 4, nb_uvt, fuvt_out);
+  if (d.codec == NDGI_CODEC_BC7) {
+    const int64_t fb_uv = nb_uv / 4, fb_uvt = nb_uvt / 4;   // footprints
+    hipLaunchKernelGGL(k_export_bc7, dim3(grid_of(fb_uv, c->n_cu * 16)), dim3(256), 0, s, P, P + d.o_uvw, d.W, d.H,
+                       fb_uv, fuv_out);
+    hipLaunchKernelGGL(k_export_bc7, dim3(grid_of(fb_uvt, c->n_cu * 16)), dim3(256), 0, s, P + d.o_tep, P + d.o_tw,
+                       d.Gu, d.Gv, fb_uvt, fuvt_out);
+  } else {
+    hipLaunchKernelGGL(k_export_bc4c, dim3(grid_of(nb_uv, c->n_cu * 16)), dim3(256), 0, s, P, P + d.o_uvw, d.W,
+                       d.H, 4, nb_uv, fuv_out);
+    hipLaunchKernelGGL(k_export_bc4c, dim3(grid_of(nb_uvt, c->n_cu * 16)), dim3(256), 0, s, P + d.o_tep,
+                       P + d.o_tw, d.Gu, d.Gv, 4, nb_uvt, fuvt_out);
+  }
   hipLaunchKernelGGL(k_quant8, dim3(grid_of((int64_t)d.Tt * d.U * 2, 1024)), dim3(256), 0, s, P + d.o_ut, fut_out,
                      (int64_t)d.Tt * d.U * 2);
   hipLaunchKernelGGL(k_quant8, dim3(grid_of((int64_t)d.Tt * d.V * 2, 1024)), dim3(256), 0, s, P + d.o_vt, fvt_out,

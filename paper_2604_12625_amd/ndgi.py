@@ -30,6 +30,7 @@ EXPORTED = (
     "ndgi_hybrid_export", "ndgi_hybrid_normalize_target", "ndgi_hybrid_restore",
 )
 HTRAIN_BCSIM, HTRAIN_NOISE, HTRAIN_QPLANES = 1, 2, 4
+CODEC_BC4, CODEC_BC7 = 0, 1
 
 
 class NdgiModel(C.Structure):
@@ -62,7 +63,7 @@ class NdgiHybridModel(C.Structure):
     _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("Gu", C.c_int32), ("Gv", C.c_int32),
                 ("S", C.c_int32), ("U", C.c_int32), ("V", C.c_int32), ("Tt", C.c_int32),
                 ("hidden", C.c_int32), ("mlp_dtype", C.c_int32), ("n_keys", C.c_int32),
-                ("reserved0", C.c_int32), ("fuv", C.c_void_p), ("fuvt", C.c_void_p),
+                ("codec", C.c_int32), ("fuv", C.c_void_p), ("fuvt", C.c_void_p),
                 ("fut", C.c_void_p), ("fvt", C.c_void_p), ("keys", C.c_void_p), ("mlp", C.c_void_p)]
 
 
@@ -70,7 +71,8 @@ class NdgiHybridTrainState(C.Structure):
     _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("Gu", C.c_int32), ("Gv", C.c_int32),
                 ("S", C.c_int32), ("U", C.c_int32), ("V", C.c_int32), ("Tt", C.c_int32),
                 ("hidden", C.c_int32), ("frames", C.c_int32), ("n_models", C.c_int32),
-                ("per_model", C.c_int32), ("keys", C.c_void_p),
+                ("per_model", C.c_int32), ("codec", C.c_int32), ("reserved0", C.c_int32),
+                ("keys", C.c_void_p),
                 ("params", C.c_void_p), ("grads", C.c_void_p), ("adam_m", C.c_void_p),
                 ("adam_v", C.c_void_p), ("step", C.c_int64), ("lr_feat", C.c_float),
                 ("lr_mlp", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
@@ -82,7 +84,7 @@ class NdgiHybridBatch(C.Structure):
 
 
 assert C.sizeof(NdgiModel) == 64 and C.sizeof(NdgiPageReq) == 24 and C.sizeof(NdgiHybridModel) == 96
-assert C.sizeof(NdgiHybridTrainState) == 120 and C.sizeof(NdgiHybridBatch) == 32
+assert C.sizeof(NdgiHybridTrainState) == 128 and C.sizeof(NdgiHybridBatch) == 32
 
 
 class NdgiError(RuntimeError):
@@ -124,7 +126,7 @@ def lib():
         hpages = [vp, vp, i32, vp, vp, i32, i32, vp, i64, i32, i32, vp]
         L.ndgi_hybrid_decode_pages.argtypes = hpages
         L.ndgi_hybrid_decode_pages_graph.argtypes = hpages
-        L.ndgi_hybrid_train_param_count.argtypes = [i32] * 9
+        L.ndgi_hybrid_train_param_count.argtypes = [i32] * 10
         L.ndgi_hybrid_train_param_count.restype = i64
         L.ndgi_hybrid_train_step.argtypes = [vp, C.POINTER(NdgiHybridTrainState), C.POINTER(NdgiHybridBatch), i32,
                                              i32, vp, vp]
@@ -181,14 +183,14 @@ class HybridModel:
     """A model in the paper's hybrid layout (F_uv, F_uvt, F_ut, F_vt, key times, decoder)
     whose arrays live in device memory (torch tensors)."""
 
-    def __init__(self, W, H, Gu, Gv, S, U, V, Tt, hidden, fuv, fuvt, fut, fvt, keys, mlp):
+    def __init__(self, W, H, Gu, Gv, S, U, V, Tt, hidden, fuv, fuvt, fut, fvt, keys, mlp, codec=CODEC_BC4):
         import torch
         self.arrays = [a.contiguous() for a in (fuv, fuvt, fut, fvt, keys, mlp)]
         fuv, fuvt, fut, fvt, keys, mlp = self.arrays
         dt = {torch.float32: DTYPE_F32, torch.float16: DTYPE_F16}
         nk = keys.numel()
         self.desc = NdgiHybridModel(int(W), int(H), int(Gu), int(Gv), int(S), int(U), int(V), int(Tt),
-                                    int(hidden), dt[mlp.dtype], nk, 0, fuv.data_ptr(), fuvt.data_ptr(),
+                                    int(hidden), dt[mlp.dtype], nk, int(codec), fuv.data_ptr(), fuvt.data_ptr(),
                                     fut.data_ptr(), fvt.data_ptr(), keys.data_ptr() if nk else None,
                                     mlp.data_ptr())
 
@@ -197,7 +199,8 @@ class HybridModel:
         import torch
         t = {k: torch.from_numpy(m[k]).to(device) for k in ("fuv", "fuvt", "fut", "fvt", "keys", "mlp")}
         return cls(m["W"], m["H"], m["Gu"], m["Gv"], m["S"], m["U"], m["V"], m["Tt"], m["hidden"],
-                   t["fuv"], t["fuvt"], t["fut"], t["fvt"], t["keys"].to(torch.float32), t["mlp"])
+                   t["fuv"], t["fuvt"], t["fut"], t["fvt"], t["keys"].to(torch.float32), t["mlp"],
+                   m.get("codec", CODEC_BC4))
 
     def desc_bytes(self) -> bytes:
         return bytes(self.desc)

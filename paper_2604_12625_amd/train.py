@@ -173,7 +173,8 @@ class HybridTrainer:
         d = inits[0]["dims"]
         self.ctx, self.d, self.M = ctx, dict(d), len(inits)
         dims = [d[k] for k in ("W", "H", "Gu", "Gv", "S", "U", "V", "Tt", "hidden")]
-        n = int(N.lib().ndgi_hybrid_train_param_count(*dims))
+        self.codec = int(d.get("codec", N.CODEC_BC4))
+        n = int(N.lib().ndgi_hybrid_train_param_count(*dims, self.codec))
         self.n_params = n * self.M
         feats = [np.concatenate([np.asarray(m[k], dtype=np.float32).ravel() for k in HYB_KEYS[:-1]]) for m in inits]
         mlps = [np.asarray(m["mlp"], dtype=np.float32).ravel() for m in inits]
@@ -187,7 +188,8 @@ class HybridTrainer:
         self.loss = torch.zeros(1, dtype=torch.float64, device=device)
         keys = np.asarray(d.get("keys", []), dtype=np.float32)
         self.keys = torch.from_numpy(keys).to(device) if keys.size else None
-        self.state = N.NdgiHybridTrainState(*dims, int(d["frames"]), self.M, int(per_model), N._ptr(self.keys),
+        self.state = N.NdgiHybridTrainState(*dims, int(d["frames"]), self.M, int(per_model), self.codec, 0,
+                                            N._ptr(self.keys),
                                             self.params.data_ptr(), self.grads.data_ptr(), self.m.data_ptr(),
                                             self.v.data_ptr(), 0, float(lr_feat), float(lr_mlp), float(betas[0]),
                                             float(betas[1]), float(eps), int(seed))
@@ -195,8 +197,9 @@ class HybridTrainer:
     def split(self, flat, model=0) -> dict:
         """Views of one model's arrays in a flat [params | grads | m | v]-shaped tensor."""
         d = self.d
-        shapes = dict(fuv_ep=(d["H"] // 4, d["W"] // 4, 4, 2), fuv_w=(d["H"], d["W"], 4),
-                      fuvt_ep=(d["S"], d["Gv"] // 4, d["Gu"] // 4, 4, 2), fuvt_w=(d["S"], d["Gv"], d["Gu"], 4),
+        cw = () if self.codec == N.CODEC_BC7 else (4,)
+        shapes = dict(fuv_ep=(d["H"] // 4, d["W"] // 4, 4, 2), fuv_w=(d["H"], d["W"]) + cw,
+                      fuvt_ep=(d["S"], d["Gv"] // 4, d["Gu"] // 4, 4, 2), fuvt_w=(d["S"], d["Gv"], d["Gu"]) + cw,
                       fut=(d["Tt"], d["U"], 2), fvt=(d["Tt"], d["V"], 2))
         out, o = {}, model * self.n_feat
         for k in HYB_KEYS[:-1]:
@@ -241,8 +244,9 @@ class HybridTrainer:
     def export(self, mlp_dtype=N.DTYPE_F16, model=0) -> N.HybridModel:
         import torch
         d, dev = self.d, self.params.device
-        fuv = torch.empty((d["H"] // 4, d["W"] // 4, 4, 8), dtype=torch.uint8, device=dev)
-        fuvt = torch.empty((d["S"], d["Gv"] // 4, d["Gu"] // 4, 4, 8), dtype=torch.uint8, device=dev)
+        blk = (16,) if self.codec == N.CODEC_BC7 else (4, 8)
+        fuv = torch.empty((d["H"] // 4, d["W"] // 4) + blk, dtype=torch.uint8, device=dev)
+        fuvt = torch.empty((d["S"], d["Gv"] // 4, d["Gu"] // 4) + blk, dtype=torch.uint8, device=dev)
         fut = torch.empty((d["Tt"], d["U"], 2), dtype=torch.uint8, device=dev)
         fvt = torch.empty((d["Tt"], d["V"], 2), dtype=torch.uint8, device=dev)
         mlp = torch.empty(N.hybrid_mlp_size(d["hidden"]), dtype=torch.float16 if mlp_dtype == N.DTYPE_F16
@@ -252,7 +256,7 @@ class HybridTrainer:
                                            N._stream(None)), "ndgi_hybrid_export")
         keys = self.keys if self.keys is not None else torch.zeros(0, dtype=torch.float32, device=dev)
         return N.HybridModel(d["W"], d["H"], d["Gu"], d["Gv"], d["S"], d["U"], d["V"], d["Tt"], d["hidden"],
-                             fuv, fuvt, fut, fvt, keys, mlp)
+                             fuv, fuvt, fut, fvt, keys, mlp, self.codec)
 
 
 def hybrid_normalize_target(ctx: N.Context, target_bits, gamma=2.2):

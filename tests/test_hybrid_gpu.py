@@ -109,7 +109,7 @@ def test_hybrid_argument_errors(N, ctx):
     hm = N.HybridModel.from_numpy(m)
     q = torch.zeros((4, 3), dtype=torch.float32, device="cuda")
     for field, val in (("hidden", 32), ("Gu", 256), ("U", 0), ("S", 0), ("n_keys", 1), ("n_keys", 300),
-                       ("W", 130), ("reserved0", 1), ("mlp_dtype", 7)):
+                       ("W", 130), ("codec", 2), ("codec", -1), ("mlp_dtype", 7)):
         bad = N.HybridModel.from_numpy(m)
         setattr(bad.desc, field, val)
         with pytest.raises(N.NdgiError):
@@ -265,3 +265,45 @@ def test_hybrid_1024_map_of_tile_models_sampled(N, ctx, profile):
         got = dst[torch.from_numpy(sel).cuda()].float().cpu().numpy()
         assert_close(got, ref, TOL[prec], f"{profile} 1024^2 prec {prec}")
     assert ctx.error_flags() == 0
+
+
+# ------------------------------------------------------------------------- BC7 mode 6
+@pytest.mark.parametrize("profile", ["L", "M.64"])
+@pytest.mark.parametrize("prec", [1, 0])
+def test_bc7_queries_match_oracle(N, ctx, profile, prec):
+    """F_uv and F_uvt as BC7 mode-6 blocks (codec 1): random blocks of every index pattern
+    and p-bit, decoded at random points."""
+    m = I.random_hybrid_model(profile=profile, config=80, codec=1)
+    assert m["fuv"].shape[-1] == 16
+    q = I.uniform_queries(4096 + 91, I.rng(80, I.P_QUERY))
+    assert_close(_dec(N, ctx, m, q, prec), O.hybrid_decode(m, q), TOL[prec], f"bc7 {profile} prec {prec}")
+
+
+def test_bc7_full_resolution_uvt_and_edges(N, ctx):
+    m = I.random_hybrid_model(256, 128, profile="M", slices=4, plane=(64, 32, 5), mlp_dtype=np.float32,
+                              keys=False, config=81, uvt_side=(256, 128), codec=1)
+    q = np.concatenate([I.uniform_queries(3000, I.rng(81, I.P_QUERY)),
+                        np.array([[-0.5, 0.5, 0.2], [1.7, 1.5, 1.2], [0.0, 0.0, 0.0], [1.0, 1.0, 1.0]],
+                                 dtype=np.float32)])
+    for prec in (1, 0):
+        assert_close(_dec(N, ctx, m, q, prec), O.hybrid_decode(m, q), TOL[prec], f"bc7 full-res prec {prec}")
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_bc7_pages_with_mixed_codecs(N, ctx, prec):
+    """One page launch over BC4 and BC7 tile models: each request decodes with its model's
+    block format."""
+    models, reqs = _hyb_vt(5)
+    rebuilt = []
+    for i, m in enumerate(models):
+        if i % 2:
+            m = I.random_hybrid_model(m["W"], m["H"], profile=["L", "M", "H", "M.64", "M", "L", "M.64", "H", "M",
+                                                               "M.64"][i], plane=(m["U"], m["V"], m["Tt"]),
+                                      config=82, index=i, uvt_side=(m["Gu"], m["Gv"]), codec=1)
+        rebuilt.append(m)
+    out, _ = _run_hpages(N, ctx, rebuilt, reqs, prec)
+    ref = np.full(out.shape, -7.0)
+    assert O.hybrid_decode_pages(rebuilt, reqs, 128, ref, 1024) == 3
+    valid = ref[:, 0] != -7.0
+    assert_close(out[valid], ref[valid], TOL[prec], "bc7 pages")
+    np.testing.assert_array_equal(out[~valid], -7.0)

@@ -29,7 +29,7 @@ def ctx(N):
     c.close()
 
 
-def _state(hidden, seed, frames=3, keys=True, on_grid=False, bigger=False):
+def _state(hidden, seed, frames=3, keys=True, on_grid=False, bigger=False, codec=0):
     st = tiny_hybrid_state(hidden, seed=seed, frames=frames, keys=keys, on_grid=on_grid)
     if bigger:   # a 64 x 48 map, F_uvt 16 x 12 x 5, planes 32 x 4 and 48 x 4
         g = np.random.default_rng(seed + 100)
@@ -42,6 +42,11 @@ def _state(hidden, seed, frames=3, keys=True, on_grid=False, bigger=False):
         st["fut"] = g.uniform(0, 1, (4, 32, 2))
         st["fvt"] = g.uniform(0, 1, (4, 48, 2))
         st["mlp"] = I.hybrid_mlp(hidden, np.float64, g)
+    if codec == 1:   # BC7: one weight per texel
+        g = np.random.default_rng(seed + 200)
+        st["dims"] = dict(st["dims"], codec=1)
+        st["fuv_w"] = g.uniform(0, 1, st["fuv_w"].shape[:-1])
+        st["fuvt_w"] = g.uniform(0, 1, st["fuvt_w"].shape[:-1])
     # the GPU holds float32 masters: the oracle reads the same values
     for k in O.HYB_KEYS:
         st[k] = np.asarray(st[k], dtype=np.float32).astype(np.float64)
@@ -184,3 +189,105 @@ def test_many_models_in_one_launch(N, ctx, hidden):
     tr2 = HybridTrainer(ctx, sts, seed=13, per_model=100)
     with pytest.raises(N.NdgiError):
         tr2.loss_grad(smp, tg, flags)
+
+
+# ------------------------------------------------------------------------- BC7 mode 6
+@pytest.mark.parametrize("hidden", [16, 64])
+@pytest.mark.parametrize("flags", [0, 1 | 2, 1 | 4])
+def test_bc7_loss_grad_and_forward_match_oracle(N, ctx, hidden, flags):
+    """The BC7 simulation (one weight per texel shared by the 4 channels, Eq. 6): forward,
+    loss and every gradient, including the shared weights' channel sums."""
+    from paper_2604_12625_amd.train import HybridTrainer
+    st = _state(hidden, seed=60 + hidden + flags, bigger=True, codec=1)
+    x, y, f, tgt = _samples(st, 900, seed=61 + flags)
+    smp, tg = _dev(N, x, y, f, tgt)
+    tr = HybridTrainer(ctx, st, seed=17)
+    assert tr.split(tr.params)["fuv_w"].shape == (48, 64)
+    pred = tr.forward(smp, flags).cpu().numpy()
+    _close(pred, O.hybrid_train_forward(st, x, y, f, flags, seed=17, step=0), 1e-5, "forward")
+    tr.zero_grad()
+    loss = float(tr.loss_grad(smp, tg, flags).item())
+    ref_loss, ref_g = O.hybrid_train_grads(st, x, y, f, tgt[f, y, x], flags, seed=17, step=0)
+    assert abs(loss - ref_loss) <= 1e-5 * abs(ref_loss), (loss, ref_loss)
+    got = tr.split(tr.grads)
+    for k in O.HYB_KEYS:
+        _close(got[k].cpu().numpy(), ref_g[k], 1e-4, k)
+
+
+def test_bc7_adam_steps_match_oracle(N, ctx):
+    from paper_2604_12625_amd.train import HybridTrainer
+    st = _state(16, seed=63, codec=1)
+    ref = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in st.items()}
+    opt = dict(step=0, lr_feat=1e-2, lr_mlp=1e-3, m={k: 0.0 for k in O.HYB_KEYS}, v={k: 0.0 for k in O.HYB_KEYS})
+    tr = HybridTrainer(ctx, st, lr_feat=1e-2, lr_mlp=1e-3, seed=6)
+    for it in range(3):
+        x, y, f, tgt = _samples(st, 500, seed=64 + it)
+        smp, tg = _dev(N, x, y, f, tgt)
+        loss = float(tr.step(smp, tg, 1 | 2).item())
+        ref_loss = O.hybrid_train_step(ref, opt, x, y, f, tgt[f, y, x], 1 | 2, seed=6)
+        assert abs(loss - ref_loss) <= 1e-4 * abs(ref_loss), (it, loss, ref_loss)
+    got = tr.split(tr.params)
+    for k in O.HYB_KEYS:
+        diff = np.abs(got[k].cpu().numpy().astype(np.float64) - ref[k])
+        tol = 1e-4 * np.abs(ref[k]) + 3e-3 * (1e-2 if k != "mlp" else 1e-3)
+        assert np.mean(diff > tol) <= 1e-3, (k, float(diff.max()))
+
+
+@pytest.mark.parametrize("on_grid", [False, True])
+def test_bc7_export_is_exact_and_decodes_to_the_simulated_forward(N, ctx, on_grid):
+    """Mode-6 blocks bit-identical to the oracle's encoder (p-bits, anchor swaps) and their
+    decode at the training samples equal to the simulated forward."""
+    import torch
+    from paper_2604_12625_amd.train import HybridTrainer
+    st = _state(64, seed=65, bigger=True, codec=1)
+    if on_grid:   # weights at index boundaries 1/30 + J/15 and endpoints on the 8-bit grid
+        g = np.random.default_rng(66)
+        for k in ("fuv_w", "fuvt_w"):
+            st[k] = np.clip(g.integers(0, 16, st[k].shape) / 15.0 + g.choice([-1, 0, 1], st[k].shape) / 30.0, 0, 1)
+            st[k] = st[k].astype(np.float32).astype(np.float64)
+        for k in ("fuv_ep", "fuvt_ep"):
+            st[k] = (g.integers(0, 256, st[k].shape) / 255.0).astype(np.float32).astype(np.float64)
+    tr = HybridTrainer(ctx, st)
+    hm = tr.export(N.DTYPE_F32)
+    ref = O.hybrid_export(st)
+    for i, k in enumerate(("fuv", "fuvt", "fut", "fvt")):
+        np.testing.assert_array_equal(hm.arrays[i].cpu().numpy(), ref[k], err_msg=k)
+    assert hm.desc.codec == 1
+    d = st["dims"]
+    g = np.random.default_rng(67)
+    n = 3000
+    x, y, f = g.integers(0, d["W"], n), g.integers(0, d["H"], n), g.integers(0, d["frames"], n)
+    fwd = O.hybrid_train_forward(st, x, y, f, 1 | 4)
+    t = np.asarray(d["keys"], dtype=np.float32)[f]
+    q = np.stack([(x + 0.5) / d["W"], (y + 0.5) / d["H"], t], 1).astype(np.float32)
+    out = ctx.hybrid_decode(hm, torch.from_numpy(q).cuda(), N.PREC_F32).cpu().numpy()
+    rms = np.sqrt(np.mean(fwd ** 2))
+    assert np.max(np.abs(out - fwd) / np.maximum(np.abs(fwd), rms)) <= 1e-5
+
+
+def test_bc7_many_models_in_one_launch(N, ctx):
+    from paper_2604_12625_amd.train import HybridTrainer
+    M, Bm = 2, 192
+    sts = [_state(16, seed=70 + i, codec=1) for i in range(M)]
+    for st in sts[1:]:
+        st["dims"] = sts[0]["dims"]
+    g = np.random.default_rng(71)
+    d = sts[0]["dims"]
+    xs, ys, fs = (g.integers(0, d["W"], M * Bm), g.integers(0, d["H"], M * Bm), g.integers(0, d["frames"], M * Bm))
+    tgt = g.normal(0.5, 0.5, (M, d["frames"], d["H"], d["W"], 3)).astype(np.float32)
+    smp, tg = _dev(N, xs, ys, fs, tgt)
+    tr = HybridTrainer(ctx, sts, seed=19, per_model=Bm)
+    tr.zero_grad()
+    loss = float(tr.loss_grad(smp, tg, 1 | 2).item())
+    ref_loss = 0.0
+    for m in range(M):
+        sl = slice(m * Bm, (m + 1) * Bm)
+        lm, gm = O.hybrid_train_grads(sts[m], xs[sl], ys[sl], fs[sl], tgt[m][fs[sl], ys[sl], xs[sl]], 1 | 2, seed=19,
+                                      step=0, s_offset=m * Bm, n_total=M * Bm)
+        ref_loss += lm
+        got = tr.split(tr.grads, m)
+        for k in O.HYB_KEYS:
+            _close(got[k].cpu().numpy(), gm[k], 1e-4, f"model {m} {k}")
+    assert abs(loss - ref_loss) <= 1e-5 * abs(ref_loss), (loss, ref_loss)
+    hm = tr.export(N.DTYPE_F16, model=1)
+    np.testing.assert_array_equal(hm.arrays[0].cpu().numpy(), O.hybrid_export(sts[1])["fuv"])
