@@ -6,8 +6,8 @@ Target: a 128 x 128 tile (the paper trains one model per VT tile) cut from the s
 like the paper's sets), FP16.  Preprocessing: gamma 2.2 and per-frame, per-channel mean
 normalisation.  Training: Adam at the paper's learning rate 1e-3 and batch 2^12 texel
 samples; phase 1 with BC simulation of F_uv / F_uvt and noise on the sampled features;
-phase 2 fine-tunes the decoder on frozen features as a decode sees them.  Export (BC4
-blocks, 8-bit planes, FP16 decoder), decode of all 26 frames through the page decoder at
+phase 2 fine-tunes the decoder on frozen features as a decode sees them.  Export (BC7
+mode-6 blocks as in the paper, or BC4 blocks per channel; 8-bit planes, FP16 decoder), decode of all 26 frames through the page decoder at
 their key times (FP16 and FP32 paths), inverse preprocessing, tiled PSNR (one 128^2 tile
 per frame).  The same run without the BC simulation in phase 1 is the simulation's
 ablation (Table 7 of the paper, on synthetic data).
@@ -96,10 +96,19 @@ def score(torch, N, ctx, tr, means, target_bits, keys):
     return out
 
 
+def _codec(args):
+    return 0 if getattr(args, "codec", "bc7") == "bc4" else 1
+
+
+def _bits(codec):
+    return 8 if codec == 1 else 16     # F_uv / F_uvt bits per texel: one BC7 block or four BC4 blocks
+
+
 def run_hfit(args, torch, N, I, ctx, profile="M", steps1=4000, steps2=1000):
     keys = I.lightmap_key_times(I.rng(6, I.P_MODEL, 1))
     target = tile_target(torch, I, keys)
-    init = I.hybrid_train_init(TILE, TILE, profile, len(keys), keys, I.rng(6, I.P_INIT))
+    codec = _codec(args)
+    init = I.hybrid_train_init(TILE, TILE, profile, len(keys), keys, I.rng(6, I.P_INIT), codec=codec)
     side, hidden = I.HYBRID_PROFILES[profile]
     runs = {}
     for name, bc in (("recipe", True), ("without_bc_simulation", False)):
@@ -111,14 +120,13 @@ def run_hfit(args, torch, N, I, ctx, profile="M", steps1=4000, steps2=1000):
     return {
         "metric": "hybrid-layout fit: tiled PSNR after export, train ms/step",
         "config": {"workload": f"one {TILE}x{TILE} tile of the synthetic 1024^2 temporal lightmap at 26 key times; "
-                               f"profile {profile} (F_uvt {side}^2 x 12 x 4, hidden {hidden}); batch {BATCH}, Adam "
+                               f"profile {profile} (F_uvt {side}^2 x 12 x 4, hidden {hidden}); "
+                               f"{'BC7 mode 6' if codec else 'BC4'} F_uv / F_uvt; batch {BATCH}, Adam "
                                f"lr {LR}; {steps1} steps with BC simulation and noise, {steps2} decoder fine-tune "
                                "steps on frozen features; gamma 2.2 + per-frame mean normalisation"},
-        "data": "synthetic",
+        "data": "synthetic", "codec": "bc7" if codec else "bc4",
         "train_params": int(runs["recipe"].get("n_params", 0)) or None,
-        "bits_per_texel_bc4": bits_per_texel_hybrid(TILE, TILE, len(keys), side, 12, (64, 64, 24), hidden, 16),
-        "bits_per_texel_bc7_accounting": bits_per_texel_hybrid(TILE, TILE, len(keys), side, 12, (64, 64, 24),
-                                                               hidden, 8),
+        "bits_per_texel": bits_per_texel_hybrid(TILE, TILE, len(keys), side, 12, (64, 64, 24), hidden, _bits(codec)),
         "runs": runs,
     }
 
@@ -148,7 +156,9 @@ def run_hfit_map(args, torch, N, I, ctx, profile="M", side=1024, steps1=6000, st
     tiles = full.view(frames, nt, TILE, nt, TILE, 3).permute(1, 3, 0, 2, 4, 5).reshape(M, frames, TILE, TILE, 3)
     tiles = tiles.contiguous()
     tgt, means = hybrid_normalize_target(ctx, tiles.view(M * frames, TILE, TILE, 3).view(torch.int16), GAMMA)
-    inits = [I.hybrid_train_init(TILE, TILE, profile, frames, keys, I.rng(7, I.P_INIT, m)) for m in range(M)]
+    codec = _codec(args)
+    inits = [I.hybrid_train_init(TILE, TILE, profile, frames, keys, I.rng(7, I.P_INIT, m), codec=codec)
+             for m in range(M)]
     tr = HybridTrainer(ctx, inits, lr_feat=LR, lr_mlp=LR, seed=1, per_model=BATCH)
     _log(f"hybrid map: {M} tile models, {tr.n_params / 1e6:.2f} M parameters")
     n_steps = steps1 + steps2
@@ -201,11 +211,11 @@ def run_hfit_map(args, torch, N, I, ctx, profile="M", side=1024, steps1=6000, st
     return {
         "metric": "hybrid-layout map fit: per-tile models trained together, tiled PSNR after export",
         "config": {"workload": f"{side}x{side} synthetic temporal lightmap at 26 key times as {M} tile models of "
-                               f"{TILE}^2, profile {profile}; batch {BATCH} per model, Adam lr {LR}; {steps1} steps with "
+                               f"{TILE}^2, profile {profile}, {'BC7 mode 6' if codec else 'BC4'} F_uv / F_uvt; "
+                               f"batch {BATCH} per model, Adam lr {LR}; {steps1} steps with "
                                f"BC simulation and noise, {steps2} decoder fine-tune steps"},
-        "data": "synthetic", "models": M, "train_params": int(tr.n_params),
+        "data": "synthetic", "codec": "bc7" if codec else "bc4", "models": M, "train_params": int(tr.n_params),
         "train_ms_per_step": train_ms / n_steps, "train_samples_per_s": M * BATCH * n_steps / (train_ms * 1e-3),
         "loss_curve": losses, "decode": out,
-        "bits_per_texel_bc4": bits_per_texel_hybrid(TILE, TILE, frames, s_uvt, 12, (64, 64, 24), hidden, 16),
-        "bits_per_texel_bc7_accounting": bits_per_texel_hybrid(TILE, TILE, frames, s_uvt, 12, (64, 64, 24), hidden, 8),
+        "bits_per_texel": bits_per_texel_hybrid(TILE, TILE, frames, s_uvt, 12, (64, 64, 24), hidden, _bits(codec)),
     }
