@@ -552,9 +552,24 @@ def hybrid_decode(model: dict, uvt: np.ndarray) -> np.ndarray:
     return hybrid_decode_f64(model, q[:, 0], q[:, 1], q[:, 2])
 
 
-def hybrid_decode_pages(models: list, reqs: list, page: int, dst: np.ndarray, pitch: int) -> int:
-    """Page decode of hybrid models (same request convention as :func:`decode_pages`)."""
+def mirror_texel(i, n: int):
+    """Mirror addressing of texel indices on a map of n texels (the graphics MIRROR mode:
+    the map reflected about its edges, so texel -1 - k is texel k and texel n + k is texel
+    n - 1 - k); one reflection, for indices in [-n, 2n)."""
+    i = np.asarray(i)
+    return np.where(i < 0, -1 - i, np.where(i >= n, 2 * n - 1 - i, i))
+
+
+def hybrid_decode_pages(models: list, reqs: list, page: int, dst: np.ndarray, pitch: int, border: int = 0) -> int:
+    """Page decode of hybrid models (same request convention as :func:`decode_pages`).
+
+    With a border of b texels (Sec. 6: tiles stored with a small border for hardware
+    filtering, padded by mirroring) a request writes a (page + 2b)^2 region: its texel
+    (i, j) is the decode at the texel centre of map texel (mirror_texel(page px - b + i, W),
+    mirror_texel(page py - b + j, H)).  Inside the map the border holds the neighbouring
+    texels; past the map's edge it mirrors the map (for a per-tile model, the tile)."""
     bad = 0
+    R = page + 2 * border
     for (m, px, py, t, off) in reqs:
         if not (0 <= m < len(models)):
             bad += 1
@@ -563,10 +578,14 @@ def hybrid_decode_pages(models: list, reqs: list, page: int, dst: np.ndarray, pi
         if px < 0 or py < 0 or page * (px + 1) > md["W"] or page * (py + 1) > md["H"]:
             bad += 1
             continue
-        _, _, u, v = page_texels(md, px, py, page)
+        jj, ii = np.meshgrid(np.arange(R), np.arange(R), indexing="ij")
+        x = mirror_texel(page * px - border + ii, md["W"])
+        y = mirror_texel(page * py - border + jj, md["H"])
+        u = (x + 0.5) / md["W"]
+        v = (y + 0.5) / md["H"]
         rgb = hybrid_decode_f64(md, u, v, np.full(u.shape, np.float64(np.float32(t))))
-        for j in range(page):
-            dst[off + j * pitch: off + j * pitch + page] = rgb[j]
+        for j in range(R):
+            dst[off + j * pitch: off + j * pitch + R] = rgb[j]
     return bad
 
 

@@ -182,6 +182,41 @@ def test_hybrid_page_decode_equals_texel_centre_queries():
     np.testing.assert_allclose(dst, O.hybrid_decode(m, q.astype(np.float32)), rtol=1e-13, atol=1e-15)
 
 
+def test_mirror_texel_is_numpys_symmetric_padding():
+    """Mirror addressing equals numpy's 'symmetric' padding of an index ramp (the edge
+    texel repeated, then the map reflected)."""
+    for n, b in ((8, 4), (128, 4), (37, 32), (5, 5)):
+        np.testing.assert_array_equal(O.mirror_texel(np.arange(-b, n + b), n),
+                                      np.pad(np.arange(n), b, mode="symmetric"))
+
+
+def test_bordered_pages_mirror_tiles_and_join_neighbours():
+    """A per-tile model's bordered page is its plain page padded symmetrically (the border
+    mirrors the tile, Sec. 6); on a map of several pages the border of an inner page holds
+    the neighbouring pages' texels, so the pages join without seams; the interior is the
+    plain page."""
+    b, t = 4, np.float32(0.63)
+    m = _model(keys=True)                                    # one 128^2 tile model
+    plain = np.zeros((128 * 128, 3))
+    O.hybrid_decode_pages([m], [(0, 0, 0, t, 0)], 128, plain, 128)
+    R = 128 + 2 * b
+    bord = np.zeros((R * R, 3))
+    assert O.hybrid_decode_pages([m], [(0, 0, 0, t, 0)], 128, bord, R, border=b) == 0
+    np.testing.assert_array_equal(bord.reshape(R, R, 3),
+                                  np.pad(plain.reshape(128, 128, 3), ((b, b), (b, b), (0, 0)), mode="symmetric"))
+    big = I.random_hybrid_model(256, 256, profile="L", plane=(64, 64, 6), config=31, uvt_side=(32, 32))
+    pages = np.zeros((256 * 256, 3))                          # the whole map as 2 x 2 plain pages
+    O.hybrid_decode_pages([big], [(0, px, py, t, py * 128 * 256 + px * 128) for py in (0, 1) for px in (0, 1)], 128,
+                          pages, 256)
+    full = pages.reshape(256, 256, 3)
+    bord = np.zeros((R * R, 3))
+    O.hybrid_decode_pages([big], [(0, 1, 0, t, 0)], 128, bord, R, border=b)
+    bord = bord.reshape(R, R, 3)
+    padded = np.pad(full, ((b, b), (b, b), (0, 0)), mode="symmetric")
+    np.testing.assert_array_equal(bord, padded[0:R, 128:128 + R])
+    np.testing.assert_array_equal(bord[b:b + 128, b:b + 128], full[0:128, 128:256])
+
+
 # ----------------------------------------------------------------- hybrid training pins
 def tiny_hybrid_state(hidden=16, seed=0, frames=3, keys=True, on_grid=False):
     """A small trainable hybrid state: 8 x 8 map, F_uvt 4 x 4 x 3, planes 4 x 3."""
