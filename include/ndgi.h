@@ -327,20 +327,28 @@ int ndgi_hybrid_decode(ndgi_ctx* ctx, const ndgi_hybrid_model* model, const floa
  *   widths: decoder widths among the requests' models, bit 0 = hidden 16, bit 1 = hidden
  *           64, 0 = either.  One persistent launch runs per width named; naming only the
  *           width in use saves the launch of the other.
+ *   border: 0..32 texels of border around each page (Sec. 6: tiles are stored with a
+ *           border for hardware filtering, padded by mirroring).  A request then writes a
+ *           (page + 2 border)^2 region at dst_offset with dst_pitch >= page + 2 border;
+ *           region texel (i, j) is the decode at map texel (mirror(page * page_x - border
+ *           + i, W), mirror(page * page_y - border + j, H)), mirror(i, n) = -1 - i below 0,
+ *           2n - 1 - i from n (the map reflected about its edges).  Inside the map the
+ *           border repeats the neighbouring texels; for a per-tile model it mirrors the tile.
  * A request whose model index or page is out of range, whose descriptor breaks the ranges
  * above, or whose decoder width is not in `widths`, is skipped and sets
- * NDGI_FLAG_BAD_PAGE_REQUEST.  Errors: INVALID_ARG (sizes, prec, widths, NULL pointers). */
+ * NDGI_FLAG_BAD_PAGE_REQUEST.  Errors: INVALID_ARG (sizes, prec, widths, border, pitch,
+ * NULL pointers). */
 int ndgi_hybrid_decode_pages(ndgi_ctx* ctx, const ndgi_hybrid_model* models_dev, int32_t n_models,
                              const ndgi_page_req* reqs_dev, const int32_t* n_reqs_dev, int32_t max_reqs,
                              int32_t page, void* dst, int64_t dst_pitch, int32_t prec, int32_t widths,
-                             hipStream_t stream);
+                             int32_t border, hipStream_t stream);
 
 /* Same work launched as a HIP graph owned by the context (captured on the first call for
  * an argument set, replayed afterwards), as ndgi_decode_pages_graph. */
 int ndgi_hybrid_decode_pages_graph(ndgi_ctx* ctx, const ndgi_hybrid_model* models_dev, int32_t n_models,
                                    const ndgi_page_req* reqs_dev, const int32_t* n_reqs_dev,
                                    int32_t max_reqs, int32_t page, void* dst, int64_t dst_pitch,
-                                   int32_t prec, int32_t widths, hipStream_t stream);
+                                   int32_t prec, int32_t widths, int32_t border, hipStream_t stream);
 
 /* Trainable state of n_models hybrid models of equal sizes (Sec. 3.4, Eq. 6-8; Sec. 4; the
  * paper trains one model per virtual-texture tile).  Per model the feature block is

@@ -249,15 +249,18 @@ int ndgi_hybrid_decode(ndgi_ctx* c, const ndgi_hybrid_model* m, const float* uvt
 
 static int check_hybrid_pages(ndgi_ctx* c, const ndgi_hybrid_model* models, int32_t n_models,
                               const ndgi_page_req* reqs, const int32_t* n_reqs, int32_t max_reqs, int32_t page,
-                              void* dst, int64_t pitch, int32_t prec, int32_t widths) {
+                              void* dst, int64_t pitch, int32_t prec, int32_t widths, int32_t border) {
   if (!c) return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: ctx is NULL");
   if (widths < 0 || widths > 3) return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: widths=%d not in 0..3", widths);
+  if (border < 0 || border > 32)
+    return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: border=%d not in 0..32", border);
   if (prec != NDGI_PREC_F32 && prec != NDGI_PREC_F16)
     return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: bad prec %d", prec);
   if (n_models < 0 || max_reqs < 0) return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: negative count");
   if (page < 32 || page > 4096 || (page & 31))
     return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: page=%d must be a multiple of 32 in [32, 4096]", page);
-  if (pitch < page) return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: dst_pitch=%lld < page", (long long)pitch);
+  if (pitch < page + 2 * border)
+    return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: dst_pitch=%lld < page + 2 border", (long long)pitch);
   if (!n_reqs || !dst || (n_models > 0 && !models) || (max_reqs > 0 && !reqs))
     return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: NULL pointer");
   return NDGI_OK;
@@ -265,24 +268,26 @@ static int check_hybrid_pages(ndgi_ctx* c, const ndgi_hybrid_model* models, int3
 
 int ndgi_hybrid_decode_pages(ndgi_ctx* c, const ndgi_hybrid_model* models, int32_t n_models,
                              const ndgi_page_req* reqs, const int32_t* n_reqs, int32_t max_reqs, int32_t page,
-                             void* dst, int64_t pitch, int32_t prec, int32_t widths, hipStream_t s) {
+                             void* dst, int64_t pitch, int32_t prec, int32_t widths, int32_t border,
+                             hipStream_t s) {
   clear_error();
-  int rc = check_hybrid_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, widths);
+  int rc = check_hybrid_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, widths, border);
   if (rc) return rc;
-  return launch_hybrid_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, widths, s);
+  return launch_hybrid_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, widths, border, s);
 }
 
 int ndgi_hybrid_decode_pages_graph(ndgi_ctx* c, const ndgi_hybrid_model* models, int32_t n_models,
                                    const ndgi_page_req* reqs, const int32_t* n_reqs, int32_t max_reqs,
                                    int32_t page, void* dst, int64_t pitch, int32_t prec, int32_t widths,
-                                   hipStream_t s) {
+                                   int32_t border, hipStream_t s) {
   clear_error();
-  int rc = check_hybrid_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, widths);
+  int rc = check_hybrid_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, widths, border);
   if (rc) return rc;
-  return launch_graph(c, GraphKey{1 + widths, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, s},
+  return launch_graph(c, GraphKey{1 + widths + 4 * border, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch,
+                                  prec, s},
                       [&](hipStream_t cs) {
                         return launch_hybrid_pages(c, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch,
-                                                   prec, widths, cs);
+                                                   prec, widths, border, cs);
                       });
 }
 

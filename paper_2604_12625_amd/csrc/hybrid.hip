@@ -350,15 +350,29 @@ __global__ __launch_bounds__(256) void k_hybrid_query(ndgi_hybrid_model m, const
 // then each pass of a wave decodes two rows of 32 texel centres: the F_uv texel straight
 // from its block (at a texel centre the bilinear weights are 1 and 0), the other maps from
 // LDS.  Texel-centre axes use exact integer arithmetic (texel_axis).
+// With a border of b texels a request's output region is (page + 2b)^2 (sub-tiles of the
+// last row and column are partly outside it); region texel i stands for map texel
+// mirror(page * px - b + i), so a sub-tile's map texels still span at most 32 per axis.
 constexpr int kHybSub = 32;
 constexpr int kHybWin = kHybSub + 1;
+constexpr int kHybMaxBorder = 32;
+
+// Mirror addressing of a texel index on n texels (one reflection: -n <= i < 2n).
+__device__ __forceinline__ int mirror_texel(int i, int n) { return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i); }
+
+// Map-texel span [lo, hi] of region positions a..e (a <= e) under mirror addressing.
+__device__ __forceinline__ void mirror_span(int a, int e, int n, int& lo, int& hi) {
+  const int fa = mirror_texel(a, n), fe = mirror_texel(e, n);
+  lo = a < 0 ? 0 : min(fa, fe);
+  hi = e >= n ? n - 1 : max(fa, fe);
+}
 
 template <int PREC, int HD>
 __global__ __launch_bounds__(256) void k_hybrid_pages(const ndgi_hybrid_model* __restrict__ models, int32_t n_models,
                                                        const ndgi_page_req* __restrict__ reqs,
                                                        const int32_t* __restrict__ n_reqs_dev, int32_t max_reqs,
                                                        int32_t page, void* __restrict__ dst, int64_t pitch,
-                                                       int32_t widths, uint32_t* __restrict__ flags) {
+                                                       int32_t widths, int32_t border, uint32_t* __restrict__ flags) {
   __shared__ HybTab<HD> tab;
   __shared__ f4v win[kHybWin * kHybWin];
   __shared__ float2 line_u[kHybWin], line_v[kHybWin];
@@ -368,7 +382,8 @@ __global__ __launch_bounds__(256) void k_hybrid_pages(const ndgi_hybrid_model* _
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int n_req = *n_reqs_dev;
   n_req = n_req < 0 ? 0 : (n_req > max_reqs ? max_reqs : n_req);
-  const int side = page / kHybSub;
+  const int reg = page + 2 * border;                    // output region side
+  const int side = (reg + kHybSub - 1) / kHybSub;
   const int64_t per_req = (int64_t)side * side;
   const int64_t total = (int64_t)n_req * per_req;
   // each workgroup takes a contiguous run of items (equal cost), so consecutive items
@@ -398,15 +413,21 @@ __global__ __launch_bounds__(256) void k_hybrid_pages(const ndgi_hybrid_model* _
     }
     const bool bad_t = !isfinite(rq.t);
     const HybTime ht = hyb_time(m, bad_t ? 0.0f : rq.t, [&](int i) { return skeys[i]; });
-    const int px0 = page * rq.page_x, py0 = page * rq.page_y;
-    const int x0 = px0 + (s % side) * kHybSub, y0 = py0 + (s / side) * kHybSub;
+    // region origin of the sub-tile, its extent inside the region, the map position of
+    // region texel 0 and the sub-tile's map-texel spans
+    const int i0 = (s % side) * kHybSub, j0 = (s / side) * kHybSub;
+    const int ni = min(kHybSub, reg - i0), nj = min(kHybSub, reg - j0);
+    const int mx0 = page * rq.page_x - border, my0 = page * rq.page_y - border;
+    int xlo, xhi, ylo, yhi;
+    mirror_span(mx0 + i0, mx0 + i0 + ni - 1, m.W, xlo, xhi);
+    mirror_span(my0 + j0, my0 + j0 + nj - 1, m.H, ylo, yhi);
     // node spans of the sub-tile; clamped to the LDS window (never reached when Gu <= W)
-    const int wx0 = texel_axis<false>(x0, m.Gu, m.W).i0, wy0 = texel_axis<false>(y0, m.Gv, m.H).i0;
-    const int nwx = min(texel_axis<false>(x0 + kHybSub - 1, m.Gu, m.W).i1 - wx0 + 1, kHybWin);
-    const int nwy = min(texel_axis<false>(y0 + kHybSub - 1, m.Gv, m.H).i1 - wy0 + 1, kHybWin);
-    const int ua0 = texel_axis<false>(x0, m.U, m.W).i0, va0 = texel_axis<false>(y0, m.V, m.H).i0;
-    const int nua = min(texel_axis<false>(x0 + kHybSub - 1, m.U, m.W).i1 - ua0 + 1, kHybWin);
-    const int nva = min(texel_axis<false>(y0 + kHybSub - 1, m.V, m.H).i1 - va0 + 1, kHybWin);
+    const int wx0 = texel_axis<false>(xlo, m.Gu, m.W).i0, wy0 = texel_axis<false>(ylo, m.Gv, m.H).i0;
+    const int nwx = min(texel_axis<false>(xhi, m.Gu, m.W).i1 - wx0 + 1, kHybWin);
+    const int nwy = min(texel_axis<false>(yhi, m.Gv, m.H).i1 - wy0 + 1, kHybWin);
+    const int ua0 = texel_axis<false>(xlo, m.U, m.W).i0, va0 = texel_axis<false>(ylo, m.V, m.H).i0;
+    const int nua = min(texel_axis<false>(xhi, m.U, m.W).i1 - ua0 + 1, kHybWin);
+    const int nva = min(texel_axis<false>(yhi, m.V, m.H).i1 - va0 + 1, kHybWin);
     {
       const uint32_t fpb = m.codec ? 16u : 32u;
       const uint32_t gbw = (uint32_t)m.Gu >> 2, slice = gbw * ((uint32_t)m.Gv >> 2) * fpb;
@@ -439,7 +460,8 @@ __global__ __launch_bounds__(256) void k_hybrid_pages(const ndgi_hybrid_model* _
       if (t >= 128 && t < 128 + 2 * kHybSub) {   // the axes of the sub-tile's rows
         const int j = (t - 128) & (kHybSub - 1);
         const bool isg = t < 128 + kHybSub;
-        const Axis a = isg ? texel_axis<false>(y0 + j, m.Gv, m.H) : texel_axis<false>(y0 + j, m.V, m.H);
+        const int yj = mirror_texel(my0 + j0 + min(j, nj - 1), m.H);
+        const Axis a = isg ? texel_axis<false>(yj, m.Gv, m.H) : texel_axis<false>(yj, m.V, m.H);
         const int o0 = isg ? wy0 : va0, nn = isg ? nwy : nva;
         const int4 e = make_int4(min(max(a.i0 - o0, 0), nn - 1), min(max(a.i1 - o0, 0), nn - 1), __float_as_int(a.w1), 0);
         if (isg) rows_g[j] = e;
@@ -447,7 +469,8 @@ __global__ __launch_bounds__(256) void k_hybrid_pages(const ndgi_hybrid_model* _
       }
     }
     __syncthreads();                // table and windows complete
-    const int x = x0 + (lane & 31);
+    const int ci = min(lane & 31, ni - 1);             // region column (clamped into the region)
+    const int x = mirror_texel(mx0 + i0 + ci, m.W);
     const Axis gx = texel_axis<false>(x, m.Gu, m.W), ux = texel_axis<false>(x, m.U, m.W);
     const int gx0 = min(max(gx.i0 - wx0, 0), nwx - 1), gx1 = min(max(gx.i1 - wx0, 0), nwx - 1);
     const float2 ut0 = line_u[min(max(ux.i0 - ua0, 0), nua - 1)], ut1 = line_u[min(max(ux.i1 - ua0, 0), nua - 1)];
@@ -455,13 +478,15 @@ __global__ __launch_bounds__(256) void k_hybrid_pages(const ndgi_hybrid_model* _
     const uint32_t fbw = (uint32_t)m.W >> 2;
     // the F_uv footprint of the next pass is loaded while this one decodes
     const uint32_t ffb = m.codec ? 16u : 32u;
-    auto fp_of = [&](int p) { return m.fuv + ((uint32_t)((y0 + 2 * p + (lane >> 5)) >> 2) * fbw + (uint32_t)(x >> 2)) * ffb; };
+    auto row_of = [&](int p) { return mirror_texel(my0 + j0 + min(2 * p + (lane >> 5), nj - 1), m.H); };
+    auto fp_of = [&](int p) { return m.fuv + ((uint32_t)(row_of(p) >> 2) * fbw + (uint32_t)(x >> 2)) * ffb; };
     // a BC7 footprint is one 16-byte block (fb unused)
     u4v fa = ((const u4v*)fp_of(wave))[0], fb = m.codec ? fa : ((const u4v*)fp_of(wave))[1];
-    for (int p = wave; p < kHybSub * kHybSub / 64; p += 4) {
-      const int j = 2 * p + (lane >> 5), y = y0 + j;
+    const int passes = (nj + 1) >> 1;               // two rows per pass
+    for (int p = wave; p < passes; p += 4) {
+      const int j = min(2 * p + (lane >> 5), nj - 1), y = row_of(p);
       const u4v ca = fa, cb = fb;
-      if (p + 4 < kHybSub * kHybSub / 64) {
+      if (p + 4 < passes) {
         fa = ((const u4v*)fp_of(p + 4))[0];
         fb = m.codec ? fa : ((const u4v*)fp_of(p + 4))[1];
       }
@@ -491,7 +516,8 @@ __global__ __launch_bounds__(256) void k_hybrid_pages(const ndgi_hybrid_model* _
 #pragma unroll
       for (int c = 0; c < 4; ++c) rr[3][c] = ht.g[c];
       const f4v acc = hyb_decode<PREC, HD>(tab, rr, lane);
-      store_lin<PREC>(dst, (size_t)(rq.dst_offset + (int64_t)(y - py0) * pitch + (x - px0)), acc, bad_t);
+      if ((lane & 31) < ni && 2 * p + (lane >> 5) < nj)
+        store_lin<PREC>(dst, (size_t)(rq.dst_offset + (int64_t)(j0 + j) * pitch + (i0 + (lane & 31))), acc, bad_t);
     }
   }
 }
@@ -539,12 +565,12 @@ int launch_hybrid_query(ndgi_ctx* ctx, const ndgi_hybrid_model& m, const float* 
 
 int launch_hybrid_pages(ndgi_ctx* ctx, const ndgi_hybrid_model* models, int32_t n_models, const ndgi_page_req* reqs,
                         const int32_t* n_reqs, int32_t max_reqs, int32_t page, void* dst, int64_t pitch, int prec,
-                        int32_t widths, hipStream_t s) {
+                        int32_t widths, int32_t border, hipStream_t s) {
   // one launch per decoder width present; each skips the requests of the other
   if (widths == 0) widths = 3;
 #define NDGI_HP(P, HD)                                                                                           \
   hipLaunchKernelGGL((k_hybrid_pages<P, HD>), dim3(resident_wgs(ctx, (const void*)k_hybrid_pages<P, HD>)), dim3(256), \
-                     0, s, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, widths, ctx->flags_dev)
+                     0, s, models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, widths, border, ctx->flags_dev)
   if (prec == NDGI_PREC_F16) {
     if (widths & 1) NDGI_HP(NDGI_PREC_F16, 16);
     if (widths & 2) NDGI_HP(NDGI_PREC_F16, 64);

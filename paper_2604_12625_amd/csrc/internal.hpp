@@ -22,7 +22,7 @@ void clear_error();
     if (e_ != hipSuccess) return ::ndgi::fail(NDGI_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-// (layout kind: 0 ndgi_model, 1 + widths hybrid; models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, stream)
+// (layout kind: 0 ndgi_model, 1 + widths + 4 border hybrid; models, n_models, reqs, n_reqs, max_reqs, page, dst, pitch, prec, stream)
 using GraphKey = std::tuple<int, const void*, int32_t, const void*, const void*, int32_t, int32_t,
                             void*, int64_t, int32_t, hipStream_t>;
 
@@ -71,5 +71,5 @@ int launch_hybrid_query(ndgi_ctx* ctx, const ndgi_hybrid_model& m, const float* 
                         hipStream_t s);
 int launch_hybrid_pages(ndgi_ctx* ctx, const ndgi_hybrid_model* models, int32_t n_models, const ndgi_page_req* reqs,
                         const int32_t* n_reqs, int32_t max_reqs, int32_t page, void* dst, int64_t pitch, int prec,
-                        int32_t widths, hipStream_t s);
+                        int32_t widths, int32_t border, hipStream_t s);
 }  // namespace ndgi

@@ -123,7 +123,7 @@ def lib():
         L.ndgi_hybrid_mlp_size.argtypes = [i32]
         L.ndgi_hybrid_mlp_size.restype = i32
         L.ndgi_hybrid_decode.argtypes = [vp, C.POINTER(NdgiHybridModel), vp, i64, vp, i32, vp]
-        hpages = [vp, vp, i32, vp, vp, i32, i32, vp, i64, i32, i32, vp]
+        hpages = [vp, vp, i32, vp, vp, i32, i32, vp, i64, i32, i32, i32, vp]
         L.ndgi_hybrid_decode_pages.argtypes = hpages
         L.ndgi_hybrid_decode_pages_graph.argtypes = hpages
         L.ndgi_hybrid_train_param_count.argtypes = [i32] * 10
@@ -280,11 +280,12 @@ class Context:
         return out
 
     def hybrid_decode_pages(self, models_dev, n_models, reqs_dev, n_reqs_dev, max_reqs, page, dst,
-                            pitch, prec=PREC_F16, widths=0, graph=False, stream=None):
-        """widths: bit 0 = models of hidden width 16 present, bit 1 = width 64; 0 = either."""
+                            pitch, prec=PREC_F16, widths=0, border=0, graph=False, stream=None):
+        """widths: bit 0 = models of hidden width 16 present, bit 1 = width 64; 0 = either.
+        border: texels of mirrored border around each page (regions of (page + 2 border)^2)."""
         f = lib().ndgi_hybrid_decode_pages_graph if graph else lib().ndgi_hybrid_decode_pages
         check(f(self.h, _ptr(models_dev), n_models, _ptr(reqs_dev), _ptr(n_reqs_dev), max_reqs,
-                page, _ptr(dst), pitch, prec, widths, _stream(stream)), "ndgi_hybrid_decode_pages")
+                page, _ptr(dst), pitch, prec, widths, border, _stream(stream)), "ndgi_hybrid_decode_pages")
         return dst
 
     def set_launch(self, tile_w, tile_h, waves_per_cu):

@@ -142,7 +142,7 @@ def _hyb_vt(seed):
     return models, reqs
 
 
-def _run_hpages(N, ctx, models, reqs, prec, graph=False, widths=0):
+def _run_hpages(N, ctx, models, reqs, prec, graph=False, widths=0, border=0, rows=None):
     import torch
     hms = [N.HybridModel.from_numpy(m) for m in models]
     marr = N.models_array(hms)
@@ -150,10 +150,11 @@ def _run_hpages(N, ctx, models, reqs, prec, graph=False, widths=0):
     rq = N.page_requests(r[:, 0].astype(np.int32), r[:, 1].astype(np.int32), r[:, 2].astype(np.int32),
                          r[:, 3].astype(np.float32), r[:, 4].astype(np.int64))
     nreq = torch.tensor([len(reqs)], dtype=torch.int32, device="cuda")
-    rows = (len(reqs) + 7) // 8 * 128
+    rows = rows or (len(reqs) + 7) // 8 * 128
     dt = torch.float16 if prec else torch.float32
     dst = torch.full((rows * 1024, 3), -7.0, dtype=dt, device="cuda")
-    ctx.hybrid_decode_pages(marr, len(models), rq, nreq, len(reqs), 128, dst, 1024, prec, widths=widths, graph=graph)
+    ctx.hybrid_decode_pages(marr, len(models), rq, nreq, len(reqs), 128, dst, 1024, prec, widths=widths,
+                            border=border, graph=graph)
     torch.cuda.synchronize()
     return dst.float().cpu().numpy(), (hms, marr, rq, nreq, dst)
 
@@ -234,6 +235,60 @@ def test_hybrid_pages_nan_time_and_page_size(N, ctx):
     for page in (16, 48, 8192):
         with pytest.raises(N.NdgiError):
             ctx.hybrid_decode_pages(marr, 1, rq, nreq, 1, page, dst, 128, 1)
+
+
+def _bordered(reqs, border):
+    """Requests re-addressed to non-overlapping (128 + 2 border)^2 regions in a 1024-wide
+    destination; returns (requests, destination rows)."""
+    R = 128 + 2 * border
+    per = 1024 // R
+    out = [(m, px, py, t, (r // per) * R * 1024 + (r % per) * R) for r, (m, px, py, t, _) in enumerate(reqs)]
+    return out, (len(reqs) + per - 1) // per * R
+
+
+@pytest.mark.parametrize("border", [4, 1, 32])
+@pytest.mark.parametrize("prec", [1, 0])
+def test_hybrid_pages_with_mirrored_border(N, ctx, border, prec):
+    """Bordered regions (ragged sub-tiles, mirror addressing at map edges, neighbours inside
+    the map) over per-tile models of both codecs and widths and two 256^2 maps."""
+    models, reqs = _hyb_vt(6)
+    models[2] = I.random_hybrid_model(profile="H", config=83, index=2, codec=1)
+    models[3] = I.random_hybrid_model(profile="M.64", config=83, index=3, codec=1)
+    reqs, rows = _bordered(reqs, border)
+    out, _ = _run_hpages(N, ctx, models, reqs, prec, border=border, rows=rows)
+    ref = np.full(out.shape, -7.0)
+    assert O.hybrid_decode_pages(models, reqs, 128, ref, 1024, border=border) == 3
+    assert ctx.error_flags() & N.FLAG_BAD_PAGE_REQUEST
+    valid = ref[:, 0] != -7.0
+    assert_close(out[valid], ref[valid], TOL[prec], f"border {border}")
+    np.testing.assert_array_equal(out[~valid], -7.0)
+
+
+def test_hybrid_pages_border_graph_and_errors(N, ctx):
+    import torch
+    ctx.error_flags()
+    models, reqs = _hyb_vt(7)
+    reqs = [r for i, r in enumerate(reqs) if i not in (5, 11, 17)][:20]
+    reqs, rows = _bordered(reqs, 4)
+    out, keep = _run_hpages(N, ctx, models, reqs, 1, graph=True, border=4, rows=rows)    # capture
+    hms, marr, rq, nreq, dst = keep
+    ref = np.full(out.shape, -7.0)
+    O.hybrid_decode_pages(models, reqs, 128, ref, 1024, border=4)
+    v = ref[:, 0] != -7.0
+    for rep in range(3):
+        if rep:              # replays into a cleared destination
+            dst.fill_(-7.0)
+            ctx.hybrid_decode_pages(marr, len(models), rq, nreq, len(reqs), 128, dst, 1024, 1, border=4, graph=True)
+            torch.cuda.synchronize()
+            out = dst.float().cpu().numpy()
+        assert_close(out[v], ref[v], TOL[1], f"bordered graph, run {rep}")
+        np.testing.assert_array_equal(out[~v], -7.0)
+    for border, pitch in ((-1, 1024), (33, 1024), (4, 135), (32, 191)):
+        with pytest.raises(N.NdgiError):
+            ctx.hybrid_decode_pages(marr, len(models), rq, nreq, len(reqs), 128, dst, pitch, 1, border=border)
+    ctx.hybrid_decode_pages(marr, len(models), rq, nreq, len(reqs), 128, dst, 136, 1, border=4)
+    torch.cuda.synchronize()
+    assert ctx.error_flags() == 0
 
 
 @pytest.mark.parametrize("profile", ["M", "M.64"])
