@@ -223,38 +223,47 @@ def run_hybrid(args, torch, N, I, ctx, reps=30, warm=5):
     128 x 128 texels (F_uv 128^2 x 4 and F_uvt side^2 x 12 x 4 as BC7 mode-6 blocks, the
     paper's format, or as four BC4 blocks per footprint; F_ut / F_vt 64 x 24 x 2 8-bit; 26
     key times), all 64 pages decoded at one t in one persistent launch, for each profile of
-    Table 3, both codecs and both precisions."""
+    Table 3, both codecs and both precisions; and profile M with the 4-texel mirrored tile
+    border of the paper's VT storage (64 regions of 136^2)."""
     import numpy as np
     out = {}
     idx = np.arange(64)
-    offs = ((idx // 8) * 128 * 1024 + (idx % 8) * 128).astype(np.int64)
-    for prof, codec in (("L", 1), ("M", 1), ("H", 1), ("M.64", 1), ("L", 0), ("M", 0), ("H", 0), ("M.64", 0)):
+    rows = (("L", 1, 0), ("M", 1, 0), ("H", 1, 0), ("M.64", 1, 0), ("L", 0, 0), ("M", 0, 0), ("H", 0, 0),
+            ("M.64", 0, 0), ("M", 1, 4))
+    for prof, codec, border in rows:
+        R = 128 + 2 * border
+        pitch = 8 * R
+        offs = ((idx // 8) * R * pitch + (idx % 8) * R).astype(np.int64)
         models = [N.HybridModel.from_numpy(I.random_hybrid_model(profile=prof, config=6, index=i, codec=codec))
                   for i in range(64)]
         marr = N.models_array(models)
         rq = N.page_requests(idx.astype(np.int32), np.zeros(64, np.int32), np.zeros(64, np.int32),
                              np.full(64, 0.4375, np.float32), offs)
         nreq = torch.tensor([64], dtype=torch.int32, device="cuda")
-        row = {"codec": "bc7" if codec else "bc4"}
+        row = {"codec": "bc7" if codec else "bc4", "border": border, "texels": 64 * R * R}
         for prec, name in ((N.PREC_F16, "f16"), (N.PREC_F32, "f32")):
-            dst = torch.empty((1024 * 1024, 3), dtype=torch.float16 if prec == N.PREC_F16 else torch.float32,
+            dst = torch.empty((pitch * pitch, 3), dtype=torch.float16 if prec == N.PREC_F16 else torch.float32,
                               device="cuda")
             widths = 2 if I.HYBRID_PROFILES[prof][1] == 64 else 1
+
+            def call():
+                ctx.hybrid_decode_pages(marr, 64, rq, nreq, 64, 128, dst, pitch, prec, widths=widths, border=border)
             for _ in range(warm):
-                ctx.hybrid_decode_pages(marr, 64, rq, nreq, 64, 128, dst, 1024, prec, widths=widths)
+                call()
             tm = Timer(torch)
             for _ in range(reps):
                 e = tm.start()
-                ctx.hybrid_decode_pages(marr, 64, rq, nreq, 64, 128, dst, 1024, prec, widths=widths)
+                call()
                 tm.stop(e)
             torch.cuda.synchronize()
             ms = sorted(tm.ms())[reps // 2]
             row[f"{name}_ms"] = ms
-            row[f"{name}_texels_per_s"] = 1024 * 1024 / (ms * 1e-3)
-        if prof in PAPER_TABLE5_MS:
+            row[f"{name}_texels_per_s"] = 64 * R * R / (ms * 1e-3)
+        if prof in PAPER_TABLE5_MS and not border:
             row["paper_rtx4060_ms"] = PAPER_TABLE5_MS[prof]
-        log(f"hybrid 1024^2 {prof} {row['codec']}: FP16 {row['f16_ms'] * 1e3:.1f} us, FP32 {row['f32_ms'] * 1e3:.1f} us")
-        out[prof if codec else prof + ".bc4"] = row
+        key = prof + ("" if codec else ".bc4") + (f".border{border}" if border else "")
+        log(f"hybrid 1024^2 {key}: FP16 {row['f16_ms'] * 1e3:.1f} us, FP32 {row['f32_ms'] * 1e3:.1f} us")
+        out[key] = row
     assert ctx.error_flags() == 0
     return out
 
@@ -330,6 +339,7 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c2", "c5", "hfit", "hmap"])
     ap.add_argument("--codec", default="bc7", choices=["bc7", "bc4"],
                     help="block format of F_uv / F_uvt for the hfit and hmap workloads")
+    ap.add_argument("--border", type=int, default=4, help="mirrored tile border (texels) of the hmap workload")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--random-path", default="binned", choices=["binned", "direct"],
                     help="decode of the random queries: tile-binned (default) or in arrival order")

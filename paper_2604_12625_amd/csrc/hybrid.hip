@@ -342,20 +342,22 @@ __global__ __launch_bounds__(256) void k_hybrid_query(ndgi_hybrid_model m, const
 }
 
 // ---------------------------------------------------------------------- page decode
-// Work item = (request, 32 x 32 sub-tile of its page), one workgroup per item over a
-// persistent grid.  Per item the workgroup stages in LDS:
+// A request writes a region of (page + 2b)^2 texels (b = border); region texel i stands
+// for map texel mirror(page * px - b + i), so the border repeats the neighbouring texels
+// inside the map and mirrors the map past its edges.  The region is cut into side x side
+// sub-tiles of at most 34 x 34 texels (side = ceil(region / 34): a 128 page is 4 x 4
+// sub-tiles of 32^2, a 136 region with a 4-texel border 4 x 4 of 34^2), and a work item
+// is (request, sub-tile), one workgroup per item over a persistent grid.  Per item the
+// workgroup stages in LDS:
 //  * the F_uvt nodes the sub-tile reads, decoded from both slices around tau and blended
-//    in time (at most 33 x 33 nodes, since Gu <= W and Gv <= H);
-//  * the F_ut row span and the F_vt column span it reads, blended in time;
-// then each pass of a wave decodes two rows of 32 texel centres: the F_uv texel straight
-// from its block (at a texel centre the bilinear weights are 1 and 0), the other maps from
-// LDS.  Texel-centre axes use exact integer arithmetic (texel_axis).
-// With a border of b texels a request's output region is (page + 2b)^2 (sub-tiles of the
-// last row and column are partly outside it); region texel i stands for map texel
-// mirror(page * px - b + i), so a sub-tile's map texels still span at most 32 per axis.
-constexpr int kHybSub = 32;
+//    in time (at most 35 x 35 nodes, since Gu <= W and Gv <= H);
+//  * per sub-tile column: its F_uvt taps and weight and its V_ut (F_ut blended in time,
+//    then along u); per row: its F_uvt taps and weight and its V_vt;
+// then each pass of a wave decodes 64 consecutive texels of the sub-tile (row-major): the
+// F_uv texel straight from its block (at a texel centre the bilinear weights are 1 and
+// 0), the rest from LDS.  Texel-centre axes use exact integer arithmetic (texel_axis).
+constexpr int kHybSub = 34;
 constexpr int kHybWin = kHybSub + 1;
-constexpr int kHybMaxBorder = 32;
 
 // Mirror addressing of a texel index on n texels (one reflection: -n <= i < 2n).
 __device__ __forceinline__ int mirror_texel(int i, int n) { return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i); }
@@ -367,6 +369,18 @@ __device__ __forceinline__ void mirror_span(int a, int e, int n, int& lo, int& h
   hi = e >= n ? n - 1 : max(fa, fe);
 }
 
+// Plane value (2 channels, / 255) of an 8-bit [N][size][2] plane at axis a, time rows k:
+// blended in time first, then along the axis.
+__device__ __forceinline__ float2 plane_at(const uint16_t* pl, uint32_t size, const Axis& a, const NodeT& k) {
+  const uint32_t q00 = pl[(uint32_t)k.i0 * size + (uint32_t)a.i0], q01 = pl[(uint32_t)k.i1 * size + (uint32_t)a.i0];
+  const uint32_t q10 = pl[(uint32_t)k.i0 * size + (uint32_t)a.i1], q11 = pl[(uint32_t)k.i1 * size + (uint32_t)a.i1];
+  const float2 v0 = make_float2(fmaf(k.w1, (float)(q01 & 0xffu), k.w0 * (float)(q00 & 0xffu)) * (1.0f / 255.0f),
+                                fmaf(k.w1, (float)(q01 >> 8), k.w0 * (float)(q00 >> 8)) * (1.0f / 255.0f));
+  const float2 v1 = make_float2(fmaf(k.w1, (float)(q11 & 0xffu), k.w0 * (float)(q10 & 0xffu)) * (1.0f / 255.0f),
+                                fmaf(k.w1, (float)(q11 >> 8), k.w0 * (float)(q10 >> 8)) * (1.0f / 255.0f));
+  return make_float2(fmaf(a.w1, v1.x, a.w0 * v0.x), fmaf(a.w1, v1.y, a.w0 * v0.y));
+}
+
 template <int PREC, int HD>
 __global__ __launch_bounds__(256) void k_hybrid_pages(const ndgi_hybrid_model* __restrict__ models, int32_t n_models,
                                                        const ndgi_page_req* __restrict__ reqs,
@@ -375,15 +389,16 @@ __global__ __launch_bounds__(256) void k_hybrid_pages(const ndgi_hybrid_model* _
                                                        int32_t widths, int32_t border, uint32_t* __restrict__ flags) {
   __shared__ HybTab<HD> tab;
   __shared__ f4v win[kHybWin * kHybWin];
-  __shared__ float2 line_u[kHybWin], line_v[kHybWin];
   __shared__ float skeys[NDGI_HYBRID_MAX_KEYS];
-  __shared__ int4 rows_g[kHybSub], rows_v[kHybSub];   // per sub-tile row: window taps and weight
+  __shared__ int4 rows_g[kHybSub], cols_g[kHybSub];     // F_uvt window taps and weight
+  __shared__ float2 rows_v[kHybSub], cols_u[kHybSub];   // V_vt per row, V_ut per column
   static_assert(NDGI_HYBRID_MAX_KEYS <= 256, "one key per thread");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int n_req = *n_reqs_dev;
   n_req = n_req < 0 ? 0 : (n_req > max_reqs ? max_reqs : n_req);
   const int reg = page + 2 * border;                    // output region side
   const int side = (reg + kHybSub - 1) / kHybSub;
+  const int sub = (reg + side - 1) / side;              // sub-tile side, <= kHybSub
   const int64_t per_req = (int64_t)side * side;
   const int64_t total = (int64_t)n_req * per_req;
   // each workgroup takes a contiguous run of items (equal cost), so consecutive items
@@ -415,8 +430,8 @@ __global__ __launch_bounds__(256) void k_hybrid_pages(const ndgi_hybrid_model* _
     const HybTime ht = hyb_time(m, bad_t ? 0.0f : rq.t, [&](int i) { return skeys[i]; });
     // region origin of the sub-tile, its extent inside the region, the map position of
     // region texel 0 and the sub-tile's map-texel spans
-    const int i0 = (s % side) * kHybSub, j0 = (s / side) * kHybSub;
-    const int ni = min(kHybSub, reg - i0), nj = min(kHybSub, reg - j0);
+    const int i0 = (s % side) * sub, j0 = (s / side) * sub;
+    const int ni = min(sub, reg - i0), nj = min(sub, reg - j0);
     const int mx0 = page * rq.page_x - border, my0 = page * rq.page_y - border;
     int xlo, xhi, ylo, yhi;
     mirror_span(mx0 + i0, mx0 + i0 + ni - 1, m.W, xlo, xhi);
@@ -425,9 +440,6 @@ __global__ __launch_bounds__(256) void k_hybrid_pages(const ndgi_hybrid_model* _
     const int wx0 = texel_axis<false>(xlo, m.Gu, m.W).i0, wy0 = texel_axis<false>(ylo, m.Gv, m.H).i0;
     const int nwx = min(texel_axis<false>(xhi, m.Gu, m.W).i1 - wx0 + 1, kHybWin);
     const int nwy = min(texel_axis<false>(yhi, m.Gv, m.H).i1 - wy0 + 1, kHybWin);
-    const int ua0 = texel_axis<false>(xlo, m.U, m.W).i0, va0 = texel_axis<false>(ylo, m.V, m.H).i0;
-    const int nua = min(texel_axis<false>(xhi, m.U, m.W).i1 - ua0 + 1, kHybWin);
-    const int nva = min(texel_axis<false>(yhi, m.V, m.H).i1 - va0 + 1, kHybWin);
     {
       const uint32_t fpb = m.codec ? 16u : 32u;
       const uint32_t gbw = (uint32_t)m.Gu >> 2, slice = gbw * ((uint32_t)m.Gv >> 2) * fpb;
@@ -444,80 +456,86 @@ __global__ __launch_bounds__(256) void k_hybrid_pages(const ndgi_hybrid_model* _
         for (int c = 0; c < 4; ++c) o[c] = fmaf(ht.s.w1, b[c], ht.s.w0 * a[c]) * (1.0f / 255.0f);
         win[idx] = o;
       }
-      const uint16_t* fu = (const uint16_t*)m.fut;
-      const uint16_t* fv = (const uint16_t*)m.fvt;
+      // threads 0..sub-1: the sub-tile's columns; 64..64+sub-1: its rows
       const int t = threadIdx.x;
-      if (t < nua || (t >= 64 && t - 64 < nva)) {
-        const bool isu = t < 64;
-        const uint16_t* pl = isu ? fu : fv;
-        const uint32_t size = (uint32_t)(isu ? m.U : m.V), a = (uint32_t)(isu ? ua0 + t : va0 + t - 64);
-        const uint32_t q0 = pl[(uint32_t)ht.k.i0 * size + a], q1 = pl[(uint32_t)ht.k.i1 * size + a];
-        const float2 o = make_float2(fmaf(ht.k.w1, (float)(q1 & 0xffu), ht.k.w0 * (float)(q0 & 0xffu)) * (1.0f / 255.0f),
-                                     fmaf(ht.k.w1, (float)(q1 >> 8), ht.k.w0 * (float)(q0 >> 8)) * (1.0f / 255.0f));
-        if (isu) line_u[t] = o;
-        else line_v[t - 64] = o;
-      }
-      if (t >= 128 && t < 128 + 2 * kHybSub) {   // the axes of the sub-tile's rows
-        const int j = (t - 128) & (kHybSub - 1);
-        const bool isg = t < 128 + kHybSub;
-        const int yj = mirror_texel(my0 + j0 + min(j, nj - 1), m.H);
-        const Axis a = isg ? texel_axis<false>(yj, m.Gv, m.H) : texel_axis<false>(yj, m.V, m.H);
-        const int o0 = isg ? wy0 : va0, nn = isg ? nwy : nva;
+      if (t < sub || (t >= 64 && t - 64 < sub)) {
+        const bool isc = t < 64;
+        const int k = isc ? t : t - 64;
+        const int n = isc ? m.W : m.H, g = isc ? m.Gu : m.Gv, pn = isc ? m.U : m.V;
+        const int pos = mirror_texel(isc ? mx0 + i0 + min(k, ni - 1) : my0 + j0 + min(k, nj - 1), n);
+        const Axis a = texel_axis<false>(pos, g, n);
+        const int o0 = isc ? wx0 : wy0, nn = isc ? nwx : nwy;
         const int4 e = make_int4(min(max(a.i0 - o0, 0), nn - 1), min(max(a.i1 - o0, 0), nn - 1), __float_as_int(a.w1), 0);
-        if (isg) rows_g[j] = e;
-        else rows_v[j] = e;
+        const float2 pv = plane_at((const uint16_t*)(isc ? m.fut : m.fvt), (uint32_t)pn, texel_axis<false>(pos, pn, n),
+                                   ht.k);
+        if (isc) {
+          cols_g[k] = e;
+          cols_u[k] = pv;
+        } else {
+          rows_g[k] = e;
+          rows_v[k] = pv;
+        }
       }
     }
     __syncthreads();                // table and windows complete
-    const int ci = min(lane & 31, ni - 1);             // region column (clamped into the region)
-    const int x = mirror_texel(mx0 + i0 + ci, m.W);
-    const Axis gx = texel_axis<false>(x, m.Gu, m.W), ux = texel_axis<false>(x, m.U, m.W);
-    const int gx0 = min(max(gx.i0 - wx0, 0), nwx - 1), gx1 = min(max(gx.i1 - wx0, 0), nwx - 1);
-    const float2 ut0 = line_u[min(max(ux.i0 - ua0, 0), nua - 1)], ut1 = line_u[min(max(ux.i1 - ua0, 0), nua - 1)];
-    const float2 vut = make_float2(fmaf(ux.w1, ut1.x, ux.w0 * ut0.x), fmaf(ux.w1, ut1.y, ux.w0 * ut0.y));
     const uint32_t fbw = (uint32_t)m.W >> 2;
-    // the F_uv footprint of the next pass is loaded while this one decodes
     const uint32_t ffb = m.codec ? 16u : 32u;
-    auto row_of = [&](int p) { return mirror_texel(my0 + j0 + min(2 * p + (lane >> 5), nj - 1), m.H); };
-    auto fp_of = [&](int p) { return m.fuv + ((uint32_t)(row_of(p) >> 2) * fbw + (uint32_t)(x >> 2)) * ffb; };
-    // a BC7 footprint is one 16-byte block (fb unused)
-    u4v fa = ((const u4v*)fp_of(wave))[0], fb = m.codec ? fa : ((const u4v*)fp_of(wave))[1];
-    const int passes = (nj + 1) >> 1;               // two rows per pass
+    const int nt = ni * nj, passes = (nt + 63) >> 6;
+    const uint32_t mag = (65536u + (uint32_t)ni - 1u) / (uint32_t)ni;   // t / ni = (t * mag) >> 16 for t < 2^11
+    // texel of pass p for this lane (row-major in the sub-tile; the tail repeats the last)
+    auto texel_of = [&](int p, int& rj, int& ci) {
+      const int tt = min(p * 64 + lane, nt - 1);
+      rj = (int)(((uint32_t)tt * mag) >> 16);
+      ci = tt - rj * ni;
+    };
+    // its F_uv footprint (one 16-byte BC7 block or 32 bytes of BC4) and texel slot
+    auto footprint = [&](int rj, int ci, uint32_t& slot) {
+      const int x = mirror_texel(mx0 + i0 + ci, m.W), y = mirror_texel(my0 + j0 + rj, m.H);
+      slot = 4u * (uint32_t)(y & 3) + (uint32_t)(x & 3);
+      return (const u4v*)(m.fuv + ((uint32_t)(y >> 2) * fbw + (uint32_t)(x >> 2)) * ffb);
+    };
+    // the F_uv footprint of the next pass is loaded while this one decodes
+    int nr, nc;
+    uint32_t nslot;
+    texel_of(wave, nr, nc);
+    const u4v* nfp = footprint(nr, nc, nslot);
+    u4v fa = nfp[0], fb = m.codec ? fa : nfp[1];
     for (int p = wave; p < passes; p += 4) {
-      const int j = min(2 * p + (lane >> 5), nj - 1), y = row_of(p);
+      const int rj = nr, ci = nc;
+      const uint32_t slot = nslot;
       const u4v ca = fa, cb = fb;
       if (p + 4 < passes) {
-        fa = ((const u4v*)fp_of(p + 4))[0];
-        fb = m.codec ? fa : ((const u4v*)fp_of(p + 4))[1];
+        texel_of(p + 4, nr, nc);
+        nfp = footprint(nr, nc, nslot);
+        fa = nfp[0];
+        fb = m.codec ? fa : nfp[1];
       }
       float rr[4][4];
       // V_uvt: bilinear over the staged nodes
-      const int4 ag = rows_g[j];
-      const float gyw1 = __int_as_float(ag.z);
-      const f4v c00 = win[ag.x * nwx + gx0], c01 = win[ag.x * nwx + gx1];
-      const f4v c10 = win[ag.y * nwx + gx0], c11 = win[ag.y * nwx + gx1];
-      const float w[4] = {(1.0f - gyw1) * gx.w0, (1.0f - gyw1) * gx.w1, gyw1 * gx.w0, gyw1 * gx.w1};
+      const int4 ag = rows_g[rj], cg = cols_g[ci];
+      const float gyw1 = __int_as_float(ag.z), gxw1 = __int_as_float(cg.z), gxw0 = 1.0f - gxw1;
+      const f4v c00 = win[ag.x * nwx + cg.x], c01 = win[ag.x * nwx + cg.y];
+      const f4v c10 = win[ag.y * nwx + cg.x], c11 = win[ag.y * nwx + cg.y];
+      const float w[4] = {(1.0f - gyw1) * gxw0, (1.0f - gyw1) * gxw1, gyw1 * gxw0, gyw1 * gxw1};
 #pragma unroll
       for (int c = 0; c < 4; ++c) rr[0][c] = fmaf(w[3], c11[c], fmaf(w[2], c10[c], fmaf(w[1], c01[c], w[0] * c00[c])));
       // V_uv: the texel itself
       float sv[4];
-      if (m.codec) bc7_fp4_regs(ca, 4u * (uint32_t)(y & 3) + (uint32_t)(x & 3), sv);
-      else bc4_fp4_regs(ca, cb, 4u * (uint32_t)(y & 3) + (uint32_t)(x & 3), sv);
+      if (m.codec) bc7_fp4_regs(ca, slot, sv);
+      else bc4_fp4_regs(ca, cb, slot, sv);
 #pragma unroll
       for (int c = 0; c < 4; ++c) rr[1][c] = sv[c] * (1.0f / 255.0f);
       // V_ut (per column), V_vt (per row)
-      const int4 av = rows_v[j];
-      const float vyw1 = __int_as_float(av.z), vyw0 = 1.0f - vyw1;
-      const float2 vt0 = line_v[av.x], vt1 = line_v[av.y];
+      const float2 vut = cols_u[ci], vvt = rows_v[rj];
       rr[2][0] = vut.x;
       rr[2][1] = vut.y;
-      rr[2][2] = fmaf(vyw1, vt1.x, vyw0 * vt0.x);
-      rr[2][3] = fmaf(vyw1, vt1.y, vyw0 * vt0.y);
+      rr[2][2] = vvt.x;
+      rr[2][3] = vvt.y;
 #pragma unroll
       for (int c = 0; c < 4; ++c) rr[3][c] = ht.g[c];
       const f4v acc = hyb_decode<PREC, HD>(tab, rr, lane);
-      if ((lane & 31) < ni && 2 * p + (lane >> 5) < nj)
-        store_lin<PREC>(dst, (size_t)(rq.dst_offset + (int64_t)(j0 + j) * pitch + (i0 + (lane & 31))), acc, bad_t);
+      if (p * 64 + lane < nt)
+        store_lin<PREC>(dst, (size_t)(rq.dst_offset + (int64_t)(j0 + rj) * pitch + (i0 + ci)), acc, bad_t);
     }
   }
 }

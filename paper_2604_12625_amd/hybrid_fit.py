@@ -144,7 +144,10 @@ def bits_per_texel_hybrid(W, H, frames, side, slices, plane, hidden, uv_bits_per
 def run_hfit_map(args, torch, N, I, ctx, profile="M", side=1024, steps1=6000, steps2=2000):
     """The paper's production setting: a side x side lightmap as (side/128)^2 per-tile models,
     trained together in one launch per step (4096 samples per model), exported, and decoded
-    for all 26 frames through the page decoder (one request per tile and frame, one launch)."""
+    for all 26 frames through the page decoder (one request per tile and frame, one launch).
+    Tiles carry a mirrored border of `--border` texels (Sec. 6; 4 by default): training
+    samples are drawn over the mirror-padded tile and each decoded page is a
+    (128 + 2 border)^2 region; PSNR is scored on the 128^2 interiors."""
     from .train import HybridTrainer, hybrid_normalize_target, hybrid_restore
     keys = I.lightmap_key_times(I.rng(6, I.P_MODEL, 1))
     frames = len(keys)
@@ -157,6 +160,8 @@ def run_hfit_map(args, torch, N, I, ctx, profile="M", side=1024, steps1=6000, st
     tiles = tiles.contiguous()
     tgt, means = hybrid_normalize_target(ctx, tiles.view(M * frames, TILE, TILE, 3).view(torch.int16), GAMMA)
     codec = _codec(args)
+    border = int(getattr(args, "border", 4))
+    R = TILE + 2 * border                       # stored page side
     inits = [I.hybrid_train_init(TILE, TILE, profile, frames, keys, I.rng(7, I.P_INIT, m), codec=codec)
              for m in range(M)]
     tr = HybridTrainer(ctx, inits, lr_feat=LR, lr_mlp=LR, seed=1, per_model=BATCH)
@@ -171,7 +176,7 @@ def run_hfit_map(args, torch, N, I, ctx, profile="M", side=1024, steps1=6000, st
     for i in range(n_steps):
         if i == steps1:
             tr.set_lr(lr_feat=0.0)
-        smp = I.train_samples_torch(M * BATCH, TILE, TILE, frames, seed=90_000 + i)
+        smp = I.train_samples_torch(M * BATCH, TILE, TILE, frames, seed=90_000 + i, border=border)
         tr.step(smp, tgt, f1 if i < steps1 else f2)
         if (i + 1) % 1000 == 0:
             losses.append((i + 1, float(tr.loss.item())))
@@ -184,37 +189,42 @@ def run_hfit_map(args, torch, N, I, ctx, profile="M", side=1024, steps1=6000, st
     mi = np.repeat(np.arange(M), frames).astype(np.int32)
     fi = np.tile(np.arange(frames), M)
     rq = N.page_requests(mi, np.zeros(M * frames, np.int32), np.zeros(M * frames, np.int32),
-                         np.asarray(keys, np.float32)[fi], (np.arange(M * frames) * TILE * TILE).astype(np.int64))
+                         np.asarray(keys, np.float32)[fi], (np.arange(M * frames) * R * R).astype(np.int64))
     nreq = torch.tensor([M * frames], dtype=torch.int32, device="cuda")
     width = 2 if I.HYBRID_PROFILES[profile][1] == 64 else 1
     out = {}
     for prec, name in ((N.PREC_F16, "f16"), (N.PREC_F32, "f32")):
-        dst = torch.empty((M * frames * TILE * TILE, 3), dtype=torch.float16 if prec == N.PREC_F16 else torch.float32,
+        dst = torch.empty((M * frames * R * R, 3), dtype=torch.float16 if prec == N.PREC_F16 else torch.float32,
                           device="cuda")
-        ctx.hybrid_decode_pages(marr, M, rq, nreq, M * frames, TILE, dst, TILE, prec, widths=width)
+        ctx.hybrid_decode_pages(marr, M, rq, nreq, M * frames, TILE, dst, R, prec, widths=width, border=border)
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         ev0.record()
-        ctx.hybrid_decode_pages(marr, M, rq, nreq, M * frames, TILE, dst, TILE, prec, widths=width)
+        ctx.hybrid_decode_pages(marr, M, rq, nreq, M * frames, TILE, dst, R, prec, widths=width, border=border)
         ev1.record()
         ev1.synchronize()
+        inner = dst.view(M * frames, R, R, 3)[:, border:border + TILE, border:border + TILE].contiguous()
+        inner = inner.view(M * frames * TILE * TILE, 3)
         stats = []
         for k in range(M * frames):
-            rec = hybrid_restore(ctx, dst[k * TILE * TILE:(k + 1) * TILE * TILE], means[k], GAMMA)
+            rec = hybrid_restore(ctx, inner[k * TILE * TILE:(k + 1) * TILE * TILE], means[k], GAMMA)
             stats.append(ctx.tile_stats(rec, tiles.view(M * frames, TILE, TILE, 3)[k].view(torch.int16), TILE, TILE,
                                         TILE).cpu().numpy())
         tiled, glob = N.psnr_from_stats(stats, TILE, TILE, TILE)
         out[name] = dict(psnr_tiled_db=tiled, psnr_global_db=glob, decode_all_frames_ms=ev0.elapsed_time(ev1))
-        _log(f"hybrid map {name}: PSNR tiled {tiled:.2f} dB, decode of {frames} frames {out[name]['decode_all_frames_ms']:.3f} ms")
+        _log(f"hybrid map {name}: PSNR tiled {tiled:.2f} dB, decode of {frames} frames "
+             f"({R}^2 pages) {out[name]['decode_all_frames_ms']:.3f} ms")
     assert ctx.error_flags() == 0
     s_uvt, hidden = I.HYBRID_PROFILES[profile]
     return {
         "metric": "hybrid-layout map fit: per-tile models trained together, tiled PSNR after export",
         "config": {"workload": f"{side}x{side} synthetic temporal lightmap at 26 key times as {M} tile models of "
-                               f"{TILE}^2, profile {profile}, {'BC7 mode 6' if codec else 'BC4'} F_uv / F_uvt; "
+                               f"{TILE}^2 with {border}-texel mirrored borders, profile {profile}, "
+                               f"{'BC7 mode 6' if codec else 'BC4'} F_uv / F_uvt; "
                                f"batch {BATCH} per model, Adam lr {LR}; {steps1} steps with "
                                f"BC simulation and noise, {steps2} decoder fine-tune steps"},
-        "data": "synthetic", "codec": "bc7" if codec else "bc4", "models": M, "train_params": int(tr.n_params),
+        "data": "synthetic", "codec": "bc7" if codec else "bc4", "border": border, "models": M,
+        "train_params": int(tr.n_params),
         "train_ms_per_step": train_ms / n_steps, "train_samples_per_s": M * BATCH * n_steps / (train_ms * 1e-3),
         "loss_curve": losses, "decode": out,
         "bits_per_texel": bits_per_texel_hybrid(TILE, TILE, frames, s_uvt, 12, (64, 64, 24), hidden, _bits(codec)),

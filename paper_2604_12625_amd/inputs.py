@@ -365,12 +365,20 @@ def train_init_torch(W: int, H: int, Gw: int, Gh: int, T: int, mean_rgb, seed: i
     return dict(dims=dict(W=W, H=H, Gw=Gw, Gh=Gh, T=T), flat=flat)
 
 
-def train_samples_torch(B: int, W: int, H: int, T: int, seed: int, device="cuda"):
-    """Packed samples (x | y << 12 | k << 24) drawn uniformly with replacement, on device."""
+def train_samples_torch(B: int, W: int, H: int, T: int, seed: int, device="cuda", border: int = 0):
+    """Packed samples (x | y << 12 | k << 24) drawn uniformly with replacement, on device.
+    With a border of b texels the positions are drawn over the map padded by b on each
+    side and folded back into it by mirror addressing (-1 - i below 0, 2n - 1 - i from n),
+    i.e. uniform samples of the mirror-padded target (b <= min(W, H))."""
     import torch
     gen = torch.Generator(device=device)
     gen.manual_seed(seed)
-    x = torch.randint(0, W, (B,), generator=gen, device=device, dtype=torch.int32)
-    y = torch.randint(0, H, (B,), generator=gen, device=device, dtype=torch.int32)
+    x = torch.randint(0, W + 2 * border, (B,), generator=gen, device=device, dtype=torch.int32)
+    y = torch.randint(0, H + 2 * border, (B,), generator=gen, device=device, dtype=torch.int32)
     k = torch.randint(0, T, (B,), generator=gen, device=device, dtype=torch.int32)
+    if border:
+        assert border <= min(W, H)
+        x, y = x - border, y - border
+        x = torch.where(x < 0, -1 - x, torch.where(x >= W, 2 * W - 1 - x, x))
+        y = torch.where(y < 0, -1 - y, torch.where(y >= H, 2 * H - 1 - y, y))
     return x | (y << 12) | (k << 24)

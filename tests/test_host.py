@@ -38,3 +38,21 @@ def test_psnr_from_stats_matches_oracle_tiled_psnr():
     o_tiled, o_glob = O.psnr_tiled(pred[None], tgt[None], tile)
     assert math.isclose(tiled, o_tiled, rel_tol=1e-12)
     assert math.isclose(glob, o_glob, rel_tol=1e-12)
+
+
+def test_bordered_training_samples_are_the_mirror_padded_tile():
+    """Samples drawn with a border are positions of the mirror-padded tile folded back by
+    mirror addressing: every texel inside the tile, and each texel drawn as often as it
+    occurs in numpy's symmetric padding of the tile."""
+    import torch
+    from paper_2604_12625_amd import inputs as I
+    W, H, T, b, n = 12, 8, 3, 4, 400_000
+    s = I.train_samples_torch(n, W, H, T, seed=5, device="cpu", border=b).numpy()
+    x, y, k = s & 0xFFF, (s >> 12) & 0xFFF, s >> 24
+    assert x.min() >= 0 and x.max() < W and y.min() >= 0 and y.max() < H and k.max() < T
+    wx = np.bincount(np.pad(np.arange(W), b, mode="symmetric"), minlength=W) / (W + 2 * b)
+    wy = np.bincount(np.pad(np.arange(H), b, mode="symmetric"), minlength=H) / (H + 2 * b)
+    fx, fy = np.bincount(x, minlength=W) / n, np.bincount(y, minlength=H) / n
+    assert np.max(np.abs(fx - wx)) < 5e-3 and np.max(np.abs(fy - wy)) < 5e-3
+    plain = I.train_samples_torch(1000, W, H, T, seed=5, device="cpu").numpy()
+    assert (plain & 0xFFF).max() < W
