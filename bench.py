@@ -43,14 +43,18 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# Sources of the kernels whose HBM byte counters profiles/traffic.json records (the frame
+# and random-access decode of the step), with the ABI header and the build flags.
+DIGEST_SOURCES = ("csrc/device.hpp", "csrc/internal.hpp", "csrc/decode.hip", "csrc/binned.hip", "build.py")
+
+
 def source_digest() -> str:
-    """sha256 over the kernel sources, the ABI header and the build flags: the identity of
-    the code whose HBM byte counters profiles/traffic.json records."""
-    import glob
+    """sha256 over DIGEST_SOURCES and include/ndgi.h: the identity of the code whose HBM byte
+    counters profiles/traffic.json records."""
     import hashlib
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_2604_12625_amd", "csrc", "*")))
-    files += [os.path.join(ROOT, "include", "ndgi.h"), os.path.join(ROOT, "paper_2604_12625_amd", "build.py")]
+    files = [os.path.join(ROOT, "paper_2604_12625_amd", f) for f in DIGEST_SOURCES]
+    files += [os.path.join(ROOT, "include", "ndgi.h")]
     for f in files:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
