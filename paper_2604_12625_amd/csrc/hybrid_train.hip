@@ -167,13 +167,40 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
-// Sum over the wave of a per-lane gradient term, added to g[idx] by lane 0.
-__device__ __forceinline__ void wave_grad(float* __restrict__ g, int64_t idx, float v, int lane) {
-  v = wave_sum(v);
-  if (lane == 0) atomicAdd(g + idx, v);
-}
 
 constexpr int kHtThreads = 64;   // one wave per workgroup: small batches still spread over the CUs
+
+// Decoder weight and bias gradients are sums over the wave's 64 samples of outer products
+// of per-sample vectors, computed on MFMA with the samples as K: each operand is staged in
+// an LDS slab [64 samples][16 units] (sample-major, written by the sample's lane).  Lane
+// (g, i) = (lane >> 4, lane & 15) supplies sample 4 q + g, unit i of both slabs at K step q;
+// the 16 x 16 result sits in lane (g, i), element r, as row 4 g + r, column i.
+constexpr int kSlab = 64 * 16;
+
+__device__ __forceinline__ void slab_store(float* slab, int lane, const float v[16]) {
+  float4* d = (float4*)(slab + lane * 16);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) d[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+}
+
+// D[u][c] = sum over samples of A[s][u] B[s][c]
+__device__ __forceinline__ f4v slab_outer(const float* A, const float* B, int lane) {
+  const int g = lane >> 4, i = lane & 15;
+  f4v acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int q = 0; q < 16; ++q)
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[(4 * q + g) * 16 + i], B[(4 * q + g) * 16 + i], acc, 0, 0, 0);
+  return acc;
+}
+
+// D[u][c] = sum over samples of A[s][u] (every column)
+__device__ __forceinline__ f4v slab_sum(const float* A, int lane) {
+  const int g = lane >> 4, i = lane & 15;
+  f4v acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[(4 * q + g) * 16 + i], 1.0f, acc, 0, 0, 0);
+  return acc;
+}
 
 // MODE: NDGI_TRAIN_FORWARD writes pred; NDGI_TRAIN_LOSS_GRAD adds the loss and gradients.
 template <int HD, int MODE>
@@ -187,7 +214,10 @@ __global__ __launch_bounds__(kHtThreads) void k_hybrid_train(HybTrainDims d, con
   using Sh = HybShape<HD>;
   static_assert(kHtThreads == 64, "one wave per workgroup: its samples belong to one model");
   __shared__ float sw[Sh::kSize];
-  const int lane = threadIdx.x & 63;
+  __shared__ float stage[2 * kSlab];   // MFMA operand slabs A, B
+  float* const slA = stage;
+  float* const slB = stage + kSlab;
+  const int lane = threadIdx.x & 63, lg = lane >> 4, li = lane & 15;
   const bool bcsim = flags & NDGI_HTRAIN_BCSIM, noise = flags & NDGI_HTRAIN_NOISE, qplanes = flags & NDGI_HTRAIN_QPLANES;
   const int64_t stride = (int64_t)gridDim.x * kHtThreads;
   const int64_t rounds = (n + stride - 1) / stride;   // every lane runs the same rounds (wave reductions)
@@ -316,44 +346,101 @@ __global__ __launch_bounds__(kHtThreads) void k_hybrid_train(HybTrainDims d, con
       }
       sq = wave_sum_d(sq);
       if (lane == 0) atomicAdd(loss_acc, sq * (double)inv3n);
-      // ---- decoder backward: layer 3
+      // ---- decoder backward.  Layer 3: dW3[c][j] = sum dout[c] h2[j], db3 = sum dout
+      {
+        float v[16];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) wave_grad(gm, Sh::oB3 + c, dout[c], lane);
+        for (int c = 0; c < 16; ++c) v[c] = c < 3 ? dout[c] : 0.0f;
+        slab_store(slA, lane, v);
+      }
+#pragma unroll
+      for (int jb = 0; jb < HD / 16; ++jb) {
+        float v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = gelu<NDGI_PREC_F32>(a2[16 * jb + u]);
+        slab_store(slB, lane, v);
+        __syncthreads();
+        const f4v w3 = slab_outer(slA, slB, lane);
+        if (lg == 0) {
+#pragma unroll
+          for (int r = 0; r < 3; ++r) atomicAdd(gm + Sh::oW3 + r * HD + 16 * jb + li, w3[r]);
+        }
+        if (jb == 0) {
+          const f4v b3 = slab_sum(slA, lane);
+          if (lane == 0) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) atomicAdd(gm + Sh::oB3 + r, b3[r]);
+          }
+        }
+        __syncthreads();
+        __builtin_amdgcn_sched_barrier(0);
+      }
 #pragma unroll
       for (int j = 0; j < HD; ++j) {
-        const float h = gelu<NDGI_PREC_F32>(a2[j]);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) wave_grad(gm, Sh::oW3 + c * HD + j, dout[c] * h, lane);
         float dh = 0.0f;
 #pragma unroll
         for (int c = 0; c < 3; ++c) dh = fmaf(sw[Sh::oW3 + c * HD + j], dout[c], dh);
         a2[j] = dh * gelu_grad(a2[j]);   // a2 now holds d loss / d a2
       }
-      // layer 2, then layer 1's pre-activation gradient (a1 is overwritten by it)
+      // Layer 2: dW2[j][k] = sum g2[j] h1[k], db2 = sum g2 (g2 = d loss / d a2)
 #pragma unroll
-      for (int j = 0; j < HD; ++j) wave_grad(gm, Sh::oB2 + j, a2[j], lane);
+      for (int kb = 0; kb < HD / 16; ++kb) {
+        {
+          float v[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) v[u] = gelu<NDGI_PREC_F32>(a1[16 * kb + u]);
+          slab_store(slB, lane, v);
+        }
+#pragma unroll
+        for (int jb = 0; jb < HD / 16; ++jb) {
+          slab_store(slA, lane, a2 + 16 * jb);
+          __syncthreads();
+          const f4v w2 = slab_outer(slA, slB, lane);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) atomicAdd(gm + Sh::oW2 + (16 * jb + 4 * lg + r) * HD + 16 * kb + li, w2[r]);
+          if (kb == 0) {
+            const f4v b2 = slab_sum(slA, lane);
+            if (li == 0) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) atomicAdd(gm + Sh::oB2 + 16 * jb + 4 * lg + r, b2[r]);
+            }
+          }
+          __syncthreads();
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      // layer 1's pre-activation gradient (a1 is overwritten by it)
 #pragma unroll
       for (int k = 0; k < HD; ++k) {
-        const float h = gelu<NDGI_PREC_F32>(a1[k]);
         float dh = 0.0f;
 #pragma unroll
-        for (int j = 0; j < HD; ++j) {
-          wave_grad(gm, Sh::oW2 + j * HD + k, a2[j] * h, lane);
-          dh = fmaf(sw[Sh::oW2 + j * HD + k], a2[j], dh);
-        }
+        for (int j = 0; j < HD; ++j) dh = fmaf(sw[Sh::oW2 + j * HD + k], a2[j], dh);
         a1[k] = dh * gelu_grad(a1[k]);
+      }
+      // Layer 1: dW1[k][i] = sum g1[k] x[i], db1 = sum g1; input gradient dx on the VALU
+      slab_store(slB, lane, xin);
+#pragma unroll
+      for (int kb = 0; kb < HD / 16; ++kb) {
+        slab_store(slA, lane, a1 + 16 * kb);
+        __syncthreads();
+        const f4v w1 = slab_outer(slA, slB, lane);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) atomicAdd(gm + Sh::oW1 + (16 * kb + 4 * lg + r) * 16 + li, w1[r]);
+        const f4v b1 = slab_sum(slA, lane);
+        if (li == 0) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) atomicAdd(gm + Sh::oB1 + 16 * kb + 4 * lg + r, b1[r]);
+        }
+        __syncthreads();
+        __builtin_amdgcn_sched_barrier(0);
       }
       float dx[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i) dx[i] = 0.0f;
 #pragma unroll
       for (int k = 0; k < HD; ++k) {
-        wave_grad(gm, Sh::oB1 + k, a1[k], lane);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          wave_grad(gm, Sh::oW1 + k * 16 + i, a1[k] * xin[i], lane);
-          dx[i] = fmaf(sw[Sh::oW1 + k * 16 + i], a1[k], dx[i]);
-        }
+        for (int i = 0; i < 16; ++i) dx[i] = fmaf(sw[Sh::oW1 + k * 16 + i], a1[k], dx[i]);
       }
       if (!live) continue;
       // ---- feature gradients (straight-through for the simulated maps)
