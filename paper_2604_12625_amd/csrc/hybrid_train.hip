@@ -168,7 +168,12 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 }
 
 
-constexpr int kHtThreads = 64;   // one wave per workgroup: small batches still spread over the CUs
+// A workgroup of 1, 2 or 4 waves takes chunks of consecutive samples of one model.  When
+// the model's F_uvt endpoints and F_ut / F_vt planes fit in LDS (kAccMaxBytes), their
+// gradients, the most contended ones (a footprint's endpoints collect every sample that
+// taps it), are summed in LDS over the chunk and added to HBM once per chunk.
+constexpr int kHtMaxThreads = 256;
+constexpr int64_t kAccMaxBytes = 64 * 1024;
 
 // Decoder weight and bias gradients are sums over the wave's 64 samples of outer products
 // of per-sample vectors, computed on MFMA with the samples as K: each operand is staged in
@@ -203,41 +208,50 @@ __device__ __forceinline__ f4v slab_sum(const float* A, int lane) {
 }
 
 // MODE: NDGI_TRAIN_FORWARD writes pred; NDGI_TRAIN_LOSS_GRAD adds the loss and gradients.
+// Dynamic LDS: per wave the MFMA operand slabs A, B ([64][16] each), then, with `accum`,
+// the accumulators [F_uvt endpoints (nE) | F_ut, F_vt (nP)] of the chunk's model.
+// `chunk` is a multiple of blockDim.x and, with several models, divides the per-model count.
 template <int HD, int MODE>
-__global__ __launch_bounds__(kHtThreads) void k_hybrid_train(HybTrainDims d, const float* __restrict__ Pall,
-                                                              float* __restrict__ Gall,
-                                                       const float* __restrict__ keys,
-                                                       const uint32_t* __restrict__ samples, int64_t n,
-                                                       const float* __restrict__ target, float* __restrict__ pred,
-                                                       int flags, uint64_t noise_base, float inv3n,
-                                                       double* __restrict__ loss_acc) {
+__global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, const float* __restrict__ Pall,
+                                                                 float* __restrict__ Gall,
+                                                                 const float* __restrict__ keys,
+                                                                 const uint32_t* __restrict__ samples, int64_t n,
+                                                                 const float* __restrict__ target,
+                                                                 float* __restrict__ pred, int flags,
+                                                                 uint64_t noise_base, float inv3n,
+                                                                 double* __restrict__ loss_acc, int64_t chunk,
+                                                                 int accum) {
   using Sh = HybShape<HD>;
-  static_assert(kHtThreads == 64, "one wave per workgroup: its samples belong to one model");
   __shared__ float sw[Sh::kSize];
-  __shared__ float stage[2 * kSlab];   // MFMA operand slabs A, B
-  float* const slA = stage;
-  float* const slB = stage + kSlab;
-  const int lane = threadIdx.x & 63, lg = lane >> 4, li = lane & 15;
+  extern __shared__ float dyn[];
+  const int nthr = blockDim.x, waves = nthr >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lg = lane >> 4, li = lane & 15;
+  float* const slA = dyn + wave * 2 * kSlab;
+  float* const slB = slA + kSlab;
+  float* const acc = dyn + waves * 2 * kSlab;
+  const int64_t nE = (int64_t)d.S * (d.Gv / 4) * (d.Gu / 4) * 8, nP = d.o_mlp - d.o_ut;
   const bool bcsim = flags & NDGI_HTRAIN_BCSIM, noise = flags & NDGI_HTRAIN_NOISE, qplanes = flags & NDGI_HTRAIN_QPLANES;
-  const int64_t stride = (int64_t)gridDim.x * kHtThreads;
-  const int64_t rounds = (n + stride - 1) / stride;   // every lane runs the same rounds (wave reductions)
+  const int64_t nchunks = (n + chunk - 1) / chunk;
+  const int rounds = (int)(chunk / nthr);
   int cur = -1;
-  for (int64_t r = 0; r < rounds; ++r) {
-    const int64_t s0 = r * stride + (int64_t)blockIdx.x * kHtThreads;
-    const int64_t s = s0 + threadIdx.x;
-    const bool live = s < n;
-    // the wave's 64 samples belong to one model (the host checks that Bm is a multiple of 64)
-    const int m = (int)min(s0 / d.Bm, (int64_t)d.M - 1);
+  for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const int64_t c0 = ch * chunk;
+    const int m = (int)min(c0 / d.Bm, (int64_t)d.M - 1);   // the chunk lies inside one model's samples
     const float* P = Pall + (int64_t)m * d.o_mlp;
     float* G = Gall + (int64_t)m * d.o_mlp;
     const int64_t mlp_off = (int64_t)d.M * d.o_mlp + (int64_t)m * (d.n - d.o_mlp);
     float* gm = Gall + mlp_off;
+    __syncthreads();   // the previous chunk's readers of sw and acc are done
     if (m != cur) {
-      __syncthreads();
-      for (int i = threadIdx.x; i < Sh::kSize; i += kHtThreads) sw[i] = Pall[mlp_off + i];
-      __syncthreads();
+      for (int i = threadIdx.x; i < Sh::kSize; i += nthr) sw[i] = Pall[mlp_off + i];
       cur = m;
     }
+    if (accum)
+      for (int64_t i = threadIdx.x; i < nE + nP; i += nthr) acc[i] = 0.0f;
+    __syncthreads();
+  for (int r = 0; r < rounds; ++r) {
+    const int64_t s = c0 + (int64_t)r * nthr + threadIdx.x;
+    const bool live = s < n;
     const uint32_t word = samples[live ? s : 0];
     const int x = min((int)(word & 0xfffu), d.W - 1), y = min((int)((word >> 12) & 0xfffu), d.H - 1);
     const int f = min((int)(word >> 24), d.frames - 1);
@@ -457,8 +471,13 @@ __global__ __launch_bounds__(kHtThreads) void k_hybrid_train(HybTrainDims d, con
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
             const float dv = wt * dx[c];
-            atomicAdd(G + d.o_tep + fp * 8 + 2 * c, dv * b.d1[c]);
-            atomicAdd(G + d.o_tep + fp * 8 + 2 * c + 1, dv * b.d2[c]);
+            if (accum) {   // LDS (ds_add) or HBM atomics: separate paths keep each pointer's address space
+              atomicAdd(acc + fp * 8 + 2 * c, dv * b.d1[c]);
+              atomicAdd(acc + fp * 8 + 2 * c + 1, dv * b.d2[c]);
+            } else {
+              atomicAdd(G + d.o_tep + fp * 8 + 2 * c, dv * b.d1[c]);
+              atomicAdd(G + d.o_tep + fp * 8 + 2 * c + 1, dv * b.d2[c]);
+            }
             if (!d.codec) atomicAdd(G + d.o_tw + wi + c, dv * b.dw[c]);
           }
           if (d.codec)
@@ -485,9 +504,26 @@ __global__ __launch_bounds__(kHtThreads) void k_hybrid_train(HybTrainDims d, con
           for (int aa = 0; aa < 2; ++aa) {
             const float w = (kk ? nk.w1 : nk.w0) * (aa ? a.w1 : a.w0);
             const int64_t idx = off + ((int64_t)(kk ? nk.i1 : nk.i0) * size + (aa ? a.i1 : a.i0)) * 2;
-            atomicAdd(G + idx, w * dx[8 + 2 * pl]);
-            atomicAdd(G + idx + 1, w * dx[9 + 2 * pl]);
+            if (accum) {
+              atomicAdd(acc + nE + (idx - d.o_ut), w * dx[8 + 2 * pl]);
+              atomicAdd(acc + nE + (idx - d.o_ut) + 1, w * dx[9 + 2 * pl]);
+            } else {
+              atomicAdd(G + idx, w * dx[8 + 2 * pl]);
+              atomicAdd(G + idx + 1, w * dx[9 + 2 * pl]);
+            }
           }
+      }
+    }
+  }
+    if (accum) {   // the chunk's sums into HBM
+      __syncthreads();
+      for (int64_t i = threadIdx.x; i < nE; i += nthr) {
+        const float v = acc[i];
+        if (v != 0.0f) atomicAdd(G + d.o_tep + i, v);
+      }
+      for (int64_t i = threadIdx.x; i < nP; i += nthr) {
+        const float v = acc[nE + i];
+        if (v != 0.0f) atomicAdd(G + d.o_ut + i, v);
       }
     }
   }
@@ -702,13 +738,34 @@ int ndgi_hybrid_train_step(ndgi_ctx* c, ndgi_hybrid_train_state* st, const ndgi_
     if (dl.M == 1) dl.Bm = (int)b->n;
     const uint64_t base = (uint64_t)st->seed * 0x9E3779B97F4A7C15ull + ((uint64_t)st->step << 32);
     const float inv3n = (float)(1.0 / (3.0 * (double)b->n));
-    int64_t wgs = (b->n + kHtThreads - 1) / kHtThreads;
+    // workgroup size: one wave for small batches (spread over the CUs), else 4 waves (2 or 1
+    // when a model's sample count is not a multiple of 256); chunks of k workgroup rounds,
+    // k up to 16 while the grid keeps about one chunk per CU
+    int nthr = b->n >= (int64_t)64 * c->n_cu ? kHtMaxThreads : 64;
+    if (dl.M > 1)
+      while (nthr > 64 && dl.Bm % nthr != 0) nthr >>= 1;
+    int64_t k = b->n / ((int64_t)nthr * c->n_cu);
+    k = k < 1 ? 1 : (k > 16 ? 16 : k);
+    while (k > 1 && dl.M > 1 && dl.Bm % (nthr * k) != 0) --k;
+    const int64_t chunk = (int64_t)nthr * k;
+    int64_t wgs = (b->n + chunk - 1) / chunk;
     const int64_t cap = (int64_t)c->n_cu * 8;
     if (wgs > cap) wgs = cap;
+    const int64_t nE = (int64_t)d.S * (d.Gv / 4) * (d.Gu / 4) * 8, nP = d.o_mlp - d.o_ut;
+    const size_t slab_bytes = (size_t)(nthr / 64) * 2 * kSlab * sizeof(float);
+    const size_t acc_bytes = (size_t)(nE + nP) * sizeof(float);
+    const size_t sw_bytes = (size_t)ndgi_hybrid_mlp_size(d.hidden) * sizeof(float);
+    int lds_max = 0;
+    NDGI_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+    // LDS sums pay off when a chunk has several waves' samples or models share the launch
+    const int accum = mode != NDGI_TRAIN_FORWARD && (nthr > 64 || dl.M > 1) && (int64_t)acc_bytes <= kAccMaxBytes &&
+                      sw_bytes + slab_bytes + acc_bytes <= (size_t)lds_max;
+    const size_t dyn_bytes = slab_bytes + (accum ? acc_bytes : 0);
     if (mode != NDGI_TRAIN_FORWARD) hipLaunchKernelGGL(k_zero_d, dim3(1), dim3(64), 0, s, loss_dev, 1);
-#define NDGI_HT(HD, M)                                                                                       \
-  hipLaunchKernelGGL((k_hybrid_train<HD, M>), dim3((unsigned)wgs), dim3(kHtThreads), 0, s, dl, st->params, st->grads, \
-                     st->keys, b->samples, b->n, b->target, b->pred, flags, base, inv3n, loss_dev)
+#define NDGI_HT(HD, M)                                                                                          \
+  hipLaunchKernelGGL((k_hybrid_train<HD, M>), dim3((unsigned)wgs), dim3(nthr), dyn_bytes, s, dl, st->params,      \
+                     st->grads, st->keys, b->samples, b->n, b->target, b->pred, flags, base, inv3n, loss_dev, chunk, \
+                     accum)
     if (mode == NDGI_TRAIN_FORWARD) {
       if (d.hidden == 16) NDGI_HT(16, NDGI_TRAIN_FORWARD);
       else NDGI_HT(64, NDGI_TRAIN_FORWARD);

@@ -291,3 +291,21 @@ def test_bc7_many_models_in_one_launch(N, ctx):
     assert abs(loss - ref_loss) <= 1e-5 * abs(ref_loss), (loss, ref_loss)
     hm = tr.export(N.DTYPE_F16, model=1)
     np.testing.assert_array_equal(hm.arrays[0].cpu().numpy(), O.hybrid_export(sts[1])["fuv"])
+
+
+@pytest.mark.parametrize("codec", [0, 1])
+def test_large_single_model_batch_matches_oracle(N, ctx, codec):
+    """A batch large enough for four-wave workgroups whose F_uvt endpoint and plane
+    gradients are summed in LDS per chunk (20000 samples: a partial last chunk)."""
+    from paper_2604_12625_amd.train import HybridTrainer
+    st = _state(16, seed=90 + codec, codec=codec)
+    x, y, f, tgt = _samples(st, 20000, seed=91)
+    smp, tg = _dev(N, x, y, f, tgt)
+    tr = HybridTrainer(ctx, st, seed=23)
+    tr.zero_grad()
+    loss = float(tr.loss_grad(smp, tg, 1 | 2).item())
+    ref_loss, ref_g = O.hybrid_train_grads(st, x, y, f, tgt[f, y, x], 1 | 2, seed=23, step=0)
+    assert abs(loss - ref_loss) <= 1e-5 * abs(ref_loss), (loss, ref_loss)
+    got = tr.split(tr.grads)
+    for k in O.HYB_KEYS:
+        _close(got[k].cpu().numpy(), ref_g[k], 1e-4, k)
