@@ -223,7 +223,7 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
                                                                  int accum) {
   using Sh = HybShape<HD>;
   __shared__ float sw[Sh::kSize];
-  extern __shared__ float dyn[];
+  extern __shared__ __align__(16) float dyn[];   // 16-byte aligned: float4 slab accesses
   const int nthr = blockDim.x, waves = nthr >> 6;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lg = lane >> 4, li = lane & 15;
   float* const slA = dyn + wave * 2 * kSlab;
@@ -396,7 +396,10 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
         for (int c = 0; c < 3; ++c) dh = fmaf(sw[Sh::oW3 + c * HD + j], dout[c], dh);
         a2[j] = dh * gelu_grad(a2[j]);   // a2 now holds d loss / d a2
       }
-      // Layer 2: dW2[j][k] = sum g2[j] h1[k], db2 = sum g2 (g2 = d loss / d a2)
+      // Layer 2: dW2[j][k] = sum g2[j] h1[k], db2 = sum g2 (g2 = d loss / d a2); the input
+      // gradient DH[k][s] = sum_j W2[j][k] g2[s][j] on MFMA as well (W2 from LDS as the A
+      // operand, the staged g2 slab as B), handed back to the sample lanes through LDS, and
+      // a1 overwritten by g1 = DH gelu'(a1) block by block.
 #pragma unroll
       for (int kb = 0; kb < HD / 16; ++kb) {
         {
@@ -405,6 +408,9 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
           for (int u = 0; u < 16; ++u) v[u] = gelu<NDGI_PREC_F32>(a1[16 * kb + u]);
           slab_store(slB, lane, v);
         }
+        f4v dh4[4];
+#pragma unroll
+        for (int sb = 0; sb < 4; ++sb) dh4[sb] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int jb = 0; jb < HD / 16; ++jb) {
           slab_store(slA, lane, a2 + 16 * jb);
@@ -419,20 +425,40 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
               for (int r = 0; r < 4; ++r) atomicAdd(gm + Sh::oB2 + 16 * jb + 4 * lg + r, b2[r]);
             }
           }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float wa = sw[Sh::oW2 + (16 * jb + 4 * q + lg) * HD + 16 * kb + li];
+#pragma unroll
+            for (int sb = 0; sb < 4; ++sb)
+              dh4[sb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa, slA[(16 * sb + li) * 16 + 4 * q + lg], dh4[sb], 0, 0,
+                                                             0);
+          }
           __syncthreads();
           __builtin_amdgcn_sched_barrier(0);
         }
-      }
-      // layer 1's pre-activation gradient (a1 is overwritten by it)
 #pragma unroll
-      for (int k = 0; k < HD; ++k) {
-        float dh = 0.0f;
+        for (int sb = 0; sb < 4; ++sb) *(f4v*)(slB + (16 * sb + li) * 16 + 4 * lg) = dh4[sb];
+        __syncthreads();
+        {
+          const float4* own = (const float4*)(slB + lane * 16);
 #pragma unroll
-        for (int j = 0; j < HD; ++j) dh = fmaf(sw[Sh::oW2 + j * HD + k], a2[j], dh);
-        a1[k] = dh * gelu_grad(a1[k]);
+          for (int q = 0; q < 4; ++q) {
+            const float4 dq = own[q];
+            a1[16 * kb + 4 * q] = dq.x * gelu_grad(a1[16 * kb + 4 * q]);
+            a1[16 * kb + 4 * q + 1] = dq.y * gelu_grad(a1[16 * kb + 4 * q + 1]);
+            a1[16 * kb + 4 * q + 2] = dq.z * gelu_grad(a1[16 * kb + 4 * q + 2]);
+            a1[16 * kb + 4 * q + 3] = dq.w * gelu_grad(a1[16 * kb + 4 * q + 3]);
+          }
+        }
+        __syncthreads();
+        __builtin_amdgcn_sched_barrier(0);
       }
-      // Layer 1: dW1[k][i] = sum g1[k] x[i], db1 = sum g1; input gradient dx on the VALU
+      // Layer 1: dW1[k][i] = sum g1[k] x[i], db1 = sum g1; the input gradient
+      // DX[i][s] = sum_k W1[k][i] g1[s][k] on MFMA, handed back to the sample lanes
       slab_store(slB, lane, xin);
+      f4v dx4[4];
+#pragma unroll
+      for (int sb = 0; sb < 4; ++sb) dx4[sb] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int kb = 0; kb < HD / 16; ++kb) {
         slab_store(slA, lane, a1 + 16 * kb);
@@ -445,16 +471,30 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
 #pragma unroll
           for (int r = 0; r < 4; ++r) atomicAdd(gm + Sh::oB1 + 16 * kb + 4 * lg + r, b1[r]);
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float wa = sw[Sh::oW1 + (16 * kb + 4 * q + lg) * 16 + li];
+#pragma unroll
+          for (int sb = 0; sb < 4; ++sb)
+            dx4[sb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa, slA[(16 * sb + li) * 16 + 4 * q + lg], dx4[sb], 0, 0, 0);
+        }
         __syncthreads();
         __builtin_amdgcn_sched_barrier(0);
       }
+#pragma unroll
+      for (int sb = 0; sb < 4; ++sb) *(f4v*)(slB + (16 * sb + li) * 16 + 4 * lg) = dx4[sb];
+      __syncthreads();
       float dx[16];
+      {
+        const float4* own = (const float4*)(slB + lane * 16);
 #pragma unroll
-      for (int i = 0; i < 16; ++i) dx[i] = 0.0f;
-#pragma unroll
-      for (int k = 0; k < HD; ++k) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) dx[i] = fmaf(sw[Sh::oW1 + k * 16 + i], a1[k], dx[i]);
+        for (int q = 0; q < 4; ++q) {
+          const float4 dq = own[q];
+          dx[4 * q] = dq.x;
+          dx[4 * q + 1] = dq.y;
+          dx[4 * q + 2] = dq.z;
+          dx[4 * q + 3] = dq.w;
+        }
       }
       if (!live) continue;
       // ---- feature gradients (straight-through for the simulated maps)
@@ -754,7 +794,7 @@ int ndgi_hybrid_train_step(ndgi_ctx* c, ndgi_hybrid_train_state* st, const ndgi_
     const int64_t nE = (int64_t)d.S * (d.Gv / 4) * (d.Gu / 4) * 8, nP = d.o_mlp - d.o_ut;
     const size_t slab_bytes = (size_t)(nthr / 64) * 2 * kSlab * sizeof(float);
     const size_t acc_bytes = (size_t)(nE + nP) * sizeof(float);
-    const size_t sw_bytes = (size_t)ndgi_hybrid_mlp_size(d.hidden) * sizeof(float);
+    const size_t sw_bytes = ((size_t)ndgi_hybrid_mlp_size(d.hidden) * sizeof(float) + 15) / 16 * 16;   // static LDS
     int lds_max = 0;
     NDGI_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
     // LDS sums pay off when a chunk has several waves' samples or models share the launch
