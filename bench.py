@@ -272,6 +272,36 @@ def run_hybrid(args, torch, N, I, ctx, reps=30, warm=5):
     return out
 
 
+def run_hybrid_train(args, torch, N, I, ctx, steps=10, warm=3):
+    """The paper's production training step: 64 tile models of 128^2 (profile M, BC7), 4096
+    samples per model (the paper's batch), one fused step (forward with BC simulation and
+    noise, loss, backward, Adam) per launch pair; samples drawn before the timed region."""
+    from paper_2604_12625_amd.train import HybridTrainer, hybrid_normalize_target
+    keys = I.lightmap_key_times(I.rng(6, I.P_MODEL, 1))
+    frames, M, Bm = len(keys), 64, 4096
+    inits = [I.hybrid_train_init(128, 128, "M", frames, keys, I.rng(7, I.P_INIT, m), codec=1) for m in range(M)]
+    tr = HybridTrainer(ctx, inits, lr_feat=1e-3, lr_mlp=1e-3, seed=1, per_model=Bm)
+    scene = I.light_scene(1024, 1024, I.rng(7, I.P_TARGET))
+    full = torch.stack([I.scene_frame_torch(scene, float(t), device="cuda").to(torch.float16) for t in keys])
+    tiles = full.view(frames, 8, 128, 8, 128, 3).permute(1, 3, 0, 2, 4, 5).reshape(M * frames, 128, 128, 3)
+    tgt, _ = hybrid_normalize_target(ctx, tiles.contiguous().view(torch.int16), 2.2)
+    smp = [I.train_samples_torch(M * Bm, 128, 128, frames, seed=80_000 + i, border=4) for i in range(warm + steps)]
+    flags = N.HTRAIN_BCSIM | N.HTRAIN_NOISE
+    for i in range(warm):
+        tr.step(smp[i], tgt, flags)
+    torch.cuda.synchronize()
+    tm = Timer(torch)
+    for i in range(steps):
+        e = tm.start()
+        tr.step(smp[warm + i], tgt, flags)
+        tm.stop(e)
+    torch.cuda.synchronize()
+    ms = sorted(tm.ms())[steps // 2]
+    log(f"hybrid train, 64 tile models x 4096 samples: {ms:.3f} ms/step ({M * Bm / ms / 1e3:.1f} M samples/s)")
+    return dict(ms_per_step=ms, samples_per_s=M * Bm / (ms * 1e-3), models=M, per_model=Bm, profile="M", codec="bc7",
+                params=int(tr.n_params), loss=float(tr.loss.item()))
+
+
 def run_c4(args, torch, N, I, ctx, steps=None, warm=3):
     """Training step with BC simulation: 1024^2 x 24 target, 2^18 samples, Adam."""
     import numpy as np
@@ -374,7 +404,8 @@ def main():
         return
     ctx = N.Context(0)
     if args.hybrid_only:
-        print(json.dumps({"hybrid_1024_tiles": run_hybrid(args, torch, N, I, ctx)}), flush=True)
+        print(json.dumps({"hybrid_1024_tiles": run_hybrid(args, torch, N, I, ctx),
+                          "hybrid_train_64_tiles": run_hybrid_train(args, torch, N, I, ctx)}), flush=True)
         return
     if args.workload == "hmap":
         from paper_2604_12625_amd.hybrid_fit import run_hfit_map
@@ -435,6 +466,7 @@ def main():
         res["vt_frame"] = run_c3(args, torch, N, I, ctx3)
         ctx3.close()
         res["hybrid_1024_tiles"] = run_hybrid(args, torch, N, I, ctx)
+        res["hybrid_train_64_tiles"] = run_hybrid_train(args, torch, N, I, ctx)
         c4 = run_c4(args, torch, N, I, ctx)
         res["train_texels_per_s"] = c4["samples_per_s"]
         res["train"] = c4
