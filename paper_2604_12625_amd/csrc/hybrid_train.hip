@@ -497,31 +497,57 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
         }
       }
       if (!live) continue;
-      // ---- feature gradients (straight-through for the simulated maps)
+      // ---- feature gradients (straight-through for the simulated maps).  Per F_uvt slice the
+      // four taps' endpoint terms are first summed per 4x4 footprint (taps 0/1 and 2/3 share
+      // one when their columns do, taps 0/2 and 1/3 when their rows do), so each footprint
+      // the sample touches takes one set of 8 atomic adds.
+      const bool fsx = (txs[0] >> 2) == (txs[1] >> 2), fsy = (tys[0] >> 2) == (tys[2] >> 2);
 #pragma unroll
       for (int sl = 0; sl < 2; ++sl) {
         const int si = sl ? ns.i1 : ns.i0;
         const float ws = sl ? ns.w1 : ns.w0;
+        float e[4][8];
+        int64_t fps[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int64_t fp = ((int64_t)si * (d.Gv / 4) + (tys[i] >> 2)) * (d.Gu / 4) + (txs[i] >> 2);
           const int64_t wi = (((int64_t)si * d.Gv + tys[i]) * d.Gu + txs[i]) * d.cw;
           const BcTex b = sim_texel(P + d.o_tep + fp * 8, P + d.o_tw + wi, bcsim, d.codec);
           const float wt = ws * tw[i];
+          fps[i] = fp;
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
             const float dv = wt * dx[c];
-            if (accum) {   // LDS (ds_add) or HBM atomics: separate paths keep each pointer's address space
-              atomicAdd(acc + fp * 8 + 2 * c, dv * b.d1[c]);
-              atomicAdd(acc + fp * 8 + 2 * c + 1, dv * b.d2[c]);
-            } else {
-              atomicAdd(G + d.o_tep + fp * 8 + 2 * c, dv * b.d1[c]);
-              atomicAdd(G + d.o_tep + fp * 8 + 2 * c + 1, dv * b.d2[c]);
-            }
+            e[i][2 * c] = dv * b.d1[c];
+            e[i][2 * c + 1] = dv * b.d2[c];
             if (!d.codec) atomicAdd(G + d.o_tw + wi + c, dv * b.dw[c]);
           }
           if (d.codec)
             atomicAdd(G + d.o_tw + wi, wt * (dx[0] * b.dw[0] + dx[1] * b.dw[1] + dx[2] * b.dw[2] + dx[3] * b.dw[3]));
+        }
+        if (fsx) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            e[0][k] += e[1][k];
+            e[2][k] += e[3][k];
+          }
+        }
+        if (fsy) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            e[0][k] += e[2][k];
+            e[1][k] += e[3][k];   // unused when fsx (tap 1 then merged into tap 0 already)
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const bool own = i == 0 || (i == 1 && !fsx) || (i == 2 && !fsy) || (i == 3 && !fsx && !fsy);
+          if (!own) continue;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            if (accum) atomicAdd(acc + fps[i] * 8 + k, e[i][k]);   // LDS (ds_add) or HBM: separate paths
+            else atomicAdd(G + d.o_tep + fps[i] * 8 + k, e[i][k]);
+          }
         }
       }
 #pragma unroll
