@@ -183,9 +183,9 @@ constexpr int64_t kAccMaxBytes = 64 * 1024;
 constexpr int kSlab = 64 * 16;
 
 __device__ __forceinline__ void slab_store(float* slab, int lane, const float v[16]) {
-  float4* d = (float4*)(slab + lane * 16);
+  f4v* d = (f4v*)(slab + lane * 16);   // one vector type for every slab access
 #pragma unroll
-  for (int q = 0; q < 4; ++q) d[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+  for (int q = 0; q < 4; ++q) d[q] = f4v{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
 }
 
 // D[u][c] = sum over samples of A[s][u] B[s][c]
@@ -440,14 +440,12 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
         for (int sb = 0; sb < 4; ++sb) *(f4v*)(slB + (16 * sb + li) * 16 + 4 * lg) = dh4[sb];
         __syncthreads();
         {
-          const float4* own = (const float4*)(slB + lane * 16);
+          const f4v* own = (const f4v*)(slB + lane * 16);
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const float4 dq = own[q];
-            a1[16 * kb + 4 * q] = dq.x * gelu_grad(a1[16 * kb + 4 * q]);
-            a1[16 * kb + 4 * q + 1] = dq.y * gelu_grad(a1[16 * kb + 4 * q + 1]);
-            a1[16 * kb + 4 * q + 2] = dq.z * gelu_grad(a1[16 * kb + 4 * q + 2]);
-            a1[16 * kb + 4 * q + 3] = dq.w * gelu_grad(a1[16 * kb + 4 * q + 3]);
+            const f4v dq = own[q];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) a1[16 * kb + 4 * q + e] = dq[e] * gelu_grad(a1[16 * kb + 4 * q + e]);
           }
         }
         __syncthreads();
@@ -486,14 +484,12 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
       __syncthreads();
       float dx[16];
       {
-        const float4* own = (const float4*)(slB + lane * 16);
+        const f4v* own = (const f4v*)(slB + lane * 16);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const float4 dq = own[q];
-          dx[4 * q] = dq.x;
-          dx[4 * q + 1] = dq.y;
-          dx[4 * q + 2] = dq.z;
-          dx[4 * q + 3] = dq.w;
+          const f4v dq = own[q];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) dx[4 * q + e] = dq[e];
         }
       }
       if (!live) continue;
