@@ -241,15 +241,19 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
     float* G = Gall + (int64_t)m * d.o_mlp;
     const int64_t mlp_off = (int64_t)d.M * d.o_mlp + (int64_t)m * (d.n - d.o_mlp);
     float* gm = Gall + mlp_off;
-    __syncthreads();   // the previous chunk's readers of sw and acc are done
-    if (m != cur) {
-      for (int i = threadIdx.x; i < Sh::kSize; i += nthr) sw[i] = Pall[mlp_off + i];
-      cur = m;
-    }
-    if (accum)
-      for (int64_t i = threadIdx.x; i < nE + nP; i += nthr) acc[i] = 0.0f;
-    __syncthreads();
   for (int r = 0; r < rounds; ++r) {
+    // staging inside the round loop (first round only): the decoder weight reads of the
+    // round cannot then be hoisted out of the loop into registers held across all rounds
+    if (r == 0) {
+      __syncthreads();   // the previous chunk's readers of sw and acc are done
+      if (m != cur) {
+        for (int i = threadIdx.x; i < Sh::kSize; i += nthr) sw[i] = Pall[mlp_off + i];
+        cur = m;
+      }
+      if (accum)
+        for (int64_t i = threadIdx.x; i < nE + nP; i += nthr) acc[i] = 0.0f;
+      __syncthreads();
+    }
     const int64_t s = c0 + (int64_t)r * nthr + threadIdx.x;
     const bool live = s < n;
     const uint32_t word = samples[live ? s : 0];
