@@ -7,11 +7,11 @@
 // One sample per lane.  A training sample is texel (x, y) of baked frame f, so its texel
 // centre and frame time fix every interpolation weight.  One launch trains any number of
 // models of the same sizes (the paper trains one model per virtual-texture tile): each
-// model owns a contiguous run of the batch, so every wave's samples share one model and its
-// decoder in LDS.  The decoder runs in FP32 on the
-// VALU from weights staged in LDS (hidden 16 or 64); the weight gradients are the sums
-// over samples of outer products, reduced across the wave with lane shuffles and added to
-// the gradient array by one lane; feature gradients go out as float atomics.
+// model owns a contiguous run of the batch, so every workgroup's samples share one model and
+// its decoder in LDS.  The decoder's forward runs in FP32 on the VALU from weights staged in
+// LDS (hidden 16 or 64); its weight gradients and its input gradients run on FP32 MFMA over
+// the wave's 64 samples (operands staged in LDS slabs); feature gradients go out as float
+// atomics, the contended F_uvt endpoint and plane ones summed in LDS per chunk first.
 #include "hybrid.hpp"
 #include "internal.hpp"
 
