@@ -56,3 +56,15 @@ def test_bordered_training_samples_are_the_mirror_padded_tile():
     assert np.max(np.abs(fx - wx)) < 5e-3 and np.max(np.abs(fy - wy)) < 5e-3
     plain = I.train_samples_torch(1000, W, H, T, seed=5, device="cpu").numpy()
     assert (plain & 0xFFF).max() < W
+
+
+def test_bench_measures_one_gpu_only():
+    """bench.py --gpus N with N > 1 exits with a message (no multi-GPU path is built)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
