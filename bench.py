@@ -384,8 +384,9 @@ def main():
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
-              "see the sharding notes of the design document", file=sys.stderr)
+        print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}); "
+              "decode would shard by map ownership and per-tile training needs no communication, so each "
+              "GPU would run this single-GPU path on its share", file=sys.stderr)
         sys.exit(2)
     import torch
 
