@@ -122,6 +122,17 @@ int ndgi_get_error_flags(ndgi_ctx* ctx, hipStream_t stream, uint32_t* flags_out)
  * n = 0 is a no-op.  Errors: INVALID_ARG (n < 0, NULL pointers when n > 0). */
 int ndgi_bc4_decode_blocks(const uint8_t* blocks, int64_t n, uint8_t* out16, hipStream_t stream);
 
+/* Decode n BC7 mode-6 blocks (the block format of the hybrid layout's F_uv and F_uvt,
+ * NDGI_CODEC_BC7; Sec. 3.4), bit-exactly, as the hybrid decode reads them.  blocks: device
+ * [n][16] bytes, 16-byte aligned, each a 128-bit little-endian value: 7-bit endpoint
+ * values R0 R1 G0 G1 B0 B1 A0 A1 at bits 7..62, p-bits at 63 and 64, texel 0's 3-bit index
+ * at 65..67, texel s's 4-bit index at 64 + 4 s (the mode bits 0..6 are not checked).
+ * out64: device [n][16][4] bytes, 16-byte aligned: channel c of texel s = 4*row + col at
+ * out64[64*i + 4*s + c] = ((64 - w) E0 + w E1 + 32) >> 6 with E = (v << 1) | p and w the
+ * index's 4-bit weight (0 4 9 13 17 21 26 30 34 38 43 47 51 55 60 64).
+ * n = 0 is a no-op.  Errors: INVALID_ARG (n < 0, NULL or misaligned pointers when n > 0). */
+int ndgi_bc7_decode_blocks(const uint8_t* blocks, int64_t n, uint8_t* out64, hipStream_t stream);
+
 /* ---------------------------------------------------------------- decode */
 
 /* Random-access decode of n queries (Sec. 3.1 Eq. 3; Sec. 3.3 "random access"):

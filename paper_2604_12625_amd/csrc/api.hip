@@ -170,6 +170,16 @@ int ndgi_bc4_decode_blocks(const uint8_t* blocks, int64_t n, uint8_t* out16, hip
   return launch_bc4_blocks(blocks, n, out16, s);
 }
 
+int ndgi_bc7_decode_blocks(const uint8_t* blocks, int64_t n, uint8_t* out64, hipStream_t s) {
+  clear_error();
+  if (n < 0) return fail(NDGI_ERR_INVALID_ARG, "bc7_decode_blocks: n < 0");
+  if (n == 0) return NDGI_OK;
+  if (!blocks || !out64) return fail(NDGI_ERR_INVALID_ARG, "bc7_decode_blocks: NULL pointer");
+  if (((uintptr_t)blocks | (uintptr_t)out64) & 15)
+    return fail(NDGI_ERR_INVALID_ARG, "bc7_decode_blocks: blocks and out64 must be 16-byte aligned");
+  return launch_bc7_blocks(blocks, n, out64, s);
+}
+
 int ndgi_decode(ndgi_ctx* c, const ndgi_model* m, const float* uvt, int64_t n, void* out, int32_t prec,
                 hipStream_t s) {
   clear_error();

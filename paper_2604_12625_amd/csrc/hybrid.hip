@@ -242,6 +242,26 @@ __device__ __forceinline__ void fp4(const uint8_t* fp, int codec, uint32_t slot,
   else bc4_fp4(fp, slot, v);
 }
 
+// Standalone decode of BC7 mode-6 blocks (the texel decode the hybrid kernels use), 16
+// texels x 4 channels per block: out[64 b + 4 s + c].
+__global__ __launch_bounds__(256) void k_bc7_blocks(const uint8_t* __restrict__ blocks, int64_t n,
+                                                     uint8_t* __restrict__ out) {
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n; b += (int64_t)gridDim.x * blockDim.x) {
+    const u4v blk = ((const u4v*)blocks)[b];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint32_t w[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        float v[4];
+        bc7_fp4_regs(blk, (uint32_t)(4 * q + k), v);
+        w[k] = (uint32_t)v[0] | (uint32_t)v[1] << 8 | (uint32_t)v[2] << 16 | (uint32_t)v[3] << 24;
+      }
+      ((u4v*)out)[4 * b + q] = (u4v){w[0], w[1], w[2], w[3]};
+    }
+  }
+}
+
 // Bilinear sample (4 channels, values / 255) of a block-compressed map of bw footprints per
 // row starting at `base` (fpb bytes per footprint), accumulated into x with weight ws.
 __device__ __forceinline__ void bc_bilinear4(const uint8_t* base, uint32_t bw, uint32_t fpb, int codec,
@@ -548,6 +568,14 @@ int check_hybrid(const ndgi_hybrid_model* m, const char* who) {
                 "%s: hybrid descriptor out of range (W %d H %d Gu %d Gv %d S %d U %d V %d Tt %d hidden %d "
                 "mlp_dtype %d n_keys %d, or a NULL buffer)",
                 who, m->W, m->H, m->Gu, m->Gv, m->S, m->U, m->V, m->Tt, m->hidden, m->mlp_dtype, m->n_keys);
+  return NDGI_OK;
+}
+
+int launch_bc7_blocks(const uint8_t* blocks, int64_t n, uint8_t* out, hipStream_t s) {
+  const int64_t want = (n + 255) / 256;
+  const int grid = (int)(want < 65536 ? want : 65536);
+  hipLaunchKernelGGL(k_bc7_blocks, dim3(grid), dim3(256), 0, s, blocks, n, out);
+  NDGI_HIP(hipGetLastError());
   return NDGI_OK;
 }
 

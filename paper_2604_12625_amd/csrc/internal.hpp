@@ -59,6 +59,7 @@ int launch_pages(ndgi_ctx* ctx, const ndgi_model* models, int32_t n_models, cons
                  const int32_t* n_reqs, int32_t max_reqs, int32_t page, void* dst, int64_t pitch, int prec,
                  hipStream_t s);
 int launch_bc4_blocks(const uint8_t* blocks, int64_t n, uint8_t* out, hipStream_t s);
+int launch_bc7_blocks(const uint8_t* blocks, int64_t n, uint8_t* out, hipStream_t s);
 int binned_workspace(const ndgi_model& m, int64_t n, int64_t* bytes);
 int launch_decode_binned(ndgi_ctx* ctx, const ndgi_model& m, const float* uvt, int64_t n, void* out, int prec,
                          void* ws, int64_t ws_bytes, hipStream_t s);

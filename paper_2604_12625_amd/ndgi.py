@@ -22,7 +22,7 @@ TRAIN_FORWARD, TRAIN_BACKWARD, TRAIN_LOSS_GRAD, TRAIN_FUSED, TRAIN_ADAM, TRAIN_Z
 
 EXPORTED = (
     "ndgi_create", "ndgi_destroy", "ndgi_last_error", "ndgi_get_error_flags",
-    "ndgi_bc4_decode_blocks", "ndgi_decode", "ndgi_decode_pages", "ndgi_decode_pages_graph",
+    "ndgi_bc4_decode_blocks", "ndgi_bc7_decode_blocks", "ndgi_decode", "ndgi_decode_pages", "ndgi_decode_pages_graph",
     "ndgi_set_launch", "ndgi_train_param_count", "ndgi_train_step", "ndgi_export",
     "ndgi_tile_stats", "ndgi_decode_binned_workspace", "ndgi_decode_binned",
     "ndgi_hybrid_mlp_size", "ndgi_hybrid_decode", "ndgi_hybrid_decode_pages",
@@ -108,6 +108,7 @@ def lib():
         L.ndgi_last_error.restype = C.c_char_p
         L.ndgi_get_error_flags.argtypes = [vp, vp, C.POINTER(C.c_uint32)]
         L.ndgi_bc4_decode_blocks.argtypes = [vp, i64, vp, vp]
+        L.ndgi_bc7_decode_blocks.argtypes = [vp, i64, vp, vp]
         L.ndgi_decode.argtypes = [vp, C.POINTER(NdgiModel), vp, i64, vp, i32, vp]
         pages = [vp, vp, i32, vp, vp, i32, i32, vp, i64, i32, vp]
         L.ndgi_decode_pages.argtypes = pages
@@ -316,6 +317,16 @@ def bc4_decode_blocks(blocks, out=None, stream=None):
         out = torch.empty((n, 16), dtype=torch.uint8, device=blocks.device)
     check(lib().ndgi_bc4_decode_blocks(_ptr(blocks), n, _ptr(out), _stream(stream)),
           "ndgi_bc4_decode_blocks")
+    return out
+
+
+def bc7_decode_blocks(blocks, out=None, stream=None):
+    """Decode [n][16] uint8 device BC7 mode-6 blocks to [n][16 texels][4 channels] uint8."""
+    import torch
+    n = blocks.shape[0]
+    if out is None:
+        out = torch.empty((n, 16, 4), dtype=torch.uint8, device=blocks.device)
+    check(lib().ndgi_bc7_decode_blocks(_ptr(blocks), n, _ptr(out), _stream(stream)), "ndgi_bc7_decode_blocks")
     return out
 
 

@@ -362,3 +362,30 @@ def test_bc7_pages_with_mixed_codecs(N, ctx, prec):
     valid = ref[:, 0] != -7.0
     assert_close(out[valid], ref[valid], TOL[prec], "bc7 pages")
     np.testing.assert_array_equal(out[~valid], -7.0)
+
+
+def _bc7_all_texels(blocks):
+    """Oracle decode of every texel of [n][16] mode-6 blocks -> [n][16][4]."""
+    n = blocks.shape[0]
+    ys, xs = np.meshgrid(np.arange(4), np.arange(4), indexing="ij")
+    b = np.repeat(blocks[:, None, :], 16, axis=1)
+    return O.bc7_texels(b, np.broadcast_to(xs.ravel(), (n, 16)), np.broadcast_to(ys.ravel(), (n, 16)))
+
+
+def test_bc7_block_decode_is_bit_exact(N):
+    """The device mode-6 texel decode, byte for byte: the hand-built golden blocks and
+    200,003 random blocks (every index pattern and p-bit) against the oracle."""
+    import torch
+    from tests.test_oracle_hybrid import _golden_bc7
+    rows = _golden_bc7()
+    gold = np.stack([b for b, _ in rows])
+    got = N.bc7_decode_blocks(torch.from_numpy(gold).cuda()).cpu().numpy()
+    for i, (_, want) in enumerate(rows):
+        np.testing.assert_array_equal(got[i], want)
+    blocks = I.random_bc7m6((200_003,), np.random.default_rng(84))
+    got = N.bc7_decode_blocks(torch.from_numpy(blocks).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(got, _bc7_all_texels(blocks))
+    assert N.bc7_decode_blocks(torch.from_numpy(blocks[:0]).cuda()).shape == (0, 16, 4)
+    with pytest.raises(N.NdgiError):   # misaligned source
+        raw = torch.from_numpy(blocks[:5]).cuda().view(-1)
+        N.bc7_decode_blocks(raw[8:8 + 64].view(4, 16))
