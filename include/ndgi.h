@@ -333,13 +333,14 @@ int ndgi_hybrid_decode(ndgi_ctx* ctx, const ndgi_hybrid_model* model, const floa
 
 /* Virtual-texturing page decode of hybrid models (Sec. 3.5; supplementary Sec. C): the
  * same request convention as ndgi_decode_pages (request count read from device memory),
- * with t clamped to [0, 1] and page a multiple of 32 in 32..4096.  Each map (one per-tile
- * model in the paper's production setting) has its own descriptor and decoder.
+ * with t clamped to [0, 1] and page 1..4096 texels (the paper's tiles are 128).  Each map
+ * (one per-tile model in the paper's production setting) has its own descriptor and
+ * decoder.
  *   widths: decoder widths among the requests' models, bit 0 = hidden 16, bit 1 = hidden
  *           64, 0 = either.  One persistent launch runs per width named; naming only the
  *           width in use saves the launch of the other.
- *   border: 0..32 texels of border around each page (Sec. 6: tiles are stored with a
- *           border for hardware filtering, padded by mirroring).  A request then writes a
+ *   border: 0..min(32, page) texels of border around each page (Sec. 6: tiles are stored
+ *           with a border for hardware filtering, padded by mirroring).  A request then writes a
  *           (page + 2 border)^2 region at dst_offset with dst_pitch >= page + 2 border;
  *           region texel (i, j) is the decode at map texel (mirror(page * page_x - border
  *           + i, W), mirror(page * page_y - border + j, H)), mirror(i, n) = -1 - i below 0,

@@ -262,13 +262,13 @@ static int check_hybrid_pages(ndgi_ctx* c, const ndgi_hybrid_model* models, int3
                               void* dst, int64_t pitch, int32_t prec, int32_t widths, int32_t border) {
   if (!c) return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: ctx is NULL");
   if (widths < 0 || widths > 3) return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: widths=%d not in 0..3", widths);
-  if (border < 0 || border > 32)
-    return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: border=%d not in 0..32", border);
+  if (border < 0 || border > 32 || border > page)
+    return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: border=%d not in 0..min(32, page)", border);
   if (prec != NDGI_PREC_F32 && prec != NDGI_PREC_F16)
     return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: bad prec %d", prec);
   if (n_models < 0 || max_reqs < 0) return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: negative count");
-  if (page < 32 || page > 4096 || (page & 31))
-    return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: page=%d must be a multiple of 32 in [32, 4096]", page);
+  if (page < 1 || page > 4096)
+    return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: page=%d not in [1, 4096]", page);
   if (pitch < page + 2 * border)
     return fail(NDGI_ERR_INVALID_ARG, "hybrid_decode_pages: dst_pitch=%lld < page + 2 border", (long long)pitch);
   if (!n_reqs || !dst || (n_models > 0 && !models) || (max_reqs > 0 && !reqs))

@@ -232,9 +232,11 @@ def test_hybrid_pages_nan_time_and_page_size(N, ctx):
     rq = N.page_requests([0], [0], [0], [0.5], [0])
     nreq = torch.tensor([1], dtype=torch.int32, device="cuda")
     dst = torch.empty((128 * 128, 3), dtype=torch.float16, device="cuda")
-    for page in (16, 48, 8192):
+    for page in (0, -32, 8192):
         with pytest.raises(N.NdgiError):
             ctx.hybrid_decode_pages(marr, 1, rq, nreq, 1, page, dst, 128, 1)
+    with pytest.raises(N.NdgiError):     # border wider than the page
+        ctx.hybrid_decode_pages(marr, 1, rq, nreq, 1, 8, dst, 128, 1, border=9)
 
 
 def _bordered(reqs, border):
@@ -389,3 +391,38 @@ def test_bc7_block_decode_is_bit_exact(N):
     with pytest.raises(N.NdgiError):   # misaligned source
         raw = torch.from_numpy(blocks[:5]).cuda().view(-1)
         N.bc7_decode_blocks(raw[8:8 + 64].view(4, 16))
+
+
+@pytest.mark.parametrize("page,border", [(100, 0), (100, 7), (40, 32), (5, 5)])
+def test_hybrid_pages_of_any_size(N, ctx, page, border):
+    """Pages need not be multiples of 32: 100-texel pages of 200 x 300 maps (ragged
+    sub-tiles), 40-texel pages with a 32-texel border, 5-texel pages."""
+    import torch
+    ctx.error_flags()   # clear what earlier tests left
+    models = [I.random_hybrid_model(200, 300, profile=p, plane=(100, 150, 24), config=85, index=i,
+                                    uvt_side=(48, 64), codec=i % 2) for i, p in enumerate(["M", "M.64", "L", "H"])]
+    R = page + 2 * border
+    g = np.random.default_rng(page + border)
+    reqs = []
+    for r in range(12):
+        mi = int(g.integers(0, 4))
+        px, py = int(g.integers(0, 200 // page)), int(g.integers(0, 300 // page))
+        reqs.append((mi, px, py, float(np.float32(g.random())), (r // 4) * R * 1024 + (r % 4) * R))
+    rows = 3 * R
+    hms = [N.HybridModel.from_numpy(m) for m in models]
+    marr = N.models_array(hms)
+    r = np.array(reqs, dtype=object)
+    rq = N.page_requests(r[:, 0].astype(np.int32), r[:, 1].astype(np.int32), r[:, 2].astype(np.int32),
+                         r[:, 3].astype(np.float32), r[:, 4].astype(np.int64))
+    nreq = torch.tensor([len(reqs)], dtype=torch.int32, device="cuda")
+    dst = torch.full((rows * 1024, 3), -7.0, dtype=torch.float16, device="cuda")
+    ctx.hybrid_decode_pages(marr, 4, rq, nreq, len(reqs), page, dst, 1024, 1, border=border)
+    torch.cuda.synchronize()
+    out = dst.float().cpu().numpy()
+    assert ctx.error_flags() == 0
+    ref = np.full(out.shape, -7.0)
+    assert O.hybrid_decode_pages(models, reqs, page, ref, 1024, border=border) == 0
+    valid = ref[:, 0] != -7.0
+    assert valid.sum() == len(reqs) * R * R
+    assert_close(out[valid], ref[valid], TOL[1], f"page {page} border {border}")
+    np.testing.assert_array_equal(out[~valid], -7.0)
