@@ -17,9 +17,9 @@
 
 namespace ndgi {
 
-constexpr int kSortWgs = 256;       // workgroups of the counting sort (1024 threads each)
+constexpr int kSortWgs = 512;       // workgroups of the counting sort (1024 threads each)
 static_assert(kSortWgs % 8 == 0, "sort slices are spread evenly over the 8 XCDs");
-constexpr int kBatch = 8;           // queries per thread whose loads are in flight together
+constexpr int kBatch = 16;          // queries per thread whose loads are in flight together
 constexpr int kSortThreads = 1024;
 constexpr int kMaxBins = 16384;     // LDS histogram capacity (64 KiB)
 constexpr int kPiece = 2048;        // at most this many queries per decode work item
@@ -92,13 +92,13 @@ __global__ __launch_bounds__(kSortThreads) void k_bin_count(ndgi_model m, BinGeo
 }
 
 // Per bin: exclusive prefix of counts over the sort workgroups, in place, and the bin's
-// total into start[bin].  A workgroup takes 64 bins; its four waves each take a quarter of
-// the sort rows, with all of a thread's loads issued together, and the quarter sums are
-// combined through LDS.
-constexpr int kColBins = 64, kColRows = kSortWgs / 4;
+// total into start[bin].  A workgroup takes 32 bins; eight groups of its threads each take
+// an eighth of the sort rows, with all of a thread's loads issued together, and the eighth
+// sums are combined through LDS.
+constexpr int kColParts = 8, kColBins = 256 / kColParts, kColRows = kSortWgs / kColParts;
 __global__ __launch_bounds__(256) void k_bin_colscan(int32_t* __restrict__ counts, int nbins,
                                                      int32_t* __restrict__ start) {
-  __shared__ int32_t part[4][kColBins];
+  __shared__ int32_t part[kColParts][kColBins];
   const int bl = threadIdx.x & (kColBins - 1), pr = threadIdx.x / kColBins;
   const int b = blockIdx.x * kColBins + bl;
   const bool live = b < nbins;
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256) void k_bin_colscan(int32_t* __restrict__ count
     counts[(int64_t)(pr * kColRows + r) * nbins + b] = run;
     run += c[r];
   }
-  if (pr == 3) start[b] = run;
+  if (pr == kColParts - 1) start[b] = run;
 }
 
 // start[0..nbins) := exclusive prefix of the bin totals, start[nbins] := n;
@@ -463,16 +463,36 @@ __device__ __forceinline__ void stage_fetch(const ndgi_model& m, const Item& I, 
                                             const float4* __restrict__ sorted, u32x4 (&wv)[kWinPer],
                                             u32x4 (&blk)[4], float4& rec0, int fx, int fy, int wave, int lane) {
   constexpr int kNodeU4 = GDT == NDGI_DTYPE_F16 ? 1 : 2;
+  constexpr uint32_t kStep = 256 / kNodeU4;          // window nodes per round of the workgroup
   const u32x4* gsrc = (const u32x4*)m.grid;
   const int total = m.T * w.ny * w.nx * kNodeU4;   // the host checked total <= kWinU4
+  // Node nd of the window is (key, rem) = (nd / A, nd % A) with A nodes per key, and rem is
+  // (row, column) = (rem / nx, rem % nx).  The thread's first node is divided once; each
+  // round then advances (key, rem) by the uniform (dq, dr) with one carry, and rem / nx is
+  // (rem * mx) >> 20 with mx = ceil(2^20 / nx), exact while ny * nx^2 <= 2^20 (the host
+  // checks this for the largest window).  All products are of 24-bit operands.
+  const uint32_t A = (uint32_t)(w.ny * w.nx), nx = (uint32_t)w.nx;
+  const uint32_t dq = kStep / A, dr = kStep - dq * A;
+  const uint32_t mx = ((1u << 20) + nx - 1) / nx;
+  const uint32_t plane = (uint32_t)m.Gh * (uint32_t)m.Gw;
+  const uint32_t nd0 = threadIdx.x / kNodeU4, part = threadIdx.x % kNodeU4;
+  const uint32_t key0 = nd0 / A;
+  uint32_t rem = nd0 - key0 * A, kbase = key0 * plane;   // the key's first node in the grid
+  const uint32_t corner = (uint32_t)w.y0 * (uint32_t)m.Gw + (uint32_t)w.x0;
 #pragma unroll
   for (int k = 0; k < kWinPer; ++k) {
-    const int idx = min((int)threadIdx.x + 256 * k, total - 1);
-    const int nd = idx / kNodeU4, part = idx - nd * kNodeU4;
-    const int key = nd / (w.ny * w.nx), rem = nd - key * (w.ny * w.nx);
-    const int gy = rem / w.nx, gx = rem - gy * w.nx;
-    wv[k] = gsrc[(((uint32_t)key * (uint32_t)m.Gh + (uint32_t)(w.y0 + gy)) * (uint32_t)m.Gw +
-                  (uint32_t)(w.x0 + gx)) * kNodeU4 + part];
+    const uint32_t gy = __umul24(rem, mx) >> 20, gx = rem - __umul24(gy, nx);
+    // threads past the window load its first node (in bounds; nothing is stored for them)
+    const uint32_t node = (int)threadIdx.x + 256 * k < total
+                              ? kbase + corner + __umul24(gy, (uint32_t)m.Gw) + gx
+                              : corner;
+    wv[k] = gsrc[node * kNodeU4 + part];
+    rem += dr;
+    kbase += dq * plane;
+    if (rem >= A) {
+      rem -= A;
+      kbase += plane;
+    }
   }
   const uint32_t bw = (uint32_t)m.W >> 2, bh = (uint32_t)m.H >> 2;
   const uint32_t gfx = min((uint32_t)(I.tx0 >> 2) + fx, bw - 1), gfy = min((uint32_t)(I.ty0 >> 2) + fy, bh - 1);
@@ -545,28 +565,36 @@ __global__ __launch_bounds__(256) void k_decode_binned_lds(
                                   query_grid8_at<GDT>(m, q.x, q.y, q.z, [&](int key, int gy, int gx) {
                                     const int ly = min(max(gy - w.y0, 0), w.ny - 1);
                                     const int lx = min(max(gx - w.x0, 0), w.nx - 1);
-                                    return (const uint4*)&gwin[((key * w.ny + ly) * w.nx + lx) * kNodeU4];
+                                    const uint32_t nd = __umul24(__umul24((uint32_t)key, (uint32_t)w.ny) + (uint32_t)ly,
+                                                                 (uint32_t)w.nx) + (uint32_t)lx;
+                                    return (const uint4*)&gwin[nd * kNodeU4];
                                   }, gr);
                                 }, out);
     }
   }
 }
 
-// Largest grid window (in uint4) of any tile of the map, by the kernel's own arithmetic.
-static int64_t max_window_u4(const ndgi_model& m, const BinGeom& bg) {
+// Largest grid window of any tile of the map, by the kernel's own arithmetic: its width
+// and height in nodes (each the largest over the tiles) and its size in uint4.
+static int64_t max_window_u4(const ndgi_model& m, const BinGeom& bg, int& mx, int& my) {
   const int TS = 1 << bg.ts_log2;
   const int64_t node_u4 = m.grid_dtype == NDGI_DTYPE_F16 ? 1 : 2;
-  if (bg.galign) return (int64_t)std::min(9, m.Gw) * std::min(9, m.Gh) * m.T * node_u4;
-  int mx = 0, my = 0, lo, hi;
-  for (int t = 0; t < bg.ntx; ++t) {
-    node_window(t * TS, TS, m.W, m.Gw, lo, hi);
-    mx = std::max(mx, hi - lo + 1);
+  if (bg.galign) {
+    mx = std::min(9, m.Gw);
+    my = std::min(9, m.Gh);
+  } else {
+    int lo, hi;
+    mx = my = 0;
+    for (int t = 0; t < bg.ntx; ++t) {
+      node_window(t * TS, TS, m.W, m.Gw, lo, hi);
+      mx = std::max(mx, hi - lo + 1);
+    }
+    for (int t = 0; t < bg.nty; ++t) {
+      node_window(t * TS, TS, m.H, m.Gh, lo, hi);
+      my = std::max(my, hi - lo + 1);
+    }
   }
-  for (int t = 0; t < bg.nty; ++t) {
-    node_window(t * TS, TS, m.H, m.Gh, lo, hi);
-    my = std::max(my, hi - lo + 1);
-  }
-  return (int64_t)mx * my * m.T * (m.grid_dtype == NDGI_DTYPE_F16 ? 1 : 2);
+  return (int64_t)mx * my * m.T * node_u4;
 }
 
 struct BinnedLayout {
@@ -625,7 +653,10 @@ int launch_decode_binned(ndgi_ctx* ctx, const ndgi_model& m, const float* uvt, i
   NDGI_HIP(hipGetLastError());
   const bool g16 = m.grid_dtype == NDGI_DTYPE_F16;
   // grid window in LDS when it fits (32-texel tiles only)
-  const bool glds = L.bg.ts_log2 == 5 && max_window_u4(m, L.bg) * 16 <= kGridLdsBytes;
+  // (the staging's row split (rem * mx) >> 20 is exact while ny * nx^2 <= 2^20)
+  int wmx, wmy;
+  const int64_t win_u4 = max_window_u4(m, L.bg, wmx, wmy);
+  const bool glds = L.bg.ts_log2 == 5 && win_u4 * 16 <= kGridLdsBytes && (int64_t)wmy * wmx * wmx <= (1 << 20);
 #define NDGI_BINNED_KERNEL(K)                                                                             \
   do {                                                                                                    \
     int64_t wgs = resident_wgs(ctx, (const void*)K);                                                      \

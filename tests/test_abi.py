@@ -60,11 +60,11 @@ def test_binned_workspace_size_query():
     m = _fake_model(ndgi, 4096, 4096, 1024, 1024, 24)        # 128 x 128 tiles of 32^2
     assert L.ndgi_decode_binned_workspace(ctypes.byref(m), 1 << 24, ctypes.byref(b)) == ndgi.OK
     nb = 128 * 128
-    assert b.value == 256 * nb * 4 + 2 * ((nb + 1) * 4 + 252) + 4 * ((1 << 24) // 2048 + nb) + 16 * (1 << 24)
+    assert b.value == 512 * nb * 4 + 2 * ((nb + 1) * 4 + 252) + 4 * ((1 << 24) // 2048 + nb) + 16 * (1 << 24)
     m = _fake_model(ndgi, 8192, 4100, 2048, 1025, 4)          # 64^2 tiles: 128 x 65 bins
     assert L.ndgi_decode_binned_workspace(ctypes.byref(m), 10, ctypes.byref(b)) == ndgi.OK
     nb = 128 * 65
-    assert b.value == 256 * nb * 4 + 2 * (((nb + 1) * 4 + 255) // 256 * 256) + (4 * nb + 255) // 256 * 256 + 160
+    assert b.value == 512 * nb * 4 + 2 * (((nb + 1) * 4 + 255) // 256 * 256) + (4 * nb + 255) // 256 * 256 + 160
     m = _fake_model(ndgi, 16384, 8192, 4096, 2048, 1)         # too many tiles
     assert L.ndgi_decode_binned_workspace(ctypes.byref(m), 10, ctypes.byref(b)) == ndgi.ERR_UNSUPPORTED
     assert b"8192" in L.ndgi_last_error() or b"tiles" in L.ndgi_last_error()

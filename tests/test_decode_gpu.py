@@ -161,6 +161,21 @@ def test_binned_long_time_axis(N, ctx, grid_dt):
         assert_rel(binned[sel], O.decode(m, q[sel]), tol, f"T=64 prec {prec}")
 
 
+@pytest.mark.parametrize("T", [2, 3])
+def test_binned_full_resolution_grid_window(N, ctx, T):
+    """A grid at the texel resolution: a 32-texel tile's window is 35 x 35 nodes, more nodes
+    per key than a workgroup stages per round, so the staging walk advances by less than one
+    key per round (T = 2 fits the LDS window; T = 3 does not and reads nodes from HBM)."""
+    m = I.random_model(160, 100, 160, 100, T, np.float16, np.float16, config=58)
+    q = np.concatenate([I.uniform_queries(30000, I.rng(58, I.P_QUERY, T)), EDGE_Q])
+    for prec, tol in ((1, TOL16), (0, TOL32)):
+        direct = _dec(N, ctx, m, q, prec)
+        binned, _ = _dec_binned(N, ctx, m, q, prec)
+        np.testing.assert_array_equal(binned, direct)
+        sel = np.random.default_rng(58).integers(0, q.shape[0], 2048)
+        assert_rel(binned[sel], O.decode(m, q[sel]), tol, f"full-resolution grid T={T} prec {prec}")
+
+
 @pytest.mark.parametrize("n", [1, 2, 63, 65, 1023, 1025, 4097])
 def test_binned_ragged_counts_reuse_workspace(N, ctx, n):
     """Counts around the wave (64) and chunk (1024) sizes; one workspace serves calls of
@@ -179,7 +194,7 @@ def test_binned_64_texel_tiles(N, ctx):
     """A map of more than 16384 tiles of 32^2 texels (8192 x 2112) bins by 64^2 tiles."""
     import torch
     m = I.random_model(8192, 2112, 2048, 528, 4, np.float16, np.float16, config=56)
-    assert ctx.binned_workspace_bytes(N.DeviceModel.from_numpy(m), 0) == 256 * 128 * 33 * 4 + \
+    assert ctx.binned_workspace_bytes(N.DeviceModel.from_numpy(m), 0) == 512 * 128 * 33 * 4 + \
         2 * (((128 * 33 + 1) * 4 + 255) // 256 * 256) + (4 * 128 * 33 + 255) // 256 * 256
     q = I.uniform_queries(300_000, I.rng(56, I.P_QUERY))
     got, _ = _dec_binned(N, ctx, m, q, 1)
