@@ -128,12 +128,17 @@ __global__ __launch_bounds__(256) void k_bin_colscan(int32_t* __restrict__ count
 // threads: the totals are staged in LDS with coalesced loads, each thread scans a run of 16
 // bins (the LDS array has one pad word per 16 so that the runs of a wave's lanes sit in
 // different banks), and the run sums are scanned across the workgroup with wave shuffles.
+// Every output goes back through the LDS array so that the global writes are coalesced
+// (a thread's own run of 16 words would put each lane of a store on its own line); the
+// item -> bin map is written straight from the runs only when it has more entries than
+// the array holds.
 __device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
 
 __global__ __launch_bounds__(1024) void k_bin_starts(int32_t* __restrict__ start, int32_t* __restrict__ items,
                                                      int32_t* __restrict__ item_bin, int nbins, int32_t n) {
-  __shared__ int32_t tot[kMaxBins + kMaxBins / 16];
-  __shared__ int32_t wsum[16], wsumi[16];
+  constexpr int kLds = kMaxBins + kMaxBins / 16;
+  __shared__ int32_t tot[kLds];
+  __shared__ int32_t wsum[16], wsumi[16], total_items;
   constexpr int kPer = kMaxBins / 1024;
   static_assert(kPer == 16, "one run of 16 bins per thread");
   {
@@ -146,11 +151,13 @@ __global__ __launch_bounds__(1024) void k_bin_starts(int32_t* __restrict__ start
   }
   __syncthreads();
   const int lo = threadIdx.x * kPer, hi = min(nbins, lo + kPer);
+  int32_t c[kPer];   // this thread's bin totals (bins past nbins count 0)
   int32_t s = 0, si = 0;
-  for (int i = lo; i < hi; ++i) {
-    const int32_t c = tot[pad16(i)];
-    s += c;
-    si += (c + kPiece - 1) / kPiece;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    c[k] = lo + k < hi ? tot[pad16(lo + k)] : 0;
+    s += c[k];
+    si += (c[k] + kPiece - 1) / kPiece;
   }
   // workgroup-wide inclusive scan of (s, si): within each wave, then over the 16 wave sums
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -180,27 +187,60 @@ __global__ __launch_bounds__(1024) void k_bin_starts(int32_t* __restrict__ start
     }
     wsum[lane] = w - wsum[lane];     // exclusive prefix of the wave sums
     wsumi[lane] = wi - wsumi[lane];
+    if (lane == 15) total_items = wi;
   }
   __syncthreads();
-  int32_t run = wsum[wave] + incl - s, runi = wsumi[wave] + incli - si;
-  // each thread rewrites only its own run of tot: totals become exclusive prefixes
-  for (int i = lo; i < hi; ++i) {
-    const int32_t c = tot[pad16(i)];
-    tot[pad16(i)] = run;
-    items[i] = runi;
-    const int32_t pieces = (c + kPiece - 1) / kPiece;
-    for (int k = 0; k < pieces; ++k) item_bin[runi + k] = i;
-    run += c;
-    runi += pieces;
-  }
-  if (threadIdx.x == 1023) {
-    start[nbins] = n;
-    items[nbins] = runi;
+  const int32_t run0 = wsum[wave] + incl - s, runi0 = wsumi[wave] + incli - si;
+  const int32_t nitems = total_items;
+  // bin starts: each thread rewrites only its own run of the array, then all write out
+  {
+    int32_t run = run0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      if (lo + k < hi) tot[pad16(lo + k)] = run;
+      run += c[k];
+    }
   }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kPer; ++k)
     if ((int)threadIdx.x + 1024 * k < nbins) start[threadIdx.x + 1024 * k] = tot[pad16(threadIdx.x + 1024 * k)];
+  __syncthreads();
+  // item prefixes per bin, the same way
+  {
+    int32_t runi = runi0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      if (lo + k < hi) tot[pad16(lo + k)] = runi;
+      runi += (c[k] + kPiece - 1) / kPiece;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    if ((int)threadIdx.x + 1024 * k < nbins) items[threadIdx.x + 1024 * k] = tot[pad16(threadIdx.x + 1024 * k)];
+  if (threadIdx.x == 0) {
+    start[nbins] = n;
+    items[nbins] = nitems;
+  }
+  // item -> bin map: staged in the array (unpadded) when it fits, else written directly
+  const bool staged = nitems <= kLds;
+  __syncthreads();
+  {
+    int32_t runi = runi0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int32_t pieces = (c[k] + kPiece - 1) / kPiece;
+      for (int j = 0; j < pieces; ++j) {
+        if (staged) tot[runi + j] = lo + k;
+        else item_bin[runi + j] = lo + k;
+      }
+      runi += pieces;
+    }
+  }
+  if (!staged) return;
+  __syncthreads();
+  for (int i = threadIdx.x; i < nitems; i += 1024) item_bin[i] = tot[i];
 }
 
 // Scatter: every query of sort workgroup wg goes to the next free slot of its bin; a

@@ -190,6 +190,19 @@ def test_binned_ragged_counts_reuse_workspace(N, ctx, n):
     assert_rel(got, O.decode(m, q), TOL16, f"n={n}")
 
 
+def test_binned_item_map_beyond_staging(N, ctx):
+    """36M queries over 6 tiles: 17,580 work items, more than the bin scan stages in LDS
+    (17,408), so the item -> bin map is written straight from the scan's runs."""
+    m = I.random_model(96, 64, 24, 16, 8, np.float16, np.float16, config=59)
+    q = I.uniform_queries(36_000_000, I.rng(59, I.P_QUERY))
+    got, _ = _dec_binned(N, ctx, m, q, 1)
+    direct = _dec(N, ctx, m, q, 1)
+    assert np.array_equal(got, direct)
+    del direct
+    sel = np.random.default_rng(59).integers(0, q.shape[0], 4096)
+    assert_rel(got[sel], O.decode(m, q[sel]), TOL16, "item map beyond staging")
+
+
 def test_binned_64_texel_tiles(N, ctx):
     """A map of more than 16384 tiles of 32^2 texels (8192 x 2112) bins by 64^2 tiles."""
     import torch
