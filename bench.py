@@ -441,6 +441,9 @@ def main():
                            "k_decode_binned_lds<FP16>)" if args.random_path == "binned" else "k_decode_query<FP16>"),
                    bytes_per_launch=RANDOM_COMPULSORY_BYTES)
     rl_rand["frac"] = rl_rand["achieved"] / HBM_PEAK_GBS
+    # HBM rate the kernels actually drive: counter bytes per launch over the live launch time
+    for rl, ms in ((rl_frame, f16["frame_ms"]), (rl_rand, f16["random_ms"])):
+        rl["traffic_gbs"] = None if rl["traffic"] is None else rl["traffic"] / (ms * 1e-3) / 1e9
     dominant = rl_rand if f16["random_ms"] >= f16["frame_ms"] else rl_frame
     other = rl_frame if dominant is rl_rand else rl_rand
 
