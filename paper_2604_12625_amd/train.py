@@ -134,29 +134,6 @@ def ndgi_apply(trainer: Trainer, samples):
     return _FN.apply(trainer.params, samples, trainer)
 
 
-def smoke_train_step(ctx: N.Context):
-    """One LOSS_GRAD step on a tiny problem checked against the oracle (used by smoke())."""
-    import torch
-
-    from oracle import ndgi_oracle as O
-
-    from . import inputs as I
-    g = I.rng(4, I.P_INIT, 99)
-    st = I.train_init(16, 16, 4, 4, 4, [0.5, 0.5, 0.5], g)
-    x, y, k = I.train_samples(512, 16, 16, 4, g)
-    tgt = g.uniform(0.1, 2.0, (4, 16, 16, 3)).astype(np.float16)
-    tr = Trainer(ctx, st)
-    smp = torch.from_numpy(I.pack_samples(x, y, k).view(np.int32)).cuda()
-    tgt_d = torch.from_numpy(tgt.view(np.uint16).view(np.int16)).cuda()
-    loss = float(tr.loss_grad(smp, tgt_d).item())
-    ref_loss, ref = O.train_grads(st, x, y, k, tgt[k, y, x].astype(np.float64))
-    assert abs(loss - ref_loss) <= 1e-5 * abs(ref_loss), (loss, ref_loss)
-    gm = tr.split(tr.grads)["mlp"].cpu().numpy()
-    err = np.max(np.abs(gm - ref["mlp"])) / np.max(np.abs(ref["mlp"]))
-    assert err <= 1e-4, err
-    print(f"smoke train: loss {loss:.6e} (oracle {ref_loss:.6e}), decoder grad err {err:.2e}")
-
-
 HYB_KEYS = ("fuv_ep", "fuv_w", "fuvt_ep", "fuvt_w", "fut", "fvt", "mlp")
 
 

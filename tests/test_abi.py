@@ -80,3 +80,24 @@ def test_hybrid_mlp_size_is_host_arithmetic():
     assert ndgi.hybrid_mlp_size(16) == 16 * 16 + 16 + 16 * 16 + 16 + 3 * 16 + 3 == 595
     assert ndgi.hybrid_mlp_size(64) == 64 * 16 + 64 + 64 * 64 + 64 + 3 * 64 + 3 == 5443
     assert ndgi.hybrid_mlp_size(32) == -1
+
+
+def test_product_package_never_imports_the_oracle():
+    """The oracle is test infrastructure: no source of the package names it, and importing
+    every module of the package leaves it out of sys.modules."""
+    import importlib
+    import subprocess
+    import sys
+    pkg = os.path.join(ROOT, "paper_2604_12625_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"\boracle\b", src), os.path.join(dirpath, f)
+    mods = [f[:-3] for f in os.listdir(pkg) if f.endswith(".py") and f != "__init__.py"]
+    code = ("import sys; sys.path.insert(0, %r)\n" % ROOT +
+            "".join(f"import paper_2604_12625_amd.{m}\n" for m in sorted(mods)) +
+            "bad = [m for m in sys.modules if m == 'oracle' or m.startswith('oracle.')]\n"
+            "assert not bad, bad\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
