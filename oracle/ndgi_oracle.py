@@ -803,25 +803,38 @@ def export_bc4(endpoints: np.ndarray, weights: np.ndarray) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------------------
-# Training of the hybrid layout (Sec. 3.4, Eq. 6-8; Sec. 4)
+# Training of the hybrid layout (Sec. 3.4, Eq. 6-7 and its noise equation; Sec. 4)
 # --------------------------------------------------------------------------------------
 # State (float32 master copies, one array per key):
-#   fuv_ep [H/4][W/4][4][2], fuv_w [H][W][4]            F_uv under BC simulation
-#   fuvt_ep [S][Gv/4][Gu/4][4][2], fuvt_w [S][Gv][Gu][4]  F_uvt slices under BC simulation
+#   fuv_ep [H/4][W/4][4][2], fuv_w [H][W][4]            F_uv as block endpoints and weights
+#   fuvt_ep [S][Gv/4][Gu/4][4][2], fuvt_w [S][Gv][Gu][4]  F_uvt slices, the same way
 #   fut [Tt][U][2], fvt [Tt][V][2]                       8-bit planes (trained in float)
 #   mlp [hybrid_mlp_size(hidden)]
+# (fuv_w [H][W] and fuvt_w [S][Gv][Gu] with codec 1: one weight per texel, Eq. (6)).
 # A training sample is texel (x, y) of baked frame i (time keys[i], or i / (n - 1) with no
-# key table), so tau = i / (n - 1).  Readings:
-# * flags: BCSIM quantises F_uv / F_uvt to the decodable 8-bit endpoints and 3-bit weights
-#   (R12) with the straight-through gradient (R14); without it the features are the plain
-#   Eq. (7) lerp (the ablation of the simulation).  NOISE adds U(-1/2, 1/2) / 256 to each of
-#   the 12 sampled map values (Eq. 8 for V_ut and V_vt; the paper adds noise to V_uvt and
-#   V_uv after the simulation as well).  QPLANES feeds F_ut / F_vt rounded to 8 bits, the
-#   values a decode sees (used to fine-tune the decoder on frozen features, Sec. 4).
+# key table), so tau = i / (n - 1).  Flags (readings):
+# * none: F_uv / F_uvt are the continuous Eq. (7) lerp of their endpoints and weights.
+#   This is the paper's BC simulation: the maps are parameterised by a block's two
+#   endpoints and per-texel weights during training (Sec. 3.4; supplementary ablation,
+#   "w/ BC simulation").
+# * NOISE adds U(-1/2, 1/2) / 256 to each of the 12 sampled map values (Sec. 3.4's noise
+#   equation for V_ut and V_vt, alpha = 1/256; the same text adds noise to the sampled V_uvt
+#   and V_uv).
+# * DIRECT: F_uv / F_uvt are per-texel values, the state's weights themselves (codec 0
+#   layout, one value per texel and channel; endpoints unused).  This is the supplementary
+#   ablation's "w/o BC simulation" arm, a directly optimised feature map that is
+#   block-compressed only after training (hybrid_encode).
+# * BCSIM rounds the endpoints and weights to the block format's grid during training (8-bit
+#   endpoints and 3-bit weights for BC4, R12; mode-6 endpoints and 4-bit weights for BC7)
+#   with the straight-through gradient (R14).  The paper does not describe rounding during
+#   training; it is kept as a variant, and for fine-tuning the decoder on features that are
+#   exactly the exported blocks' decode.
+# * QPLANES feeds F_ut / F_vt rounded to 8 bits, the values a decode sees (used to fine-tune
+#   the decoder on frozen features, Sec. 4).
 # * the noise of sample s, channel c in step `step` is a counter-based draw: the 64-bit
 #   SplitMix64 output function (Steele, Lea, Flood 2014) applied to
 #   seed * 0x9E3779B97F4A7C15 + step * 2^32 + s * 16 + c; its top 24 bits / 2^24 - 1/2.
-HT_BCSIM, HT_NOISE, HT_QPLANES = 1, 2, 4
+HT_BCSIM, HT_NOISE, HT_QPLANES, HT_DIRECT = 1, 2, 4, 8
 NOISE_ALPHA = 1.0 / 256.0
 _M64 = (1 << 64) - 1
 
@@ -845,17 +858,22 @@ def hybrid_noise(seed: int, step: int, s, c) -> np.ndarray:
     return top / float(1 << 24) - 0.5
 
 
-def _bc_texels(ep, wt, sl, ys, xs, bcsim: bool, codec: int = 0):
-    """4-channel texels of a BC-simulated map at (ys, xs) (and slice sl, or None):
+def _bc_texels(ep, wt, sl, ys, xs, bcsim: bool, codec: int = 0, direct: bool = False):
+    """4-channel texels of a block-parameterised map at (ys, xs) (and slice sl, or None):
     (value in [0, 1], d/de1, d/de2, d/dw) per channel.  codec 0: one weight per channel
     (BC4 per channel); codec 1: one weight per texel shared by the 4 channels (BC7 mode 6,
-    Eq. (6)), whose gradient is the sum over channels of dw."""
+    Eq. (6)), whose gradient is the sum over channels of dw.  direct: the weights are the
+    texel values themselves (codec 0 layout)."""
     if sl is None:
         e = ep[ys >> 2, xs >> 2]            # [..., 4, 2]
         w = wt[ys, xs]                      # [..., 4] or [...]
     else:
         e = ep[sl, ys >> 2, xs >> 2]
         w = wt[sl, ys, xs]
+    if direct:
+        assert codec == 0, "a directly optimised map keeps one value per texel and channel"
+        zero = np.zeros(np.shape(w))
+        return np.asarray(w, dtype=np.float64), zero, zero, np.ones(np.shape(w))
     if codec == 1:
         w = np.repeat(np.asarray(w)[..., None], 4, axis=-1)
         if bcsim:
@@ -890,6 +908,8 @@ def hybrid_train_forward(state: dict, xs, ys, fs, flags: int, seed: int = 0, ste
     keys = np.asarray(d["keys"], dtype=np.float64)
     t = keys[fs] if keys.size else tau
     bc = bool(flags & HT_BCSIM)
+    direct = bool(flags & HT_DIRECT)
+    assert not (bc and direct), "BCSIM and DIRECT exclude each other"
     codec = d.get("codec", 0)
     u = (xs + 0.5) / d["W"]
     v = (ys + 0.5) / d["H"]
@@ -903,12 +923,12 @@ def hybrid_train_forward(state: dict, xs, ys, fs, flags: int, seed: int = 0, ste
     for (ss, ws) in ((s0, ws0), (s1, ws1)):
         for (yy, wy) in ((gy0, wy0), (gy1, wy1)):
             for (xx, wx) in ((gx0, wx0), (gx1, wx1)):
-                val, d1, d2, dw = _bc_texels(state["fuvt_ep"], state["fuvt_w"], ss, yy, xx, bc, codec)
+                val, d1, d2, dw = _bc_texels(state["fuvt_ep"], state["fuvt_w"], ss, yy, xx, bc, codec, direct)
                 w = ws * wy * wx
                 Vuvt += w[..., None] * val
                 taps["uvt"].append((ss, yy, xx, w, d1, d2, dw))
     # V_uv: the texel itself
-    val, d1, d2, dw = _bc_texels(state["fuv_ep"], state["fuv_w"], None, ys, xs, bc, codec)
+    val, d1, d2, dw = _bc_texels(state["fuv_ep"], state["fuv_w"], None, ys, xs, bc, codec, direct)
     Vuv = val
     taps["uv"] = (d1, d2, dw)
     # planes
@@ -951,15 +971,18 @@ def gelu_grad(a: np.ndarray) -> np.ndarray:
 
 
 def hybrid_train_grads(state: dict, xs, ys, fs, target, flags: int, seed: int = 0, step: int = 0,
-                       s_offset: int = 0, n_total: int | None = None):
-    """L2 loss (mean over samples and channels) and its gradients for every state array.
-    With several models trained together the mean runs over all n_total samples of the
-    batch; this model's samples start at position s_offset."""
+                       s_offset: int = 0):
+    """L2 loss (mean over this model's samples and channels) and its gradients for every
+    state array.  Reading (several per-tile models trained together): each model's loss is
+    the mean over its own samples, so a model's gradients do not depend on how many other
+    models share the launch (Adam is not invariant to a common gradient scale, through its
+    epsilon); the loss reported for the launch is the mean of the models' losses.  This
+    model's samples start at position s_offset of the batch (their noise counters)."""
     d = state["dims"]
     codec = d.get("codec", 0)
     out, c = hybrid_train_forward(state, xs, ys, fs, flags, seed, step, need_cache=True, s_offset=s_offset)
     target = np.asarray(target, dtype=np.float64)
-    n = out.size if n_total is None else 3 * n_total
+    n = out.size
     loss = float(np.sum((out - target) ** 2) / n)
     P = c["P"]
     dout = (2.0 / n) * (out - target)
@@ -1042,6 +1065,274 @@ def hybrid_export(state: dict) -> dict:
                 hidden=d["hidden"], codec=codec, fuv=enc(state["fuv_ep"], state["fuv_w"]), fuvt=fuvt,
                 fut=q(state["fut"]), fvt=q(state["fvt"]), keys=np.asarray(d["keys"], dtype=np.float32),
                 mlp=np.asarray(state["mlp"], dtype=np.float32))
+
+
+# --------------------------------------------------------------------------------------
+# Block encoders from texel values, and the paper's export path (Sec. 3.4)
+# --------------------------------------------------------------------------------------
+# After training the paper reconstructs F_uv and F_uvt from the learned parameters,
+# quantises them to 8 bits and block-compresses the result (Sec. 3.4, last paragraph of
+# "Feature Map Compression"); the "w/o BC simulation" ablation arm compresses a directly
+# optimised map the same way (supplementary ablation study).  The paper names no encoder.
+# Readings:
+# * BC4: the block nearest to the 16 texels in summed squared error, found by trying every
+#   one of the 65536 endpoint pairs (both palette modes of R1) with each texel's best
+#   selector; ties go to the lowest e0 * 256 + e1, and per texel to the lowest selector.
+#   Exhaustive, so it is the optimum.
+# * BC7 mode 6: 2^58 endpoint settings are too many to try, so the encoder is a fixed,
+#   integer-only search (identical steps run on the GPU):
+#     1. endpoints at the corners of the texels' bounding box along its principal
+#        diagonal: the channel of largest spread is the reference, and each other channel
+#        runs from its minimum to its maximum when its covariance with the reference is
+#        >= 0, else from maximum to minimum;
+#     2. every target endpoint is quantised for each of the four p-bit pairs
+#        (v = clamp(floor((x - p + 1) / 2), 0, 127), endpoint 2 v + p); each texel takes its
+#        best 4-bit index (lowest index on ties) and the pair of least summed squared error
+#        is kept (a candidate replaces the current one only if strictly better);
+#     3. twice: the least-squares endpoints for the current indices (per channel, the 2x2
+#        normal equations of sum ((64 - w) E0 + w E1 - 64 x)^2, solved exactly and rounded
+#        half up, clamped to 0..255), quantised as in 2;
+#     4. best-improvement local search at step sizes s = 8, 4, 2, 1 in turn: 22 moves (each
+#        7-bit value of each endpoint -s and +s; all 4 values of one endpoint -s and +s
+#        together; each p-bit flipped; a move leaving 0..127 is not taken), indices refitted
+#        per move; the best move is taken while it is strictly better (ties between moves
+#        go to the first in that order), at most 64 rounds per step size;
+#     5. when texel 0's index has its top bit set, the endpoints swap and each index J
+#        becomes 15 - J (the anchor index has 3 bits; the decode is unchanged).
+#   Exact on blocks that one mode-6 block reproduces when the block uses indices 0 and 15;
+#   pinned by brute force on small cases (tests).
+
+def encode_bc4(texels) -> np.ndarray:
+    """BC4 blocks [n][8] of 8-bit texels [n][16] (texel s = 4 row + col): the exhaustive
+    search described above."""
+    X = np.asarray(texels, dtype=np.int64).reshape(-1, 16)
+    pair = np.arange(65536, dtype=np.int64)
+    code = np.arange(8, dtype=np.int64)
+    pal = bc4_palette_value((pair >> 8)[:, None], (pair & 255)[:, None], code[None, :]).astype(np.int64)
+    out = np.zeros((X.shape[0], 8), dtype=np.uint8)
+    for b in range(X.shape[0]):
+        vals, counts = np.unique(X[b], return_counts=True)
+        d = (pal[:, None, :] - vals[None, :, None]) ** 2          # [pairs][distinct values][codes]
+        sse = (d.min(-1) * counts[None, :]).sum(-1)
+        p = int(np.argmin(sse))                                    # first minimum: lowest pair
+        e0, e1 = p >> 8, p & 255
+        dp = (pal[p][None, :] - X[b][:, None]) ** 2                # [16][codes]
+        codes = dp.argmin(-1)                                      # lowest code on ties
+        field = 0
+        for s_ in range(16):
+            field |= int(codes[s_]) << (3 * s_)
+        out[b, 0], out[b, 1] = e0, e1
+        for k in range(6):
+            out[b, 2 + k] = (field >> (8 * k)) & 0xFF
+    return out
+
+
+_W4 = np.asarray(BC7_WEIGHTS4, dtype=np.int64)
+BC7_SEARCH_STEPS = (8, 4, 2, 1)
+BC7_SEARCH_ROUNDS = 64
+
+
+def _m6_fit(X, E0, E1):
+    """Best 4-bit index of every texel for endpoints E0, E1 [nb][4]: (J [nb][16], sse [nb])."""
+    pal = ((64 - _W4)[None, :, None] * E0[:, None, :] + _W4[None, :, None] * E1[:, None, :] + 32) >> 6
+    d = ((pal[:, None, :, :] - X[:, :, None, :]) ** 2).sum(-1)     # [nb][texel][index]
+    return d.argmin(-1), d.min(-1).sum(-1)
+
+
+def _m6_q7(x, p):
+    """7-bit value of target x [nb][4] for p-bit p [nb]."""
+    return np.clip((x - p[:, None] + 1) >> 1, 0, 127)
+
+
+def encode_bc7m6(texels) -> np.ndarray:
+    """BC7 mode-6 blocks [n][16] of 8-bit RGBA texels [n][16][4]: the search described above."""
+    X = np.asarray(texels, dtype=np.int64).reshape(-1, 16, 4)
+    nb = X.shape[0]
+    rows = np.arange(nb)
+    big = np.iinfo(np.int64).max
+    cur = dict(v0=np.zeros((nb, 4), np.int64), p0=np.zeros(nb, np.int64), v1=np.zeros((nb, 4), np.int64),
+               p1=np.zeros(nb, np.int64), J=np.zeros((nb, 16), np.int64), sse=np.full(nb, big))
+
+    def take(v0, p0, v1, p1):
+        J, sse = _m6_fit(X, 2 * v0 + p0[:, None], 2 * v1 + p1[:, None])
+        t = sse < cur["sse"]
+        for k, val in (("v0", v0), ("p0", p0), ("v1", v1), ("p1", p1), ("J", J), ("sse", sse)):
+            cur[k] = np.where(t[:, None], val, cur[k]) if val.ndim == 2 else np.where(t, val, cur[k])
+
+    def quantised(A, B):
+        for q0, q1 in ((0, 0), (0, 1), (1, 0), (1, 1)):
+            p0, p1 = np.full(nb, q0, np.int64), np.full(nb, q1, np.int64)
+            take(_m6_q7(A, p0), p0, _m6_q7(B, p1), p1)
+
+    # 1-2: bounding-box diagonal
+    D = 16 * X - X.sum(1, keepdims=True)
+    var = (D * D).sum(1)
+    ref = var.argmax(-1)
+    cov = (D * D[rows, :, ref][:, :, None]).sum(1)
+    lo, hi = X.min(1), X.max(1)
+    pos = cov >= 0
+    quantised(np.where(pos, lo, hi), np.where(pos, hi, lo))
+    # 3: least-squares endpoints for the current indices, twice
+    for _ in range(2):
+        w = _W4[cur["J"]]
+        a, b = 64 - w, w
+        Aa, Bab, Cb = (a * a).sum(1), (a * b).sum(1), (b * b).sum(1)
+        r0 = 64 * (a[:, :, None] * X).sum(1)
+        r1 = 64 * (b[:, :, None] * X).sum(1)
+        det = Aa * Cb - Bab * Bab
+        ok = det > 0
+        dd = np.where(ok, det, 1)[:, None]
+        n0 = Cb[:, None] * r0 - Bab[:, None] * r1
+        n1 = Aa[:, None] * r1 - Bab[:, None] * r0
+        E0 = np.clip(np.floor_divide(2 * n0 + dd, 2 * dd), 0, 255)
+        E1 = np.clip(np.floor_divide(2 * n1 + dd, 2 * dd), 0, 255)
+        E0 = np.where(ok[:, None], E0, 2 * cur["v0"] + cur["p0"][:, None])
+        E1 = np.where(ok[:, None], E1, 2 * cur["v1"] + cur["p1"][:, None])
+        quantised(E0, E1)
+    # 4: local search, coarse to fine
+    for st in BC7_SEARCH_STEPS:
+        moves = ([(k, c, dv) for k in (0, 1) for c in range(4) for dv in (-st, st)] +
+                 [(k, 4, dv) for k in (0, 1) for dv in (-st, st)] + [(0, -1, 0), (1, -1, 0)])
+        for _ in range(BC7_SEARCH_ROUNDS):
+            cand = []
+            for (k, c, dv) in moves:
+                v0, p0, v1, p1 = cur["v0"].copy(), cur["p0"].copy(), cur["v1"].copy(), cur["p1"].copy()
+                if c >= 0:
+                    v = v0 if k == 0 else v1
+                    cols = slice(None) if c == 4 else slice(c, c + 1)
+                    v[:, cols] += dv
+                    valid = ((v[:, cols] >= 0) & (v[:, cols] <= 127)).all(1)
+                    np.clip(v, 0, 127, out=v)
+                else:
+                    valid = np.ones(nb, bool)
+                    if k == 0:
+                        p0 = 1 - p0
+                    else:
+                        p1 = 1 - p1
+                J, sse = _m6_fit(X, 2 * v0 + p0[:, None], 2 * v1 + p1[:, None])
+                cand.append((np.where(valid, sse, big), v0, p0, v1, p1, J))
+            S = np.stack([c_[0] for c_ in cand], axis=1)
+            best = S.argmin(1)
+            better = S[rows, best] < cur["sse"]
+            if not better.any():
+                break
+            for i, (sse, v0, p0, v1, p1, J) in enumerate(cand):
+                t = better & (best == i)
+                for kk, val in (("v0", v0), ("p0", p0), ("v1", v1), ("p1", p1), ("J", J), ("sse", sse)):
+                    cur[kk] = np.where(t[:, None], val, cur[kk]) if val.ndim == 2 else np.where(t, val, cur[kk])
+    # 5: anchor and packing
+    out = np.zeros((nb, 16), dtype=np.uint8)
+    for i in range(nb):
+        a, b, pa, pb = cur["v0"][i], cur["v1"][i], int(cur["p0"][i]), int(cur["p1"][i])
+        idx = [int(j) for j in cur["J"][i]]
+        if idx[0] >= 8:
+            a, b, pa, pb = b, a, pb, pa
+            idx = [15 - j for j in idx]
+        bits = 0x40
+        for c in range(4):
+            bits |= int(a[c]) << (7 + 14 * c)
+            bits |= int(b[c]) << (14 + 14 * c)
+        bits |= pa << 63
+        bits |= pb << 64
+        bits |= idx[0] << 65
+        for s_ in range(1, 16):
+            bits |= idx[s_] << (64 + 4 * s_)
+        out[i] = np.frombuffer(bits.to_bytes(16, "little"), dtype=np.uint8)
+    return out
+
+
+def _map_texels_u8(ep, wt, flags: int, codec: int) -> np.ndarray:
+    """8-bit texels [..][H][W][4] of a block-parameterised map (endpoints [..][H/4][W/4][4][2],
+    weights [..][H][W][4] or, codec 1, [..][H][W]) as training with `flags` reads it: the
+    simulated texel under BCSIM; else the value v (the weight itself under DIRECT, the float32
+    Eq. (7) lerp fl32(fl32(fl32(1 - w) e1) + fl32(w e2)) otherwise) quantised as
+    clamp(rint(fl32(255 v)), 0, 255)."""
+    ep = np.asarray(ep, dtype=np.float32)
+    wt = np.asarray(wt, dtype=np.float32)
+    if codec == 1:
+        wt = np.repeat(wt[..., None], 4, axis=-1)
+    e = np.repeat(np.repeat(ep, 4, axis=-4), 4, axis=-3)          # [..][H][W][4][2]
+    if flags & HT_BCSIM:
+        if codec == 1:
+            E1 = bc7_quantise_endpoint(ep[..., 0])[0]
+            E2 = bc7_quantise_endpoint(ep[..., 1])[0]
+            E1 = np.repeat(np.repeat(E1, 4, axis=-3), 4, axis=-2)
+            E2 = np.repeat(np.repeat(E2, 4, axis=-3), 4, axis=-2)
+            w = _W4[quantise_weight4(wt)]
+            return ((64 - w) * E1 + w * E2 + 32) >> 6
+        return bcsim_value(quantise_endpoint(e[..., 0]), quantise_endpoint(e[..., 1]), quantise_weight(wt))
+    if flags & HT_DIRECT:
+        v = wt
+    else:
+        one = np.float32(1.0)
+        v = ((one - wt) * e[..., 0]) + (wt * e[..., 1])            # float32 throughout
+    return np.clip(np.rint(np.float32(255.0) * v), 0, 255).astype(np.int64)
+
+
+def _footprints(tex):
+    """[..][H][W][4] texels -> [..][H/4][W/4][16][4] (texel s = 4 row + col)."""
+    sh = tex.shape
+    t = tex.reshape(sh[:-3] + (sh[-3] // 4, 4, sh[-2] // 4, 4, 4))
+    n = len(sh) - 3
+    t = np.moveaxis(t, n + 2, n + 1)                               # [..][Hb][Wb][4 rows][4 cols][4]
+    return t.reshape(sh[:-3] + (sh[-3] // 4, sh[-2] // 4, 16, 4))
+
+
+def encode_map(tex, codec: int) -> np.ndarray:
+    """Blocks of an 8-bit 4-channel map [..][H][W][4]: BC7 mode 6 ([..][H/4][W/4][16], codec 1)
+    or one BC4 block per channel ([..][H/4][W/4][4][8], codec 0)."""
+    fp = _footprints(np.asarray(tex, dtype=np.int64))
+    lead = fp.shape[:-2]
+    if codec == 1:
+        return encode_bc7m6(fp.reshape(-1, 16, 4)).reshape(lead + (16,))
+    per_ch = np.moveaxis(fp, -1, -2)                               # [..][Hb][Wb][4 ch][16]
+    return encode_bc4(per_ch.reshape(-1, 16)).reshape(lead + (4, 8))
+
+
+def hybrid_encode(state: dict, flags: int, codec: int) -> dict:
+    """The paper's export (Sec. 3.4): F_uv and every F_uvt slice reconstructed from the
+    trained state as training with `flags` reads it, quantised to 8 bits and block-encoded
+    in `codec` (encode_map); planes rounded to 8 bits (rint of the float32 product 255 v);
+    the decoder as trained."""
+    d = state["dims"]
+    sc = d.get("codec", 0)
+    fuv = encode_map(_map_texels_u8(state["fuv_ep"], state["fuv_w"], flags, sc), codec)
+    fuvt = encode_map(_map_texels_u8(state["fuvt_ep"], state["fuvt_w"], flags, sc), codec)
+    q = lambda a: np.rint(np.float32(255.0) * np.asarray(a, dtype=np.float32)).astype(np.uint8)
+    return dict(W=d["W"], H=d["H"], Gu=d["Gu"], Gv=d["Gv"], S=d["S"], U=d["U"], V=d["V"], Tt=d["Tt"],
+                hidden=d["hidden"], codec=codec, fuv=fuv, fuvt=fuvt, fut=q(state["fut"]), fvt=q(state["fvt"]),
+                keys=np.asarray(d["keys"], dtype=np.float32), mlp=np.asarray(state["mlp"], dtype=np.float32))
+
+
+def _decode_map(blocks, codec: int, lead: tuple, H: int, W: int) -> np.ndarray:
+    """8-bit texels [..][H][W][4] of a block-compressed map."""
+    ys, xs = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    blocks = np.asarray(blocks, dtype=np.uint8)
+    out = []
+    for idx in np.ndindex(*lead):
+        b = blocks[idx]
+        sel = b[ys >> 2, xs >> 2]
+        out.append(bc7_texels(sel, xs, ys) if codec == 1 else bc4_texels(sel, xs, ys))
+    return np.stack(out).reshape(lead + (H, W, 4))
+
+
+def hybrid_import(model: dict, frames: int) -> dict:
+    """A directly parameterised training state (codec 0 layout, flag DIRECT) holding a
+    compressed model: F_uv / F_uvt weights = decoded byte / 255 (float32 division), endpoints
+    (0, 1) (so the plain Eq. (7) lerp reads the same values), planes = byte / 255, the decoder
+    in float32.  Fine-tuning the decoder on it with frozen features (DIRECT | QPLANES) trains
+    on exactly what a decode of the model reads (Sec. 4, final training stage)."""
+    codec = model.get("codec", 0)
+    H, W, S, Gu, Gv = model["H"], model["W"], model["S"], model["Gu"], model["Gv"]
+    f32 = lambda q: np.asarray(q, dtype=np.float32) / np.float32(255.0)
+    uv = _decode_map(model["fuv"], codec, (), H, W)
+    uvt = _decode_map(model["fuvt"], codec, (S,), Gv, Gu)
+    ep = lambda lead: np.stack([np.zeros(lead + (4,), np.float32), np.ones(lead + (4,), np.float32)], axis=-1)
+    dims = dict(W=W, H=H, Gu=Gu, Gv=Gv, S=S, U=model["U"], V=model["V"], Tt=model["Tt"], hidden=model["hidden"],
+                frames=frames, keys=np.asarray(model.get("keys", []), dtype=np.float32), codec=0)
+    return dict(dims=dims, fuv_ep=ep((H // 4, W // 4)), fuv_w=f32(uv), fuvt_ep=ep((S, Gv // 4, Gu // 4)),
+                fuvt_w=f32(uvt), fut=f32(model["fut"]), fvt=f32(model["fvt"]),
+                mlp=np.asarray(model["mlp"], dtype=np.float32).copy())
 
 
 # --------------------------------------------------------------------------------------
