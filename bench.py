@@ -274,8 +274,9 @@ def run_hybrid(args, torch, N, I, ctx, reps=30, warm=5):
 
 def run_hybrid_train(args, torch, N, I, ctx, steps=10, warm=3):
     """The paper's production training step: 64 tile models of 128^2 (profile M, BC7), 4096
-    samples per model (the paper's batch), one fused step (forward with BC simulation and
-    noise, loss, backward, Adam) per launch pair; samples drawn before the timed region."""
+    samples per model (the paper's batch), one fused phase-1 step (forward on the continuous
+    endpoint / weight maps with noise, loss, backward, Adam) per launch pair; samples drawn
+    before the timed region."""
     from paper_2604_12625_amd.train import HybridTrainer, hybrid_normalize_target
     keys = I.lightmap_key_times(I.rng(6, I.P_MODEL, 1))
     frames, M, Bm = len(keys), 64, 4096
@@ -286,7 +287,7 @@ def run_hybrid_train(args, torch, N, I, ctx, steps=10, warm=3):
     tiles = full.view(frames, 8, 128, 8, 128, 3).permute(1, 3, 0, 2, 4, 5).reshape(M * frames, 128, 128, 3)
     tgt, _ = hybrid_normalize_target(ctx, tiles.contiguous().view(torch.int16), 2.2)
     smp = [I.train_samples_torch(M * Bm, 128, 128, frames, seed=80_000 + i, border=4) for i in range(warm + steps)]
-    flags = N.HTRAIN_BCSIM | N.HTRAIN_NOISE
+    flags = N.HTRAIN_NOISE
     for i in range(warm):
         tr.step(smp[i], tgt, flags)
     torch.cuda.synchronize()
@@ -371,7 +372,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2", choices=["c2", "c5", "hfit", "hmap"])
-    ap.add_argument("--codec", default="bc7", choices=["bc7", "bc4"],
+    ap.add_argument("--codec", default="both", choices=["both", "bc7", "bc4"],
                     help="block format of F_uv / F_uvt for the hfit and hmap workloads")
     ap.add_argument("--border", type=int, default=4, help="mirrored tile border (texels) of the hmap workload")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)

@@ -122,6 +122,15 @@ int ndgi_get_error_flags(ndgi_ctx* ctx, hipStream_t stream, uint32_t* flags_out)
  * n = 0 is a no-op.  Errors: INVALID_ARG (n < 0, NULL pointers when n > 0). */
 int ndgi_bc4_decode_blocks(const uint8_t* blocks, int64_t n, uint8_t* out16, hipStream_t stream);
 
+/* The same decode through one of the texel decoders inside the decode kernels, for checking
+ * them exhaustively: impl 0 = the integer decoder above, 1 = the float decoder of the query,
+ * page and hybrid kernels (floor(e0 + 0.5 + j (e1 - e0) / D) as one FMA), 2 = the row decoder
+ * of the frame and binned kernels (palette built once per block in FP16 packs, four texels
+ * per byte permute).  Same layouts and errors as ndgi_bc4_decode_blocks (also impl out of
+ * 0..2). */
+int ndgi_bc4_decode_blocks_impl(const uint8_t* blocks, int64_t n, uint8_t* out16, int32_t impl,
+                                hipStream_t stream);
+
 /* Decode n BC7 mode-6 blocks (the block format of the hybrid layout's F_uv and F_uvt,
  * NDGI_CODEC_BC7; Sec. 3.4), bit-exactly, as the hybrid decode reads them.  blocks: device
  * [n][16] bytes, 16-byte aligned, each a 128-bit little-endian value: 7-bit endpoint
@@ -132,6 +141,38 @@ int ndgi_bc4_decode_blocks(const uint8_t* blocks, int64_t n, uint8_t* out16, hip
  * index's 4-bit weight (0 4 9 13 17 21 26 30 34 38 43 47 51 55 60 64).
  * n = 0 is a no-op.  Errors: INVALID_ARG (n < 0, NULL or misaligned pointers when n > 0). */
 int ndgi_bc7_decode_blocks(const uint8_t* blocks, int64_t n, uint8_t* out64, hipStream_t stream);
+
+/* ---------------------------------------------------------------- block encoders */
+/* The paper block-compresses its trained feature maps after quantising them to 8 bits
+ * (Sec. 3.4, last paragraph of Feature Map Compression) and names no encoder.  These encode
+ * 8-bit texel values; ndgi_hybrid_encode applies them to a training state. */
+
+/* BC4: for each block of 16 texels (texels: device [n][16] bytes, texel s = 4*row + col) the
+ * block of least summed squared error over all 65536 endpoint pairs of both palette modes
+ * (ndgi_bc4_decode_blocks' palettes), each texel at its nearest palette entry: the exact
+ * optimum.  Ties: the lowest e0 * 256 + e1, then per texel the lowest selector.  out: device
+ * [n][8], 8-byte aligned.  n = 0 is a no-op.  Errors: INVALID_ARG (n < 0, NULL or misaligned
+ * pointers). */
+int ndgi_bc4_encode_blocks(const uint8_t* texels, int64_t n, uint8_t* out, hipStream_t stream);
+
+/* BC7 mode 6: for each block of 16 RGBA texels (texels: device [n][16][4] bytes) a mode-6
+ * block found by a fixed integer search (the optimum is out of reach: 2^58 endpoint
+ * settings): (1) endpoints at the corners of the texels' bounding box along its principal
+ * diagonal (reference channel = largest spread; a channel runs min -> max when its
+ * covariance with the reference is >= 0, else max -> min); (2) both endpoints quantised for
+ * each of the four p-bit pairs, v = clamp(floor((x - p + 1) / 2), 0, 127); (3) twice, the
+ * least-squares endpoints of the current indices (2x2 normal equations per channel, exact
+ * integers, rounded half up, clamped to 0..255), quantised as in (2); (4) best-improvement
+ * local search at steps 8, 4, 2, 1 (at most 64 rounds each) over 22 moves in a fixed order:
+ * each 7-bit value of endpoint 0 then endpoint 1 by -s, +s; all four values of endpoint 0 then
+ * endpoint 1 by -s, +s; the p-bit of endpoint 0, then of endpoint 1, flipped (moves leaving
+ * 0..127 are not taken), the first strictly best move taken while it improves; a candidate
+ * replaces the current block only when strictly better, and every candidate's indices are
+ * refitted (each texel its least-error index, the lowest on ties); (5) when texel 0's index
+ * is >= 8 the endpoints swap and each index J becomes 15 - J.  out: device [n][16], 16-byte
+ * aligned, in ndgi_bc7_decode_blocks' layout.  Reproduces exactly any texels that a mode-6
+ * block using indices 0 and 15 decodes to.  n = 0 is a no-op.  Errors: INVALID_ARG. */
+int ndgi_bc7_encode_blocks(const uint8_t* texels, int64_t n, uint8_t* out, hipStream_t stream);
 
 /* ---------------------------------------------------------------- decode */
 
@@ -339,8 +380,9 @@ int ndgi_hybrid_decode(ndgi_ctx* ctx, const ndgi_hybrid_model* model, const floa
  *   widths: decoder widths among the requests' models, bit 0 = hidden 16, bit 1 = hidden
  *           64, 0 = either.  One persistent launch runs per width named; naming only the
  *           width in use saves the launch of the other.
- *   border: 0..min(32, page) texels of border around each page (Sec. 6: tiles are stored
- *           with a border for hardware filtering, padded by mirroring).  A request then writes a
+ *   border: 0..min(32, page) texels of border around each page (supplementary Virtual
+ *           Texturing section: tiles are stored with a border for hardware filtering, padded
+ *           by mirroring).  A request then writes a
  *           (page + 2 border)^2 region at dst_offset with dst_pitch >= page + 2 border;
  *           region texel (i, j) is the decode at map texel (mirror(page * page_x - border
  *           + i, W), mirror(page * page_y - border + j, H)), mirror(i, n) = -1 - i below 0,
@@ -362,7 +404,7 @@ int ndgi_hybrid_decode_pages_graph(ndgi_ctx* ctx, const ndgi_hybrid_model* model
                                    int32_t max_reqs, int32_t page, void* dst, int64_t dst_pitch,
                                    int32_t prec, int32_t widths, int32_t border, hipStream_t stream);
 
-/* Trainable state of n_models hybrid models of equal sizes (Sec. 3.4, Eq. 6-8; Sec. 4; the
+/* Trainable state of n_models hybrid models of equal sizes (Sec. 3.4, Eq. 6-7; Sec. 4; the
  * paper trains one model per virtual-texture tile).  Per model the feature block is
  *   [ F_uv endpoints [H/4][W/4][4][2] | F_uv weights [H][W][4]
  *   | F_uvt endpoints [S][Gv/4][Gu/4][4][2] | F_uvt weights [S][Gv][Gu][4]
@@ -370,8 +412,9 @@ int ndgi_hybrid_decode_pages_graph(ndgi_ctx* ctx, const ndgi_hybrid_model* model
  * (weights [H][W] and [S][Gv][Gu] with codec NDGI_CODEC_BC7) and the decoder block
  * [ndgi_hybrid_mlp_size(hidden)]; params, grads, adam_m and adam_v
  * hold all feature blocks, model after model, then all decoder blocks:
- * n_models * ndgi_hybrid_train_param_count values.  Sizes as ndgi_hybrid_model, with W, H
- * <= 4096.  A training sample is texel (x, y) of baked frame f: t = keys[f] (keys given) or
+ * n_models * ndgi_hybrid_train_param_count values (with several models Tt * (U + V) must be
+ * even, so that every feature block is 16-byte aligned).  Sizes as ndgi_hybrid_model, with
+ * W, H <= 4096.  A training sample is texel (x, y) of baked frame f: t = keys[f] (keys given) or
  * f / (frames - 1), and tau = f / (frames - 1); model m's samples are batch entries
  * [m * per_model, (m + 1) * per_model) and its target is target[m]. */
 typedef struct ndgi_hybrid_train_state {
@@ -402,31 +445,46 @@ typedef struct ndgi_hybrid_batch {
     float* pred;              /* device [n][3] (FORWARD)                                  */
 } ndgi_hybrid_batch;
 
-/* Feature flags of a hybrid training step:
- *   BCSIM   F_uv and F_uvt under BC simulation: E = rint(fl32(255 e)), J = rint(fl32(7 w)),
- *           value floor(((7-J) E1 + J E2 + 3)/7) / 255, straight-through gradient of Eq. 7
- *           at (E/255, J/7); without it the plain Eq. 7 lerp (the simulation's ablation).
- *           With codec NDGI_CODEC_BC7 each endpoint takes the mode-6 7-bit values and p-bit
- *           E = 2 v + p nearest to fl32(255 e) in summed squared error (v = rint((x - p)/2)
- *           clamped to 0..127, ties p = 0), J = rint(fl32(15 w)), weight wt = (64 J + 7)/15,
- *           value ((64 - wt) E1 + wt E2 + 32) >> 6 / 255, gradient at (E/255, wt/64).
- *   NOISE   U(-1/2, 1/2) / 256 added to each of the 12 sampled map values (Eq. 8); draw c of
- *           sample s in a step is the SplitMix64 output of seed * 0x9E3779B97F4A7C15 +
- *           step * 2^32 + 16 s + c, top 24 bits / 2^24 - 1/2.
+/* Feature flags of a hybrid training step.  With no flag F_uv and every F_uvt slice are the
+ * continuous Eq. 7 lerp of their block endpoints and per-texel weights (Eq. 6): this is the
+ * paper's BC simulation (Sec. 3.4; the supplementary ablation's "w/ BC simulation" arm).
+ *   NOISE   U(-1/2, 1/2) / 256 added to each of the 12 sampled map values (Sec. 3.4's noise
+ *           equation names V_ut and V_vt with alpha = 1/256; the same section adds noise to
+ *           the sampled V_uvt and V_uv); draw c of sample s in a step is the SplitMix64
+ *           output of seed * 0x9E3779B97F4A7C15 + step * 2^32 + 16 s + c, top 24 bits / 2^24
+ *           - 1/2.
+ *   DIRECT  F_uv / F_uvt are per-texel values, the state's weights themselves (the state
+ *           must have codec NDGI_CODEC_BC4: one value per texel and channel; endpoints are
+ *           unused and get no gradient).  The supplementary ablation's "w/o BC simulation"
+ *           arm (a directly optimised map, block-compressed after training), and the layout
+ *           ndgi_hybrid_import writes.  Excludes BCSIM.
+ *   BCSIM   rounding to the block format's grid during training, a variant the paper does
+ *           not describe: E = rint(fl32(255 e)), J = rint(fl32(7 w)), value
+ *           floor(((7-J) E1 + J E2 + 3)/7) / 255, straight-through gradient of Eq. 7 at
+ *           (E/255, J/7).  With codec NDGI_CODEC_BC7 each endpoint takes the mode-6 7-bit
+ *           values and p-bit E = 2 v + p nearest to fl32(255 e) in summed squared error
+ *           (v = rint((x - p)/2) clamped to 0..127, ties p = 0), J = rint(fl32(15 w)),
+ *           weight wt = (64 J + 7)/15, value ((64 - wt) E1 + wt E2 + 32) >> 6 / 255,
+ *           gradient at (E/255, wt/64).  The forward then equals the decode of
+ *           ndgi_hybrid_export's blocks.
  *   QPLANES F_ut and F_vt rounded to 8 bits as a decode sees them (decoder fine-tune on
  *           frozen features: lr_feat = 0). */
 #define NDGI_HTRAIN_BCSIM   1
 #define NDGI_HTRAIN_NOISE   2
 #define NDGI_HTRAIN_QPLANES 4
+#define NDGI_HTRAIN_DIRECT  8
 
 /* Float parameters of one model of a hybrid state; -1 for sizes out of range. */
 int64_t ndgi_hybrid_train_param_count(int32_t W, int32_t H, int32_t Gu, int32_t Gv, int32_t S, int32_t U,
                                       int32_t V, int32_t Tt, int32_t hidden, int32_t codec);
 
 /* One hybrid training operation: mode NDGI_TRAIN_FORWARD (pred), NDGI_TRAIN_LOSS_GRAD
- * (*loss_dev = mean over samples and channels of (pred - target)^2, FP64; grads +=), FUSED
+ * (grads += the gradient of each model's loss, the mean over that model's own samples and
+ * channels of (pred - target)^2, so a model trains as it would alone (Sec. 4 trains one model
+ * per tile); *loss_dev = the mean of the models' losses, FP64), FUSED
  * (LOSS_GRAD then ADAM), ADAM (dense Adam, PyTorch semantics, feature maps projected to
- * [0, 1], grads zeroed, step += 1), ZERO_GRAD.  flags: NDGI_HTRAIN_*.  Errors: INVALID_ARG. */
+ * [0, 1], grads zeroed, step += 1), ZERO_GRAD.  flags: NDGI_HTRAIN_*.  Errors: INVALID_ARG
+ * (also DIRECT with BCSIM or with a BC7-layout state). */
 int ndgi_hybrid_train_step(ndgi_ctx* ctx, ndgi_hybrid_train_state* state, const ndgi_hybrid_batch* batch,
                            int32_t mode, int32_t flags, double* loss_dev, hipStream_t stream);
 
@@ -440,6 +498,32 @@ int ndgi_hybrid_train_step(ndgi_ctx* ctx, ndgi_hybrid_train_state* state, const 
 int ndgi_hybrid_export(ndgi_ctx* ctx, const ndgi_hybrid_train_state* state, int32_t model,
                        uint8_t* fuv_out, uint8_t* fuvt_out, uint8_t* fut_out, uint8_t* fvt_out,
                        void* mlp_out, int32_t mlp_dtype, hipStream_t stream);
+
+/* The paper's export (Sec. 3.4, last paragraph of Feature Map Compression) of model `model`
+ * of a trained state: F_uv and every F_uvt slice reconstructed as a training step with
+ * `flags` reads them (no flag: the FP32 Eq. 7 lerp fl32(fl32(fl32(1 - w) e1) + fl32(w e2));
+ * DIRECT: the weights; BCSIM: the rounded simulation's texel), quantised to 8 bits as
+ * clamp(rint(fl32(255 v)), 0, 255) (BCSIM: its byte), and block-encoded in `codec` by
+ * ndgi_bc4_encode_blocks (one block per channel, [H/4][W/4][4][8], [S][Gv/4][Gu/4][4][8]) or
+ * ndgi_bc7_encode_blocks ([H/4][W/4][16], [S][Gv/4][Gu/4][16]); planes rounded to 8 bits
+ * (rint of fl32(255 v)); the decoder converted to mlp_dtype.  Any output may be NULL to skip
+ * it (e.g. only the decoder and planes of a fine-tuned imported state).  Outputs are device
+ * memory, block outputs aligned to their block size.  Errors: INVALID_ARG (also DIRECT with
+ * BCSIM or with a BC7-layout state). */
+int ndgi_hybrid_encode(ndgi_ctx* ctx, const ndgi_hybrid_train_state* state, int32_t model, int32_t flags,
+                       int32_t codec, uint8_t* fuv_out, uint8_t* fuvt_out, uint8_t* fut_out, uint8_t* fvt_out,
+                       void* mlp_out, int32_t mlp_dtype, hipStream_t stream);
+
+/* Import of a block-compressed hybrid model into model `model` of a state with the BC4 layout
+ * (one value per texel and channel) and the model's sizes, for the final training stage
+ * (Sec. 4: the decoder fine-tuned on frozen features under quantisation and BC compression):
+ * F_uv / F_uvt weights = the decoded byte / 255 (FP32 division) in [H][W][4] and
+ * [S][Gv][Gu][4], their endpoints (0, 1), planes = byte / 255, the decoder as float.  A step
+ * with DIRECT | QPLANES (lr_feat = 0) then reads exactly what a decode of the model reads.
+ * model: host descriptor of device buffers.  Errors: INVALID_ARG (sizes differ, BC7-layout
+ * state, model index). */
+int ndgi_hybrid_import(ndgi_ctx* ctx, const ndgi_hybrid_model* model, ndgi_hybrid_train_state* state,
+                       int32_t model_index, hipStream_t stream);
 
 /* Target preprocessing of Sec. 4: y^(1/gamma) per texel and channel, divided per frame and
  * channel by its mean.  target: device FP16 bits [frames][H][W][3]; out: device float, same
@@ -464,6 +548,18 @@ int ndgi_hybrid_restore(ndgi_ctx* ctx, const void* pred, int32_t pred_dtype, int
 int ndgi_tile_stats(ndgi_ctx* ctx, const void* pred, int32_t pred_dtype,
                     const uint16_t* target, int32_t W, int32_t H, int32_t tile,
                     double* stats, hipStream_t stream);
+
+/* Tiled PSNR of supplementary Sec. D.2 from ndgi_tile_stats outputs, in FP64:
+ *   stats:   device double [n_maps][ceil(H/tile)][ceil(W/tile)][3] (n_maps maps of W x H)
+ *   tile_db: device double [n_maps][ceil(H/tile)][ceil(W/tile)] or NULL: each tile's
+ *            10 log10(range^2 / MSE), range = max - min of the target over the tile and its
+ *            channels, MSE over its texels and channels; NaN for a tile of zero range
+ *            (skipped), 100 dB for MSE 0
+ *   summary: device double [5] = (mean of tile_db over scored tiles, global PSNR over every
+ *            texel with the range of all tiles, least tile PSNR, scored tiles, tiles).
+ * Errors: INVALID_ARG. */
+int ndgi_psnr(ndgi_ctx* ctx, const double* stats, int32_t n_maps, int32_t W, int32_t H, int32_t tile,
+              double* tile_db, double* summary, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -563,8 +563,8 @@ def mirror_texel(i, n: int):
 def hybrid_decode_pages(models: list, reqs: list, page: int, dst: np.ndarray, pitch: int, border: int = 0) -> int:
     """Page decode of hybrid models (same request convention as :func:`decode_pages`).
 
-    With a border of b texels (Sec. 6: tiles stored with a small border for hardware
-    filtering, padded by mirroring) a request writes a (page + 2b)^2 region: its texel
+    With a border of b texels (supplementary Virtual Texturing section: tiles stored with a
+    small border for hardware filtering, padded by mirroring) a request writes a (page + 2b)^2 region: its texel
     (i, j) is the decode at the texel centre of map texel (mirror_texel(page px - b + i, W),
     mirror_texel(page py - b + j, H)).  Inside the map the border holds the neighbouring
     texels; past the map's edge it mirrors the map (for a per-tile model, the tile)."""

@@ -167,7 +167,16 @@ int ndgi_bc4_decode_blocks(const uint8_t* blocks, int64_t n, uint8_t* out16, hip
   if (n < 0) return fail(NDGI_ERR_INVALID_ARG, "bc4_decode_blocks: n < 0");
   if (n == 0) return NDGI_OK;
   if (!blocks || !out16) return fail(NDGI_ERR_INVALID_ARG, "bc4_decode_blocks: NULL pointer");
-  return launch_bc4_blocks(blocks, n, out16, s);
+  return launch_bc4_blocks(blocks, n, out16, 0, s);
+}
+
+int ndgi_bc4_decode_blocks_impl(const uint8_t* blocks, int64_t n, uint8_t* out16, int32_t impl, hipStream_t s) {
+  clear_error();
+  if (n < 0) return fail(NDGI_ERR_INVALID_ARG, "bc4_decode_blocks_impl: n < 0");
+  if (impl < 0 || impl > 2) return fail(NDGI_ERR_INVALID_ARG, "bc4_decode_blocks_impl: impl %d", impl);
+  if (n == 0) return NDGI_OK;
+  if (!blocks || !out16) return fail(NDGI_ERR_INVALID_ARG, "bc4_decode_blocks_impl: NULL pointer");
+  return launch_bc4_blocks(blocks, n, out16, impl, s);
 }
 
 int ndgi_bc7_decode_blocks(const uint8_t* blocks, int64_t n, uint8_t* out64, hipStream_t s) {

@@ -5,26 +5,39 @@
 namespace ndgi {
 
 // ------------------------------------------------------------------------ BC4 blocks
+// IMPL selects the texel decoder: 0 the integer bc4_texel, 1 the float bc4_texel_f of the
+// query, page and hybrid kernels, 2 the row decode bc4_rows of the frame and binned kernels.
+template <int IMPL>
 __global__ __launch_bounds__(256) void k_bc4_blocks(const uint8_t* __restrict__ blocks, int64_t n,
                                                      uint8_t* __restrict__ out) {
   for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n; b += (int64_t)gridDim.x * blockDim.x) {
     const uint2 w = ((const uint2*)blocks)[b];
     uint32_t o[4];
+    if constexpr (IMPL == 2) {
+      bc4_rows(w.x, w.y, 0, o[0], o[1]);
+      bc4_rows(w.x, w.y, 1, o[2], o[3]);
+    } else {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      uint32_t v = 0;
+      for (int r = 0; r < 4; ++r) {
+        uint32_t v = 0;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) v |= bc4_texel(w.x, w.y, 4 * r + c) << (8 * c);
-      o[r] = v;
+        for (int c = 0; c < 4; ++c) {
+          const uint32_t t = IMPL == 1 ? (uint32_t)bc4_texel_f(w.x, w.y, 4 * r + c) : bc4_texel(w.x, w.y, 4 * r + c);
+          v |= t << (8 * c);
+        }
+        o[r] = v;
+      }
     }
     ((uint4*)out)[b] = make_uint4(o[0], o[1], o[2], o[3]);
   }
 }
 
-int launch_bc4_blocks(const uint8_t* blocks, int64_t n, uint8_t* out, hipStream_t s) {
+int launch_bc4_blocks(const uint8_t* blocks, int64_t n, uint8_t* out, int impl, hipStream_t s) {
   const int64_t want = (n + 255) / 256;
   const int grid = (int)(want < 65536 ? want : 65536);
-  hipLaunchKernelGGL(k_bc4_blocks, dim3(grid), dim3(256), 0, s, blocks, n, out);
+  if (impl == 1) hipLaunchKernelGGL(k_bc4_blocks<1>, dim3(grid), dim3(256), 0, s, blocks, n, out);
+  else if (impl == 2) hipLaunchKernelGGL(k_bc4_blocks<2>, dim3(grid), dim3(256), 0, s, blocks, n, out);
+  else hipLaunchKernelGGL(k_bc4_blocks<0>, dim3(grid), dim3(256), 0, s, blocks, n, out);
   NDGI_HIP(hipGetLastError());
   return NDGI_OK;
 }

@@ -571,6 +571,33 @@ int check_hybrid(const ndgi_hybrid_model* m, const char* who) {
   return NDGI_OK;
 }
 
+// Import of a block-compressed 4-channel map into a directly parameterised training state:
+// texel (x, y) of slice sl becomes w[((sl H + y) W + x) 4 + c] = byte / 255 (FP32 division),
+// the byte being the texel decode of the model's blocks (codec 0: 32 bytes of BC4 per
+// footprint, codec 1: one BC7 mode-6 block).
+__global__ __launch_bounds__(256) void k_import_map(const uint8_t* __restrict__ blocks, int codec, int W, int H,
+                                                     int64_t texels, float* __restrict__ w) {
+  const int64_t per = (int64_t)W * H;
+  const int fpb = codec ? 16 : 32;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < texels; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t sl = i / per, rem = i - sl * per;
+    const int x = (int)(rem % W), y = (int)(rem / W);
+    const int64_t f = (sl * (H >> 2) + (y >> 2)) * (W >> 2) + (x >> 2);
+    float v[4];
+    fp4(blocks + f * fpb, codec, (uint32_t)(4 * (y & 3) + (x & 3)), v);
+    *(float4*)(w + i * 4) = make_float4(v[0] / 255.0f, v[1] / 255.0f, v[2] / 255.0f, v[3] / 255.0f);
+  }
+}
+
+int launch_import_map(const uint8_t* blocks, int codec, int W, int H, int S, float* w, int n_cu, hipStream_t s) {
+  const int64_t texels = (int64_t)W * H * S;
+  const int64_t want = (texels + 255) / 256, cap = (int64_t)n_cu * 16;
+  hipLaunchKernelGGL(k_import_map, dim3((unsigned)(want < cap ? (want < 1 ? 1 : want) : cap)), dim3(256), 0, s, blocks,
+                     codec, W, H, texels, w);
+  NDGI_HIP(hipGetLastError());
+  return NDGI_OK;
+}
+
 int launch_bc7_blocks(const uint8_t* blocks, int64_t n, uint8_t* out, hipStream_t s) {
   const int64_t want = (n + 255) / 256;
   const int grid = (int)(want < 65536 ? want : 65536);

@@ -1,8 +1,10 @@
-// Training of the hybrid layout (Sec. 3.4, Eq. 6-8; Sec. 4): BC simulation of F_uv and of
-// each F_uvt slice, 8-bit planes F_ut / F_vt trained in float with uniform noise standing
-// in for their quantisation, the GELU decoder, L2 loss in FP64, gradients, Adam (shared
-// with the other layout), export to a decodable model, and the target preprocessing
-// (gamma, per-frame mean) with its inverse.
+// Training of the hybrid layout (Sec. 3.4, Eq. 6-7 and its noise equation; Sec. 4): F_uv and
+// each F_uvt slice parameterised by block endpoints and per-texel weights (the paper's BC
+// simulation; optionally rounded to the block format's grid) or, for the ablation, directly
+// by texel values; 8-bit planes F_ut / F_vt trained in float with uniform noise standing in
+// for their quantisation; the GELU decoder, L2 loss in FP64, gradients, Adam (shared with the
+// other layout), export to a decodable model, and the target preprocessing (gamma,
+// per-frame mean) with its inverse.
 //
 // One sample per lane.  A training sample is texel (x, y) of baked frame f, so its texel
 // centre and frame time fix every interpolation weight.  One launch trains any number of
@@ -12,6 +14,7 @@
 // LDS (hidden 16 or 64); its weight gradients and its input gradients run on FP32 MFMA over
 // the wave's 64 samples (operands staged in LDS slabs); feature gradients go out as float
 // atomics, the contended F_uvt endpoint and plane ones summed in LDS per chunk first.
+#include "bcsim.hpp"
 #include "hybrid.hpp"
 #include "internal.hpp"
 
@@ -63,97 +66,6 @@ __device__ __forceinline__ float hyb_noise(uint64_t base, uint64_t ctr) {
   x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
   x ^= x >> 31;
   return (float)(uint32_t)(x >> 40) * (1.0f / 16777216.0f) - 0.5f;
-}
-
-// One 4-channel texel of a BC-simulated map: ep = the footprint's [4][2] endpoints,
-// w = the texel's 4 weights.  With the simulation: E = rint(fl32(255 e)), J = rint(fl32(7 w)),
-// value floor(((7-J) E1 + J E2 + 3) / 7) / 255 and the straight-through derivatives of
-// Eq. 7 at (E/255, J/7); without it, Eq. 7 itself.
-struct BcTex { float v[4], d1[4], d2[4], dw[4]; };
-__device__ __forceinline__ BcTex bc_texel(const float* __restrict__ ep, const float* __restrict__ w, bool bcsim) {
-#pragma clang fp contract(off)
-  BcTex r;
-  const float4 ea = *(const float4*)ep, eb = *(const float4*)(ep + 4);
-  const float4 wv = *(const float4*)w;
-  const float e1[4] = {ea.x, ea.z, eb.x, eb.z}, e2[4] = {ea.y, ea.w, eb.y, eb.w}, ww[4] = {wv.x, wv.y, wv.z, wv.w};
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    if (bcsim) {
-      const int E1 = (int)rintf(255.0f * e1[c]), E2 = (int)rintf(255.0f * e2[c]), J = (int)rintf(7.0f * ww[c]);
-      r.v[c] = (float)(((7 - J) * E1 + J * E2 + 3) / 7) * (1.0f / 255.0f);
-      r.d1[c] = 1.0f - (float)J * (1.0f / 7.0f);
-      r.d2[c] = (float)J * (1.0f / 7.0f);
-      r.dw[c] = (float)(E2 - E1) * (1.0f / 255.0f);
-    } else {
-      r.v[c] = (1.0f - ww[c]) * e1[c] + ww[c] * e2[c];
-      r.d1[c] = 1.0f - ww[c];
-      r.d2[c] = ww[c];
-      r.dw[c] = e2[c] - e1[c];
-    }
-  }
-  return r;
-}
-
-// The same for the BC7 simulation (codec 1): one weight w per texel shared by the 4
-// channels.  Each endpoint takes the 7-bit values and p-bit of BC7 mode 6 nearest to
-// x = fl32(255 e) in summed squared error (v = rint((x - p) / 2) clamped to 0..127, E = 2 v + p;
-// ties keep p = 0; the errors are compared exactly, in FP64); J = rint(fl32(15 w)) with
-// weight (64 J + 7) / 15 (the format's table); value ((64 - w) E1 + w E2 + 32) >> 6 / 255;
-// straight-through derivatives of Eq. 7 at (E/255, w/64).  dw[c] is the channel's share of
-// the shared weight's derivative.
-__device__ __forceinline__ void bc7_endpoint(const float e[4], int E[4]) {
-#pragma clang fp contract(off)
-  double err[2] = {0.0, 0.0};
-  int Ep[2][4];
-#pragma unroll
-  for (int p = 0; p < 2; ++p)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const float x = 255.0f * e[c];
-      const int v = min(max((int)rintf((x - (float)p) * 0.5f), 0), 127);
-      Ep[p][c] = 2 * v + p;
-      const double dd = (double)Ep[p][c] - (double)x;
-      err[p] += dd * dd;
-    }
-  const int p = err[1] < err[0] ? 1 : 0;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) E[c] = p ? Ep[1][c] : Ep[0][c];
-}
-
-__device__ __forceinline__ BcTex bc7_texel(const float* __restrict__ ep, float w, bool bcsim) {
-#pragma clang fp contract(off)
-  BcTex r;
-  const float4 ea = *(const float4*)ep, eb = *(const float4*)(ep + 4);
-  const float e1[4] = {ea.x, ea.z, eb.x, eb.z}, e2[4] = {ea.y, ea.w, eb.y, eb.w};
-  if (bcsim) {
-    int E1[4], E2[4];
-    bc7_endpoint(e1, E1);
-    bc7_endpoint(e2, E2);
-    const int J = (int)rintf(15.0f * w);
-    const int wt = (64 * J + 7) / 15;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      r.v[c] = (float)(((64 - wt) * E1[c] + wt * E2[c] + 32) >> 6) * (1.0f / 255.0f);
-      r.d1[c] = 1.0f - (float)wt * (1.0f / 64.0f);
-      r.d2[c] = (float)wt * (1.0f / 64.0f);
-      r.dw[c] = (float)(E2[c] - E1[c]) * (1.0f / 255.0f);
-    }
-  } else {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      r.v[c] = (1.0f - w) * e1[c] + w * e2[c];
-      r.d1[c] = 1.0f - w;
-      r.d2[c] = w;
-      r.dw[c] = e2[c] - e1[c];
-    }
-  }
-  return r;
-}
-
-// Texel of either codec: weights at w (4 per texel for BC4, 1 for BC7).
-__device__ __forceinline__ BcTex sim_texel(const float* __restrict__ ep, const float* __restrict__ w, bool bcsim,
-                                           int codec) {
-  return codec ? bc7_texel(ep, *w, bcsim) : bc_texel(ep, w, bcsim);
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -218,7 +130,7 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
                                                                  const uint32_t* __restrict__ samples, int64_t n,
                                                                  const float* __restrict__ target,
                                                                  float* __restrict__ pred, int flags,
-                                                                 uint64_t noise_base, float inv3n,
+                                                                 uint64_t noise_base, float inv3n, double loss_w,
                                                                  double* __restrict__ loss_acc, int64_t chunk,
                                                                  int accum) {
   using Sh = HybShape<HD>;
@@ -231,6 +143,7 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
   float* const acc = dyn + waves * 2 * kSlab;
   const int64_t nE = (int64_t)d.S * (d.Gv / 4) * (d.Gu / 4) * 8, nP = d.o_mlp - d.o_ut;
   const bool bcsim = flags & NDGI_HTRAIN_BCSIM, noise = flags & NDGI_HTRAIN_NOISE, qplanes = flags & NDGI_HTRAIN_QPLANES;
+  const bool direct = flags & NDGI_HTRAIN_DIRECT;
   const int64_t nchunks = (n + chunk - 1) / chunk;
   const int rounds = (int)(chunk / nthr);
   int cur = -1;
@@ -278,13 +191,13 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
       for (int i = 0; i < 4; ++i) {
         const int64_t fp = ((int64_t)si * (d.Gv / 4) + (tys[i] >> 2)) * (d.Gu / 4) + (txs[i] >> 2);
         const BcTex b = sim_texel(P + d.o_tep + fp * 8, P + d.o_tw + (((int64_t)si * d.Gv + tys[i]) * d.Gu + txs[i]) * d.cw,
-                                  bcsim, d.codec);
+                                  bcsim, direct, d.codec);
 #pragma unroll
         for (int c = 0; c < 4; ++c) xin[c] = fmaf(ws * tw[i], b.v[c], xin[c]);
       }
     }
     const int64_t fpu = (int64_t)(y >> 2) * (d.W / 4) + (x >> 2);
-    const BcTex bu = sim_texel(P + fpu * 8, P + d.o_uvw + ((int64_t)y * d.W + x) * d.cw, bcsim, d.codec);
+    const BcTex bu = sim_texel(P + fpu * 8, P + d.o_uvw + ((int64_t)y * d.W + x) * d.cw, bcsim, direct, d.codec);
 #pragma unroll
     for (int c = 0; c < 4; ++c) xin[4 + c] = bu.v[c];
     const Axis pu = texel_axis<false>(x, d.U, d.W), pv = texel_axis<false>(y, d.V, d.H);
@@ -363,7 +276,7 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
         dout[c] = 2.0f * inv3n * e;
       }
       sq = wave_sum_d(sq);
-      if (lane == 0) atomicAdd(loss_acc, sq * (double)inv3n);
+      if (lane == 0) atomicAdd(loss_acc, sq * loss_w);
       // ---- decoder backward.  Layer 3: dW3[c][j] = sum dout[c] h2[j], db3 = sum dout
       {
         float v[16];
@@ -512,7 +425,7 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
         for (int i = 0; i < 4; ++i) {
           const int64_t fp = ((int64_t)si * (d.Gv / 4) + (tys[i] >> 2)) * (d.Gu / 4) + (txs[i] >> 2);
           const int64_t wi = (((int64_t)si * d.Gv + tys[i]) * d.Gu + txs[i]) * d.cw;
-          const BcTex b = sim_texel(P + d.o_tep + fp * 8, P + d.o_tw + wi, bcsim, d.codec);
+          const BcTex b = sim_texel(P + d.o_tep + fp * 8, P + d.o_tw + wi, bcsim, direct, d.codec);
           const float wt = ws * tw[i];
           fps[i] = fp;
 #pragma unroll
@@ -542,7 +455,7 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const bool own = i == 0 || (i == 1 && !fsx) || (i == 2 && !fsy) || (i == 3 && !fsx && !fsy);
-          if (!own) continue;
+          if (!own || direct) continue;   // a directly optimised map has no endpoints
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
             if (accum) atomicAdd(acc + fps[i] * 8 + k, e[i][k]);   // LDS (ds_add) or HBM: separate paths
@@ -552,8 +465,10 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
       }
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        atomicAdd(G + fpu * 8 + 2 * c, dx[4 + c] * bu.d1[c]);
-        atomicAdd(G + fpu * 8 + 2 * c + 1, dx[4 + c] * bu.d2[c]);
+        if (!direct) {
+          atomicAdd(G + fpu * 8 + 2 * c, dx[4 + c] * bu.d1[c]);
+          atomicAdd(G + fpu * 8 + 2 * c + 1, dx[4 + c] * bu.d2[c]);
+        }
         if (!d.codec) atomicAdd(G + d.o_uvw + ((int64_t)y * d.W + x) * 4 + c, dx[4 + c] * bu.dw[c]);
       }
       if (d.codec)
@@ -670,6 +585,24 @@ __global__ __launch_bounds__(256) void k_quant8(const float* __restrict__ src, u
     dst[i] = (uint8_t)min(max((int)rintf(__fmul_rn(255.0f, src[i])), 0), 255);
 }
 
+// Import helpers: block endpoints (e1, e2) = (0, 1), so that the Eq. 7 lerp reads the weight
+// itself; 8-bit planes as byte / 255; a decoder of either dtype as float.
+__global__ __launch_bounds__(256) void k_fill_ep01(float* __restrict__ ep, int64_t pairs) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < pairs; i += (int64_t)gridDim.x * blockDim.x)
+    *(float2*)(ep + 2 * i) = make_float2(0.0f, 1.0f);
+}
+
+__global__ __launch_bounds__(256) void k_unit8(const uint8_t* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i] / 255.0f;
+}
+
+__global__ __launch_bounds__(256) void k_to_f32(const void* __restrict__ src, int dt, float* __restrict__ dst,
+                                                 int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = dt == NDGI_DTYPE_F16 ? (float)((const _Float16*)src)[i] : ((const float*)src)[i];
+}
+
 // Target preprocessing (Sec. 4): y^(1/gamma) per texel and channel; per frame and channel the
 // FP64 sum, then division by the mean.  One workgroup per (frame, 64K-texel chunk).
 constexpr int kNormChunk = 65536;
@@ -742,6 +675,9 @@ static int check_htrain(const ndgi_hybrid_train_state* st, const char* who) {
   if (st->W > 4096 || st->H > 4096) return fail(NDGI_ERR_INVALID_ARG, "%s: W, H above 4096", who);
   if (st->frames < 1 || st->frames > 256) return fail(NDGI_ERR_INVALID_ARG, "%s: frames=%d not in 1..256", who, st->frames);
   if (st->n_models < 1) return fail(NDGI_ERR_INVALID_ARG, "%s: n_models=%d < 1", who, st->n_models);
+  if (st->n_models > 1 && ((int64_t)st->Tt * (st->U + st->V)) % 2)
+    return fail(NDGI_ERR_INVALID_ARG, "%s: with several models Tt * (U + V) must be even (16-byte aligned model blocks)",
+                who);
   if (st->reserved0) return fail(NDGI_ERR_INVALID_ARG, "%s: reserved0 must be 0", who);
   return NDGI_OK;
 }
@@ -781,8 +717,12 @@ int ndgi_hybrid_train_step(ndgi_ctx* c, ndgi_hybrid_train_state* st, const ndgi_
   if (mode != NDGI_TRAIN_FORWARD && mode != NDGI_TRAIN_LOSS_GRAD && mode != NDGI_TRAIN_FUSED &&
       mode != NDGI_TRAIN_ADAM && mode != NDGI_TRAIN_ZERO_GRAD)
     return fail(NDGI_ERR_INVALID_ARG, "hybrid_train_step: unsupported mode %d", mode);
-  if (flags & ~(NDGI_HTRAIN_BCSIM | NDGI_HTRAIN_NOISE | NDGI_HTRAIN_QPLANES))
+  if (flags & ~(NDGI_HTRAIN_BCSIM | NDGI_HTRAIN_NOISE | NDGI_HTRAIN_QPLANES | NDGI_HTRAIN_DIRECT))
     return fail(NDGI_ERR_INVALID_ARG, "hybrid_train_step: unknown flags 0x%x", flags);
+  if ((flags & NDGI_HTRAIN_DIRECT) && ((flags & NDGI_HTRAIN_BCSIM) || st->codec != NDGI_CODEC_BC4))
+    return fail(NDGI_ERR_INVALID_ARG,
+                "hybrid_train_step: DIRECT needs a state in the BC4 layout (one value per texel and channel) and "
+                "excludes BCSIM");
   const HybTrainDims d = htd_of(st);
   const int64_t total = (int64_t)d.M * d.n;
   if (mode == NDGI_TRAIN_ZERO_GRAD) return launch_fill_zero(c, st->grads, total, s);
@@ -803,7 +743,10 @@ int ndgi_hybrid_train_step(ndgi_ctx* c, ndgi_hybrid_train_state* st, const ndgi_
     HybTrainDims dl = d;
     if (dl.M == 1) dl.Bm = (int)b->n;
     const uint64_t base = (uint64_t)st->seed * 0x9E3779B97F4A7C15ull + ((uint64_t)st->step << 32);
-    const float inv3n = (float)(1.0 / (3.0 * (double)b->n));
+    // each model's loss is the mean over its own samples; the launch reports the mean of the
+    // models' losses
+    const float inv3n = (float)(1.0 / (3.0 * (double)dl.Bm));
+    const double loss_w = 1.0 / (3.0 * (double)dl.Bm * (double)dl.M);
     // workgroup size: one wave for small batches (spread over the CUs), else 4 waves (2 or 1
     // when a model's sample count is not a multiple of 256); chunks of k workgroup rounds,
     // k up to 16 while the grid keeps about one chunk per CU
@@ -830,7 +773,7 @@ int ndgi_hybrid_train_step(ndgi_ctx* c, ndgi_hybrid_train_state* st, const ndgi_
     if (mode != NDGI_TRAIN_FORWARD) hipLaunchKernelGGL(k_zero_d, dim3(1), dim3(64), 0, s, loss_dev, 1);
 #define NDGI_HT(HD, M)                                                                                          \
   hipLaunchKernelGGL((k_hybrid_train<HD, M>), dim3((unsigned)wgs), dim3(nthr), dyn_bytes, s, dl, st->params,      \
-                     st->grads, st->keys, b->samples, b->n, b->target, b->pred, flags, base, inv3n, loss_dev, chunk, \
+                     st->grads, st->keys, b->samples, b->n, b->target, b->pred, flags, base, inv3n, loss_w, loss_dev, chunk, \
                      accum)
     if (mode == NDGI_TRAIN_FORWARD) {
       if (d.hidden == 16) NDGI_HT(16, NDGI_TRAIN_FORWARD);
@@ -887,6 +830,95 @@ int ndgi_hybrid_export(ndgi_ctx* c, const ndgi_hybrid_train_state* st, int32_t m
                      (int64_t)d.Tt * d.V * 2);
   NDGI_HIP(hipGetLastError());
   return launch_convert(c, mlp, mlp_out, mlp_dtype, d.n - d.o_mlp, s);
+}
+
+int ndgi_hybrid_encode(ndgi_ctx* c, const ndgi_hybrid_train_state* st, int32_t model, int32_t flags, int32_t codec,
+                       uint8_t* fuv_out, uint8_t* fuvt_out, uint8_t* fut_out, uint8_t* fvt_out, void* mlp_out,
+                       int32_t mlp_dtype, hipStream_t s) {
+  clear_error();
+  if (!c) return fail(NDGI_ERR_INVALID_ARG, "hybrid_encode: ctx is NULL");
+  int rc = check_htrain(st, "hybrid_encode");
+  if (rc) return rc;
+  if (flags & ~(NDGI_HTRAIN_BCSIM | NDGI_HTRAIN_NOISE | NDGI_HTRAIN_QPLANES | NDGI_HTRAIN_DIRECT))
+    return fail(NDGI_ERR_INVALID_ARG, "hybrid_encode: unknown flags 0x%x", flags);
+  const bool direct = flags & NDGI_HTRAIN_DIRECT, rounded = flags & NDGI_HTRAIN_BCSIM;
+  if (direct && (rounded || st->codec != NDGI_CODEC_BC4))
+    return fail(NDGI_ERR_INVALID_ARG, "hybrid_encode: DIRECT needs a BC4-layout state and excludes BCSIM");
+  if (codec != NDGI_CODEC_BC4 && codec != NDGI_CODEC_BC7)
+    return fail(NDGI_ERR_INVALID_ARG, "hybrid_encode: codec %d", codec);
+  if (mlp_out && mlp_dtype != NDGI_DTYPE_F32 && mlp_dtype != NDGI_DTYPE_F16)
+    return fail(NDGI_ERR_INVALID_ARG, "hybrid_encode: bad dtype");
+  const uintptr_t al = codec == NDGI_CODEC_BC7 ? 15u : 7u;
+  if (((uintptr_t)fuv_out & al) || ((uintptr_t)fuvt_out & al))
+    return fail(NDGI_ERR_INVALID_ARG, "hybrid_encode: block outputs must be aligned to a block");
+  const HybTrainDims d = htd_of(st);
+  if (model < 0 || model >= d.M) return fail(NDGI_ERR_INVALID_ARG, "hybrid_encode: model %d of %d", model, d.M);
+  const float* P = st->params + (int64_t)model * d.o_mlp;
+  const float* mlp = st->params + (int64_t)d.M * d.o_mlp + (int64_t)model * (d.n - d.o_mlp);
+  TexSrc S = {};
+  S.codec = d.codec;
+  S.kind = direct ? kSrcDirect : (rounded ? kSrcRounded : kSrcLerp);
+  const int per_fp = codec == NDGI_CODEC_BC7 ? 1 : 4;   // blocks per footprint
+  if (fuv_out) {
+    S.ep = P;
+    S.w = P + d.o_uvw;
+    S.W = d.W;
+    S.H = d.H;
+    rc = launch_encode(S, codec, (int64_t)(d.H / 4) * (d.W / 4) * per_fp, fuv_out, c->n_cu, s);
+    if (rc) return rc;
+  }
+  if (fuvt_out) {
+    S.ep = P + d.o_tep;
+    S.w = P + d.o_tw;
+    S.W = d.Gu;
+    S.H = d.Gv;
+    rc = launch_encode(S, codec, (int64_t)d.S * (d.Gv / 4) * (d.Gu / 4) * per_fp, fuvt_out, c->n_cu, s);
+    if (rc) return rc;
+  }
+  if (fut_out)
+    hipLaunchKernelGGL(k_quant8, dim3(grid_of((int64_t)d.Tt * d.U * 2, 1024)), dim3(256), 0, s, P + d.o_ut, fut_out,
+                       (int64_t)d.Tt * d.U * 2);
+  if (fvt_out)
+    hipLaunchKernelGGL(k_quant8, dim3(grid_of((int64_t)d.Tt * d.V * 2, 1024)), dim3(256), 0, s, P + d.o_vt, fvt_out,
+                       (int64_t)d.Tt * d.V * 2);
+  NDGI_HIP(hipGetLastError());
+  if (mlp_out) return launch_convert(c, mlp, mlp_out, mlp_dtype, d.n - d.o_mlp, s);
+  return NDGI_OK;
+}
+
+int ndgi_hybrid_import(ndgi_ctx* c, const ndgi_hybrid_model* m, ndgi_hybrid_train_state* st, int32_t model,
+                       hipStream_t s) {
+  clear_error();
+  if (!c) return fail(NDGI_ERR_INVALID_ARG, "hybrid_import: ctx is NULL");
+  int rc = check_htrain(st, "hybrid_import");
+  if (rc) return rc;
+  rc = check_hybrid(m, "hybrid_import");
+  if (rc) return rc;
+  if (st->codec != NDGI_CODEC_BC4)
+    return fail(NDGI_ERR_INVALID_ARG, "hybrid_import: the state must have the BC4 layout (a value per texel and "
+                                      "channel)");
+  if (m->W != st->W || m->H != st->H || m->Gu != st->Gu || m->Gv != st->Gv || m->S != st->S || m->U != st->U ||
+      m->V != st->V || m->Tt != st->Tt || m->hidden != st->hidden)
+    return fail(NDGI_ERR_INVALID_ARG, "hybrid_import: model and state sizes differ");
+  const HybTrainDims d = htd_of(st);
+  if (model < 0 || model >= d.M) return fail(NDGI_ERR_INVALID_ARG, "hybrid_import: model %d of %d", model, d.M);
+  float* P = st->params + (int64_t)model * d.o_mlp;
+  float* mlp = st->params + (int64_t)d.M * d.o_mlp + (int64_t)model * (d.n - d.o_mlp);
+  const int64_t ep_uv = d.o_uvw / 2, ep_uvt = (d.o_tw - d.o_tep) / 2;
+  hipLaunchKernelGGL(k_fill_ep01, dim3(grid_of(ep_uv, c->n_cu * 16)), dim3(256), 0, s, P, ep_uv);
+  hipLaunchKernelGGL(k_fill_ep01, dim3(grid_of(ep_uvt, c->n_cu * 16)), dim3(256), 0, s, P + d.o_tep, ep_uvt);
+  rc = launch_import_map(m->fuv, m->codec, d.W, d.H, 1, P + d.o_uvw, c->n_cu, s);
+  if (rc) return rc;
+  rc = launch_import_map(m->fuvt, m->codec, d.Gu, d.Gv, d.S, P + d.o_tw, c->n_cu, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_unit8, dim3(grid_of((int64_t)d.Tt * d.U * 2, 1024)), dim3(256), 0, s, m->fut, P + d.o_ut,
+                     (int64_t)d.Tt * d.U * 2);
+  hipLaunchKernelGGL(k_unit8, dim3(grid_of((int64_t)d.Tt * d.V * 2, 1024)), dim3(256), 0, s, m->fvt, P + d.o_vt,
+                     (int64_t)d.Tt * d.V * 2);
+  hipLaunchKernelGGL(k_to_f32, dim3(grid_of(d.n - d.o_mlp, 64)), dim3(256), 0, s, m->mlp, m->mlp_dtype, mlp,
+                     d.n - d.o_mlp);
+  NDGI_HIP(hipGetLastError());
+  return NDGI_OK;
 }
 
 int ndgi_hybrid_normalize_target(ndgi_ctx* c, const uint16_t* target, int32_t frames, int32_t W, int32_t H,

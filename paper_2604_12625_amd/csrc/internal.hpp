@@ -52,14 +52,29 @@ struct ndgi_ctx {
 };
 
 namespace ndgi {
+// Where the block encoders read 8-bit texels: texels in memory (u8 != NULL: [blocks][16][C],
+// texel s = 4 row + col), or a block-parameterised map of a hybrid training state
+// (endpoints [..][H/4][W/4][4][2], weights [..][H][W][4] or, codec 1, [..][H][W]) reconstructed
+// as kind (kSrcLerp, kSrcRounded, kSrcDirect) says; a footprint of the map is one block of 4
+// channels.
+struct TexSrc {
+  const uint8_t* u8;
+  int C;
+  const float* ep;
+  const float* w;
+  int W, H, codec, kind;
+};
+// n blocks (BC7: footprints; BC4: footprint * 4 + channel for a map source) into out.
+int launch_encode(const TexSrc& S, int codec, int64_t n, uint8_t* out, int n_cu, hipStream_t s);
 int check_model(const ndgi_model* m, const char* who);
 int launch_decode(ndgi_ctx* ctx, const ndgi_model& m, const float* uvt, int64_t n, void* out, int prec,
                   hipStream_t s);
 int launch_pages(ndgi_ctx* ctx, const ndgi_model* models, int32_t n_models, const ndgi_page_req* reqs,
                  const int32_t* n_reqs, int32_t max_reqs, int32_t page, void* dst, int64_t pitch, int prec,
                  hipStream_t s);
-int launch_bc4_blocks(const uint8_t* blocks, int64_t n, uint8_t* out, hipStream_t s);
+int launch_bc4_blocks(const uint8_t* blocks, int64_t n, uint8_t* out, int impl, hipStream_t s);
 int launch_bc7_blocks(const uint8_t* blocks, int64_t n, uint8_t* out, hipStream_t s);
+int launch_import_map(const uint8_t* blocks, int codec, int W, int H, int S, float* w, int n_cu, hipStream_t s);
 int binned_workspace(const ndgi_model& m, int64_t n, int64_t* bytes);
 int launch_decode_binned(ndgi_ctx* ctx, const ndgi_model& m, const float* uvt, int64_t n, void* out, int prec,
                          void* ws, int64_t ws_bytes, hipStream_t s);

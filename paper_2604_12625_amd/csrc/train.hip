@@ -526,6 +526,58 @@ __global__ __launch_bounds__(256) void k_tile_stats(const void* __restrict__ pre
   }
 }
 
+// Tiled PSNR from per-tile statistics [n maps][ny][nx][3] (max, min, squared error), FP64,
+// one workgroup: per tile 10 log10(range^2 / MSE) over its texels and channels (range 0:
+// skipped, NaN in tile_db; MSE 0: 100 dB); summary = [mean over scored tiles, global PSNR
+// over every texel with the range of all tiles, least tile PSNR, scored tiles, tiles].
+__global__ __launch_bounds__(256) void k_psnr(const double* __restrict__ stats, int64_t ntiles, int ny, int nx,
+                                               int W, int H, int tile, double* __restrict__ tile_db,
+                                               double* __restrict__ summary) {
+  double sdb = 0.0, sse = 0.0, cnt = 0.0, nsc = 0.0, gmx = -INFINITY, gmn = INFINITY, dmin = INFINITY;
+  for (int64_t i = threadIdx.x; i < ntiles; i += blockDim.x) {
+    const int64_t r = i % ((int64_t)ny * nx);
+    const int ty = (int)(r / nx), tx = (int)(r % nx);
+    const double c = (double)min(tile, H - tile * ty) * (double)min(tile, W - tile * tx) * 3.0;
+    const double mx = stats[3 * i], mn = stats[3 * i + 1], e = stats[3 * i + 2];
+    sse += e;
+    cnt += c;
+    gmx = fmax(gmx, mx);
+    gmn = fmin(gmn, mn);
+    const double rng = mx - mn;
+    double db = NAN;
+    if (rng > 0.0) {
+      db = e == 0.0 ? 100.0 : 10.0 * log10(rng * rng / (e / c));
+      sdb += db;
+      nsc += 1.0;
+      dmin = fmin(dmin, db);
+    }
+    if (tile_db) tile_db[i] = db;
+  }
+  __shared__ double red[7][256];
+  const double v[7] = {sdb, sse, cnt, nsc, gmx, gmn, dmin};
+#pragma unroll
+  for (int k = 0; k < 7; ++k) red[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + st];
+      red[4][threadIdx.x] = fmax(red[4][threadIdx.x], red[4][threadIdx.x + st]);
+      red[5][threadIdx.x] = fmin(red[5][threadIdx.x], red[5][threadIdx.x + st]);
+      red[6][threadIdx.x] = fmin(red[6][threadIdx.x], red[6][threadIdx.x + st]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double g = red[4][0] - red[5][0];
+    summary[0] = red[3][0] > 0.0 ? red[0][0] / red[3][0] : NAN;
+    summary[1] = red[1][0] == 0.0 ? 100.0 : 10.0 * log10(g * g / (red[1][0] / red[2][0]));
+    summary[2] = red[3][0] > 0.0 ? red[6][0] : NAN;
+    summary[3] = red[3][0];
+    summary[4] = (double)ntiles;
+  }
+}
+
 }  // namespace ndgi
 
 using namespace ndgi;
@@ -690,6 +742,19 @@ int ndgi_export(ndgi_ctx* c, const ndgi_train_state* st, uint8_t* bc4_out, void*
                      grid_dtype, ng);
   hipLaunchKernelGGL(k_convert, dim3(grid_for(NDGI_MLP_SIZE, 64)), dim3(256), 0, s, st->params + d.off_mlp, mlp_out,
                      mlp_dtype, (int64_t)NDGI_MLP_SIZE);
+  NDGI_HIP(hipGetLastError());
+  return NDGI_OK;
+}
+
+int ndgi_psnr(ndgi_ctx* c, const double* stats, int32_t n_maps, int32_t W, int32_t H, int32_t tile, double* tile_db,
+              double* summary, hipStream_t s) {
+  clear_error();
+  if (!c || !stats || !summary) return fail(NDGI_ERR_INVALID_ARG, "psnr: NULL argument");
+  if (n_maps < 1 || W < 1 || H < 1 || tile < 1 || tile > 4096)
+    return fail(NDGI_ERR_INVALID_ARG, "psnr: bad sizes (n_maps %d, W %d, H %d, tile %d)", n_maps, W, H, tile);
+  const int ny = (H + tile - 1) / tile, nx = (W + tile - 1) / tile;
+  hipLaunchKernelGGL(k_psnr, dim3(1), dim3(256), 0, s, stats, (int64_t)n_maps * ny * nx, ny, nx, W, H, tile, tile_db,
+                     summary);
   NDGI_HIP(hipGetLastError());
   return NDGI_OK;
 }

@@ -97,11 +97,16 @@ def run_c5(args, torch, N, I, ctx, steps: int | None = None, batch: int = BATCH)
         e1.synchronize()
         ms = e0.elapsed_time(e1)
         assert ctx.error_flags() == 0
-        stats = [ctx.tile_stats(dst[k * W * H:(k + 1) * W * H], tgt_bits[k], W, H, TILE).cpu().numpy()
-                 for k in range(T)]
-        tiled, glob = N.psnr_from_stats(stats, W, H, TILE)
+        stats = torch.stack([ctx.tile_stats(dst[k * W * H:(k + 1) * W * H], tgt_bits[k], W, H, TILE)
+                             for k in range(T)])
+        ps = ctx.psnr(stats, W, H, TILE)
+        tiled, glob = ps["tiled"], ps["global"]
+        db = ps["tile_db"].cpu().numpy().ravel()
+        db = db[~np.isnan(db)]
         res[name] = dict(decode_ms_all_keys=ms, decode_texels_per_s=T * W * H / (ms * 1e-3),
-                         psnr_tiled_db=tiled, psnr_global_db=glob)
+                         psnr_tiled_db=tiled, psnr_global_db=glob, psnr_tile_min_db=ps["min"],
+                         psnr_tile_quantiles_db={q: float(np.quantile(db, q)) for q in (0.01, 0.1, 0.5, 0.9)},
+                         tiles_scored=ps["scored"], tiles=ps["tiles"])
         _log(f"C5 decode {name}: {ms:.2f} ms for {T} keys ({T * W * H / ms / 1e6:.1f} G texels/s), "
              f"PSNR tiled {tiled:.2f} dB, global {glob:.2f} dB")
         del dst

@@ -29,7 +29,7 @@ EXPORTED = (
     "ndgi_hybrid_decode_pages_graph", "ndgi_hybrid_train_param_count", "ndgi_hybrid_train_step",
     "ndgi_hybrid_export", "ndgi_hybrid_normalize_target", "ndgi_hybrid_restore",
 )
-HTRAIN_BCSIM, HTRAIN_NOISE, HTRAIN_QPLANES = 1, 2, 4
+HTRAIN_BCSIM, HTRAIN_NOISE, HTRAIN_QPLANES, HTRAIN_DIRECT = 1, 2, 4, 8
 CODEC_BC4, CODEC_BC7 = 0, 1
 
 
@@ -109,6 +109,9 @@ def lib():
         L.ndgi_get_error_flags.argtypes = [vp, vp, C.POINTER(C.c_uint32)]
         L.ndgi_bc4_decode_blocks.argtypes = [vp, i64, vp, vp]
         L.ndgi_bc7_decode_blocks.argtypes = [vp, i64, vp, vp]
+        L.ndgi_bc4_decode_blocks_impl.argtypes = [vp, i64, vp, i32, vp]
+        L.ndgi_bc4_encode_blocks.argtypes = [vp, i64, vp, vp]
+        L.ndgi_bc7_encode_blocks.argtypes = [vp, i64, vp, vp]
         L.ndgi_decode.argtypes = [vp, C.POINTER(NdgiModel), vp, i64, vp, i32, vp]
         pages = [vp, vp, i32, vp, vp, i32, i32, vp, i64, i32, vp]
         L.ndgi_decode_pages.argtypes = pages
@@ -119,6 +122,7 @@ def lib():
         L.ndgi_train_step.argtypes = [vp, C.POINTER(NdgiTrainState), C.POINTER(NdgiBatch), i32, vp, vp]
         L.ndgi_export.argtypes = [vp, C.POINTER(NdgiTrainState), vp, vp, i32, vp, i32, vp]
         L.ndgi_tile_stats.argtypes = [vp, vp, i32, vp, i32, i32, i32, vp, vp]
+        L.ndgi_psnr.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, vp]
         L.ndgi_decode_binned_workspace.argtypes = [C.POINTER(NdgiModel), i64, C.POINTER(i64)]
         L.ndgi_decode_binned.argtypes = [vp, C.POINTER(NdgiModel), vp, i64, vp, i32, vp, i64, vp]
         L.ndgi_hybrid_mlp_size.argtypes = [i32]
@@ -132,6 +136,9 @@ def lib():
         L.ndgi_hybrid_train_step.argtypes = [vp, C.POINTER(NdgiHybridTrainState), C.POINTER(NdgiHybridBatch), i32,
                                              i32, vp, vp]
         L.ndgi_hybrid_export.argtypes = [vp, C.POINTER(NdgiHybridTrainState), i32, vp, vp, vp, vp, vp, i32, vp]
+        L.ndgi_hybrid_encode.argtypes = [vp, C.POINTER(NdgiHybridTrainState), i32, i32, i32, vp, vp, vp, vp, vp, i32,
+                                         vp]
+        L.ndgi_hybrid_import.argtypes = [vp, C.POINTER(NdgiHybridModel), C.POINTER(NdgiHybridTrainState), i32, vp]
         L.ndgi_hybrid_normalize_target.argtypes = [vp, vp, i32, i32, i32, C.c_float, vp, vp, vp]
         L.ndgi_hybrid_restore.argtypes = [vp, vp, i32, i64, vp, C.c_float, vp, vp]
         _lib = L
@@ -303,20 +310,41 @@ class Context:
                                     _stream(stream)), "ndgi_tile_stats")
         return out
 
+    def psnr(self, stats, W, H, tile=128, stream=None) -> dict:
+        """Tiled PSNR (ndgi_psnr) of stacked per-map tile statistics [n][ny][nx][3] (device
+        FP64): dict(tiled, global, min, p10, scored, tiles, tile_db) with the per-tile dB on the
+        device (NaN for skipped tiles)."""
+        import torch
+        stats = stats.contiguous()
+        n = stats.shape[0] if stats.dim() == 4 else 1
+        tile_db = torch.empty(stats.shape[:-1], dtype=torch.float64, device=stats.device)
+        summ = torch.empty(5, dtype=torch.float64, device=stats.device)
+        check(lib().ndgi_psnr(self.h, _ptr(stats), n, W, H, tile, _ptr(tile_db), _ptr(summ), _stream(stream)),
+              "ndgi_psnr")
+        v = summ.cpu().tolist()
+        scored = tile_db[~torch.isnan(tile_db)]
+        p10 = float(torch.quantile(scored, 0.1).item()) if scored.numel() else float("nan")
+        return dict(tiled=v[0], **{"global": v[1]}, min=v[2], p10=p10, scored=int(v[3]), tiles=int(v[4]),
+                    tile_db=tile_db)
+
     def error_flags(self, stream=None) -> int:
         f = C.c_uint32(0)
         check(lib().ndgi_get_error_flags(self.h, _stream(stream), C.byref(f)), "ndgi_get_error_flags")
         return f.value
 
 
-def bc4_decode_blocks(blocks, out=None, stream=None):
-    """Decode [n][8] uint8 device blocks to [n][16] uint8."""
+def bc4_decode_blocks(blocks, out=None, stream=None, impl=None):
+    """Decode [n][8] uint8 device blocks to [n][16] uint8 (impl: one of the kernels' texel
+    decoders, ndgi_bc4_decode_blocks_impl)."""
     import torch
     n = blocks.shape[0]
     if out is None:
         out = torch.empty((n, 16), dtype=torch.uint8, device=blocks.device)
-    check(lib().ndgi_bc4_decode_blocks(_ptr(blocks), n, _ptr(out), _stream(stream)),
-          "ndgi_bc4_decode_blocks")
+    if impl is None:
+        check(lib().ndgi_bc4_decode_blocks(_ptr(blocks), n, _ptr(out), _stream(stream)), "ndgi_bc4_decode_blocks")
+    else:
+        check(lib().ndgi_bc4_decode_blocks_impl(_ptr(blocks), n, _ptr(out), int(impl), _stream(stream)),
+              "ndgi_bc4_decode_blocks_impl")
     return out
 
 
@@ -327,6 +355,26 @@ def bc7_decode_blocks(blocks, out=None, stream=None):
     if out is None:
         out = torch.empty((n, 16, 4), dtype=torch.uint8, device=blocks.device)
     check(lib().ndgi_bc7_decode_blocks(_ptr(blocks), n, _ptr(out), _stream(stream)), "ndgi_bc7_decode_blocks")
+    return out
+
+
+def bc4_encode_blocks(texels, out=None, stream=None):
+    """Encode [n][16] uint8 device texels as [n][8] BC4 blocks (the exhaustive optimum)."""
+    import torch
+    n = texels.shape[0]
+    if out is None:
+        out = torch.empty((n, 8), dtype=torch.uint8, device=texels.device)
+    check(lib().ndgi_bc4_encode_blocks(_ptr(texels), n, _ptr(out), _stream(stream)), "ndgi_bc4_encode_blocks")
+    return out
+
+
+def bc7_encode_blocks(texels, out=None, stream=None):
+    """Encode [n][16][4] uint8 device texels as [n][16] BC7 mode-6 blocks."""
+    import torch
+    n = texels.shape[0]
+    if out is None:
+        out = torch.empty((n, 16), dtype=torch.uint8, device=texels.device)
+    check(lib().ndgi_bc7_encode_blocks(_ptr(texels), n, _ptr(out), _stream(stream)), "ndgi_bc7_encode_blocks")
     return out
 
 
@@ -347,30 +395,3 @@ def page_requests(model, px, py, t, dst_offset, device="cuda"):
                                        ("t", "<f4"), ("off", "<i8")]))
     rec["model"], rec["px"], rec["py"], rec["t"], rec["off"] = model, px, py, t, dst_offset
     return torch.from_numpy(rec.view(np.uint8).copy()).to(device)
-
-
-def psnr_from_stats(stats, W, H, tile=128):
-    """Mean tiled PSNR and global PSNR from per-map tile statistics (host arithmetic on the
-    FP64 sums): PSNR = 10 log10(range^2 / MSE) per tile, tiles of zero range skipped,
-    MSE = 0 scored 100 dB."""
-    import math
-    scores = []
-    sse = 0.0
-    cnt_all = 0
-    gmax, gmin = -math.inf, math.inf
-    for s in stats:
-        ny, nx = s.shape[0], s.shape[1]
-        for ty in range(ny):
-            for tx in range(nx):
-                mx, mn, e = (float(v) for v in s[ty, tx])
-                c = min(tile, H - tile * ty) * min(tile, W - tile * tx) * 3
-                sse += e
-                cnt_all += c
-                gmax, gmin = max(gmax, mx), min(gmin, mn)
-                rng = mx - mn
-                if rng <= 0:
-                    continue
-                scores.append(100.0 if e == 0 else 10.0 * math.log10(rng * rng / (e / c)))
-    tiled = sum(scores) / len(scores) if scores else float("nan")
-    glob = 100.0 if sse == 0 else 10.0 * math.log10((gmax - gmin) ** 2 / (sse / cnt_all))
-    return tiled, glob

@@ -235,6 +235,49 @@ class HybridTrainer:
         return N.HybridModel(d["W"], d["H"], d["Gu"], d["Gv"], d["S"], d["U"], d["V"], d["Tt"], d["hidden"],
                              fuv, fuvt, fut, fvt, keys, mlp, self.codec)
 
+    def encode(self, flags, codec, mlp_dtype=N.DTYPE_F16, model=0, maps=True) -> N.HybridModel:
+        """The paper's export (ndgi_hybrid_encode): maps reconstructed as a step with `flags`
+        reads them, quantised to 8 bits and block-encoded in `codec`; planes to 8 bits; the
+        decoder in mlp_dtype.  maps=False skips the map encoding (the maps are then left
+        uninitialised: for taking only a fine-tuned decoder and planes)."""
+        import torch
+        d, dev = self.d, self.params.device
+        blk = (16,) if codec == N.CODEC_BC7 else (4, 8)
+        fuv = torch.empty((d["H"] // 4, d["W"] // 4) + blk, dtype=torch.uint8, device=dev)
+        fuvt = torch.empty((d["S"], d["Gv"] // 4, d["Gu"] // 4) + blk, dtype=torch.uint8, device=dev)
+        fut = torch.empty((d["Tt"], d["U"], 2), dtype=torch.uint8, device=dev)
+        fvt = torch.empty((d["Tt"], d["V"], 2), dtype=torch.uint8, device=dev)
+        mlp = torch.empty(N.hybrid_mlp_size(d["hidden"]), dtype=torch.float16 if mlp_dtype == N.DTYPE_F16
+                          else torch.float32, device=dev)
+        N.check(N.lib().ndgi_hybrid_encode(self.ctx.h, C.byref(self.state), model, flags, codec,
+                                           fuv.data_ptr() if maps else None, fuvt.data_ptr() if maps else None,
+                                           fut.data_ptr(), fvt.data_ptr(), mlp.data_ptr(), mlp_dtype,
+                                           N._stream(None)), "ndgi_hybrid_encode")
+        keys = self.keys if self.keys is not None else torch.zeros(0, dtype=torch.float32, device=dev)
+        return N.HybridModel(d["W"], d["H"], d["Gu"], d["Gv"], d["S"], d["U"], d["V"], d["Tt"], d["hidden"],
+                             fuv, fuvt, fut, fvt, keys, mlp, codec)
+
+
+def hybrid_import_models(ctx: N.Context, models, frames: int, lr_mlp=1e-3, seed=0, per_model=0, keys=None,
+                         device="cuda") -> "HybridTrainer":
+    """A directly parameterised state (BC4 layout, flag DIRECT) holding block-compressed
+    models (ndgi_hybrid_import): for the final stage that fine-tunes the decoders on frozen
+    features exactly as a decode of the models reads them (lr_feat = 0)."""
+    m0 = models[0]
+    d = m0.desc
+    dims = dict(W=d.W, H=d.H, Gu=d.Gu, Gv=d.Gv, S=d.S, U=d.U, V=d.V, Tt=d.Tt, hidden=d.hidden, frames=int(frames),
+                keys=np.zeros(0, np.float32) if keys is None else np.asarray(keys, np.float32), codec=N.CODEC_BC4)
+    z = lambda *sh: np.zeros(sh, np.float32)
+    init = dict(dims=dims, fuv_ep=z(d.H // 4, d.W // 4, 4, 2), fuv_w=z(d.H, d.W, 4),
+                fuvt_ep=z(d.S, d.Gv // 4, d.Gu // 4, 4, 2), fuvt_w=z(d.S, d.Gv, d.Gu, 4), fut=z(d.Tt, d.U, 2),
+                fvt=z(d.Tt, d.V, 2), mlp=z(N.hybrid_mlp_size(d.hidden)))
+    tr = HybridTrainer(ctx, [init] * len(models), lr_feat=0.0, lr_mlp=lr_mlp, seed=seed, per_model=per_model,
+                       device=device)
+    for i, m in enumerate(models):
+        N.check(N.lib().ndgi_hybrid_import(ctx.h, C.byref(m.desc), C.byref(tr.state), i, N._stream(None)),
+                "ndgi_hybrid_import")
+    return tr
+
 
 def hybrid_normalize_target(ctx: N.Context, target_bits, gamma=2.2):
     """(normalised float target [n][H][W][3], means [n][3] float64) of an FP16 target."""

@@ -53,6 +53,26 @@ def test_bc4_blocks_bit_exact(N):
     assert N.bc4_decode_blocks(empty).shape == (0, 16)
 
 
+@pytest.mark.parametrize("impl", [0, 1, 2])
+def test_kernel_bc4_decoders_exhaustive(N, impl):
+    """Every (e0, e1) pair with every selector at every texel position (8 blocks per pair,
+    selector (s + k) mod 8 at texel s), through each texel decoder the kernels use, equals
+    the oracle's palette byte for byte."""
+    import torch
+    e = np.arange(65536)
+    blocks = np.zeros((65536, 8, 8), dtype=np.uint8)
+    for k in range(8):
+        field = 0
+        for s_ in range(16):
+            field |= ((s_ + k) % 8) << (3 * s_)
+        blocks[:, k, 0] = e >> 8
+        blocks[:, k, 1] = e & 255
+        blocks[:, k, 2:] = np.frombuffer(field.to_bytes(6, "little"), np.uint8)
+    blocks = blocks.reshape(-1, 8)
+    out = N.bc4_decode_blocks(torch.from_numpy(blocks).cuda(), impl=impl).cpu().numpy()
+    np.testing.assert_array_equal(out, O.bc4_decode_blocks(blocks))
+
+
 # --------------------------------------------------------------------------- decode
 def c1_model():
     """64x64 map, grid 16x16x8(t)x8 FP32 U[-1,1], He-normal FP32 decoder (seed 0)."""
@@ -337,7 +357,9 @@ def c2_model():
 
 def test_c2_frame_and_random_sampled(N, ctx, c2_model):
     """4096^2 atlas, T = 24, FP16 storage: the full frame through the page decoder and
-    16M random queries, both at their real size, checked on sampled outputs."""
+    16M random queries, both at their real size, checked on the oracle subsample (2^20
+    frame texels at stride 16 and the first 2^20 queries: the FP16 error's tail matters at
+    this count)."""
     import torch
     m = c2_model
     dm = N.DeviceModel.from_numpy(m)
@@ -347,8 +369,9 @@ def test_c2_frame_and_random_sampled(N, ctx, c2_model):
     rq = N.page_requests(np.zeros(1024, np.int32), px.ravel().astype(np.int32), py.ravel().astype(np.int32),
                          np.full(1024, t, np.float32), (py * 128 * 4096 + px * 128).ravel().astype(np.int64))
     nreq = torch.tensor([1024], dtype=torch.int32, device="cuda")
+    # the oracle subsample: 2^20 frame texels at stride 16 and the first 2^20 random queries
     g = np.random.default_rng(21)
-    sel = g.integers(0, 4096 * 4096, 1 << 16)
+    sel = np.arange(0, 4096 * 4096, 16)
     xs, ys = sel % 4096, sel // 4096
     ref = O.decode_f64(m, (xs + 0.5) / 4096, (ys + 0.5) / 4096, np.full(sel.size, np.float64(np.float32(t))))
     for prec, tol in ((1, TOL16), (0, TOL32)):
@@ -358,7 +381,7 @@ def test_c2_frame_and_random_sampled(N, ctx, c2_model):
         assert_rel(got, ref, tol, f"frame prec {prec}")
     q = I.uniform_queries(16_000_000, I.rng(2, I.P_QUERY, 1))
     qd = torch.from_numpy(q).cuda()
-    sel = g.integers(0, q.shape[0], 1 << 16)
+    sel = np.arange(1 << 20)
     ref = O.decode(m, q[sel])
     ws = None
     for prec, tol in ((1, TOL16), (0, TOL32)):
@@ -368,3 +391,48 @@ def test_c2_frame_and_random_sampled(N, ctx, c2_model):
         binned, ws = ctx.decode_binned(dm, qd, prec, workspace=ws)
         assert torch.equal(binned.view(torch.int16 if prec else torch.int32),
                            out.view(torch.int16 if prec else torch.int32)), f"binned != direct, prec {prec}"
+
+
+def test_c3_vt_frame_at_real_size_and_autotuned_shape(N):
+    """One frame of the virtual-texturing workload at its real size: 32 maps of side
+    128 * round(2^U[1,5]) with T = 24, 2000 page requests drawn Zipf(1.1), one
+    graph-replayed persistent launch at the launch shape the autotuner picks for it on this
+    GPU (tile 2 x 16, 32 waves per CU); 64 texels of every request checked against the
+    oracle (FP16 path)."""
+    import torch
+    c = N.Context(0)
+    c.set_launch(2, 16, 32)
+    sides = I.vt_map_sides(32, I.rng(3, I.P_MODEL))
+    dms, hms = [], []
+    for i, sd in enumerate(sides):
+        sd = int(sd)
+        m = I.random_model_torch(sd, sd, sd // 4, sd // 4, 24, seed=1000 + i, device="cuda")
+        dms.append(N.DeviceModel(sd, sd, sd // 4, sd // 4, 24, m["bc4"], m["grid"], m["mlp"]))
+        hms.append(m)
+    marr = N.models_array(dms)
+    n_req, per_row, page = 2000, 50, 128
+    pitch = per_row * page
+    offs = np.array([(i // per_row) * page * pitch + (i % per_row) * page for i in range(n_req)], dtype=np.int64)
+    mi, px, py, t = I.vt_requests(sides, n_req, I.rng(3, I.P_REQ, 0))
+    rq = N.page_requests(mi, px, py, t, offs)
+    nreq = torch.tensor([n_req], dtype=torch.int32, device="cuda")
+    dst = torch.full((((n_req + per_row - 1) // per_row) * page * pitch, 3), -7.0, dtype=torch.float16,
+                     device="cuda")
+    c.decode_pages(marr, len(dms), rq, nreq, n_req, page, dst, pitch, N.PREC_F16, graph=True)
+    torch.cuda.synchronize()
+    assert c.error_flags() == 0
+    g = np.random.default_rng(33)
+    ii, jj = g.integers(0, page, (n_req, 64)), g.integers(0, page, (n_req, 64))
+    rows = offs[:, None] + jj * pitch + ii
+    got = dst[torch.from_numpy(rows.ravel()).cuda()].float().cpu().numpy().reshape(n_req, 64, 3)
+    for k in np.unique(mi):
+        sel = np.nonzero(mi == k)[0]
+        hm = hms[k]
+        m = dict(W=hm["W"], H=hm["H"], Gw=hm["Gw"], Gh=hm["Gh"], T=hm["T"], bc4=hm["bc4"].cpu().numpy(),
+                 grid=hm["grid"].cpu().numpy(), mlp=hm["mlp"].cpu().numpy())
+        x = page * px[sel, None] + ii[sel]
+        y = page * py[sel, None] + jj[sel]
+        ref = O.decode_f64(m, (x.ravel() + 0.5) / m["W"], (y.ravel() + 0.5) / m["H"],
+                           np.repeat(t[sel].astype(np.float64), 64))
+        assert_rel(got[sel].reshape(-1, 3), ref, TOL16, f"VT map {k} (side {m['W']})")
+    c.close()

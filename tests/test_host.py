@@ -17,29 +17,6 @@ def test_large_run_bits_per_texel_matches_oracle():
                         32 / 48 + 8 + 1699 * 16 / (4096 * 4096 * 48), rel_tol=1e-12)
 
 
-def test_psnr_from_stats_matches_oracle_tiled_psnr():
-    """The binding's reduction of per-tile (max, min, SSE) equals the oracle's tiled PSNR
-    computed from the full images (ragged tiles, a zero-range tile, an exact tile)."""
-    from paper_2604_12625_amd.ndgi import psnr_from_stats
-    g = np.random.default_rng(7)
-    W, H, tile = 300, 200, 128
-    tgt = g.uniform(0.1, 4.0, (H, W, 3))
-    tgt[:128, 128:256] = 1.5                       # zero-range tile: skipped
-    pred = tgt + g.normal(0, 0.05, tgt.shape)
-    pred[128:, 256:] = tgt[128:, 256:]             # exact tile: 100 dB
-    ny, nx = (H + tile - 1) // tile, (W + tile - 1) // tile
-    stats = np.zeros((ny, nx, 3))
-    for ty in range(ny):
-        for tx in range(nx):
-            t = tgt[ty * tile:(ty + 1) * tile, tx * tile:(tx + 1) * tile]
-            p = pred[ty * tile:(ty + 1) * tile, tx * tile:(tx + 1) * tile]
-            stats[ty, tx] = (t.max(), t.min(), ((p - t) ** 2).sum())
-    tiled, glob = psnr_from_stats([stats], W, H, tile)
-    o_tiled, o_glob = O.psnr_tiled(pred[None], tgt[None], tile)
-    assert math.isclose(tiled, o_tiled, rel_tol=1e-12)
-    assert math.isclose(glob, o_glob, rel_tol=1e-12)
-
-
 def test_bordered_training_samples_are_the_mirror_padded_tile():
     """Samples drawn with a border are positions of the mirror-padded tile folded back by
     mirror addressing: every texel inside the tile, and each texel drawn as often as it

@@ -76,7 +76,7 @@ def _close(got, ref, rel, what, floor=1e-6):
 
 
 @pytest.mark.parametrize("hidden", [16, 64])
-@pytest.mark.parametrize("flags", [0, 1 | 2, 1 | 4])
+@pytest.mark.parametrize("flags", [0, 2, 1 | 2, 1 | 4, 8 | 2, 8 | 4])
 @pytest.mark.parametrize("bigger", [False, True])
 def test_hybrid_loss_grad_and_forward_match_oracle(N, ctx, hidden, flags, bigger):
     from paper_2604_12625_amd.train import HybridTrainer
@@ -102,7 +102,7 @@ def test_hybrid_adam_steps_match_oracle(N, ctx):
     ref = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in st.items()}
     opt = dict(step=0, lr_feat=1e-2, lr_mlp=1e-3, m={k: 0.0 for k in O.HYB_KEYS}, v={k: 0.0 for k in O.HYB_KEYS})
     tr = HybridTrainer(ctx, st, lr_feat=1e-2, lr_mlp=1e-3, seed=5)
-    flags = 1 | 2
+    flags = O.HT_NOISE            # the paper's phase 1: continuous endpoints and weights, noise
     for it in range(3):
         x, y, f, tgt = _samples(st, 500, seed=20 + it)
         smp, tg = _dev(N, x, y, f, tgt)
@@ -113,11 +113,11 @@ def test_hybrid_adam_steps_match_oracle(N, ctx):
     got = tr.split(tr.params)
     for k in O.HYB_KEYS:
         g = got[k].cpu().numpy().astype(np.float64)
-        # after Adam an FP32 and an FP64 master can round to different 8-bit endpoints at a
-        # quantisation boundary: an lr-scaled absolute floor, as for the other layout
+        # no quantisation in these steps; Adam turns FP32 noise on a cancelling gradient sum
+        # into a fraction of lr, hence the lr-scaled absolute floor (as for the other layout)
         diff = np.abs(g - ref[k])
         tol = 1e-4 * np.abs(ref[k]) + 3e-3 * (1e-2 if k != "mlp" else 1e-3)
-        assert np.mean(diff > tol) <= 1e-3, (k, float(diff.max()))
+        assert not (diff > tol).any(), (k, int((diff > tol).sum()), float(diff.max()))
 
 
 def test_hybrid_export_is_exact_and_decodes_to_the_simulated_forward(N, ctx):
@@ -158,9 +158,8 @@ def test_target_normalisation_and_restore(N, ctx):
 
 @pytest.mark.parametrize("hidden", [16, 64])
 def test_many_models_in_one_launch(N, ctx, hidden):
-    """Three models trained together: each model's gradients are its own samples' gradients
-    of the loss averaged over the whole batch; Adam runs per element, so a fused step equals
-    three independent oracle steps with that mean."""
+    """Three models trained together: each model's gradients are those of its own loss (the
+    mean over its own samples), and the launch reports the mean of the models' losses."""
     from paper_2604_12625_amd.train import HybridTrainer
     M, Bm = 3, 128
     sts = [_state(hidden, seed=40 + i) for i in range(M)]
@@ -179,8 +178,8 @@ def test_many_models_in_one_launch(N, ctx, hidden):
     for m in range(M):
         sl = slice(m * Bm, (m + 1) * Bm)
         lm, gm = O.hybrid_train_grads(sts[m], xs[sl], ys[sl], fs[sl], tgt[m][fs[sl], ys[sl], xs[sl]], flags, seed=13,
-                                      step=0, s_offset=m * Bm, n_total=M * Bm)
-        ref_loss += lm
+                                      step=0, s_offset=m * Bm)
+        ref_loss += lm / M
         got = tr.split(tr.grads, m)
         for k in O.HYB_KEYS:
             _close(got[k].cpu().numpy(), gm[k], 1e-4, f"model {m} {k}")
@@ -193,7 +192,7 @@ def test_many_models_in_one_launch(N, ctx, hidden):
 
 # ------------------------------------------------------------------------- BC7 mode 6
 @pytest.mark.parametrize("hidden", [16, 64])
-@pytest.mark.parametrize("flags", [0, 1 | 2, 1 | 4])
+@pytest.mark.parametrize("flags", [0, 2, 1 | 2, 1 | 4])
 def test_bc7_loss_grad_and_forward_match_oracle(N, ctx, hidden, flags):
     """The BC7 simulation (one weight per texel shared by the 4 channels, Eq. 6): forward,
     loss and every gradient, including the shared weights' channel sums."""
@@ -223,14 +222,14 @@ def test_bc7_adam_steps_match_oracle(N, ctx):
     for it in range(3):
         x, y, f, tgt = _samples(st, 500, seed=64 + it)
         smp, tg = _dev(N, x, y, f, tgt)
-        loss = float(tr.step(smp, tg, 1 | 2).item())
-        ref_loss = O.hybrid_train_step(ref, opt, x, y, f, tgt[f, y, x], 1 | 2, seed=6)
+        loss = float(tr.step(smp, tg, O.HT_NOISE).item())
+        ref_loss = O.hybrid_train_step(ref, opt, x, y, f, tgt[f, y, x], O.HT_NOISE, seed=6)
         assert abs(loss - ref_loss) <= 1e-4 * abs(ref_loss), (it, loss, ref_loss)
     got = tr.split(tr.params)
     for k in O.HYB_KEYS:
         diff = np.abs(got[k].cpu().numpy().astype(np.float64) - ref[k])
         tol = 1e-4 * np.abs(ref[k]) + 3e-3 * (1e-2 if k != "mlp" else 1e-3)
-        assert np.mean(diff > tol) <= 1e-3, (k, float(diff.max()))
+        assert not (diff > tol).any(), (k, int((diff > tol).sum()), float(diff.max()))
 
 
 @pytest.mark.parametrize("on_grid", [False, True])
@@ -283,8 +282,8 @@ def test_bc7_many_models_in_one_launch(N, ctx):
     for m in range(M):
         sl = slice(m * Bm, (m + 1) * Bm)
         lm, gm = O.hybrid_train_grads(sts[m], xs[sl], ys[sl], fs[sl], tgt[m][fs[sl], ys[sl], xs[sl]], 1 | 2, seed=19,
-                                      step=0, s_offset=m * Bm, n_total=M * Bm)
-        ref_loss += lm
+                                      step=0, s_offset=m * Bm)
+        ref_loss += lm / M
         got = tr.split(tr.grads, m)
         for k in O.HYB_KEYS:
             _close(got[k].cpu().numpy(), gm[k], 1e-4, f"model {m} {k}")
@@ -309,3 +308,156 @@ def test_large_single_model_batch_matches_oracle(N, ctx, codec):
     got = tr.split(tr.grads)
     for k in O.HYB_KEYS:
         _close(got[k].cpu().numpy(), ref_g[k], 1e-4, k)
+
+
+@pytest.mark.parametrize("codec", [0, 1])
+def test_production_size_multi_model_batch_matches_oracle(N, ctx, codec):
+    """Four tile models x 4096 samples (the map workload's per-model batch): four-wave
+    workgroups over chunks of one model's samples with the F_uvt endpoint and plane
+    gradients summed in LDS, several chunks per model; the paper's phase-1 flags (noise on the
+    continuous endpoint / weight maps)."""
+    from paper_2604_12625_amd.train import HybridTrainer
+    M, Bm = 4, 4096
+    sts = [_state(16, seed=120 + i, bigger=True, codec=codec) for i in range(M)]
+    for st in sts[1:]:
+        st["dims"] = sts[0]["dims"]
+    g = np.random.default_rng(121)
+    d = sts[0]["dims"]
+    xs, ys, fs = (g.integers(0, d["W"], M * Bm), g.integers(0, d["H"], M * Bm), g.integers(0, d["frames"], M * Bm))
+    tgt = g.normal(0.5, 0.5, (M, d["frames"], d["H"], d["W"], 3)).astype(np.float32)
+    smp, tg = _dev(N, xs, ys, fs, tgt)
+    tr = HybridTrainer(ctx, sts, seed=29, per_model=Bm)
+    tr.zero_grad()
+    loss = float(tr.loss_grad(smp, tg, N.HTRAIN_NOISE).item())
+    ref_loss = 0.0
+    for m in range(M):
+        sl = slice(m * Bm, (m + 1) * Bm)
+        lm, gm = O.hybrid_train_grads(sts[m], xs[sl], ys[sl], fs[sl], tgt[m][fs[sl], ys[sl], xs[sl]], O.HT_NOISE,
+                                      seed=29, step=0, s_offset=m * Bm)
+        ref_loss += lm / M
+        got = tr.split(tr.grads, m)
+        for k in O.HYB_KEYS:
+            _close(got[k].cpu().numpy(), gm[k], 1e-4, f"model {m} {k}")
+    assert abs(loss - ref_loss) <= 1e-5 * abs(ref_loss), (loss, ref_loss)
+
+
+def test_identical_models_trained_together_equal_one_trained_alone(N, ctx):
+    """Per-model normalisation: M copies of a model with the same samples, trained together,
+    stay equal step for step to the model trained alone (Adam is not invariant to a common
+    gradient scale, so a batch-wide mean would drift)."""
+    from paper_2604_12625_amd.train import HybridTrainer
+    M, Bm = 4, 1024
+    st = _state(16, seed=130, bigger=True)
+    d = st["dims"]
+    alone = HybridTrainer(ctx, st, lr_feat=1e-2, lr_mlp=1e-3, seed=31)
+    many = HybridTrainer(ctx, [st] * M, lr_feat=1e-2, lr_mlp=1e-3, seed=31, per_model=Bm)
+    g = np.random.default_rng(131)
+    tgt = g.normal(0.5, 0.5, (d["frames"], d["H"], d["W"], 3)).astype(np.float32)
+    for it in range(3):
+        x, y, f = g.integers(0, d["W"], Bm), g.integers(0, d["H"], Bm), g.integers(0, d["frames"], Bm)
+        smp, tg = _dev(N, x, y, f, tgt)
+        smp_m, tg_m = _dev(N, np.tile(x, M), np.tile(y, M), np.tile(f, M), np.stack([tgt] * M))
+        la = float(alone.step(smp, tg, 0).item())
+        lm = float(many.step(smp_m, tg_m, 0).item())
+        assert abs(la - lm) <= 1e-6 * abs(la), (it, la, lm)
+    pa = alone.split(alone.params)
+    for m in range(M):
+        pm = many.split(many.params, m)
+        for k in O.HYB_KEYS:
+            a, b = pa[k].cpu().numpy(), pm[k].cpu().numpy()
+            # same samples, same arithmetic; only the order of float atomics differs
+            assert np.max(np.abs(a - b)) <= 1e-5 * max(float(np.max(np.abs(a))), 1e-30) + 1e-7, (m, k)
+
+
+# ------------------------------------------------------------ export path and the ablation arm
+def _blocks_bc4(seed):
+    g = np.random.default_rng(seed)
+    dec = g.integers(0, 256, (64, 8)).astype(np.uint8)
+    dec[:32, 0] = np.maximum(dec[:32, 0], dec[:32, 1] + 1)
+    dec[32:, 0] = np.minimum(dec[32:, 0], dec[32:, 1])
+    smooth = np.clip(np.round(np.linspace(g.uniform(0, 120, (48, 1)), g.uniform(130, 255, (48, 1)), 16, axis=1)[..., 0]
+                              + g.normal(0, 4, (48, 16))), 0, 255)
+    return np.concatenate([g.integers(0, 256, (48, 16)), g.integers(100, 108, (16, 16)),
+                           O.bc4_decode_blocks(dec).astype(np.int64), smooth.astype(np.int64),
+                           np.full((2, 16), 100), np.full((2, 16), 255), np.zeros((2, 16), np.int64)]).astype(np.uint8)
+
+
+def test_bc4_encoder_matches_oracle_bit_for_bit(N, ctx):
+    import torch
+    tex = _blocks_bc4(140)
+    got = N.bc4_encode_blocks(torch.from_numpy(tex).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(got, O.encode_bc4(tex))
+
+
+def test_bc7_encoder_matches_oracle_bit_for_bit(N, ctx):
+    import torch
+    from tests.test_oracle_encode import _test_blocks
+    g = np.random.default_rng(141)
+    dec = np.stack([O.bc7m6_decode_block(b) for b in I.random_bc7m6((200,), g)]).astype(np.int64)
+    tex = np.concatenate([_test_blocks(142), _test_blocks(143), dec,
+                          np.repeat(g.integers(0, 256, (40, 16, 1)), 4, axis=2)]).astype(np.uint8)
+    got = N.bc7_encode_blocks(torch.from_numpy(tex).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(got, O.encode_bc7m6(tex))
+    # and the decode of what it wrote is the decode of the oracle's blocks (both decoders pinned)
+    np.testing.assert_array_equal(N.bc7_decode_blocks(torch.from_numpy(got).cuda()).cpu().numpy(),
+                                  np.stack([O.bc7m6_decode_block(b) for b in got]))
+
+
+@pytest.mark.parametrize("state_codec,flags,codec", [(0, 0, 0), (0, 0, 1), (1, 0, 1), (1, 0, 0), (0, 8, 0), (0, 8, 1),
+                                                     (0, 1, 0), (1, 1, 1)])
+def test_hybrid_encode_matches_oracle(N, ctx, state_codec, flags, codec):
+    """The paper's export: reconstruct (lerp, direct or rounded), quantise, encode; every
+    output bit for bit."""
+    from paper_2604_12625_amd.train import HybridTrainer
+    # BC4 output: the oracle's exhaustive encoder takes tens of ms per block, so the 8 x 8 map
+    st = _state(16, seed=150 + 3 * state_codec + flags, bigger=codec == 1, codec=state_codec)
+    tr = HybridTrainer(ctx, st)
+    hm = tr.encode(flags, codec, N.DTYPE_F32)
+    ref = O.hybrid_encode(st, flags, codec)
+    for i, k in enumerate(("fuv", "fuvt", "fut", "fvt")):
+        np.testing.assert_array_equal(hm.arrays[i].cpu().numpy(), ref[k], err_msg=k)
+    np.testing.assert_array_equal(hm.arrays[5].cpu().numpy(), ref["mlp"])
+    assert hm.desc.codec == codec
+
+
+def test_hybrid_encode_rejects_bad_flags(N, ctx):
+    from paper_2604_12625_amd.train import HybridTrainer
+    tr = HybridTrainer(ctx, _state(16, seed=160, codec=1))
+    with pytest.raises(N.NdgiError):
+        tr.encode(N.HTRAIN_DIRECT, 1)          # a directly optimised map has the BC4 layout
+    tr0 = HybridTrainer(ctx, _state(16, seed=161))
+    with pytest.raises(N.NdgiError):
+        tr0.encode(N.HTRAIN_DIRECT | N.HTRAIN_BCSIM, 1)
+    with pytest.raises(N.NdgiError):
+        tr0.encode(0, 7)
+    with pytest.raises(N.NdgiError):          # DIRECT training on a BC7-layout state
+        import torch
+        tr.loss_grad(torch.zeros(64, dtype=torch.int32, device="cuda"),
+                     torch.zeros((3, 8, 8, 3), dtype=torch.float32, device="cuda"), N.HTRAIN_DIRECT)
+
+
+@pytest.mark.parametrize("codec", [0, 1])
+def test_import_equals_oracle_and_fine_tune_reads_the_decode(N, ctx, codec):
+    """ndgi_hybrid_import writes the oracle's imported state bit for bit; a DIRECT | QPLANES
+    forward on it equals the FP32 decode of the model (the final stage trains on what a decode
+    reads)."""
+    import torch
+    from paper_2604_12625_amd.train import hybrid_import_models
+    m = I.random_hybrid_model(W=64, H=48, profile="L", slices=5, plane=(32, 48, 4), keys=True, config=170 + codec,
+                              codec=codec, uvt_side=(16, 12), mlp_dtype=np.float16)
+    hm = N.HybridModel.from_numpy(m)
+    frames = len(m["keys"])
+    tr = hybrid_import_models(ctx, [hm], frames, keys=m["keys"])
+    ref = O.hybrid_import(m, frames)
+    got = tr.split(tr.params)
+    for k in O.HYB_KEYS:
+        np.testing.assert_array_equal(got[k].cpu().numpy(), ref[k].astype(np.float32), err_msg=k)
+    g = np.random.default_rng(171)
+    n = 5000
+    x, y, f = g.integers(0, m["W"], n), g.integers(0, m["H"], n), g.integers(0, frames, n)
+    smp, _ = _dev(N, x, y, f, np.zeros((frames, m["H"], m["W"], 3), np.float32))
+    fwd = tr.forward(smp, N.HTRAIN_DIRECT | N.HTRAIN_QPLANES).cpu().numpy()
+    q = np.stack([(x + 0.5) / m["W"], (y + 0.5) / m["H"], np.asarray(m["keys"], np.float32)[f]], 1).astype(np.float32)
+    dec = ctx.hybrid_decode(hm, torch.from_numpy(q).cuda(), N.PREC_F32).cpu().numpy()
+    rms = np.sqrt(np.mean(dec.astype(np.float64) ** 2))
+    assert np.max(np.abs(fwd - dec) / np.maximum(np.abs(dec), rms)) <= 1e-5

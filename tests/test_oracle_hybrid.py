@@ -192,7 +192,7 @@ def test_mirror_texel_is_numpys_symmetric_padding():
 
 def test_bordered_pages_mirror_tiles_and_join_neighbours():
     """A per-tile model's bordered page is its plain page padded symmetrically (the border
-    mirrors the tile, Sec. 6); on a map of several pages the border of an inner page holds
+    mirrors the tile, supplementary Virtual Texturing section); on a map of several pages the border of an inner page holds
     the neighbouring pages' texels, so the pages join without seams; the interior is the
     plain page."""
     b, t = 4, np.float32(0.63)

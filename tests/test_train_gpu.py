@@ -1,5 +1,7 @@
 """GPU parity of the training path (BC-simulated forward, FP64 loss, hand-written backward,
 Adam, export, tile statistics) against the CPU oracle, through the C ABI."""
+import math
+
 import numpy as np
 import pytest
 
@@ -144,8 +146,18 @@ def test_fused_steps_match_oracle_on_c4_sized_problem(env):
     # gradient noise on a cancelling sum shows up as a fraction of lr: the absolute floor
     # is 1e-3 * lr per step.  Separately, an FP32 and an FP64 master value can round to
     # different 8-bit endpoints / 3-bit weights at a quantisation boundary, which changes
-    # that texel's feature by a code step; all but 1e-3 of the parameters must match to
-    # 1e-4 relative + 1e-6.
+    # that texel's feature by a code step: exactly the footprints (block and channel) whose
+    # quantised endpoints or weights differ between the two masters are exempt from the
+    # tighter 1e-4 relative + 1e-6 bound, which every other parameter meets.
+    a_ep, b_ep = got["endpoints"].cpu().numpy(), ref["endpoints"]
+    a_w, b_w = got["weights"].cpu().numpy(), ref["weights"]
+    flip_e = (O.quantise_endpoint(a_ep) != O.quantise_endpoint(b_ep)).any(-1)          # [Hb][Wb][8]
+    fj = O.quantise_weight(a_w) != O.quantise_weight(b_w)                              # [H][W][8]
+    flip_j = fj.reshape(H // 4, 4, W // 4, 4, 8).any(axis=(1, 3))
+    flip = flip_e | flip_j
+    exempt = dict(endpoints=np.repeat(flip[..., None], 2, axis=-1),
+                  weights=np.repeat(np.repeat(flip, 4, axis=0), 4, axis=1),
+                  grid=np.zeros(ref["grid"].shape, bool), mlp=np.zeros(ref["mlp"].shape, bool))
     for kk in ("mlp", "grid", "endpoints", "weights"):
         lr = 1e-3 if kk == "mlp" else 1e-2
         a = got[kk].cpu().numpy().astype(np.float64)
@@ -153,8 +165,9 @@ def test_fused_steps_match_oracle_on_c4_sized_problem(env):
         err = np.abs(a - b)
         bad = err > 1e-4 * np.abs(b) + 3e-3 * lr
         assert bad.sum() == 0, f"{kk}: {int(bad.sum())} params off, worst {err.max():.3e}"
-        loose = err > 1e-4 * np.abs(b) + 1e-6
-        assert loose.sum() <= max(1, int(1e-3 * b.size)), f"{kk}: {int(loose.sum())} params above 1e-4"
+        loose = (err > 1e-4 * np.abs(b) + 1e-6) & ~exempt[kk]
+        assert loose.sum() == 0, (f"{kk}: {int(loose.sum())} params above 1e-4 outside the {int(flip.sum())} "
+                                  f"footprints with a quantisation flip, worst {err[loose].max():.3e}")
     assert float(tr.grads.abs().max()) == 0.0       # Adam zeroes the gradients
 
 
@@ -185,10 +198,61 @@ def test_tile_stats_match_oracle_psnr(env):
     tgt = g.uniform(0.0, 4.0, (T, H, W, 3)).astype(np.float16)
     tgt[1, :128, :128] = 1.5                    # a zero-range tile (skipped)
     pred = (tgt.astype(np.float32) + g.normal(0, 0.01, tgt.shape)).astype(np.float32)
-    stats = [ctx.tile_stats(torch.from_numpy(pred[kk]).cuda(),
-                            torch.from_numpy(tgt[kk].view(np.int16)).cuda(), W, H, 128).cpu().numpy()
-             for kk in range(T)]
-    tiled, glob = N.psnr_from_stats(stats, W, H, 128)
+    stats = torch.stack([ctx.tile_stats(torch.from_numpy(pred[kk]).cuda(),
+                                        torch.from_numpy(tgt[kk].view(np.int16)).cuda(), W, H, 128)
+                         for kk in range(T)])
+    ps = ctx.psnr(stats, W, H, 128)
     want_tiled, want_glob = O.psnr_tiled(pred, tgt, 128)
-    assert abs(tiled - want_tiled) < 1e-9
-    assert abs(glob - want_glob) < 1e-9
+    assert abs(ps["tiled"] - want_tiled) < 1e-9
+    assert abs(ps["global"] - want_glob) < 1e-9
+    assert ps["tiles"] == T * 3 * 3 and ps["scored"] == T * 3 * 3 - 1
+    db = ps["tile_db"].cpu().numpy()
+    assert np.isnan(db[1, 0, 0]) and np.nanmin(db) == ps["min"]
+
+
+def test_psnr_reduction_closed_forms(env):
+    """ndgi_psnr on hand-made statistics: a tile of range R with constant error d scores
+    20 log10(R / d); a zero-range tile is skipped; an exact tile scores 100 dB; ragged tiles
+    count their own texels (300 x 200 map, 128-texel tiles)."""
+    torch, N, TR, ctx = env
+    W, H, tile = 300, 200, 128
+    ny, nx = 2, 3
+    st = np.zeros((ny, nx, 3))
+    cnt = lambda ty, tx: min(tile, H - tile * ty) * min(tile, W - tile * tx) * 3
+    want = []
+    for ty in range(ny):
+        for tx in range(nx):
+            R, d = 2.0 + ty + tx, 0.01 * (1 + tx)
+            st[ty, tx] = (1.0 + R, 1.0, d * d * cnt(ty, tx))
+            want.append(20 * math.log10(R / d))
+    st[0, 1] = (1.5, 1.5, 0.3)          # zero range: skipped
+    del want[1]
+    st[1, 2, 2] = 0.0                   # exact tile
+    want[-1] = 100.0
+    ps = ctx.psnr(torch.from_numpy(st[None]).cuda(), W, H, tile)
+    assert math.isclose(ps["tiled"], sum(want) / len(want), rel_tol=1e-12)
+    assert ps["scored"] == 5 and ps["tiles"] == 6
+    gsse = st[..., 2].sum()
+    grng = st[..., 0].max() - st[..., 1].min()
+    assert math.isclose(ps["global"], 10 * math.log10(grng ** 2 / (gsse / (W * H * 3))), rel_tol=1e-12)
+
+
+def test_c4_sized_batch_runs_every_accumulation_path(env):
+    """A batch of 2^18 samples (the C4 training batch) on a 256^2 x 8 map the oracle finishes
+    in about a second: every wave of the training kernel loops over several 16-sample groups
+    (8 on a 256-CU GPU) and the row reduction of the decoder gradients sees its full
+    2048-row case.  Loss, forward and the four gradient arrays against the oracle."""
+    torch, N, TR, ctx = env
+    W = H = 256
+    st, x, y, k, tgt = problem(W, H, 64, 64, 8, 1 << 18, seed=51)
+    tr = TR.Trainer(ctx, st)
+    smp, tg = device_batch(torch, x, y, k, tgt)
+    pred = tr.forward(smp).cpu().numpy()
+    sel = np.arange(0, 1 << 18, 97)
+    assert_rel(pred[sel], O.train_forward(st, x[sel], y[sel], k[sel]), 1e-5, "train forward")
+    loss = float(tr.loss_grad(smp, tg).item())
+    ref_loss, ref = O.train_grads(st, x, y, k, tgt[k, y, x].astype(np.float64))
+    assert abs(loss - ref_loss) <= 2e-6 * ref_loss, (loss, ref_loss)
+    gr = tr.split(tr.grads)
+    for key in ("mlp", "grid", "endpoints", "weights"):
+        assert_grad(gr[key].cpu().numpy(), ref[key], key)
