@@ -24,7 +24,7 @@ __device__ __forceinline__ BcTex bc_texel(const float* __restrict__ ep, const fl
     if (bcsim) {
       const int E1 = (int)rintf(255.0f * e1[c]), E2 = (int)rintf(255.0f * e2[c]), J = (int)rintf(7.0f * ww[c]);
       r.v[c] = (float)(((7 - J) * E1 + J * E2 + 3) / 7) * (1.0f / 255.0f);
-      r.d1[c] = 1.0f - (float)J * (1.0f / 7.0f);
+      r.d1[c] = (float)(7 - J) * (1.0f / 7.0f);
       r.d2[c] = (float)J * (1.0f / 7.0f);
       r.dw[c] = (float)(E2 - E1) * (1.0f / 255.0f);
     } else {

@@ -152,6 +152,14 @@ __global__ __launch_bounds__(256) void k_encode_bc4(TexSrc S, int64_t n, uint8_t
 }
 
 // ---------------------------------------------------------------------------- BC7 mode 6
+// Sum over all 64 lanes, returned in every lane.  Callers pass one texel's value in its
+// first lane (lane & 3 == 0) and 0 in the other three.
+__device__ __forceinline__ int wave_isum(int v) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 // Index fit of endpoints E0, E1 for the wave's block: J = this lane's texel's best index
 // (the lowest on ties); returns the block's summed squared error (the same in every lane).
 __device__ __forceinline__ int m6_fit(const int X[4], const int E0[4], const int E1[4], int lane, int& J) {
@@ -180,21 +188,13 @@ __device__ __forceinline__ int m6_fit(const int X[4], const int E0[4], const int
     }
   }
   J = bj;
-  int v = (lane & 3) == 0 ? best : 0;
-#pragma unroll
-  for (int off = 4; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  return wave_isum((lane & 3) == 0 ? best : 0);
 }
 
 struct M6 {
   int v0[4], v1[4], p0, p1, sse, J;
 };
 
-__device__ __forceinline__ int wave_isum(int v) {
-#pragma unroll
-  for (int off = 4; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 // Try (v0, p0, v1, p1): taken when strictly better than the current block.
 __device__ __forceinline__ void m6_take(M6& cur, const int X[4], const int v0[4], int p0, const int v1[4], int p1,

@@ -245,9 +245,11 @@ __global__ __launch_bounds__(256) void k_train(TrainDims d, const float* __restr
     if (valid) {
       const float da = dx[0], db = dx[1];
       float* ge = g_ep + blk * 2;
-      atomicAdd(ge + 0, da * (1.0f - (float)Ja * (1.0f / 7.0f)));
+      // straight-through derivatives 1 - J/7 and J/7, written (7 - J)/7 so that J = 7 gives
+      // exactly 0 (1 - J * (1/7) contracts to an FMA that leaves -4e-8 there)
+      atomicAdd(ge + 0, da * ((float)(7 - Ja) * (1.0f / 7.0f)));
       atomicAdd(ge + 1, da * ((float)Ja * (1.0f / 7.0f)));
-      atomicAdd(ge + 2, db * (1.0f - (float)Jb * (1.0f / 7.0f)));
+      atomicAdd(ge + 2, db * ((float)(7 - Jb) * (1.0f / 7.0f)));
       atomicAdd(ge + 3, db * ((float)Jb * (1.0f / 7.0f)));
       float* gw = g_w + ((size_t)y * d.W + x) * 8 + 2 * g;
       atomicAdd(gw + 0, da * (float)(E2a - E1a) * (1.0f / 255.0f));

@@ -131,33 +131,62 @@ def test_fused_steps_match_oracle_on_c4_sized_problem(env):
                v={kk: np.zeros(np.asarray(st[kk]).shape) for kk in ("endpoints", "weights", "grid", "mlp")})
     ref = {kk: np.asarray(st[kk], np.float64).copy() for kk in ("endpoints", "weights", "grid", "mlp")}
     ref["dims"] = st["dims"]
+
+    def flipped_blocks():
+        # footprints whose quantised endpoints or weights differ between the FP32 and FP64
+        # masters in any channel
+        cur = tr.split(tr.params)
+        a_ep, b_ep = cur["endpoints"].cpu().numpy(), ref["endpoints"]
+        a_w, b_w = cur["weights"].cpu().numpy(), ref["weights"]
+        fe = (O.quantise_endpoint(a_ep) != O.quantise_endpoint(b_ep)).any(axis=(-1, -2))   # [Hb][Wb]
+        fj = (O.quantise_weight(a_w) != O.quantise_weight(b_w)).any(-1)                     # [H][W]
+        return fe | fj.reshape(H // 4, 4, W // 4, 4).any(axis=(1, 3))
+
+    flip = np.zeros((H // 4, W // 4), bool)
+    tiny = {kk: np.zeros(np.asarray(st[kk]).shape, bool) for kk in ("endpoints", "weights", "grid", "mlp")}
+    steps = []
     for step in range(3):
         x, y, k = I.train_samples(4096, W, H, T, I.rng(4, I.P_SAMPLES, step))
+        steps.append((x, y, k))
         tv = g.uniform(0.05, 3.0, (4096, 3)).astype(np.float16)
         tgt = np.zeros((T, H, W, 3), dtype=np.float16)
         tgt[k, y, x] = tv
         smp, tg = device_batch(torch, x, y, k, tgt)
         loss = float(tr.step(smp, tg).item())
+        _, g64 = O.train_grads(ref, x, y, k, tgt[k, y, x].astype(np.float64))
+        for kk in tiny:
+            tiny[kk] |= (g64[kk] != 0) & (np.abs(g64[kk]) < 100 * 1e-8)
         ref_loss = O.train_step(ref, opt, x, y, k, tgt[k, y, x].astype(np.float64))
         assert abs(loss - ref_loss) <= 1e-5 * ref_loss, (step, loss, ref_loss)
+        flip |= flipped_blocks()
     assert tr.step_count == 3
     got = tr.split(tr.params)
     # Adam moves a parameter by about lr per step whatever the gradient's size, so FP32
     # gradient noise on a cancelling sum shows up as a fraction of lr: the absolute floor
     # is 1e-3 * lr per step.  Separately, an FP32 and an FP64 master value can round to
     # different 8-bit endpoints / 3-bit weights at a quantisation boundary, which changes
-    # that texel's feature by a code step: exactly the footprints (block and channel) whose
-    # quantised endpoints or weights differ between the two masters are exempt from the
-    # tighter 1e-4 relative + 1e-6 bound, which every other parameter meets.
-    a_ep, b_ep = got["endpoints"].cpu().numpy(), ref["endpoints"]
-    a_w, b_w = got["weights"].cpu().numpy(), ref["weights"]
-    flip_e = (O.quantise_endpoint(a_ep) != O.quantise_endpoint(b_ep)).any(-1)          # [Hb][Wb][8]
-    fj = O.quantise_weight(a_w) != O.quantise_weight(b_w)                              # [H][W][8]
-    flip_j = fj.reshape(H // 4, 4, W // 4, 4, 8).any(axis=(1, 3))
-    flip = flip_e | flip_j
-    exempt = dict(endpoints=np.repeat(flip[..., None], 2, axis=-1),
-                  weights=np.repeat(np.repeat(flip, 4, axis=0), 4, axis=1),
-                  grid=np.zeros(ref["grid"].shape, bool), mlp=np.zeros(ref["mlp"].shape, bool))
+    # that texel's feature by a code step and so the output error of every sample there.
+    # Exempt from the tighter 1e-4 relative + 1e-6 bound (which every other parameter
+    # meets) are exactly what such a sample's gradient reaches: every channel of a
+    # footprint that flipped after any step, and the grid nodes that samples on its texels
+    # interpolate (their key and the next, the 2 x 2 grid cell around the texel centre).
+    # Also exempt: parameters whose FP64 gradient in some step is nonzero but below
+    # 100 eps (eps = 1e-8).  There Adam's update is about g / eps rather than sign(g), so
+    # the FP32 gradient's absolute rounding error (cancelling channel and sample sums) moves
+    # the parameter by up to lr times that error over eps.
+    grid_ex = np.zeros(ref["grid"].shape[:3], bool)                                      # [T][Gh][Gw]
+    for x, y, k in steps:
+        on = flip[y // 4, x // 4]
+        gx0 = np.floor((x[on] + 0.5) * Gw / W - 0.5).astype(np.int64)
+        gy0 = np.floor((y[on] + 0.5) * Gh / H - 0.5).astype(np.int64)
+        for dk in (0, 1):
+            for dy in (0, 1):
+                for dx in (0, 1):
+                    grid_ex[(k[on] + dk) % T, np.clip(gy0 + dy, 0, Gh - 1), np.clip(gx0 + dx, 0, Gw - 1)] = True
+    fl8 = np.repeat(flip[..., None], 8, axis=-1)
+    exempt = dict(endpoints=np.repeat(fl8[..., None], 2, axis=-1),
+                  weights=np.repeat(np.repeat(fl8, 4, axis=0), 4, axis=1),
+                  grid=np.repeat(grid_ex[..., None], 8, axis=-1), mlp=np.zeros(ref["mlp"].shape, bool))
     for kk in ("mlp", "grid", "endpoints", "weights"):
         lr = 1e-3 if kk == "mlp" else 1e-2
         a = got[kk].cpu().numpy().astype(np.float64)
@@ -165,9 +194,10 @@ def test_fused_steps_match_oracle_on_c4_sized_problem(env):
         err = np.abs(a - b)
         bad = err > 1e-4 * np.abs(b) + 3e-3 * lr
         assert bad.sum() == 0, f"{kk}: {int(bad.sum())} params off, worst {err.max():.3e}"
-        loose = (err > 1e-4 * np.abs(b) + 1e-6) & ~exempt[kk]
+        loose = (err > 1e-4 * np.abs(b) + 1e-6) & ~exempt[kk] & ~tiny[kk]
         assert loose.sum() == 0, (f"{kk}: {int(loose.sum())} params above 1e-4 outside the {int(flip.sum())} "
-                                  f"footprints with a quantisation flip, worst {err[loose].max():.3e}")
+                                  f"footprints with a quantisation flip and the {int(tiny[kk].sum())} with a "
+                                  f"gradient below 100 eps, worst {err[loose].max():.3e}")
     assert float(tr.grads.abs().max()) == 0.0       # Adam zeroes the gradients
 
 
