@@ -206,6 +206,24 @@ int ndgi_decode_binned(ndgi_ctx* ctx, const ndgi_model* model, const float* uvt,
                        void* out, int32_t prec, void* workspace, int64_t workspace_bytes,
                        hipStream_t stream);
 
+/* Binned decode that allocates nothing and takes no workspace: for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same kernels and the same result, bit for bit, as
+ * ndgi_decode_binned; the sort's scratch is a static device array of
+ * NDGI_NOALLOC_SCRATCH_BYTES bytes that the library holds on each GPU it runs on until the
+ * process ends (its address is taken once per device by ndgi_create).
+ *   uvt, out, prec, model, n: as for ndgi_decode_binned.
+ * The call fails with INVALID_ARG when ndgi_decode_binned_workspace reports more than
+ * NDGI_NOALLOC_SCRATCH_BYTES for (model, n) (above 2,084,576 queries on a 4096x4096 map with a
+ * 1024x1024 grid, 4,061,936 on a 1024x1024 map with a 256x256 grid), before any launch.
+ * No hipMalloc, hipFree or allocating library call is made.  Every call on one GPU shares that GPU's scratch, whose contents carry over from
+ * the last call (nothing in it needs to start at zero): calls that overlap on one GPU, from
+ * any context, stream or thread, race and give undefined results; order them on one stream.
+ * Errors: as ndgi_decode_binned. */
+#define NDGI_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int ndgi_decode_binned_noalloc(ndgi_ctx* ctx, const ndgi_model* model, const float* uvt, int64_t n,
+                               void* out, int32_t prec, hipStream_t stream);
+
 /* Batched virtual-texturing page decode (Sec. 3.5; supplementary Sec. C): every valid
  * request decodes the page x page texel centres of its page of models_dev[model] at its
  * time t and writes texel (i, j) of the page to dst[dst_offset + j*dst_pitch + i]

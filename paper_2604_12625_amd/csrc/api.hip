@@ -2,10 +2,37 @@
 #include <climits>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "internal.hpp"
 
 namespace ndgi {
+
+// Scratch of ndgi_decode_binned_noalloc: a file-scope device array, one copy on every GPU
+// the library runs on, held until the process ends.  In host code the array's name is not
+// a device address: its address on a device comes from hipGetSymbolAddress, taken once per
+// device (with that device current) by ndgi_create and kept per device here and in the
+// context.
+static __device__ __align__(256) unsigned char scratch[NDGI_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be the current device.
+static int scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(NDGI_ERR_UNSUPPORTED, "create: device %d >= %d", device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(NDGI_ERR_HIP, "create: hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_dev[device] = p;
+  }
+  *out = g_scratch_dev[device];
+  return NDGI_OK;
+}
 
 static thread_local std::string g_last_error;
 
@@ -122,6 +149,10 @@ int ndgi_create(ndgi_ctx** out, int32_t device) {
   }
   c->n_cu = prop.multiProcessorCount;
   c->train_waves = c->n_cu * 8;
+  if (const int rc = scratch_address(device, &c->scratch_dev)) {
+    delete c;
+    return rc;
+  }
   bool ok = hipMalloc(&c->flags_dev, 256) == hipSuccess &&
             hipMalloc(&c->partials_dev, sizeof(float) * (size_t)c->train_waves * kPartialStride) == hipSuccess &&
             hipMalloc(&c->loss_part_dev, sizeof(double) * (size_t)c->train_waves) == hipSuccess &&
@@ -224,6 +255,28 @@ int ndgi_decode_binned(ndgi_ctx* c, const ndgi_model* m, const float* uvt, int64
   if (n == 0) return NDGI_OK;
   if (!uvt || !out || !workspace) return fail(NDGI_ERR_INVALID_ARG, "decode_binned: NULL query/output/workspace");
   return launch_decode_binned(c, *m, uvt, n, out, prec, workspace, workspace_bytes, s);
+}
+
+int ndgi_decode_binned_noalloc(ndgi_ctx* c, const ndgi_model* m, const float* uvt, int64_t n, void* out,
+                               int32_t prec, hipStream_t s) {
+  clear_error();
+  if (!c) return fail(NDGI_ERR_INVALID_ARG, "decode_binned_noalloc: ctx is NULL");
+  if (n < 0 || n > INT32_MAX) return fail(NDGI_ERR_INVALID_ARG, "decode_binned_noalloc: n out of [0, 2^31)");
+  if (prec != NDGI_PREC_F32 && prec != NDGI_PREC_F16)
+    return fail(NDGI_ERR_INVALID_ARG, "decode_binned_noalloc: bad prec %d", prec);
+  int rc = check_model(m, "decode_binned_noalloc");
+  if (rc) return rc;
+  int64_t need = 0;
+  rc = binned_workspace(*m, n, &need);
+  if (rc) return rc;
+  if (need > NDGI_NOALLOC_SCRATCH_BYTES)
+    return fail(NDGI_ERR_INVALID_ARG,
+                "decode_binned_noalloc: %lld queries on a %dx%d map need %lld bytes of scratch, above the static "
+                "%lld bytes; decode in smaller batches or call ndgi_decode_binned with a workspace",
+                (long long)n, m->W, m->H, (long long)need, (long long)NDGI_NOALLOC_SCRATCH_BYTES);
+  if (n == 0) return NDGI_OK;
+  if (!uvt || !out) return fail(NDGI_ERR_INVALID_ARG, "decode_binned_noalloc: NULL query/output");
+  return launch_decode_binned(c, *m, uvt, n, out, prec, c->scratch_dev, NDGI_NOALLOC_SCRATCH_BYTES, s);
 }
 
 int ndgi_decode_pages(ndgi_ctx* c, const ndgi_model* models, int32_t n_models, const ndgi_page_req* reqs,

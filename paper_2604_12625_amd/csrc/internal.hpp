@@ -42,6 +42,7 @@ struct ndgi_ctx {
   int tile_w = 1, tile_h = 4, waves_per_cu = 32;  // page decode launch shape
   hipStream_t capture_stream = nullptr;
   uint32_t* flags_dev = nullptr;
+  void* scratch_dev = nullptr;   // this device's copy of the static scratch of decode_binned_noalloc
   // training workspace
   int train_waves = 0;          // persistent waves of the training kernel
   float* partials_dev = nullptr;  // [train_waves][kPartialStride]

@@ -24,7 +24,7 @@ EXPORTED = (
     "ndgi_create", "ndgi_destroy", "ndgi_last_error", "ndgi_get_error_flags",
     "ndgi_bc4_decode_blocks", "ndgi_bc7_decode_blocks", "ndgi_decode", "ndgi_decode_pages", "ndgi_decode_pages_graph",
     "ndgi_set_launch", "ndgi_train_param_count", "ndgi_train_step", "ndgi_export",
-    "ndgi_tile_stats", "ndgi_decode_binned_workspace", "ndgi_decode_binned",
+    "ndgi_tile_stats", "ndgi_decode_binned_workspace", "ndgi_decode_binned", "ndgi_decode_binned_noalloc",
     "ndgi_hybrid_mlp_size", "ndgi_hybrid_decode", "ndgi_hybrid_decode_pages",
     "ndgi_hybrid_decode_pages_graph", "ndgi_hybrid_train_param_count", "ndgi_hybrid_train_step",
     "ndgi_hybrid_export", "ndgi_hybrid_normalize_target", "ndgi_hybrid_restore",
@@ -125,6 +125,7 @@ def lib():
         L.ndgi_psnr.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, vp]
         L.ndgi_decode_binned_workspace.argtypes = [C.POINTER(NdgiModel), i64, C.POINTER(i64)]
         L.ndgi_decode_binned.argtypes = [vp, C.POINTER(NdgiModel), vp, i64, vp, i32, vp, i64, vp]
+        L.ndgi_decode_binned_noalloc.argtypes = [vp, C.POINTER(NdgiModel), vp, i64, vp, i32, vp]
         L.ndgi_hybrid_mlp_size.argtypes = [i32]
         L.ndgi_hybrid_mlp_size.restype = i32
         L.ndgi_hybrid_decode.argtypes = [vp, C.POINTER(NdgiHybridModel), vp, i64, vp, i32, vp]
@@ -269,6 +270,13 @@ class Context:
                                        _ptr(workspace), workspace.numel(), _stream(stream)),
               "ndgi_decode_binned")
         return out, workspace
+
+    def decode_binned_noalloc(self, model: DeviceModel, uvt, out, prec=PREC_F16, stream=None):
+        """Binned decode into the caller's `out` through the library's static scratch
+        (allocates nothing, takes no workspace)."""
+        check(lib().ndgi_decode_binned_noalloc(self.h, C.byref(model.desc), _ptr(uvt), uvt.shape[0], _ptr(out),
+                                               prec, _stream(stream)), "ndgi_decode_binned_noalloc")
+        return out
 
     def decode_pages(self, models_dev, n_models, reqs_dev, n_reqs_dev, max_reqs, page, dst,
                      pitch, prec=PREC_F16, graph=False, stream=None):
