@@ -175,6 +175,58 @@ def run_c2(args, torch, N, I, ctx):
     return out, (dm, q)
 
 
+# Decoder work per texel (2 (16 x 32 + 32 x 32 + 32 x 3) flop) and the dense FP16 MFMA peak.
+MLP_FLOP_PER_TEXEL = 3264
+MFMA_F16_PEAK_TFLOPS = 2500.0
+
+
+def vt_frame_bytes(sides, mi, px, py, t, page=PAGE):
+    """Compulsory HBM bytes of one VT frame: the BC4 blocks of every distinct (map, page),
+    the 8-channel FP16 grid nodes of every distinct (map, page, key) window the page's
+    texel centres interpolate (keys k0 and k1 of each request's t, periodic over T), and the
+    6-byte RGB of every requested texel."""
+    import numpy as np
+    mi, px, py = np.asarray(mi), np.asarray(px), np.asarray(py)
+    pages = set(zip(mi.tolist(), px.tolist(), py.tolist()))
+    tau = np.asarray(t, np.float64) * T
+    k0 = np.floor(tau).astype(np.int64) % T
+    k1 = (k0 + 1) % T
+    windows = set(zip(mi.tolist(), px.tolist(), py.tolist(), k0.tolist())) | \
+        set(zip(mi.tolist(), px.tolist(), py.tolist(), k1.tolist()))
+    total = len(pages) * (page * page // 16) * 64
+    gp = page // 4                       # grid nodes per page side (grid at a quarter of the texels)
+    for m, x, y, _ in windows:
+        G = int(sides[m]) // 4
+        nx = min(G - 1, gp * x + gp) - max(0, gp * x - 1) + 1
+        ny = min(G - 1, gp * y + gp) - max(0, gp * y - 1) + 1
+        total += nx * ny * 16
+    return total + len(mi) * page * page * 6
+
+
+def run_c1(args, torch, N, I, ctx, reps=50):
+    """The tiny parity configuration: 64 x 64 map, 16 x 16 x 8 grid, all 4096 texel centres at
+    8 times (32,768 queries); decode latency of one call, FP32 and FP16."""
+    import numpy as np
+    m = I.random_model(64, 64, 16, 16, 8, np.float32, np.float32, config=1)
+    dm = N.DeviceModel.from_numpy(m)
+    ts = I.rng(1, I.P_QUERY).random(8, dtype=np.float32)
+    q = torch.from_numpy(I.texel_centre_queries(64, 64, ts)).cuda()
+    out = {"queries": int(q.shape[0])}
+    for prec, name in ((N.PREC_F32, "f32"), (N.PREC_F16, "f16")):
+        o = ctx.decode(dm, q, prec)
+        tm = Timer(torch)
+        for _ in range(reps):
+            e = tm.start()
+            ctx.decode(dm, q, prec, out=o)
+            tm.stop(e)
+        torch.cuda.synchronize()
+        ms = sorted(tm.ms())
+        out[f"{name}_latency_us_p50"] = 1e3 * ms[reps // 2]
+        out[f"{name}_latency_us_p99"] = 1e3 * ms[min(reps - 1, int(round(0.99 * (reps - 1))))]
+    log(f"C1: FP32 {out['f32_latency_us_p50']:.1f} us, FP16 {out['f16_latency_us_p50']:.1f} us per call")
+    return out
+
+
 def run_c3(args, torch, N, I, ctx, frames=110, warm=10):
     """32 maps, 2000 page requests per frame (Zipf 1.1), one graph replay per frame."""
     import numpy as np
@@ -190,10 +242,11 @@ def run_c3(args, torch, N, I, ctx, frames=110, warm=10):
     pitch = per_row * PAGE
     dst = torch.empty((((n_req + per_row - 1) // per_row) * PAGE * pitch, 3), dtype=torch.float16, device="cuda")
     offs = np.array([(i // per_row) * PAGE * pitch + (i % per_row) * PAGE for i in range(n_req)], dtype=np.int64)
-    all_rq = []
+    all_rq, frame_bytes = [], []
     for f in range(frames):
         mi, px, py, t = I.vt_requests(sides, n_req, I.rng(3, I.P_REQ, f))
         all_rq.append(N.page_requests(mi, px, py, t, offs))
+        frame_bytes.append(vt_frame_bytes(sides, mi, px, py, t))
     rq = torch.empty_like(all_rq[0])
     nreq = torch.tensor([n_req], dtype=torch.int32, device="cuda")
     rq.copy_(all_rq[0])
@@ -208,13 +261,29 @@ def run_c3(args, torch, N, I, ctx, frames=110, warm=10):
         ctx.decode_pages(marr, len(models), rq, nreq, n_req, PAGE, dst, pitch, N.PREC_F16, graph=True)
         tm.stop(e)
     torch.cuda.synchronize()
-    ms = sorted(tm.ms()[warm:])
+    times = tm.ms()[warm:]
+    ms = sorted(times)
     p50 = ms[len(ms) // 2]
     p99 = ms[min(len(ms) - 1, int(round(0.99 * (len(ms) - 1))))]
     log(f"C3 VT frame: p50 {p50:.3f} ms, p99 {p99:.3f} ms ({texels / p50 / 1e6:.1f} G texels/s at p50)")
     assert ctx.error_flags() == 0
+    # roofline per frame: its compulsory bytes at the HBM peak against its decoder flops at
+    # the FP16 MFMA peak; the median over the timed frames of (bound time / frame time)
+    fb = frame_bytes[warm:]
+    t_hbm = [b / (HBM_PEAK_GBS * 1e9) for b in fb]
+    t_mfma = texels * MLP_FLOP_PER_TEXEL / (MFMA_F16_PEAK_TFLOPS * 1e12)
+    fracs = sorted(max(th, t_mfma) / (tt * 1e-3) for th, tt in zip(t_hbm, times))
+    mean_b = sum(fb) / len(fb)
+    bound = "hbm" if sum(t_hbm) / len(t_hbm) >= t_mfma else "mfma"
+    rl = dict(bound=bound, peak=HBM_PEAK_GBS if bound == "hbm" else MFMA_F16_PEAK_TFLOPS,
+              unit="GB/s" if bound == "hbm" else "TFLOP/s", traffic=None, kernel="k_decode_tiles (graph replay)",
+              bytes_per_launch=mean_b, flop_per_launch=texels * MLP_FLOP_PER_TEXEL)
+    rl["achieved"] = (mean_b / (p50 * 1e-3) / 1e9 if bound == "hbm"
+                      else texels * MLP_FLOP_PER_TEXEL / (p50 * 1e-3) / 1e12)
+    rl["frac"] = fracs[len(fracs) // 2]
     return dict(p50_ms=p50, p99_ms=p99, texels_per_frame=texels, launch_shape=list(shape),
-                maps=[int(s) for s in sides])
+                maps=[int(s) for s in sides], roofline=rl,
+                bound_us=dict(hbm=1e6 * sum(t_hbm) / len(t_hbm), mfma=1e6 * t_mfma))
 
 
 # Decode latency of a 1024 x 1024 lightmap reported for the paper's profiles on an RTX 4060
@@ -265,6 +334,19 @@ def run_hybrid(args, torch, N, I, ctx, reps=30, warm=5):
             row[f"{name}_texels_per_s"] = 64 * R * R / (ms * 1e-3)
         if prof in PAPER_TABLE5_MS and not border:
             row["paper_rtx4060_ms"] = PAPER_TABLE5_MS[prof]
+        # roofline of the FP16 launch: compulsory bytes of one decode at one t (every F_uv
+        # block, the two F_uvt slices and the two F_ut / F_vt time columns around t, the
+        # decoder) plus the FP16 RGB out, against the decoder's flops at the FP16 MFMA peak
+        d = models[0].desc
+        hid = d.hidden
+        blk = 1 if codec else 2                                      # bytes per texel of a BC7 / 4 x BC4 map
+        in_b = 64 * (d.W * d.H * blk + 2 * d.Gu * d.Gv * blk + 2 * 2 * (d.U + d.V) + 2 * I.hybrid_mlp_size(hid))
+        flop = 64 * R * R * 2 * (16 * hid + hid * hid + 3 * hid)
+        t_h, t_m = (in_b + 64 * R * R * 6) / (HBM_PEAK_GBS * 1e9), flop / (MFMA_F16_PEAK_TFLOPS * 1e12)
+        row["roofline_f16"] = dict(bound="hbm" if t_h >= t_m else "mfma", bytes_per_launch=in_b + 64 * R * R * 6,
+                                   flop_per_launch=flop, frac=max(t_h, t_m) / (row["f16_ms"] * 1e-3),
+                                   achieved=(in_b + 64 * R * R * 6) / (row["f16_ms"] * 1e-3) / 1e9, unit="GB/s",
+                                   peak=HBM_PEAK_GBS, traffic=None)
         key = prof + ("" if codec else ".bc4") + (f".border{border}" if border else "")
         log(f"hybrid 1024^2 {key}: FP16 {row['f16_ms'] * 1e3:.1f} us, FP32 {row['f32_ms'] * 1e3:.1f} us")
         out[key] = row
@@ -299,8 +381,17 @@ def run_hybrid_train(args, torch, N, I, ctx, steps=10, warm=3):
     torch.cuda.synchronize()
     ms = sorted(tm.ms())[steps // 2]
     log(f"hybrid train, 64 tile models x 4096 samples: {ms:.3f} ms/step ({M * Bm / ms / 1e3:.1f} M samples/s)")
+    # algorithmic bytes of a step: per sample 4 B of index and 6 B of target, FP32 reads of the
+    # parameters it touches (F_uv footprint: 8 endpoints + 1 weight; F_uvt: 4 taps x 2 slices x
+    # (8 endpoints + 1 weight); F_ut / F_vt: 2 planes x 2 positions x 2 times x 2 channels) and
+    # the read-modify-write of their gradients; dense Adam at 32 B per parameter
+    touched = (8 + 1) + 4 * 2 * (8 + 1) + 2 * 2 * 2 * 2
+    step_bytes = M * Bm * (10 + 3 * 4 * touched) + int(tr.n_params) * 32
+    rl = dict(bound="hbm", achieved=step_bytes / (ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s", traffic=None,
+              bytes_per_launch=step_bytes, kernel="ndgi_hybrid_train_step FUSED (k_hybrid_train, k_adam)")
+    rl["frac"] = rl["achieved"] / HBM_PEAK_GBS
     return dict(ms_per_step=ms, samples_per_s=M * Bm / (ms * 1e-3), models=M, per_model=Bm, profile="M", codec="bc7",
-                params=int(tr.n_params), loss=float(tr.loss.item()))
+                params=int(tr.n_params), loss=float(tr.loss.item()), roofline=rl)
 
 
 def run_c4(args, torch, N, I, ctx, steps=None, warm=3):
@@ -332,38 +423,127 @@ def run_c4(args, torch, N, I, ctx, steps=None, warm=3):
     ms = sum(tm.ms()) / steps
     loss = float(tr.loss.item())
     log(f"C4 train: {ms:.3f} ms/step, {B / ms / 1e6:.3f} G samples/s, loss {loss:.4e}")
-    return dict(ms_per_step=ms, samples_per_s=B / (wall / steps), batch=B, params=int(tr.n_params), loss=loss)
+    # algorithmic bytes of a step: per sample 4 B of index, 6 B of target, 224 B of gathered
+    # parameters (8 channels x (2 endpoints + 1 weight) + 4 grid nodes x 8 channels, FP32) and
+    # 448 B of atomic read-modify-write on their gradients; dense Adam reads parameter,
+    # gradient, m, v and writes all four (32 B per parameter)
+    n_par = int(tr.n_params)
+    step_bytes = B * (4 + 6 + 224 + 448) + n_par * 32
+    rl = dict(bound="hbm", achieved=step_bytes / (ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s", traffic=None,
+              kernel="ndgi_train_step FUSED (k_train, partial-row reduction, k_adam)", bytes_per_launch=step_bytes)
+    rl["frac"] = rl["achieved"] / HBM_PEAK_GBS
+    tgt_np = tgt.cpu().numpy()
+    oracle_state = ({kk: np.asarray(st[kk], np.float64) for kk in ("endpoints", "weights", "grid", "mlp")}
+                    | {"dims": st["dims"]}, lambda x, y, k: tgt_np[k, y, x].astype(np.float64))
+    return (dict(ms_per_step=ms, samples_per_s=B / (wall / steps), batch=B, params=n_par, loss=loss, roofline=rl),
+            oracle_state)
 
 
-def cpu_baseline(args, dm, q, seconds):
-    """The CPU oracle decoding a bounded sample of the same workload on this host."""
-    import numpy as np
+def _host_cpu():
+    """Cores this process may run on (capped at 16, the host share of one GPU here) and the CPU
+    model."""
+    cores = len(os.sched_getaffinity(0))
+    model = "unknown"
     try:
-        from threadpoolctl import threadpool_limits
-    except Exception:
-        threadpool_limits = None
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return cores, min(cores, 16), model
+
+
+_POOL_MODEL = None
+
+
+def _pool_chunk(a):
+    """Worker of the multi-process oracle: decode one chunk of the shared query array."""
+    from threadpoolctl import threadpool_limits
     from oracle import ndgi_oracle as O
+    model, qs, chunk = _POOL_MODEL
+    with threadpool_limits(limits=1):
+        O.decode(model, qs[a * chunk:(a + 1) * chunk])
+    return chunk
+
+
+def cpu_baseline(args, dm, q, seconds, c4_state=None):
+    """The CPU oracle (FP64 numpy, as it stands) on bounded samples of the same workload on
+    this host: (i) one process with BLAS pinned to 1 thread and (ii) worker processes over the
+    host cores (forked from this process; they only run numpy), on the first 2^20 random
+    queries; the frame subsample (2^20 texel centres at stride 16) and the C1 set in mode (i);
+    and the training oracle's gradient on a 2^12-sample C4 batch."""
+    import multiprocessing as mp
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import ndgi_oracle as O
+    global _POOL_MODEL
+    n_aff, n_use, cpu_model = _host_cpu()
     model = dict(W=W, H=H, Gw=GW, Gh=GH, T=T, bc4=dm.bc4.cpu().numpy(), grid=dm.grid.cpu().numpy(),
                  mlp=dm.mlp.cpu().numpy())
     qs = q[: 1 << 20].cpu().numpy()
     chunk = 1 << 15
-    done = 0
-    t0 = time.perf_counter()
-    ctxm = threadpool_limits(limits=1) if threadpool_limits else None
-    try:
+    nchunks = (1 << 20) // chunk
+    res = {}
+
+    def timed(fn, budget):
+        done, t0 = 0, time.perf_counter()
         while True:
-            a = (done // chunk) % ((1 << 20) // chunk)
+            done += fn(done)
+            if time.perf_counter() - t0 >= budget:
+                return done, time.perf_counter() - t0
+
+    with threadpool_limits(limits=1):
+        # (i) random queries, one thread
+        def rnd(done):
+            a = (done // chunk) % nchunks
             O.decode(model, qs[a * chunk:(a + 1) * chunk])
-            done += chunk
-            if time.perf_counter() - t0 >= seconds:
-                break
-    finally:
-        if ctxm is not None:
-            ctxm.__exit__(None, None, None)
-    el = time.perf_counter() - t0
-    return dict(value=done / el, unit="texels/s", cores=1, kind="oracle",
-                sample=f"{done} of the workload's uniform random queries (chunks of {chunk}), FP64 numpy, "
-                       f"1 thread, {el:.1f} s")
+            return chunk
+        done, el = timed(rnd, 0.5 * seconds)
+        res["random_1thread_queries_per_s"] = done / el
+        # frame subsample: 2^20 texel centres at stride 16 (t of the frame), one thread
+        sel = np.arange(0, W * H, 16)
+        xs, ys = sel % W, sel // W
+        tf = np.float64(np.float32(0.3711))
+
+        def frame(done):
+            a = (done // chunk) % nchunks
+            xx, yy = xs[a * chunk:(a + 1) * chunk], ys[a * chunk:(a + 1) * chunk]
+            O.decode_f64(model, (xx + 0.5) / W, (yy + 0.5) / H, np.full(xx.size, tf))
+            return chunk
+        done, el = timed(frame, 0.2 * seconds)
+        res["frame_1thread_texels_per_s"] = done / el
+        # C1 set (64^2 map, all texel centres at 8 times), one thread
+        from paper_2604_12625_amd import inputs as I
+        m1 = I.random_model(64, 64, 16, 16, 8, np.float32, np.float32, config=1)
+        q1 = I.texel_centre_queries(64, 64, I.rng(1, I.P_QUERY).random(8, dtype=np.float32))
+        t0 = time.perf_counter()
+        O.decode(m1, q1)
+        res["c1_1thread_s"] = time.perf_counter() - t0
+        # training oracle: gradient of one 2^12-sample batch on the C4 state
+        if c4_state is not None:
+            st, tgt_fn = c4_state
+            x, y, k = I.train_samples(1 << 12, 1024, 1024, T, I.rng(4, I.P_SAMPLES, 99))
+            t0 = time.perf_counter()
+            O.train_grads(st, x, y, k, tgt_fn(x, y, k))
+            el = time.perf_counter() - t0
+            res["train_1thread_us_per_sample"] = 1e6 * el / (1 << 12)
+    # (ii) random queries over the host cores
+    _POOL_MODEL = (model, qs, chunk)
+    per = max(1, int(0.3 * seconds * res["random_1thread_queries_per_s"] / chunk))   # ~0.3 s-budget per worker
+    jobs = [a % nchunks for a in range(per * n_use)]
+    with mp.get_context("fork").Pool(n_use) as pool:
+        t0 = time.perf_counter()
+        done = sum(pool.map(_pool_chunk, jobs, chunksize=1))
+        el = time.perf_counter() - t0
+    _POOL_MODEL = None
+    res["random_multiproc_queries_per_s"] = done / el
+    return dict(value=res["random_multiproc_queries_per_s"], unit="texels/s", cores=n_use, kind="oracle",
+                sample=f"{done} decodes cycling over the workload's first 2^20 uniform random queries (chunks of "
+                       f"{chunk}) in {n_use} worker processes, FP64 numpy, BLAS 1 thread each, {el:.1f} s; host "
+                       f"{cpu_model}, {n_aff} cores in this process's affinity",
+                host_cpu=cpu_model, host_cores=n_aff, modes=res)
 
 
 def main():
@@ -466,18 +646,20 @@ def main():
         "fp16_over_fp32": value / fp32_value,
     }
     res["config"]["launch_shape"] = c2["launch_shape"]
+    res["c1"] = run_c1(args, torch, N, I, ctx)
+    c4_state = None
     if not args.headline_only:
         ctx3 = N.Context(0)
         res["vt_frame"] = run_c3(args, torch, N, I, ctx3)
         ctx3.close()
         res["hybrid_1024_tiles"] = run_hybrid(args, torch, N, I, ctx)
         res["hybrid_train_64_tiles"] = run_hybrid_train(args, torch, N, I, ctx)
-        c4 = run_c4(args, torch, N, I, ctx)
+        c4, c4_state = run_c4(args, torch, N, I, ctx)
         res["train_texels_per_s"] = c4["samples_per_s"]
         res["train"] = c4
     if not args.no_cpu_baseline:
         log("CPU oracle baseline ...")
-        res["cpu_baseline"] = cpu_baseline(args, dm, q, args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(args, dm, q, args.cpu_seconds, c4_state)
     print(json.dumps(res), flush=True)
     ctx.close()
 
