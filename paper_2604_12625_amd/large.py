@@ -101,12 +101,24 @@ def run_c5(args, torch, N, I, ctx, steps: int | None = None, batch: int = BATCH)
                              for k in range(T)])
         ps = ctx.psnr(stats, W, H, TILE)
         tiled, glob = ps["tiled"], ps["global"]
-        db = ps["tile_db"].cpu().numpy().ravel()
-        db = db[~np.isnan(db)]
+        db_all = ps["tile_db"].cpu().numpy().ravel()
+        st = stats.cpu().numpy().reshape(-1, 3)
+        rng_all = st[:, 0] - st[:, 1]                     # per tile: max - min of the target
+        ok = ~np.isnan(db_all)
+        db, rng = db_all[ok], rng_all[ok]
+        # tile PSNR by the tile's dynamic range (the tiled mean weighs every tile equally, so
+        # near-constant dark tiles with a tiny range dominate it)
+        edges = [0.0, 0.01, 0.1, 1.0, 10.0, np.inf]
+        by_range = []
+        for lo, hi in zip(edges[:-1], edges[1:]):
+            sel = (rng >= lo) & (rng < hi)
+            if sel.any():
+                by_range.append(dict(range_lo=lo, range_hi=None if np.isinf(hi) else hi, tiles=int(sel.sum()),
+                                     mean_db=float(db[sel].mean()), p10_db=float(np.quantile(db[sel], 0.1))))
         res[name] = dict(decode_ms_all_keys=ms, decode_texels_per_s=T * W * H / (ms * 1e-3),
                          psnr_tiled_db=tiled, psnr_global_db=glob, psnr_tile_min_db=ps["min"],
                          psnr_tile_quantiles_db={q: float(np.quantile(db, q)) for q in (0.01, 0.1, 0.5, 0.9)},
-                         tiles_scored=ps["scored"], tiles=ps["tiles"])
+                         psnr_by_tile_range=by_range, tiles_scored=ps["scored"], tiles=ps["tiles"])
         _log(f"C5 decode {name}: {ms:.2f} ms for {T} keys ({T * W * H / ms / 1e6:.1f} G texels/s), "
              f"PSNR tiled {tiled:.2f} dB, global {glob:.2f} dB")
         del dst
