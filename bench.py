@@ -115,6 +115,7 @@ def c2_inputs(torch, N, I):
 def run_c2(args, torch, N, I, ctx):
     from paper_2604_12625_amd.autotune import tune_pages
     dm, marr, rq, nreq, n_pages, q = c2_inputs(torch, N, I)
+    plain = N.Context(0)   # no reserved workspace: ndgi_decode's query-order pass
     out = {}
     tune_dst = torch.empty((W * H, 3), dtype=torch.float16, device="cuda")
     shape, timings = tune_pages(ctx, lambda: ctx.decode_pages(marr, 1, rq, nreq, n_pages, PAGE, tune_dst, W,
@@ -126,14 +127,18 @@ def run_c2(args, torch, N, I, ctx):
         dt = torch.float16 if prec == N.PREC_F16 else torch.float32
         frame = torch.empty((W * H, 3), dtype=dt, device="cuda")
         rnd = torch.empty((N_RANDOM, 3), dtype=dt, device="cuda")
-        # the binned decode's workspace is allocated once, outside the timed region
+        # workspaces are reserved once, outside the timed region: the context's for ndgi_decode
+        # (which then takes the binned kernels), a caller buffer for ndgi_decode_binned
         ws = torch.empty(ctx.binned_workspace_bytes(dm, N_RANDOM), dtype=torch.uint8, device="cuda")
+        ctx.reserve_decode(dm, N_RANDOM)
 
         def random_leg():
-            if args.random_path == "binned":
+            if args.random_path == "decode":
+                ctx.decode(dm, q, prec, out=rnd)
+            elif args.random_path == "binned":
                 ctx.decode_binned(dm, q, prec, out=rnd, workspace=ws)
             else:
-                ctx.decode(dm, q, prec, out=rnd)
+                plain.decode(dm, q, prec, out=rnd)
 
         def step(tf=None, tr=None):
             e = tf.start() if tf else None
@@ -157,21 +162,20 @@ def run_c2(args, torch, N, I, ctx):
         wall = time.perf_counter() - t0
         fm, rm = tf.ms(), tr.ms()
         out[name] = dict(steps=steps, wall_s=wall, frame_ms=sum(fm) / len(fm), random_ms=sum(rm) / len(rm))
-        # the other random-access path on the same queries, for comparison (not in the step)
-        other = "direct" if args.random_path == "binned" else "binned"
+        # the query-order pass on the same queries (a context with no reservation), for
+        # comparison (not in the step)
         to = Timer(torch)
         for _ in range(3):
             e = to.start()
-            if other == "binned":
-                ctx.decode_binned(dm, q, prec, out=rnd, workspace=ws)
-            else:
-                ctx.decode(dm, q, prec, out=rnd)
+            plain.decode(dm, q, prec, out=rnd)
             to.stop(e)
         torch.cuda.synchronize()
-        out[name][f"random_{other}_ms"] = sorted(to.ms())[1]
+        out[name]["random_direct_ms"] = sorted(to.ms())[1]
         log(f"C2 {name}: {1e3 * wall / steps:.3f} ms/step (frame {out[name]['frame_ms']:.3f} ms, "
             f"random {out[name]['random_ms']:.3f} ms)")
         del frame, rnd, ws
+    ctx.reserve_decode(None, 0)
+    plain.close()
     return out, (dm, q)
 
 
@@ -556,8 +560,10 @@ def main():
                     help="block format of F_uv / F_uvt for the hfit and hmap workloads")
     ap.add_argument("--border", type=int, default=4, help="mirrored tile border (texels) of the hmap workload")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--random-path", default="binned", choices=["binned", "direct"],
-                    help="decode of the random queries: tile-binned (default) or in arrival order")
+    ap.add_argument("--random-path", default="decode", choices=["decode", "binned", "direct"],
+                    help="decode of the random queries: ndgi_decode with a reserved context workspace (the "
+                         "binned kernels; default), ndgi_decode_binned with a caller workspace, or ndgi_decode "
+                         "without a reservation (one pass in query order)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--headline-only", action="store_true", help="skip the VT, hybrid and training legs")
     ap.add_argument("--hybrid-only", action="store_true", help="only the hybrid-layout decode leg")
@@ -617,9 +623,11 @@ def main():
     rl_frame["frac"] = rl_frame["achieved"] / HBM_PEAK_GBS
     rl_rand = dict(bound="hbm", achieved=RANDOM_COMPULSORY_BYTES / (f16["random_ms"] * 1e-3) / 1e9,
                    peak=HBM_PEAK_GBS, unit="GB/s",
-                   traffic=measured_traffic("random_f16_" + args.random_path),
-                   kernel=("ndgi_decode_binned (k_bin_count, k_bin_colscan, k_bin_starts, k_bin_scatter, "
-                           "k_decode_binned_lds<FP16>)" if args.random_path == "binned" else "k_decode_query<FP16>"),
+                   traffic=measured_traffic("random_f16_" + ("direct" if args.random_path == "direct" else "binned")),
+                   kernel=("k_decode_query<FP16>" if args.random_path == "direct" else
+                           ("ndgi_decode with a reserved workspace -> " if args.random_path == "decode" else
+                            "ndgi_decode_binned -> ") +
+                           "k_bin_count, k_bin_colscan, k_bin_starts, k_bin_scatter, k_decode_binned_lds<FP16>"),
                    bytes_per_launch=RANDOM_COMPULSORY_BYTES)
     rl_rand["frac"] = rl_rand["achieved"] / HBM_PEAK_GBS
     # HBM rate the kernels actually drive: counter bytes per launch over the live launch time

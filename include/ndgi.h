@@ -183,9 +183,23 @@ int ndgi_bc7_encode_blocks(const uint8_t* texels, int64_t n, uint8_t* out, hipSt
  *        A query with a non-finite coordinate decodes to NaN.
  *   out: device [n][3]; float if prec == NDGI_PREC_F32, _Float16 if NDGI_PREC_F16.
  *   model: host pointer to a descriptor whose buffers are device memory.
+ * With a workspace reserved by ndgi_reserve_decode that holds the binned layout for (model,
+ * n), and at least 100 queries per 32 x 32-texel tile on average, the call runs the binned
+ * kernels of ndgi_decode_binned (the same result bit for bit); otherwise one pass in query
+ * order.
  * n = 0 is a no-op.  Errors: INVALID_ARG (bad descriptor, sizes, prec, NULL buffers). */
 int ndgi_decode(ndgi_ctx* ctx, const ndgi_model* model, const float* uvt, int64_t n,
                 void* out, int32_t prec, hipStream_t stream);
+
+/* Reserve (allocate, once) the context's decode workspace for up to max_queries queries on
+ * maps of model's sizes, so that later ndgi_decode calls with many queries per tile take the
+ * binned kernels (Sec. 3.3 "random access" at batch scale) without allocating.  A
+ * reservation that already holds the layout is kept; a larger one replaces it (the device
+ * is synchronised before the old one is freed); max_queries = 0 releases it (model may then
+ * be NULL).  Call it when no decode of this context is in flight.
+ * Errors: INVALID_ARG (ctx NULL, bad descriptor, max_queries out of [0, 2^31)), UNSUPPORTED
+ * (maps the binned kernels do not take), OUT_OF_MEMORY, HIP. */
+int ndgi_reserve_decode(ndgi_ctx* ctx, const ndgi_model* model, int64_t max_queries);
 
 /* Binned random-access decode: the same result as ndgi_decode, bit for bit, for the same
  * queries (Sec. 3.1 Eq. 3; Sec. 3.3 "random access"), reached by first counting-sorting the

@@ -178,6 +178,7 @@ int ndgi_destroy(ndgi_ctx* c) {
   hipFree(c->partials_dev);
   hipFree(c->loss_part_dev);
   hipFree(c->stage_dev);
+  hipFree(c->dec_ws);
   delete c;
   return NDGI_OK;
 }
@@ -230,7 +231,43 @@ int ndgi_decode(ndgi_ctx* c, const ndgi_model* m, const float* uvt, int64_t n, v
   if (rc) return rc;
   if (n == 0) return NDGI_OK;
   if (!uvt || !out) return fail(NDGI_ERR_INVALID_ARG, "decode: NULL query/output pointer");
+  if (c->dec_ws && binned_route(*m, n, c->dec_ws_bytes))
+    return launch_decode_binned(c, *m, uvt, n, out, prec, c->dec_ws, c->dec_ws_bytes, s);
   return launch_decode(c, *m, uvt, n, out, prec, s);
+}
+
+int ndgi_reserve_decode(ndgi_ctx* c, const ndgi_model* m, int64_t max_queries) {
+  clear_error();
+  if (!c) return fail(NDGI_ERR_INVALID_ARG, "reserve_decode: ctx is NULL");
+  if (max_queries < 0 || max_queries > INT32_MAX)
+    return fail(NDGI_ERR_INVALID_ARG, "reserve_decode: max_queries out of [0, 2^31)");
+  if (max_queries == 0) {
+    if (c->dec_ws) {
+      NDGI_HIP(hipSetDevice(c->device));
+      NDGI_HIP(hipDeviceSynchronize());   // no decode of this context may still use it
+      NDGI_HIP(hipFree(c->dec_ws));
+    }
+    c->dec_ws = nullptr;
+    c->dec_ws_bytes = 0;
+    return NDGI_OK;
+  }
+  int rc = check_model(m, "reserve_decode");
+  if (rc) return rc;
+  int64_t need = 0;
+  rc = binned_workspace(*m, max_queries, &need);
+  if (rc) return rc;
+  if (need <= c->dec_ws_bytes) return NDGI_OK;   // the current reservation already holds it
+  NDGI_HIP(hipSetDevice(c->device));
+  void* p = nullptr;
+  if (hipMalloc(&p, (size_t)need) != hipSuccess)
+    return fail(NDGI_ERR_OUT_OF_MEMORY, "reserve_decode: %lld bytes", (long long)need);
+  if (c->dec_ws) {
+    NDGI_HIP(hipDeviceSynchronize());
+    NDGI_HIP(hipFree(c->dec_ws));
+  }
+  c->dec_ws = p;
+  c->dec_ws_bytes = need;
+  return NDGI_OK;
 }
 
 int ndgi_decode_binned_workspace(const ndgi_model* m, int64_t n, int64_t* bytes_out) {

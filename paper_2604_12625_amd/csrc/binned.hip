@@ -660,6 +660,12 @@ static bool binned_layout(const ndgi_model& m, int64_t n, BinnedLayout& L) {
   return true;
 }
 
+bool binned_route(const ndgi_model& m, int64_t n, int64_t ws_bytes) {
+  BinnedLayout L;
+  if (n <= 0 || n > INT32_MAX || !binned_layout(m, n, L)) return false;
+  return n >= kRouteQueriesPerTile * L.nbins && L.bytes <= ws_bytes;
+}
+
 int binned_workspace(const ndgi_model& m, int64_t n, int64_t* bytes) {
   BinnedLayout L;
   if (!binned_layout(m, n, L))

@@ -43,6 +43,8 @@ struct ndgi_ctx {
   hipStream_t capture_stream = nullptr;
   uint32_t* flags_dev = nullptr;
   void* scratch_dev = nullptr;   // this device's copy of the static scratch of decode_binned_noalloc
+  void* dec_ws = nullptr;        // workspace reserved by ndgi_reserve_decode (binned route of ndgi_decode)
+  int64_t dec_ws_bytes = 0;
   // training workspace
   int train_waves = 0;          // persistent waves of the training kernel
   float* partials_dev = nullptr;  // [train_waves][kPartialStride]
@@ -77,6 +79,11 @@ int launch_bc4_blocks(const uint8_t* blocks, int64_t n, uint8_t* out, int impl, 
 int launch_bc7_blocks(const uint8_t* blocks, int64_t n, uint8_t* out, hipStream_t s);
 int launch_import_map(const uint8_t* blocks, int codec, int W, int H, int S, float* w, int n_cu, hipStream_t s);
 int binned_workspace(const ndgi_model& m, int64_t n, int64_t* bytes);
+// Whether ndgi_decode takes the binned kernels for n queries on m with a reserved workspace
+// of ws_bytes: the map bins, there are at least kRouteQueriesPerTile queries per tile on
+// average, and the workspace holds the layout.
+constexpr int64_t kRouteQueriesPerTile = 100;
+bool binned_route(const ndgi_model& m, int64_t n, int64_t ws_bytes);
 int launch_decode_binned(ndgi_ctx* ctx, const ndgi_model& m, const float* uvt, int64_t n, void* out, int prec,
                          void* ws, int64_t ws_bytes, hipStream_t s);
 int check_hybrid(const ndgi_hybrid_model* m, const char* who);

@@ -24,7 +24,7 @@ EXPORTED = (
     "ndgi_create", "ndgi_destroy", "ndgi_last_error", "ndgi_get_error_flags",
     "ndgi_bc4_decode_blocks", "ndgi_bc7_decode_blocks", "ndgi_decode", "ndgi_decode_pages", "ndgi_decode_pages_graph",
     "ndgi_set_launch", "ndgi_train_param_count", "ndgi_train_step", "ndgi_export",
-    "ndgi_tile_stats", "ndgi_decode_binned_workspace", "ndgi_decode_binned", "ndgi_decode_binned_noalloc",
+    "ndgi_tile_stats", "ndgi_decode_binned_workspace", "ndgi_decode_binned", "ndgi_decode_binned_noalloc", "ndgi_reserve_decode",
     "ndgi_hybrid_mlp_size", "ndgi_hybrid_decode", "ndgi_hybrid_decode_pages",
     "ndgi_hybrid_decode_pages_graph", "ndgi_hybrid_train_param_count", "ndgi_hybrid_train_step",
     "ndgi_hybrid_export", "ndgi_hybrid_normalize_target", "ndgi_hybrid_restore",
@@ -126,6 +126,7 @@ def lib():
         L.ndgi_decode_binned_workspace.argtypes = [C.POINTER(NdgiModel), i64, C.POINTER(i64)]
         L.ndgi_decode_binned.argtypes = [vp, C.POINTER(NdgiModel), vp, i64, vp, i32, vp, i64, vp]
         L.ndgi_decode_binned_noalloc.argtypes = [vp, C.POINTER(NdgiModel), vp, i64, vp, i32, vp]
+        L.ndgi_reserve_decode.argtypes = [vp, C.POINTER(NdgiModel), i64]
         L.ndgi_hybrid_mlp_size.argtypes = [i32]
         L.ndgi_hybrid_mlp_size.restype = i32
         L.ndgi_hybrid_decode.argtypes = [vp, C.POINTER(NdgiHybridModel), vp, i64, vp, i32, vp]
@@ -270,6 +271,12 @@ class Context:
                                        _ptr(workspace), workspace.numel(), _stream(stream)),
               "ndgi_decode_binned")
         return out, workspace
+
+    def reserve_decode(self, model, max_queries: int):
+        """Reserve the context's decode workspace (ndgi_reserve_decode): later decode() calls
+        with many queries per tile run the binned kernels; max_queries = 0 releases it."""
+        check(lib().ndgi_reserve_decode(self.h, C.byref(model.desc) if model is not None else None, max_queries),
+              "ndgi_reserve_decode")
 
     def decode_binned_noalloc(self, model: DeviceModel, uvt, out, prec=PREC_F16, stream=None):
         """Binned decode into the caller's `out` through the library's static scratch

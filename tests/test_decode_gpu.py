@@ -237,6 +237,43 @@ def test_binned_64_texel_tiles(N, ctx):
     del torch
 
 
+def test_reserved_decode_takes_the_binned_route(N):
+    """ndgi_decode on a context with a reserved workspace: at 100+ queries per tile it runs
+    the binned kernels, below that or when the reservation is too small the query-order pass;
+    every route gives the unreserved decode's bits, and the oracle's values on a sample."""
+    import torch
+    m = I.random_model(1024, 1024, 256, 256, 24, np.float16, np.float16, config=73)   # 1024 tiles
+    dm = N.DeviceModel.from_numpy(m)
+    plain = N.Context(0)
+    res = N.Context(0)
+    try:
+        q_big = torch.from_numpy(I.uniform_queries(300_000, I.rng(73, I.P_QUERY, 0))).cuda()   # 293 per tile
+        q_small = torch.from_numpy(I.uniform_queries(50_000, I.rng(73, I.P_QUERY, 1))).cuda()  # below 100 per tile
+        res.reserve_decode(dm, 300_000)
+        for prec, tol in ((1, TOL16), (0, TOL32)):
+            for q in (q_big, q_small):
+                want = plain.decode(dm, q, prec)
+                got = res.decode(dm, q, prec)
+                torch.cuda.synchronize()
+                assert torch.equal(got.view(torch.int16 if prec else torch.int32),
+                                   want.view(torch.int16 if prec else torch.int32)), (prec, q.shape[0])
+            sel = np.random.default_rng(73).integers(0, q_big.shape[0], 2048)
+            g = res.decode(dm, q_big, prec).float().cpu().numpy()
+            assert_rel(g[sel], O.decode(m, q_big.cpu().numpy()[sel]), tol, f"reserved prec {prec}")
+        # a reservation too small for the batch: the query-order pass, same bits
+        res.reserve_decode(None, 0)
+        res.reserve_decode(dm, 120_000)
+        got = res.decode(dm, q_big, 1)
+        want = plain.decode(dm, q_big, 1)
+        torch.cuda.synchronize()
+        assert torch.equal(got.view(torch.int16), want.view(torch.int16))
+        with pytest.raises(N.NdgiError):
+            res.reserve_decode(dm, -1)
+    finally:
+        plain.close()
+        res.close()
+
+
 def test_binned_argument_errors(N, ctx):
     import ctypes
     import torch
