@@ -119,21 +119,61 @@ struct TileLoads {
   uint32_t g0[2], g1[2];
 };
 
-__device__ __forceinline__ void tile_issue(const ndgi_model& m, const Keys& k, int x0, int y0, int lane, int db,
-                                           int dc, TileLoads& t) {
-  t.blk = *(const uint2*)(m.bc4 + ((size_t)(y0 >> 2) * (m.W >> 2) + (x0 >> 2) + db) * 64 + 8 * dc);
-  const int gx0 = (x0 >> 2) - 1, gy0 = (y0 >> 2) - 1;
-  const size_t plane = (size_t)m.Gh * m.Gw;
+// Addressing of a sub-tile's loads: the map's block and the two keys' grid planes as uniform
+// bases, and this lane's pass-invariant share (its block within a pass's four footprints and
+// its two grid window items).  Offsets are 32-bit: the model check bounds the map below 4 GiB
+// of blocks and the grid below 4 GiB.
+// The model's buffers are device memory: global address-space pointers let each load take a
+// uniform 64-bit base and a 32-bit lane offset (no 64-bit address arithmetic per lane).
+typedef const __attribute__((address_space(1))) uint8_t* gbyte_ptr;
+template <typename T>
+__device__ __forceinline__ T gload(gbyte_ptr base, uint32_t byte_off) {
+  return *(const __attribute__((address_space(1))) T*)(base + byte_off);
+}
+struct TileAddr {
+  gbyte_ptr bc4;        // the map's blocks
+  gbyte_ptr g0;         // grid of key k0: words of two FP16 channels
+  gbyte_ptr g1;         // key k1
+  int wb, gw, gw1, gh1;
+  uint32_t boff;        // byte offset of this lane's block in a pass: footprint db, channel dc
+  int nx[2], ny[2], pr[2];
+};
+
+__device__ __forceinline__ TileAddr tile_addr(const ndgi_model& m, const Keys& k, int lane, int db, int dc) {
+  TileAddr a;
+  const size_t plane_words = (size_t)m.Gh * m.Gw * 4;
+  a.bc4 = (gbyte_ptr)m.bc4;
+  a.g0 = (gbyte_ptr)m.grid + (size_t)k.k0 * plane_words * 4;
+  a.g1 = (gbyte_ptr)m.grid + (size_t)k.k1 * plane_words * 4;
+  a.wb = m.W >> 2;
+  a.gw = m.Gw;
+  a.gw1 = m.Gw - 1;
+  a.gh1 = m.Gh - 1;
+  a.boff = (uint32_t)(db * 64 + 8 * dc);
 #pragma unroll
   for (int it = 0; it < 2; ++it) {
     const int item = it ? (lane < 8 ? lane + 64 : lane) : lane;   // items 64..71 on lanes 0..7
-    const int n = item >> 2, pr = item & 3;
-    const int ny = n / 6, nx = n - 6 * ny;
-    const int gx = min(max(gx0 + nx, 0), m.Gw - 1), gy = min(max(gy0 + ny, 0), m.Gh - 1);
-    const size_t node = (size_t)gy * m.Gw + gx;
-    const uint32_t* gp = (const uint32_t*)m.grid;
-    t.g0[it] = gp[((size_t)k.k0 * plane + node) * 4 + pr];
-    t.g1[it] = gp[((size_t)k.k1 * plane + node) * 4 + pr];
+    const int n = item >> 2;
+    a.pr[it] = item & 3;
+    a.ny[it] = n / 6;
+    a.nx[it] = n - 6 * a.ny[it];
+  }
+  return a;
+}
+
+// Global loads of the pass at texel (x0, y0): this lane's BC4 block and its grid window items
+// of both keys (node window from grid node (x0/4 - 1, y0/4 - 1), clamped to the grid).
+__device__ __forceinline__ void tile_issue(const TileAddr& a, int x0, int y0, TileLoads& t) {
+  const uint32_t bi = (uint32_t)((y0 >> 2) * a.wb + (x0 >> 2)) * 64u + a.boff;
+  const unsigned long long bw = gload<unsigned long long>(a.bc4, bi);
+  t.blk = make_uint2((uint32_t)bw, (uint32_t)(bw >> 32));
+  const int gx0 = (x0 >> 2) - 1, gy0 = (y0 >> 2) - 1;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const int gx = min(max(gx0 + a.nx[it], 0), a.gw1), gy = min(max(gy0 + a.ny[it], 0), a.gh1);
+    const uint32_t off = (((uint32_t)__umul24(gy, a.gw) + (uint32_t)gx) * 4u + (uint32_t)a.pr[it]) * 4u;
+    t.g0[it] = gload<uint32_t>(a.g0, off);
+    t.g1[it] = gload<uint32_t>(a.g1, off);
   }
 }
 
@@ -156,8 +196,9 @@ __device__ __forceinline__ void tile_subtile(const Dec16& dec, const ndgi_model&
   const uint8_t* sp8 = (const uint8_t*)L.sp;
   const int bx = page * rq.page_x + ox, by = page * rq.page_y + oy;
   const int np = tw * th;
+  const TileAddr ta = tile_addr(m, k, lane, db, dc);
   TileLoads cur;
-  tile_issue(m, k, bx, by, lane, db, dc, cur);
+  tile_issue(ta, bx, by, cur);
   for (int p = 0; p < np; ++p) {
     const int a = p % tw, b = p / tw;
     // stage this pass: time-blend the grid window, decode the BC4 rows
@@ -174,7 +215,7 @@ __device__ __forceinline__ void tile_subtile(const Dec16& dec, const ndgi_model&
     L.sp[dc * 20 + (2 * drp + 1) * 4 + db] = row1;
     if (p + 1 < np) {
       const int a1 = (p + 1) % tw, b1 = (p + 1) / tw;
-      tile_issue(m, k, bx + 16 * a1, by + 4 * b1, lane, db, dc, cur);
+      tile_issue(ta, bx + 16 * a1, by + 4 * b1, cur);
     }
     wave_sync();
     f4v acc = dec.c3;
