@@ -197,6 +197,9 @@ __device__ __forceinline__ void tile_subtile(const Dec16& dec, const ndgi_model&
   const int bx = page * rq.page_x + ox, by = page * rq.page_y + oy;
   const int np = tw * th;
   const TileAddr ta = tile_addr(m, k, lane, db, dc);
+  // this lane's output texel (row g, column j) of the sub-tile's first pass; later passes add
+  // a uniform offset
+  _Float16* const out0 = (_Float16*)dst + (rq.dst_offset + (int64_t)(oy + g) * pitch + (ox + j)) * 3;
   TileLoads cur;
   tile_issue(ta, bx, by, cur);
   for (int p = 0; p < np; ++p) {
@@ -206,7 +209,10 @@ __device__ __forceinline__ void tile_subtile(const Dec16& dec, const ndgi_model&
     for (int it = 0; it < 2; ++it) {
       if (it == 0 || lane < 8) {
         const float2 v0 = half2_bits(cur.g0[it]), v1 = half2_bits(cur.g1[it]);
-        L.gt[it ? lane + 64 : lane] = make_float2(fmaf(k.w1, v1.x, k.w0 * v0.x), fmaf(k.w1, v1.y, k.w0 * v0.y));
+        // w0 v0 as an FMA with a zero addend: one mixed-precision FMA on the FP16 word (the
+        // same rounded product)
+        L.gt[it ? lane + 64 : lane] =
+            make_float2(fmaf(k.w1, v1.x, fmaf(k.w0, v0.x, 0.0f)), fmaf(k.w1, v1.y, fmaf(k.w0, v0.y, 0.0f)));
       }
     }
     uint32_t row0, row1;
@@ -233,8 +239,7 @@ __device__ __forceinline__ void tile_subtile(const Dec16& dec, const ndgi_model&
       dec16_group(dec, texel_x(spair, ga, gb), q, acc);
     }
     wave_sync();
-    const int64_t di = rq.dst_offset + (int64_t)(oy + 4 * b + g) * pitch + (ox + 16 * a + j);
-    store_rgb<NDGI_PREC_F16>(dst, (size_t)di, acc, false);
+    store_rgb<NDGI_PREC_F16>(out0 + ((int64_t)(4 * b) * pitch + 16 * a) * 3, 0, acc, false);
   }
 }
 
