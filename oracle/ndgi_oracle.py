@@ -317,23 +317,149 @@ def bc7m6_decode_block(block) -> np.ndarray:
     return out
 
 
+def _bc7_take(B, pos, n):
+    """Bits pos .. pos + n - 1 (n <= 8) of each block of B [..., 17] (bytes, int64, padded)."""
+    pos = np.broadcast_to(np.asarray(pos, dtype=np.int64), B.shape[:-1])
+    byte = (pos >> 3)[..., None]
+    lo = np.take_along_axis(B, byte, -1)[..., 0]
+    hi = np.take_along_axis(B, np.minimum(byte + 1, 16), -1)[..., 0]
+    return ((lo | (hi << 8)) >> (pos & 7)) & ((1 << n) - 1)
+
+
 def bc7_texels(blocks: np.ndarray, xs, ys) -> np.ndarray:
-    """Vectorised decode of texels (xs, ys) from their selected 16-byte blocks [..., 16] -> [..., 4]."""
+    """Vectorised decode of texels (xs, ys) from their selected 16-byte blocks [..., 16] -> [..., 4]
+    (modes 4, 5 and 6; zeros for other modes), as bc7_decode_block."""
     blocks = np.asarray(blocks, dtype=np.uint8)
-    lo = np.zeros(blocks.shape[:-1], dtype=np.uint64)
-    hi = np.zeros(blocks.shape[:-1], dtype=np.uint64)
-    for k in range(8):
-        lo |= blocks[..., k].astype(np.uint64) << np.uint64(8 * k)
-        hi |= blocks[..., 8 + k].astype(np.uint64) << np.uint64(8 * k)
-    v = [((lo >> np.uint64(7 + 7 * k)) & np.uint64(0x7F)).astype(np.int64) for k in range(8)]
-    p0 = ((lo >> np.uint64(63)) & np.uint64(1)).astype(np.int64)
-    p1 = (hi & np.uint64(1)).astype(np.int64)
-    slot = (4 * (np.asarray(ys) & 3) + (np.asarray(xs) & 3)).astype(np.uint64)
-    idx = np.where(slot == 0, (hi >> np.uint64(1)) & np.uint64(7), (hi >> (np.uint64(4) * slot)) & np.uint64(0xF))
-    w = np.asarray(BC7_WEIGHTS4, dtype=np.int64)[idx.astype(np.int64)]
-    out = np.stack([((64 - w) * ((v[2 * c] << 1) | p0) + w * ((v[2 * c + 1] << 1) | p1) + 32) >> 6
-                    for c in range(4)], axis=-1)
+    B = np.concatenate([blocks, np.zeros(blocks.shape[:-1] + (1,), np.uint8)], axis=-1).astype(np.int64)
+    slot = (4 * (np.asarray(ys) & 3) + (np.asarray(xs) & 3)).astype(np.int64)
+    slot = np.broadcast_to(slot, B.shape[:-1])
+    b0 = B[..., 0]
+    mode = np.where(b0 & 0x10, 4, np.where(b0 & 0x20, 5, np.where(b0 & 0x40, 6, -1)))
+    mode = np.where(b0 & 0x0F, -1, mode)     # modes 0-3 (and 7 / reserved below) decode to 0
+
+    def idx(P, bits):     # the texel's index in a set starting at bit P
+        pos = np.where(slot == 0, P, P + bits - 1 + bits * (slot - 1))
+        return np.where(slot == 0, _bc7_take(B, pos, bits - 1), _bc7_take(B, pos, bits))
+
+    def expand(v, n):
+        return (v << (8 - n)) | (v >> (2 * n - 8)) if n < 8 else v
+
+    def lerp(e0, e1, w):
+        return ((64 - w) * e0 + w * e1 + 32) >> 6
+    W2, W3, W4 = (np.asarray(BC7_WEIGHTS[k], dtype=np.int64) for k in (2, 3, 4))
+    out = np.zeros(B.shape[:-1] + (4,), dtype=np.int64)
+    # mode 6
+    p0, p1 = _bc7_take(B, 63, 1), _bc7_take(B, 64, 1)
+    w6 = W4[idx(65, 4)]
+    m6 = np.stack([lerp((_bc7_take(B, 7 + 14 * c, 7) << 1) | p0, (_bc7_take(B, 14 + 14 * c, 7) << 1) | p1, w6)
+                   for c in range(4)], axis=-1)
+    # mode 5
+    wc5, wa5 = W2[idx(66, 2)], W2[idx(97, 2)]
+    m5 = np.stack([lerp(expand(_bc7_take(B, 8 + 14 * c, 7), 7), expand(_bc7_take(B, 15 + 14 * c, 7), 7), wc5)
+                   for c in range(3)] + [lerp(_bc7_take(B, 50, 8), _bc7_take(B, 58, 8), wa5)], axis=-1)
+    # mode 4
+    sel = _bc7_take(B, 7, 1)
+    w2, w3 = W2[idx(50, 2)], W3[idx(81, 3)]
+    wc4, wa4 = np.where(sel == 1, w3, w2), np.where(sel == 1, w2, w3)
+    m4 = np.stack([lerp(expand(_bc7_take(B, 8 + 10 * c, 5), 5), expand(_bc7_take(B, 13 + 10 * c, 5), 5), wc4)
+                   for c in range(3)] + [lerp(expand(_bc7_take(B, 38, 6), 6), expand(_bc7_take(B, 44, 6), 6), wa4)],
+                  axis=-1)
+    for m, val, rpos in ((4, m4, 5), (5, m5, 6)):
+        rot = _bc7_take(B, rpos, 2)
+        for r in (1, 2, 3):
+            sw = (rot == r)[..., None]
+            v2 = val.copy()
+            v2[..., r - 1], v2[..., 3] = val[..., 3], val[..., r - 1]
+            val = np.where(sw, v2, val)
+        out = np.where((mode == m)[..., None], val, out)
+    out = np.where((mode == 6)[..., None], m6, out)
     return out.astype(np.uint8)
+
+
+# --------------------------------------------------------------------------------------
+# BC7 modes 4, 5 and 6: the format's single-subset modes that carry four channels.  Modes 4
+# and 5 hold the colour (R, G, B) and alpha endpoints apart, each with its own index set,
+# and a 2-bit rotation swaps alpha with one colour channel after decoding (1: R, 2: G, 3:
+# B); mode 4 has 5-bit colour and 6-bit alpha endpoints, 2-bit and 3-bit indices (its index
+# selection bit gives the 3-bit set to colour when 1), mode 5 7-bit colour and 8-bit alpha
+# endpoints and 2-bit indices for both.  Fields in bit order from bit 0: the mode (m zero
+# bits then a one), then mode 4: rotation (2), selection (1), R0 R1 G0 G1 B0 B1 (5 each),
+# A0 A1 (6 each), the 2-bit index set (31 bits), the 3-bit set (47 bits); mode 5: rotation
+# (2), R0 .. B1 (7 each), A0 A1 (8 each), colour indices (31), alpha indices (31); mode 6
+# as above.  In every index set texel 0 drops its top bit (it is 0).  An n-bit endpoint
+# value v is the 8-bit (v << (8 - n)) | (v >> (2n - 8)); a texel is
+# ((64 - w) E0 + w E1 + 32) >> 6 with w from the b-bit weight table (64 j + (2^b - 1) / 2)
+# / (2^b - 1).  Reading: blocks of modes 0-3 and 7 (partitioned or RGB only) and the
+# reserved mode are not used by these feature maps and decode to zero texels.
+BC7_WEIGHTS = {2: (0, 21, 43, 64), 3: (0, 9, 18, 27, 37, 46, 55, 64), 4: BC7_WEIGHTS4}
+
+
+def bc7_mode(block) -> int:
+    """Mode of a 16-byte block (the number of zero bits before the first one), 8 if none."""
+    b0 = int(np.asarray(block, dtype=np.uint8)[0])
+    for m in range(8):
+        if (b0 >> m) & 1:
+            return m
+    return 8
+
+
+def _bc7_expand(v: int, n: int) -> int:
+    return ((v << (8 - n)) | (v >> (2 * n - 8))) if n < 8 else v
+
+
+def bc7_fields(block):
+    """(mode, rotation, E0 [4], E1 [4], colour indices [16], colour index bits, alpha indices
+    [16], alpha index bits) of a mode 4, 5 or 6 block, endpoints as 8-bit values in
+    R, G, B, A order before the rotation; None for any other mode."""
+    b = int.from_bytes(bytes(np.asarray(block, dtype=np.uint8)), "little")
+    m = bc7_mode(block)
+
+    def take(pos, n):
+        return (b >> pos) & ((1 << n) - 1)
+
+    def index_set(pos, bits):
+        out = [take(pos, bits - 1)]
+        pos += bits - 1
+        for _ in range(15):
+            out.append(take(pos, bits))
+            pos += bits
+        return out
+    if m == 6:
+        E0, E1, idx = bc7m6_fields(block)
+        return 6, 0, E0, E1, idx, 4, idx, 4
+    if m == 5:
+        rot = take(6, 2)
+        col = [take(8 + 7 * k, 7) for k in range(6)]
+        a0, a1 = take(50, 8), take(58, 8)
+        E0 = [_bc7_expand(col[2 * c], 7) for c in range(3)] + [a0]
+        E1 = [_bc7_expand(col[2 * c + 1], 7) for c in range(3)] + [a1]
+        return 5, rot, E0, E1, index_set(66, 2), 2, index_set(97, 2), 2
+    if m == 4:
+        rot, sel = take(5, 2), take(7, 1)
+        col = [take(8 + 5 * k, 5) for k in range(6)]
+        a0, a1 = _bc7_expand(take(38, 6), 6), _bc7_expand(take(44, 6), 6)
+        E0 = [_bc7_expand(col[2 * c], 5) for c in range(3)] + [a0]
+        E1 = [_bc7_expand(col[2 * c + 1], 5) for c in range(3)] + [a1]
+        i2, i3 = index_set(50, 2), index_set(81, 3)
+        return (4, rot, E0, E1, i3, 3, i2, 2) if sel else (4, rot, E0, E1, i2, 2, i3, 3)
+    return None
+
+
+def bc7_decode_block(block) -> np.ndarray:
+    """[16 texels][4 channels] uint8 of one BC7 block of mode 4, 5 or 6 (zeros otherwise)."""
+    f = bc7_fields(block)
+    out = np.zeros((16, 4), dtype=np.uint8)
+    if f is None:
+        return out
+    _, rot, E0, E1, ci, cb, ai, ab = f
+    for s_ in range(16):
+        wc, wa = BC7_WEIGHTS[cb][ci[s_]], BC7_WEIGHTS[ab][ai[s_]]
+        v = [((64 - wc) * E0[c] + wc * E1[c] + 32) >> 6 for c in range(3)]
+        v.append(((64 - wa) * E0[3] + wa * E1[3] + 32) >> 6)
+        if rot:
+            v[rot - 1], v[3] = v[3], v[rot - 1]
+        out[s_] = v
+    return out
 
 
 def bc7_quantise_endpoint(e4):
@@ -1237,6 +1363,198 @@ def encode_bc7m6(texels) -> np.ndarray:
         bits |= idx[0] << 65
         for s_ in range(1, 16):
             bits |= idx[s_] << (64 + 4 * s_)
+        out[i] = np.frombuffer(bits.to_bytes(16, "little"), dtype=np.uint8)
+    return out
+
+
+# BC7 with several modes (Sec. 3.4 compresses each block "using multiple modes"): every
+# block tries mode 6 (the search above), mode 5 under each of its 4 rotations and mode 4
+# under each rotation and both index selections, and keeps the candidate of least summed
+# squared error over its 16 texels and 4 channels (ties: mode 6, then mode 5 by rotation,
+# then mode 4 by rotation then selection).  A rotation r > 0 encodes the texels with channel
+# r - 1 and channel 3 exchanged (the decoder exchanges them back).  Modes 5 and 4 fit their
+# colour (3 channels) and alpha (1 channel) endpoints apart, each with the same fixed search
+# at its own endpoint precision n and index width b (mode 5: 7 / 2 and 8 / 2; mode 4: 5 / b
+# and 6 / b' with (b, b') = (2, 3), or (3, 2) under selection 1):
+#   1. endpoints at the bounding-box diagonal as in step 1 above (one channel: its minimum
+#      and maximum), each 8-bit target x quantised to the n-bit value whose expansion is
+#      nearest (ties to the lower value; the candidates are round(x (2^n - 1) / 255) and
+#      its two neighbours);
+#   2. twice: least-squares endpoints for the current indices as in step 3 above, quantised
+#      as in 1;
+#   3. best-improvement local search at step sizes 2^(n - 4), ..., 2, 1: each value of each
+#      endpoint -s and +s, then (several channels only) all values of one endpoint -s and
+#      +s, a move leaving 0 .. 2^n - 1 not taken, at most 64 rounds per step size;
+#   4. when texel 0's index has its top bit set, the endpoints swap and each index J becomes
+#      2^b - 1 - J (the weight tables are symmetric).
+# Every candidate's indices are refitted (each texel its least-error index, the lowest on
+# ties) and a candidate replaces the current one only when strictly better.
+def _bc7_q(x, n: int):
+    """n-bit values whose expansion is nearest to the 8-bit targets x (ties to the lower)."""
+    x = np.asarray(x, dtype=np.int64)
+    top = (1 << n) - 1
+    g = np.clip((x * top + 127) // 255, 0, top)
+    best, bd = None, None
+    for dv in (-1, 0, 1):
+        v = np.clip(g + dv, 0, top)
+        d = np.abs(((v << (8 - n)) | (v >> (2 * n - 8)) if n < 8 else v) - x)
+        if best is None:
+            best, bd = v, d
+        else:
+            t = (d < bd) | ((d == bd) & (v < best))
+            best, bd = np.where(t, v, best), np.where(t, d, bd)
+    return best
+
+
+def _bc7_x(v, n: int):
+    return ((v << (8 - n)) | (v >> (2 * n - 8))) if n < 8 else v
+
+
+def _sub_search(X, n: int, ib: int):
+    """The fixed search for one endpoint pair of n-bit values and b-bit indices over texels
+    X [nb][16][C] (8-bit): (v0 [nb][C], v1 [nb][C], J [nb][16], sse [nb])."""
+    nb, _, C = X.shape
+    rows = np.arange(nb)
+    Wt = np.asarray(BC7_WEIGHTS[ib], dtype=np.int64)
+    top = (1 << n) - 1
+    big = np.iinfo(np.int64).max
+    cur = dict(v0=np.zeros((nb, C), np.int64), v1=np.zeros((nb, C), np.int64), J=np.zeros((nb, 16), np.int64),
+               sse=np.full(nb, big))
+
+    def fit(v0, v1):
+        E0, E1 = _bc7_x(v0, n), _bc7_x(v1, n)
+        pal = ((64 - Wt)[None, :, None] * E0[:, None, :] + Wt[None, :, None] * E1[:, None, :] + 32) >> 6
+        d = ((pal[:, None, :, :] - X[:, :, None, :]) ** 2).sum(-1)
+        return d.argmin(-1), d.min(-1).sum(-1)
+
+    def take(v0, v1):
+        J, sse = fit(v0, v1)
+        t = sse < cur["sse"]
+        for k, val in (("v0", v0), ("v1", v1), ("J", J), ("sse", sse)):
+            cur[k] = np.where(t[:, None], val, cur[k]) if val.ndim == 2 else np.where(t, val, cur[k])
+    # 1
+    lo, hi = X.min(1), X.max(1)
+    if C > 1:
+        D = 16 * X - X.sum(1, keepdims=True)
+        ref = (D * D).sum(1).argmax(-1)
+        pos = (D * D[rows, :, ref][:, :, None]).sum(1) >= 0
+    else:
+        pos = np.ones((nb, 1), bool)
+    take(_bc7_q(np.where(pos, lo, hi), n), _bc7_q(np.where(pos, hi, lo), n))
+    # 2
+    for _ in range(2):
+        w = Wt[cur["J"]]
+        a, b = 64 - w, w
+        Aa, Bab, Cb = (a * a).sum(1), (a * b).sum(1), (b * b).sum(1)
+        r0, r1 = 64 * (a[:, :, None] * X).sum(1), 64 * (b[:, :, None] * X).sum(1)
+        det = Aa * Cb - Bab * Bab
+        ok = det > 0
+        dd = np.where(ok, det, 1)[:, None]
+        E0 = np.clip(np.floor_divide(2 * (Cb[:, None] * r0 - Bab[:, None] * r1) + dd, 2 * dd), 0, 255)
+        E1 = np.clip(np.floor_divide(2 * (Aa[:, None] * r1 - Bab[:, None] * r0) + dd, 2 * dd), 0, 255)
+        E0 = np.where(ok[:, None], E0, _bc7_x(cur["v0"], n))
+        E1 = np.where(ok[:, None], E1, _bc7_x(cur["v1"], n))
+        take(_bc7_q(E0, n), _bc7_q(E1, n))
+    # 3
+    for st in [1 << e for e in range(n - 4, -1, -1)]:
+        moves = [(k, c, dv) for k in (0, 1) for c in range(C) for dv in (-st, st)]
+        if C > 1:
+            moves += [(k, C, dv) for k in (0, 1) for dv in (-st, st)]
+        for _ in range(BC7_SEARCH_ROUNDS):
+            cand = []
+            for (k, c, dv) in moves:
+                v0, v1 = cur["v0"].copy(), cur["v1"].copy()
+                v = v0 if k == 0 else v1
+                cols = slice(None) if c == C else slice(c, c + 1)
+                v[:, cols] += dv
+                valid = ((v[:, cols] >= 0) & (v[:, cols] <= top)).all(1)
+                np.clip(v, 0, top, out=v)
+                J, sse = fit(v0, v1)
+                cand.append((np.where(valid, sse, big), v0, v1, J))
+            S = np.stack([c_[0] for c_ in cand], axis=1)
+            best = S.argmin(1)
+            better = S[rows, best] < cur["sse"]
+            if not better.any():
+                break
+            for i, (sse, v0, v1, J) in enumerate(cand):
+                t = better & (best == i)
+                for kk, val in (("v0", v0), ("v1", v1), ("J", J), ("sse", sse)):
+                    cur[kk] = np.where(t[:, None], val, cur[kk]) if val.ndim == 2 else np.where(t, val, cur[kk])
+    # 4
+    sw = cur["J"][:, 0] >= (1 << (ib - 1))
+    v0 = np.where(sw[:, None], cur["v1"], cur["v0"])
+    v1 = np.where(sw[:, None], cur["v0"], cur["v1"])
+    J = np.where(sw[:, None], (1 << ib) - 1 - cur["J"], cur["J"])
+    return v0, v1, J, cur["sse"]
+
+
+def _pack_set(bits: int, pos: int, J, b: int) -> tuple:
+    bits |= int(J[0]) << pos
+    pos += b - 1
+    for s_ in range(1, 16):
+        bits |= int(J[s_]) << pos
+        pos += b
+    return bits, pos
+
+
+def _bc7_rotated(X, r: int):
+    if r == 0:
+        return X
+    Y = X.copy()
+    Y[..., r - 1], Y[..., 3] = X[..., 3], X[..., r - 1]
+    return Y
+
+
+def encode_bc7(texels) -> np.ndarray:
+    """BC7 blocks [n][16] of 8-bit 4-channel texels [n][16][4] using modes 6, 5 and 4: the
+    per-block choice described above."""
+    X = np.asarray(texels, dtype=np.int64).reshape(-1, 16, 4)
+    nb = X.shape[0]
+    m6 = encode_bc7m6(X)
+    sse6 = ((np.stack([bc7m6_decode_block(b) for b in m6]).astype(np.int64) - X) ** 2).sum((1, 2))
+    best = [("m6", i) for i in range(nb)]
+    best_sse = sse6.copy()
+    cands = []
+    for r in range(4):
+        Y = _bc7_rotated(X, r)
+        cands.append((5, r, 0, _sub_search(Y[..., :3], 7, 2), _sub_search(Y[..., 3:], 8, 2)))
+    for r in range(4):
+        Y = _bc7_rotated(X, r)
+        for sel in (0, 1):
+            cb, ab = (2, 3) if sel == 0 else (3, 2)
+            cands.append((4, r, sel, _sub_search(Y[..., :3], 5, cb), _sub_search(Y[..., 3:], 6, ab)))
+    choice = np.full(nb, -1)
+    for ci, (_, _, _, col, alp) in enumerate(cands):
+        sse = col[3] + alp[3]
+        t = sse < best_sse
+        best_sse = np.where(t, sse, best_sse)
+        choice = np.where(t, ci, choice)
+    out = m6.copy()
+    for i in range(nb):
+        if choice[i] < 0:
+            continue
+        mode, r, sel, col, alp = cands[choice[i]]
+        cv0, cv1, cJ = col[0][i], col[1][i], col[2][i]
+        av0, av1, aJ = alp[0][i], alp[1][i], alp[2][i]
+        if mode == 5:
+            bits = (1 << 5) | (r << 6)
+            for c in range(3):
+                bits |= int(cv0[c]) << (8 + 14 * c)
+                bits |= int(cv1[c]) << (15 + 14 * c)
+            bits |= int(av0[0]) << 50
+            bits |= int(av1[0]) << 58
+            bits, _ = _pack_set(bits, 66, cJ, 2)
+            bits, _ = _pack_set(bits, 97, aJ, 2)
+        else:
+            bits = (1 << 4) | (r << 5) | (sel << 7)
+            for c in range(3):
+                bits |= int(cv0[c]) << (8 + 10 * c)
+                bits |= int(cv1[c]) << (13 + 10 * c)
+            bits |= int(av0[0]) << 38
+            bits |= int(av1[0]) << 44
+            s2, s3 = (cJ, aJ) if sel == 0 else (aJ, cJ)
+            bits, _ = _pack_set(bits, 50, s2, 2)
+            bits, _ = _pack_set(bits, 81, s3, 3)
         out[i] = np.frombuffer(bits.to_bytes(16, "little"), dtype=np.uint8)
     return out
 

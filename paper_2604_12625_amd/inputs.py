@@ -114,6 +114,16 @@ def random_bc7m6(shape, g: np.random.Generator) -> np.ndarray:
     return b
 
 
+def random_bc7(shape, g: np.random.Generator, modes=(4, 5, 6)) -> np.ndarray:
+    """Random BC7 blocks [*shape][16] of the given modes (drawn uniformly per block): uniform
+    bytes with the mode bits of byte 0 set (mode m: bits 0..m-1 clear, bit m set)."""
+    b = g.integers(0, 256, size=tuple(shape) + (16,), dtype=np.uint8)
+    m = np.asarray(modes)[g.integers(0, len(modes), size=tuple(shape))]
+    keep = (0xFF << (m + 1)) & 0xFF
+    b[..., 0] = ((b[..., 0] & keep) | (1 << m)).astype(np.uint8)
+    return b
+
+
 def random_hybrid_model(W: int = 128, H: int = 128, profile: str = "M", slices: int = 12,
                         plane=(64, 64, 24), mlp_dtype=np.float16, keys: bool = True,
                         config: int = 0, index: int = 0, uvt_side=None, codec: int = 0) -> dict:

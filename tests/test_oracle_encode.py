@@ -232,3 +232,105 @@ def test_direct_gradients_match_finite_differences():
     _fd_check(st, xs, ys, fs, tgt, O.HT_DIRECT | O.HT_NOISE, O.HYB_KEYS)
     _, g = O.hybrid_train_grads(st, xs, ys, fs, tgt, O.HT_DIRECT)
     assert not g["fuv_ep"].any() and not g["fuvt_ep"].any()
+
+
+# --------------------------------------------------------------- BC7 modes 4, 5 and 6
+def _pillow_bc7(blocks):
+    """[n][16][4] texels of BC7 blocks [n][16] decoded by Pillow's BC7 decoder (a DDS file in
+    memory, DXGI_FORMAT_BC7_UNORM): a decoder independent of the oracle."""
+    import io
+    import struct
+    import pytest
+    Image = pytest.importorskip("PIL.Image")
+    blocks = np.asarray(blocks, dtype=np.uint8).reshape(-1, 16)
+    n = blocks.shape[0]
+    wb = 1
+    while wb * wb < n:
+        wb *= 2
+    hb = (n + wb - 1) // wb
+    data = np.zeros((wb * hb, 16), np.uint8)
+    data[:n] = blocks
+    hdr = struct.pack("<4sI", b"DDS ", 124)
+    hdr += struct.pack("<IIIIII", 0x1 | 0x2 | 0x4 | 0x1000 | 0x80000, 4 * hb, 4 * wb, wb * hb * 16, 0, 1) + b"\0" * 44
+    hdr += struct.pack("<II4sIIIII", 32, 0x4, b"DX10", 0, 0, 0, 0, 0)
+    hdr += struct.pack("<IIIII", 0x1000, 0, 0, 0, 0)
+    hdr += struct.pack("<IIIII", 98, 3, 0, 1, 0)
+    img = Image.open(io.BytesIO(hdr + data.tobytes()))
+    img.load()
+    px = np.asarray(img.convert("RGBA")).reshape(hb, 4, wb, 4, 4).transpose(0, 2, 1, 3, 4).reshape(-1, 16, 4)
+    return px[:n]
+
+
+def test_bc7_decoder_modes_4_5_6_match_pillow():
+    blocks = I.random_bc7((3000,), np.random.default_rng(31))
+    ref = _pillow_bc7(blocks)
+    np.testing.assert_array_equal(np.stack([O.bc7_decode_block(b) for b in blocks]), ref)
+    xs, ys = np.tile(np.arange(4), 4), np.repeat(np.arange(4), 4)
+    np.testing.assert_array_equal(O.bc7_texels(np.repeat(blocks[:, None], 16, 1), xs[None], ys[None]), ref)
+    assert set(O.bc7_mode(b) for b in blocks) == {4, 5, 6}
+
+
+def _end_index_blocks(g, n):
+    """Random mode 4 / 5 / 6 blocks whose every index set uses its lowest index at texel 0
+    and its highest at texel 15 (so texels 0 and 15 are the endpoints of each set)."""
+    out = I.random_bc7((n,), g)
+    for blk in out:
+        b = int.from_bytes(bytes(blk), "little")
+        m = O.bc7_mode(blk)
+        sets = {6: ((65, 4),), 5: ((66, 2), (97, 2)), 4: ((50, 2), (81, 3))}[m]
+        for pos, bits in sets:
+            b &= ~(((1 << (bits - 1)) - 1) << pos)                 # texel 0: index 0
+            last = pos + bits - 1 + bits * 14
+            b |= ((1 << bits) - 1) << last                        # texel 15: the top index
+        blk[:] = np.frombuffer(b.to_bytes(16, "little"), np.uint8)
+    return out
+
+
+def test_bc7_multimode_encoder_reproduces_blocks_using_both_end_indices():
+    blocks = _end_index_blocks(np.random.default_rng(32), 48)
+    tex = np.stack([O.bc7_decode_block(b) for b in blocks])
+    enc = O.encode_bc7(tex)
+    np.testing.assert_array_equal(_pillow_bc7(enc), tex)
+
+
+def test_bc7_multimode_encoder_is_valid_and_never_worse_than_mode_6():
+    g = np.random.default_rng(33)
+    tex = np.concatenate([g.integers(0, 256, (30, 16, 4)), _smooth_blocks(g, 30, 8)]).astype(np.uint8)
+    enc = O.encode_bc7(tex)
+    assert set(O.bc7_mode(b) for b in enc) <= {4, 5, 6}
+    got = _pillow_bc7(enc).astype(np.int64)
+    sse = ((got - tex) ** 2).sum((1, 2))
+    sse6 = ((_pillow_bc7(O.encode_bc7m6(tex)).astype(np.int64) - tex) ** 2).sum((1, 2))
+    assert (sse <= sse6).all()
+    assert sse.sum() < sse6.sum()            # the other modes win on some of these blocks
+
+
+def test_bc7_subset_search_ends_in_a_local_minimum_of_its_moves():
+    """For each precision of modes 4 and 5, no single move of the search (one value +-1, all
+    values +-1) lowers the error of its result, checked by brute force on the moves."""
+    g = np.random.default_rng(34)
+    for (n, b, C) in ((7, 2, 3), (8, 2, 1), (5, 2, 3), (5, 3, 3), (6, 3, 1), (6, 2, 1)):
+        X = g.integers(0, 256, (6, 16, C))
+        v0, v1, J, sse = O._sub_search(X, n, b)
+        Wt = np.asarray({2: (0, 21, 43, 64), 3: (0, 9, 18, 27, 37, 46, 55, 64)}[b])
+        top = (1 << n) - 1
+
+        def err(a, z, x):
+            ea = (a << (8 - n)) | (a >> (2 * n - 8)) if n < 8 else a
+            ez = (z << (8 - n)) | (z >> (2 * n - 8)) if n < 8 else z
+            pal = ((64 - Wt)[:, None] * ea[None] + Wt[:, None] * ez[None] + 32) >> 6   # [index][C]
+            return int(((pal[None] - x[:, None]) ** 2).sum(-1).min(-1).sum())
+        for i in range(6):
+            assert err(v0[i], v1[i], X[i]) == sse[i]
+            for k in (0, 1):
+                for c in list(range(C)) + ([C] if C > 1 else []):
+                    for dv in (-1, 1):
+                        a, z = v0[i].copy(), v1[i].copy()
+                        v = a if k == 0 else z
+                        if c == C:
+                            v += dv
+                        else:
+                            v[c] += dv
+                        if (v < 0).any() or (v > top).any():
+                            continue
+                        assert err(a, z, X[i]) >= sse[i], (n, b, C, i, k, c, dv)
