@@ -131,14 +131,25 @@ int ndgi_bc4_decode_blocks(const uint8_t* blocks, int64_t n, uint8_t* out16, hip
 int ndgi_bc4_decode_blocks_impl(const uint8_t* blocks, int64_t n, uint8_t* out16, int32_t impl,
                                 hipStream_t stream);
 
-/* Decode n BC7 mode-6 blocks (the block format of the hybrid layout's F_uv and F_uvt,
- * NDGI_CODEC_BC7; Sec. 3.4), bit-exactly, as the hybrid decode reads them.  blocks: device
- * [n][16] bytes, 16-byte aligned, each a 128-bit little-endian value: 7-bit endpoint
- * values R0 R1 G0 G1 B0 B1 A0 A1 at bits 7..62, p-bits at 63 and 64, texel 0's 3-bit index
- * at 65..67, texel s's 4-bit index at 64 + 4 s (the mode bits 0..6 are not checked).
- * out64: device [n][16][4] bytes, 16-byte aligned: channel c of texel s = 4*row + col at
- * out64[64*i + 4*s + c] = ((64 - w) E0 + w E1 + 32) >> 6 with E = (v << 1) | p and w the
- * index's 4-bit weight (0 4 9 13 17 21 26 30 34 38 43 47 51 55 60 64).
+/* Decode n BC7 blocks of modes 4, 5 and 6, the single-subset modes with four channels (the
+ * block format of the hybrid layout's F_uv and F_uvt, NDGI_CODEC_BC7; Sec. 3.4 compresses
+ * with several modes), bit-exactly, as the hybrid decode reads them.  blocks: device [n][16]
+ * bytes, 16-byte aligned, each a 128-bit little-endian value; the mode is the position of
+ * the lowest set bit of byte 0:
+ *  - mode 6: 7-bit endpoint values R0 R1 G0 G1 B0 B1 A0 A1 at bits 7..62, p-bits at 63 and
+ *    64, texel 0's 3-bit index at 65..67, texel s's 4-bit index at 64 + 4 s; E = (v << 1) | p;
+ *  - mode 5: rotation at bits 6..7, 7-bit colour values R0 R1 G0 G1 B0 B1 from bit 8, 8-bit
+ *    alpha values at 50 and 58, 2-bit colour indices from bit 66, 2-bit alpha indices from 97;
+ *  - mode 4: rotation at bits 5..6, index selection at 7, 5-bit colour values from bit 8,
+ *    6-bit alpha values at 38 and 44, a 2-bit index set from bit 50 and a 3-bit set from 81
+ *    (colour takes the 2-bit set when the selection is 0, the 3-bit set when it is 1);
+ * in an index set texel 0's index has one bit less (its top bit is 0); an n-bit value v
+ * expands to E = (v << (8 - n)) | (v >> (2n - 8)).  out64: device [n][16][4] bytes, 16-byte
+ * aligned: channel c of texel s = 4*row + col at out64[64*i + 4*s + c] =
+ * ((64 - w) E0 + w E1 + 32) >> 6 with w the b-bit weight of the texel's index (b = 2: 0 21
+ * 43 64; b = 3: 0 9 18 27 37 46 55 64; b = 4: 0 4 9 13 17 21 26 30 34 38 43 47 51 55 60 64),
+ * colour with the colour index, alpha with the alpha index; then a rotation r > 0 exchanges
+ * channel r - 1 and channel 3.  A block of any other mode (or none) decodes to 0.
  * n = 0 is a no-op.  Errors: INVALID_ARG (n < 0, NULL or misaligned pointers when n > 0). */
 int ndgi_bc7_decode_blocks(const uint8_t* blocks, int64_t n, uint8_t* out64, hipStream_t stream);
 
@@ -155,10 +166,13 @@ int ndgi_bc7_decode_blocks(const uint8_t* blocks, int64_t n, uint8_t* out64, hip
  * pointers). */
 int ndgi_bc4_encode_blocks(const uint8_t* texels, int64_t n, uint8_t* out, hipStream_t stream);
 
-/* BC7 mode 6: for each block of 16 RGBA texels (texels: device [n][16][4] bytes) a mode-6
- * block found by a fixed integer search (the optimum is out of reach: 2^58 endpoint
- * settings): (1) endpoints at the corners of the texels' bounding box along its principal
- * diagonal (reference channel = largest spread; a channel runs min -> max when its
+/* BC7 with modes 6, 5 and 4: for each block of 16 RGBA texels (texels: device [n][16][4]
+ * bytes) the candidate of least summed squared error among a mode-6 block, a mode-5 block
+ * under each of the 4 rotations and a mode-4 block under each rotation and both index
+ * selections (ties: mode 6, then mode 5 by rotation, then mode 4 by rotation, then selection),
+ * each found by a fixed integer search (the optimum is out of reach: 2^58 endpoint settings
+ * in mode 6).  Mode 6: (1) endpoints at the corners of the texels' bounding box along its
+ * principal diagonal (reference channel = largest spread; a channel runs min -> max when its
  * covariance with the reference is >= 0, else max -> min); (2) both endpoints quantised for
  * each of the four p-bit pairs, v = clamp(floor((x - p + 1) / 2), 0, 127); (3) twice, the
  * least-squares endpoints of the current indices (2x2 normal equations per channel, exact
@@ -169,9 +183,17 @@ int ndgi_bc4_encode_blocks(const uint8_t* texels, int64_t n, uint8_t* out, hipSt
  * 0..127 are not taken), the first strictly best move taken while it improves; a candidate
  * replaces the current block only when strictly better, and every candidate's indices are
  * refitted (each texel its least-error index, the lowest on ties); (5) when texel 0's index
- * is >= 8 the endpoints swap and each index J becomes 15 - J.  out: device [n][16], 16-byte
- * aligned, in ndgi_bc7_decode_blocks' layout.  Reproduces exactly any texels that a mode-6
- * block using indices 0 and 15 decodes to.  n = 0 is a no-op.  Errors: INVALID_ARG. */
+ * is >= 8 the endpoints swap and each index J becomes 15 - J.  Modes 5 and 4 (the rotated
+ * texels: channel r - 1 and channel 3 exchanged) fit the colour endpoints (3 channels) and
+ * the alpha endpoints (1 channel) apart, each by the same steps at its value width n and
+ * index width b: (1) as above (one channel: min -> max), each 8-bit target quantised to the
+ * n-bit value whose expansion is nearest (ties to the lower); (2) twice, least squares as
+ * above, quantised likewise; (3) local search at steps 2^(n-4) .. 1 over each value of
+ * endpoint 0 then endpoint 1 by -s, +s, then (colour) all values of one endpoint by -s, +s;
+ * (4) when texel 0's index has its top bit set, the endpoints swap and J becomes
+ * 2^b - 1 - J.  out: device [n][16], 16-byte aligned, in ndgi_bc7_decode_blocks' layout.
+ * Reproduces exactly any texels that a mode-6 block using indices 0 and 15 decodes to.
+ * n = 0 is a no-op.  Errors: INVALID_ARG. */
 int ndgi_bc7_encode_blocks(const uint8_t* texels, int64_t n, uint8_t* out, hipStream_t stream);
 
 /* ---------------------------------------------------------------- decode */
@@ -342,7 +364,7 @@ int ndgi_export(ndgi_ctx* ctx, const ndgi_train_state* state, uint8_t* bc4_out,
 /* The paper's own feature layout (Sec. 3.3, Eq. 4-5; Table 1; Table 3), decoded by its
  * GELU decoder (Sec. 4).  Four feature maps per model:
  *   F_uv   W x H texels, 4 channels, block-compressed per 4x4 footprint (codec below:
- *          [H/4][W/4][4][8 bytes] BC4 or [H/4][W/4][16 bytes] BC7 mode 6)
+ *          [H/4][W/4][4][8 bytes] BC4 or [H/4][W/4][16 bytes] BC7)
  *   F_uvt  Gu x Gv texels x S time slices, 4 channels, each slice block-compressed on its
  *          own (Sec. 3.4): [S][Gv/4][Gu/4] footprints as for F_uv
  *   F_ut   U x Tt texels, 2 channels, 8-bit: [Tt][U][2] bytes
@@ -366,9 +388,10 @@ int ndgi_export(ndgi_ctx* ctx, const ndgi_train_state* state, uint8_t* bc4_out,
 /* Block formats of F_uv and F_uvt:
  *   NDGI_CODEC_BC4  one BC4 block per channel (8 bytes per 4x4 footprint and channel: a weight
  *                   per texel and channel), 16 bits per texel for the 4 channels;
- *   NDGI_CODEC_BC7  one BC7 mode-6 block per footprint (16 bytes: 7-bit RGBA endpoints with a
- *                   p-bit each, one 4-bit index per texel shared by the 4 channels, as Eq. 6
- *                   writes the simulation), 8 bits per texel - the rate of the paper's Table 3. */
+ *   NDGI_CODEC_BC7  one BC7 block per footprint of mode 4, 5 or 6 (ndgi_bc7_decode_blocks;
+ *                   16 bytes; mode 6: 7-bit RGBA endpoints with a p-bit each, one 4-bit index
+ *                   per texel shared by the 4 channels, as Eq. 6 writes the simulation), 8
+ *                   bits per texel - the rate of the paper's Table 3. */
 #define NDGI_CODEC_BC4 0
 #define NDGI_CODEC_BC7 1
 

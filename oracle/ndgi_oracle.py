@@ -1597,12 +1597,12 @@ def _footprints(tex):
 
 
 def encode_map(tex, codec: int) -> np.ndarray:
-    """Blocks of an 8-bit 4-channel map [..][H][W][4]: BC7 mode 6 ([..][H/4][W/4][16], codec 1)
-    or one BC4 block per channel ([..][H/4][W/4][4][8], codec 0)."""
+    """Blocks of an 8-bit 4-channel map [..][H][W][4]: BC7 of modes 6, 5 and 4 (encode_bc7;
+    [..][H/4][W/4][16], codec 1) or one BC4 block per channel ([..][H/4][W/4][4][8], codec 0)."""
     fp = _footprints(np.asarray(tex, dtype=np.int64))
     lead = fp.shape[:-2]
     if codec == 1:
-        return encode_bc7m6(fp.reshape(-1, 16, 4)).reshape(lead + (16,))
+        return encode_bc7(fp.reshape(-1, 16, 4)).reshape(lead + (16,))
     per_ch = np.moveaxis(fp, -1, -2)                               # [..][Hb][Wb][4 ch][16]
     return encode_bc4(per_ch.reshape(-1, 16)).reshape(lead + (4, 8))
 

@@ -29,6 +29,21 @@
 //   index J becomes 15 - J, which decodes identically.  Every candidate's indices are
 //   refitted: each texel takes its least-error index, the lowest on ties.  One wave per
 //   block: lane (s, g) = (lane >> 2, lane & 3) holds texel s and tries indices 4g .. 4g + 3.
+//
+// * BC7 with several modes (Sec. 3.4 compresses each block "using multiple modes"): after the
+//   mode-6 search, every block tries mode 5 under each of its 4 rotations and mode 4 under
+//   each rotation and both index selections, and keeps the candidate of least summed squared
+//   error (ties: mode 6, then mode 5 by rotation, then mode 4 by rotation then selection).  A
+//   rotation r > 0 encodes the texels with channel r - 1 and channel 3 exchanged.  Modes 5
+//   and 4 fit their colour (3 channels) and alpha (1 channel) endpoints apart, each by the
+//   same fixed search at its endpoint precision n and index width b: (1) the bounding-box
+//   diagonal (one channel: its minimum and maximum), each 8-bit target quantised to the
+//   n-bit value whose expansion is nearest (ties to the lower; the candidates are
+//   round(x (2^n - 1) / 255) and its neighbours); (2) twice, the least-squares endpoints of
+//   the current indices, quantised as in (1); (3) best-improvement local search at steps
+//   2^(n - 4) .. 1 over each value of each endpoint -s and +s, then (several channels) all
+//   values of one endpoint -s and +s, at most 64 rounds per step; (4) the anchor swap of
+//   endpoints and indices J -> 2^b - 1 - J when texel 0's index has its top bit set.
 #include <climits>
 
 #include "bcsim.hpp"
@@ -239,6 +254,282 @@ __device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {   // b > 0
   return (a % b != 0 && a < 0) ? q - 1 : q;
 }
 
+// ------------------------------------------------------------ BC7 modes 4 and 5 (subsets)
+__device__ __forceinline__ int bc7_xpand(int v, int n) { return n < 8 ? (v << (8 - n)) | (v >> (2 * n - 8)) : v; }
+
+// The n-bit value whose expansion is nearest to the 8-bit target x (ties to the lower).
+template <int N>
+__device__ __forceinline__ int bc7_quant(int x) {
+  constexpr int top = (1 << N) - 1;
+  const int g = min(max((x * top + 127) / 255, 0), top);
+  int best = 0, bd = INT_MAX;
+#pragma unroll
+  for (int dv = -1; dv <= 1; ++dv) {
+    const int v = min(max(g + dv, 0), top);
+    const int d = abs(bc7_xpand(v, N) - x);
+    if (d < bd || (d == bd && v < best)) {
+      best = v;
+      bd = d;
+    }
+  }
+  return best;
+}
+
+template <int C>
+struct SubRes {
+  int v0[C], v1[C], sse, J;
+};
+
+// Index fit of endpoints (n-bit values v0, v1) with b-bit indices: J = this lane's texel's
+// best index (the lowest on ties; lane (s, g) tries indices PER g .. PER g + PER - 1); returns
+// the block's summed squared error in every lane.
+template <int C, int N, int IB>
+__device__ __forceinline__ int sub_fit(const int X[C], const int v0[C], const int v1[C], int lane, int& J) {
+  constexpr int PER = (1 << IB) / 4;
+  int E0[C], E1[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    E0[c] = bc7_xpand(v0[c], N);
+    E1[c] = bc7_xpand(v1[c], N);
+  }
+  int best = INT_MAX, bj = 0;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int j = PER * (lane & 3) + k;
+    const int w = (64 * j + ((1 << IB) - 1) / 2) / ((1 << IB) - 1);   // the format's weight table
+    int d = 0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int e = (((64 - w) * E0[c] + w * E1[c] + 32) >> 6) - X[c];
+      d += e * e;
+    }
+    if (d < best) {
+      best = d;
+      bj = j;
+    }
+  }
+#pragma unroll
+  for (int off = 1; off < 4; off <<= 1) {
+    const int ob = __shfl_xor(best, off, 64), oj = __shfl_xor(bj, off, 64);
+    if (ob < best || (ob == best && oj < bj)) {
+      best = ob;
+      bj = oj;
+    }
+  }
+  J = bj;
+  return wave_isum((lane & 3) == 0 ? best : 0);
+}
+
+template <int C, int N, int IB>
+__device__ __forceinline__ void sub_take(SubRes<C>& cur, const int X[C], const int v0[C], const int v1[C], int lane) {
+  int J;
+  const int sse = sub_fit<C, N, IB>(X, v0, v1, lane, J);
+  if (sse < cur.sse) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      cur.v0[c] = v0[c];
+      cur.v1[c] = v1[c];
+    }
+    cur.sse = sse;
+    cur.J = J;
+  }
+}
+
+template <int C, int N, int IB>
+__device__ SubRes<C> sub_search(const int X[C], int lane) {
+  constexpr int top = (1 << N) - 1;
+  SubRes<C> cur;
+  cur.sse = INT_MAX;
+  cur.J = 0;
+#pragma unroll
+  for (int c = 0; c < C; ++c) cur.v0[c] = cur.v1[c] = 0;
+  // (1) bounding-box diagonal
+  {
+    int lo[C], hi[C], A[C], B[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      int mn = X[c], mx = X[c];
+#pragma unroll
+      for (int off = 4; off < 64; off <<= 1) {
+        mn = min(mn, __shfl_xor(mn, off, 64));
+        mx = max(mx, __shfl_xor(mx, off, 64));
+      }
+      lo[c] = mn;
+      hi[c] = mx;
+    }
+    if constexpr (C > 1) {
+      int D[C], var[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int sum = wave_isum((lane & 3) == 0 ? X[c] : 0);
+        D[c] = 16 * X[c] - sum;
+        var[c] = wave_isum((lane & 3) == 0 ? D[c] * D[c] : 0);
+      }
+      int ref = 0;
+#pragma unroll
+      for (int c = 1; c < C; ++c)
+        if (var[c] > var[ref]) ref = c;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int cov = wave_isum((lane & 3) == 0 ? D[c] * D[ref] : 0);
+        A[c] = cov >= 0 ? lo[c] : hi[c];
+        B[c] = cov >= 0 ? hi[c] : lo[c];
+      }
+    } else {
+      A[0] = lo[0];
+      B[0] = hi[0];
+    }
+    int q0[C], q1[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      q0[c] = bc7_quant<N>(A[c]);
+      q1[c] = bc7_quant<N>(B[c]);
+    }
+    sub_take<C, N, IB>(cur, X, q0, q1, lane);
+  }
+  // (2) least-squares endpoints of the current indices, twice
+#pragma unroll 1
+  for (int it = 0; it < 2; ++it) {
+    const int w = (64 * cur.J + ((1 << IB) - 1) / 2) / ((1 << IB) - 1), a = 64 - w;
+    const bool mine = (lane & 3) == 0;
+    const int64_t Aa = wave_isum(mine ? a * a : 0), Bab = wave_isum(mine ? a * w : 0), Cb = wave_isum(mine ? w * w : 0);
+    const int64_t det = Aa * Cb - Bab * Bab;
+    int q0[C], q1[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int64_t r0 = 64 * (int64_t)wave_isum(mine ? a * X[c] : 0);
+      const int64_t r1 = 64 * (int64_t)wave_isum(mine ? w * X[c] : 0);
+      int E0, E1;
+      if (det > 0) {
+        const int64_t n0 = Cb * r0 - Bab * r1, n1 = Aa * r1 - Bab * r0;
+        E0 = (int)min(max(floor_div(2 * n0 + det, 2 * det), (int64_t)0), (int64_t)255);
+        E1 = (int)min(max(floor_div(2 * n1 + det, 2 * det), (int64_t)0), (int64_t)255);
+      } else {
+        E0 = bc7_xpand(cur.v0[c], N);
+        E1 = bc7_xpand(cur.v1[c], N);
+      }
+      q0[c] = bc7_quant<N>(E0);
+      q1[c] = bc7_quant<N>(E1);
+    }
+    sub_take<C, N, IB>(cur, X, q0, q1, lane);
+  }
+  // (3) local search, coarse to fine
+  constexpr int NM = 4 * C + (C > 1 ? 4 : 0);
+#pragma unroll 1
+  for (int st = 1 << (N - 4); st >= 1; st >>= 1) {
+#pragma unroll 1
+    for (int round = 0; round < 64; ++round) {
+      int bsse = INT_MAX, bmove = -1, bJ = 0;
+#pragma unroll 1
+      for (int mv = 0; mv < NM; ++mv) {
+        int v0[C], v1[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          v0[c] = cur.v0[c];
+          v1[c] = cur.v1[c];
+        }
+        bool valid = true;
+        const int k = mv < 4 * C ? mv / (2 * C) : (mv - 4 * C) >> 1;
+        const int cc = mv < 4 * C ? (mv >> 1) % C : C;   // C: every value of the endpoint
+        const int dv = (mv & 1) ? st : -st;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+          if (cc == C || cc == c) {
+            if (k) v1[c] += dv;
+            else v0[c] += dv;
+            const int t = k ? v1[c] : v0[c];
+            valid = valid && t >= 0 && t <= top;
+          }
+        if (!valid) continue;
+        int J;
+        const int sse = sub_fit<C, N, IB>(X, v0, v1, lane, J);
+        if (sse < bsse) {
+          bsse = sse;
+          bmove = mv;
+          bJ = J;
+        }
+      }
+      if (bmove < 0 || bsse >= cur.sse) break;
+      const int k = bmove < 4 * C ? bmove / (2 * C) : (bmove - 4 * C) >> 1;
+      const int cc = bmove < 4 * C ? (bmove >> 1) % C : C;
+      const int dv = (bmove & 1) ? st : -st;
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        if (cc == C || cc == c) {
+          if (k) cur.v1[c] += dv;
+          else cur.v0[c] += dv;
+        }
+      cur.sse = bsse;
+      cur.J = bJ;
+    }
+  }
+  // (4) anchor: texel 0's index without its top bit
+  if (__shfl(cur.J, 0, 64) >= (1 << (IB - 1))) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int t = cur.v0[c];
+      cur.v0[c] = cur.v1[c];
+      cur.v1[c] = t;
+    }
+    cur.J = (1 << IB) - 1 - cur.J;
+  }
+  return cur;
+}
+
+// OR value v (< 256) into the 128-bit block (lo, hi) at bit pos.
+__device__ __forceinline__ void bc7_put(uint64_t& lo, uint64_t& hi, uint32_t v, int pos) {
+  if (pos >= 64) {
+    hi |= (uint64_t)v << (pos - 64);
+  } else {
+    lo |= (uint64_t)v << pos;
+    if (pos > 56) hi |= (uint64_t)v >> (64 - pos);
+  }
+}
+
+// This lane's texel index J into an index set of b-bit indices starting at bit pos (lanes
+// of texel s: s = lane >> 2; only the first lane of a texel contributes).
+__device__ __forceinline__ void bc7_put_index(uint64_t& lo, uint64_t& hi, int J, int pos, int b, int lane) {
+  const int s = lane >> 2;
+  if ((lane & 3) == 0) bc7_put(lo, hi, (uint32_t)J, s ? pos + b - 1 + b * (s - 1) : pos);
+}
+
+// The winning candidate of modes 4 and 5 for a block.
+struct M45 {
+  int mode, rot, sel, sse;
+  SubRes<3> col;
+  SubRes<1> alp;
+};
+
+template <int MODE, int SEL>
+__device__ __forceinline__ void m45_try(M45& best, const int X[4], int rot, int lane) {
+  int Y[4] = {X[0], X[1], X[2], X[3]};
+  if (rot) {
+    Y[rot - 1] = X[3];
+    Y[3] = X[rot - 1];
+  }
+  SubRes<3> col;
+  SubRes<1> alp;
+  if constexpr (MODE == 5) {
+    col = sub_search<3, 7, 2>(Y, lane);
+    alp = sub_search<1, 8, 2>(Y + 3, lane);
+  } else if constexpr (SEL == 0) {
+    col = sub_search<3, 5, 2>(Y, lane);
+    alp = sub_search<1, 6, 3>(Y + 3, lane);
+  } else {
+    col = sub_search<3, 5, 3>(Y, lane);
+    alp = sub_search<1, 6, 2>(Y + 3, lane);
+  }
+  const int sse = col.sse + alp.sse;
+  if (sse < best.sse) {
+    best.mode = MODE;
+    best.rot = rot;
+    best.sel = SEL;
+    best.sse = sse;
+    best.col = col;
+    best.alp = alp;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_encode_bc7(TexSrc S, int64_t n, uint8_t* __restrict__ out) {
   const int lane = threadIdx.x & 63;
   const int s = lane >> 2;
@@ -382,6 +673,56 @@ __global__ __launch_bounds__(256) void k_encode_bc7(TexSrc S, int64_t n, uint8_t
         cur.sse = bsse;
         cur.J = bJ;
       }
+    }
+    // modes 5 and 4, each rotation (and, mode 4, index selection): a candidate replaces the
+    // block only when strictly better
+    M45 alt;
+    alt.mode = 6;
+    alt.sse = cur.sse;
+#pragma unroll 1
+    for (int r = 0; r < 4; ++r) m45_try<5, 0>(alt, X, r, lane);
+#pragma unroll 1
+    for (int r = 0; r < 4; ++r) {
+      m45_try<4, 0>(alt, X, r, lane);
+      m45_try<4, 1>(alt, X, r, lane);
+    }
+    if (alt.mode != 6) {   // wave-uniform
+      uint64_t lo = 0, hi = 0;
+      if (alt.mode == 5) {
+        bc7_put_index(lo, hi, alt.col.J, 66, 2, lane);
+        bc7_put_index(lo, hi, alt.alp.J, 97, 2, lane);
+      } else {
+        bc7_put_index(lo, hi, alt.sel ? alt.alp.J : alt.col.J, 50, 2, lane);
+        bc7_put_index(lo, hi, alt.sel ? alt.col.J : alt.alp.J, 81, 3, lane);
+      }
+#pragma unroll
+      for (int off = 4; off < 64; off <<= 1) {
+        lo |= __shfl_xor(lo, off, 64);
+        hi |= __shfl_xor(hi, off, 64);
+      }
+      if (lane == 0) {
+        if (alt.mode == 5) {
+          lo |= (uint64_t)((1 << 5) | (alt.rot << 6));
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            bc7_put(lo, hi, (uint32_t)alt.col.v0[c], 8 + 14 * c);
+            bc7_put(lo, hi, (uint32_t)alt.col.v1[c], 15 + 14 * c);
+          }
+          bc7_put(lo, hi, (uint32_t)alt.alp.v0[0], 50);
+          bc7_put(lo, hi, (uint32_t)alt.alp.v1[0], 58);
+        } else {
+          lo |= (uint64_t)((1 << 4) | (alt.rot << 5) | (alt.sel << 7));
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            bc7_put(lo, hi, (uint32_t)alt.col.v0[c], 8 + 10 * c);
+            bc7_put(lo, hi, (uint32_t)alt.col.v1[c], 13 + 10 * c);
+          }
+          bc7_put(lo, hi, (uint32_t)alt.alp.v0[0], 38);
+          bc7_put(lo, hi, (uint32_t)alt.alp.v1[0], 44);
+        }
+        *(u4v*)(out + f * 16) = (u4v){(uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32)};
+      }
+      continue;
     }
     // (5): anchor and packing; texel s's index sits in lane 4 s
     const int j0 = __shfl(cur.J, 0, 64);

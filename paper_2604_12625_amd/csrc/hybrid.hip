@@ -1,6 +1,6 @@
 // Decode of the paper's hybrid layout (Sec. 3.3, Eq. 4-5): F_uvt (4 channels in time
 // slices, each slice block-compressed), F_uv (4 channels, block-compressed: BC4 per channel
-// or BC7 mode 6), F_ut and F_vt (2 channels each, 8-bit)
+// or BC7 blocks of modes 4-6), F_ut and F_vt (2 channels each, 8-bit)
 // and gamma(t) feed a 16 -> h -> h -> 3 decoder with GELU hidden layers and a linear
 // output (Sec. 4), h = 16 or 64.
 //
@@ -217,32 +217,100 @@ __device__ __forceinline__ void bc4_fp4_regs(const u4v& a, const u4v& b, uint32_
   v[3] = bc4_texel_f(b.z, b.w, slot);
 }
 
-// Four channels of texel `slot` of a BC7 mode-6 block (b = the 16 bytes as a 128-bit
-// little-endian value): 7-bit endpoint values R0 R1 G0 G1 B0 B1 A0 A1 at bits 7..62, p-bits
-// at 63 and 64, texel 0's 3-bit index at 65..67 and texel i's 4-bit index at 64 + 4 i;
-// endpoint (v << 1) | p, texel ((64 - w) E0 + w E1 + 32) >> 6.  The weight is
-// (64 J + 7) / 15, which equals the format's 4-bit weight table at every index J.
+// Bits [pos, pos + n) (n <= 8) of a BC7 block held as a 128-bit little-endian value.
+__device__ __forceinline__ uint32_t bc7_bits(uint64_t lo, uint64_t hi, uint32_t pos, uint32_t n) {
+  const uint64_t v = pos >= 64u ? hi >> (pos - 64u) : (pos == 0u ? lo : (lo >> pos) | (hi << (64u - pos)));
+  return (uint32_t)v & ((1u << n) - 1u);
+}
+// Index of texel `slot` in an index set of b-bit indices starting at bit pos (texel 0 has
+// b - 1 bits).
+__device__ __forceinline__ uint32_t bc7_index(uint64_t lo, uint64_t hi, uint32_t pos, uint32_t b, uint32_t slot) {
+  return slot ? bc7_bits(lo, hi, pos + b - 1u + b * (slot - 1u), b) : bc7_bits(lo, hi, pos, b - 1u);
+}
+// n-bit endpoint value as 8 bits: the top bits replicated below.
+__device__ __forceinline__ uint32_t bc7_expand(uint32_t v, uint32_t n) { return (v << (8u - n)) | (v >> (2u * n - 8u)); }
+
+// Four channels of texel `slot` of a BC7 block (b = the 16 bytes as a 128-bit little-endian
+// value) in mode 4, 5 or 6, the single-subset modes with four channels; other modes give 0.
+//  * mode 6 (bits 0..6 = 1000000b): 7-bit endpoint values R0 R1 G0 G1 B0 B1 A0 A1 at bits
+//    7..62, p-bits at 63 and 64, one 4-bit index per texel from bit 65; endpoint (v << 1) | p;
+//  * mode 5 (bits 0..5 = 100000b): rotation at 6..7, 7-bit colour endpoints R0 .. B1 from
+//    bit 8, 8-bit alpha endpoints at 50 and 58, 2-bit colour indices from 66 and 2-bit
+//    alpha indices from 97;
+//  * mode 4 (bits 0..4 = 10000b): rotation at 5..6, index selection at 7, 5-bit colour
+//    endpoints from bit 8, 6-bit alpha endpoints at 38 and 44, a 2-bit index set from 50 and
+//    a 3-bit set from 81 (colour takes the 3-bit set when the selection bit is 1).
+// An n-bit endpoint is (v << (8 - n)) | (v >> (2n - 8)); texel ((64 - w) E0 + w E1 + 32) >> 6
+// with w = (64 J + (2^b - 1) / 2) / (2^b - 1), which equals the format's b-bit weight table;
+// rotation r > 0 exchanges channel r - 1 with channel 3 after decoding.
 __device__ __forceinline__ void bc7_fp4_regs(const u4v& b, uint32_t slot, float v[4]) {
   const uint64_t lo = ((uint64_t)b.y << 32) | b.x, hi = ((uint64_t)b.w << 32) | b.z;
-  const uint32_t p0 = (uint32_t)(lo >> 63), p1 = (uint32_t)hi & 1u;
-  const uint32_t j = slot ? (uint32_t)(hi >> (4u * slot)) & 15u : (uint32_t)(hi >> 1) & 7u;
-  const uint32_t w = (64u * j + 7u) / 15u;
+  const uint32_t m = b.x & 0xffu;
+  uint32_t e0[4], e1[4], wc, wa, rot;
+  if ((m & 0x7fu) == 0x40u) {
+    const uint32_t p0 = (uint32_t)(lo >> 63), p1 = (uint32_t)hi & 1u;
+    const uint32_t j = bc7_index(lo, hi, 65u, 4u, slot);
+    wc = wa = (64u * j + 7u) / 15u;
+    rot = 0u;
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const uint32_t e0 = (((uint32_t)(lo >> (7 + 14 * c)) & 127u) << 1) | p0;
-    const uint32_t e1 = (((uint32_t)(lo >> (14 + 14 * c)) & 127u) << 1) | p1;
-    v[c] = (float)(((64u - w) * e0 + w * e1 + 32u) >> 6);
+    for (int c = 0; c < 4; ++c) {
+      e0[c] = (bc7_bits(lo, hi, 7u + 14u * c, 7u) << 1) | p0;
+      e1[c] = (bc7_bits(lo, hi, 14u + 14u * c, 7u) << 1) | p1;
+    }
+  } else if ((m & 0x3fu) == 0x20u) {
+    rot = bc7_bits(lo, hi, 6u, 2u);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      e0[c] = bc7_expand(bc7_bits(lo, hi, 8u + 14u * c, 7u), 7u);
+      e1[c] = bc7_expand(bc7_bits(lo, hi, 15u + 14u * c, 7u), 7u);
+    }
+    e0[3] = bc7_bits(lo, hi, 50u, 8u);
+    e1[3] = bc7_bits(lo, hi, 58u, 8u);
+    wc = (64u * bc7_index(lo, hi, 66u, 2u, slot) + 1u) / 3u;
+    wa = (64u * bc7_index(lo, hi, 97u, 2u, slot) + 1u) / 3u;
+  } else if ((m & 0x1fu) == 0x10u) {
+    rot = bc7_bits(lo, hi, 5u, 2u);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      e0[c] = bc7_expand(bc7_bits(lo, hi, 8u + 10u * c, 5u), 5u);
+      e1[c] = bc7_expand(bc7_bits(lo, hi, 13u + 10u * c, 5u), 5u);
+    }
+    e0[3] = bc7_expand(bc7_bits(lo, hi, 38u, 6u), 6u);
+    e1[3] = bc7_expand(bc7_bits(lo, hi, 44u, 6u), 6u);
+    const uint32_t w2 = (64u * bc7_index(lo, hi, 50u, 2u, slot) + 1u) / 3u;
+    const uint32_t w3 = (64u * bc7_index(lo, hi, 81u, 3u, slot) + 3u) / 7u;
+    const bool sel = (lo >> 7) & 1u;
+    wc = sel ? w3 : w2;
+    wa = sel ? w2 : w3;
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = 0.0f;
+    return;
   }
+  uint32_t t[4];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) t[c] = ((64u - wc) * e0[c] + wc * e1[c] + 32u) >> 6;
+  t[3] = ((64u - wa) * e0[3] + wa * e1[3] + 32u) >> 6;
+  if (rot) {
+    const uint32_t r = rot - 1u;
+    const uint32_t x = r == 0u ? t[0] : (r == 1u ? t[1] : t[2]);
+    t[0] = r == 0u ? t[3] : t[0];
+    t[1] = r == 1u ? t[3] : t[1];
+    t[2] = r == 2u ? t[3] : t[2];
+    t[3] = x;
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) v[c] = (float)t[c];
 }
 
 // Four channels (0..255) of texel `slot` of a footprint: 32 bytes of BC4 (codec 0) or one
-// 16-byte BC7 mode-6 block (codec 1).
+// 16-byte BC7 block of mode 4, 5 or 6 (codec 1).
 __device__ __forceinline__ void fp4(const uint8_t* fp, int codec, uint32_t slot, float v[4]) {
   if (codec) bc7_fp4_regs(*(const u4v*)fp, slot, v);
   else bc4_fp4(fp, slot, v);
 }
 
-// Standalone decode of BC7 mode-6 blocks (the texel decode the hybrid kernels use), 16
+// Standalone decode of BC7 blocks (the texel decode the hybrid kernels use), 16
 // texels x 4 channels per block: out[64 b + 4 s + c].
 __global__ __launch_bounds__(256) void k_bc7_blocks(const uint8_t* __restrict__ blocks, int64_t n,
                                                      uint8_t* __restrict__ out) {
@@ -574,7 +642,7 @@ int check_hybrid(const ndgi_hybrid_model* m, const char* who) {
 // Import of a block-compressed 4-channel map into a directly parameterised training state:
 // texel (x, y) of slice sl becomes w[((sl H + y) W + x) 4 + c] = byte / 255 (FP32 division),
 // the byte being the texel decode of the model's blocks (codec 0: 32 bytes of BC4 per
-// footprint, codec 1: one BC7 mode-6 block).
+// footprint, codec 1: one BC7 block of mode 4, 5 or 6).
 __global__ __launch_bounds__(256) void k_import_map(const uint8_t* __restrict__ blocks, int codec, int W, int H,
                                                      int64_t texels, float* __restrict__ w) {
   const int64_t per = (int64_t)W * H;

@@ -126,13 +126,14 @@ def random_bc7(shape, g: np.random.Generator, modes=(4, 5, 6)) -> np.ndarray:
 
 def random_hybrid_model(W: int = 128, H: int = 128, profile: str = "M", slices: int = 12,
                         plane=(64, 64, 24), mlp_dtype=np.float16, keys: bool = True,
-                        config: int = 0, index: int = 0, uvt_side=None, codec: int = 0) -> dict:
+                        config: int = 0, index: int = 0, uvt_side=None, codec: int = 0,
+                        bc7_modes=(4, 5, 6)) -> dict:
     """A hybrid model with uniformly random block bytes and 8-bit planes.
 
     ``plane`` = (U, V, Tt): F_ut is [Tt][U][2] and F_vt is [Tt][V][2] (uint8);
     F_uv is [H/4][W/4][4][8] and F_uvt is [S][Gv/4][Gu/4][4][8] BC4 bytes (codec 0), or
-    one 16-byte BC7 mode-6 block per footprint (codec 1).  ``keys`` attaches a non-uniform
-    key-time table (:func:`lightmap_key_times`)."""
+    one 16-byte BC7 block per footprint (codec 1) of a mode drawn uniformly from
+    ``bc7_modes``.  ``keys`` attaches a non-uniform key-time table (:func:`lightmap_key_times`)."""
     side, hidden = HYBRID_PROFILES[profile]
     Gu, Gv = (side, side) if uvt_side is None else uvt_side
     U, V, Tt = plane
@@ -140,7 +141,7 @@ def random_hybrid_model(W: int = 128, H: int = 128, profile: str = "M", slices: 
     assert W % 4 == 0 and H % 4 == 0 and Gu % 4 == 0 and Gv % 4 == 0
 
     def blocks(shape):
-        return random_bc7m6(shape, g) if codec == 1 else g.integers(0, 256, size=tuple(shape) + (4, 8),
+        return random_bc7(shape, g, bc7_modes) if codec == 1 else g.integers(0, 256, size=tuple(shape) + (4, 8),
                                                                        dtype=np.uint8)
 
     return dict(

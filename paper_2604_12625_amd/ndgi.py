@@ -384,7 +384,8 @@ def bc4_encode_blocks(texels, out=None, stream=None):
 
 
 def bc7_encode_blocks(texels, out=None, stream=None):
-    """Encode [n][16][4] uint8 device texels as [n][16] BC7 mode-6 blocks."""
+    """Encode [n][16][4] uint8 device texels as [n][16] BC7 blocks (modes 6, 5 and 4, each
+    block its least-error candidate)."""
     import torch
     n = texels.shape[0]
     if out is None:

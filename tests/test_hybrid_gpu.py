@@ -324,12 +324,12 @@ def test_hybrid_1024_map_of_tile_models_sampled(N, ctx, profile):
     assert ctx.error_flags() == 0
 
 
-# ------------------------------------------------------------------------- BC7 mode 6
+# ------------------------------------------------------------------------- BC7 modes 4-6
 @pytest.mark.parametrize("profile", ["L", "M.64"])
 @pytest.mark.parametrize("prec", [1, 0])
 def test_bc7_queries_match_oracle(N, ctx, profile, prec):
-    """F_uv and F_uvt as BC7 mode-6 blocks (codec 1): random blocks of every index pattern
-    and p-bit, decoded at random points."""
+    """F_uv and F_uvt as BC7 blocks (codec 1): random blocks of modes 4, 5 and 6 mixed, every
+    index pattern, rotation, index selection and p-bit, decoded at random points."""
     m = I.random_hybrid_model(profile=profile, config=80, codec=1)
     assert m["fuv"].shape[-1] == 16
     q = I.uniform_queries(4096 + 91, I.rng(80, I.P_QUERY))
@@ -367,7 +367,7 @@ def test_bc7_pages_with_mixed_codecs(N, ctx, prec):
 
 
 def _bc7_all_texels(blocks):
-    """Oracle decode of every texel of [n][16] mode-6 blocks -> [n][16][4]."""
+    """Oracle decode of every texel of [n][16] BC7 blocks -> [n][16][4]."""
     n = blocks.shape[0]
     ys, xs = np.meshgrid(np.arange(4), np.arange(4), indexing="ij")
     b = np.repeat(blocks[:, None, :], 16, axis=1)
@@ -375,8 +375,10 @@ def _bc7_all_texels(blocks):
 
 
 def test_bc7_block_decode_is_bit_exact(N):
-    """The device mode-6 texel decode, byte for byte: the hand-built golden blocks and
-    200,003 random blocks (every index pattern and p-bit) against the oracle."""
+    """The device BC7 texel decode, byte for byte: the hand-built golden blocks, 200,003
+    random mode-6 blocks (every index pattern and p-bit) and 200,003 random blocks of modes
+    4, 5 and 6 mixed (every rotation and index selection), against the oracle; a block of
+    another mode decodes to 0."""
     import torch
     from tests.test_oracle_hybrid import _golden_bc7
     rows = _golden_bc7()
@@ -387,6 +389,11 @@ def test_bc7_block_decode_is_bit_exact(N):
     blocks = I.random_bc7m6((200_003,), np.random.default_rng(84))
     got = N.bc7_decode_blocks(torch.from_numpy(blocks).cuda()).cpu().numpy()
     np.testing.assert_array_equal(got, _bc7_all_texels(blocks))
+    mixed = I.random_bc7((200_003,), np.random.default_rng(85))
+    mixed[:7, 0] = [0x00, 0x01, 0x02, 0x04, 0x08, 0x80, 0x00]     # modes 0-3 and 7, no mode
+    got = N.bc7_decode_blocks(torch.from_numpy(mixed).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(got, _bc7_all_texels(mixed))
+    np.testing.assert_array_equal(got[:7], 0)
     assert N.bc7_decode_blocks(torch.from_numpy(blocks[:0]).cuda()).shape == (0, 16, 4)
     with pytest.raises(N.NdgiError):   # misaligned source
         raw = torch.from_numpy(blocks[:5]).cuda().view(-1)

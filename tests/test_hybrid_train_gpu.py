@@ -389,18 +389,31 @@ def test_bc4_encoder_matches_oracle_bit_for_bit(N, ctx):
     np.testing.assert_array_equal(got, O.encode_bc4(tex))
 
 
-def test_bc7_encoder_matches_oracle_bit_for_bit(N, ctx):
-    import torch
+def _blocks_bc7(seed):
+    """Encoder inputs [n][16][4]: random, smooth and grey texels (_test_blocks), decodes of
+    random mode-6 blocks and of random mode-4 and mode-5 blocks, constant blocks."""
     from tests.test_oracle_encode import _test_blocks
-    g = np.random.default_rng(141)
-    dec = np.stack([O.bc7m6_decode_block(b) for b in I.random_bc7m6((200,), g)]).astype(np.int64)
-    tex = np.concatenate([_test_blocks(142), _test_blocks(143), dec,
-                          np.repeat(g.integers(0, 256, (40, 16, 1)), 4, axis=2)]).astype(np.uint8)
+    g = np.random.default_rng(seed)
+    dec6 = np.stack([O.bc7_decode_block(b) for b in I.random_bc7m6((40,), g)])
+    dec45 = np.stack([O.bc7_decode_block(b) for b in I.random_bc7((60,), g, modes=(4, 5))])
+    const = np.repeat(g.integers(0, 256, (8, 1, 4)), 16, axis=1)
+    return np.concatenate([_test_blocks(seed + 1), dec6, dec45, const,
+                           np.zeros((1, 16, 4)), np.full((1, 16, 4), 255)]).astype(np.uint8)
+
+
+def test_bc7_encoder_matches_oracle_bit_for_bit(N, ctx):
+    """The multi-mode encoder (modes 6, 5 and 4, each block its least-error candidate) writes
+    the oracle's blocks, byte for byte; and the decode of what it wrote is the oracle's decode
+    of it (both decoders pinned)."""
+    import torch
+    tex = _blocks_bc7(141)
     got = N.bc7_encode_blocks(torch.from_numpy(tex).cuda()).cpu().numpy()
-    np.testing.assert_array_equal(got, O.encode_bc7m6(tex))
-    # and the decode of what it wrote is the decode of the oracle's blocks (both decoders pinned)
+    want = O.encode_bc7(tex)
+    np.testing.assert_array_equal(got, want)
+    modes = [O.bc7_mode(b) for b in want]
+    assert {4, 5, 6} <= set(modes)                  # every mode occurs among the winners
     np.testing.assert_array_equal(N.bc7_decode_blocks(torch.from_numpy(got).cuda()).cpu().numpy(),
-                                  np.stack([O.bc7m6_decode_block(b) for b in got]))
+                                  np.stack([O.bc7_decode_block(b) for b in got]))
 
 
 @pytest.mark.parametrize("state_codec,flags,codec", [(0, 0, 0), (0, 0, 1), (1, 0, 1), (1, 0, 0), (0, 8, 0), (0, 8, 1),
