@@ -297,8 +297,8 @@ PAPER_TABLE5_MS = {"L": 0.201, "M": 0.203, "M.64": 0.314}
 
 def run_hybrid(args, torch, N, I, ctx, reps=30, warm=5):
     """The paper's own layout and decoder: a 1024 x 1024 lightmap as 64 per-tile models of
-    128 x 128 texels (F_uv 128^2 x 4 and F_uvt side^2 x 12 x 4 as BC7 mode-6 blocks, the
-    paper's format, or as four BC4 blocks per footprint; F_ut / F_vt 64 x 24 x 2 8-bit; 26
+    128 x 128 texels (F_uv 128^2 x 4 and F_uvt side^2 x 12 x 4 as BC7 blocks of modes 4, 5
+    and 6 mixed per block, the paper's format, or as four BC4 blocks per footprint; F_ut / F_vt 64 x 24 x 2 8-bit; 26
     key times), all 64 pages decoded at one t in one persistent launch, for each profile of
     Table 3, both codecs and both precisions; and profile M with the 4-texel mirrored tile
     border of the paper's VT storage (64 regions of 136^2)."""

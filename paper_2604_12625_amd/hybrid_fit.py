@@ -17,7 +17,7 @@ Arms (the supplementary ablation compares the first two; both compress after tra
 * rounded_simulation (a variant the paper does not describe): phase 1 rounds endpoints and
   weights to the block grid with straight-through gradients (BCSIM | NOISE), the export is the
   exact encoding of the rounded parameters, phase 2 fine-tunes on BCSIM | QPLANES.
-Each arm's model (BC7 mode-6 blocks as in the paper, or BC4 blocks per channel; 8-bit planes,
+Each arm's model (BC7 blocks of modes 4-6 as in the paper, or BC4 blocks per channel; 8-bit planes,
 FP16 decoder) is decoded for all 26 frames through the page decoder at their key times (FP16
 and FP32 paths), restored, and scored by tiled PSNR (one 128^2 tile per frame).
 """
@@ -117,8 +117,18 @@ def train_arm(torch, N, ctx, arm, codec, inits, tgt, keys, frames, steps1, steps
     torch.cuda.synchronize()
     losses.append((steps1 + steps2, float(tr.loss.item())))
     wall = time.perf_counter() - t0
-    return final, dict(train_ms_per_step=ms1 / steps1, wall_s=wall, encode_ms=enc_ms, loss_curve=losses,
-                       flags_phase1=int(f1), flags_export=int(fx), flags_phase2=int(f2), n_params=n_params)
+    info = dict(train_ms_per_step=ms1 / steps1, wall_s=wall, encode_ms=enc_ms, loss_curve=losses,
+                flags_phase1=int(f1), flags_export=int(fx), flags_phase2=int(f2), n_params=n_params)
+    if codec == 1:
+        info["bc7_mode_share"] = bc7_mode_share(torch, [a for m in final for a in m.arrays[:2]])
+    return final, info
+
+
+def bc7_mode_share(torch, block_arrays):
+    """Share of BC7 blocks per mode (4, 5, 6) over device arrays of 16-byte blocks."""
+    b0 = torch.cat([a.reshape(-1, 16)[:, 0] for a in block_arrays]).to(torch.int32)
+    n = max(int(b0.numel()), 1)
+    return {str(m): int(((b0 & ((2 << m) - 1)) == (1 << m)).sum().item()) / n for m in (4, 5, 6)}
 
 
 def score(torch, N, ctx, models, means, target_tiles, keys, border=0):

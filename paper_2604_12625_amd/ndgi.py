@@ -364,7 +364,8 @@ def bc4_decode_blocks(blocks, out=None, stream=None, impl=None):
 
 
 def bc7_decode_blocks(blocks, out=None, stream=None):
-    """Decode [n][16] uint8 device BC7 mode-6 blocks to [n][16 texels][4 channels] uint8."""
+    """Decode [n][16] uint8 device BC7 blocks (modes 4, 5 and 6; other modes decode to 0) to
+    [n][16 texels][4 channels] uint8."""
     import torch
     n = blocks.shape[0]
     if out is None:
