@@ -181,6 +181,23 @@ def test_binned_long_time_axis(N, ctx, grid_dt):
         assert_rel(binned[sel], O.decode(m, q[sel]), tol, f"T=64 prec {prec}")
 
 
+@pytest.mark.parametrize("T", [24, 25, 31])
+def test_binned_lds_window_capacities(N, ctx, T):
+    """Grid-aligned tiles (9 x 9 nodes per key) with windows up to the largest that the
+    LDS-staged decode takes (T = 31: 2511 of its 2560 uint4); queries reach the region's
+    first and last texel rows and columns (map edges, non-finite inputs)."""
+    m = I.random_model(256, 160, 64, 40, T, np.float16, np.float16, config=60)
+    q = np.concatenate([I.uniform_queries(30000, I.rng(60, I.P_QUERY, T)), EDGE_Q, BAD_Q,
+                        I.texel_centre_queries(256, 160, [0.61])])
+    for prec, tol in ((1, TOL16), (0, TOL32)):
+        direct = _dec(N, ctx, m, q, prec)
+        binned, _ = _dec_binned(N, ctx, m, q, prec)
+        np.testing.assert_array_equal(binned, direct)
+        ok = np.isfinite(q).all(axis=1)
+        sel = np.flatnonzero(ok)[np.random.default_rng(60).integers(0, ok.sum(), 2048)]
+        assert_rel(binned[sel], O.decode(m, q[sel]), tol, f"T={T} prec {prec}")
+
+
 @pytest.mark.parametrize("T", [2, 3])
 def test_binned_full_resolution_grid_window(N, ctx, T):
     """A grid at the texel resolution: a 32-texel tile's window is 35 x 35 nodes, more nodes
