@@ -93,6 +93,7 @@ constexpr int64_t kAccMaxBytes = 64 * 1024;
 // (g, i) = (lane >> 4, lane & 15) supplies sample 4 q + g, unit i of both slabs at K step q;
 // the 16 x 16 result sits in lane (g, i), element r, as row 4 g + r, column i.
 constexpr int kSlab = 64 * 16;
+constexpr int kSlabsPerWave = 3;   // A, B, and C holding the decoder inputs during the backward
 
 __device__ __forceinline__ void slab_store(float* slab, int lane, const float v[16]) {
   f4v* d = (f4v*)(slab + lane * 16);   // one vector type for every slab access
@@ -119,6 +120,34 @@ __device__ __forceinline__ f4v slab_sum(const float* A, int lane) {
   return acc;
 }
 
+// Where a training sample reads its features: the F_uvt taps (bilinear in the grid, linear
+// between slices), the F_ut / F_vt taps, and F_uv's footprint.
+struct SampleTaps {
+  Axis gx, gy, pu, pv;
+  NodeT ns, nk;
+  float tw[4];
+  int txs[4], tys[4];
+  int64_t fpu;
+};
+__device__ __forceinline__ SampleTaps sample_taps(const HybTrainDims& d, int x, int y, float tau) {
+  SampleTaps T;
+  T.gx = texel_axis<false>(x, d.Gu, d.W);
+  T.gy = texel_axis<false>(y, d.Gv, d.H);
+  T.ns = node_axis(tau, d.S);
+  T.nk = node_axis(tau, d.Tt);
+  tap_weights(T.gx, T.gy, T.tw);
+  const int txs[4] = {T.gx.i0, T.gx.i1, T.gx.i0, T.gx.i1}, tys[4] = {T.gy.i0, T.gy.i0, T.gy.i1, T.gy.i1};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    T.txs[i] = txs[i];
+    T.tys[i] = tys[i];
+  }
+  T.fpu = (int64_t)(y >> 2) * (d.W / 4) + (x >> 2);
+  T.pu = texel_axis<false>(x, d.U, d.W);
+  T.pv = texel_axis<false>(y, d.V, d.H);
+  return T;
+}
+
 // MODE: NDGI_TRAIN_FORWARD writes pred; NDGI_TRAIN_LOSS_GRAD adds the loss and gradients.
 // Dynamic LDS: per wave the MFMA operand slabs A, B ([64][16] each), then, with `accum`,
 // the accumulators [F_uvt endpoints (nE) | F_ut, F_vt (nP)] of the chunk's model.
@@ -138,9 +167,10 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
   extern __shared__ __align__(16) float dyn[];   // 16-byte aligned: float4 slab accesses
   const int nthr = blockDim.x, waves = nthr >> 6;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lg = lane >> 4, li = lane & 15;
-  float* const slA = dyn + wave * 2 * kSlab;
+  float* const slA = dyn + wave * kSlabsPerWave * kSlab;
   float* const slB = slA + kSlab;
-  float* const acc = dyn + waves * 2 * kSlab;
+  float* const slC = slB + kSlab;
+  float* const acc = dyn + waves * kSlabsPerWave * kSlab;
   const int64_t nE = (int64_t)d.S * (d.Gv / 4) * (d.Gu / 4) * 8, nP = d.o_mlp - d.o_ut;
   const bool bcsim = flags & NDGI_HTRAIN_BCSIM, noise = flags & NDGI_HTRAIN_NOISE, qplanes = flags & NDGI_HTRAIN_QPLANES;
   const bool direct = flags & NDGI_HTRAIN_DIRECT;
@@ -176,11 +206,16 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
     const float t = keys ? keys[f] : tau;
     // ---- features
     float xin[16];
-    const Axis gx = texel_axis<false>(x, d.Gu, d.W), gy = texel_axis<false>(y, d.Gv, d.H);
-    const NodeT ns = node_axis(tau, d.S), nk = node_axis(tau, d.Tt);
-    float tw[4];
-    tap_weights(gx, gy, tw);
-    const int txs[4] = {gx.i0, gx.i1, gx.i0, gx.i1}, tys[4] = {gy.i0, gy.i0, gy.i1, gy.i1};
+    auto plane_at = [&](int64_t off, int size, int k, int a, int c) {
+      const float v = P[off + ((int64_t)k * size + a) * 2 + c];
+      return qplanes ? rintf(__fmul_rn(255.0f, v)) * (1.0f / 255.0f) : v;
+    };
+    {
+    const SampleTaps T = sample_taps(d, x, y, tau);
+    const NodeT &ns = T.ns, &nk = T.nk;
+    const float* tw = T.tw;
+    const int *txs = T.txs, *tys = T.tys;
+    const int64_t fpu = T.fpu;
 #pragma unroll
     for (int c = 0; c < 4; ++c) xin[c] = 0.0f;
 #pragma unroll
@@ -196,15 +231,12 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
         for (int c = 0; c < 4; ++c) xin[c] = fmaf(ws * tw[i], b.v[c], xin[c]);
       }
     }
-    const int64_t fpu = (int64_t)(y >> 2) * (d.W / 4) + (x >> 2);
-    const BcTex bu = sim_texel(P + fpu * 8, P + d.o_uvw + ((int64_t)y * d.W + x) * d.cw, bcsim, direct, d.codec);
+    {
+      const BcTex bu = sim_texel(P + fpu * 8, P + d.o_uvw + ((int64_t)y * d.W + x) * d.cw, bcsim, direct, d.codec);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) xin[4 + c] = bu.v[c];
-    const Axis pu = texel_axis<false>(x, d.U, d.W), pv = texel_axis<false>(y, d.V, d.H);
-    auto plane_at = [&](int64_t off, int size, int k, int a, int c) {
-      const float v = P[off + ((int64_t)k * size + a) * 2 + c];
-      return qplanes ? rintf(__fmul_rn(255.0f, v)) * (1.0f / 255.0f) : v;
-    };
+      for (int c = 0; c < 4; ++c) xin[4 + c] = bu.v[c];
+    }
+    const Axis &pu = T.pu, &pv = T.pv;
 #pragma unroll
     for (int pl = 0; pl < 2; ++pl) {
       const int64_t off = pl ? d.o_vt : d.o_ut;
@@ -222,6 +254,7 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
         xin[8 + 2 * pl + c] = acc;
       }
     }
+    }
     if (noise) {
 #pragma unroll
       for (int c = 0; c < 12; ++c) xin[c] += (1.0f / 256.0f) * hyb_noise(noise_base, (uint64_t)s * 16u + (uint64_t)c);
@@ -234,20 +267,21 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
       xin[14] = 2.0f * sn * cs;
       xin[15] = fmaf(cs, cs, -sn * sn);
     }
-    // ---- decoder forward (pre-activations kept; activations recomputed when needed)
-    float a1[HD], a2[HD];
-#pragma unroll
-    for (int j = 0; j < HD; ++j) {
+    // ---- decoder forward.  Only the layer-2 pre-activations are kept: a layer-1
+    // pre-activation is recomputed (the same FMA chain) wherever it is needed again, so the
+    // backward holds one 16-unit block of them at a time.
+    auto pre1 = [&](int j) {
       float acc = sw[Sh::oB1 + j];
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc = fmaf(sw[Sh::oW1 + j * 16 + i], xin[i], acc);
-      a1[j] = acc;
-    }
+      return acc;
+    };
+    float a2[HD];
 #pragma unroll
     for (int j = 0; j < HD; ++j) a2[j] = sw[Sh::oB2 + j];
 #pragma unroll
     for (int k = 0; k < HD; ++k) {
-      const float h = gelu<NDGI_PREC_F32>(a1[k]);
+      const float h = gelu<NDGI_PREC_F32>(pre1(k));
 #pragma unroll
       for (int j = 0; j < HD; ++j) a2[j] = fmaf(sw[Sh::oW2 + j * HD + k], h, a2[j]);
     }
@@ -313,16 +347,38 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
         for (int c = 0; c < 3; ++c) dh = fmaf(sw[Sh::oW3 + c * HD + j], dout[c], dh);
         a2[j] = dh * gelu_grad(a2[j]);   // a2 now holds d loss / d a2
       }
-      // Layer 2: dW2[j][k] = sum g2[j] h1[k], db2 = sum g2 (g2 = d loss / d a2); the input
-      // gradient DH[k][s] = sum_j W2[j][k] g2[s][j] on MFMA as well (W2 from LDS as the A
-      // operand, the staged g2 slab as B), handed back to the sample lanes through LDS, and
-      // a1 overwritten by g1 = DH gelu'(a1) block by block.
+      // Layers 2 and 1, one 16-unit block kb of layer 1 at a time.  Layer 2: dW2[j][k] =
+      // sum g2[j] h1[k], db2 = sum g2 (g2 = d loss / d a2); the input gradient DH[k][s] =
+      // sum_j W2[j][k] g2[s][j] on MFMA as well (W2 from LDS as the A operand, the staged g2
+      // slab as B), handed back to the sample lanes through LDS, giving the block's
+      // g1 = DH gelu'(a1).  Layer 1 for that block: dW1[k][i] = sum g1[k] x[i], db1 = sum g1,
+      // and its share of the input gradient DX[i][s] = sum_k W1[k][i] g1[s][k], on MFMA.
+      slab_store(slC, lane, xin);
+      // the decoder inputs are read back from the lane's own row of slab C (written by this
+      // lane, so no barrier) rather than kept in registers through the backward
+      auto pre1c = [&](int j) {
+        const f4v* xr = (const f4v*)(slC + lane * 16);
+        float acc = sw[Sh::oB1 + j];
 #pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const f4v xq = xr[q];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc = fmaf(sw[Sh::oW1 + j * 16 + 4 * q + e], xq[e], acc);
+        }
+        return acc;
+      };
+      f4v dx4[4];
+#pragma unroll
+      for (int sb = 0; sb < 4; ++sb) dx4[sb] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 1
       for (int kb = 0; kb < HD / 16; ++kb) {
+        float a1b[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) a1b[u] = pre1c(16 * kb + u);
         {
           float v[16];
 #pragma unroll
-          for (int u = 0; u < 16; ++u) v[u] = gelu<NDGI_PREC_F32>(a1[16 * kb + u]);
+          for (int u = 0; u < 16; ++u) v[u] = gelu<NDGI_PREC_F32>(a1b[u]);
           slab_store(slB, lane, v);
         }
         f4v dh4[4];
@@ -362,23 +418,12 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
           for (int q = 0; q < 4; ++q) {
             const f4v dq = own[q];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) a1[16 * kb + 4 * q + e] = dq[e] * gelu_grad(a1[16 * kb + 4 * q + e]);
+            for (int e = 0; e < 4; ++e) a1b[4 * q + e] = dq[e] * gelu_grad(a1b[4 * q + e]);   // now g1
           }
         }
+        slab_store(slA, lane, a1b);
         __syncthreads();
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      // Layer 1: dW1[k][i] = sum g1[k] x[i], db1 = sum g1; the input gradient
-      // DX[i][s] = sum_k W1[k][i] g1[s][k] on MFMA, handed back to the sample lanes
-      slab_store(slB, lane, xin);
-      f4v dx4[4];
-#pragma unroll
-      for (int sb = 0; sb < 4; ++sb) dx4[sb] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-      for (int kb = 0; kb < HD / 16; ++kb) {
-        slab_store(slA, lane, a1 + 16 * kb);
-        __syncthreads();
-        const f4v w1 = slab_outer(slA, slB, lane);
+        const f4v w1 = slab_outer(slA, slC, lane);
 #pragma unroll
         for (int r = 0; r < 4; ++r) atomicAdd(gm + Sh::oW1 + (16 * kb + 4 * lg + r) * 16 + li, w1[r]);
         const f4v b1 = slab_sum(slA, lane);
@@ -410,6 +455,18 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
         }
       }
       if (!live) continue;
+      // The taps again, recomputed from the sample's texel and time rather than kept through
+      // the decoder backward (the empty asm hides that they equal the forward's, so they are
+      // not reused from it).
+      int xr = x, yr = y;
+      float taur = tau;
+      asm volatile("" : "+v"(xr), "+v"(yr), "+v"(taur));
+      const SampleTaps T = sample_taps(d, xr, yr, taur);
+      const NodeT &ns = T.ns, &nk = T.nk;
+      const float* tw = T.tw;
+      const int *txs = T.txs, *tys = T.tys;
+      const int64_t fpu = T.fpu;
+      const Axis &pu = T.pu, &pv = T.pv;
       // ---- feature gradients (straight-through for the simulated maps).  Per F_uvt slice the
       // four taps' endpoint terms are first summed per 4x4 footprint (taps 0/1 and 2/3 share
       // one when their columns do, taps 0/2 and 1/3 when their rows do), so each footprint
@@ -463,6 +520,8 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
           }
         }
       }
+      // F_uv's texel again (recomputed rather than kept through the decoder backward)
+      const BcTex bu = sim_texel(P + fpu * 8, P + d.o_uvw + ((int64_t)y * d.W + x) * d.cw, bcsim, direct, d.codec);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         if (!direct) {
@@ -761,7 +820,7 @@ int ndgi_hybrid_train_step(ndgi_ctx* c, ndgi_hybrid_train_state* st, const ndgi_
     const int64_t cap = (int64_t)c->n_cu * 8;
     if (wgs > cap) wgs = cap;
     const int64_t nE = (int64_t)d.S * (d.Gv / 4) * (d.Gu / 4) * 8, nP = d.o_mlp - d.o_ut;
-    const size_t slab_bytes = (size_t)(nthr / 64) * 2 * kSlab * sizeof(float);
+    const size_t slab_bytes = (size_t)(nthr / 64) * kSlabsPerWave * kSlab * sizeof(float);
     const size_t acc_bytes = (size_t)(nE + nP) * sizeof(float);
     const size_t sw_bytes = ((size_t)ndgi_hybrid_mlp_size(d.hidden) * sizeof(float) + 15) / 16 * 16;   // static LDS
     int lds_max = 0;
