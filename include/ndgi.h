@@ -100,7 +100,9 @@ typedef struct ndgi_ctx ndgi_ctx;
  * out == NULL), HIP, OUT_OF_MEMORY. */
 int ndgi_create(ndgi_ctx** out, int32_t device);
 
-/* Release the context, its workspace and any captured graphs.  NULL is a no-op. */
+/* Release the context, its workspace and any captured graphs.  NULL is a no-op.  Every
+ * release is attempted and the context is freed in any case; Errors: HIP (the first release
+ * that failed). */
 int ndgi_destroy(ndgi_ctx* ctx);
 
 /* Message describing the calling thread's most recent failed call ("" if none).
@@ -293,7 +295,7 @@ int ndgi_decode_pages_graph(ndgi_ctx* ctx, const ndgi_model* models_dev, int32_t
  * (16*tile_w) x (4*tile_h) texel sub-tile of one page; waves_per_cu persistent waves per
  * compute unit.  tile_w, tile_h in 1..32 (page must be a multiple of both sub-tile sides,
  * checked per call); waves_per_cu in 1..32.  Also sets the launch size of ndgi_decode.
- * Drops captured graphs.  Errors: INVALID_ARG. */
+ * Drops captured graphs.  Errors: INVALID_ARG, HIP (releasing a captured graph). */
 int ndgi_set_launch(ndgi_ctx* ctx, int32_t tile_w, int32_t tile_h, int32_t waves_per_cu);
 
 /* ---------------------------------------------------------------- training */

@@ -110,13 +110,13 @@ static int launch_graph(ndgi_ctx* c, const GraphKey& key, Launch launch) {
     const int rc = launch(c->capture_stream);
     hipError_t e = hipStreamEndCapture(c->capture_stream, &graph);
     if (rc) {
-      if (graph) hipGraphDestroy(graph);
+      if (graph) (void)hipGraphDestroy(graph);   // the launch's own error is the one reported
       return rc;
     }
     if (e != hipSuccess) return fail(NDGI_ERR_HIP, "pages graph: capture failed: %s", hipGetErrorString(e));
     hipGraphExec_t exec = nullptr;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);   // the executable graph does not need it
     if (e != hipSuccess) return fail(NDGI_ERR_HIP, "pages graph: instantiate failed: %s", hipGetErrorString(e));
     it = c->graphs.emplace(key, exec).first;
   }
@@ -171,15 +171,20 @@ int ndgi_create(ndgi_ctx** out, int32_t device) {
 int ndgi_destroy(ndgi_ctx* c) {
   clear_error();
   if (!c) return NDGI_OK;
-  hipSetDevice(c->device);
-  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
-  if (c->capture_stream) hipStreamDestroy(c->capture_stream);
-  hipFree(c->flags_dev);
-  hipFree(c->partials_dev);
-  hipFree(c->loss_part_dev);
-  hipFree(c->stage_dev);
-  hipFree(c->dec_ws);
+  // best-effort teardown: every release is attempted, the first failure is reported
+  hipError_t first = hipSetDevice(c->device);
+  auto keep = [&](hipError_t e) {
+    if (first == hipSuccess) first = e;
+  };
+  for (auto& kv : c->graphs) keep(hipGraphExecDestroy(kv.second));
+  if (c->capture_stream) keep(hipStreamDestroy(c->capture_stream));
+  keep(hipFree(c->flags_dev));
+  keep(hipFree(c->partials_dev));
+  keep(hipFree(c->loss_part_dev));
+  keep(hipFree(c->stage_dev));
+  keep(hipFree(c->dec_ws));
   delete c;
+  if (first != hipSuccess) return fail(NDGI_ERR_HIP, "destroy: %s", hipGetErrorString(first));
   return NDGI_OK;
 }
 
@@ -405,8 +410,8 @@ int ndgi_set_launch(ndgi_ctx* c, int32_t tile_w, int32_t tile_h, int32_t waves_p
   if (!c) return fail(NDGI_ERR_INVALID_ARG, "set_launch: ctx is NULL");
   if (tile_w < 1 || tile_w > 32 || tile_h < 1 || tile_h > 32 || waves_per_cu < 1 || waves_per_cu > 32)
     return fail(NDGI_ERR_INVALID_ARG, "set_launch: tile_w, tile_h, waves_per_cu must be in [1, 32]");
-  hipSetDevice(c->device);
-  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+  NDGI_HIP(hipSetDevice(c->device));
+  for (auto& kv : c->graphs) NDGI_HIP(hipGraphExecDestroy(kv.second));
   c->graphs.clear();
   c->tile_w = tile_w;
   c->tile_h = tile_h;
