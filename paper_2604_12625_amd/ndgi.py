@@ -229,8 +229,8 @@ class Context:
 
     def close(self):
         if self.h:
-            lib().ndgi_destroy(self.h)
-            self.h = C.c_void_p()
+            h, self.h = self.h, C.c_void_p()
+            check(lib().ndgi_destroy(h), "ndgi_destroy")
 
     def __del__(self):
         try:
