@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libndgi.so")
@@ -188,6 +189,19 @@ class DeviceModel:
     def desc_bytes(self) -> bytes:
         return bytes(self.desc)
 
+    def to_numpy(self) -> dict:
+        """Host copy in from_numpy's layout."""
+        return dict(W=self.W, H=self.H, Gw=self.Gw, Gh=self.Gh, T=self.T, bc4=self.bc4.cpu().numpy(),
+                    grid=self.grid.cpu().numpy(), mlp=self.mlp.cpu().numpy())
+
+    def save(self, path):
+        """The compressed model as an .npz file (arrays only, no pickled objects)."""
+        np.savez(path, **to_npz(self.to_numpy()))
+
+    @classmethod
+    def load(cls, path, device="cuda"):
+        return cls.from_numpy(from_npz(path), device)
+
 
 class HybridModel:
     """A model in the paper's hybrid layout (F_uv, F_uvt, F_ut, F_vt, key times, decoder)
@@ -214,6 +228,33 @@ class HybridModel:
 
     def desc_bytes(self) -> bytes:
         return bytes(self.desc)
+
+    def to_numpy(self) -> dict:
+        """Host copy in from_numpy's layout."""
+        d = self.desc
+        out = dict(W=d.W, H=d.H, Gu=d.Gu, Gv=d.Gv, S=d.S, U=d.U, V=d.V, Tt=d.Tt, hidden=d.hidden, codec=d.codec)
+        for k, a in zip(("fuv", "fuvt", "fut", "fvt", "keys", "mlp"), self.arrays):
+            out[k] = a.cpu().numpy()
+        return out
+
+    def save(self, path):
+        """The compressed model as an .npz file (arrays only, no pickled objects)."""
+        np.savez(path, **to_npz(self.to_numpy()))
+
+    @classmethod
+    def load(cls, path, device="cuda"):
+        return cls.from_numpy(from_npz(path), device)
+
+
+def to_npz(d: dict) -> dict:
+    """A dict of numbers, strings and arrays as .npz entries: each value becomes an array."""
+    return {k: np.asarray(v) for k, v in d.items()}
+
+
+def from_npz(path) -> dict:
+    """Inverse of to_npz (allow_pickle stays off): 0-d arrays become Python scalars."""
+    with np.load(path) as z:
+        return {k: (z[k].item() if z[k].ndim == 0 else z[k]) for k in z.files}
 
 
 def hybrid_mlp_size(hidden: int) -> int:

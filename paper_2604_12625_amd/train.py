@@ -54,6 +54,31 @@ class Trainer:
     def step_count(self) -> int:
         return int(self.state.step)
 
+    # checkpoint -----------------------------------------------------------------------
+    def save(self, path):
+        """Checkpoint as an .npz file (arrays only): sizes, parameters, Adam moments, step
+        count and optimiser settings.  Trainer.load resumes from it; the gradients are not
+        part of the state (every step rebuilds them)."""
+        st = self.state
+        np.savez(path, **N.to_npz(dict(
+            kind="ndgi_train", W=self.W, H=self.H, Gw=self.Gw, Gh=self.Gh, T=self.T,
+            params=self.params.cpu().numpy(), m=self.m.cpu().numpy(), v=self.v.cpu().numpy(), step=int(st.step),
+            lr_feat=st.lr_feat, lr_mlp=st.lr_mlp, beta1=st.beta1, beta2=st.beta2, eps=st.eps)))
+
+    @classmethod
+    def load(cls, ctx: N.Context, path, device="cuda") -> "Trainer":
+        import torch
+        z = N.from_npz(path)
+        if z.get("kind") != "ndgi_train":
+            raise ValueError(f"{path}: not a Trainer checkpoint")
+        dims = {k: int(z[k]) for k in ("W", "H", "Gw", "Gh", "T")}
+        tr = cls(ctx, dict(dims=dims, flat=torch.from_numpy(z["params"])), lr_feat=z["lr_feat"], lr_mlp=z["lr_mlp"],
+                 betas=(z["beta1"], z["beta2"]), eps=z["eps"], device=device)
+        tr.m.copy_(torch.from_numpy(z["m"]))
+        tr.v.copy_(torch.from_numpy(z["v"]))
+        tr.state.step = int(z["step"])
+        return tr
+
     def _run(self, mode, samples=None, target=None, pred=None, grad_pred=None, stream=None):
         b = N.NdgiBatch(N._ptr(samples), 0 if samples is None else samples.shape[0],
                         N._ptr(target), N._ptr(pred), N._ptr(grad_pred))
@@ -146,17 +171,25 @@ class HybridTrainer:
     def __init__(self, ctx: N.Context, init, lr_feat=1e-3, lr_mlp=1e-3, betas=(0.9, 0.999), eps=1e-8,
                  seed=0, per_model=0, device="cuda"):
         import torch
-        inits = init if isinstance(init, (list, tuple)) else [init]
-        d = inits[0]["dims"]
-        self.ctx, self.d, self.M = ctx, dict(d), len(inits)
+        if isinstance(init, dict) and "flat" in init:   # a checkpoint's flat state of n_models models
+            d, M = init["dims"], int(init["n_models"])
+        else:
+            inits = init if isinstance(init, (list, tuple)) else [init]
+            d, M = inits[0]["dims"], len(inits)
+        self.ctx, self.d, self.M = ctx, dict(d), M
         dims = [d[k] for k in ("W", "H", "Gu", "Gv", "S", "U", "V", "Tt", "hidden")]
         self.codec = int(d.get("codec", N.CODEC_BC4))
         n = int(N.lib().ndgi_hybrid_train_param_count(*dims, self.codec))
         self.n_params = n * self.M
-        feats = [np.concatenate([np.asarray(m[k], dtype=np.float32).ravel() for k in HYB_KEYS[:-1]]) for m in inits]
-        mlps = [np.asarray(m["mlp"], dtype=np.float32).ravel() for m in inits]
-        self.n_feat = feats[0].size
-        flat = np.concatenate(feats + mlps)
+        self.n_feat = n - N.hybrid_mlp_size(d["hidden"])
+        if isinstance(init, dict) and "flat" in init:
+            flat = np.asarray(init["flat"], dtype=np.float32)
+        else:
+            feats = [np.concatenate([np.asarray(m[k], dtype=np.float32).ravel() for k in HYB_KEYS[:-1]])
+                     for m in inits]
+            mlps = [np.asarray(m["mlp"], dtype=np.float32).ravel() for m in inits]
+            assert feats[0].size == self.n_feat, (feats[0].size, self.n_feat)
+            flat = np.concatenate(feats + mlps)
         assert flat.size == self.n_params, (flat.size, self.n_params)
         self.params = torch.from_numpy(flat).to(device)
         self.grads = torch.zeros_like(self.params)
@@ -193,6 +226,36 @@ class HybridTrainer:
                               N._ptr(pred))
         N.check(N.lib().ndgi_hybrid_train_step(self.ctx.h, C.byref(self.state), C.byref(b), mode, flags,
                                                self.loss.data_ptr(), N._stream(stream)), "ndgi_hybrid_train_step")
+
+    def save(self, path):
+        """Checkpoint as an .npz file (arrays only): sizes and key times, parameters, Adam
+        moments, step count, optimiser settings and the noise seed (the noise stream is a
+        function of seed and step, so a resumed run draws what the uninterrupted one would).
+        HybridTrainer.load resumes from it."""
+        st = self.state
+        d = {k: v for k, v in self.d.items() if k != "keys"}
+        keys = np.asarray(self.d.get("keys", []), dtype=np.float32)
+        np.savez(path, **N.to_npz(dict(
+            kind="ndgi_hybrid_train", n_models=self.M, per_model=int(st.per_model), seed=int(st.seed),
+            keys=keys, params=self.params.cpu().numpy(), m=self.m.cpu().numpy(), v=self.v.cpu().numpy(),
+            step=int(st.step), lr_feat=st.lr_feat, lr_mlp=st.lr_mlp, beta1=st.beta1, beta2=st.beta2, eps=st.eps,
+            **{"dim_" + k: v for k, v in d.items()})))
+
+    @classmethod
+    def load(cls, ctx: N.Context, path, device="cuda") -> "HybridTrainer":
+        import torch
+        z = N.from_npz(path)
+        if z.get("kind") != "ndgi_hybrid_train":
+            raise ValueError(f"{path}: not a HybridTrainer checkpoint")
+        dims = {k[4:]: int(v) for k, v in z.items() if k.startswith("dim_")}
+        dims["keys"] = np.asarray(z["keys"], dtype=np.float32).reshape(-1)
+        tr = cls(ctx, dict(dims=dims, n_models=z["n_models"], flat=z["params"]), lr_feat=z["lr_feat"],
+                 lr_mlp=z["lr_mlp"], betas=(z["beta1"], z["beta2"]), eps=z["eps"], seed=z["seed"],
+                 per_model=z["per_model"], device=device)
+        tr.m.copy_(torch.from_numpy(z["m"]))
+        tr.v.copy_(torch.from_numpy(z["v"]))
+        tr.state.step = int(z["step"])
+        return tr
 
     def set_lr(self, lr_feat=None, lr_mlp=None):
         if lr_feat is not None:

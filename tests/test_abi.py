@@ -101,3 +101,21 @@ def test_product_package_never_imports_the_oracle():
             "assert not bad, bad\n")
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr
+
+
+def test_npz_checkpoint_format_round_trips_without_pickle(tmp_path):
+    """Checkpoints and saved models are plain .npz arrays: numbers, strings and arrays come
+    back as they went in, through a loader that refuses pickled objects."""
+    import numpy as np
+    from paper_2604_12625_amd import ndgi as N
+    d = dict(kind="ndgi_train", W=64, lr=1e-3, step=7, a=np.arange(6, dtype=np.float32).reshape(2, 3),
+             keys=np.zeros(0, np.float32))
+    p = tmp_path / "c.npz"
+    np.savez(p, **N.to_npz(d))
+    with np.load(p, allow_pickle=False) as z:
+        assert set(z.files) == set(d)
+    back = N.from_npz(p)
+    assert back["kind"] == "ndgi_train" and back["W"] == 64 and back["step"] == 7
+    assert isinstance(back["W"], int) and abs(back["lr"] - 1e-3) < 1e-18
+    np.testing.assert_array_equal(back["a"], d["a"])
+    assert back["keys"].shape == (0,)

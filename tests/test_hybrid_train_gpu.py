@@ -382,6 +382,39 @@ def _blocks_bc4(seed):
                            np.full((2, 16), 100), np.full((2, 16), 255), np.zeros((2, 16), np.int64)]).astype(np.uint8)
 
 
+@pytest.mark.parametrize("codec", [0, 1])
+def test_checkpoint_resumes_the_run(N, ctx, tmp_path, codec):
+    """HybridTrainer.save / load of a two-model state with key times: the state comes back
+    exactly, and the resumed trainer's next noisy steps see the uninterrupted one's losses
+    (the noise is a function of seed and step)."""
+    import torch
+    from paper_2604_12625_amd.train import HybridTrainer
+    sts = [_state(16, seed=170 + i, codec=codec) for i in range(2)]
+    a = HybridTrainer(ctx, sts, lr_feat=1e-2, lr_mlp=1e-3, seed=9, per_model=256)
+    x, y, f, tgt = _samples(sts[0], 512, seed=171)
+    smp, tg = _dev(N, x, y, f, np.concatenate([tgt, tgt]))
+    for _ in range(3):
+        a.step(smp, tg, N.HTRAIN_NOISE)
+    p = tmp_path / "hyb.npz"
+    a.save(p)
+    b = HybridTrainer.load(ctx, p)
+    assert b.state.step == a.state.step == 3 and b.M == 2 and b.codec == codec
+    for name in ("params", "m", "v"):
+        assert torch.equal(getattr(a, name), getattr(b, name)), name
+    assert torch.equal(a.keys, b.keys)
+    # the first step reads identical parameters (its FP64 loss sums differ in order only);
+    # the second follows updates whose FP32 gradient sums were added in another order
+    for rel in (1e-12, 1e-6):
+        la = float(a.step(smp, tg, N.HTRAIN_NOISE).item())
+        lb = float(b.step(smp, tg, N.HTRAIN_NOISE).item())
+        assert abs(la - lb) <= rel * abs(la), (la, lb, rel)
+    m = b.export(N.DTYPE_F16, model=1)
+    m.save(tmp_path / "m.npz")
+    m2 = N.HybridModel.load(tmp_path / "m.npz")
+    for u, v in zip(m.arrays, m2.arrays):
+        assert torch.equal(u, v)
+
+
 def test_bc4_encoder_matches_oracle_bit_for_bit(N, ctx):
     import torch
     tex = _blocks_bc4(140)

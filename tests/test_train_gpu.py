@@ -286,3 +286,39 @@ def test_c4_sized_batch_runs_every_accumulation_path(env):
     gr = tr.split(tr.grads)
     for key in ("mlp", "grid", "endpoints", "weights"):
         assert_grad(gr[key].cpu().numpy(), ref[key], key)
+
+
+def test_checkpoint_resumes_the_run(env, tmp_path):
+    """Trainer.save / Trainer.load: the state comes back exactly, and the resumed trainer's
+    next steps see the losses of the uninterrupted one (Adam moments and step count
+    restored; the sums differ only in atomic order)."""
+    torch, N, TR, ctx = env
+    st, x, y, k, tgt = problem(64, 32, 16, 8, 6, 4096, seed=17)
+    smp, tg = device_batch(torch, x, y, k, tgt)
+    a = TR.Trainer(ctx, st, lr_feat=1e-2, lr_mlp=1e-3)
+    for _ in range(3):
+        a.step(smp, tg)
+    p = tmp_path / "train.npz"
+    a.save(p)
+    b = TR.Trainer.load(ctx, p)
+    assert b.step_count == a.step_count == 3 and b.n_params == a.n_params
+    for name in ("params", "m", "v"):
+        assert torch.equal(getattr(a, name), getattr(b, name)), name
+    # the first step reads identical parameters (its FP64 loss sums differ in order only);
+    # the second follows updates whose FP32 gradient sums were added in another order
+    for rel in (1e-12, 1e-6):
+        la, lb = float(a.step(smp, tg).item()), float(b.step(smp, tg).item())
+        assert abs(la - lb) <= rel * abs(la), (la, lb, rel)
+    with pytest.raises(ValueError):
+        TR.HybridTrainer.load(ctx, p)
+
+
+def test_exported_model_save_load_decodes_the_same(env, tmp_path):
+    torch, N, TR, ctx = env
+    st, x, y, k, tgt = problem(64, 32, 16, 8, 6, 1024, seed=18)
+    dm = TR.Trainer(ctx, st).export()
+    p = tmp_path / "model.npz"
+    dm.save(p)
+    dm2 = N.DeviceModel.load(p)
+    q = torch.from_numpy(I.uniform_queries(5000, I.rng(18, I.P_QUERY))).cuda()
+    assert torch.equal(ctx.decode(dm, q, N.PREC_F16), ctx.decode(dm2, q, N.PREC_F16))
