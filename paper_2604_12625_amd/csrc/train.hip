@@ -399,8 +399,12 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const float* __restrict
   }
 }
 
+typedef float nf4 __attribute__((ext_vector_type(4)));
+constexpr int64_t kLlcBytes = 256ll << 20;   // MI355X last-level (Infinity) cache
+
 // Dense Adam (bias-corrected, as torch.optim.Adam), projection of the BC parameters to
 // [0, 1], gradient reset.  Four parameters per thread; segment boundaries are multiples of 4.
+template <bool NT>
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __restrict__ gr, float* __restrict__ m,
                                                float* __restrict__ v, int64_t n, int64_t off_g, int64_t off_mlp,
                                                float lr_feat, float lr_mlp, float b1, float b2, float eps,
@@ -413,11 +417,18 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __re
     const bool clampseg = i0 < off_g;
     const float ss = i0 < off_mlp ? step_feat : step_mlp;
     if (i0 + 4 <= n) {
-      float4 P = *(float4*)(p + i0), Gv = *(float4*)(gr + i0), M = *(float4*)(m + i0), V = *(float4*)(v + i0);
-      float* pp = &P.x;
-      float* gg = &Gv.x;
-      float* mm = &M.x;
-      float* vv = &V.x;
+      // NT: streaming (non-temporal) accesses for a state larger than the last-level cache, so
+      // that its lines do not displace what the next gradient pass re-reads
+      auto ld = [&](const float* q) {
+        return NT ? __builtin_nontemporal_load((const nf4*)q) : *(const nf4*)q;
+      };
+      auto st = [&](float* q, nf4 x) {
+        if constexpr (NT) __builtin_nontemporal_store(x, (nf4*)q);
+        else *(nf4*)q = x;
+      };
+      const nf4 P = ld(p + i0), Gv = ld(gr + i0), M = ld(m + i0), V = ld(v + i0);
+      float pp[4] = {P.x, P.y, P.z, P.w}, gg[4] = {Gv.x, Gv.y, Gv.z, Gv.w}, mm[4] = {M.x, M.y, M.z, M.w},
+            vv[4] = {V.x, V.y, V.z, V.w};
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         mm[e] = b1 * mm[e] + (1.0f - b1) * gg[e];
@@ -427,10 +438,10 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __re
         if (clampseg) np = fminf(fmaxf(np, 0.0f), 1.0f);
         pp[e] = np;
       }
-      *(float4*)(p + i0) = P;
-      *(float4*)(m + i0) = M;
-      *(float4*)(v + i0) = V;
-      *(float4*)(gr + i0) = make_float4(0, 0, 0, 0);
+      st(p + i0, (nf4){pp[0], pp[1], pp[2], pp[3]});
+      st(m + i0, (nf4){mm[0], mm[1], mm[2], mm[3]});
+      st(v + i0, (nf4){vv[0], vv[1], vv[2], vv[3]});
+      st(gr + i0, (nf4){0.0f, 0.0f, 0.0f, 0.0f});
     } else {
       for (int64_t i = i0; i < n; ++i) {
         const float gg = gr[i];
@@ -624,8 +635,15 @@ int launch_adam(ndgi_ctx* c, float* p, float* g, float* m, float* v, int64_t n, 
   const double bc2 = 1.0 - pow((double)beta2, (double)step);
   const float sf = (float)((double)lr_feat / bc1), sm = (float)((double)lr_mlp / bc1);
   const float isb = (float)(1.0 / sqrt(bc2));
-  hipLaunchKernelGGL(k_adam, dim3(grid_for((n + 3) / 4, c->n_cu * 16)), dim3(256), 0, s, p, g, m, v, n, clamp_end,
-                     off_mlp, 1.0f, 1.0f, beta1, beta2, eps, sf, sm, isb);
+  // streaming accesses once the state (params, grads, m, v: 16 bytes a parameter) outgrows
+  // the 256 MiB last-level cache; a smaller state stays cached for the next step's gathers
+  const dim3 grid(grid_for((n + 3) / 4, c->n_cu * 16));
+  if (n * 16 > kLlcBytes)
+    hipLaunchKernelGGL(k_adam<true>, grid, dim3(256), 0, s, p, g, m, v, n, clamp_end, off_mlp, 1.0f, 1.0f, beta1,
+                       beta2, eps, sf, sm, isb);
+  else
+    hipLaunchKernelGGL(k_adam<false>, grid, dim3(256), 0, s, p, g, m, v, n, clamp_end, off_mlp, 1.0f, 1.0f, beta1,
+                       beta2, eps, sf, sm, isb);
   NDGI_HIP(hipGetLastError());
   return NDGI_OK;
 }
@@ -713,14 +731,9 @@ int ndgi_train_step(ndgi_ctx* c, ndgi_train_state* st, const ndgi_batch* b, int3
   }
   if (mode == NDGI_TRAIN_ADAM || mode == NDGI_TRAIN_FUSED) {
     const int64_t t = st->step + 1;
-    const double bc1 = 1.0 - pow((double)st->beta1, (double)t);
-    const double bc2 = 1.0 - pow((double)st->beta2, (double)t);
-    const float sf = (float)((double)st->lr_feat / bc1), sm = (float)((double)st->lr_mlp / bc1);
-    const float isb = (float)(1.0 / sqrt(bc2));
-    hipLaunchKernelGGL(k_adam, dim3(grid_for((np + 3) / 4, c->n_cu * 16)), dim3(256), 0, s, st->params, st->grads,
-                       st->adam_m, st->adam_v, np, d.off_g, d.off_mlp, 1.0f, 1.0f, st->beta1, st->beta2, st->eps, sf,
-                       sm, isb);
-    NDGI_HIP(hipGetLastError());
+    rc = launch_adam(c, st->params, st->grads, st->adam_m, st->adam_v, np, d.off_g, d.off_mlp, st->lr_feat,
+                     st->lr_mlp, st->beta1, st->beta2, st->eps, t, s);
+    if (rc) return rc;
     st->step = t;
   }
   return NDGI_OK;
