@@ -449,6 +449,25 @@ def test_bc7_encoder_matches_oracle_bit_for_bit(N, ctx):
                                   np.stack([O.bc7_decode_block(b) for b in got]))
 
 
+def test_block_encoders_at_scale_match_oracle_on_a_sample(N, ctx):
+    """65,536 blocks per encoder in one launch each (the grid-stride loops run many blocks
+    per wave): a sample of them against the oracle, byte for byte, and every block decodes."""
+    import torch
+    g = np.random.default_rng(145)
+    n = 65536
+    base = g.integers(0, 256, (n, 1, 4))
+    tex7 = np.clip(base + g.normal(0, 10, (n, 16, 4)), 0, 255).astype(np.uint8)
+    got7 = N.bc7_encode_blocks(torch.from_numpy(tex7).cuda()).cpu().numpy()
+    sel = g.choice(n, 96, replace=False)
+    np.testing.assert_array_equal(got7[sel], O.encode_bc7(tex7[sel]))
+    modes = np.array([O.bc7_mode(b) for b in got7[:4096]])
+    assert set(modes.tolist()) <= {4, 5, 6}
+    tex4 = np.clip(g.integers(0, 256, (n, 1)) + g.normal(0, 12, (n, 16)), 0, 255).astype(np.uint8)
+    got4 = N.bc4_encode_blocks(torch.from_numpy(tex4).cuda()).cpu().numpy()
+    sel = g.choice(n, 24, replace=False)
+    np.testing.assert_array_equal(got4[sel], O.encode_bc4(tex4[sel]))
+
+
 @pytest.mark.parametrize("state_codec,flags,codec", [(0, 0, 0), (0, 0, 1), (1, 0, 1), (1, 0, 0), (0, 8, 0), (0, 8, 1),
                                                      (0, 1, 0), (1, 1, 1)])
 def test_hybrid_encode_matches_oracle(N, ctx, state_codec, flags, codec):
