@@ -1367,7 +1367,7 @@ def encode_bc7m6(texels) -> np.ndarray:
     return out
 
 
-# BC7 with several modes (Sec. 3.4 compresses each block "using multiple modes"): every
+# BC7 with several modes (Sec. 3.4: the BC7 compression may pick among the format's modes): every
 # block tries mode 6 (the search above), mode 5 under each of its 4 rotations and mode 4
 # under each rotation and both index selections, and keeps the candidate of least summed
 # squared error over its 16 texels and 4 channels (ties: mode 6, then mode 5 by rotation,

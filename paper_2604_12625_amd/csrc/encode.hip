@@ -30,7 +30,7 @@
 //   refitted: each texel takes its least-error index, the lowest on ties.  One wave per
 //   block: lane (s, g) = (lane >> 2, lane & 3) holds texel s and tries indices 4g .. 4g + 3.
 //
-// * BC7 with several modes (Sec. 3.4 compresses each block "using multiple modes"): after the
+// * BC7 with several modes (Sec. 3.4: the BC7 compression may pick among the format's modes): after the
 //   mode-6 search, every block tries mode 5 under each of its 4 rotations and mode 4 under
 //   each rotation and both index selections, and keeps the candidate of least summed squared
 //   error (ties: mode 6, then mode 5 by rotation, then mode 4 by rotation then selection).  A
