@@ -254,9 +254,10 @@ int ndgi_decode_binned(ndgi_ctx* ctx, const ndgi_model* model, const float* uvt,
  * The call fails with INVALID_ARG when ndgi_decode_binned_workspace reports more than
  * NDGI_NOALLOC_SCRATCH_BYTES for (model, n) (above 2,084,576 queries on a 4096x4096 map with a
  * 1024x1024 grid, 4,061,936 on a 1024x1024 map with a 256x256 grid), before any launch.
- * No hipMalloc, hipFree or allocating library call is made.  Every call on one GPU shares that GPU's scratch, whose contents carry over from
- * the last call (nothing in it needs to start at zero): calls that overlap on one GPU, from
- * any context, stream or thread, race and give undefined results; order them on one stream.
+ * No hipMalloc, hipFree or allocating library call is made.  Every call on one GPU shares
+ * that GPU's scratch, whose contents carry over from the last call (nothing in it needs to
+ * start at zero): calls that overlap on one GPU, from any context, stream or thread, race
+ * and give undefined results; order them on one stream.
  * Errors: as ndgi_decode_binned. */
 #define NDGI_NOALLOC_SCRATCH_BYTES (64ll << 20)
 int ndgi_decode_binned_noalloc(ndgi_ctx* ctx, const ndgi_model* model, const float* uvt, int64_t n,
@@ -549,8 +550,8 @@ int ndgi_hybrid_train_step(ndgi_ctx* ctx, ndgi_hybrid_train_state* state, const 
  * paragraph): blocks of F_uv and of every F_uvt slice in the state's codec (BC4:
  * [H/4][W/4][4][8] and [S][Gv/4][Gu/4][4][8] in the encoding of ndgi_export; BC7 mode 6:
  * [H/4][W/4][16] and [S][Gv/4][Gu/4][16], endpoints and indices of the simulation, the
- * endpoints swapped and every index J replaced by 15 - J when texel 0's would be >= 8), planes rounded to 8 bits (rint of fl32(255 v)), decoder converted to
- * mlp_dtype.  The decode of the export at a training sample equals the FORWARD with
+ * endpoints swapped and every index J replaced by 15 - J when texel 0's would be >= 8),
+ * planes rounded to 8 bits (rint of fl32(255 v)), decoder converted to mlp_dtype.  The decode of the export at a training sample equals the FORWARD with
  * BCSIM | QPLANES.  Errors: INVALID_ARG. */
 int ndgi_hybrid_export(ndgi_ctx* ctx, const ndgi_hybrid_train_state* state, int32_t model,
                        uint8_t* fuv_out, uint8_t* fuvt_out, uint8_t* fut_out, uint8_t* fvt_out,
