@@ -51,13 +51,16 @@ __device__ __forceinline__ float gelu(float x) {
     for (int i = 2; i < 10; ++i) p = fmaf(t, p, kNRf[i]);
     half_erfc = t * __builtin_amdgcn_exp2f(fmaf(x * x, (float)(-0.5 * kLog2e), p));
   } else {
-    const float a = fminf(ax, 6.0f);
+    const float a = __builtin_amdgcn_fmed3f(ax, 0.0f, 6.0f);   // min(|x|, 6)
     float p = fmaf(a, kQ[5], kQ[4]);
 #pragma unroll
     for (int i = 3; i >= 0; --i) p = fmaf(a, p, kQ[i]);
     half_erfc = __builtin_amdgcn_exp2f(p);
   }
-  return fmaf(-ax, half_erfc, fmaxf(x, 0.0f));
+  // max(x, 0) as one median-of-three with the largest float (fmaxf would first quieten
+  // signalling NaNs, one more instruction per operand, and a median with +inf is folded
+  // back into fmaxf; a non-finite query's output is set to NaN explicitly anyway)
+  return fmaf(-ax, half_erfc, __builtin_amdgcn_fmed3f(x, 0.0f, 3.40282347e38f));
 }
 
 // GELU and its derivative Phi(x) + x phi(x) for training, in FP32: Phi from the same
