@@ -87,6 +87,9 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 constexpr int kHtMaxThreads = 256;
 constexpr int64_t kAccMaxBytes = 64 * 1024;
 
+// The slabs are private to their wave: ordering a wave's writes before its lanes' reads is a
+// wavefront-scope fence (wave_sync), and the waves of a workgroup never wait for each other
+// inside a round.
 // Decoder weight and bias gradients are sums over the wave's 64 samples of outer products
 // of per-sample vectors, computed on MFMA with the samples as K: each operand is staged in
 // an LDS slab [64 samples][16 units] (sample-major, written by the sample's lane).  Lane
@@ -324,7 +327,7 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
 #pragma unroll
         for (int u = 0; u < 16; ++u) v[u] = gelu<NDGI_PREC_F32>(a2[16 * jb + u]);
         slab_store(slB, lane, v);
-        __syncthreads();
+        wave_sync();
         const f4v w3 = slab_outer(slA, slB, lane);
         if (lg == 0) {
 #pragma unroll
@@ -337,7 +340,7 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
             for (int r = 0; r < 3; ++r) atomicAdd(gm + Sh::oB3 + r, b3[r]);
           }
         }
-        __syncthreads();
+        wave_sync();
         __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
@@ -387,7 +390,7 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
 #pragma unroll
         for (int jb = 0; jb < HD / 16; ++jb) {
           slab_store(slA, lane, a2 + 16 * jb);
-          __syncthreads();
+          wave_sync();
           const f4v w2 = slab_outer(slA, slB, lane);
 #pragma unroll
           for (int r = 0; r < 4; ++r) atomicAdd(gm + Sh::oW2 + (16 * jb + 4 * lg + r) * HD + 16 * kb + li, w2[r]);
@@ -406,12 +409,12 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
               dh4[sb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa, slA[(16 * sb + li) * 16 + 4 * q + lg], dh4[sb], 0, 0,
                                                              0);
           }
-          __syncthreads();
+          wave_sync();
           __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
         for (int sb = 0; sb < 4; ++sb) *(f4v*)(slB + (16 * sb + li) * 16 + 4 * lg) = dh4[sb];
-        __syncthreads();
+        wave_sync();
         {
           const f4v* own = (const f4v*)(slB + lane * 16);
 #pragma unroll
@@ -422,7 +425,7 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
           }
         }
         slab_store(slA, lane, a1b);
-        __syncthreads();
+        wave_sync();
         const f4v w1 = slab_outer(slA, slC, lane);
 #pragma unroll
         for (int r = 0; r < 4; ++r) atomicAdd(gm + Sh::oW1 + (16 * kb + 4 * lg + r) * 16 + li, w1[r]);
@@ -438,12 +441,12 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
           for (int sb = 0; sb < 4; ++sb)
             dx4[sb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa, slA[(16 * sb + li) * 16 + 4 * q + lg], dx4[sb], 0, 0, 0);
         }
-        __syncthreads();
+        wave_sync();
         __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
       for (int sb = 0; sb < 4; ++sb) *(f4v*)(slB + (16 * sb + li) * 16 + 4 * lg) = dx4[sb];
-      __syncthreads();
+      wave_sync();
       float dx[16];
       {
         const f4v* own = (const f4v*)(slB + lane * 16);
