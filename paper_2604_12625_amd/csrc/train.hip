@@ -242,28 +242,60 @@ __global__ __launch_bounds__(256) void k_train(TrainDims d, const float* __restr
     // dx[r] = dLoss/d(input_of(g, r)) of sample j
 
     // ---- scatter input gradients (straight-through BC simulation; grid corners)
-    if (valid) {
+    // A float atomic costs one memory request per 64-byte segment it touches, however many
+    // of the segment's words its lanes add to.  Lane (g, j) holds the gradients of channels
+    // 2g, 2g+1 of sample j, so atomics issued from there would cover 16 segments with four
+    // words each.  The values are first moved between lanes so that each instruction covers
+    // whole segments: the 16 endpoint words of 4 samples, the 8 weight words of 8 samples,
+    // and the two adjacent grid nodes of one corner row (8 channels each) of 4 samples.  The
+    // values and the words they go to are unchanged.
+    {
       const float da = dx[0], db = dx[1];
-      float* ge = g_ep + blk * 2;
       // straight-through derivatives 1 - J/7 and J/7, written (7 - J)/7 so that J = 7 gives
       // exactly 0 (1 - J * (1/7) contracts to an FMA that leaves -4e-8 there)
-      atomicAdd(ge + 0, da * ((float)(7 - Ja) * (1.0f / 7.0f)));
-      atomicAdd(ge + 1, da * ((float)Ja * (1.0f / 7.0f)));
-      atomicAdd(ge + 2, db * ((float)(7 - Jb) * (1.0f / 7.0f)));
-      atomicAdd(ge + 3, db * ((float)Jb * (1.0f / 7.0f)));
-      float* gw = g_w + ((size_t)y * d.W + x) * 8 + 2 * g;
-      atomicAdd(gw + 0, da * (float)(E2a - E1a) * (1.0f / 255.0f));
-      atomicAdd(gw + 1, db * (float)(E2b - E1b) * (1.0f / 255.0f));
+      const float ve0 = da * ((float)(7 - Ja) * (1.0f / 7.0f)), ve1 = da * ((float)Ja * (1.0f / 7.0f));
+      const float ve2 = db * ((float)(7 - Jb) * (1.0f / 7.0f)), ve3 = db * ((float)Jb * (1.0f / 7.0f));
+      const float vw0 = da * (float)(E2a - E1a) * (1.0f / 255.0f), vw1 = db * (float)(E2b - E1b) * (1.0f / 255.0f);
+      const int ok_j = valid ? 1 : 0;
+      const uint32_t block_j = (uint32_t)(blk >> 3), texel_j = (uint32_t)y * (uint32_t)d.W + (uint32_t)x;
+      const uint32_t row0_j = (uint32_t)k * (uint32_t)d.Gh + (uint32_t)ay.i0;
+      const uint32_t row1_j = (uint32_t)k * (uint32_t)d.Gh + (uint32_t)ay.i1;
+      const int w16 = lane & 15, s4 = lane >> 4;   // word of a 16-word segment, sample of four
+      // endpoints [block][channel][2]: word w of a block's 16 is channel w / 2, held by g = w / 4
 #pragma unroll
-      for (int yy = 0; yy < 2; ++yy)
+      for (int r = 0; r < 4; ++r) {
+        const int src = (w16 >> 2) * 16 + 4 * r + s4;
+        const float t0 = __shfl(ve0, src), t1 = __shfl(ve1, src), t2 = __shfl(ve2, src), t3 = __shfl(ve3, src);
+        const uint32_t bq = __shfl(block_j, src);
+        const int c = w16 & 3;
+        if (__shfl(ok_j, src)) atomicAdd(g_ep + (size_t)bq * 16 + w16, c == 0 ? t0 : (c == 1 ? t1 : (c == 2 ? t2 : t3)));
+      }
+      // weights [texel][channel]: eight samples per instruction, channel w8 held by g = w8 / 2
+      const int w8 = lane & 7, s8 = lane >> 3;
 #pragma unroll
-        for (int xx = 0; xx < 2; ++xx) {
-          const float w = (yy ? ay.w1 : ay.w0) * (xx ? ax.w1 : ax.w0);
-          const size_t node = ((size_t)k * d.Gh + (yy ? ay.i1 : ay.i0)) * d.Gw + (xx ? ax.i1 : ax.i0);
-          float* gg = g_grid + node * 8 + 2 * g;
-          atomicAdd(gg + 0, w * dx[2]);
-          atomicAdd(gg + 1, w * dx[3]);
+      for (int r = 0; r < 2; ++r) {
+        const int src = (w8 >> 1) * 16 + 8 * r + s8;
+        const float t0 = __shfl(vw0, src), t1 = __shfl(vw1, src);
+        const uint32_t tq = __shfl(texel_j, src);
+        if (__shfl(ok_j, src)) atomicAdd(g_w + (size_t)tq * 8 + w8, (w8 & 1) ? t1 : t0);
+      }
+      // grid [key][row][column][channel]: per corner row, columns i0, i1 (8 channels each)
+      const int ch = w16 & 7, xx = w16 >> 3;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int src = (ch >> 1) * 16 + 4 * r + s4;
+        const float g2 = __shfl(dx[2], src), g3 = __shfl(dx[3], src);
+        const float wx0 = __shfl(ax.w0, src), wx1 = __shfl(ax.w1, src);
+        const float wy0 = __shfl(ay.w0, src), wy1 = __shfl(ay.w1, src);
+        const int ix0 = __shfl(ax.i0, src), ix1 = __shfl(ax.i1, src);
+        const uint32_t rq0 = __shfl(row0_j, src), rq1 = __shfl(row1_j, src);
+        if (__shfl(ok_j, src)) {
+          const float gv = (ch & 1) ? g3 : g2, wx = xx ? wx1 : wx0;
+          const int ix = xx ? ix1 : ix0;
+          atomicAdd(g_grid + ((size_t)rq0 * d.Gw + ix) * 8 + ch, (wy0 * wx) * gv);
+          atomicAdd(g_grid + ((size_t)rq1 * d.Gw + ix) * 8 + ch, (wy1 * wx) * gv);
         }
+      }
     }
 
     // ---- decoder weight gradients: stage activations with units on columns
