@@ -123,6 +123,26 @@ __device__ __forceinline__ f4v slab_sum(const float* A, int lane) {
   return acc;
 }
 
+// Float adds into a model's gradients in global memory, staged by the wave: lane s wrote R
+// runs of L consecutive words, run r at sv[(s R + r) L ..] to words so[s R + r] + 0..L-1 of
+// G (a negative offset skips the run).  An atomic add costs one memory request per 64-byte
+// segment and instruction however many of the segment's words its lanes add to, so the
+// 64 R L adds are issued sample-major, entry e by lane e % 64: an instruction covers the
+// whole runs of 64 / (R L) samples.  Zero values are skipped (a sum that starts at +0
+// never changes by adding +-0).
+template <int R, int L>
+__device__ __forceinline__ void ht_scatter(float* G, const float* sv, const int* so, int lane) {
+  wave_sync();   // the staging is visible to the wave
+#pragma unroll 1
+  for (int t = 0; t < R * L; ++t) {
+    const int e = 64 * t + lane;
+    const int o = so[e / L];
+    const float v = sv[e];
+    if (o >= 0 && v != 0.0f) atomicAdd(G + o + e % L, v);
+  }
+  wave_sync();   // the slabs may be staged again
+}
+
 // Where a training sample reads its features: the F_uvt taps (bilinear in the grid, linear
 // between slices), the F_ut / F_vt taps, and F_uv's footprint.
 struct SampleTaps {
@@ -457,7 +477,7 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
           for (int e = 0; e < 4; ++e) dx[4 * q + e] = dq[e];
         }
       }
-      if (!live) continue;
+      wave_sync();   // every lane holds its dx: the slabs take the scatter staging below
       // The taps again, recomputed from the sample's texel and time rather than kept through
       // the decoder backward (the empty asm hides that they equal the forward's, so they are
       // not reused from it).
@@ -470,10 +490,15 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
       const int *txs = T.txs, *tys = T.tys;
       const int64_t fpu = T.fpu;
       const Axis &pu = T.pu, &pv = T.pv;
-      // ---- feature gradients (straight-through for the simulated maps).  Per F_uvt slice the
-      // four taps' endpoint terms are first summed per 4x4 footprint (taps 0/1 and 2/3 share
-      // one when their columns do, taps 0/2 and 1/3 when their rows do), so each footprint
-      // the sample touches takes one set of 8 atomic adds.
+      // ---- feature gradients (straight-through for the simulated maps).  Adds into HBM go
+      // through the wave's slabs in runs of consecutive words (ht_scatter), so that an
+      // instruction covers whole runs of a few samples; adds into the chunk's LDS
+      // accumulators are issued per lane.  Dead lanes stage skipped runs.
+      float* const sv = slA;          // staged values [64][R x L] (slabs A and B)
+      int* const so = (int*)slC;      // staged run offsets into G [64][R]; negative skips
+      // Per F_uvt slice the four taps' endpoint terms are first summed per 4x4 footprint (taps
+      // 0/1 and 2/3 share one when their columns do, taps 0/2 and 1/3 when their rows do), so
+      // each footprint the sample touches takes one set of 8 adds.
       const bool fsx = (txs[0] >> 2) == (txs[1] >> 2), fsy = (tys[0] >> 2) == (tys[2] >> 2);
 #pragma unroll
       for (int sl = 0; sl < 2; ++sl) {
@@ -493,11 +518,14 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
             const float dv = wt * dx[c];
             e[i][2 * c] = dv * b.d1[c];
             e[i][2 * c + 1] = dv * b.d2[c];
-            if (!d.codec) atomicAdd(G + d.o_tw + wi + c, dv * b.dw[c]);
+            if (!d.codec) sv[lane * 16 + 4 * i + c] = dv * b.dw[c];
           }
-          if (d.codec)
-            atomicAdd(G + d.o_tw + wi, wt * (dx[0] * b.dw[0] + dx[1] * b.dw[1] + dx[2] * b.dw[2] + dx[3] * b.dw[3]));
+          if (d.codec) sv[lane * 4 + i] = wt * (dx[0] * b.dw[0] + dx[1] * b.dw[1] + dx[2] * b.dw[2] + dx[3] * b.dw[3]);
+          so[lane * 4 + i] = live ? (int)(d.o_tw + wi) : -1;
         }
+        if (d.codec) ht_scatter<4, 1>(G, sv, so, lane);
+        else ht_scatter<4, 4>(G, sv, so, lane);
+        if (direct) continue;   // a directly optimised map has no endpoints
         if (fsx) {
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
@@ -514,28 +542,40 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const bool own = i == 0 || (i == 1 && !fsx) || (i == 2 && !fsy) || (i == 3 && !fsx && !fsy);
-          if (!own || direct) continue;   // a directly optimised map has no endpoints
+          const bool own = live && (i == 0 || (i == 1 && !fsx) || (i == 2 && !fsy) || (i == 3 && !fsx && !fsy));
+          if (accum) {
+            if (own) {
 #pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            if (accum) atomicAdd(acc + fps[i] * 8 + k, e[i][k]);   // LDS (ds_add) or HBM: separate paths
-            else atomicAdd(G + d.o_tep + fps[i] * 8 + k, e[i][k]);
+              for (int k = 0; k < 8; ++k) atomicAdd(acc + fps[i] * 8 + k, e[i][k]);   // LDS (ds_add)
+            }
+          } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) sv[lane * 32 + 8 * i + k] = e[i][k];
+            so[lane * 4 + i] = own ? (int)(d.o_tep + fps[i] * 8) : -1;
           }
         }
+        if (!accum) ht_scatter<4, 8>(G, sv, so, lane);
       }
       // F_uv's texel again (recomputed rather than kept through the decoder backward)
       const BcTex bu = sim_texel(P + fpu * 8, P + d.o_uvw + ((int64_t)y * d.W + x) * d.cw, bcsim, direct, d.codec);
+      if (!direct) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        if (!direct) {
-          atomicAdd(G + fpu * 8 + 2 * c, dx[4 + c] * bu.d1[c]);
-          atomicAdd(G + fpu * 8 + 2 * c + 1, dx[4 + c] * bu.d2[c]);
+        for (int c = 0; c < 4; ++c) {
+          sv[lane * 8 + 2 * c] = dx[4 + c] * bu.d1[c];
+          sv[lane * 8 + 2 * c + 1] = dx[4 + c] * bu.d2[c];
         }
-        if (!d.codec) atomicAdd(G + d.o_uvw + ((int64_t)y * d.W + x) * 4 + c, dx[4 + c] * bu.dw[c]);
+        so[lane] = live ? (int)(fpu * 8) : -1;
+        ht_scatter<1, 8>(G, sv, so, lane);
       }
-      if (d.codec)
+      if (!d.codec) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sv[lane * 4 + c] = dx[4 + c] * bu.dw[c];
+        so[lane] = live ? (int)(d.o_uvw + ((int64_t)y * d.W + x) * 4) : -1;
+        ht_scatter<1, 4>(G, sv, so, lane);
+      } else if (live) {
         atomicAdd(G + d.o_uvw + (int64_t)y * d.W + x,
                   dx[4] * bu.dw[0] + dx[5] * bu.dw[1] + dx[6] * bu.dw[2] + dx[7] * bu.dw[3]);
+      }
 #pragma unroll
       for (int pl = 0; pl < 2; ++pl) {
         const int64_t off = pl ? d.o_vt : d.o_ut;
@@ -547,15 +587,20 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
           for (int aa = 0; aa < 2; ++aa) {
             const float w = (kk ? nk.w1 : nk.w0) * (aa ? a.w1 : a.w0);
             const int64_t idx = off + ((int64_t)(kk ? nk.i1 : nk.i0) * size + (aa ? a.i1 : a.i0)) * 2;
+            const int tap = 4 * pl + 2 * kk + aa;
             if (accum) {
-              atomicAdd(acc + nE + (idx - d.o_ut), w * dx[8 + 2 * pl]);
-              atomicAdd(acc + nE + (idx - d.o_ut) + 1, w * dx[9 + 2 * pl]);
+              if (live) {
+                atomicAdd(acc + nE + (idx - d.o_ut), w * dx[8 + 2 * pl]);
+                atomicAdd(acc + nE + (idx - d.o_ut) + 1, w * dx[9 + 2 * pl]);
+              }
             } else {
-              atomicAdd(G + idx, w * dx[8 + 2 * pl]);
-              atomicAdd(G + idx + 1, w * dx[9 + 2 * pl]);
+              sv[lane * 16 + 2 * tap] = w * dx[8 + 2 * pl];
+              sv[lane * 16 + 2 * tap + 1] = w * dx[9 + 2 * pl];
+              so[lane * 8 + tap] = live ? (int)idx : -1;
             }
           }
       }
+      if (!accum) ht_scatter<8, 2>(G, sv, so, lane);
     }
   }
     if (accum) {   // the chunk's sums into HBM
@@ -741,6 +786,8 @@ static int check_htrain(const ndgi_hybrid_train_state* st, const char* who) {
     return fail(NDGI_ERR_INVALID_ARG, "%s: with several models Tt * (U + V) must be even (16-byte aligned model blocks)",
                 who);
   if (st->reserved0) return fail(NDGI_ERR_INVALID_ARG, "%s: reserved0 must be 0", who);
+  if (htd_of(st).o_mlp > INT32_MAX)   // the gradient scatter stages 32-bit offsets
+    return fail(NDGI_ERR_INVALID_ARG, "%s: a model's feature block exceeds 2^31 words", who);
   return NDGI_OK;
 }
 
