@@ -390,16 +390,14 @@ __global__ __launch_bounds__(256) void k_reduce_rows(const float* __restrict__ p
   const int col = blockIdx.x * 256 + threadIdx.x;
   if (col >= NDGI_MLP_SIZE) return;
   const int r0 = blockIdx.y * kRowBlock, r1 = min(rows, r0 + kRowBlock);
+  // all of the thread's loads in flight together, then summed in row order (rows past the
+  // end add +0, which leaves a sum that started at +0 unchanged)
+  float v[kRowBlock];
+#pragma unroll
+  for (int k = 0; k < kRowBlock; ++k) v[k] = r0 + k < r1 ? partials[(size_t)(r0 + k) * kPartialStride + col] : 0.0f;
   float acc = 0.0f;
-  int r = r0;
-  for (; r + 8 <= r1; r += 8) {
-    float v[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = partials[(size_t)(r + k) * kPartialStride + col];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) acc += v[k];
-  }
-  for (; r < r1; ++r) acc += partials[(size_t)r * kPartialStride + col];
+  for (int k = 0; k < kRowBlock; ++k) acc += v[k];
   stage[(size_t)blockIdx.y * kPartialStride + col] = acc;
 }
 
@@ -413,14 +411,26 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const float* __restrict
   const int col = blockIdx.x * 64 + c;
   float acc = 0.0f;
   if (col < NDGI_MLP_SIZE)
-    for (int r = ph; r < rows; r += 4) acc += partials[(size_t)r * kPartialStride + col];
+    for (int r = ph; r < rows; r += 4 * 8) {   // eight rows' loads in flight, summed in row order
+      float v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = r + 4 * k < rows ? partials[(size_t)(r + 4 * k) * kPartialStride + col] : 0.0f;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc += v[k];
+    }
   red[ph][c] = acc;
   __syncthreads();
   if (ph == 0 && col < NDGI_MLP_SIZE) g_mlp[col] += ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
   if (blockIdx.x == 0 && loss_out) {
     __shared__ double lred[256];
     double l = 0.0;
-    for (int r = threadIdx.x; r < loss_rows; r += 256) l += loss_part[r];
+    for (int r = threadIdx.x; r < loss_rows; r += 256 * 8) {   // eight loads in flight
+      double v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = r + 256 * k < loss_rows ? loss_part[r + 256 * k] : 0.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) l += v[k];
+    }
     lred[threadIdx.x] = l;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
