@@ -115,21 +115,69 @@ __global__ __launch_bounds__(256) void k_train(TrainDims d, const float* __restr
   const int64_t groups = (n + 15) >> 4;
   const int64_t nwaves = (int64_t)gridDim.x * 4;
   const int64_t wave_id = (int64_t)blockIdx.x * 4 + wave;
-  for (int64_t grp = wave_id; grp < groups; grp += nwaves) {
+  // A group's sample words and gathered inputs are loaded one group ahead of their use (the
+  // word two groups ahead), so that the loads a group waits for were issued before the
+  // previous group's gradient atomics and its wait does not include them.
+  struct GroupIn {
+    bool valid;
+    int x, y, k;
+    float4 e4;       // (e1, e2) of channels 2g, 2g+1
+    float2 w2;       // weights of channels 2g, 2g+1
+    float2 gv[4];    // grid corners (yy, xx), channels 2g, 2g+1
+    float tg[3];     // target RGB (lanes g = 0)
+  };
+  auto word_at = [&](int64_t grp) -> uint32_t {
     const int64_t s = (grp << 4) + j;
-    bool valid = s < n;
-    uint32_t word = valid ? samples[s] : 0u;
+    return grp < groups && s < n ? samples[s] : 0u;
+  };
+  auto fetch = [&](int64_t grp, uint32_t word) {
+    GroupIn in;
+    const int64_t s = (grp << 4) + j;
+    in.valid = grp < groups && s < n;
     int x = word & 0xfff, y = (word >> 12) & 0xfff, k = word >> 24;
-    if (valid && (x >= d.W || y >= d.H || k >= d.T)) {
-      valid = false;
+    if (in.valid && (x >= d.W || y >= d.H || k >= d.T)) {
+      in.valid = false;
       if (g == 0) atomicOr(flags, 2u);
     }
-    if (!valid) x = y = k = 0;
+    if (!in.valid) x = y = k = 0;
+    in.x = x;
+    in.y = y;
+    in.k = k;
+    const size_t blk = ((size_t)(y >> 2) * (d.W >> 2) + (x >> 2)) * 8 + 2 * g;
+    in.e4 = *(const float4*)(ep + blk * 2);
+    in.w2 = *(const float2*)(wts + ((size_t)y * d.W + x) * 8 + 2 * g);
+    const Axis ax = texel_axis<R4>(x, d.Gw, d.W), ay = texel_axis<R4>(y, d.Gh, d.H);
+#pragma unroll
+    for (int yy = 0; yy < 2; ++yy)
+#pragma unroll
+      for (int xx = 0; xx < 2; ++xx) {
+        const size_t node = ((size_t)k * d.Gh + (yy ? ay.i1 : ay.i0)) * d.Gw + (xx ? ax.i1 : ax.i0);
+        in.gv[2 * yy + xx] = *(const float2*)(grid + node * 8 + 2 * g);
+      }
+    in.tg[0] = in.tg[1] = in.tg[2] = 0.0f;
+    if constexpr (MODE == NDGI_TRAIN_LOSS_GRAD) {
+      if (g == 0 && in.valid) {
+        const uint16_t* tp = target + (((size_t)k * d.H + y) * d.W + x) * 3;
+        in.tg[0] = half_bits(tp[0]);
+        in.tg[1] = half_bits(tp[1]);
+        in.tg[2] = half_bits(tp[2]);
+      }
+    }
+    return in;
+  };
+  uint32_t word_next = word_at(wave_id + nwaves);
+  GroupIn cur = fetch(wave_id, word_at(wave_id)), nxt;
+  for (int64_t grp = wave_id; grp < groups; grp += nwaves, cur = nxt) {
+    nxt = fetch(grp + nwaves, word_next);
+    word_next = word_at(grp + 2 * nwaves);
+    const int64_t s = (grp << 4) + j;
+    const bool valid = cur.valid;
+    const int x = cur.x, y = cur.y, k = cur.k;
 
     // ---- inputs: BC-simulated spatial texel (channels 2g, 2g+1) and grid at key k
     const size_t blk = ((size_t)(y >> 2) * (d.W >> 2) + (x >> 2)) * 8 + 2 * g;   // block-channel index
-    const float4 e4 = *(const float4*)(ep + blk * 2);            // (e1, e2) of channels 2g, 2g+1
-    const float2 w2 = *(const float2*)(wts + ((size_t)y * d.W + x) * 8 + 2 * g);
+    const float4 e4 = cur.e4;
+    const float2 w2 = cur.w2;
     const int E1a = (int)rintf(__fmul_rn(255.0f, e4.x)), E2a = (int)rintf(__fmul_rn(255.0f, e4.y));
     const int E1b = (int)rintf(__fmul_rn(255.0f, e4.z)), E2b = (int)rintf(__fmul_rn(255.0f, e4.w));
     const int Ja = (int)rintf(__fmul_rn(7.0f, w2.x)), Jb = (int)rintf(__fmul_rn(7.0f, w2.y));
@@ -144,8 +192,7 @@ __global__ __launch_bounds__(256) void k_train(TrainDims d, const float* __restr
 #pragma unroll
         for (int xx = 0; xx < 2; ++xx) {
           const float w = (yy ? ay.w1 : ay.w0) * (xx ? ax.w1 : ax.w0);
-          const size_t node = ((size_t)k * d.Gh + (yy ? ay.i1 : ay.i0)) * d.Gw + (xx ? ax.i1 : ax.i0);
-          const float2 v = *(const float2*)(grid + node * 8 + 2 * g);
+          const float2 v = cur.gv[2 * yy + xx];
           a = fmaf(w, v.x, a);
           b = fmaf(w, v.y, b);
         }
@@ -195,8 +242,7 @@ __global__ __launch_bounds__(256) void k_train(TrainDims d, const float* __restr
         dz1 = grad_pred[s * 3 + 1] * c1;
         dz2 = grad_pred[s * 3 + 2] * c2;
       } else {
-        const uint16_t* tp = target + (((size_t)k * d.H + y) * d.W + x) * 3;
-        const float e0 = c0 - half_bits(tp[0]), e1 = c1 - half_bits(tp[1]), e2 = c2 - half_bits(tp[2]);
+        const float e0 = c0 - cur.tg[0], e1 = c1 - cur.tg[1], e2 = c2 - cur.tg[2];
         loss += (double)e0 * e0 + (double)e1 * e1 + (double)e2 * e2;
         dz0 = 2.0f * inv3n * e0 * c0;
         dz1 = 2.0f * inv3n * e1 * c1;
