@@ -59,6 +59,7 @@ extern "C" {
 
 /* device error flags (ndgi_get_error_flags) */
 #define NDGI_FLAG_BAD_PAGE_REQUEST 1u
+#define NDGI_FLAG_BAD_SAMPLE       2u  /* ndgi_train_step: a sample outside the state's map */
 
 /* number of packed decoder parameters: [W1 32x16 | b1 32 | W2 32x32 | b2 32 | W3 3x32 | b3 3],
  * row-major W[out][in], layer y = W x + b */
@@ -347,7 +348,9 @@ int64_t ndgi_train_param_count(int32_t W, int32_t H, int32_t Gw, int32_t Gh, int
  * by LOSS_GRAD and FUSED (mean over samples and channels of (pred - target)^2; the sum is
  * accumulated in FP64).  The quantisation is E = rint(fl32(255 e)), J = rint(fl32(7 w)),
  * texel value floor(((7-J) E1 + J E2 + 3)/7) / 255; gradients reach e1, e2, w through the
- * straight-through derivative of Eq. 7 at (E/255, J/7).
+ * straight-through derivative of Eq. 7 at (E/255, J/7).  A sample with x >= W, y >= H or
+ * k >= T is skipped (it adds nothing to the loss or the gradients but still counts in n)
+ * and sets NDGI_FLAG_BAD_SAMPLE.
  * Errors: INVALID_ARG (sizes, mode, NULL pointers needed by the mode). */
 int ndgi_train_step(ndgi_ctx* ctx, ndgi_train_state* state, const ndgi_batch* batch,
                     int32_t mode, double* loss_dev, hipStream_t stream);
@@ -496,7 +499,8 @@ typedef struct ndgi_hybrid_train_state {
 } ndgi_hybrid_train_state;
 
 typedef struct ndgi_hybrid_batch {
-    const uint32_t* samples;  /* device [n]: x | y << 12 | f << 24                        */
+    const uint32_t* samples;  /* device [n]: x | y << 12 | f << 24; x, y and f above the
+                                 map's last texel or frame are clamped to it               */
     int64_t n;                /* 1 .. 2^31 - 1                                            */
     const float* target;      /* device [n_models][frames][H][W][3] preprocessed target
                                  (LOSS_GRAD, FUSED; see ndgi_hybrid_normalize_target)     */

@@ -18,6 +18,7 @@ OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_OOM = 0, -1, -2, -3, -4
 DTYPE_F32, DTYPE_F16 = 0, 1
 PREC_F32, PREC_F16 = 0, 1
 FLAG_BAD_PAGE_REQUEST = 1
+FLAG_BAD_SAMPLE = 2
 MLP_SIZE = 1699
 TRAIN_FORWARD, TRAIN_BACKWARD, TRAIN_LOSS_GRAD, TRAIN_FUSED, TRAIN_ADAM, TRAIN_ZERO_GRAD = range(6)
 

@@ -65,6 +65,35 @@ def test_forward_loss_and_gradients(env, shape):
         assert_grad(gr[key].cpu().numpy(), ref[key], key)
 
 
+def test_out_of_range_samples_are_skipped_and_flagged(env):
+    """A sample outside the map (x >= W, y >= H or k >= T) adds nothing but counts in n, and
+    sets the device flag: the loss and gradients are the oracle's over the valid samples,
+    scaled by n_valid / n.  Bad samples sit in the first, a middle and the last group."""
+    torch, N, TR, ctx = env
+    W, H, Gw, Gh, T, B = 32, 16, 8, 4, 5, 1000
+    st, x, y, k, tgt = problem(W, H, Gw, Gh, T, B, seed=11)
+    ctx.error_flags()                                  # clear what earlier tests left
+    tr = TR.Trainer(ctx, st)
+    smp, tg = device_batch(torch, x, y, k, tgt)
+    tr.loss_grad(smp, tg)
+    assert ctx.error_flags() == 0
+    bad = np.array([3, 517, B - 1])
+    xb, yb, kb = x.copy(), y.copy(), k.copy()
+    xb[bad[0]], yb[bad[1]], kb[bad[2]] = W, H + 7, T
+    tr = TR.Trainer(ctx, st)
+    smp, tg = device_batch(torch, xb, yb, kb, tgt)
+    loss = float(tr.loss_grad(smp, tg).item())
+    assert ctx.error_flags() & N.FLAG_BAD_SAMPLE
+    keep = np.ones(B, bool)
+    keep[bad] = False
+    ref_loss, ref = O.train_grads(st, x[keep], y[keep], k[keep], tgt[k[keep], y[keep], x[keep]].astype(np.float64))
+    f = keep.sum() / B
+    assert abs(loss - f * ref_loss) <= 2e-6 * f * ref_loss
+    gr = tr.split(tr.grads)
+    for key in ("mlp", "grid", "endpoints", "weights"):
+        assert_grad(gr[key].cpu().numpy(), f * np.asarray(ref[key]), key)
+
+
 def test_backward_mode_equals_loss_gradient(env):
     torch, N, TR, ctx = env
     st, x, y, k, tgt = problem(32, 32, 8, 8, 4, 3000, seed=7)
