@@ -137,7 +137,7 @@ __global__ __launch_bounds__(256) void k_train(TrainDims d, const float* __restr
     int x = word & 0xfff, y = (word >> 12) & 0xfff, k = word >> 24;
     if (in.valid && (x >= d.W || y >= d.H || k >= d.T)) {
       in.valid = false;
-      if (g == 0) atomicOr(flags, 2u);
+      if (g == 0) atomicOr(flags, NDGI_FLAG_BAD_SAMPLE);
     }
     if (!in.valid) x = y = k = 0;
     in.x = x;
