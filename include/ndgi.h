@@ -253,8 +253,8 @@ int ndgi_decode_binned(ndgi_ctx* ctx, const ndgi_model* model, const float* uvt,
  * process ends (its address is taken once per device by ndgi_create).
  *   uvt, out, prec, model, n: as for ndgi_decode_binned.
  * The call fails with INVALID_ARG when ndgi_decode_binned_workspace reports more than
- * NDGI_NOALLOC_SCRATCH_BYTES for (model, n) (above 2,084,576 queries on a 4096x4096 map with a
- * 1024x1024 grid, 4,061,936 on a 1024x1024 map with a 256x256 grid), before any launch.
+ * NDGI_NOALLOC_SCRATCH_BYTES for (model, n) (above 2,084,320 queries on a 4096x4096 map with a
+ * 1024x1024 grid, 4,061,680 on a 1024x1024 map with a 256x256 grid), before any launch.
  * No hipMalloc, hipFree or allocating library call is made.  Every call on one GPU shares
  * that GPU's scratch, whose contents carry over from the last call (nothing in it needs to
  * start at zero): calls that overlap on one GPU, from any context, stream or thread, race

@@ -24,6 +24,8 @@ constexpr int kSortThreads = 1024;
 constexpr int kMaxBins = 16384;     // LDS histogram capacity (64 KiB)
 constexpr int kPiece = 2048;        // at most this many queries per decode work item
 constexpr int kMaxKeys = 1024;      // largest T the host accepts
+constexpr int kStartBins = 1024;    // bins per workgroup of the bin-start scan
+constexpr int kStartWgs = kMaxBins / kStartBins;
 
 struct BinGeom {
   int ts_log2;      // tile side = 1 << ts_log2 texels (5 or 6)
@@ -94,10 +96,11 @@ __global__ __launch_bounds__(kSortThreads) void k_bin_count(ndgi_model m, BinGeo
 // Per bin: exclusive prefix of counts over the sort workgroups, in place, and the bin's
 // total into start[bin].  A workgroup takes 32 bins; eight groups of its threads each take
 // an eighth of the sort rows, with all of a thread's loads issued together, and the eighth
-// sums are combined through LDS.
+// sums are combined through LDS.  The workgroup's bin totals and work items (ceil(total /
+// kPiece) per bin) are summed into wsums[2 g], wsums[2 g + 1] for workgroup g.
 constexpr int kColParts = 8, kColBins = 256 / kColParts, kColRows = kSortWgs / kColParts;
 __global__ __launch_bounds__(256) void k_bin_colscan(int32_t* __restrict__ counts, int nbins,
-                                                     int32_t* __restrict__ start) {
+                                                     int32_t* __restrict__ start, int32_t* __restrict__ wsums) {
   __shared__ int32_t part[kColParts][kColBins];
   const int bl = threadIdx.x & (kColBins - 1), pr = threadIdx.x / kColBins;
   const int b = blockIdx.x * kColBins + bl;
@@ -113,55 +116,64 @@ __global__ __launch_bounds__(256) void k_bin_colscan(int32_t* __restrict__ count
   __syncthreads();
   int32_t run = 0;
   for (int q = 0; q < pr; ++q) run += part[q][bl];
-  if (!live) return;
+  if (live) {
 #pragma unroll
-  for (int r = 0; r < kColRows; ++r) {
-    counts[(int64_t)(pr * kColRows + r) * nbins + b] = run;
-    run += c[r];
+    for (int r = 0; r < kColRows; ++r) {
+      counts[(int64_t)(pr * kColRows + r) * nbins + b] = run;
+      run += c[r];
+    }
   }
-  if (pr == kColParts - 1) start[b] = run;
+  if (pr == kColParts - 1) {   // the last 32 threads, lanes 32..63 of the last wave
+    if (live) start[b] = run;
+    int32_t t = live ? run : 0, ti = live ? (run + kPiece - 1) / kPiece : 0;
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) {
+      t += __shfl_xor(t, off, 32);
+      ti += __shfl_xor(ti, off, 32);
+    }
+    if (bl == 0) {
+      wsums[2 * blockIdx.x] = t;
+      wsums[2 * blockIdx.x + 1] = ti;
+    }
+  }
 }
 
 // start[0..nbins) := exclusive prefix of the bin totals, start[nbins] := n;
 // items[b] := exclusive prefix of the work items per bin (ceil(count / kPiece)),
-// items[nbins] := total; item_bin[i] := the bin of work item i.  One workgroup of 1024
-// threads: the totals are staged in LDS with coalesced loads, each thread scans a run of 16
-// bins (the LDS array has one pad word per 16 so that the runs of a wave's lanes sit in
-// different banks), and the run sums are scanned across the workgroup with wave shuffles.
-// Every output goes back through the LDS array so that the global writes are coalesced
-// (a thread's own run of 16 words would put each lane of a store on its own line); the
-// item -> bin map is written straight from the runs only when it has more entries than
-// the array holds.
-__device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
-
-__global__ __launch_bounds__(1024) void k_bin_starts(int32_t* __restrict__ start, int32_t* __restrict__ items,
-                                                     int32_t* __restrict__ item_bin, int nbins, int32_t n) {
-  constexpr int kLds = kMaxBins + kMaxBins / 16;
-  __shared__ int32_t tot[kLds];
-  __shared__ int32_t wsum[16], wsumi[16], total_items;
-  constexpr int kPer = kMaxBins / 1024;
-  static_assert(kPer == 16, "one run of 16 bins per thread");
-  {
-    int32_t v[kPer];   // every load of a thread in flight together
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) v[k] = start[min((int)threadIdx.x + 1024 * k, nbins - 1)];
-#pragma unroll
-    for (int k = 0; k < kPer; ++k)
-      if ((int)threadIdx.x + 1024 * k < nbins) tot[pad16(threadIdx.x + 1024 * k)] = v[k];
-  }
-  __syncthreads();
-  const int lo = threadIdx.x * kPer, hi = min(nbins, lo + kPer);
-  int32_t c[kPer];   // this thread's bin totals (bins past nbins count 0)
-  int32_t s = 0, si = 0;
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    c[k] = lo + k < hi ? tot[pad16(lo + k)] : 0;
-    s += c[k];
-    si += (c[k] + kPiece - 1) / kPiece;
-  }
-  // workgroup-wide inclusive scan of (s, si): within each wave, then over the 16 wave sums
+// items[nbins] := total; item_bin[i] := the bin of work item i.  Workgroup w takes bins
+// [w kStartBins, (w + 1) kStartBins), one per thread: its offsets start from the sums of
+// the column-scan workgroups before its block (wsums, one pair per 32 bins, reduced with
+// wave shuffles and LDS), and its own bins are scanned with wave shuffles and the 16 wave
+// sums.  Each thread reads and rewrites only its own bin's entry.
+__global__ __launch_bounds__(kStartBins) void k_bin_starts(int32_t* __restrict__ start, int32_t* __restrict__ items,
+                                                           int32_t* __restrict__ item_bin, int nbins, int32_t n,
+                                                           const int32_t* __restrict__ wsums) {
+  static_assert(kStartBins % kColBins == 0 && kStartBins / kColBins * kStartWgs <= kStartBins,
+                "the column-scan sums before any block fit one per thread");
+  __shared__ int32_t wsum[16], wsumi[16], bsum[2];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int32_t incl = s, incli = si;
+  const int b = blockIdx.x * kStartBins + threadIdx.x;
+  // bins and items of the blocks before this one: thread t < (column-scan workgroups before
+  // the block) takes workgroup t's pair
+  {
+    const int before = (int)blockIdx.x * (kStartBins / kColBins);
+    int32_t p = (int)threadIdx.x < before ? wsums[2 * threadIdx.x] : 0;
+    int32_t pi = (int)threadIdx.x < before ? wsums[2 * threadIdx.x + 1] : 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      p += __shfl_xor(p, off, 64);
+      pi += __shfl_xor(pi, off, 64);
+    }
+    if (threadIdx.x < 2) bsum[threadIdx.x] = 0;
+    __syncthreads();
+    if (lane == 0 && p) atomicAdd(&bsum[0], p);
+    if (lane == 0 && pi) atomicAdd(&bsum[1], pi);
+    __syncthreads();
+  }
+  const int32_t base = bsum[0], basei = bsum[1];
+  const int32_t c = b < nbins ? start[b] : 0;
+  const int32_t ci = (c + kPiece - 1) / kPiece;
+  int32_t incl = c, incli = ci;
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
     const int32_t o = __shfl_up(incl, off, 64), oi = __shfl_up(incli, off, 64);
@@ -175,72 +187,20 @@ __global__ __launch_bounds__(1024) void k_bin_starts(int32_t* __restrict__ start
     wsumi[wave] = incli;
   }
   __syncthreads();
-  if (wave == 0 && lane < 16) {
-    int32_t w = wsum[lane], wi = wsumi[lane];
-#pragma unroll
-    for (int off = 1; off < 16; off <<= 1) {
-      const int32_t o = __shfl_up(w, off, 64), oi = __shfl_up(wi, off, 64);
-      if (lane >= off) {
-        w += o;
-        wi += oi;
-      }
-    }
-    wsum[lane] = w - wsum[lane];     // exclusive prefix of the wave sums
-    wsumi[lane] = wi - wsumi[lane];
-    if (lane == 15) total_items = wi;
+  int32_t run = base + incl - c, runi = basei + incli - ci;
+  for (int q = 0; q < wave; ++q) {
+    run += wsum[q];
+    runi += wsumi[q];
   }
-  __syncthreads();
-  const int32_t run0 = wsum[wave] + incl - s, runi0 = wsumi[wave] + incli - si;
-  const int32_t nitems = total_items;
-  // bin starts: each thread rewrites only its own run of the array, then all write out
-  {
-    int32_t run = run0;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      if (lo + k < hi) tot[pad16(lo + k)] = run;
-      run += c[k];
-    }
+  if (b < nbins) {
+    start[b] = run;
+    items[b] = runi;
+    for (int j = 0; j < ci; ++j) item_bin[runi + j] = b;
   }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < kPer; ++k)
-    if ((int)threadIdx.x + 1024 * k < nbins) start[threadIdx.x + 1024 * k] = tot[pad16(threadIdx.x + 1024 * k)];
-  __syncthreads();
-  // item prefixes per bin, the same way
-  {
-    int32_t runi = runi0;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      if (lo + k < hi) tot[pad16(lo + k)] = runi;
-      runi += (c[k] + kPiece - 1) / kPiece;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < kPer; ++k)
-    if ((int)threadIdx.x + 1024 * k < nbins) items[threadIdx.x + 1024 * k] = tot[pad16(threadIdx.x + 1024 * k)];
-  if (threadIdx.x == 0) {
+  if (b == nbins - 1) {   // the map's last bin closes both tables
     start[nbins] = n;
-    items[nbins] = nitems;
+    items[nbins] = runi + ci;
   }
-  // item -> bin map: staged in the array (unpadded) when it fits, else written directly
-  const bool staged = nitems <= kLds;
-  __syncthreads();
-  {
-    int32_t runi = runi0;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const int32_t pieces = (c[k] + kPiece - 1) / kPiece;
-      for (int j = 0; j < pieces; ++j) {
-        if (staged) tot[runi + j] = lo + k;
-        else item_bin[runi + j] = lo + k;
-      }
-      runi += pieces;
-    }
-  }
-  if (!staged) return;
-  __syncthreads();
-  for (int i = threadIdx.x; i < nitems; i += 1024) item_bin[i] = tot[i];
 }
 
 // Scatter: every query of sort workgroup wg goes to the next free slot of its bin; a
@@ -641,7 +601,7 @@ struct BinnedLayout {
   BinGeom bg;
   int nbins;
   int64_t max_items;
-  int64_t counts_off, start_off, items_off, item_bin_off, sorted_off, bytes;
+  int64_t counts_off, start_off, items_off, item_bin_off, bsum_off, sorted_off, bytes;
 };
 
 static int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
@@ -655,7 +615,8 @@ static bool binned_layout(const ndgi_model& m, int64_t n, BinnedLayout& L) {
   // at most one item per kPiece queries plus one per bin
   L.max_items = n / kPiece + L.nbins;
   L.item_bin_off = L.items_off + align256((int64_t)(L.nbins + 1) * 4);
-  L.sorted_off = L.item_bin_off + align256(L.max_items * 4);
+  L.bsum_off = L.item_bin_off + align256(L.max_items * 4);
+  L.sorted_off = L.bsum_off + align256((int64_t)(kMaxBins / kColBins) * 2 * 4);   // column-scan sums
   L.bytes = L.sorted_off + n * 16;
   return true;
 }
@@ -689,11 +650,14 @@ int launch_decode_binned(ndgi_ctx* ctx, const ndgi_model& m, const float* uvt, i
   int32_t* start = (int32_t*)((char*)ws + L.start_off);
   int32_t* items = (int32_t*)((char*)ws + L.items_off);
   int32_t* item_bin = (int32_t*)((char*)ws + L.item_bin_off);
+  int32_t* bsum = (int32_t*)((char*)ws + L.bsum_off);
   float4* sorted = (float4*)((char*)ws + L.sorted_off);
   const int64_t slice = (n + kSortWgs - 1) / kSortWgs;
   hipLaunchKernelGGL(k_bin_count, dim3(kSortWgs), dim3(kSortThreads), 0, s, m, L.bg, uvt, n, slice, counts);
-  hipLaunchKernelGGL(k_bin_colscan, dim3((L.nbins + kColBins - 1) / kColBins), dim3(256), 0, s, counts, L.nbins, start);
-  hipLaunchKernelGGL(k_bin_starts, dim3(1), dim3(1024), 0, s, start, items, item_bin, L.nbins, (int32_t)n);
+  hipLaunchKernelGGL(k_bin_colscan, dim3((L.nbins + kColBins - 1) / kColBins), dim3(256), 0, s, counts, L.nbins, start,
+                     bsum);
+  hipLaunchKernelGGL(k_bin_starts, dim3((L.nbins + kStartBins - 1) / kStartBins), dim3(kStartBins), 0, s, start, items,
+                     item_bin, L.nbins, (int32_t)n, bsum);
   hipLaunchKernelGGL(k_bin_scatter, dim3(kSortWgs), dim3(kSortThreads), 0, s, m, L.bg, uvt, n, slice, counts, start,
                      sorted);
   NDGI_HIP(hipGetLastError());

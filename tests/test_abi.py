@@ -49,9 +49,10 @@ def _fake_model(ndgi, W, H, Gw, Gh, T):
 
 
 def test_binned_workspace_size_query():
-    """The workspace query is host arithmetic: 256 sort slices x bins of int32 counts,
+    """The workspace query is host arithmetic: 512 sort slices x bins of int32 counts,
     bins + 1 int32 starts, bins + 1 int32 work-item offsets, an int32 bin per work item
-    (at most n / 2048 + bins items), 16 bytes per query, each region 256-byte aligned."""
+    (at most n / 2048 + bins items), 4 KiB of column-scan sums, 16 bytes per query, each
+    region 256-byte aligned."""
     from paper_2604_12625_amd import ndgi
     if not os.path.exists(ndgi.LIB_PATH):
         pytest.skip("libndgi.so not built (run __graft_entry__.build())")
@@ -60,11 +61,11 @@ def test_binned_workspace_size_query():
     m = _fake_model(ndgi, 4096, 4096, 1024, 1024, 24)        # 128 x 128 tiles of 32^2
     assert L.ndgi_decode_binned_workspace(ctypes.byref(m), 1 << 24, ctypes.byref(b)) == ndgi.OK
     nb = 128 * 128
-    assert b.value == 512 * nb * 4 + 2 * ((nb + 1) * 4 + 252) + 4 * ((1 << 24) // 2048 + nb) + 16 * (1 << 24)
+    assert b.value == 512 * nb * 4 + 2 * ((nb + 1) * 4 + 252) + 4 * ((1 << 24) // 2048 + nb) + 4096 + 16 * (1 << 24)
     m = _fake_model(ndgi, 8192, 4100, 2048, 1025, 4)          # 64^2 tiles: 128 x 65 bins
     assert L.ndgi_decode_binned_workspace(ctypes.byref(m), 10, ctypes.byref(b)) == ndgi.OK
     nb = 128 * 65
-    assert b.value == 512 * nb * 4 + 2 * (((nb + 1) * 4 + 255) // 256 * 256) + (4 * nb + 255) // 256 * 256 + 160
+    assert b.value == 512 * nb * 4 + 2 * (((nb + 1) * 4 + 255) // 256 * 256) + (4 * nb + 255) // 256 * 256 + 4096 + 160
     m = _fake_model(ndgi, 16384, 8192, 4096, 2048, 1)         # too many tiles
     assert L.ndgi_decode_binned_workspace(ctypes.byref(m), 10, ctypes.byref(b)) == ndgi.ERR_UNSUPPORTED
     assert b"8192" in L.ndgi_last_error() or b"tiles" in L.ndgi_last_error()

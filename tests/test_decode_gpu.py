@@ -245,7 +245,7 @@ def test_binned_64_texel_tiles(N, ctx):
     import torch
     m = I.random_model(8192, 2112, 2048, 528, 4, np.float16, np.float16, config=56)
     assert ctx.binned_workspace_bytes(N.DeviceModel.from_numpy(m), 0) == 512 * 128 * 33 * 4 + \
-        2 * (((128 * 33 + 1) * 4 + 255) // 256 * 256) + (4 * 128 * 33 + 255) // 256 * 256
+        2 * (((128 * 33 + 1) * 4 + 255) // 256 * 256) + (4 * 128 * 33 + 255) // 256 * 256 + 4096
     q = I.uniform_queries(300_000, I.rng(56, I.P_QUERY))
     got, _ = _dec_binned(N, ctx, m, q, 1)
     np.testing.assert_array_equal(got, _dec(N, ctx, m, q, 1))

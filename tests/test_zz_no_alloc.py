@@ -56,7 +56,7 @@ def test_noalloc_refuses_more_queries_than_its_scratch_holds(env):
     torch, N, ctx = env
     m = I.random_model(1024, 1024, 256, 256, 24, np.float16, np.float16, config=72)
     dm = N.DeviceModel.from_numpy(m)
-    n_max = 4_061_936            # the largest batch whose layout fits 64 MiB on this map
+    n_max = 4_061_680            # the largest batch whose layout fits 64 MiB on this map
     need = ctypes.c_int64()
     assert N.lib().ndgi_decode_binned_workspace(ctypes.byref(dm.desc), n_max, ctypes.byref(need)) == N.OK
     assert need.value <= 64 << 20
