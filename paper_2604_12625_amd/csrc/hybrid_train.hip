@@ -104,20 +104,19 @@ __device__ __forceinline__ void slab_store(float* slab, int lane, const float v[
   for (int q = 0; q < 4; ++q) d[q] = f4v{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
 }
 
-// D[u][c] = sum over samples of A[s][u] B[s][c]
-__device__ __forceinline__ f4v slab_outer(const float* A, const float* B, int lane) {
+// D[u][c] = acc + sum over samples of A[s][u] B[s][c]
+__device__ __forceinline__ f4v slab_outer(const float* A, const float* B, int lane,
+                                          f4v acc = f4v{0.0f, 0.0f, 0.0f, 0.0f}) {
   const int g = lane >> 4, i = lane & 15;
-  f4v acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
   for (int q = 0; q < 16; ++q)
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[(4 * q + g) * 16 + i], B[(4 * q + g) * 16 + i], acc, 0, 0, 0);
   return acc;
 }
 
-// D[u][c] = sum over samples of A[s][u] (every column)
-__device__ __forceinline__ f4v slab_sum(const float* A, int lane) {
+// D[u][c] = acc + sum over samples of A[s][u] (every column)
+__device__ __forceinline__ f4v slab_sum(const float* A, int lane, f4v acc = f4v{0.0f, 0.0f, 0.0f, 0.0f}) {
   const int g = lane >> 4, i = lane & 15;
-  f4v acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
   for (int q = 0; q < 16; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[(4 * q + g) * 16 + i], 1.0f, acc, 0, 0, 0);
   return acc;
@@ -207,6 +206,11 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
     float* G = Gall + (int64_t)m * d.o_mlp;
     const int64_t mlp_off = (int64_t)d.M * d.o_mlp + (int64_t)m * (d.n - d.o_mlp);
     float* gm = Gall + mlp_off;
+    // h = 16: the decoder's weight and bias gradients of the chunk's rounds continue one MFMA
+    // chain each (the next round's sums start from this round's) and reach HBM once per
+    // chunk; h = 64 adds each round's (its sums would hold 85 more registers a lane)
+    constexpr bool kChain = HD == 16;
+    f4v cw3 = {0.0f, 0.0f, 0.0f, 0.0f}, cb3 = cw3, cw2 = cw3, cb2 = cw3, cw1 = cw3, cb1 = cw3;
   for (int r = 0; r < rounds; ++r) {
     // staging inside the round loop (first round only): the decoder weight reads of the
     // round cannot then be hoisted out of the loop into registers held across all rounds
@@ -348,16 +352,21 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
         for (int u = 0; u < 16; ++u) v[u] = gelu<NDGI_PREC_F32>(a2[16 * jb + u]);
         slab_store(slB, lane, v);
         wave_sync();
-        const f4v w3 = slab_outer(slA, slB, lane);
-        if (lg == 0) {
+        if constexpr (kChain) {
+          cw3 = slab_outer(slA, slB, lane, cw3);
+          cb3 = slab_sum(slA, lane, cb3);
+        } else {
+          const f4v w3 = slab_outer(slA, slB, lane);
+          if (lg == 0) {
 #pragma unroll
-          for (int r = 0; r < 3; ++r) atomicAdd(gm + Sh::oW3 + r * HD + 16 * jb + li, w3[r]);
-        }
-        if (jb == 0) {
-          const f4v b3 = slab_sum(slA, lane);
-          if (lane == 0) {
+            for (int r = 0; r < 3; ++r) atomicAdd(gm + Sh::oW3 + r * HD + 16 * jb + li, w3[r]);
+          }
+          if (jb == 0) {
+            const f4v b3 = slab_sum(slA, lane);
+            if (lane == 0) {
 #pragma unroll
-            for (int r = 0; r < 3; ++r) atomicAdd(gm + Sh::oB3 + r, b3[r]);
+              for (int r = 0; r < 3; ++r) atomicAdd(gm + Sh::oB3 + r, b3[r]);
+            }
           }
         }
         wave_sync();
@@ -411,14 +420,19 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
         for (int jb = 0; jb < HD / 16; ++jb) {
           slab_store(slA, lane, a2 + 16 * jb);
           wave_sync();
-          const f4v w2 = slab_outer(slA, slB, lane);
+          if constexpr (kChain) {
+            cw2 = slab_outer(slA, slB, lane, cw2);
+            cb2 = slab_sum(slA, lane, cb2);
+          } else {
+            const f4v w2 = slab_outer(slA, slB, lane);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) atomicAdd(gm + Sh::oW2 + (16 * jb + 4 * lg + r) * HD + 16 * kb + li, w2[r]);
-          if (kb == 0) {
-            const f4v b2 = slab_sum(slA, lane);
-            if (li == 0) {
+            for (int r = 0; r < 4; ++r) atomicAdd(gm + Sh::oW2 + (16 * jb + 4 * lg + r) * HD + 16 * kb + li, w2[r]);
+            if (kb == 0) {
+              const f4v b2 = slab_sum(slA, lane);
+              if (li == 0) {
 #pragma unroll
-              for (int r = 0; r < 4; ++r) atomicAdd(gm + Sh::oB2 + 16 * jb + 4 * lg + r, b2[r]);
+                for (int r = 0; r < 4; ++r) atomicAdd(gm + Sh::oB2 + 16 * jb + 4 * lg + r, b2[r]);
+              }
             }
           }
 #pragma unroll
@@ -446,13 +460,18 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
         }
         slab_store(slA, lane, a1b);
         wave_sync();
-        const f4v w1 = slab_outer(slA, slC, lane);
+        if constexpr (kChain) {
+          cw1 = slab_outer(slA, slC, lane, cw1);
+          cb1 = slab_sum(slA, lane, cb1);
+        } else {
+          const f4v w1 = slab_outer(slA, slC, lane);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) atomicAdd(gm + Sh::oW1 + (16 * kb + 4 * lg + r) * 16 + li, w1[r]);
-        const f4v b1 = slab_sum(slA, lane);
-        if (li == 0) {
+          for (int r = 0; r < 4; ++r) atomicAdd(gm + Sh::oW1 + (16 * kb + 4 * lg + r) * 16 + li, w1[r]);
+          const f4v b1 = slab_sum(slA, lane);
+          if (li == 0) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) atomicAdd(gm + Sh::oB1 + 16 * kb + 4 * lg + r, b1[r]);
+            for (int r = 0; r < 4; ++r) atomicAdd(gm + Sh::oB1 + 16 * kb + 4 * lg + r, b1[r]);
+          }
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -603,6 +622,28 @@ __global__ __launch_bounds__(kHtMaxThreads) void k_hybrid_train(HybTrainDims d, 
       if (!accum) ht_scatter<8, 2>(G, sv, so, lane);
     }
   }
+    if constexpr (kChain && MODE != NDGI_TRAIN_FORWARD) {   // the chunk's decoder sums into HBM
+      if (lg == 0) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) atomicAdd(gm + Sh::oW3 + r * HD + li, cw3[r]);
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) atomicAdd(gm + Sh::oB3 + r, cb3[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        atomicAdd(gm + Sh::oW2 + (4 * lg + r) * HD + li, cw2[r]);
+        atomicAdd(gm + Sh::oW1 + (4 * lg + r) * 16 + li, cw1[r]);
+      }
+      if (li == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          atomicAdd(gm + Sh::oB2 + 4 * lg + r, cb2[r]);
+          atomicAdd(gm + Sh::oB1 + 4 * lg + r, cb1[r]);
+        }
+      }
+    }
     if (accum) {   // the chunk's sums into HBM
       __syncthreads();
       for (int64_t i = threadIdx.x; i < nE; i += nthr) {
