@@ -341,6 +341,38 @@ def test_production_size_multi_model_batch_matches_oracle(N, ctx, codec):
     assert abs(loss - ref_loss) <= 1e-5 * abs(ref_loss), (loss, ref_loss)
 
 
+@pytest.mark.parametrize("hidden", [16, 64])
+def test_rounds_of_a_chunk_equal_separate_calls(N, ctx, hidden):
+    """Eight models x 32768 samples run several 256-sample rounds per chunk (four on a
+    256-CU GPU), where h = 16 carries the decoder's weight-gradient sums across the rounds
+    in its MFMA chains; the same samples as four calls of each model's quarters (one round
+    per chunk) must give four times the gradients and the loss (each call normalises by its
+    own per-model count).  No noise, so that the draws do not depend on a sample's index."""
+    from paper_2604_12625_amd.train import HybridTrainer
+    M, Bm = 8, 32768
+    sts = [_state(hidden, seed=140 + i, bigger=True, codec=1) for i in range(M)]
+    for st in sts[1:]:
+        st["dims"] = sts[0]["dims"]
+    g = np.random.default_rng(141)
+    d = sts[0]["dims"]
+    xs, ys, fs = (g.integers(0, d["W"], M * Bm), g.integers(0, d["H"], M * Bm), g.integers(0, d["frames"], M * Bm))
+    tgt = g.normal(0.5, 0.5, (M, d["frames"], d["H"], d["W"], 3)).astype(np.float32)
+    smp, tg = _dev(N, xs, ys, fs, tgt)
+    one = HybridTrainer(ctx, sts, seed=3, per_model=Bm)
+    one.zero_grad()
+    loss_one = float(one.loss_grad(smp, tg, 0).item())
+    q = Bm // 4
+    four = HybridTrainer(ctx, sts, seed=3, per_model=q)
+    four.zero_grad()
+    loss_four = 0.0
+    for k in range(4):
+        idx = np.concatenate([np.arange(m * Bm + k * q, m * Bm + (k + 1) * q) for m in range(M)])
+        sk, _ = _dev(N, xs[idx], ys[idx], fs[idx], tgt)
+        loss_four += float(four.loss_grad(sk, tg, 0).item())
+    assert abs(loss_four - 4 * loss_one) <= 1e-5 * abs(loss_four), (loss_four, loss_one)
+    _close(four.grads.cpu().numpy(), 4.0 * one.grads.cpu().numpy(), 1e-4, "gradients")
+
+
 def test_identical_models_trained_together_equal_one_trained_alone(N, ctx):
     """Per-model normalisation: M copies of a model with the same samples, trained together,
     stay equal step for step to the model trained alone (Adam is not invariant to a common
